@@ -1,0 +1,318 @@
+"""Seeded synthetic inputs shaped like the paper's capillary workloads.
+
+This module is the only code shared by the HIP path and the FP64 oracle, and
+it holds none of the method's arithmetic: it maps the physical set-up of
+Sec. 3.1 to lattice parameters, draws membrane shapes and ligand sites, and
+returns plain arrays.  Both sides receive identical numbers from here and
+compute everything else themselves.
+
+Lattice units throughout: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3.
+"""
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+DEFORMABLE, RIGID, FIXED = 0, 1, 2
+TAG_CELL, TAG_PARTICLE = 1, 2
+
+# Eq. (12) prefactor; minimum allowed vertex distance dx; probe length 1.2 dx (Sec. 2.6)
+REP_PREFACTOR = 1.0e-4 / (8.0 * np.sqrt(2.0))
+REP_CUTOFF = 1.0
+PROBE_DIST = 1.2
+P_REF = 1.0 / 3.0          # reference pressure c_s^2 rho_0 of the area penalty
+KA = 1.0                   # incompressibility coefficient k_a (Sec. 2.3)
+Y_CR_M = 25e-9             # critical bond gap, 25 nm (Sec. 2.5)
+KF_OVER_KR0 = 8.5e3        # biochemical affinity k_f / k_r0 (Sec. 3.1)
+
+
+@dataclass
+class Body:
+    kind: int
+    xy: np.ndarray                    # (n, 2) counter-clockwise, unwrapped lattice coordinates
+    xy_rest: Optional[np.ndarray]     # stress-free shape or None (= xy)
+    ks: float = 0.0
+    kb: float = 0.0
+    ka: float = KA
+    pref: float = P_REF
+    rho_r: float = 1.0
+    tag: int = 0
+
+
+@dataclass
+class Bonds:
+    body: int
+    host: np.ndarray                  # (ns,) int32 element index (element e joins vertex e to e+1)
+    frac: np.ndarray                  # (ns,) position along the element, [0, 1)
+    sigma: float
+    ycr: float
+    yeq: float
+    kf: float
+    kr0: float
+    lb: float
+    seed: int
+
+
+@dataclass
+class Config:
+    name: str
+    nx: int
+    ny: int
+    tau: float
+    gx: float
+    gy: float = 0.0
+    walls: int = 3
+    ux_init: Optional[np.ndarray] = None   # (ny,) initial x-velocity per row, None = rest
+    bodies: List[Body] = field(default_factory=list)
+    bonds: List[Bonds] = field(default_factory=list)
+    rep_pref: float = REP_PREFACTOR
+    rep_cut: float = REP_CUTOFF
+    probe_dist: float = PROBE_DIST
+    steps: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_vertices(self):
+        return sum(len(b.xy) for b in self.bodies)
+
+    @property
+    def n_sites(self):
+        return sum(len(b.host) for b in self.bonds)
+
+
+# ---- parameter mapping (Sec. 3.1) -------------------------------------------------
+
+def viscosity(tau):
+    """nu = c_s^2 (tau - 1/2) dt (Sec. 2.1)."""
+    return (tau - 0.5) / 3.0
+
+
+def channel(H, Re, tau):
+    """Centre-line speed and driving body force of a channel of height H
+    (lattice nodes) at Reynolds number Re = u_max H / nu (Sec. 3.1):
+    u_max = Re nu / H and g = 8 nu u_max / H^2 (plane Poiseuille flow)."""
+    nu = viscosity(tau)
+    umax = Re * nu / H
+    g = 8.0 * nu * umax / H ** 2
+    return nu, umax, g
+
+
+def poiseuille_profile(ny, g, tau):
+    """Steady x-velocity per row of the body-force driven channel with
+    halfway bounce-back walls at y = -1/2 and y = ny - 1/2: the parabola plus
+    the lattice slip of BGK bounce-back, g (16 Lambda - 3) / (24 nu) with
+    Lambda = (tau - 1/2)^2 (used only as an initial condition)."""
+    nu = viscosity(tau)
+    H = float(ny)
+    eta = np.arange(ny) + 0.5
+    lam = (tau - 0.5) ** 2
+    return g / (2 * nu) * eta * (H - eta) + g * (16 * lam - 3) / (24 * nu)
+
+
+def stiffness(umax, tau, Ca):
+    """k_s from Ca = rho nu u_max / k_s (Sec. 3.1)."""
+    return viscosity(tau) * umax / Ca
+
+
+def bond_spring(tau, H, sigma_star=1.0):
+    """sigma in lattice units from its dimensionless group rho nu^2 / H (Sec. 2.5)."""
+    return sigma_star * viscosity(tau) ** 2 / H
+
+
+# ---- shapes ----------------------------------------------------------------------------
+
+def _resample(fx, fy, q0, q1, n, dense=200000):
+    """n points on the closed curve (fx(q), fy(q)), q in [q0, q1), equally spaced in arc length."""
+    q = np.linspace(q0, q1, dense + 1)
+    x, y = fx(q), fy(q)
+    s = np.concatenate([[0.0], np.cumsum(np.hypot(np.diff(x), np.diff(y)))])
+    target = np.arange(n) * s[-1] / n
+    qs = np.interp(target, s, q)
+    return np.stack([fx(qs), fy(qs)], 1)
+
+
+def circle(n, R, cx, cy, start=-np.pi / 2):
+    t = start + 2 * np.pi * np.arange(n) / n
+    return np.stack([cx + R * np.cos(t), cy + R * np.sin(t)], 1)
+
+
+def ellipse(n, a, b, cx, cy):
+    """Ellipse with semi-axes a (x) and b (y), counter-clockwise from the bottom, uniform in arc length."""
+    return _resample(lambda q: cx + a * np.cos(q), lambda q: cy + b * np.sin(q),
+                     -np.pi / 2, 1.5 * np.pi, n)
+
+
+def biconcave(n, a_alpha, cx, cy):
+    """Median section of a red blood cell, Eq. (21), with a*alpha the cell
+    radius; reversed to counter-clockwise order; uniform in arc length."""
+    fx = lambda q: cx - a_alpha * np.sin(q)        # x -> -x reverses the orientation
+    fy = lambda q: cy + 0.5 * a_alpha * (0.207 + 2.003 * np.sin(q) ** 2 - 1.123 * np.sin(q) ** 4) * np.cos(q)
+    return _resample(fx, fy, -0.5 * np.pi, 1.5 * np.pi, n)
+
+
+def rectangle(n, b, h, cx, y_bottom):
+    """Discoidal particle section: a b x h rectangle, corners included, each
+    side divided evenly, counter-clockwise from the bottom-left corner."""
+    nb = int(round(n * b / (2 * (b + h))))
+    nh = n // 2 - nb
+    if nb < 1 or nh < 1 or 2 * (nb + nh) != n:
+        raise ValueError("vertex count does not fit the rectangle")
+    x0, x1, y0, y1 = cx - b / 2, cx + b / 2, y_bottom, y_bottom + h
+    pts = []
+    for k in range(nb):
+        pts.append((x0 + b * k / nb, y0))
+    for k in range(nh):
+        pts.append((x1, y0 + h * k / nh))
+    for k in range(nb):
+        pts.append((x1 - b * k / nb, y1))
+    for k in range(nh):
+        pts.append((x0, y1 - h * k / nh))
+    return np.array(pts, dtype=np.float64)
+
+
+# ---- ligand sites ------------------------------------------------------------------------
+
+def place_sites(xy, n_bound, ycr, wall_y=-0.5):
+    """Ligand sites evenly spaced in arc length along the whole perimeter, with
+    the spacing chosen so that exactly ``n_bound`` sites lie closer than ``ycr``
+    to the wall at t = 0 (they are placed at the centres of n_bound equal parts
+    of the arc where the gap is below ycr).  Returns (host element, fraction)."""
+    xy = np.asarray(xy, dtype=np.float64)
+    n = len(xy)
+    nxt = np.roll(xy, -1, axis=0)
+    seg = np.hypot(*(nxt - xy).T)
+    s0 = np.concatenate([[0.0], np.cumsum(seg)])
+    P = s0[-1]
+
+    def point(s):
+        s = np.mod(s, P)
+        e = np.minimum(np.searchsorted(s0, s, side="right") - 1, n - 1)
+        f = (s - s0[e]) / seg[e]
+        return e, f, xy[e] + f[:, None] * (nxt[e] - xy[e])
+
+    dense = np.linspace(0.0, P, 400001)[:-1]
+    _, _, pts = point(dense)
+    close = pts[:, 1] - wall_y < ycr
+    if not close.any() or close.all():
+        raise ValueError("no contiguous binding arc")
+    # rotate so that the binding arc is contiguous and starts at index 0
+    k0 = int(np.argmax(close & ~np.roll(close, 1)))
+    roll = np.roll(close, -k0)
+    m = int(np.argmin(roll))            # first not-close index after the run
+    if roll[m:].any():
+        raise ValueError("binding arc is not contiguous")
+    ds = P / len(dense)
+    a = dense[k0]
+    length = m * ds
+    spacing = length / n_bound
+    total = int(np.floor(P / spacing))
+    s = a + spacing * (np.arange(total) + 0.5)
+    e, f, p = point(s)
+    nclose = int(np.sum(p[:, 1] - wall_y < ycr))
+    if nclose != n_bound:
+        raise ValueError(f"site placement gave {nclose} bound sites, wanted {n_bound}")
+    order = np.lexsort((f, e))
+    return e[order].astype(np.int32), f[order]
+
+
+# ---- workloads --------------------------------------------------------------------------------
+
+def config_c1(seed=0, steps=2000):
+    """Plain method, small: 480x60 channel (dx = 0.125 um, H = 7.5 um), tau = 1,
+    Re = 0.01, walls top and bottom, periodic in x; one circular deformable
+    cell (R = 28, 256 vertices, Ca = 1e-3, beta = 0.1) upstream; one rigid
+    16x4 elliptical particle (64 vertices, rho_P/rho = 1.1) on the lower wall
+    with 50 bonds engaged."""
+    nx, ny, tau = 480, 60, 1.0
+    nu, umax, g = channel(ny, 0.01, tau)
+    dx_um = 7.5 / ny
+    ks = stiffness(umax, tau, 1e-3)
+    cell = Body(DEFORMABLE, circle(256, 28.0, 40.0, 29.5), None, ks=ks, kb=0.1 * ks, rho_r=1.0, tag=TAG_CELL)
+    ycr = Y_CR_M / (dx_um * 1e-6)
+    yeq = 0.5 * ycr
+    part_xy = ellipse(64, 8.0, 2.0, 100.0, -0.5 + yeq + 2.0)
+    part = Body(RIGID, part_xy, None, rho_r=1.1, tag=TAG_PARTICLE)
+    host, frac = place_sites(part_xy, 50, ycr)
+    kf = 8.5e-3
+    bonds = Bonds(1, host, frac, sigma=bond_spring(tau, ny), ycr=ycr, yeq=yeq, kf=kf,
+                  kr0=kf / KF_OVER_KR0, lb=ycr / 20.0, seed=seed)
+    return Config("c1_480x60", nx, ny, tau, g, ux_init=poiseuille_profile(ny, g, tau),
+                  bodies=[cell, part], bonds=[bonds], steps=steps,
+                  meta=dict(umax=umax, nu=nu, dx_um=dx_um, n_bound0=50))
+
+
+def config_c2(seed=0, steps=50000, ar=None, ca=None):
+    """Paper-scale: 3840x240 channel (dx = 0.03125 um), Re = 0.01, tau = 1;
+    six cells alternating biconcave and globular (radius 3.5 um = 112 nodes,
+    512 vertices each) on the centre line at x = 320 + 640 k; one discoidal
+    particle 2 um long (64 nodes), aspect ratio from {0.25, 0.5, 1.0} and Ca
+    from {0, 1e-4, 1e-3} drawn with the seed, 128 vertices, 200 bonds
+    engaged, mid-gap between the first two cells on the lower wall."""
+    nx, ny, tau = 3840, 240, 1.0
+    nu, umax, g = channel(ny, 0.01, tau)
+    dx_um = 7.5 / ny
+    rng = np.random.default_rng(seed)
+    ar = float(rng.choice([0.25, 0.5, 1.0])) if ar is None else ar
+    ca = float(rng.choice([0.0, 1e-4, 1e-3])) if ca is None else ca
+    ks_cell = stiffness(umax, tau, 1e-3)
+    bodies = []
+    for k in range(6):
+        cx = 320.0 + 640.0 * k
+        xy = biconcave(512, 112.0, cx, 119.5) if k % 2 == 0 else circle(512, 112.0, cx, 119.5)
+        bodies.append(Body(DEFORMABLE, xy, None, ks=ks_cell, kb=0.1 * ks_cell, rho_r=1.0, tag=TAG_CELL))
+    ycr = Y_CR_M / (dx_um * 1e-6)
+    yeq = 0.5 * ycr
+    b, h = 64.0, ar * 64.0
+    part_xy = rectangle(128, b, h, 640.0, -0.5 + yeq)
+    if ca == 0.0:
+        part = Body(RIGID, part_xy, None, rho_r=1.1, tag=TAG_PARTICLE)
+    else:
+        ks = stiffness(umax, tau, ca)
+        part = Body(DEFORMABLE, part_xy, None, ks=ks, kb=0.1 * ks, rho_r=1.1, tag=TAG_PARTICLE)
+    bodies.append(part)
+    host, frac = place_sites(part_xy, 200, ycr)
+    kf = 8.5e-3
+    bonds = Bonds(6, host, frac, sigma=bond_spring(tau, ny), ycr=ycr, yeq=yeq, kf=kf,
+                  kr0=kf / KF_OVER_KR0, lb=ycr / 20.0, seed=seed)
+    return Config("c2_3840x240", nx, ny, tau, g, ux_init=poiseuille_profile(ny, g, tau),
+                  bodies=bodies, bonds=[bonds], steps=steps,
+                  meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, n_bound0=200))
+
+
+def config_tiny(nx=37, ny=22, tau=0.8, seed=3, walls=3, kinds=(DEFORMABLE, RIGID), umax=2e-3, ca=5e-2):
+    """Small channel that still spans several kernel tiles with ragged edges:
+    a deformable circle and an adhered particle with bonds, parameters scaled
+    up so that the coupling terms are far above round-off in a few hundred
+    steps."""
+    nu = viscosity(tau)
+    g = 8.0 * nu * umax / ny ** 2 if walls else 1e-6
+    ks = stiffness(umax, tau, ca)
+    bodies = []
+    bonds = []
+    cy = (ny - 1) / 2.0
+    if DEFORMABLE in kinds:
+        bodies.append(Body(DEFORMABLE, circle(40, 5.0, 9.3, cy + 0.37), None, ks=ks, kb=0.1 * ks,
+                           rho_r=1.0, tag=TAG_CELL))
+    ycr = 0.6
+    yeq = 0.3
+    if RIGID in kinds or FIXED in kinds:
+        kind = RIGID if RIGID in kinds else FIXED
+        pxy = ellipse(24, 4.0, 1.5, 24.6, -0.5 + yeq + 1.5)
+        bodies.append(Body(kind, pxy, None, rho_r=1.1, tag=TAG_PARTICLE))
+        if walls:
+            host, frac = place_sites(pxy, 10, ycr)
+            bonds.append(Bonds(len(bodies) - 1, host, frac, sigma=2e-3, ycr=ycr, yeq=yeq, kf=0.05,
+                               kr0=2e-3, lb=ycr / 6.0, seed=seed))
+    ux = poiseuille_profile(ny, g, tau) if walls else None
+    return Config(f"tiny_{nx}x{ny}", nx, ny, tau, g, walls=walls, ux_init=ux, bodies=bodies, bonds=bonds,
+                  meta=dict(umax=umax, nu=nu))
+
+
+def lattice_only(nx, ny, tau, walls=3, umax=1e-3, seed=0, noise=0.0):
+    """Channel without bodies; optionally a seeded perturbation of the initial
+    velocity (returned as a per-node array in meta['ux0'], meta['uy0'])."""
+    nu = viscosity(tau)
+    g = 8.0 * nu * umax / ny ** 2 if walls else 1e-6
+    cfg = Config(f"lattice_{nx}x{ny}", nx, ny, tau, g, walls=walls,
+                 ux_init=poiseuille_profile(ny, g, tau) if walls else None, meta=dict(umax=umax))
+    return cfg

@@ -1,0 +1,152 @@
+"""Throughput of the fused LBM-IB step on one MI355X.
+
+A step is one pass of the whole hot path: interpolation to every vertex and
+probe, membrane/interaction/bond/load forces, integration, direct forcing
+and spreading, bond kinetics and the lattice sweep.  The default workload is
+the paper-scale capillary (3840 x 240 lattice, six cells of 512 vertices, a
+discoidal particle of 128 vertices with 200 engaged bonds), inputs resident
+in HBM.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LBM-IBM MLUPS & HBM GB/s (FP32 vs FP16-store); batched sweep runs/hour"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ["capib_dev.hpp", "lattice.hip"]:
+        h.update(open(os.path.join(ROOT, "paper_2210_06043_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counters(name):
+    """HBM bytes per launch of the lattice sweep from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{name}_counters.json")
+    if not os.path.exists(p):
+        return None
+    c = json.load(open(p))
+    if c.get("source_hash") != kernel_source_hash():
+        return None
+    return c.get("bytes_per_launch")
+
+
+def workload(name, seed):
+    from paper_2210_06043_amd import inputs
+    if name == "c2":
+        cfg = inputs.config_c2(seed=seed)
+        desc = (f"paper-scale capillary 3840x240 (dx=0.03125um), 6 cells x 512 markers, discoidal particle "
+                f"AR={cfg.meta['ar']} Ca={cfg.meta['ca']} x 128 markers, 200 bonds engaged, Re=0.01")
+    else:
+        cfg = inputs.config_c1(seed=seed)
+        desc = "small capillary 480x60, circular cell 256 markers, rigid ellipse 64 markers, 50 bonds, Re=0.01"
+    return cfg, desc
+
+
+def cpu_baseline(cfg, steps):
+    import oracle
+    s = oracle.Sim(cfg.nx, cfg.ny, cfg.tau, cfg.gx, cfg.gy, cfg.walls)
+    s.set_interactions(cfg.rep_pref, cfg.rep_cut, cfg.probe_dist)
+    s.init_flow(cfg.ux_init)
+    for b in cfg.bodies:
+        s.add_body(b.kind, b.xy, b.xy_rest, b.ks, b.kb, b.ka, b.pref, b.rho_r, b.tag)
+    for bd in cfg.bonds:
+        s.add_bonds(bd.body, bd.host, bd.frac, bd.sigma, bd.ycr, bd.yeq, bd.kf, bd.kr0, bd.lb, bd.seed)
+    t0 = time.perf_counter()
+    s.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=round(cfg.nx * cfg.ny * steps / dt / 1e6, 3), unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{steps} full coupled steps of the same workload (FP64, single thread), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32")
+    ap.add_argument("--workload", choices=["c2", "c1"], default="c2")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
+              f"DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2210_06043_amd import capib
+
+    torch.cuda.set_device(0)
+    cfg, desc = workload(args.workload, args.seed)
+    storage = capib.FP16_SHIFTED if args.storage == "fp16" else capib.FP32_SHIFTED
+    scale = 2.0 ** 20 if storage == capib.FP16_SHIFTED else 1.0
+    sim = capib.from_config(cfg, storage=storage, fp16_scale=scale, graph=not args.no_graph)
+    nodes = cfg.nx * cfg.ny
+    st = sim.stream
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    sim.step(args.steps)
+    e1.record(st)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+
+    # per-kernel HIP events on the library's stream, same number of steps
+    sim.set_timing(True)
+    sim.step(args.steps)
+    sim.set_timing(False)
+    ph, n = sim.read_timing()
+    lat_ms = ph[2] / n
+    diag = sim.diagnostics()
+
+    bytes_per_node = 72 if storage == capib.FP32_SHIFTED else 36
+    alg_bytes = bytes_per_node * nodes
+    achieved = alg_bytes / (lat_ms * 1e-3) / 1e9
+    kname = f"lattice_{args.storage}_{args.workload}"
+    traffic = counters(kname)
+
+    out = {
+        "metric": METRIC,
+        "value": round(nodes * args.steps / (ms * 1e-3) / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "nodes": nodes, "population_storage": args.storage + "_shifted",
+                   "hip_graphs": not args.no_graph, "vertices": cfg.n_vertices, "sites": cfg.n_sites},
+        "roofline": {"bound": "hbm", "kernel": "k_lattice", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_us": round(lat_ms * 1e3, 3)},
+        "phase_us_per_step": {"interp": round(ph[0] / n * 1e3, 3), "body": round(ph[1] / n * 1e3, 3),
+                              "lattice": round(ph[2] / n * 1e3, 3)},
+        "error_flags": diag["error_flags"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * capib — C-ABI of the MI355X (gfx950) implementation of the hybrid lattice
+ * Boltzmann / immersed-boundary method of Coclite, Pascazio, de Tullio and
+ * Decuzzi, "Predicting the vascular adhesion of deformable drug carriers in
+ * narrow capillaries traversed by blood cells" (arXiv 2210.06043).
+ *
+ * The calls follow the paper's statement of the problem: a D2Q9 lattice with
+ * capillary walls (Sec. 2.1-2.2, 3.1), immersed membranes (Sec. 2.2-2.3),
+ * ligand-receptor bonds (Sec. 2.5) and a time step (Sec. 2.6-2.8).
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3.
+ *   - Fluid nodes (i, j), i in [0, nx), j in [0, ny); x is periodic.  With
+ *     walls the no-slip walls sit half-way between nodes at y = -1/2 and
+ *     y = ny - 1/2 (halfway bounce-back).
+ *   - Host arrays of node fields are row-major [ny][nx] doubles; population
+ *     arrays are [9][ny][nx] in the velocity order of Eq. (3): rest, +x, +y,
+ *     -x, -y, (+1,+1), (-1,+1), (-1,-1), (+1,-1), stored shifted, h = f - w.
+ *   - Membrane vertices are given counter-clockwise as interleaved (x, y)
+ *     doubles in unwrapped lattice coordinates; element e joins vertex e to
+ *     vertex e+1 (mod n).
+ *
+ * Ownership and memory
+ *   - The caller owns all device memory: one workspace of
+ *     capib_workspace_bytes() bytes (256-byte aligned), bound once with
+ *     capib_bind_workspace().  The library never allocates or frees device
+ *     memory.  Host arrays passed in are copied during the call.
+ *   - All GPU work is enqueued on the hip stream given at creation (a
+ *     hipStream_t passed as void*; NULL = the null stream).  Calls documented
+ *     "syncs" wait for that stream before returning.
+ *
+ * Errors
+ *   - Every call returns a capib_status; capib_last_error() gives a message
+ *     for the last failing call on that context.  Arguments are validated
+ *     before any device work.  Numerical trouble detected on the device
+ *     (non-finite values, |u| > 0.3 c_s, rho <= 0, a vertex outside the rows
+ *     [-1, ny], a spread force beyond the fixed-point range) is sticky and is
+ *     reported as CAPIB_E_UNSTABLE by capib_diagnostics().
+ *
+ * Threads: one context per host thread at a time; distinct contexts are
+ * independent.
+ */
+#ifndef CAPIB_H
+#define CAPIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CAPIB_OK = 0,
+    CAPIB_E_ARG = -1,      /* invalid argument (message says which) */
+    CAPIB_E_STATE = -2,    /* call out of order (e.g. no workspace bound) */
+    CAPIB_E_HIP = -3,      /* HIP runtime error */
+    CAPIB_E_UNSTABLE = -4, /* device error flag raised (see capib_diag.error_flags) */
+    CAPIB_E_CAPACITY = -5  /* more bodies, vertices or sites than the capacities */
+} capib_status;
+
+/* population storage of the lattice sweep */
+enum { CAPIB_FP32_SHIFTED = 0, CAPIB_FP16_SHIFTED = 1 };
+/* membrane kinds: deformable (Eqs. 16-18), rigid (Eqs. 19-20), fixed (no motion) */
+enum { CAPIB_DEFORMABLE = 0, CAPIB_RIGID = 1, CAPIB_FIXED = 2 };
+/* device error flag bits */
+enum {
+    CAPIB_FLAG_VERTEX_OUT = 1,   /* a vertex left the rows [-1, ny] */
+    CAPIB_FLAG_FLUID = 2,        /* non-finite population, rho <= 0 or |u| > 0.3 c_s */
+    CAPIB_FLAG_FORCE_RANGE = 4,  /* a spread contribution beyond the fixed-point range */
+    CAPIB_FLAG_NONFINITE_IB = 8  /* non-finite vertex force or position */
+};
+
+typedef struct capib_ctx capib_ctx;
+
+/* The lattice of Sec. 2.1 and the channel of Sec. 3.1.
+ *   nx, ny     nodes (ny >= 2, nx >= 1)
+ *   tau        BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3, Sec. 2.1)
+ *   gx, gy     uniform driving body force per node (added to the Guo term)
+ *   walls      3: bounce-back walls at both y ends; 0: periodic in y too
+ *   storage    CAPIB_FP32_SHIFTED or CAPIB_FP16_SHIFTED
+ *   fp16_scale power of two multiplying stored FP16 deviations (ignored for FP32)
+ *   max_*      capacities of the workspace; max_vertices counts all bodies,
+ *              a single body holds at most 1024 vertices                    */
+typedef struct {
+    int32_t nx, ny;
+    double tau, gx, gy;
+    int32_t walls;
+    int32_t storage;
+    double fp16_scale;
+    int32_t max_bodies, max_vertices, max_sites;
+} capib_lattice;
+
+/* An immersed membrane (Sec. 2.2-2.3).
+ *   kind           CAPIB_DEFORMABLE | CAPIB_RIGID | CAPIB_FIXED
+ *   n, xy          vertex count (3..1024) and 2n coordinates, counter-clockwise
+ *   xy_rest        stress-free shape (2n) or NULL for xy (rest lengths, angles, A0)
+ *   ks, kb, ka     spring (Eq. 8), bending (Eq. 10) and area (Eq. 11) constants
+ *   p_ref          reference pressure of Eq. (11)
+ *   density_ratio  rho_body / rho_0: vertex mass rho_r A0 / n (deformable),
+ *                  mass rho_r A0 and inertia rho_r J0 (rigid)
+ *   tag            free caller label                                          */
+typedef struct {
+    int32_t kind;
+    int32_t n;
+    const double *xy;
+    const double *xy_rest;
+    double ks, kb, ka, p_ref, density_ratio;
+    int32_t tag;
+} capib_membrane;
+
+/* Ligand sites on a body, receptors on the lower wall (Sec. 2.5).
+ *   host_elem, frac  site s sits on element host_elem[s] at fraction frac[s]
+ *   sigma            bond spring constant of Eq. (13)
+ *   y_cr, y_eq       critical gap for binding and equilibrium bond length
+ *   k_f, k_r0        forward rate and unstressed reverse rate per step
+ *   bell_len         Bell length: k_r = k_r0 exp(|y - y_eq| / bell_len)
+ *   seed             key of the Philox4x32-10 stream of this body          */
+typedef struct {
+    int32_t n_sites;
+    const int32_t *host_elem;
+    const double *frac;
+    double sigma, y_cr, y_eq, k_f, k_r0, bell_len;
+    uint64_t seed;
+} capib_bonds;
+
+typedef struct {
+    int64_t step;         /* completed steps */
+    int32_t error_flags;  /* CAPIB_FLAG_* bits raised so far */
+    int32_t n_bodies;
+    double mass;          /* sum over nodes of drho, FP64 accumulation */
+    double mom_x, mom_y;  /* sum over nodes of sum_i h_i e_i, FP64 accumulation */
+} capib_diag;
+
+typedef struct {
+    double area, perimeter, cx, cy;  /* current polygon, FP64 sums (Green's theorem) */
+    double area0, perimeter0;        /* rest area and initial perimeter */
+    int32_t n_bound;                 /* engaged bonds N_L */
+    int32_t kind;
+    double xc, yc, phi, ucx, ucy, omega; /* rigid state (zero for other kinds) */
+} capib_body_diag;
+
+/* Creates a context for the lattice; validates tau > 1/2, sizes, walls in
+ * {0, 3}, storage, capacities.  hip_stream: hipStream_t or NULL.           */
+capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx **out);
+
+/* Bytes of device workspace the context needs (multiple of 256). */
+size_t capib_workspace_bytes(const capib_ctx *ctx);
+
+/* Binds caller-owned device memory (>= capib_workspace_bytes, 256-byte
+ * aligned) and clears it on the stream.  Must precede every call below.   */
+capib_status capib_bind_workspace(capib_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* Sets the populations to the equilibrium of Eq. (2) at drho = 0 and the
+ * x-velocity ux_of_y[j] in row j (ny values; NULL = rest).  Enqueued.     */
+capib_status capib_init_flow(capib_ctx *ctx, const double *ux_of_y);
+
+/* Writes / reads the stored populations as [9][ny][nx] doubles (h = f - w),
+ * rounding to the storage type on write.  Syncs.                          */
+capib_status capib_write_populations(capib_ctx *ctx, const double *h);
+capib_status capib_read_populations(capib_ctx *ctx, double *h);
+
+/* Adds a membrane (Sec. 2.2-2.3); returns its index in *body_id.  Rest
+ * lengths, angles, area and (rigid) mass and polar moment are computed from
+ * the shape in FP64.  Fails with CAPIB_E_CAPACITY beyond the capacities.   */
+capib_status capib_add_membrane(capib_ctx *ctx, const capib_membrane *m, int32_t *body_id);
+
+/* Adds the ligand sites of one body (Sec. 2.5).  A site is engaged at the
+ * start iff its gap to the wall y = -1/2 is below y_cr; its anchor is then
+ * straight below it.  Once per body.                                       */
+capib_status capib_add_bonds(capib_ctx *ctx, int32_t body_id, const capib_bonds *b);
+
+/* Interaction constants: repulsion prefactor and range of Eq. (12) (defaults
+ * 1e-4/(8 sqrt 2) and dx) and the probe length of Sec. 2.6 (default 1.2).  */
+capib_status capib_set_interactions(capib_ctx *ctx, double rep_prefactor, double rep_cutoff,
+                                    double probe_dist);
+
+/* Advances nsteps full steps (interpolation, forces, integration, spreading,
+ * bonds, lattice sweep).  Enqueued on the stream, returns immediately.     */
+capib_status capib_step(capib_ctx *ctx, int32_t nsteps);
+
+/* Replays the steps through captured HIP graphs of two steps when
+ * enable != 0 (results identical to plain launches).                      */
+capib_status capib_set_graph(capib_ctx *ctx, int32_t enable);
+
+/* Macroscopic fields of the current state, [ny][nx] each (any may be NULL):
+ * drho = sum h and u* = (sum h e + g/2)/rho of the streamed populations,
+ * the moments the next step starts from.  Syncs.                          */
+capib_status capib_read_macro(capib_ctx *ctx, double *drho, double *ux, double *uy);
+
+/* Vertex positions x^n of a body, 2n doubles.  Syncs. */
+capib_status capib_read_vertices(capib_ctx *ctx, int32_t body_id, double *xy);
+
+/* Bond states (0/1) and anchor x of a body's sites in the order given to
+ * capib_add_bonds.  Syncs.                                                 */
+capib_status capib_read_bonds(capib_ctx *ctx, int32_t body_id, uint8_t *state, double *anchor_x);
+
+/* Per-vertex data of the last step of a body (any may be NULL): interpolated
+ * u* (2n), probe pressure and viscous stress per element (4n: p, sxx, sxy,
+ * syy), total Lagrangian force (2n), target velocity U^{n+1} (2n).  Syncs. */
+capib_status capib_read_body_work(capib_ctx *ctx, int32_t body_id, double *ustar, double *probe,
+                                  double *force, double *target);
+
+/* Global FP64 sums and the sticky error flags; returns CAPIB_E_UNSTABLE if
+ * any flag is set.  Syncs.                                                  */
+capib_status capib_diagnostics(capib_ctx *ctx, capib_diag *out);
+
+/* FP64 geometry of a body's current polygon, N_L and rigid state.  Syncs. */
+capib_status capib_body_diagnostics(capib_ctx *ctx, int32_t body_id, capib_body_diag *out);
+
+/* Checkpoint: with host_buf == NULL stores the needed size in *bytes;
+ * otherwise copies the whole device state (populations, bodies, bonds, step)
+ * into host_buf (*bytes on input is its capacity).  Syncs.                  */
+capib_status capib_save(capib_ctx *ctx, void *host_buf, size_t *bytes);
+
+/* Restores a checkpoint written by capib_save on a context created with the
+ * same lattice and capacities and the same bodies and bonds added.  Syncs.  */
+capib_status capib_load(capib_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Per-kernel timing with HIP events on the context's stream.  While enabled,
+ * capib_step records events around the IB phase and the lattice sweep of
+ * every step and synchronises at its end.  capib_read_timing returns the
+ * summed milliseconds of {interpolation, body phase, lattice sweep} and the
+ * number of steps timed, then resets the sums.                             */
+capib_status capib_set_timing(capib_ctx *ctx, int32_t enable);
+capib_status capib_read_timing(capib_ctx *ctx, double *ms3, int64_t *steps);
+
+/* Message of the last failing call on this context (never NULL). */
+const char *capib_last_error(const capib_ctx *ctx);
+
+/* Frees the host-side context; the workspace stays the caller's.  Waits for
+ * the stream.                                                               */
+void capib_destroy(capib_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAPIB_H */

@@ -1,0 +1,815 @@
+// C-ABI of libcapib: context, workspace layout, set-up of membranes and
+// bonds (FP64 on the host, once), the step loop and read-outs.  Every step
+// of the method runs in the kernels of lattice.hip and ib.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/capib.h"
+#include "capib_dev.hpp"
+#include "capib_kernels.hpp"
+
+using namespace capib;
+
+namespace {
+
+struct BodyHost {
+    int kind, n, vstart;
+    int site_start = 0, n_sites = 0;
+    bool has_bonds = false;
+    double A0, P0;
+    std::vector<double> xy;        // shape at creation
+    std::vector<int> perm;         // sorted site k -> caller's site index
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void split(double x, float &hi, float &lo) {
+    hi = (float)x;
+    lo = (float)(x - (double)hi);
+}
+
+}  // namespace
+
+struct capib_ctx {
+    capib_lattice lat;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Dev d{};
+    int pitch = 0, ntx = 0, nty = 0;
+    size_t esize = 4;
+    // workspace layout
+    size_t ws_bytes = 0;
+    size_t off_pop[2]{}, off_fib = 0, off_tflag = 0, off_red = 0, off_macro = 0, off_uinit = 0, off_scal = 0;
+    size_t off_ib = 0, ib_bytes = 0;
+    size_t off_bp = 0, off_bs = 0, off_vbody = 0, off_pos[8]{}, off_dxm = 0, off_dym = 0, off_x0[4]{};
+    size_t off_r0x = 0, off_r0y = 0, off_l0 = 0, off_th0 = 0, off_ustar = 0, off_probe = 0, off_force = 0;
+    size_t off_target = 0, off_srange = 0, off_shost = 0, off_sstate = 0, off_sorig = 0, off_sfrac = 0;
+    size_t off_sanh = 0, off_sanl = 0;
+    char *base = nullptr;
+    bool bound = false;
+    int par = 0;
+    long long step = 0;
+    int nbodies = 0, nverts = 0, nsites = 0;
+    std::vector<BodyHost> bodies;
+    std::string err = "no error";
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    double ms[3] = {0, 0, 0};
+    long long tsteps = 0;
+    // graphs
+    bool use_graph = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+};
+
+static capib_status fail(capib_ctx *c, capib_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIPCHK(c, call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail((c), CAPIB_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static void layout(capib_ctx *c) {
+    const capib_lattice &L = c->lat;
+    size_t o = 0;
+    const size_t N = (size_t)c->pitch * L.ny;
+    for (int p = 0; p < 2; p++) { c->off_pop[p] = o; o = align256(o + 9 * N * c->esize); }
+    c->off_fib = o; o = align256(o + 2 * N * sizeof(long long));
+    c->off_tflag = o; o = align256(o + (size_t)c->ntx * c->nty * 4);
+    c->off_red = o; o = align256(o + (3 * (size_t)c->ntx * c->nty + 3) * 8);
+    c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
+    c->off_uinit = o; o = align256(o + (size_t)L.ny * 8);
+    c->off_scal = o; o = align256(o + 64);
+    // IB region: one contiguous block (checkpointed whole)
+    const size_t B = (size_t)std::max(1, L.max_bodies), V = (size_t)std::max(1, L.max_vertices),
+                 S = (size_t)std::max(1, L.max_sites);
+    c->off_ib = o;
+    c->off_bp = o; o = align256(o + B * sizeof(BodyParams));
+    c->off_bs = o; o = align256(o + B * sizeof(BodyState));
+    c->off_vbody = o; o = align256(o + V * 4);
+    for (int k = 0; k < 8; k++) { c->off_pos[k] = o; o = align256(o + V * 4); }
+    c->off_dxm = o; o = align256(o + V * 4);
+    c->off_dym = o; o = align256(o + V * 4);
+    for (int k = 0; k < 4; k++) { c->off_x0[k] = o; o = align256(o + V * 4); }
+    c->off_r0x = o; o = align256(o + V * 4);
+    c->off_r0y = o; o = align256(o + V * 4);
+    c->off_l0 = o; o = align256(o + V * 4);
+    c->off_th0 = o; o = align256(o + V * 4);
+    c->off_ustar = o; o = align256(o + V * 8);
+    c->off_probe = o; o = align256(o + V * 16);
+    c->off_force = o; o = align256(o + V * 8);
+    c->off_target = o; o = align256(o + V * 8);
+    c->off_srange = o; o = align256(o + V * 8);
+    c->off_shost = o; o = align256(o + S * 4);
+    c->off_sstate = o; o = align256(o + S * 4);
+    c->off_sorig = o; o = align256(o + S * 4);
+    c->off_sfrac = o; o = align256(o + S * 4);
+    c->off_sanh = o; o = align256(o + S * 4);
+    c->off_sanl = o; o = align256(o + S * 4);
+    c->ib_bytes = o - c->off_ib;
+    c->ws_bytes = o;
+}
+
+static void fill_dev(capib_ctx *c) {
+    Dev &d = c->d;
+    const capib_lattice &L = c->lat;
+    char *b = c->base;
+    d.nx = L.nx; d.ny = L.ny; d.pitch = c->pitch; d.walls = L.walls;
+    d.ntx = c->ntx; d.nty = c->nty; d.storage = L.storage;
+    d.qstride = (long long)c->pitch * L.ny;
+    d.omega = (float)(1.0 / L.tau);
+    d.fc = (float)(1.0 - 0.5 / L.tau);
+    d.gx = (float)L.gx; d.gy = (float)L.gy;
+    d.scale = L.storage ? (float)L.fp16_scale : 1.0f;
+    d.inv_scale = L.storage ? (float)(1.0 / L.fp16_scale) : 1.0f;
+    for (int p = 0; p < 2; p++) d.pop[p] = b + c->off_pop[p];
+    d.fib = (long long *)(b + c->off_fib);
+    d.tflag = (uint32_t *)(b + c->off_tflag);
+    d.red = (double *)(b + c->off_red);
+    d.macro = (float *)(b + c->off_macro);
+    d.uinit = (double *)(b + c->off_uinit);
+    d.counter = (long long *)(b + c->off_scal);
+    d.err = (int *)(b + c->off_scal + 8);
+    d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites;
+    d.bp = (BodyParams *)(b + c->off_bp);
+    d.bs = (BodyState *)(b + c->off_bs);
+    d.vbody = (int *)(b + c->off_vbody);
+    for (int p = 0; p < 2; p++) {
+        d.pxh[p] = (float *)(b + c->off_pos[4 * p + 0]);
+        d.pxl[p] = (float *)(b + c->off_pos[4 * p + 1]);
+        d.pyh[p] = (float *)(b + c->off_pos[4 * p + 2]);
+        d.pyl[p] = (float *)(b + c->off_pos[4 * p + 3]);
+    }
+    d.dxm = (float *)(b + c->off_dxm); d.dym = (float *)(b + c->off_dym);
+    d.x0h = (float *)(b + c->off_x0[0]); d.x0l = (float *)(b + c->off_x0[1]);
+    d.y0h = (float *)(b + c->off_x0[2]); d.y0l = (float *)(b + c->off_x0[3]);
+    d.r0x = (float *)(b + c->off_r0x); d.r0y = (float *)(b + c->off_r0y);
+    d.l0 = (float *)(b + c->off_l0); d.th0 = (float *)(b + c->off_th0);
+    d.ustar = (float2 *)(b + c->off_ustar);
+    d.probe4 = (float4 *)(b + c->off_probe);
+    d.force = (float2 *)(b + c->off_force);
+    d.target = (float2 *)(b + c->off_target);
+    d.srange = (int2 *)(b + c->off_srange);
+    d.s_host = (int *)(b + c->off_shost); d.s_state = (int *)(b + c->off_sstate);
+    d.s_orig = (int *)(b + c->off_sorig); d.s_frac = (float *)(b + c->off_sfrac);
+    d.s_anh = (float *)(b + c->off_sanh); d.s_anl = (float *)(b + c->off_sanl);
+}
+
+static void drop_graphs(capib_ctx *c) {
+    for (int p = 0; p < 2; p++)
+        if (c->gexec[p]) { (void)hipGraphExecDestroy(c->gexec[p]); c->gexec[p] = nullptr; }
+}
+
+static capib_status need_ws(capib_ctx *c) {
+    if (!c) return CAPIB_E_ARG;
+    if (!c->bound) return fail(c, CAPIB_E_STATE, "no workspace bound");
+    return CAPIB_OK;
+}
+
+static capib_status h2d(capib_ctx *c, size_t off, const void *src, size_t bytes) {
+    if (!bytes) return CAPIB_OK;
+    HIPCHK(c, hipMemcpyAsync(c->base + off, src, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CAPIB_OK;
+}
+
+static capib_status d2h(capib_ctx *c, void *dst, size_t off, size_t bytes) {
+    if (!bytes) return CAPIB_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, c->base + off, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CAPIB_OK;
+}
+
+extern "C" {
+
+capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx **out) {
+    if (!lat || !out) return CAPIB_E_ARG;
+    *out = nullptr;
+    const capib_lattice &L = *lat;
+    if (L.nx < 1 || L.ny < 2 || (long long)L.nx * L.ny > (1LL << 31)) return CAPIB_E_ARG;
+    if (!(L.tau > 0.5) || !std::isfinite(L.tau) || !std::isfinite(L.gx) || !std::isfinite(L.gy)) return CAPIB_E_ARG;
+    if (L.walls != 0 && L.walls != 3) return CAPIB_E_ARG;
+    if (L.storage != CAPIB_FP32_SHIFTED && L.storage != CAPIB_FP16_SHIFTED) return CAPIB_E_ARG;
+    if (L.storage == CAPIB_FP16_SHIFTED) {
+        int ex;
+        double m = std::frexp(L.fp16_scale, &ex);
+        if (!(L.fp16_scale > 0) || m != 0.5) return CAPIB_E_ARG;   // a power of two
+    }
+    if (L.max_bodies < 0 || L.max_vertices < 0 || L.max_sites < 0) return CAPIB_E_ARG;
+    capib_ctx *c = new capib_ctx();
+    c->lat = L;
+    c->stream = (hipStream_t)hip_stream;
+    c->esize = L.storage == CAPIB_FP32_SHIFTED ? 4 : 2;
+    c->pitch = (L.nx + TILE_X - 1) / TILE_X * TILE_X;
+    c->ntx = (L.nx + TILE_X - 1) / TILE_X;
+    c->nty = (L.ny + TILE_Y - 1) / TILE_Y;
+    // Eq. (12) prefactor, minimum allowed distance dx, distance floor, probe 1.2 dx
+    c->d.rep_pref = (float)(1.0e-4 / (8.0 * std::sqrt(2.0)));
+    c->d.rep_cut = 1.0f;
+    c->d.rep_dmin = 0.1f;
+    c->d.probe = 1.2f;
+    layout(c);
+    *out = c;
+    return CAPIB_OK;
+}
+
+size_t capib_workspace_bytes(const capib_ctx *c) { return c ? c->ws_bytes : 0; }
+
+capib_status capib_bind_workspace(capib_ctx *c, void *ptr, size_t bytes) {
+    if (!c) return CAPIB_E_ARG;
+    if (!ptr || bytes < c->ws_bytes) return fail(c, CAPIB_E_ARG, "workspace of %zu bytes needs %zu", bytes, c->ws_bytes);
+    if (((uintptr_t)ptr & 255) != 0) return fail(c, CAPIB_E_ARG, "workspace not 256-byte aligned");
+    drop_graphs(c);
+    c->base = (char *)ptr;
+    c->bound = true;
+    c->par = 0;
+    c->step = 0;
+    c->nbodies = c->nverts = c->nsites = 0;
+    c->bodies.clear();
+    fill_dev(c);
+    HIPCHK(c, hipMemsetAsync(c->base, 0, c->ws_bytes, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CAPIB_OK;
+}
+
+capib_status capib_init_flow(capib_ctx *c, const double *ux) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (ux) {
+        for (int j = 0; j < c->lat.ny; j++)
+            if (!std::isfinite(ux[j]) || std::fabs(ux[j]) > 0.1) return fail(c, CAPIB_E_ARG, "bad velocity in row %d", j);
+        if ((s = h2d(c, c->off_uinit, ux, (size_t)c->lat.ny * 8))) return s;
+    }
+    HIPCHK(c, launch_init_flow(c->d, c->par, ux ? 1 : 0, c->stream));
+    return CAPIB_OK;
+}
+
+capib_status capib_write_populations(capib_ctx *c, const double *h) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!h) return fail(c, CAPIB_E_ARG, "null populations");
+    const capib_lattice &L = c->lat;
+    const size_t N = (size_t)c->pitch * L.ny;
+    std::vector<char> buf(9 * N * c->esize, 0);
+    for (int q = 0; q < 9; q++)
+        for (int j = 0; j < L.ny; j++)
+            for (int i = 0; i < L.nx; i++) {
+                const double v = h[((size_t)q * L.ny + j) * L.nx + i];
+                if (!std::isfinite(v)) return fail(c, CAPIB_E_ARG, "non-finite population");
+                const size_t k = q * N + (size_t)j * c->pitch + i;
+                if (c->esize == 4) ((float *)buf.data())[k] = (float)v;
+                else ((_Float16 *)buf.data())[k] = (_Float16)(float)(v * L.fp16_scale);
+            }
+    return h2d(c, c->off_pop[c->par], buf.data(), buf.size());
+}
+
+capib_status capib_read_populations(capib_ctx *c, double *h) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!h) return fail(c, CAPIB_E_ARG, "null output");
+    const capib_lattice &L = c->lat;
+    const size_t N = (size_t)c->pitch * L.ny;
+    std::vector<char> buf(9 * N * c->esize);
+    if ((s = d2h(c, buf.data(), c->off_pop[c->par], buf.size()))) return s;
+    for (int q = 0; q < 9; q++)
+        for (int j = 0; j < L.ny; j++)
+            for (int i = 0; i < L.nx; i++) {
+                const size_t k = q * N + (size_t)j * c->pitch + i;
+                h[((size_t)q * L.ny + j) * L.nx + i] =
+                    c->esize == 4 ? (double)((float *)buf.data())[k]
+                                  : (double)(float)((_Float16 *)buf.data())[k] / L.fp16_scale;
+            }
+    return CAPIB_OK;
+}
+
+capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *body_id) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!m || !m->xy) return fail(c, CAPIB_E_ARG, "null membrane");
+    if (m->kind < 0 || m->kind > 2) return fail(c, CAPIB_E_ARG, "bad membrane kind %d", m->kind);
+    const int n = m->n;
+    if (n < 3 || n > MAXV_BODY) return fail(c, CAPIB_E_CAPACITY, "membrane of %d vertices (3..%d)", n, MAXV_BODY);
+    if (c->nbodies + 1 > c->lat.max_bodies) return fail(c, CAPIB_E_CAPACITY, "more than %d bodies", c->lat.max_bodies);
+    if (c->nverts + n > c->lat.max_vertices)
+        return fail(c, CAPIB_E_CAPACITY, "more than %d vertices", c->lat.max_vertices);
+    if (c->step != 0) return fail(c, CAPIB_E_STATE, "membranes are added before the first step");
+    const double params[] = {m->ks, m->kb, m->ka, m->p_ref, m->density_ratio};
+    for (double p : params)
+        if (!std::isfinite(p)) return fail(c, CAPIB_E_ARG, "non-finite membrane parameter");
+    if (!(m->density_ratio > 0)) return fail(c, CAPIB_E_ARG, "density ratio must be > 0");
+    const double *xy = m->xy, *rs = m->xy_rest ? m->xy_rest : m->xy;
+    for (int k = 0; k < 2 * n; k++)
+        if (!std::isfinite(xy[k]) || !std::isfinite(rs[k])) return fail(c, CAPIB_E_ARG, "non-finite vertex");
+    for (int v = 0; v < n; v++) {
+        const double y = xy[2 * v + 1];
+        if (c->lat.walls && (y < -0.5 || y > c->lat.ny - 0.5)) return fail(c, CAPIB_E_ARG, "vertex %d outside the fluid", v);
+    }
+    // FP64 geometry of a polygon
+    auto geo = [n](const double *p, std::vector<double> &len, std::vector<double> &th, double &A, double &P,
+                   double &cx, double &cy) {
+        len.assign(n, 0); th.assign(n, 0);
+        std::vector<double> tx(n), ty(n);
+        for (int l = 0; l < n; l++) {
+            const int q = (l + 1) % n;
+            tx[l] = p[2 * q] - p[2 * l]; ty[l] = p[2 * q + 1] - p[2 * l + 1];
+            len[l] = std::sqrt(tx[l] * tx[l] + ty[l] * ty[l]);
+        }
+        for (int v = 0; v < n; v++) {
+            const int q = (v + n - 1) % n;
+            th[v] = std::atan2(tx[q] * ty[v] - ty[q] * tx[v], tx[q] * tx[v] + ty[q] * ty[v]);
+        }
+        A = 0; P = 0;
+        double sx = 0, sy = 0;
+        for (int l = 0; l < n; l++) {
+            const int q = (l + 1) % n;
+            const double xa = p[2 * l] - p[0], ya = p[2 * l + 1] - p[1], xb = p[2 * q] - p[0], yb = p[2 * q + 1] - p[1];
+            const double cr = xa * yb - xb * ya;
+            A += cr; sx += (xa + xb) * cr; sy += (ya + yb) * cr;
+            P += len[l];
+        }
+        A *= 0.5;
+        cx = p[0] + sx / (6 * A);
+        cy = p[1] + sy / (6 * A);
+    };
+    std::vector<double> l0, th0, len, th;
+    double A0, P0r, cxr, cyr, A, P, cx, cy;
+    geo(rs, l0, th0, A0, P0r, cxr, cyr);
+    geo(xy, len, th, A, P, cx, cy);
+    if (!(A > 0) || !(A0 > 0)) return fail(c, CAPIB_E_ARG, "membrane is not counter-clockwise");
+    for (int l = 0; l < n; l++)
+        if (!(l0[l] > 0) || !(len[l] > 0)) return fail(c, CAPIB_E_ARG, "degenerate element %d", l);
+    double J = 0;
+    for (int l = 0; l < n; l++) {
+        const int q = (l + 1) % n;
+        const double xa = xy[2 * l] - cx, ya = xy[2 * l + 1] - cy, xb = xy[2 * q] - cx, yb = xy[2 * q + 1] - cy;
+        const double cr = xa * yb - xb * ya;
+        J += cr * (xa * xa + xa * xb + xb * xb + ya * ya + ya * yb + yb * yb);
+    }
+    J /= 12.0;
+
+    const int b = c->nbodies, v0 = c->nverts;
+    BodyParams bp{};
+    bp.kind = m->kind; bp.n = n; bp.vstart = v0; bp.tag = m->tag;
+    bp.ks = (float)m->ks; bp.kb = (float)m->kb; bp.ka = (float)m->ka; bp.pref = (float)m->p_ref;
+    bp.vmass = (float)(m->density_ratio * A0 / n);
+    bp.inv_mass = (float)(1.0 / (m->density_ratio * A));
+    bp.inv_inertia = (float)(1.0 / (m->density_ratio * J));
+    bp.A0 = A0;
+    split(cx, bp.c0xh, bp.c0xl);
+    split(cy, bp.c0yh, bp.c0yl);
+    BodyState bs{};
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    std::vector<float> xh(n), xl(n), yh(n), yl(n), r0x(n), r0y(n), fl0(n), fth0(n);
+    std::vector<int> vb(n, b);
+    for (int v = 0; v < n; v++) {
+        split(xy[2 * v], xh[v], xl[v]);
+        split(xy[2 * v + 1], yh[v], yl[v]);
+        r0x[v] = (float)(xy[2 * v] - cx);
+        r0y[v] = (float)(xy[2 * v + 1] - cy);
+        fl0[v] = (float)l0[v];
+        fth0[v] = (float)th0[v];
+        xmin = std::min(xmin, xy[2 * v]); xmax = std::max(xmax, xy[2 * v]);
+        ymin = std::min(ymin, xy[2 * v + 1]); ymax = std::max(ymax, xy[2 * v + 1]);
+    }
+    for (int p = 0; p < 2; p++) {
+        bs.bbox[p][0] = (float)xmin; bs.bbox[p][1] = (float)xmax;
+        bs.bbox[p][2] = (float)ymin; bs.bbox[p][3] = (float)ymax;
+    }
+    const size_t fo = (size_t)v0 * 4;
+    const int pp = c->par;
+    if ((s = h2d(c, c->off_bp + b * sizeof(BodyParams), &bp, sizeof bp))) return s;
+    if ((s = h2d(c, c->off_bs + b * sizeof(BodyState), &bs, sizeof bs))) return s;
+    if ((s = h2d(c, c->off_vbody + fo, vb.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_pos[4 * pp + 0] + fo, xh.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_pos[4 * pp + 1] + fo, xl.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_pos[4 * pp + 2] + fo, yh.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_pos[4 * pp + 3] + fo, yl.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_x0[0] + fo, xh.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_x0[1] + fo, xl.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_x0[2] + fo, yh.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_x0[3] + fo, yl.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_r0x + fo, r0x.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_r0y + fo, r0y.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_l0 + fo, fl0.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_th0 + fo, fth0.data(), n * 4))) return s;
+    BodyHost bh;
+    bh.kind = m->kind; bh.n = n; bh.vstart = v0; bh.A0 = A0; bh.P0 = P;
+    bh.xy.assign(xy, xy + 2 * n);
+    c->bodies.push_back(bh);
+    c->nbodies++;
+    c->nverts += n;
+    drop_graphs(c);
+    fill_dev(c);
+    if (body_id) *body_id = b;
+    return CAPIB_OK;
+}
+
+capib_status capib_add_bonds(capib_ctx *c, int32_t body_id, const capib_bonds *bd) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!bd || body_id < 0 || body_id >= c->nbodies) return fail(c, CAPIB_E_ARG, "bad body id %d", body_id);
+    BodyHost &bh = c->bodies[body_id];
+    if (bh.has_bonds) return fail(c, CAPIB_E_STATE, "body %d already has bonds", body_id);
+    if (c->step != 0) return fail(c, CAPIB_E_STATE, "bonds are added before the first step");
+    const int ns = bd->n_sites;
+    if (ns < 0 || (ns > 0 && (!bd->host_elem || !bd->frac))) return fail(c, CAPIB_E_ARG, "bad site arrays");
+    if (c->nsites + ns > c->lat.max_sites) return fail(c, CAPIB_E_CAPACITY, "more than %d sites", c->lat.max_sites);
+    const double pr[] = {bd->sigma, bd->y_cr, bd->y_eq, bd->k_f, bd->k_r0, bd->bell_len};
+    for (double p : pr)
+        if (!std::isfinite(p)) return fail(c, CAPIB_E_ARG, "non-finite bond parameter");
+    if (!(bd->bell_len > 0) || bd->k_f < 0 || bd->k_r0 < 0) return fail(c, CAPIB_E_ARG, "bad bond rates");
+    for (int k = 0; k < ns; k++)
+        if (bd->host_elem[k] < 0 || bd->host_elem[k] >= bh.n || !(bd->frac[k] >= 0 && bd->frac[k] <= 1))
+            return fail(c, CAPIB_E_ARG, "bad site %d", k);
+    std::vector<int> perm(ns);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+        return bd->host_elem[a] != bd->host_elem[b] ? bd->host_elem[a] < bd->host_elem[b] : bd->frac[a] < bd->frac[b];
+    });
+    const int s0 = c->nsites, n = bh.n;
+    std::vector<int> host(ns), state(ns), orig(ns);
+    std::vector<float> frac(ns), anh(ns, 0), anl(ns, 0);
+    std::vector<int2> sr(n, make_int2(s0, s0));
+    int nb = 0;
+    for (int k = 0; k < ns; k++) {
+        const int q = perm[k];
+        const int e = bd->host_elem[q], mm = (e + 1) % n;
+        host[k] = bh.vstart + e;
+        frac[k] = (float)bd->frac[q];
+        orig[k] = q;
+        const double xs = bh.xy[2 * e] + bd->frac[q] * (bh.xy[2 * mm] - bh.xy[2 * e]);
+        const double ys = bh.xy[2 * e + 1] + bd->frac[q] * (bh.xy[2 * mm + 1] - bh.xy[2 * e + 1]);
+        state[k] = (ys + 0.5 < bd->y_cr) ? 1 : 0;
+        if (state[k]) split(xs, anh[k], anl[k]);
+        nb += state[k];
+    }
+    for (int k = 0; k < ns; k++) {
+        const int e = host[k] - bh.vstart;
+        if (sr[e].x == s0 && sr[e].y == s0) sr[e] = make_int2(s0 + k, s0 + k + 1);
+        else sr[e].y = s0 + k + 1;
+    }
+    // elements without sites get an empty range
+    for (int e = 0; e < n; e++)
+        if (sr[e].y == s0) sr[e] = make_int2(s0, s0);
+    BodyParams bp{};
+    if ((s = d2h(c, &bp, c->off_bp + body_id * sizeof(BodyParams), sizeof bp))) return s;
+    bp.site_start = s0; bp.n_sites = ns;
+    bp.sigma = (float)bd->sigma; bp.ycr = (float)bd->y_cr; bp.yeq = (float)bd->y_eq;
+    bp.kf = (float)bd->k_f; bp.kr0 = (float)bd->k_r0; bp.lb = (float)bd->bell_len;
+    bp.seed_lo = (uint32_t)(bd->seed & 0xffffffffu);
+    bp.seed_hi = (uint32_t)(bd->seed >> 32);
+    BodyState bs{};
+    if ((s = d2h(c, &bs, c->off_bs + body_id * sizeof(BodyState), sizeof bs))) return s;
+    bs.n_bound = nb;
+    const size_t so = (size_t)s0 * 4;
+    if ((s = h2d(c, c->off_bp + body_id * sizeof(BodyParams), &bp, sizeof bp))) return s;
+    if ((s = h2d(c, c->off_bs + body_id * sizeof(BodyState), &bs, sizeof bs))) return s;
+    if ((s = h2d(c, c->off_shost + so, host.data(), ns * 4))) return s;
+    if ((s = h2d(c, c->off_sstate + so, state.data(), ns * 4))) return s;
+    if ((s = h2d(c, c->off_sorig + so, orig.data(), ns * 4))) return s;
+    if ((s = h2d(c, c->off_sfrac + so, frac.data(), ns * 4))) return s;
+    if ((s = h2d(c, c->off_sanh + so, anh.data(), ns * 4))) return s;
+    if ((s = h2d(c, c->off_sanl + so, anl.data(), ns * 4))) return s;
+    if ((s = h2d(c, c->off_srange + (size_t)bh.vstart * 8, sr.data(), n * 8))) return s;
+    bh.has_bonds = true;
+    bh.site_start = s0;
+    bh.n_sites = ns;
+    bh.perm = perm;
+    c->nsites += ns;
+    drop_graphs(c);
+    fill_dev(c);
+    return CAPIB_OK;
+}
+
+capib_status capib_set_interactions(capib_ctx *c, double pref, double cut, double probe) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!std::isfinite(pref) || !(cut >= 0) || !std::isfinite(cut) || !std::isfinite(probe))
+        return fail(c, CAPIB_E_ARG, "bad interaction constants");
+    c->d.rep_pref = (float)pref;
+    c->d.rep_cut = (float)cut;
+    c->d.probe = (float)probe;
+    drop_graphs(c);
+    return CAPIB_OK;
+}
+
+static capib_status one_step(capib_ctx *c, int par) {
+    HIPCHK(c, launch_interp(c->d, par, c->stream));
+    HIPCHK(c, launch_body(c->d, par, c->stream));
+    HIPCHK(c, launch_lattice(c->d, par, c->stream));
+    return CAPIB_OK;
+}
+
+static capib_status make_graph(capib_ctx *c, int par) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t keep = c->stream;
+    c->stream = c->cap_stream;
+    capib_status s = one_step(c, par);
+    if (!s) s = one_step(c, par ^ 1);
+    c->stream = keep;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (s) return s;
+    if (e != hipSuccess) return fail(c, CAPIB_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, CAPIB_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    return CAPIB_OK;
+}
+
+capib_status capib_step(capib_ctx *c, int32_t nsteps) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (nsteps < 0) return fail(c, CAPIB_E_ARG, "negative step count");
+    if (c->timing) {
+        const size_t need = 4 * (size_t)nsteps;
+        while (c->ev.size() < need) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+        for (int t = 0; t < nsteps; t++) {
+            hipEvent_t *e = &c->ev[4 * t];
+            HIPCHK(c, hipEventRecord(e[0], c->stream));
+            HIPCHK(c, launch_interp(c->d, c->par, c->stream));
+            HIPCHK(c, hipEventRecord(e[1], c->stream));
+            HIPCHK(c, launch_body(c->d, c->par, c->stream));
+            HIPCHK(c, hipEventRecord(e[2], c->stream));
+            HIPCHK(c, launch_lattice(c->d, c->par, c->stream));
+            HIPCHK(c, hipEventRecord(e[3], c->stream));
+            c->par ^= 1;
+            c->step++;
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int t = 0; t < nsteps; t++) {
+            hipEvent_t *e = &c->ev[4 * t];
+            for (int k = 0; k < 3; k++) {
+                float ms = 0;
+                HIPCHK(c, hipEventElapsedTime(&ms, e[k], e[k + 1]));
+                c->ms[k] += ms;
+            }
+        }
+        c->tsteps += nsteps;
+        return CAPIB_OK;
+    }
+    int t = 0;
+    if (c->use_graph) {
+        for (; t + 2 <= nsteps; t += 2) {
+            if (!c->gexec[c->par] && (s = make_graph(c, c->par))) return s;
+            HIPCHK(c, hipGraphLaunch(c->gexec[c->par], c->stream));
+            c->step += 2;
+        }
+    }
+    for (; t < nsteps; t++) {
+        if ((s = one_step(c, c->par))) return s;
+        c->par ^= 1;
+        c->step++;
+    }
+    return CAPIB_OK;
+}
+
+capib_status capib_set_graph(capib_ctx *c, int32_t enable) {
+    if (!c) return CAPIB_E_ARG;
+    c->use_graph = enable != 0;
+    if (!c->use_graph) drop_graphs(c);
+    return CAPIB_OK;
+}
+
+capib_status capib_read_macro(capib_ctx *c, double *drho, double *ux, double *uy) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    HIPCHK(c, launch_macro(c->d, c->par, c->stream));
+    const size_t N = (size_t)c->lat.nx * c->lat.ny;
+    std::vector<float> buf(3 * N);
+    if ((s = d2h(c, buf.data(), c->off_macro, buf.size() * 4))) return s;
+    for (size_t k = 0; k < N; k++) {
+        if (drho) drho[k] = buf[k];
+        if (ux) ux[k] = buf[N + k];
+        if (uy) uy[k] = buf[2 * N + k];
+    }
+    return CAPIB_OK;
+}
+
+static capib_status check_body(capib_ctx *c, int32_t b) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (b < 0 || b >= c->nbodies) return fail(c, CAPIB_E_ARG, "bad body id %d", b);
+    return CAPIB_OK;
+}
+
+capib_status capib_read_vertices(capib_ctx *c, int32_t b, double *xy) {
+    capib_status s = check_body(c, b);
+    if (s) return s;
+    if (!xy) return fail(c, CAPIB_E_ARG, "null output");
+    const BodyHost &bh = c->bodies[b];
+    const int n = bh.n;
+    std::vector<float> a(4 * n);
+    for (int k = 0; k < 4; k++)
+        if ((s = d2h(c, a.data() + k * n, c->off_pos[4 * c->par + k] + (size_t)bh.vstart * 4, n * 4))) return s;
+    for (int v = 0; v < n; v++) {
+        xy[2 * v] = (double)a[v] + (double)a[n + v];
+        xy[2 * v + 1] = (double)a[2 * n + v] + (double)a[3 * n + v];
+    }
+    return CAPIB_OK;
+}
+
+capib_status capib_read_bonds(capib_ctx *c, int32_t b, uint8_t *state, double *anchor) {
+    capib_status s = check_body(c, b);
+    if (s) return s;
+    const BodyHost &bh = c->bodies[b];
+    const int ns = bh.n_sites;
+    std::vector<int> st(ns);
+    std::vector<float> ah(ns), al(ns);
+    const size_t so = (size_t)bh.site_start * 4;
+    if ((s = d2h(c, st.data(), c->off_sstate + so, ns * 4))) return s;
+    if ((s = d2h(c, ah.data(), c->off_sanh + so, ns * 4))) return s;
+    if ((s = d2h(c, al.data(), c->off_sanl + so, ns * 4))) return s;
+    for (int k = 0; k < ns; k++) {
+        const int q = bh.perm[k];
+        if (state) state[q] = (uint8_t)st[k];
+        if (anchor) anchor[q] = (double)ah[k] + (double)al[k];
+    }
+    return CAPIB_OK;
+}
+
+capib_status capib_read_body_work(capib_ctx *c, int32_t b, double *ustar, double *probe, double *force, double *target) {
+    capib_status s = check_body(c, b);
+    if (s) return s;
+    const BodyHost &bh = c->bodies[b];
+    const int n = bh.n;
+    std::vector<float> f(4 * n);
+    const size_t v0 = bh.vstart;
+    struct { double *dst; size_t off; int w; } items[] = {
+        {ustar, c->off_ustar + v0 * 8, 2}, {probe, c->off_probe + v0 * 16, 4},
+        {force, c->off_force + v0 * 8, 2}, {target, c->off_target + v0 * 8, 2}};
+    for (auto &it : items) {
+        if (!it.dst) continue;
+        if ((s = d2h(c, f.data(), it.off, (size_t)n * it.w * 4))) return s;
+        for (int k = 0; k < n * it.w; k++) it.dst[k] = f[k];
+    }
+    return CAPIB_OK;
+}
+
+capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!out) return fail(c, CAPIB_E_ARG, "null output");
+    HIPCHK(c, launch_diag(c->d, c->par, c->stream));
+    double r[3];
+    const size_t nblk = (size_t)c->ntx * c->nty;
+    if ((s = d2h(c, r, c->off_red + 3 * nblk * 8, 24))) return s;
+    long long cnt;
+    int err;
+    if ((s = d2h(c, &cnt, c->off_scal, 8))) return s;
+    if ((s = d2h(c, &err, c->off_scal + 8, 4))) return s;
+    out->step = c->step;
+    out->error_flags = err;
+    out->n_bodies = c->nbodies;
+    out->mass = r[0];
+    out->mom_x = r[1];
+    out->mom_y = r[2];
+    if (cnt != c->step) return fail(c, CAPIB_E_STATE, "device step counter %lld != %lld", cnt, c->step);
+    if (err) return fail(c, CAPIB_E_UNSTABLE, "device error flags 0x%x", err);
+    return CAPIB_OK;
+}
+
+capib_status capib_body_diagnostics(capib_ctx *c, int32_t b, capib_body_diag *out) {
+    capib_status s = check_body(c, b);
+    if (s) return s;
+    if (!out) return fail(c, CAPIB_E_ARG, "null output");
+    HIPCHK(c, launch_body_geom(c->d, c->par, c->stream));
+    BodyState bs;
+    if ((s = d2h(c, &bs, c->off_bs + b * sizeof(BodyState), sizeof bs))) return s;
+    const BodyHost &bh = c->bodies[b];
+    out->area = bs.geo[0];
+    out->perimeter = bs.geo[1];
+    out->cx = bs.geo[2];
+    out->cy = bs.geo[3];
+    out->area0 = bh.A0;
+    out->perimeter0 = bh.P0;
+    out->n_bound = bs.n_bound;
+    out->kind = bh.kind;
+    if (bh.kind == CAPIB_RIGID) {
+        BodyParams bp;
+        if ((s = d2h(c, &bp, c->off_bp + b * sizeof(BodyParams), sizeof bp))) return s;
+        out->xc = ((double)bp.c0xh + bp.c0xl) + ((double)bs.dcxh + bs.dcxl);
+        out->yc = ((double)bp.c0yh + bp.c0yl) + ((double)bs.dcyh + bs.dcyl);
+        out->phi = (double)bs.phih + bs.phil;
+        out->ucx = bs.ucx; out->ucy = bs.ucy; out->omega = bs.om;
+    } else {
+        out->xc = out->yc = out->phi = out->ucx = out->ucy = out->omega = 0;
+    }
+    return CAPIB_OK;
+}
+
+// checkpoint: header, current populations, IB region, scalars
+struct CkptHeader {
+    uint64_t magic;
+    int32_t nx, ny, pitch, storage, nbodies, nverts, nsites, par;
+    int64_t step;
+    uint64_t pop_bytes, ib_bytes;
+};
+static const uint64_t CKPT_MAGIC = 0x31424950414331ULL;
+
+capib_status capib_save(capib_ctx *c, void *buf, size_t *bytes) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!bytes) return fail(c, CAPIB_E_ARG, "null size");
+    const size_t pop_bytes = 9 * (size_t)c->pitch * c->lat.ny * c->esize;
+    const size_t total = sizeof(CkptHeader) + pop_bytes + c->ib_bytes + 16;
+    if (!buf) { *bytes = total; return CAPIB_OK; }
+    if (*bytes < total) return fail(c, CAPIB_E_ARG, "checkpoint buffer of %zu bytes needs %zu", *bytes, total);
+    CkptHeader h{CKPT_MAGIC, c->lat.nx, c->lat.ny, c->pitch, c->lat.storage, c->nbodies, c->nverts, c->nsites,
+                  c->par, c->step, pop_bytes, c->ib_bytes};
+    char *p = (char *)buf;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    if ((s = d2h(c, p, c->off_pop[c->par], pop_bytes))) return s;
+    p += pop_bytes;
+    if ((s = d2h(c, p, c->off_ib, c->ib_bytes))) return s;
+    p += c->ib_bytes;
+    if ((s = d2h(c, p, c->off_scal, 16))) return s;
+    *bytes = total;
+    return CAPIB_OK;
+}
+
+capib_status capib_load(capib_ctx *c, const void *buf, size_t bytes) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!buf || bytes < sizeof(CkptHeader)) return fail(c, CAPIB_E_ARG, "checkpoint too short");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    const size_t pop_bytes = 9 * (size_t)c->pitch * c->lat.ny * c->esize;
+    if (h.magic != CKPT_MAGIC || h.nx != c->lat.nx || h.ny != c->lat.ny || h.pitch != c->pitch ||
+        h.storage != c->lat.storage || h.nbodies != c->nbodies || h.nverts != c->nverts || h.nsites != c->nsites ||
+        h.pop_bytes != pop_bytes || h.ib_bytes != c->ib_bytes || (h.par != 0 && h.par != 1))
+        return fail(c, CAPIB_E_ARG, "checkpoint does not match this context");
+    if (bytes < sizeof h + pop_bytes + c->ib_bytes + 16) return fail(c, CAPIB_E_ARG, "checkpoint truncated");
+    const char *p = (const char *)buf + sizeof h;
+    // reject non-finite populations before touching the device
+    if (c->esize == 4) {
+        const float *f = (const float *)p;
+        for (size_t k = 0; k < pop_bytes / 4; k++)
+            if (!std::isfinite(f[k])) return fail(c, CAPIB_E_ARG, "checkpoint holds a non-finite population");
+    } else {
+        const _Float16 *f = (const _Float16 *)p;
+        for (size_t k = 0; k < pop_bytes / 2; k++)
+            if (!std::isfinite((float)f[k])) return fail(c, CAPIB_E_ARG, "checkpoint holds a non-finite population");
+    }
+    drop_graphs(c);
+    c->par = h.par;
+    c->step = h.step;
+    if ((s = h2d(c, c->off_pop[c->par], p, pop_bytes))) return s;
+    p += pop_bytes;
+    if ((s = h2d(c, c->off_ib, p, c->ib_bytes))) return s;
+    p += c->ib_bytes;
+    if ((s = h2d(c, c->off_scal, p, 16))) return s;
+    // spread-force field and tile tags start clean
+    HIPCHK(c, hipMemsetAsync(c->base + c->off_fib, 0, 2 * (size_t)c->pitch * c->lat.ny * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->base + c->off_tflag, 0, (size_t)c->ntx * c->nty * 4, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CAPIB_OK;
+}
+
+capib_status capib_set_timing(capib_ctx *c, int32_t enable) {
+    if (!c) return CAPIB_E_ARG;
+    c->timing = enable != 0;
+    return CAPIB_OK;
+}
+
+capib_status capib_read_timing(capib_ctx *c, double *ms3, int64_t *steps) {
+    if (!c || !ms3) return CAPIB_E_ARG;
+    for (int k = 0; k < 3; k++) { ms3[k] = c->ms[k]; c->ms[k] = 0; }
+    if (steps) *steps = c->tsteps;
+    c->tsteps = 0;
+    return CAPIB_OK;
+}
+
+const char *capib_last_error(const capib_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void capib_destroy(capib_ctx *c) {
+    if (!c) return;
+    if (c->bound) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Device-side data layout and helpers shared by the kernels of libcapib.
+// gfx950 only: wave64, LDS-resident membranes, int64 fixed-point spreading.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace capib {
+
+// Lattice sweep tile: one wave per row segment of 64 nodes, four rows per
+// workgroup.  The spread-force tile flags use the same tiling.
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 4;
+constexpr int LAT_THREADS = TILE_X * TILE_Y;
+constexpr int MAXV_BODY = 1024;    // vertices of one membrane held in LDS
+constexpr int BODY_THREADS = 256;
+constexpr int INTERP_THREADS = 256;  // 16 lanes per interpolation point
+// Spread forces accumulate as int64 with 56 fractional bits: exact,
+// order-independent sums; contributions must stay below 2^7 in magnitude.
+constexpr float FIX_ONE = 72057594037927936.0f;   // 2^56
+constexpr float FIX_INV = 1.3877787807814457e-17f; // 2^-56
+constexpr float FIX_LIMIT = 127.0f;
+
+enum { DEFORMABLE = 0, RIGID = 1, FIXED = 2 };
+enum { FLAG_VERTEX_OUT = 1, FLAG_FLUID = 2, FLAG_FORCE_RANGE = 4, FLAG_NONFINITE_IB = 8 };
+
+// Read-only description of a body.
+struct BodyParams {
+    int kind, n, vstart, tag;
+    int site_start, n_sites, pad0, pad1;
+    float ks, kb, ka, pref;
+    float vmass, inv_mass, inv_inertia, pad2;
+    double A0;
+    float sigma, ycr, yeq, kf;
+    float kr0, lb;
+    uint32_t seed_lo, seed_hi;
+    float c0xh, c0xl, c0yh, c0yl;   // rigid: centroid at t = 0 (hi + lo)
+};
+
+// Mutable per-body state.
+struct BodyState {
+    float dcxh, dcxl, dcyh, dcyl;   // rigid: centroid displacement (hi + lo)
+    float phih, phil;               // rigid: rotation angle (hi + lo)
+    float ucx, ucy, ucxm, ucym, om, omm;  // rigid: u, omega at n and n-1
+    float bbox[2][4];               // xmin, xmax, ymin, ymax of the vertices, parity-indexed
+    int n_bound, pad;
+    double geo[4];                  // diagnostics: area, perimeter, cx, cy
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+    int nx, ny, pitch, walls;
+    int ntx, nty, storage, pad0;
+    long long qstride;              // ny * pitch elements per population
+    float omega, fc, gx, gy;        // 1/tau, 1 - 1/(2 tau), body force
+    float scale, inv_scale;         // FP16 storage scale
+    void *pop[2];                   // populations, parity-indexed
+    long long *fib;                 // spread force [ny][pitch][2], 2^-56 units
+    uint32_t *tflag;                // per tile: step tag of the last spread into it
+    // immersed boundary
+    int nbodies, nverts, nsites, pad1;
+    float rep_pref, rep_cut, rep_dmin, probe;
+    BodyParams *bp;
+    BodyState *bs;
+    int *vbody;
+    float *pxh[2], *pxl[2], *pyh[2], *pyl[2];   // vertex positions, parity-indexed
+    float *dxm, *dym;                           // previous increment x^n - x^{n-1}
+    float *x0h, *x0l, *y0h, *y0l;               // positions at t = 0
+    float *r0x, *r0y;                           // rigid: offsets from the centroid at t = 0
+    float *l0, *th0;                            // rest lengths and turning angles
+    float2 *ustar;                              // u* at vertices
+    float4 *probe4;                             // p, sxx, sxy, syy at element probes
+    float2 *force;                              // total Lagrangian force
+    float2 *target;                             // U^{n+1}
+    int2 *srange;                               // sites [begin, end) per element
+    int *s_host, *s_state, *s_orig;
+    float *s_frac, *s_anh, *s_anl;
+    // scalars and scratch
+    long long *counter;   // steps started
+    int *err;             // sticky error flags
+    double *red;          // reduction partials
+    float *macro;         // [3][ny][nx] readout
+    double *uinit;        // [ny] initial profile
+};
+
+// ---- small helpers -------------------------------------------------------------
+
+// Workgroup index -> tile index such that each XCD (workgroups are dealt
+// round-robin to the 8 XCDs) receives one contiguous range of tiles, so that
+// neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    int q = nb >> 3, r = nb & 7;
+    int x = b & 7, local = b >> 3;
+    return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Error-free sum of a float pair (hi, lo) and a float d, renormalised.
+__device__ __forceinline__ void df_add(float &hi, float &lo, float d) {
+    float s = hi + d;
+    float bb = s - hi;
+    float err = (hi - (s - bb)) + (d - bb);
+    float l = lo + err;
+    float h = s + l;
+    lo = l - (h - s);
+    hi = h;
+}
+
+// Cosine-kernel stencil of a point given as hi + lo: node offsets and the
+// 4 + 4 one-dimensional weights phi(X - i), phi(Y - j) for i = ix0 .. ix0+3,
+// j = iy0 .. iy0+3.  With walls, Y is clamped to [-1, ny], rows outside the
+// fluid get weight zero; 'inv' divides every product weight so that the 16
+// weights sum to one.  Returns true when the unclamped Y left [-1, ny].
+__device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float yh, float yl,
+                                        int &ix0, int &iy0, float wx[4], float wy[4], float &inv) {
+    bool out = false;
+    // non-finite or absurd coordinates are flagged and mapped to the origin so
+    // that every index below stays in range
+    if (!(fabsf(xh) < 1.0e8f) || !(fabsf(xl) < 1.0e4f)) { xh = 0.0f; xl = 0.0f; out = true; }
+    if (!(fabsf(yh) < 1.0e8f) || !(fabsf(yl) < 1.0e4f)) { yh = 0.0f; yl = 0.0f; out = true; }
+    int ix = (int)floorf(xh);
+    float sx = (xh - (float)ix) + xl;
+    float kx = floorf(sx);
+    ix += (int)kx;
+    sx -= kx;
+    int iy;
+    float sy;
+    if (d.walls) {
+        float Y = yh + yl;
+        if (Y < -1.0f) { Y = -1.0f; out = true; yh = -1.0f; yl = 0.0f; }
+        if (Y > (float)d.ny) { Y = (float)d.ny; out = true; yh = (float)d.ny; yl = 0.0f; }
+    }
+    iy = (int)floorf(yh);
+    sy = (yh - (float)iy) + yl;
+    float ky = floorf(sy);
+    iy += (int)ky;
+    sy -= ky;
+    float cx, snx, cy, sny;
+    sincospif(0.5f * sx, &snx, &cx);
+    sincospif(0.5f * sy, &sny, &cy);
+    // phi(1+s), phi(s), phi(s-1), phi(s-2) with phi(r) = (1 + cos(pi r/2))/4
+    wx[0] = 0.25f * (1.0f - snx); wx[1] = 0.25f * (1.0f + cx);
+    wx[2] = 0.25f * (1.0f + snx); wx[3] = 0.25f * (1.0f - cx);
+    wy[0] = 0.25f * (1.0f - sny); wy[1] = 0.25f * (1.0f + cy);
+    wy[2] = 0.25f * (1.0f + sny); wy[3] = 0.25f * (1.0f - cy);
+    ix0 = ix - 1;
+    iy0 = iy - 1;
+    if (d.walls) {
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            int j = iy0 + b;
+            if (j < 0 || j >= d.ny) wy[b] = 0.0f;
+        }
+    }
+    float sxw = (wx[0] + wx[1]) + (wx[2] + wx[3]);
+    float syw = (wy[0] + wy[1]) + (wy[2] + wy[3]);
+    inv = 1.0f / (sxw * syw);
+    return out;
+}
+
+// Streamed (pulled) populations at node (i, j): h_q(x) = A_q(x - e_q), with
+// halfway bounce-back across the walls and periodic wrap otherwise.
+template <typename T>
+__device__ __forceinline__ float ldpop(const T *p, float inv_scale);
+template <>
+__device__ __forceinline__ float ldpop<float>(const float *p, float) { return *p; }
+template <>
+__device__ __forceinline__ float ldpop<_Float16>(const _Float16 *p, float inv_scale) {
+    return (float)(*p) * inv_scale;
+}
+
+template <typename T>
+__device__ __forceinline__ void pull9(const Dev &d, const T *__restrict__ A, int i, int j, float h[9]) {
+    const long long Q = d.qstride;
+    const int im = (i == 0) ? d.nx - 1 : i - 1;
+    const int ip = (i == d.nx - 1) ? 0 : i + 1;
+    const bool bot = (j == 0), top = (j == d.ny - 1);
+    const int jm = bot ? d.ny - 1 : j - 1;
+    const int jp = top ? 0 : j + 1;
+    const long long r0 = (long long)j * d.pitch, rm = (long long)jm * d.pitch, rp = (long long)jp * d.pitch;
+    const float is = d.inv_scale;
+    h[0] = ldpop(A + r0 + i, is);
+    h[1] = ldpop(A + Q + r0 + im, is);
+    h[3] = ldpop(A + 3 * Q + r0 + ip, is);
+    if (d.walls && bot) {
+        h[2] = ldpop(A + 4 * Q + r0 + i, is);
+        h[5] = ldpop(A + 7 * Q + r0 + i, is);
+        h[6] = ldpop(A + 8 * Q + r0 + i, is);
+    } else {
+        h[2] = ldpop(A + 2 * Q + rm + i, is);
+        h[5] = ldpop(A + 5 * Q + rm + im, is);
+        h[6] = ldpop(A + 6 * Q + rm + ip, is);
+    }
+    if (d.walls && top) {
+        h[4] = ldpop(A + 2 * Q + r0 + i, is);
+        h[7] = ldpop(A + 5 * Q + r0 + i, is);
+        h[8] = ldpop(A + 6 * Q + r0 + i, is);
+    } else {
+        h[4] = ldpop(A + 4 * Q + rp + i, is);
+        h[7] = ldpop(A + 7 * Q + rp + ip, is);
+        h[8] = ldpop(A + 8 * Q + rp + im, is);
+    }
+}
+
+// Counter-based generator: Philox4x32-10 (Salmon et al., SC'11), word 0.
+__device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return c0;
+}
+
+}  // namespace capib

@@ -1,0 +1,221 @@
+// Lattice sweep of the LBM-IB step: pull streaming with halfway bounce-back
+// walls (Eq. 1; no-slip capillary walls of Sec. 3.1), moments (Sec. 2.1,
+// Eqs. 5-6), the Hermite equilibrium (Eq. 2) and the BGK collision with the
+// Guo forcing term (Eq. 4) for the total force g + f_ib, fused in one pass
+// that reads 9 and writes 9 populations per node.
+//
+// Layout: structure of arrays pop[q][j][i], i fastest, row pitch a multiple
+// of 64 elements, two buffers swapped every step.  Populations are stored as
+// deviations h = f - w from the rest state, FP32 or FP16 (scaled).
+#include "capib_dev.hpp"
+#include "capib_kernels.hpp"
+
+namespace capib {
+
+template <typename T>
+__device__ __forceinline__ T stpop(float v, float scale);
+template <>
+__device__ __forceinline__ float stpop<float>(float v, float) { return v; }
+template <>
+__device__ __forceinline__ _Float16 stpop<_Float16>(float v, float scale) { return (_Float16)(v * scale); }
+
+template <typename T>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice(Dev d, int par) {
+    const T *__restrict__ A = (const T *)d.pop[par];
+    T *__restrict__ B = (T *)d.pop[par ^ 1];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int ty = tile / d.ntx;
+    const int tx = tile - ty * d.ntx;
+    const int i = tx * TILE_X + (threadIdx.x & (TILE_X - 1));
+    const int j = ty * TILE_Y + (threadIdx.x / TILE_X);
+    if (i >= d.nx || j >= d.ny) return;
+    float h[9];
+    pull9<T>(d, A, i, j, h);
+
+    // moments of the streamed populations
+    const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+    const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+    const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+
+    // total force: uniform drive plus the spread IB force of this step
+    float Fx = d.gx, Fy = d.gy;
+    const long long node = (long long)j * d.pitch + i;
+    const uint32_t tag = (uint32_t)(*d.counter);
+    if (d.tflag[tile] == tag) {
+        long long *f = d.fib + 2 * node;
+        long long qx = f[0], qy = f[1];
+        if (qx | qy) {
+            Fx += (float)qx * FIX_INV;
+            Fy += (float)qy * FIX_INV;
+            f[0] = 0;
+            f[1] = 0;
+        }
+    }
+
+    const float rho = 1.0f + drho;
+    const float irho = 1.0f / rho;
+    const float ux = (jx + 0.5f * Fx) * irho;
+    const float uy = (jy + 0.5f * Fy) * irho;
+    const float uu = ux * ux + uy * uy;
+    if (!(rho > 0.0f) || !(uu < 0.03f)) atomicOr(d.err, FLAG_FLUID);  // NaN fails both tests
+
+    // h' = (1 - omega) h + omega h_eq + F_i with
+    // h_eq = w [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)]
+    // F_i  = (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
+    const float om = d.omega, om1 = 1.0f - d.omega, fc = d.fc;
+    const float uF = ux * Fx + uy * Fy;
+    const float base = drho - 1.5f * rho * uu;   // drho + rho(-1.5 u.u)
+    const float fb = -3.0f * uF;                 // 3 (-u).F
+    float out[9];
+    {
+        const float w = 4.0f / 9.0f;
+        out[0] = om1 * h[0] + om * w * base + fc * w * fb;
+    }
+#define CAPIB_DIR(q, ex, ey, w)                                                              \
+    {                                                                                        \
+        const float eu = (ex) * ux + (ey) * uy;                                              \
+        const float eF = (ex) * Fx + (ey) * Fy;                                              \
+        const float heq = (w) * (base + rho * (3.0f * eu + 4.5f * eu * eu));                 \
+        const float Fi = fc * (w) * (fb + 3.0f * eF + 9.0f * eu * eF);                       \
+        out[q] = om1 * h[q] + om * heq + Fi;                                                 \
+    }
+    CAPIB_DIR(1, 1.0f, 0.0f, 1.0f / 9.0f)
+    CAPIB_DIR(2, 0.0f, 1.0f, 1.0f / 9.0f)
+    CAPIB_DIR(3, -1.0f, 0.0f, 1.0f / 9.0f)
+    CAPIB_DIR(4, 0.0f, -1.0f, 1.0f / 9.0f)
+    CAPIB_DIR(5, 1.0f, 1.0f, 1.0f / 36.0f)
+    CAPIB_DIR(6, -1.0f, 1.0f, 1.0f / 36.0f)
+    CAPIB_DIR(7, -1.0f, -1.0f, 1.0f / 36.0f)
+    CAPIB_DIR(8, 1.0f, -1.0f, 1.0f / 36.0f)
+#undef CAPIB_DIR
+    const long long Q = d.qstride;
+#pragma unroll
+    for (int q = 0; q < 9; q++) B[q * Q + node] = stpop<T>(out[q], d.scale);
+}
+
+// Moments of the current state for read-out: drho and u* = (j + g/2)/rho.
+template <typename T>
+__global__ __launch_bounds__(LAT_THREADS) void k_macro(Dev d, int par) {
+    const T *__restrict__ A = (const T *)d.pop[par];
+    const int i = blockIdx.x * TILE_X + (threadIdx.x & (TILE_X - 1));
+    const int j = blockIdx.y * TILE_Y + (threadIdx.x / TILE_X);
+    if (i >= d.nx || j >= d.ny) return;
+    float h[9];
+    pull9<T>(d, A, i, j, h);
+    const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+    const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+    const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+    const float irho = 1.0f / (1.0f + drho);
+    const long long N = (long long)d.nx * d.ny, k = (long long)j * d.nx + i;
+    d.macro[k] = drho;
+    d.macro[N + k] = (jx + 0.5f * d.gx) * irho;
+    d.macro[2 * N + k] = (jy + 0.5f * d.gy) * irho;
+}
+
+// Equilibrium populations at drho = 0 and u = (uinit[j], 0), in FP64, rounded once.
+template <typename T>
+__global__ __launch_bounds__(LAT_THREADS) void k_init_flow(Dev d, int par, int has_profile) {
+    T *__restrict__ A = (T *)d.pop[par];
+    const int i = blockIdx.x * TILE_X + (threadIdx.x & (TILE_X - 1));
+    const int j = blockIdx.y * TILE_Y + (threadIdx.x / TILE_X);
+    if (i >= d.nx || j >= d.ny) return;
+    const double u = has_profile ? d.uinit[j] : 0.0;
+    const double ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const long long node = (long long)j * d.pitch + i;
+    for (int q = 0; q < 9; q++) {
+        const double eu = ex[q] * u;
+        const double heq = w[q] * (3.0 * eu + 4.5 * eu * eu - 1.5 * u * u);
+        A[q * d.qstride + node] = stpop<T>((float)heq, d.scale);
+    }
+}
+
+// FP64 partial sums per tile of the stored populations: sum h, sum h e.
+template <typename T>
+__global__ __launch_bounds__(LAT_THREADS) void k_diag_partial(Dev d, int par) {
+    const T *__restrict__ A = (const T *)d.pop[par];
+    const int i = blockIdx.x * TILE_X + (threadIdx.x & (TILE_X - 1));
+    const int j = blockIdx.y * TILE_Y + (threadIdx.x / TILE_X);
+    double m = 0, px = 0, py = 0;
+    if (i < d.nx && j < d.ny) {
+        const long long node = (long long)j * d.pitch + i;
+        double h[9];
+        for (int q = 0; q < 9; q++) h[q] = (double)ldpop<T>(A + q * d.qstride + node, d.inv_scale);
+        m = h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6] + h[7] + h[8];
+        px = h[1] - h[3] + h[5] - h[6] - h[7] + h[8];
+        py = h[2] - h[4] + h[5] + h[6] - h[7] - h[8];
+    }
+    __shared__ double sm[3][LAT_THREADS];
+    sm[0][threadIdx.x] = m;
+    sm[1][threadIdx.x] = px;
+    sm[2][threadIdx.x] = py;
+    __syncthreads();
+    for (int s = LAT_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 3; c++) sm[c][threadIdx.x] += sm[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        d.red[3 * blk + threadIdx.x] = sm[threadIdx.x][0];
+    }
+}
+
+// Fixed-order final sum of the partials into red[3 * nblk .. +2].
+__global__ __launch_bounds__(256) void k_diag_final(Dev d, int nblk) {
+    __shared__ double sm[3][256];
+    double a[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int c = 0; c < 3; c++) a[c] += d.red[3 * b + c];
+    for (int c = 0; c < 3; c++) sm[c][threadIdx.x] = a[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 3; c++) sm[c][threadIdx.x] += sm[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) d.red[3 * (long long)nblk + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// ---- host launchers ---------------------------------------------------------------
+
+hipError_t launch_lattice(const Dev &d, int par, hipStream_t st) {
+    const int nb = d.ntx * d.nty;
+    if (d.storage == 0)
+        hipLaunchKernelGGL(k_lattice<float>, dim3(nb), dim3(LAT_THREADS), 0, st, d, par);
+    else
+        hipLaunchKernelGGL(k_lattice<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, d, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro(const Dev &d, int par, hipStream_t st) {
+    dim3 g(d.ntx, d.nty);
+    if (d.storage == 0)
+        hipLaunchKernelGGL(k_macro<float>, g, dim3(LAT_THREADS), 0, st, d, par);
+    else
+        hipLaunchKernelGGL(k_macro<_Float16>, g, dim3(LAT_THREADS), 0, st, d, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_flow(const Dev &d, int par, int has_profile, hipStream_t st) {
+    dim3 g(d.ntx, d.nty);
+    if (d.storage == 0)
+        hipLaunchKernelGGL(k_init_flow<float>, g, dim3(LAT_THREADS), 0, st, d, par, has_profile);
+    else
+        hipLaunchKernelGGL(k_init_flow<_Float16>, g, dim3(LAT_THREADS), 0, st, d, par, has_profile);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const Dev &d, int par, hipStream_t st) {
+    dim3 g(d.ntx, d.nty);
+    if (d.storage == 0)
+        hipLaunchKernelGGL(k_diag_partial<float>, g, dim3(LAT_THREADS), 0, st, d, par);
+    else
+        hipLaunchKernelGGL(k_diag_partial<_Float16>, g, dim3(LAT_THREADS), 0, st, d, par);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, d, d.ntx * d.nty);
+    return hipGetLastError();
+}
+
+}  // namespace capib

@@ -14,3 +14,20 @@ def oracle_sim(cfg: inputs.Config) -> "oracle.Sim":
     for bd in cfg.bonds:
         s.add_bonds(bd.body, bd.host, bd.frac, bd.sigma, bd.ycr, bd.yeq, bd.kf, bd.kr0, bd.lb, bd.seed)
     return s
+
+
+def gpu_sim(cfg: inputs.Config, **kw):
+    from paper_2210_06043_amd import capib
+    return capib.from_config(cfg, **kw)
+
+
+def rel_max(a, b):
+    """max |a - b| / max |b| (max-norm relative error)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def say(*a):
+    print(*a, flush=True)

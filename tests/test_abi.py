@@ -1,0 +1,103 @@
+"""The C-ABI library builds, loads and exports every symbol its header
+declares; host-side argument validation works without a GPU (no compute
+calls are made here)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2210_06043_amd import capib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "capib.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(capib_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["capib_create", "capib_bind_workspace", "capib_init_flow", "capib_add_membrane",
+                 "capib_add_bonds", "capib_step", "capib_read_macro", "capib_read_vertices", "capib_read_bonds",
+                 "capib_diagnostics", "capib_save", "capib_load", "capib_destroy"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = capib.load_library()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", capib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (capib_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_binding_covers_the_header():
+    assert set(capib.SIGNATURES) == set(declared_functions())
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and field offsets of the ABI structs seen by a C compiler equal
+    the ctypes mirrors of the binding."""
+    structs = {
+        "capib_lattice": capib.capib_lattice, "capib_membrane": capib.capib_membrane,
+        "capib_bonds": capib.capib_bonds, "capib_diag": capib.capib_diag,
+        "capib_body_diag": capib.capib_body_diag,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append(f'printf("{sname} %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{sname}.{fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", str(c), "-o", str(exe)])
+    got = dict(ln.split() for ln in subprocess.check_output([str(exe)], text=True).splitlines())
+    for sname, cls in structs.items():
+        assert int(got[sname]) == C.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{sname}.{fname}"]) == getattr(cls, fname).offset, f"{sname}.{fname}"
+
+
+def _create(**kw):
+    L = capib.load_library()
+    base = dict(nx=32, ny=16, tau=1.0, gx=0.0, gy=0.0, walls=3, storage=0, fp16_scale=1.0, max_bodies=2,
+                max_vertices=64, max_sites=16)
+    base.update(kw)
+    lat = capib.capib_lattice(**base)
+    ctx = C.c_void_p()
+    st = L.capib_create(C.byref(lat), None, C.byref(ctx))
+    return L, st, ctx
+
+
+@pytest.mark.parametrize("bad", [dict(tau=0.5), dict(tau=0.3), dict(walls=1), dict(ny=1), dict(nx=0),
+                                 dict(storage=7), dict(storage=1, fp16_scale=3.0), dict(tau=float("nan")),
+                                 dict(max_sites=-1)])
+def test_create_rejects_bad_lattices(bad):
+    L, st, ctx = _create(**bad)
+    assert st == capib.CAPIB_E_ARG
+    assert not ctx.value
+
+
+def test_create_sizes_the_workspace_and_checks_order():
+    L, st, ctx = _create()
+    assert st == capib.CAPIB_OK
+    n = L.capib_workspace_bytes(ctx)
+    # two population buffers of 9 x 16 x 64 floats at least
+    assert n >= 2 * 9 * 16 * 64 * 4 and n % 256 == 0
+    # nothing may run before a workspace is bound
+    assert L.capib_step(ctx, 1) == capib.CAPIB_E_STATE
+    assert b"workspace" in L.capib_last_error(ctx)
+    assert L.capib_bind_workspace(ctx, C.c_void_p(12345), n) == capib.CAPIB_E_ARG   # misaligned
+    L.capib_destroy(ctx)
+    L2, st2, ctx2 = _create(storage=1, fp16_scale=2.0 ** 16)
+    assert st2 == capib.CAPIB_OK
+    assert L2.capib_workspace_bytes(ctx2) < n      # FP16 populations take half the bytes
+    L2.capib_destroy(ctx2)

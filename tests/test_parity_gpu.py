@@ -1,0 +1,178 @@
+"""HIP path against the FP64 oracle, element by element on the same seeded
+inputs (spec tolerance 1e-5 relative for FP32 storage; bond states and
+N_L exact).  All calls go through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import gpu_sim, oracle_sim, rel_max, say
+from paper_2210_06043_amd import capib, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _perturb(cfg, seed, amp):
+    """Seeded perturbation of the initial populations, written to both sides."""
+    o = oracle_sim(cfg)
+    A = o.populations()
+    rng = np.random.default_rng(seed)
+    A = A + amp * rng.standard_normal(A.shape)
+    A32 = A.astype(np.float32).astype(np.float64)    # both start from the same representable state
+    o.set_populations(A32)
+    g = gpu_sim(cfg)
+    g.write_populations(A32)
+    return o, g
+
+
+@pytest.mark.parametrize("walls,nx,ny,tau", [(3, 37, 22, 0.8), (0, 70, 9, 1.3), (3, 130, 7, 0.55)])
+def test_lattice_sweep_parity(walls, nx, ny, tau):
+    """Lattice sweep alone (no bodies) over several tiles with ragged edges:
+    u* and drho after 200 steps from a perturbed state."""
+    say(f"lattice parity walls={walls} {nx}x{ny} tau={tau}")
+    cfg = inputs.lattice_only(nx, ny, tau, walls=walls, umax=1e-3)
+    o, g = _perturb(cfg, 1, 2e-4)
+    o.step(200)
+    g.step(200)
+    ro, uxo, uyo = o.macro()
+    rg, uxg, uyg = g.macro()
+    assert rel_max(np.stack([uxg, uyg]), np.stack([uxo, uyo])) < TOL
+    assert np.abs(rg - ro).max() < 1e-6 * max(np.abs(ro).max(), 1e-4)
+    d = g.diagnostics()
+    assert d["step"] == 200 and d["error_flags"] == 0
+    # FP64 device sum of the populations equals the (conserved) oracle mass
+    assert abs(d["mass"] - o.totals()[0]) < 1e-9
+
+
+def test_first_step_interpolation_and_forces():
+    """One coupled step of the small channel: interpolated u*, probe pressure
+    and stress, Lagrangian forces and target velocities per vertex."""
+    say("first-step IB parity, tiny config")
+    cfg = inputs.config_tiny()
+    o = oracle_sim(cfg)
+    g = gpu_sim(cfg)
+    o.step(1)
+    g.step(1)
+    for k in range(len(cfg.bodies)):
+        wo, wg = o.body_work(k), g.body_work(k)
+        assert rel_max(wg["ustar"], wo["ustar"]) < TOL, k
+        assert rel_max(wg["probe"], wo["probe"]) < 1e-4, k
+        assert rel_max(wg["force"], wo["force"]) < 1e-4, k
+        assert rel_max(wg["U"], wo["U"]) < TOL, k
+        np.testing.assert_allclose(g.vertices(k), o.vertices(k), rtol=0, atol=1e-9)
+
+
+def _compare_run(cfg, steps, label, o=None, g=None):
+    o = o or oracle_sim(cfg)
+    g = g or gpu_sim(cfg)
+    x0 = [o.vertices(k).copy() for k in range(len(cfg.bodies))]
+    o.step(steps)
+    g.step(steps)
+    _, uxo, uyo = o.macro()
+    _, uxg, uyg = g.macro()
+    eu = rel_max(np.stack([uxg, uyg]), np.stack([uxo, uyo]))
+    say(f"{label}: velocity rel err {eu:.3e}")
+    assert eu < TOL
+    for k in range(len(cfg.bodies)):
+        xo, xg = o.vertices(k), g.vertices(k)
+        assert rel_max(xg, xo) < TOL
+        dx = rel_max(xg - x0[k], xo - x0[k])
+        say(f"{label}: body {k} displacement rel err {dx:.3e} (max disp {np.abs(xo - x0[k]).max():.3e})")
+        assert dx < TOL
+    margin = o.min_margin
+    say(f"{label}: min bond-decision margin {margin:.3e}")
+    for bd in cfg.bonds:
+        so, ao = o.bonds(bd.body)
+        sg, ag = g.bonds(bd.body)
+        if margin > 1e-6:
+            assert np.array_equal(so, sg)
+            np.testing.assert_allclose(ag[so == 1], ao[so == 1], rtol=0, atol=1e-5)
+            assert g.body_diagnostics(bd.body)["n_bound"] == o.count_bound(bd.body)
+    d = g.diagnostics()
+    assert d["error_flags"] == 0
+    return o, g
+
+
+def test_tiny_coupled_parity():
+    """Small channel, deformable cell and bonded rigid particle, 300 steps."""
+    say("tiny coupled parity")
+    _compare_run(inputs.config_tiny(), 300, "tiny")
+
+
+def test_tiny_fixed_body_periodic_parity():
+    """Fully periodic box with a deformable cell and a fixed obstacle."""
+    say("tiny periodic fixed-body parity")
+    cfg = inputs.config_tiny(walls=0, kinds=(inputs.DEFORMABLE, inputs.FIXED))
+    _compare_run(cfg, 200, "tiny-periodic")
+
+
+def test_c1_full_run_parity():
+    """The small workload (480x60, cell + bonded rigid ellipse), all 2000 steps."""
+    say("C1 2000-step parity")
+    cfg = inputs.config_c1()
+    _compare_run(cfg, cfg.steps, "c1")
+
+
+def test_c2_window_parity():
+    """The paper-scale workload (3840x240, six cells, particle, 200 bonds) at
+    full size, first 60 steps, in the launch configuration the benchmark
+    times (graphs on)."""
+    say("C2 window parity")
+    cfg = inputs.config_c2(seed=0)
+    g = gpu_sim(cfg, graph=True)
+    _compare_run(cfg, 60, "c2", g=g)
+
+
+def test_determinism_and_graph_equivalence():
+    """Two runs, and a run replayed through HIP graphs, are bitwise identical
+    (deterministic fixed-point spreading: a race would show up here)."""
+    say("determinism")
+    cfg = inputs.config_tiny()
+    res = []
+    for graph in (False, False, True):
+        g = gpu_sim(cfg, graph=graph)
+        g.step(51)
+        res.append((g.read_populations(), g.vertices(0), g.vertices(1), g.bonds(1)[0]))
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert np.array_equal(a, b)
+
+
+def test_checkpoint_resume_bitwise():
+    """N steps, save, N more == 2N steps; a restored checkpoint continues
+    identically; a checkpoint with a non-finite population is refused."""
+    say("checkpoint")
+    cfg = inputs.config_tiny()
+    g1 = gpu_sim(cfg)
+    g1.step(40)
+    blob = g1.save()
+    g1.step(40)
+    g2 = gpu_sim(cfg)
+    g2.load(blob)
+    g2.step(40)
+    assert np.array_equal(g1.read_populations(), g2.read_populations())
+    assert np.array_equal(g1.vertices(0), g2.vertices(0))
+    assert np.array_equal(g1.bonds(1)[0], g2.bonds(1)[0])
+    assert g2.diagnostics()["step"] == 80
+    bad = bytearray(blob)
+    hdr = 72                        # checkpoint header: magic, 9 ints, padding, step, two sizes
+    bad[hdr:hdr + 4] = np.array([np.nan], np.float32).tobytes()
+    with pytest.raises(capib.CapibError) as e:
+        g2.load(bytes(bad))
+    assert e.value.status == capib.CAPIB_E_ARG
+
+
+def test_unstable_state_is_reported():
+    """A state with |u| beyond 0.3 c_s raises the sticky device flag and the
+    diagnostics return CAPIB_E_UNSTABLE (forced from the host)."""
+    say("instability flag")
+    cfg = inputs.lattice_only(16, 8, 1.0)
+    g = gpu_sim(cfg)
+    h = g.read_populations()
+    h[1] += 0.15                   # +x populations: u_x ~ 0.3 per node
+    g.write_populations(h)
+    g.step(1)
+    d = g.diagnostics(allow_unstable=True)
+    assert d["status"] == capib.CAPIB_E_UNSTABLE
+    assert d["error_flags"] & capib.FLAG_FLUID

@@ -45,7 +45,7 @@ struct capib_ctx {
     size_t esize = 4;
     // workspace layout
     size_t ws_bytes = 0;
-    size_t off_pop[2]{}, off_fib = 0, off_tflag = 0, off_red = 0, off_macro = 0, off_uinit = 0, off_scal = 0;
+    size_t off_pop[2]{}, off_fib = 0, off_tflag = 0, off_red = 0, off_macro = 0, off_rowref = 0, off_scal = 0;
     size_t off_ib = 0, ib_bytes = 0;
     size_t off_bp = 0, off_bs = 0, off_vbody = 0, off_pos[8]{}, off_dxm = 0, off_dym = 0, off_x0[4]{};
     size_t off_r0x = 0, off_r0y = 0, off_l0 = 0, off_th0 = 0, off_ustar = 0, off_probe = 0, off_force = 0;
@@ -57,6 +57,7 @@ struct capib_ctx {
     long long step = 0;
     int nbodies = 0, nverts = 0, nsites = 0;
     std::vector<BodyHost> bodies;
+    std::vector<double> ref_u;     // reference x-velocity per row (FP64)
     std::string err = "no error";
     // timing
     bool timing = false;
@@ -93,7 +94,7 @@ static void layout(capib_ctx *c) {
     c->off_tflag = o; o = align256(o + (size_t)c->ntx * c->nty * 4);
     c->off_red = o; o = align256(o + (3 * (size_t)c->ntx * c->nty + 3) * 8);
     c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
-    c->off_uinit = o; o = align256(o + (size_t)L.ny * 8);
+    c->off_rowref = o; o = align256(o + (size_t)L.ny * 16 * 4);
     c->off_scal = o; o = align256(o + 64);
     // IB region: one contiguous block (checkpointed whole)
     const size_t B = (size_t)std::max(1, L.max_bodies), V = (size_t)std::max(1, L.max_vertices),
@@ -142,7 +143,7 @@ static void fill_dev(capib_ctx *c) {
     d.tflag = (uint32_t *)(b + c->off_tflag);
     d.red = (double *)(b + c->off_red);
     d.macro = (float *)(b + c->off_macro);
-    d.uinit = (double *)(b + c->off_uinit);
+    d.rowref = (const float *)(b + c->off_rowref);
     d.counter = (long long *)(b + c->off_scal);
     d.err = (int *)(b + c->off_scal + 8);
     d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites;
@@ -195,6 +196,42 @@ static capib_status d2h(capib_ctx *c, void *dst, size_t off, size_t bytes) {
     return CAPIB_OK;
 }
 
+// D2Q9 in the order of Eq. (3)
+static const int EXq[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EYq[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPPq[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double Wq[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// Reference population of row y: h_eq(drho = 0, u = (u_ref(y), 0)), FP64.
+static double ref_pop(const capib_ctx *c, int y, int q) {
+    const double u = c->ref_u[y], eu = EXq[q] * u;
+    return Wq[q] * (3.0 * eu + 4.5 * eu * eu - 1.5 * u * u);
+}
+
+// Per-row constants of the deviation storage (see Dev::rowref), from FP64.
+static capib_status upload_ref(capib_ctx *c) {
+    const int ny = c->lat.ny;
+    std::vector<float> t((size_t)ny * 16, 0.0f);
+    for (int y = 0; y < ny; y++) {
+        for (int q = 0; q < 9; q++) {
+            int ys = y - EYq[q];
+            double v;
+            if (ys < 0 || ys >= ny) {
+                if (c->lat.walls) {
+                    v = ref_pop(c, y, OPPq[q]) - ref_pop(c, y, q);   // bounce-back from the node itself
+                    t[16 * y + q] = (float)v;
+                    continue;
+                }
+                ys = (ys + ny) % ny;
+            }
+            v = ref_pop(c, ys, q) - ref_pop(c, y, q);
+            t[16 * y + q] = (float)v;
+        }
+        t[16 * y + 9] = (float)c->ref_u[y];
+    }
+    return h2d(c, c->off_rowref, t.data(), t.size() * 4);
+}
+
 extern "C" {
 
 capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx **out) {
@@ -242,6 +279,7 @@ capib_status capib_bind_workspace(capib_ctx *c, void *ptr, size_t bytes) {
     c->nbodies = c->nverts = c->nsites = 0;
     c->bodies.clear();
     fill_dev(c);
+    c->ref_u.assign(c->lat.ny, 0.0);
     HIPCHK(c, hipMemsetAsync(c->base, 0, c->ws_bytes, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return CAPIB_OK;
@@ -250,12 +288,14 @@ capib_status capib_bind_workspace(capib_ctx *c, void *ptr, size_t bytes) {
 capib_status capib_init_flow(capib_ctx *c, const double *ux) {
     capib_status s = need_ws(c);
     if (s) return s;
-    if (ux) {
+    if (c->step != 0) return fail(c, CAPIB_E_STATE, "the flow is initialised before the first step");
+    if (ux)
         for (int j = 0; j < c->lat.ny; j++)
             if (!std::isfinite(ux[j]) || std::fabs(ux[j]) > 0.1) return fail(c, CAPIB_E_ARG, "bad velocity in row %d", j);
-        if ((s = h2d(c, c->off_uinit, ux, (size_t)c->lat.ny * 8))) return s;
-    }
-    HIPCHK(c, launch_init_flow(c->d, c->par, ux ? 1 : 0, c->stream));
+    // the initial profile becomes the reference of the deviation storage
+    for (int j = 0; j < c->lat.ny; j++) c->ref_u[j] = ux ? ux[j] : 0.0;
+    if ((s = upload_ref(c))) return s;
+    HIPCHK(c, launch_init_flow(c->d, c->par, c->stream));
     return CAPIB_OK;
 }
 
@@ -269,8 +309,9 @@ capib_status capib_write_populations(capib_ctx *c, const double *h) {
     for (int q = 0; q < 9; q++)
         for (int j = 0; j < L.ny; j++)
             for (int i = 0; i < L.nx; i++) {
-                const double v = h[((size_t)q * L.ny + j) * L.nx + i];
-                if (!std::isfinite(v)) return fail(c, CAPIB_E_ARG, "non-finite population");
+                const double hv = h[((size_t)q * L.ny + j) * L.nx + i];
+                if (!std::isfinite(hv)) return fail(c, CAPIB_E_ARG, "non-finite population");
+                const double v = hv - ref_pop(c, j, q);
                 const size_t k = q * N + (size_t)j * c->pitch + i;
                 if (c->esize == 4) ((float *)buf.data())[k] = (float)v;
                 else ((_Float16 *)buf.data())[k] = (_Float16)(float)(v * L.fp16_scale);
@@ -291,8 +332,8 @@ capib_status capib_read_populations(capib_ctx *c, double *h) {
             for (int i = 0; i < L.nx; i++) {
                 const size_t k = q * N + (size_t)j * c->pitch + i;
                 h[((size_t)q * L.ny + j) * L.nx + i] =
-                    c->esize == 4 ? (double)((float *)buf.data())[k]
-                                  : (double)(float)((_Float16 *)buf.data())[k] / L.fp16_scale;
+                    ref_pop(c, j, q) + (c->esize == 4 ? (double)((float *)buf.data())[k]
+                                                       : (double)(float)((_Float16 *)buf.data())[k] / L.fp16_scale);
             }
     return CAPIB_OK;
 }
@@ -678,11 +719,18 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     int err;
     if ((s = d2h(c, &cnt, c->off_scal, 8))) return s;
     if ((s = d2h(c, &err, c->off_scal + 8, 4))) return s;
+    // add the reference part of the stored deviations (FP64, host)
+    double rm = 0, rx = 0;
+    for (int y = 0; y < c->lat.ny; y++)
+        for (int q = 0; q < 9; q++) {
+            rm += ref_pop(c, y, q);
+            rx += ref_pop(c, y, q) * EXq[q];
+        }
     out->step = c->step;
     out->error_flags = err;
     out->n_bodies = c->nbodies;
-    out->mass = r[0];
-    out->mom_x = r[1];
+    out->mass = r[0] + c->lat.nx * rm;
+    out->mom_x = r[1] + c->lat.nx * rx;
     out->mom_y = r[2];
     if (cnt != c->step) return fail(c, CAPIB_E_STATE, "device step counter %lld != %lld", cnt, c->step);
     if (err) return fail(c, CAPIB_E_UNSTABLE, "device error flags 0x%x", err);
@@ -732,7 +780,7 @@ capib_status capib_save(capib_ctx *c, void *buf, size_t *bytes) {
     if (s) return s;
     if (!bytes) return fail(c, CAPIB_E_ARG, "null size");
     const size_t pop_bytes = 9 * (size_t)c->pitch * c->lat.ny * c->esize;
-    const size_t total = sizeof(CkptHeader) + pop_bytes + c->ib_bytes + 16;
+    const size_t total = sizeof(CkptHeader) + pop_bytes + c->ib_bytes + 16 + (size_t)c->lat.ny * 8;
     if (!buf) { *bytes = total; return CAPIB_OK; }
     if (*bytes < total) return fail(c, CAPIB_E_ARG, "checkpoint buffer of %zu bytes needs %zu", *bytes, total);
     CkptHeader h{CKPT_MAGIC, c->lat.nx, c->lat.ny, c->pitch, c->lat.storage, c->nbodies, c->nverts, c->nsites,
@@ -745,6 +793,8 @@ capib_status capib_save(capib_ctx *c, void *buf, size_t *bytes) {
     if ((s = d2h(c, p, c->off_ib, c->ib_bytes))) return s;
     p += c->ib_bytes;
     if ((s = d2h(c, p, c->off_scal, 16))) return s;
+    p += 16;
+    std::memcpy(p, c->ref_u.data(), (size_t)c->lat.ny * 8);
     *bytes = total;
     return CAPIB_OK;
 }
@@ -760,7 +810,8 @@ capib_status capib_load(capib_ctx *c, const void *buf, size_t bytes) {
         h.storage != c->lat.storage || h.nbodies != c->nbodies || h.nverts != c->nverts || h.nsites != c->nsites ||
         h.pop_bytes != pop_bytes || h.ib_bytes != c->ib_bytes || (h.par != 0 && h.par != 1))
         return fail(c, CAPIB_E_ARG, "checkpoint does not match this context");
-    if (bytes < sizeof h + pop_bytes + c->ib_bytes + 16) return fail(c, CAPIB_E_ARG, "checkpoint truncated");
+    if (bytes < sizeof h + pop_bytes + c->ib_bytes + 16 + (size_t)c->lat.ny * 8)
+        return fail(c, CAPIB_E_ARG, "checkpoint truncated");
     const char *p = (const char *)buf + sizeof h;
     // reject non-finite populations before touching the device
     if (c->esize == 4) {
@@ -780,6 +831,9 @@ capib_status capib_load(capib_ctx *c, const void *buf, size_t bytes) {
     if ((s = h2d(c, c->off_ib, p, c->ib_bytes))) return s;
     p += c->ib_bytes;
     if ((s = h2d(c, c->off_scal, p, 16))) return s;
+    p += 16;
+    std::memcpy(c->ref_u.data(), p, (size_t)c->lat.ny * 8);
+    if ((s = upload_ref(c))) return s;
     // spread-force field and tile tags start clean
     HIPCHK(c, hipMemsetAsync(c->base + c->off_fib, 0, 2 * (size_t)c->pitch * c->lat.ny * 8, c->stream));
     HIPCHK(c, hipMemsetAsync(c->base + c->off_tflag, 0, (size_t)c->ntx * c->nty * 4, c->stream));

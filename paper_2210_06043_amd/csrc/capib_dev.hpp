@@ -54,6 +54,11 @@ struct Dev {
     float omega, fc, gx, gy;        // 1/tau, 1 - 1/(2 tau), body force
     float scale, inv_scale;         // FP16 storage scale
     void *pop[2];                   // populations, parity-indexed
+    // Per-row reference: stored populations are deviations s_i = A_i - r_i(y)
+    // from the equilibrium r_i(y) = h_eq(0, (u_ref(y), 0)) of the initial
+    // channel profile.  rowref[16 y + i] (i < 9) is the constant that turns a
+    // pulled stored value into h_i - r_i(y); rowref[16 y + 9] = u_ref(y).
+    const float *rowref;
     long long *fib;                 // spread force [ny][pitch][2], 2^-56 units
     uint32_t *tflag;                // per tile: step tag of the last spread into it
     // immersed boundary
@@ -79,7 +84,6 @@ struct Dev {
     int *err;             // sticky error flags
     double *red;          // reduction partials
     float *macro;         // [3][ny][nx] readout
-    double *uinit;        // [ny] initial profile
 };
 
 // ---- small helpers -------------------------------------------------------------
@@ -204,6 +208,36 @@ __device__ __forceinline__ void pull9(const Dev &d, const T *__restrict__ A, int
         h[8] = ldpop(A + 8 * Q + rp + im, is);
     }
 }
+
+// Pulled populations as deviations from the reference of row j:
+// dh_i = h_i - r_i(y_j) = s_i(x - e_i) + rowref_i(j).  Returns u_ref(y_j).
+template <typename T>
+__device__ __forceinline__ float pull_dev(const Dev &d, const T *__restrict__ A, int i, int j, float h[9]) {
+    pull9<T>(d, A, i, j, h);
+    const float *R = d.rowref + 16 * j;
+    h[2] += R[2]; h[4] += R[4]; h[5] += R[5];
+    h[6] += R[6]; h[7] += R[7]; h[8] += R[8];
+    return R[9];
+}
+
+// Equilibrium of Eq. (2) as a deviation from the row reference, with
+// u = (uref + dux, duy):
+//   h_eq_i(drho, u) - r_i = w [drho (1 - 1.5 u.u) - 1.5 du.(u + uref)
+//                              + drho (3 e.u + 4.5 (e.u)^2) + 3 e.du
+//                              + 4.5 (e.du)(e.u + e.uref)]
+// Every term carries a deviation (drho or du), so nothing large is rounded.
+struct EqDev {
+    float drho, ux, uy, dux, duy, uref, c0;
+    __device__ __forceinline__ EqDev(float drho_, float uref_, float dux_, float duy_)
+        : drho(drho_), ux(uref_ + dux_), uy(duy_), dux(dux_), duy(duy_), uref(uref_) {
+        c0 = drho * (1.0f - 1.5f * (ux * ux + uy * uy)) - 1.5f * (dux * (ux + uref) + duy * uy);
+    }
+    __device__ __forceinline__ float operator()(float ex, float ey, float w) const {
+        const float eu = ex * ux + ey * uy;
+        const float edu = ex * dux + ey * duy;
+        return w * (c0 + drho * (3.0f * eu + 4.5f * eu * eu) + 3.0f * edu + 4.5f * edu * (eu + ex * uref));
+    }
+};
 
 // Counter-based generator: Philox4x32-10 (Salmon et al., SC'11), word 0.
 __device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,

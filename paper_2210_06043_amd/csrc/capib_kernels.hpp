@@ -6,7 +6,7 @@ namespace capib {
 
 hipError_t launch_lattice(const Dev &d, int par, hipStream_t st);
 hipError_t launch_macro(const Dev &d, int par, hipStream_t st);
-hipError_t launch_init_flow(const Dev &d, int par, int has_profile, hipStream_t st);
+hipError_t launch_init_flow(const Dev &d, int par, hipStream_t st);
 hipError_t launch_diag(const Dev &d, int par, hipStream_t st);
 
 hipError_t launch_interp(const Dev &d, int par, hipStream_t st);

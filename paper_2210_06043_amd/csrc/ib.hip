@@ -64,29 +64,28 @@ __device__ __forceinline__ void df_add2(float &ah, float &al, float bh, float bl
 template <typename T>
 __device__ __forceinline__ void node_moments(const Dev &d, const T *A, int i, int j, bool stress, float out[4]) {
     float h[9];
-    pull9<T>(d, A, i, j, h);
+    const float uref = pull_dev<T>(d, A, i, j, h);   // deviations from the row reference
     const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
     const float rho = 1.0f + drho;
-    const float ux = (jx + 0.5f * d.gx) / rho;
-    const float uy = (jy + 0.5f * d.gy) / rho;
+    const float dux = (jx + 0.5f * d.gx - drho * uref) / rho;
+    const float duy = (jy + 0.5f * d.gy) / rho;
     if (!stress) {
-        out[0] = ux;
-        out[1] = uy;
+        out[0] = uref + dux;
+        out[1] = duy;
         return;
     }
-    // non-equilibrium momentum flux with h_eq(drho, u*) (Eq. 2)
-    const float base = drho - 1.5f * rho * (ux * ux + uy * uy);
+    // non-equilibrium momentum flux h - h_eq(drho, u*) (Eq. 2); the row
+    // reference cancels between the two terms
+    const EqDev E(drho, uref, dux, duy);
     float neq[9];
-    neq[0] = h[0] - (4.0f / 9.0f) * base;
     const float ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const float ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 #pragma unroll
-    for (int q = 1; q < 9; q++) {
-        const float w = q < 5 ? 1.0f / 9.0f : 1.0f / 36.0f;
-        const float eu = ex[q] * ux + ey[q] * uy;
-        neq[q] = h[q] - w * (base + rho * (3.0f * eu + 4.5f * eu * eu));
+    for (int q = 0; q < 9; q++) {
+        const float w = q == 0 ? 4.0f / 9.0f : (q < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+        neq[q] = h[q] - E(ex[q], ey[q], w);
     }
     const float pxx = (neq[1] + neq[3]) + ((neq[5] + neq[6]) + (neq[7] + neq[8]));
     const float pyy = (neq[2] + neq[4]) + ((neq[5] + neq[6]) + (neq[7] + neq[8]));

@@ -27,12 +27,13 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(Dev d, int par) {
     const int ty = tile / d.ntx;
     const int tx = tile - ty * d.ntx;
     const int i = tx * TILE_X + (threadIdx.x & (TILE_X - 1));
-    const int j = ty * TILE_Y + (threadIdx.x / TILE_X);
+    // one wave per row: the row index (and the row reference) is wave-uniform
+    const int j = __builtin_amdgcn_readfirstlane(ty * TILE_Y + (int)(threadIdx.x / TILE_X));
     if (i >= d.nx || j >= d.ny) return;
     float h[9];
-    pull9<T>(d, A, i, j, h);
+    const float uref = pull_dev<T>(d, A, i, j, h);
 
-    // moments of the streamed populations
+    // moments of the streamed deviations: drho, and j - u_ref x
     const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
@@ -54,30 +55,30 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(Dev d, int par) {
 
     const float rho = 1.0f + drho;
     const float irho = 1.0f / rho;
-    const float ux = (jx + 0.5f * Fx) * irho;
-    const float uy = (jy + 0.5f * Fy) * irho;
+    // u = (j + F/2)/rho written as u_ref + du with du from deviations only
+    const float dux = (jx + 0.5f * Fx - drho * uref) * irho;
+    const float duy = (jy + 0.5f * Fy) * irho;
+    const EqDev E(drho, uref, dux, duy);
+    const float ux = E.ux, uy = E.uy;
     const float uu = ux * ux + uy * uy;
     if (!(rho > 0.0f) || !(uu < 0.03f)) atomicOr(d.err, FLAG_FLUID);  // NaN fails both tests
 
-    // h' = (1 - omega) h + omega h_eq + F_i with
-    // h_eq = w [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)]
-    // F_i  = (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
+    // s'_i = (1 - omega) dh_i + omega (h_eq_i - r_i) + F_i with the Guo term
+    // F_i = (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
     const float om = d.omega, om1 = 1.0f - d.omega, fc = d.fc;
     const float uF = ux * Fx + uy * Fy;
-    const float base = drho - 1.5f * rho * uu;   // drho + rho(-1.5 u.u)
     const float fb = -3.0f * uF;                 // 3 (-u).F
     float out[9];
     {
         const float w = 4.0f / 9.0f;
-        out[0] = om1 * h[0] + om * w * base + fc * w * fb;
+        out[0] = om1 * h[0] + om * E(0.0f, 0.0f, w) + fc * w * fb;
     }
 #define CAPIB_DIR(q, ex, ey, w)                                                              \
     {                                                                                        \
         const float eu = (ex) * ux + (ey) * uy;                                              \
         const float eF = (ex) * Fx + (ey) * Fy;                                              \
-        const float heq = (w) * (base + rho * (3.0f * eu + 4.5f * eu * eu));                 \
         const float Fi = fc * (w) * (fb + 3.0f * eF + 9.0f * eu * eF);                       \
-        out[q] = om1 * h[q] + om * heq + Fi;                                                 \
+        out[q] = om1 * h[q] + om * E((ex), (ey), (w)) + Fi;                                  \
     }
     CAPIB_DIR(1, 1.0f, 0.0f, 1.0f / 9.0f)
     CAPIB_DIR(2, 0.0f, 1.0f, 1.0f / 9.0f)
@@ -101,33 +102,27 @@ __global__ __launch_bounds__(LAT_THREADS) void k_macro(Dev d, int par) {
     const int j = blockIdx.y * TILE_Y + (threadIdx.x / TILE_X);
     if (i >= d.nx || j >= d.ny) return;
     float h[9];
-    pull9<T>(d, A, i, j, h);
+    const float uref = pull_dev<T>(d, A, i, j, h);
     const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
     const float irho = 1.0f / (1.0f + drho);
     const long long N = (long long)d.nx * d.ny, k = (long long)j * d.nx + i;
     d.macro[k] = drho;
-    d.macro[N + k] = (jx + 0.5f * d.gx) * irho;
+    d.macro[N + k] = uref + (jx + 0.5f * d.gx - drho * uref) * irho;
     d.macro[2 * N + k] = (jy + 0.5f * d.gy) * irho;
 }
 
-// Equilibrium populations at drho = 0 and u = (uinit[j], 0), in FP64, rounded once.
+// Initial state: the equilibrium at drho = 0 and the reference profile,
+// i.e. zero deviation everywhere.
 template <typename T>
-__global__ __launch_bounds__(LAT_THREADS) void k_init_flow(Dev d, int par, int has_profile) {
+__global__ __launch_bounds__(LAT_THREADS) void k_init_flow(Dev d, int par) {
     T *__restrict__ A = (T *)d.pop[par];
     const int i = blockIdx.x * TILE_X + (threadIdx.x & (TILE_X - 1));
     const int j = blockIdx.y * TILE_Y + (threadIdx.x / TILE_X);
     if (i >= d.nx || j >= d.ny) return;
-    const double u = has_profile ? d.uinit[j] : 0.0;
-    const double ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     const long long node = (long long)j * d.pitch + i;
-    for (int q = 0; q < 9; q++) {
-        const double eu = ex[q] * u;
-        const double heq = w[q] * (3.0 * eu + 4.5 * eu * eu - 1.5 * u * u);
-        A[q * d.qstride + node] = stpop<T>((float)heq, d.scale);
-    }
+    for (int q = 0; q < 9; q++) A[q * d.qstride + node] = stpop<T>(0.0f, d.scale);
 }
 
 // FP64 partial sums per tile of the stored populations: sum h, sum h e.
@@ -197,12 +192,12 @@ hipError_t launch_macro(const Dev &d, int par, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_init_flow(const Dev &d, int par, int has_profile, hipStream_t st) {
+hipError_t launch_init_flow(const Dev &d, int par, hipStream_t st) {
     dim3 g(d.ntx, d.nty);
     if (d.storage == 0)
-        hipLaunchKernelGGL(k_init_flow<float>, g, dim3(LAT_THREADS), 0, st, d, par, has_profile);
+        hipLaunchKernelGGL(k_init_flow<float>, g, dim3(LAT_THREADS), 0, st, d, par);
     else
-        hipLaunchKernelGGL(k_init_flow<_Float16>, g, dim3(LAT_THREADS), 0, st, d, par, has_profile);
+        hipLaunchKernelGGL(k_init_flow<_Float16>, g, dim3(LAT_THREADS), 0, st, d, par);
     return hipGetLastError();
 }
 

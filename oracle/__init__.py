@@ -13,6 +13,7 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 _lib = None
 
 DEFORMABLE, RIGID, FIXED = 0, 1, 2
+STEN_VELOCITY, STEN_PROBE = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
@@ -68,9 +69,9 @@ def lib():
                                         C.POINTER(C.c_uint32)]
         L.orc_uniform.restype = C.c_double
         L.orc_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_int32]
-        L.orc_stencil.argtypes = [C.c_void_p, C.c_double, C.c_double, _ip, _ip, _dp]
+        L.orc_stencil.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _ip, _ip, _dp]
         L.orc_interp_field.restype = C.c_double
-        L.orc_interp_field.argtypes = [C.c_void_p, _dp, C.c_double, C.c_double]
+        L.orc_interp_field.argtypes = [C.c_void_p, _dp, C.c_double, C.c_double, C.c_int]
         L.orc_polygon.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_polar_moment.restype = C.c_double
         L.orc_polar_moment.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double]
@@ -287,14 +288,14 @@ class Sim:
     def integrate_body(self, body):
         lib().orc_integrate_body(self.p, body)
 
-    def stencil(self, X, Y):
+    def stencil(self, X, Y, mode=STEN_VELOCITY):
         ii = np.zeros(4, np.int32)
         jj = np.zeros(4, np.int32)
         w = np.zeros(16)
-        lib().orc_stencil(self.p, X, Y, ii.ctypes.data_as(_ip), jj.ctypes.data_as(_ip), _d(w))
+        lib().orc_stencil(self.p, X, Y, mode, ii.ctypes.data_as(_ip), jj.ctypes.data_as(_ip), _d(w))
         return ii, jj, w.reshape(4, 4)
 
-    def interp_field(self, field, X, Y):
+    def interp_field(self, field, X, Y, mode=STEN_VELOCITY):
         f = np.ascontiguousarray(field, dtype=np.float64)
         assert f.shape == (self.ny, self.nx)
-        return lib().orc_interp_field(self.p, _d(f), X, Y)
+        return lib().orc_interp_field(self.p, _d(f), X, Y, mode)

@@ -280,10 +280,22 @@ static void node_moments(orc_sim *s) {
 
 /* ---- S4 helper: stencil of the cosine kernel -----------------------------------
  * Nodes i0..i0+3, j0..j0+3 with i0 = floor(X)-1, j0 = floor(Y)-1; weight
- * W = phi(X-i) phi(Y-j).  With walls the point's Y is clamped to [-1, ny],
- * rows outside [0, ny) get weight zero, and the weights are divided by their
- * sum.  Returns the weights in w[b*4+a] (a along x) and the wrapped indices.  */
-static void stencil(orc_sim *s, double X, double Y, int ii[4], int jj[4], double w[16]) {
+ * W = phi(X-i) phi(Y-j), divided by the sum of the weights.  With walls the
+ * point's Y is clamped to [-1, ny] and rows beyond a wall are read in one of
+ * two ways (the paper does not say how a stencil that crosses a wall is
+ * treated):
+ *   STEN_VELOCITY (interpolation of u* to vertices, spreading): the rows
+ *     beyond the wall are wall nodes at rest.  They keep their kernel weight
+ *     in the sum, contribute zero velocity and take no spread force.
+ *   STEN_PROBE (pressure and stress at the probes): the rows beyond the wall
+ *     are dropped and the remaining weights renormalised, i.e. the fluid
+ *     field is extrapolated.
+ * (Renormalising the velocity coupling too makes deformable membranes whose
+ * vertices sit between the wall and the first fluid row unstable.)
+ * Returns the weights in w[b*4+a] (a along x), the wrapped node indices, and
+ * jj[b] = -1 for rows beyond a wall.                                         */
+enum { STEN_VELOCITY = 0, STEN_PROBE = 1 };
+static void stencil(orc_sim *s, double X, double Y, int mode, int ii[4], int jj[4], double w[16]) {
     if (s->walls) {
         if (Y < -1.0) Y = -1.0;
         if (Y > (double)s->ny) Y = (double)s->ny;
@@ -301,22 +313,23 @@ static void stencil(orc_sim *s, double X, double Y, int ii[4], int jj[4], double
         for (int a = 0; a < 4; a++) {
             int i = i0 + a;
             ii[a] = ((i % s->nx) + s->nx) % s->nx;
-            double ww = valid ? orc_phi(X - (double)(i0 + a)) * orc_phi(Y - (double)(j0 + b)) : 0.0;
-            w[b * 4 + a] = ww;
+            double ww = orc_phi(X - (double)(i0 + a)) * orc_phi(Y - (double)(j0 + b));
+            if (!valid && mode == STEN_PROBE) ww = 0.0;
             sum += ww;
+            w[b * 4 + a] = valid ? ww : 0.0;
         }
     }
     for (int k = 0; k < 16; k++) w[k] /= sum;
 }
 
 /* exported for tests: weights and node indices of the stencil of (X, Y) */
-void orc_stencil(orc_sim *s, double X, double Y, int *ii, int *jj, double *w) {
-    stencil(s, X, Y, ii, jj, w);
+void orc_stencil(orc_sim *s, double X, double Y, int mode, int *ii, int *jj, double *w) {
+    stencil(s, X, Y, mode, ii, jj, w);
 }
 
-static double interp(orc_sim *s, const double *field, double X, double Y) {
+static double interp(orc_sim *s, const double *field, double X, double Y, int mode) {
     int ii[4], jj[4]; double w[16];
-    stencil(s, X, Y, ii, jj, w);
+    stencil(s, X, Y, mode, ii, jj, w);
     double acc = 0;
     for (int b = 0; b < 4; b++) {
         if (jj[b] < 0) continue;
@@ -325,15 +338,15 @@ static double interp(orc_sim *s, const double *field, double X, double Y) {
     return acc;
 }
 
-/* exported for tests: interpolate a node field [ny][nx] at (X, Y) */
-double orc_interp_field(orc_sim *s, const double *field, double X, double Y) {
-    return interp(s, field, X, Y);
+/* exported for tests: interpolate a node field [ny][nx] at (X, Y) (mode: STEN_*) */
+double orc_interp_field(orc_sim *s, const double *field, double X, double Y, int mode) {
+    return interp(s, field, X, Y, mode);
 }
 
-/* spread: field(x) += W(x, X) * val, the transpose of interp */
+/* spread: field(x) += W(x, X) * val, the transpose of the velocity interpolation */
 static void spread(orc_sim *s, double *field, double X, double Y, double val) {
     int ii[4], jj[4]; double w[16];
-    stencil(s, X, Y, ii, jj, w);
+    stencil(s, X, Y, STEN_VELOCITY, ii, jj, w);
     for (int b = 0; b < 4; b++) {
         if (jj[b] < 0) continue;
         for (int a = 0; a < 4; a++) field[(size_t)jj[b] * s->nx + ii[a]] += w[b * 4 + a] * val;
@@ -712,18 +725,18 @@ static void one_step(orc_sim *s) {
         geometry(b->n, b->x, b->y, &G[k]);
         for (int v = 0; v < b->n; v++) {
             if (s->walls && (b->y[v] < -1.0 || b->y[v] > (double)s->ny)) s->flags |= 1;
-            b->usx[v] = interp(s, s->usx, b->x[v], b->y[v]);
-            b->usy[v] = interp(s, s->usy, b->x[v], b->y[v]);
+            b->usx[v] = interp(s, s->usx, b->x[v], b->y[v], STEN_VELOCITY);
+            b->usy[v] = interp(s, s->usy, b->x[v], b->y[v], STEN_VELOCITY);
         }
         for (int l = 0; l < b->n; l++) {
             int m = (l + 1) % b->n;
             double px = 0.5 * (b->x[l] + b->x[m]) + s->probe_dist * G[k].nlx[l];
             double py = 0.5 * (b->y[l] + b->y[m]) + s->probe_dist * G[k].nly[l];
-            double pd = interp(s, s->drho, px, py);
+            double pd = interp(s, s->drho, px, py, STEN_PROBE);
             b->pp[l] = pd / 3.0;
-            b->psxx[l] = interp(s, s->sxx, px, py);
-            b->psxy[l] = interp(s, s->sxy, px, py);
-            b->psyy[l] = interp(s, s->syy, px, py);
+            b->psxx[l] = interp(s, s->sxx, px, py, STEN_PROBE);
+            b->psxy[l] = interp(s, s->sxy, px, py, STEN_PROBE);
+            b->psyy[l] = interp(s, s->syy, px, py, STEN_PROBE);
         }
     }
     for (int k = 0; k < s->nb; k++) body_forces(s, k, G);    /* S5 */

@@ -115,10 +115,13 @@ __device__ __forceinline__ void df_add(float &hi, float &lo, float d) {
 
 // Cosine-kernel stencil of a point given as hi + lo: node offsets and the
 // 4 + 4 one-dimensional weights phi(X - i), phi(Y - j) for i = ix0 .. ix0+3,
-// j = iy0 .. iy0+3.  With walls, Y is clamped to [-1, ny], rows outside the
-// fluid get weight zero; 'inv' divides every product weight so that the 16
-// weights sum to one.  Returns true when the unclamped Y left [-1, ny].
-__device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float yh, float yl,
+// j = iy0 .. iy0+3; 'inv' divides every product weight.  With walls, Y is
+// clamped to [-1, ny] and rows beyond a wall get weight zero.  For the
+// velocity coupling (renorm = false) those rows stand for wall nodes at rest:
+// they stay in the normalising sum.  For the probe fields (renorm = true) the
+// fluid rows are renormalised to sum one.  Returns true when the unclamped Y
+// left [-1, ny].
+__device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float yh, float yl, bool renorm,
                                         int &ix0, int &iy0, float wx[4], float wy[4], float &inv) {
     bool out = false;
     // non-finite or absurd coordinates are flagged and mapped to the origin so
@@ -152,6 +155,8 @@ __device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float 
     wy[2] = 0.25f * (1.0f + sny); wy[3] = 0.25f * (1.0f - cy);
     ix0 = ix - 1;
     iy0 = iy - 1;
+    const float sxw = (wx[0] + wx[1]) + (wx[2] + wx[3]);
+    const float syfull = (wy[0] + wy[1]) + (wy[2] + wy[3]);
     if (d.walls) {
 #pragma unroll
         for (int b = 0; b < 4; b++) {
@@ -159,8 +164,7 @@ __device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float 
             if (j < 0 || j >= d.ny) wy[b] = 0.0f;
         }
     }
-    float sxw = (wx[0] + wx[1]) + (wx[2] + wx[3]);
-    float syw = (wy[0] + wy[1]) + (wy[2] + wy[3]);
+    const float syw = renorm ? (wy[0] + wy[1]) + (wy[2] + wy[3]) : syfull;
     inv = 1.0f / (sxw * syw);
     return out;
 }

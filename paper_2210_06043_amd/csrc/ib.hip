@@ -116,7 +116,7 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d, int par) {
     }
     int ix0, iy0;
     float wx[4], wy[4], inv;
-    const bool out = stencil(d, xh, xl, yh, yl, ix0, iy0, wx, wy, inv);
+    const bool out = stencil(d, xh, xl, yh, yl, probe, ix0, iy0, wx, wy, inv);
     if (out && !probe && lane == 0) atomicOr(d.err, FLAG_VERTEX_OUT);
     const int a = lane & 3, bb = lane >> 2;
     const float W = wx[a] * wy[bb] * inv;
@@ -160,7 +160,7 @@ __device__ __forceinline__ void spread(const Dev &d, float xh, float xl, float y
                                        uint32_t tag) {
     int ix0, iy0;
     float wx[4], wy[4], inv;
-    stencil(d, xh, xl, yh, yl, ix0, iy0, wx, wy, inv);
+    stencil(d, xh, xl, yh, yl, false, ix0, iy0, wx, wy, inv);
 #pragma unroll
     for (int b = 0; b < 4; b++) {
         if (wy[b] == 0.0f) continue;

@@ -61,21 +61,29 @@ def test_stencil_equals_brute_force():
 
 
 def test_stencil_wall_truncation():
-    """With walls, rows outside the fluid get weight zero and the weights are
-    divided by their sum (reading of the paper's silence on stencils that
-    cross a wall); points are clamped to Y in [-1, ny]."""
+    """Stencils that cross a wall (the paper is silent): points are clamped to
+    Y in [-1, ny]; for the velocity coupling the rows beyond the wall are
+    wall nodes at rest (zero weight in the result, full kernel weight in the
+    normalisation, so the weights sum to the fluid share); for the probes the
+    fluid rows are renormalised to sum 1."""
     s = oracle.Sim(10, 6, 1.0, 0, 0, walls=3)
-    for Y in [-1.5, -1.0, -0.4, 0.3, 4.6, 5.2, 6.0, 7.0]:
-        ii, jj, w = s.stencil(4.3, Y)
+    for Y in [-1.5, -1.0, -0.4, 0.3, 2.5, 4.6, 5.2, 6.0, 7.0]:
+        Yc = min(max(Y, -1.0), 6.0)
+        j0 = int(np.floor(Yc)) - 1
+        full = np.array([oracle.phi(Yc - (j0 + b)) for b in range(4)])
+        fluid = np.array([full[b] if 0 <= j0 + b < 6 else 0.0 for b in range(4)])
+        px = np.array([oracle.phi(4.3 - (3 + a)) for a in range(4)])
+        ii, jj, w = s.stencil(4.3, Y, oracle.STEN_PROBE)
         assert abs(w.sum() - 1) < 1e-15
+        np.testing.assert_allclose(w, np.outer(fluid, px) / (fluid.sum() * px.sum()), atol=1e-15)
+        ii, jj, w = s.stencil(4.3, Y, oracle.STEN_VELOCITY)
+        np.testing.assert_allclose(w, np.outer(fluid, px) / (full.sum() * px.sum()), atol=1e-15)
+        assert abs(w.sum() - fluid.sum() / full.sum()) < 1e-15
         for b in range(4):
             if jj[b] < 0:
                 assert np.all(w[b] == 0)
-        Yc = min(max(Y, -1.0), 6.0)
-        j0 = int(np.floor(Yc)) - 1
-        py = np.array([oracle.phi(Yc - (j0 + b)) if 0 <= j0 + b < 6 else 0.0 for b in range(4)])
-        px = np.array([oracle.phi(4.3 - (3 + a)) for a in range(4)])
-        np.testing.assert_allclose(w, np.outer(py, px) / (py.sum() * px.sum()), atol=1e-15)
+        if 1.0 <= Yc <= 4.0:                  # away from the walls both readings agree
+            assert abs(w.sum() - 1) < 1e-15
 
 
 def test_interp_linear_field_closed_form():

@@ -12,7 +12,7 @@ constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int LAT_THREADS = TILE_X * TILE_Y;
 constexpr int MAXV_BODY = 1024;    // vertices of one membrane held in LDS
-constexpr int BODY_THREADS = 256;
+constexpr int BODY_THREADS = 512;
 constexpr int INTERP_THREADS = 256;  // 16 lanes per interpolation point
 // Spread forces accumulate as int64 with 56 fractional bits: exact,
 // order-independent sums; contributions must stay below 2^7 in magnitude.
@@ -242,6 +242,13 @@ struct EqDev {
         return w * (c0 + drho * (3.0f * eu + 4.5f * eu * eu) + 3.0f * edu + 4.5f * edu * (eu + ex * uref));
     }
 };
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
 
 // Counter-based generator: Philox4x32-10 (Salmon et al., SC'11), word 0.
 __device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,

@@ -22,9 +22,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
+    """Hash of the lattice-sweep device code (shared header + kernels of
+    lattice.hip, not its host launchers)."""
+    csrc = os.path.join(ROOT, "paper_2210_06043_amd", "csrc")
     h = hashlib.sha256()
-    for f in ["capib_dev.hpp", "lattice.hip"]:
-        h.update(open(os.path.join(ROOT, "paper_2210_06043_amd", "csrc", f), "rb").read())
+    h.update(open(os.path.join(csrc, "capib_dev.hpp"), "rb").read())
+    lat = open(os.path.join(csrc, "lattice.hip"), "rb").read()
+    h.update(lat.split(b"// ---- host launchers")[0])
     return h.hexdigest()[:16]
 
 

@@ -406,9 +406,14 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     }
 }
 
-hipError_t launch_body(const Dev &d, int par, hipStream_t st) {
-    if (d.nbodies == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_body, dim3(d.nbodies), dim3(BT), 0, st, d, par);
+hipError_t launch_body(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (d.nbodies == 0) {
+        // keep the event pair meaningful for callers that time every phase
+        if (e0) { hipError_t e = hipEventRecord(e0, st); if (e != hipSuccess) return e; }
+        if (e1) return hipEventRecord(e1, st);
+        return hipSuccess;
+    }
+    hipExtLaunchKernelGGL(k_body, dim3(d.nbodies), dim3(BT), 0, st, e0, e1, 0, d, par);
     return hipGetLastError();
 }
 

@@ -579,30 +579,28 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
     if (s) return s;
     if (nsteps < 0) return fail(c, CAPIB_E_ARG, "negative step count");
     if (c->timing) {
-        const size_t need = 4 * (size_t)nsteps;
+        // each kernel launched with a start/stop event pair stamped at its
+        // own start and end
+        const size_t need = 6 * (size_t)nsteps;
         while (c->ev.size() < need) {
             hipEvent_t e;
             HIPCHK(c, hipEventCreate(&e));
             c->ev.push_back(e);
         }
         for (int t = 0; t < nsteps; t++) {
-            hipEvent_t *e = &c->ev[4 * t];
-            HIPCHK(c, hipEventRecord(e[0], c->stream));
-            HIPCHK(c, launch_interp(c->d, c->par, c->stream));
-            HIPCHK(c, hipEventRecord(e[1], c->stream));
-            HIPCHK(c, launch_body(c->d, c->par, c->stream));
-            HIPCHK(c, hipEventRecord(e[2], c->stream));
-            HIPCHK(c, launch_lattice(c->d, c->par, c->stream));
-            HIPCHK(c, hipEventRecord(e[3], c->stream));
+            hipEvent_t *e = &c->ev[6 * t];
+            HIPCHK(c, launch_interp(c->d, c->par, c->stream, e[0], e[1]));
+            HIPCHK(c, launch_body(c->d, c->par, c->stream, e[2], e[3]));
+            HIPCHK(c, launch_lattice(c->d, c->par, c->stream, e[4], e[5]));
             c->par ^= 1;
             c->step++;
         }
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (int t = 0; t < nsteps; t++) {
-            hipEvent_t *e = &c->ev[4 * t];
+            hipEvent_t *e = &c->ev[6 * t];
             for (int k = 0; k < 3; k++) {
                 float ms = 0;
-                HIPCHK(c, hipEventElapsedTime(&ms, e[k], e[k + 1]));
+                HIPCHK(c, hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]));
                 c->ms[k] += ms;
             }
         }

@@ -1,16 +1,21 @@
 // Host-side launchers of the libcapib kernels (internal).
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "capib_dev.hpp"
 
 namespace capib {
 
-hipError_t launch_lattice(const Dev &d, int par, hipStream_t st);
+// The step kernels take an optional pair of events that, when given, are
+// stamped at the start and the end of the kernel's execution
+// (hipExtLaunchKernelGGL), so that the elapsed time is the kernel alone.
+hipError_t launch_lattice(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_macro(const Dev &d, int par, hipStream_t st);
 hipError_t launch_init_flow(const Dev &d, int par, hipStream_t st);
 hipError_t launch_diag(const Dev &d, int par, hipStream_t st);
 
-hipError_t launch_interp(const Dev &d, int par, hipStream_t st);
-hipError_t launch_body(const Dev &d, int par, hipStream_t st);
+hipError_t launch_interp(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_body(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_body_geom(const Dev &d, int par, hipStream_t st);
 
 }  // namespace capib

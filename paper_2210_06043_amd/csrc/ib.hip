@@ -151,11 +151,11 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_body_geom(Dev d, int par) {
 
 // ---- host launchers --------------------------------------------------------------------------------
 
-hipError_t launch_interp(const Dev &d, int par, hipStream_t st) {
+hipError_t launch_interp(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int pts = 2 * d.nverts;
     int nb = (pts * 16 + INTERP_THREADS - 1) / INTERP_THREADS;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_interp, dim3(nb), dim3(INTERP_THREADS), 0, st, d, par);
+    hipExtLaunchKernelGGL(k_interp, dim3(nb), dim3(INTERP_THREADS), 0, st, e0, e1, 0, d, par);
     return hipGetLastError();
 }
 

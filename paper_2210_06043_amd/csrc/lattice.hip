@@ -174,12 +174,12 @@ __global__ __launch_bounds__(256) void k_diag_final(Dev d, int nblk) {
 
 // ---- host launchers ---------------------------------------------------------------
 
-hipError_t launch_lattice(const Dev &d, int par, hipStream_t st) {
+hipError_t launch_lattice(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nb = d.ntx * d.nty;
     if (d.storage == 0)
-        hipLaunchKernelGGL(k_lattice<float>, dim3(nb), dim3(LAT_THREADS), 0, st, d, par);
+        hipExtLaunchKernelGGL(k_lattice<float>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
     else
-        hipLaunchKernelGGL(k_lattice<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, d, par);
+        hipExtLaunchKernelGGL(k_lattice<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
     return hipGetLastError();
 }
 

@@ -34,8 +34,8 @@
  *     for the last failing call on that context.  Arguments are validated
  *     before any device work.  Numerical trouble detected on the device
  *     (non-finite values, |u| > 0.3 c_s, rho <= 0, a vertex outside the rows
- *     [-1, ny], a spread force beyond the fixed-point range) is sticky and is
- *     reported as CAPIB_E_UNSTABLE by capib_diagnostics().
+ *     [-1, ny]) is sticky and is reported as CAPIB_E_UNSTABLE by
+ *     capib_diagnostics().
  *
  * Threads: one context per host thread at a time; distinct contexts are
  * independent.
@@ -67,7 +67,6 @@ enum { CAPIB_DEFORMABLE = 0, CAPIB_RIGID = 1, CAPIB_FIXED = 2 };
 enum {
     CAPIB_FLAG_VERTEX_OUT = 1,   /* a vertex left the rows [-1, ny] */
     CAPIB_FLAG_FLUID = 2,        /* non-finite population, rho <= 0 or |u| > 0.3 c_s */
-    CAPIB_FLAG_FORCE_RANGE = 4,  /* a spread contribution beyond the fixed-point range */
     CAPIB_FLAG_NONFINITE_IB = 8  /* non-finite vertex force or position */
 };
 
@@ -130,6 +129,8 @@ typedef struct {
     int32_t n_bodies;
     double mass;          /* sum over nodes of drho, FP64 accumulation */
     double mom_x, mom_y;  /* sum over nodes of sum_i h_i e_i, FP64 accumulation */
+    int32_t near_tiles;   /* 64x4 lattice tiles under membrane stencils for the next step */
+    int32_t tiles;        /* all lattice tiles */
 } capib_diag;
 
 typedef struct {
@@ -176,7 +177,11 @@ capib_status capib_set_interactions(capib_ctx *ctx, double rep_prefactor, double
                                     double probe_dist);
 
 /* Advances nsteps full steps (interpolation, forces, integration, spreading,
- * bonds, lattice sweep).  Enqueued on the stream, returns immediately.     */
+ * bonds, lattice sweep).  Enqueued on the stream, returns immediately.  The
+ * lattice tiles that receive no spread force are swept on a second stream
+ * of the library concurrently with the immersed-boundary kernels; the step
+ * is joined back into the caller's stream before the tiles under the
+ * membranes are swept, so the caller sees ordinary stream order.          */
 capib_status capib_step(capib_ctx *ctx, int32_t nsteps);
 
 /* Replays the steps through captured HIP graphs of two steps when
@@ -218,12 +223,14 @@ capib_status capib_save(capib_ctx *ctx, void *host_buf, size_t *bytes);
 capib_status capib_load(capib_ctx *ctx, const void *host_buf, size_t bytes);
 
 /* Per-kernel timing with HIP events on the context's stream.  While enabled,
- * capib_step records events around the IB phase and the lattice sweep of
- * every step and synchronises at its end.  capib_read_timing returns the
- * summed milliseconds of {interpolation, body phase, lattice sweep} and the
- * number of steps timed, then resets the sums.                             */
+ * capib_step runs the kernels of each step in sequence on the caller's
+ * stream, each launched with a start/stop event pair stamped at its own
+ * start and end, and synchronises at its end.  capib_read_timing returns the
+ * summed milliseconds of {interpolation, membrane phase, lattice sweep of
+ * the far tiles, lattice sweep of the near tiles} (4 doubles) and the number
+ * of steps timed, then resets the sums.                                     */
 capib_status capib_set_timing(capib_ctx *ctx, int32_t enable);
-capib_status capib_read_timing(capib_ctx *ctx, double *ms3, int64_t *steps);
+capib_status capib_read_timing(capib_ctx *ctx, double *ms4, int64_t *steps);
 
 /* Message of the last failing call on this context (never NULL). */
 const char *capib_last_error(const capib_ctx *ctx);

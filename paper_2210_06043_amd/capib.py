@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libcapib.so")
 CAPIB_OK, CAPIB_E_ARG, CAPIB_E_STATE, CAPIB_E_HIP, CAPIB_E_UNSTABLE, CAPIB_E_CAPACITY = 0, -1, -2, -3, -4, -5
 FP32_SHIFTED, FP16_SHIFTED = 0, 1
 DEFORMABLE, RIGID, FIXED = 0, 1, 2
-FLAG_VERTEX_OUT, FLAG_FLUID, FLAG_FORCE_RANGE, FLAG_NONFINITE_IB = 1, 2, 4, 8
+FLAG_VERTEX_OUT, FLAG_FLUID, FLAG_NONFINITE_IB = 1, 2, 8
 
 _dp = C.POINTER(C.c_double)
 
@@ -41,7 +41,7 @@ class capib_bonds(C.Structure):
 
 class capib_diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("error_flags", C.c_int32), ("n_bodies", C.c_int32), ("mass", C.c_double),
-                ("mom_x", C.c_double), ("mom_y", C.c_double)]
+                ("mom_x", C.c_double), ("mom_y", C.c_double), ("near_tiles", C.c_int32), ("tiles", C.c_int32)]
 
 
 class capib_body_diag(C.Structure):
@@ -199,7 +199,8 @@ class Simulation:
         self._check(self.L.capib_set_timing(self.ctx, 1 if enable else 0))
 
     def read_timing(self):
-        ms = np.zeros(3)
+        """Summed ms of {interpolation, membrane phase, far tiles, near tiles}."""
+        ms = np.zeros(4)
         n = C.c_int64()
         self._check(self.L.capib_read_timing(self.ctx, _d(ms), C.byref(n)))
         return ms, n.value
@@ -237,7 +238,7 @@ class Simulation:
         if st != CAPIB_OK and not (allow_unstable and st == CAPIB_E_UNSTABLE):
             self._check(st)
         return dict(step=d.step, error_flags=d.error_flags, n_bodies=d.n_bodies, mass=d.mass, mom_x=d.mom_x,
-                    mom_y=d.mom_y, status=st)
+                    mom_y=d.mom_y, near_tiles=d.near_tiles, tiles=d.tiles, status=st)
 
     def body_diagnostics(self, body):
         d = capib_body_diag()

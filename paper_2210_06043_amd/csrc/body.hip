@@ -7,8 +7,9 @@
 //   pressure and viscous loads from the element probes (Eqs. 14-15)
 //   Verlet position update (Eq. 17) and BDF2 vertex velocity (Eq. 18), or the
 //   rigid BDF2 updates (Eqs. 19-20) with rigid kinematics
-//   direct forcing U - u* and spreading into the int64 fixed-point field
+//   direct forcing U - u*: spread records for the near-tile sweep
 //   bond kinetics with one Philox4x32-10 draw per site (Sec. 2.5)
+//   the near tiles of the next step (tiles under the stencils of x^{n+1})
 //
 // The kernel is latency-bound (a few thousand vertices per step against a
 // lattice of a million nodes), so every per-vertex global load is issued in
@@ -34,37 +35,58 @@ __device__ __forceinline__ void df_add2(float &ah, float &al, float bh, float bl
     ah = h;
 }
 
-// Direct-forcing spread at x^n: f_ib(x) += W(x, X) (vx, vy), weights of the
-// velocity coupling; accumulated exactly in 2^-56 units, tile tagged.
-__device__ __forceinline__ void spread(const Dev &d, float xh, float xl, float yh, float yl, float vx, float vy,
-                                       uint32_t tag) {
+constexpr int TILE_SLOTS = 512;       // distinct 64x4 tiles per membrane in the LDS table
+constexpr int HASH_PROBES = 64;       // linear-probe limit of the LDS table
+constexpr int NEW_SLOTS = 1024;       // newly marked tiles listed per workgroup
+constexpr int EMPTY_KEY = -1;
+
+__device__ __forceinline__ unsigned hash_slot(int key, int slots) {
+    return ((unsigned)key * 2654435761u) >> (32 - __builtin_ctz((unsigned)slots));
+}
+
+// Marks a tile as near for the step of parity p: flag and list entry, once.
+// Within a workgroup an LDS table (stile, may be null) filters repeats before
+// they reach global memory; across workgroups the flag's exchange does.  New
+// tiles go to the workgroup's LDS list (snew/snum) when one is given, so that
+// the global list is extended with a single counter update per workgroup
+// (a counter that every vertex incremented would serialise the kernel).
+__device__ __forceinline__ void mark_tile(const Dev &d, int p, int tile, int *stile, int *snew, int *snum) {
+    if (stile) {
+        unsigned t = hash_slot(tile, TILE_SLOTS);
+        for (int q = 0; q < HASH_PROBES; q++) {
+            int k = stile[t];
+            if (k == EMPTY_KEY) k = atomicCAS(&stile[t], EMPTY_KEY, tile);
+            if (k == EMPTY_KEY) break;   // first time in this workgroup
+            if (k == tile) return;       // this workgroup has marked it already
+            t = (t + 1) & (TILE_SLOTS - 1);
+        }
+    }
+    if (atomicExch(&d.tnear[p][tile], 1) == 0) {
+        if (snew) {
+            const int k = atomicAdd(snum, 1);
+            if (k < NEW_SLOTS) {
+                snew[k] = tile;
+                return;
+            }
+        }
+        const int slot = atomicAdd(&d.ncount[p], 1);
+        d.nlist[p][slot] = tile;
+    }
+}
+
+// Spread record of vertex g at x^n: the stencil of the velocity coupling and
+// the force dV (U - u*) to spread; the near-tile sweep gathers these records
+// (spreading as a gather: no atomics, sums in vertex order).
+__device__ __forceinline__ void write_spread(const Dev &d, int g, float xh, float xl, float yh, float yl, float fx,
+                                             float fy) {
     int ix0, iy0;
     float wx[4], wy[4], inv;
     stencil(d, xh, xl, yh, yl, false, ix0, iy0, wx, wy, inv);
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-        if (wy[b] == 0.0f) continue;
-        int j = iy0 + b;
-        if (!d.walls) j = wrapi(j, d.ny);
-        if (j < 0 || j >= d.ny) continue;
-#pragma unroll
-        for (int a = 0; a < 4; a++) {
-            const float W = wx[a] * wy[b] * inv;
-            if (W == 0.0f) continue;
-            const int i = wrapi(ix0 + a, d.nx);
-            const float cx = W * vx, cy = W * vy;
-            if (!(fabsf(cx) <= FIX_LIMIT) || !(fabsf(cy) <= FIX_LIMIT)) {
-                atomicOr(d.err, FLAG_FORCE_RANGE);
-                continue;
-            }
-            const long long qx = __float2ll_rn(cx * FIX_ONE);
-            const long long qy = __float2ll_rn(cy * FIX_ONE);
-            unsigned long long *f = (unsigned long long *)(d.fib + 2 * ((long long)j * d.pitch + i));
-            if (qx) atomicAdd(f, (unsigned long long)qx);
-            if (qy) atomicAdd(f + 1, (unsigned long long)qy);
-            d.tflag[(j / TILE_Y) * d.ntx + i / TILE_X] = tag;
-        }
-    }
+    // columns wrapped into [0, nx); rows too when y is periodic
+    d.sp_org[g] = make_int2(wrapi(ix0, d.nx), d.walls ? iy0 : wrapi(iy0, d.ny));
+    d.sp_wx[g] = make_float4(wx[0] * inv, wx[1] * inv, wx[2] * inv, wx[3] * inv);
+    d.sp_wy[g] = make_float4(wy[0], wy[1], wy[2], wy[3]);
+    d.sp_f[g] = make_float2(fx, fy);
 }
 
 __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
@@ -77,12 +99,16 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
     __shared__ float srig[8];
+    __shared__ int stile[TILE_SLOTS];
+    __shared__ int snew[NEW_SLOTS];
+    __shared__ int snum, snbase;
 
     const int b = blockIdx.x, tid = threadIdx.x;
+    if (tid == 0) snum = 0;
+    for (int h = tid; h < TILE_SLOTS; h += BT) stile[h] = EMPTY_KEY;
     const BodyParams P = d.bp[b];
     const int n = P.n, v0 = P.vstart, npar = par ^ 1;
     const long long step = *d.counter - 1;
-    const uint32_t tag = (uint32_t)(step + 1);
     const bool deform = P.kind == DEFORMABLE, rigid = P.kind == RIGID;
 
     // ---- every per-vertex global load of the step, issued together -------------
@@ -291,7 +317,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
             d.target[v0 + v] = make_float2(Ux, Uy);
             const int p = (v == 0) ? n - 1 : v - 1;
             const float dV = 0.5f * (slen[p] + slen[v]);
-            spread(d, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y), tag);
+            write_spread(d, v0 + v, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y));
         }
     } else {
         bool bad = false;
@@ -315,11 +341,28 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
             d.target[v0 + v] = make_float2(Ux, Uy);
             const int p = (v == 0) ? n - 1 : v - 1;
             const float dV = 0.5f * (slen[p] + slen[v]);
-            spread(d, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y), tag);
+            write_spread(d, v0 + v, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y));
         }
         if (bad) atomicOr(d.err, FLAG_NONFINITE_IB);
     }
     __syncthreads();   // every thread has read x^n from LDS
+
+    // near tiles of the next step: the tiles under the stencils of x^{n+1}
+#pragma unroll
+    for (int k = 0; k < VPT; k++) {
+        const int v = tid + k * BT;
+        if (v >= n) continue;
+        int tl[9];
+        const int c = stencil_tiles(d, nxh[k], nxl[k], nyh[k], nyl[k], tl);
+        for (int q = 0; q < c; q++) mark_tile(d, npar, tl[q], stile, snew, &snum);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int m = min(snum, NEW_SLOTS);
+        snbase = m ? atomicAdd(&d.ncount[npar], m) : 0;
+    }
+    __syncthreads();
+    for (int k = tid; k < min(snum, NEW_SLOTS); k += BT) d.nlist[npar][snbase + k] = snew[k];
 #pragma unroll
     for (int k = 0; k < VPT; k++) {
         const int v = tid + k * BT;
@@ -404,6 +447,23 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         S.bbox[npar][0] = a0; S.bbox[npar][1] = a1;
         S.bbox[npar][2] = a2; S.bbox[npar][3] = a3;
     }
+}
+
+// Near tiles of the current positions (before the first step, after a
+// checkpoint is loaded or membranes are added).  The flags and the count of
+// parity par must be clear.
+__global__ __launch_bounds__(256) void k_mark(Dev d, int par) {
+    const int v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= d.nverts) return;
+    int tl[9];
+    const int c = stencil_tiles(d, d.pxh[par][v], d.pxl[par][v], d.pyh[par][v], d.pyl[par][v], tl);
+    for (int q = 0; q < c; q++) mark_tile(d, par, tl[q], nullptr, nullptr, nullptr);
+}
+
+hipError_t launch_mark(const Dev &d, int par, hipStream_t st) {
+    if (d.nverts == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark, dim3((d.nverts + 255) / 256), dim3(256), 0, st, d, par);
+    return hipGetLastError();
 }
 
 hipError_t launch_body(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {

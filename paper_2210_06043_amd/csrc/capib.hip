@@ -45,7 +45,7 @@ struct capib_ctx {
     size_t esize = 4;
     // workspace layout
     size_t ws_bytes = 0;
-    size_t off_pop[2]{}, off_fib = 0, off_tflag = 0, off_red = 0, off_macro = 0, off_rowref = 0, off_scal = 0;
+    size_t off_pop[2]{}, off_sp = 0, off_near = 0, off_red = 0, off_macro = 0, off_rowref = 0, off_scal = 0;
     size_t off_ib = 0, ib_bytes = 0;
     size_t off_bp = 0, off_bs = 0, off_vbody = 0, off_pos[8]{}, off_dxm = 0, off_dym = 0, off_x0[4]{};
     size_t off_r0x = 0, off_r0y = 0, off_l0 = 0, off_th0 = 0, off_ustar = 0, off_probe = 0, off_force = 0;
@@ -62,11 +62,15 @@ struct capib_ctx {
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev;
-    double ms[3] = {0, 0, 0};
+    double ms[4] = {0, 0, 0, 0};
     long long tsteps = 0;
     // graphs
     bool use_graph = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // fork/join of the immersed-boundary phase with the far lattice tiles
+    hipStream_t side = nullptr, cap_side = nullptr;
+    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
+    bool marks_valid = false;
 };
 
 static capib_status fail(capib_ctx *c, capib_status s, const char *fmt, ...) {
@@ -90,12 +94,15 @@ static void layout(capib_ctx *c) {
     size_t o = 0;
     const size_t N = (size_t)c->pitch * L.ny;
     for (int p = 0; p < 2; p++) { c->off_pop[p] = o; o = align256(o + 9 * N * c->esize); }
-    c->off_fib = o; o = align256(o + 2 * N * sizeof(long long));
-    c->off_tflag = o; o = align256(o + (size_t)c->ntx * c->nty * 4);
+    // near-tile flags and lists (two parities each) and their two counts
+    c->off_near = o; o = align256(o + 4 * (size_t)c->ntx * c->nty * 4 + 64);
     c->off_red = o; o = align256(o + (3 * (size_t)c->ntx * c->nty + 3) * 8);
     c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
     c->off_rowref = o; o = align256(o + (size_t)L.ny * 16 * 4);
     c->off_scal = o; o = align256(o + 64);
+    // spread records (rewritten every step, not checkpointed): origin, x and y
+    // weights, force per vertex
+    c->off_sp = o; o = align256(o + (size_t)std::max(1, L.max_vertices) * (8 + 16 + 16 + 8));
     // IB region: one contiguous block (checkpointed whole)
     const size_t B = (size_t)std::max(1, L.max_bodies), V = (size_t)std::max(1, L.max_vertices),
                  S = (size_t)std::max(1, L.max_sites);
@@ -139,8 +146,23 @@ static void fill_dev(capib_ctx *c) {
     d.scale = L.storage ? (float)L.fp16_scale : 1.0f;
     d.inv_scale = L.storage ? (float)(1.0 / L.fp16_scale) : 1.0f;
     for (int p = 0; p < 2; p++) d.pop[p] = b + c->off_pop[p];
-    d.fib = (long long *)(b + c->off_fib);
-    d.tflag = (uint32_t *)(b + c->off_tflag);
+    {
+        const size_t V = (size_t)std::max(1, L.max_vertices);
+        char *q = b + c->off_sp;
+        d.sp_wx = (float4 *)q;
+        d.sp_wy = (float4 *)(q + 16 * V);
+        d.sp_org = (int2 *)(q + 32 * V);
+        d.sp_f = (float2 *)(q + 40 * V);
+    }
+    {
+        const size_t nt = (size_t)c->ntx * c->nty;
+        int *nb = (int *)(b + c->off_near);
+        d.tnear[0] = nb;
+        d.tnear[1] = nb + nt;
+        d.nlist[0] = nb + 2 * nt;
+        d.nlist[1] = nb + 3 * nt;
+        d.ncount = nb + 4 * nt;
+    }
     d.red = (double *)(b + c->off_red);
     d.macro = (float *)(b + c->off_macro);
     d.rowref = (const float *)(b + c->off_rowref);
@@ -274,6 +296,7 @@ capib_status capib_bind_workspace(capib_ctx *c, void *ptr, size_t bytes) {
     drop_graphs(c);
     c->base = (char *)ptr;
     c->bound = true;
+    c->marks_valid = false;
     c->par = 0;
     c->step = 0;
     c->nbodies = c->nverts = c->nsites = 0;
@@ -454,6 +477,7 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     c->bodies.push_back(bh);
     c->nbodies++;
     c->nverts += n;
+    c->marks_valid = false;
     drop_graphs(c);
     fill_dev(c);
     if (body_id) *body_id = b;
@@ -549,22 +573,52 @@ capib_status capib_set_interactions(capib_ctx *c, double pref, double cut, doubl
     return CAPIB_OK;
 }
 
-static capib_status one_step(capib_ctx *c, int par) {
-    HIPCHK(c, launch_interp(c->d, par, c->stream));
-    HIPCHK(c, launch_body(c->d, par, c->stream));
-    HIPCHK(c, launch_lattice(c->d, par, c->stream));
+// Streams and events of the fork/join step, created once.
+static capib_status ensure_streams(capib_ctx *c) {
+    if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->cap_side) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_side, hipStreamNonBlocking));
+    for (int k = 0; k < 2; k++) {
+        if (!c->ev_fork[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork[k], hipEventDisableTiming));
+        if (!c->ev_join[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
+    }
+    return CAPIB_OK;
+}
+
+// Near tiles of the current positions, needed before a step when the
+// previous step did not mark them (start, new membranes, loaded checkpoint).
+static capib_status ensure_marks(capib_ctx *c) {
+    if (c->marks_valid) return CAPIB_OK;
+    const size_t nt = (size_t)c->ntx * c->nty;
+    HIPCHK(c, hipMemsetAsync(c->base + c->off_near, 0, 4 * nt * 4 + 64, c->stream));
+    HIPCHK(c, launch_mark(c->d, c->par, c->stream));
+    c->marks_valid = true;
+    return CAPIB_OK;
+}
+
+// One step: the far tiles of the lattice sweep run on the main stream while
+// the interpolation and membrane kernels run on the side stream; the near
+// tiles follow the join.  main/side are the streams to enqueue on, k selects
+// the event pair (so that two steps can be captured in one graph).
+static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_t side, int k) {
+    HIPCHK(c, hipEventRecord(c->ev_fork[k], main));
+    HIPCHK(c, hipStreamWaitEvent(side, c->ev_fork[k], 0));
+    HIPCHK(c, launch_interp(c->d, par, side));
+    HIPCHK(c, launch_body(c->d, par, side));
+    HIPCHK(c, launch_lattice_far(c->d, par, main));
+    HIPCHK(c, hipEventRecord(c->ev_join[k], side));
+    HIPCHK(c, hipStreamWaitEvent(main, c->ev_join[k], 0));
+    HIPCHK(c, launch_lattice_near(c->d, par, main));
     return CAPIB_OK;
 }
 
 static capib_status make_graph(capib_ctx *c, int par) {
-    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    capib_status s = ensure_streams(c);
+    if (s) return s;
     hipGraph_t g;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipStream_t keep = c->stream;
-    c->stream = c->cap_stream;
-    capib_status s = one_step(c, par);
-    if (!s) s = one_step(c, par ^ 1);
-    c->stream = keep;
+    s = one_step(c, par, c->cap_stream, c->cap_side, 0);
+    if (!s) s = one_step(c, par ^ 1, c->cap_stream, c->cap_side, 1);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (s) return s;
     if (e != hipSuccess) return fail(c, CAPIB_E_HIP, "graph capture: %s", hipGetErrorString(e));
@@ -578,27 +632,30 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
     capib_status s = need_ws(c);
     if (s) return s;
     if (nsteps < 0) return fail(c, CAPIB_E_ARG, "negative step count");
+    if ((s = ensure_streams(c))) return s;
+    if ((s = ensure_marks(c))) return s;
     if (c->timing) {
-        // each kernel launched with a start/stop event pair stamped at its
-        // own start and end
-        const size_t need = 6 * (size_t)nsteps;
+        // kernels in sequence on the main stream, each launched with a
+        // start/stop event pair stamped at its own start and end
+        const size_t need = 8 * (size_t)nsteps;
         while (c->ev.size() < need) {
             hipEvent_t e;
             HIPCHK(c, hipEventCreate(&e));
             c->ev.push_back(e);
         }
         for (int t = 0; t < nsteps; t++) {
-            hipEvent_t *e = &c->ev[6 * t];
+            hipEvent_t *e = &c->ev[8 * t];
             HIPCHK(c, launch_interp(c->d, c->par, c->stream, e[0], e[1]));
             HIPCHK(c, launch_body(c->d, c->par, c->stream, e[2], e[3]));
-            HIPCHK(c, launch_lattice(c->d, c->par, c->stream, e[4], e[5]));
+            HIPCHK(c, launch_lattice_far(c->d, c->par, c->stream, e[4], e[5]));
+            HIPCHK(c, launch_lattice_near(c->d, c->par, c->stream, e[6], e[7]));
             c->par ^= 1;
             c->step++;
         }
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (int t = 0; t < nsteps; t++) {
-            hipEvent_t *e = &c->ev[6 * t];
-            for (int k = 0; k < 3; k++) {
+            hipEvent_t *e = &c->ev[8 * t];
+            for (int k = 0; k < 4; k++) {
                 float ms = 0;
                 HIPCHK(c, hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]));
                 c->ms[k] += ms;
@@ -616,7 +673,7 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
         }
     }
     for (; t < nsteps; t++) {
-        if ((s = one_step(c, c->par))) return s;
+        if ((s = one_step(c, c->par, c->stream, c->side, 0))) return s;
         c->par ^= 1;
         c->step++;
     }
@@ -730,6 +787,13 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     out->mass = r[0] + c->lat.nx * rm;
     out->mom_x = r[1] + c->lat.nx * rx;
     out->mom_y = r[2];
+    out->tiles = c->ntx * c->nty;
+    out->near_tiles = 0;
+    if (c->marks_valid) {
+        int cnt = 0;
+        if ((s = d2h(c, &cnt, c->off_near + 4 * (size_t)c->ntx * c->nty * 4 + 4 * (size_t)c->par, 4))) return s;
+        out->near_tiles = cnt;
+    }
     if (cnt != c->step) return fail(c, CAPIB_E_STATE, "device step counter %lld != %lld", cnt, c->step);
     if (err) return fail(c, CAPIB_E_UNSTABLE, "device error flags 0x%x", err);
     return CAPIB_OK;
@@ -832,9 +896,8 @@ capib_status capib_load(capib_ctx *c, const void *buf, size_t bytes) {
     p += 16;
     std::memcpy(c->ref_u.data(), p, (size_t)c->lat.ny * 8);
     if ((s = upload_ref(c))) return s;
-    // spread-force field and tile tags start clean
-    HIPCHK(c, hipMemsetAsync(c->base + c->off_fib, 0, 2 * (size_t)c->pitch * c->lat.ny * 8, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->base + c->off_tflag, 0, (size_t)c->ntx * c->nty * 4, c->stream));
+    // near tiles are marked afresh
+    c->marks_valid = false;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return CAPIB_OK;
 }
@@ -845,9 +908,9 @@ capib_status capib_set_timing(capib_ctx *c, int32_t enable) {
     return CAPIB_OK;
 }
 
-capib_status capib_read_timing(capib_ctx *c, double *ms3, int64_t *steps) {
-    if (!c || !ms3) return CAPIB_E_ARG;
-    for (int k = 0; k < 3; k++) { ms3[k] = c->ms[k]; c->ms[k] = 0; }
+capib_status capib_read_timing(capib_ctx *c, double *ms4, int64_t *steps) {
+    if (!c || !ms4) return CAPIB_E_ARG;
+    for (int k = 0; k < 4; k++) { ms4[k] = c->ms[k]; c->ms[k] = 0; }
     if (steps) *steps = c->tsteps;
     c->tsteps = 0;
     return CAPIB_OK;
@@ -860,6 +923,12 @@ void capib_destroy(capib_ctx *c) {
     if (c->bound) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; k++) {
+        if (c->ev_fork[k]) (void)hipEventDestroy(c->ev_fork[k]);
+        if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+    }
+    if (c->side) { (void)hipStreamSynchronize(c->side); (void)hipStreamDestroy(c->side); }
+    if (c->cap_side) (void)hipStreamDestroy(c->cap_side);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }

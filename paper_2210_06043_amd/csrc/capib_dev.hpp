@@ -1,5 +1,5 @@
 // Device-side data layout and helpers shared by the kernels of libcapib.
-// gfx950 only: wave64, LDS-resident membranes, int64 fixed-point spreading.
+// gfx950 only: wave64, LDS-resident membranes, spreading gathered per tile.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -7,21 +7,16 @@
 namespace capib {
 
 // Lattice sweep tile: one wave per row segment of 64 nodes, four rows per
-// workgroup.  The spread-force tile flags use the same tiling.
+// workgroup.  The near-tile flags use the same tiling.
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int LAT_THREADS = TILE_X * TILE_Y;
 constexpr int MAXV_BODY = 1024;    // vertices of one membrane held in LDS
 constexpr int BODY_THREADS = 512;
 constexpr int INTERP_THREADS = 256;  // 16 lanes per interpolation point
-// Spread forces accumulate as int64 with 56 fractional bits: exact,
-// order-independent sums; contributions must stay below 2^7 in magnitude.
-constexpr float FIX_ONE = 72057594037927936.0f;   // 2^56
-constexpr float FIX_INV = 1.3877787807814457e-17f; // 2^-56
-constexpr float FIX_LIMIT = 127.0f;
 
 enum { DEFORMABLE = 0, RIGID = 1, FIXED = 2 };
-enum { FLAG_VERTEX_OUT = 1, FLAG_FLUID = 2, FLAG_FORCE_RANGE = 4, FLAG_NONFINITE_IB = 8 };
+enum { FLAG_VERTEX_OUT = 1, FLAG_FLUID = 2, FLAG_NONFINITE_IB = 8 };
 
 // Read-only description of a body.
 struct BodyParams {
@@ -59,8 +54,13 @@ struct Dev {
     // channel profile.  rowref[16 y + i] (i < 9) is the constant that turns a
     // pulled stored value into h_i - r_i(y); rowref[16 y + 9] = u_ref(y).
     const float *rowref;
-    long long *fib;                 // spread force [ny][pitch][2], 2^-56 units
-    uint32_t *tflag;                // per tile: step tag of the last spread into it
+    // Near tiles of a step: the 64x4 tiles that the stencils of the vertex
+    // positions x^n cover, i.e. the only tiles that can receive spread force
+    // in step n.  Double-buffered by step parity: tnear[p][tile] is 1 for a
+    // near tile, nlist[p][0 .. ncount[p]) lists them.
+    int *tnear[2];
+    int *nlist[2];
+    int *ncount;
     // immersed boundary
     int nbodies, nverts, nsites, pad1;
     float rep_pref, rep_cut, rep_dmin, probe;
@@ -76,6 +76,13 @@ struct Dev {
     float4 *probe4;                             // p, sxx, sxy, syy at element probes
     float2 *force;                              // total Lagrangian force
     float2 *target;                             // U^{n+1}
+    // spread records of the step, one per vertex (written by the membrane
+    // kernel, gathered by the near-tile sweep): stencil origin, x and y
+    // weights (x weights already divided by the normalising sum), and the
+    // force dV (U - u*) to spread
+    int2 *sp_org;
+    float4 *sp_wx, *sp_wy;
+    float2 *sp_f;
     int2 *srange;                               // sites [begin, end) per element
     int *s_host, *s_state, *s_orig;
     float *s_frac, *s_anh, *s_anl;
@@ -121,30 +128,40 @@ __device__ __forceinline__ void df_add(float &hi, float &lo, float d) {
 // they stay in the normalising sum.  For the probe fields (renorm = true) the
 // fluid rows are renormalised to sum one.  Returns true when the unclamped Y
 // left [-1, ny].
-__device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float yh, float yl, bool renorm,
-                                        int &ix0, int &iy0, float wx[4], float wy[4], float &inv) {
+// Origin of the stencil of a point given as hi + lo: ix0 = floor(X) - 1,
+// iy0 = floor(Y) - 1 and the fractions sx, sy.  With walls, Y is clamped to
+// [-1, ny].  Non-finite or absurd coordinates are flagged and mapped to the
+// origin so that every index stays in range.  Returns true when the point
+// was moved (unclamped Y outside [-1, ny], or unusable coordinates).
+__device__ __forceinline__ bool stencil_origin(const Dev &d, float xh, float xl, float yh, float yl, int &ix0,
+                                               int &iy0, float &sx, float &sy) {
     bool out = false;
-    // non-finite or absurd coordinates are flagged and mapped to the origin so
-    // that every index below stays in range
     if (!(fabsf(xh) < 1.0e8f) || !(fabsf(xl) < 1.0e4f)) { xh = 0.0f; xl = 0.0f; out = true; }
     if (!(fabsf(yh) < 1.0e8f) || !(fabsf(yl) < 1.0e4f)) { yh = 0.0f; yl = 0.0f; out = true; }
     int ix = (int)floorf(xh);
-    float sx = (xh - (float)ix) + xl;
+    sx = (xh - (float)ix) + xl;
     float kx = floorf(sx);
     ix += (int)kx;
     sx -= kx;
-    int iy;
-    float sy;
     if (d.walls) {
-        float Y = yh + yl;
-        if (Y < -1.0f) { Y = -1.0f; out = true; yh = -1.0f; yl = 0.0f; }
-        if (Y > (float)d.ny) { Y = (float)d.ny; out = true; yh = (float)d.ny; yl = 0.0f; }
+        const float Y = yh + yl;
+        if (Y < -1.0f) { out = true; yh = -1.0f; yl = 0.0f; }
+        if (Y > (float)d.ny) { out = true; yh = (float)d.ny; yl = 0.0f; }
     }
-    iy = (int)floorf(yh);
+    int iy = (int)floorf(yh);
     sy = (yh - (float)iy) + yl;
     float ky = floorf(sy);
     iy += (int)ky;
     sy -= ky;
+    ix0 = ix - 1;
+    iy0 = iy - 1;
+    return out;
+}
+
+__device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float yh, float yl, bool renorm,
+                                        int &ix0, int &iy0, float wx[4], float wy[4], float &inv) {
+    float sx, sy;
+    const bool out = stencil_origin(d, xh, xl, yh, yl, ix0, iy0, sx, sy);
     float cx, snx, cy, sny;
     sincospif(0.5f * sx, &snx, &cx);
     sincospif(0.5f * sy, &sny, &cy);
@@ -153,8 +170,6 @@ __device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float 
     wx[2] = 0.25f * (1.0f + snx); wx[3] = 0.25f * (1.0f - cx);
     wy[0] = 0.25f * (1.0f - sny); wy[1] = 0.25f * (1.0f + cy);
     wy[2] = 0.25f * (1.0f + sny); wy[3] = 0.25f * (1.0f - cy);
-    ix0 = ix - 1;
-    iy0 = iy - 1;
     const float sxw = (wx[0] + wx[1]) + (wx[2] + wx[3]);
     const float syfull = (wy[0] + wy[1]) + (wy[2] + wy[3]);
     if (d.walls) {
@@ -242,6 +257,43 @@ struct EqDev {
         return w * (c0 + drho * (3.0f * eu + 4.5f * eu * eu) + 3.0f * edu + 4.5f * edu * (eu + ex * uref));
     }
 };
+
+// The tiles covered by the velocity-coupling stencil of a point: its four
+// rows (clipped to the fluid with walls, wrapped without) and four columns
+// (wrapped).  Four consecutive wrapped rows or columns can meet three tiles
+// when the last tile of the lattice is narrower than the stencil.  Returns
+// the count (at most 9) and writes the tile indices.
+__device__ __forceinline__ int stencil_tiles(const Dev &d, float xh, float xl, float yh, float yl, int tiles[9]) {
+    int ix0, iy0;
+    float sx, sy;
+    stencil_origin(d, xh, xl, yh, yl, ix0, iy0, sx, sy);
+    int ty[3], nty = 0;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        int j = iy0 + b;
+        if (d.walls) {
+            if (j < 0 || j >= d.ny) continue;
+        } else {
+            j = wrapi(j, d.ny);
+        }
+        const int t = j / TILE_Y;
+        bool seen = false;
+        for (int k = 0; k < nty; k++) seen |= (ty[k] == t);
+        if (!seen && nty < 3) ty[nty++] = t;
+    }
+    int tx[3], ntx = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int t = wrapi(ix0 + a, d.nx) / TILE_X;
+        bool seen = false;
+        for (int k = 0; k < ntx; k++) seen |= (tx[k] == t);
+        if (!seen && ntx < 3) tx[ntx++] = t;
+    }
+    int c = 0;
+    for (int a = 0; a < nty; a++)
+        for (int b = 0; b < ntx; b++) tiles[c++] = ty[a] * d.ntx + tx[b];
+    return c;
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -9,7 +9,11 @@ namespace capib {
 // The step kernels take an optional pair of events that, when given, are
 // stamped at the start and the end of the kernel's execution
 // (hipExtLaunchKernelGGL), so that the elapsed time is the kernel alone.
-hipError_t launch_lattice(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr,
+                              hipEvent_t e1 = nullptr);
+hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr,
+                               hipEvent_t e1 = nullptr);
+hipError_t launch_mark(const Dev &d, int par, hipStream_t st);
 hipError_t launch_macro(const Dev &d, int par, hipStream_t st);
 hipError_t launch_init_flow(const Dev &d, int par, hipStream_t st);
 hipError_t launch_diag(const Dev &d, int par, hipStream_t st);

@@ -19,11 +19,12 @@ __device__ __forceinline__ float stpop<float>(float v, float) { return v; }
 template <>
 __device__ __forceinline__ _Float16 stpop<_Float16>(float v, float scale) { return (_Float16)(v * scale); }
 
-template <typename T>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice(Dev d, int par) {
+// One node of one 64x4 tile.  FORCED: the tile is a near tile of this step
+// and (ax, ay) is the IB force spread onto this node.
+template <typename T, bool FORCED>
+__device__ __forceinline__ void lattice_node(const Dev &d, int par, int tile, float ax = 0.0f, float ay = 0.0f) {
     const T *__restrict__ A = (const T *)d.pop[par];
     T *__restrict__ B = (T *)d.pop[par ^ 1];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int ty = tile / d.ntx;
     const int tx = tile - ty * d.ntx;
     const int i = tx * TILE_X + (threadIdx.x & (TILE_X - 1));
@@ -41,16 +42,9 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(Dev d, int par) {
     // total force: uniform drive plus the spread IB force of this step
     float Fx = d.gx, Fy = d.gy;
     const long long node = (long long)j * d.pitch + i;
-    const uint32_t tag = (uint32_t)(*d.counter);
-    if (d.tflag[tile] == tag) {
-        long long *f = d.fib + 2 * node;
-        long long qx = f[0], qy = f[1];
-        if (qx | qy) {
-            Fx += (float)qx * FIX_INV;
-            Fy += (float)qy * FIX_INV;
-            f[0] = 0;
-            f[1] = 0;
-        }
+    if (FORCED) {
+        Fx += ax;
+        Fy += ay;
     }
 
     const float rho = 1.0f + drho;
@@ -92,6 +86,117 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(Dev d, int par) {
     const long long Q = d.qstride;
 #pragma unroll
     for (int q = 0; q < 9; q++) B[q * Q + node] = stpop<T>(out[q], d.scale);
+}
+
+// Far tiles: every tile of the lattice except this step's near tiles, in
+// XCD-contiguous order.  Runs concurrently with the immersed-boundary phase.
+template <typename T>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int par) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (d.tnear[par][tile]) return;
+    lattice_node<T, false>(d, par, tile);
+}
+
+// Does a 4-wide stencil starting at o (wrapped into [0, n)) meet the range
+// [t0, t0 + w) of a periodic axis of length n?
+__device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
+    int r = o - t0;
+    if (r < 0) r += n;
+    return r < w || r + 3 >= n;
+}
+
+// Near tiles of this step, after the membrane kernel: grid-stride over the
+// list.  Spreading (Sec. 2.2) is done here as a gather: for each tile the
+// workgroup scans the membranes whose bounding box (of x^n, widened by the
+// stencil reach) meets the tile, 256 vertices at a time, compacts the
+// vertices whose stencil covers the tile into LDS in vertex order, and every
+// node sums W f over them in that order, so the result does not depend on
+// scheduling.  Each tile's flag is cleared for the next step of the same
+// parity.
+template <typename T>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par) {
+    __shared__ int2 sorg[LAT_THREADS];
+    __shared__ float sw[LAT_THREADS][10];   // x weights (normalised), y weights, force
+    __shared__ int swave[LAT_THREADS / 64];
+    const int cnt = d.ncount[par];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+        const int tile = d.nlist[par][k];
+        const int ty = tile / d.ntx, tx = tile - ty * d.ntx;
+        const int x0 = tx * TILE_X, y0 = ty * TILE_Y;
+        const int tw = min(TILE_X, d.nx - x0), th = min(TILE_Y, d.ny - y0);
+        const int i = x0 + lane, j = y0 + wv;
+        float ax = 0.0f, ay = 0.0f;
+        for (int b = 0; b < d.nbodies; b++) {
+            const float bx0 = d.bs[b].bbox[par][0], bx1 = d.bs[b].bbox[par][1];
+            const float by0 = d.bs[b].bbox[par][2], by1 = d.bs[b].bbox[par][3];
+            bool meet = true;   // an unusable box (non-finite, huge) meets every tile
+            if (fabsf(bx0) < 1.0e8f && fabsf(bx1) < 1.0e8f && bx1 - bx0 < (float)(d.nx - 8)) {
+                const int lo = wrapi((int)floorf(bx0) - 3, d.nx);
+                const int wd = (int)ceilf(bx1) - (int)floorf(bx0) + 6;
+                int r = lo - x0;
+                if (r < 0) r += d.nx;
+                meet = r < tw || r + wd >= d.nx;
+            }
+            if (meet && fabsf(by0) < 1.0e8f && fabsf(by1) < 1.0e8f) {
+                const int lo = (int)floorf(d.walls ? fminf(fmaxf(by0, -1.0f), (float)d.ny) : by0) - 3;
+                const int hi = (int)ceilf(d.walls ? fminf(fmaxf(by1, -1.0f), (float)d.ny) : by1) + 3;
+                if (d.walls) {
+                    meet = hi >= y0 && lo < y0 + th;
+                } else if (hi - lo < d.ny) {
+                    int r = wrapi(lo, d.ny) - y0;
+                    if (r < 0) r += d.ny;
+                    meet = r < th || r + (hi - lo) >= d.ny;
+                }
+            }
+            if (!meet) continue;
+            const int vs = d.bp[b].vstart, n = d.bp[b].n;
+            for (int c0 = 0; c0 < n; c0 += LAT_THREADS) {
+                const int v = c0 + (int)threadIdx.x;
+                bool hit = false;
+                int2 o = make_int2(0, 0);
+                if (v < n) {
+                    o = d.sp_org[vs + v];
+                    const bool hx = meets_periodic(o.x, x0, tw, d.nx);
+                    const bool hy = d.walls ? (o.y + 3 >= y0 && o.y < y0 + th) : meets_periodic(o.y, y0, th, d.ny);
+                    hit = hx && hy;
+                }
+                const unsigned long long m = __ballot(hit);
+                if (lane == 0) swave[wv] = __popcll(m);
+                __syncthreads();
+                int base = 0, tot = 0;
+#pragma unroll
+                for (int w = 0; w < LAT_THREADS / 64; w++) {
+                    base += (w < wv) ? swave[w] : 0;
+                    tot += swave[w];
+                }
+                if (hit) {
+                    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                    const float4 wx = d.sp_wx[vs + v], wy = d.sp_wy[vs + v];
+                    const float2 f = d.sp_f[vs + v];
+                    sorg[slot] = o;
+                    sw[slot][0] = wx.x; sw[slot][1] = wx.y; sw[slot][2] = wx.z; sw[slot][3] = wx.w;
+                    sw[slot][4] = wy.x; sw[slot][5] = wy.y; sw[slot][6] = wy.z; sw[slot][7] = wy.w;
+                    sw[slot][8] = f.x; sw[slot][9] = f.y;
+                }
+                __syncthreads();
+                for (int h = 0; h < tot; h++) {
+                    int a = i - sorg[h].x;
+                    if (a < 0) a += d.nx;
+                    int c = j - sorg[h].y;
+                    if (!d.walls && c < 0) c += d.ny;
+                    if (a < 4 && (unsigned)c < 4u) {
+                        const float w = sw[h][a] * sw[h][4 + c];
+                        ax += w * sw[h][8];
+                        ay += w * sw[h][9];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x == 0) d.tnear[par][tile] = 0;
+        lattice_node<T, true>(d, par, tile, ax, ay);
+    }
 }
 
 // Moments of the current state for read-out: drho and u* = (j + g/2)/rho.
@@ -174,12 +279,24 @@ __global__ __launch_bounds__(256) void k_diag_final(Dev d, int nblk) {
 
 // ---- host launchers ---------------------------------------------------------------
 
-hipError_t launch_lattice(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nb = d.ntx * d.nty;
     if (d.storage == 0)
-        hipExtLaunchKernelGGL(k_lattice<float>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+        hipExtLaunchKernelGGL(k_lattice_far<float>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
     else
-        hipExtLaunchKernelGGL(k_lattice<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+        hipExtLaunchKernelGGL(k_lattice_far<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    // enough workgroups for the near tiles of a few thousand vertices; the
+    // grid-stride loop covers any count
+    const int nt = d.ntx * d.nty;
+    const int nb = nt < 1024 ? nt : 1024;
+    if (d.storage == 0)
+        hipExtLaunchKernelGGL(k_lattice_near<float>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+    else
+        hipExtLaunchKernelGGL(k_lattice_near<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
     return hipGetLastError();
 }
 

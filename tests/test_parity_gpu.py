@@ -133,7 +133,7 @@ def test_c2_window_parity():
 
 def test_determinism_and_graph_equivalence():
     """Two runs, and a run replayed through HIP graphs, are bitwise identical
-    (deterministic fixed-point spreading: a race would show up here)."""
+    (spreading is a gather summed in vertex order: a race would show up here)."""
     say("determinism")
     cfg = inputs.config_tiny()
     res = []

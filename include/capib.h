@@ -80,7 +80,7 @@ typedef struct capib_ctx capib_ctx;
  *   storage    CAPIB_FP32_SHIFTED or CAPIB_FP16_SHIFTED
  *   fp16_scale power of two multiplying stored FP16 deviations (ignored for FP32)
  *   max_*      capacities of the workspace; max_vertices counts all bodies,
- *              a single body holds at most 1024 vertices                    */
+ *              a single body holds at most 1024 vertices and 2048 sites     */
 typedef struct {
     int32_t nx, ny;
     double tau, gx, gy;
@@ -109,6 +109,7 @@ typedef struct {
 } capib_membrane;
 
 /* Ligand sites on a body, receptors on the lower wall (Sec. 2.5).
+ *   n_sites          0..2048 (CAPIB_E_CAPACITY beyond)
  *   host_elem, frac  site s sits on element host_elem[s] at fraction frac[s]
  *   sigma            bond spring constant of Eq. (13)
  *   y_cr, y_eq       critical gap for binding and equilibrium bond length

@@ -9,7 +9,6 @@
 //   rigid BDF2 updates (Eqs. 19-20) with rigid kinematics
 //   direct forcing U - u*: spread records for the near-tile sweep
 //   bond kinetics with one Philox4x32-10 draw per site (Sec. 2.5)
-//   the near tiles of the next step (tiles under the stencils of x^{n+1})
 //
 // The kernel is latency-bound (a few thousand vertices per step against a
 // lattice of a million nodes), so every per-vertex global load is issued in
@@ -22,6 +21,7 @@ namespace capib {
 
 constexpr int BT = BODY_THREADS;
 constexpr int VPT = MAXV_BODY / BT;   // vertices per thread
+constexpr int SPT = MAXS_BODY / BT;   // ligand sites per thread
 constexpr int MAX_BOX = 64;           // bounding boxes cached in LDS
 
 // (ah, al) += (bh, bl), renormalised.
@@ -35,40 +35,10 @@ __device__ __forceinline__ void df_add2(float &ah, float &al, float bh, float bl
     ah = h;
 }
 
-constexpr int TILE_SLOTS = 512;       // distinct 64x4 tiles per membrane in the LDS table
-constexpr int HASH_PROBES = 64;       // linear-probe limit of the LDS table
-constexpr int NEW_SLOTS = 1024;       // newly marked tiles listed per workgroup
-constexpr int EMPTY_KEY = -1;
-
-__device__ __forceinline__ unsigned hash_slot(int key, int slots) {
-    return ((unsigned)key * 2654435761u) >> (32 - __builtin_ctz((unsigned)slots));
-}
-
-// Marks a tile as near for the step of parity p: flag and list entry, once.
-// Within a workgroup an LDS table (stile, may be null) filters repeats before
-// they reach global memory; across workgroups the flag's exchange does.  New
-// tiles go to the workgroup's LDS list (snew/snum) when one is given, so that
-// the global list is extended with a single counter update per workgroup
-// (a counter that every vertex incremented would serialise the kernel).
-__device__ __forceinline__ void mark_tile(const Dev &d, int p, int tile, int *stile, int *snew, int *snum) {
-    if (stile) {
-        unsigned t = hash_slot(tile, TILE_SLOTS);
-        for (int q = 0; q < HASH_PROBES; q++) {
-            int k = stile[t];
-            if (k == EMPTY_KEY) k = atomicCAS(&stile[t], EMPTY_KEY, tile);
-            if (k == EMPTY_KEY) break;   // first time in this workgroup
-            if (k == tile) return;       // this workgroup has marked it already
-            t = (t + 1) & (TILE_SLOTS - 1);
-        }
-    }
+// Marks a tile as near for the step of parity p: flag and list entry, once
+// (the flag's exchange decides which caller appends it).
+__device__ __forceinline__ void mark_tile(const Dev &d, int p, int tile) {
     if (atomicExch(&d.tnear[p][tile], 1) == 0) {
-        if (snew) {
-            const int k = atomicAdd(snum, 1);
-            if (k < NEW_SLOTS) {
-                snew[k] = tile;
-                return;
-            }
-        }
         const int slot = atomicAdd(&d.ncount[p], 1);
         d.nlist[p][slot] = tile;
     }
@@ -96,22 +66,25 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     __shared__ float sSx[MAXV_BODY], sSy[MAXV_BODY];   // spring force k (l - l0) t_hat of each element
     __shared__ float sHx[MAXV_BODY], sHy[MAXV_BODY];   // half of the element's area, bond and load force
     __shared__ float sbox[MAX_BOX][4];
+    __shared__ float sqxh[MAXV_BODY], sqxl[MAXV_BODY], sqyh[MAXV_BODY], sqyl[MAXV_BODY];   // another body, staged
+    __shared__ int ss_state[MAXS_BODY];
+    __shared__ float ss_frac[MAXS_BODY], ss_anh[MAXS_BODY], ss_anl[MAXS_BODY];
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
     __shared__ float srig[8];
-    __shared__ int stile[TILE_SLOTS];
-    __shared__ int snew[NEW_SLOTS];
-    __shared__ int snum, snbase;
 
     const int b = blockIdx.x, tid = threadIdx.x;
-    if (tid == 0) snum = 0;
-    for (int h = tid; h < TILE_SLOTS; h += BT) stile[h] = EMPTY_KEY;
     const BodyParams P = d.bp[b];
-    const int n = P.n, v0 = P.vstart, npar = par ^ 1;
+    const int4 rg = b < ARG_BODIES ? d.brange[b] : make_int4(P.vstart, P.n, P.site_start, P.n_sites);
+    const int n = rg.y, v0 = rg.x, ns = rg.w, s0 = rg.z, npar = par ^ 1;
     const long long step = *d.counter - 1;
     const bool deform = P.kind == DEFORMABLE, rigid = P.kind == RIGID;
+    // rigid state (centroid displacement, angle, velocities), read up front
+    const float4 RS0 = *(const float4 *)&d.bs[b].dcxh;   // dcxh, dcxl, dcyh, dcyl
+    const float4 RS1 = *(const float4 *)&d.bs[b].phih;   // phih, phil, ucx, ucy
+    const float4 RS2 = *(const float4 *)&d.bs[b].ucxm;   // ucxm, ucym, om, omm
 
-    // ---- every per-vertex global load of the step, issued together -------------
+    // ---- every per-vertex and per-site global load of the step, issued together --
     float rxh[VPT], rxl[VPT], ryh[VPT], ryl[VPT], rl0[VPT], rth0[VPT], rdxm[VPT], rdym[VPT];
     float2 rus[VPT];
     float4 rpr[VPT];
@@ -127,7 +100,31 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         rus[k] = d.ustar[g];
         rpr[k] = d.probe4[g];
         rdxm[k] = d.dxm[g]; rdym[k] = d.dym[g];
-        rsr[k] = P.n_sites ? d.srange[g] : make_int2(0, 0);
+        rsr[k] = ns ? d.srange[g] : make_int2(0, 0);
+    }
+    // rigid: offsets from the centroid and positions at t = 0
+    float rr0x[VPT], rr0y[VPT], rx0h[VPT], rx0l[VPT], ry0h[VPT], ry0l[VPT];
+    if (rigid) {
+#pragma unroll
+        for (int k = 0; k < VPT; k++) {
+            const int v = tid + k * BT;
+            if (v >= n) continue;
+            const int g = v0 + v;
+            rr0x[k] = d.r0x[g]; rr0y[k] = d.r0y[g];
+            rx0h[k] = d.x0h[g]; rx0l[k] = d.x0l[g]; ry0h[k] = d.y0h[g]; ry0l[k] = d.y0l[g];
+        }
+    }
+    // sites: the element loop reads state, fraction and anchor of any site
+    // (LDS); the kinetics keep the host element and draw index of their own
+    int rsh[SPT], rso[SPT], rst[SPT];
+    float rsf[SPT], rsah[SPT], rsal[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int q = tid + k * BT;
+        if (q >= ns) continue;
+        const int g = s0 + q;
+        rsh[k] = d.s_host[g]; rso[k] = d.s_orig[g]; rst[k] = d.s_state[g];
+        rsf[k] = d.s_frac[g]; rsah[k] = d.s_anh[g]; rsal[k] = d.s_anl[g];
     }
     if (tid < d.nbodies && tid < MAX_BOX)
         for (int c = 0; c < 4; c++) sbox[tid][c] = d.bs[tid].bbox[par][c];
@@ -136,6 +133,12 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         const int v = tid + k * BT;
         if (v >= n) continue;
         sxh[v] = rxh[k]; sxl[v] = rxl[k]; syh[v] = ryh[k]; syl[v] = ryl[k];
+    }
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int q = tid + k * BT;
+        if (q >= ns) continue;
+        ss_state[q] = rst[k]; ss_frac[q] = rsf[k]; ss_anh[q] = rsah[k]; ss_anl[q] = rsal[k];
     }
     __syncthreads();
 
@@ -162,10 +165,10 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         sSy[l] = ks * nx;
         // Eq. (13): engaged bonds of this element, along its outward normal
         float bm = 0.0f;
-        for (int s = rsr[k].x; s < rsr[k].y; s++) {
-            if (!d.s_state[s]) continue;
-            const float f = d.s_frac[s];
-            const float dx = (rxh[k] - d.s_anh[s]) + ((rxl[k] - d.s_anl[s]) + f * tx);
+        for (int s = rsr[k].x - s0; s < rsr[k].y - s0; s++) {
+            if (!ss_state[s]) continue;
+            const float f = ss_frac[s];
+            const float dx = (rxh[k] - ss_anh[s]) + ((rxl[k] - ss_anl[s]) + f * tx);
             const float dy = (ryh[k] + 0.5f) + (ryl[k] + f * ty);
             bm += P.sigma * (sqrtf(dx * dx + dy * dy) - P.yeq);
         }
@@ -205,6 +208,67 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     }
     __syncthreads();
 
+    // ---- Eq. (12): repulsion from the vertices of other bodies within the cut-off -------
+    // A body whose box (of x^n) comes within the cut-off of this body's box is
+    // staged in LDS; every vertex near that box then scans it.  rep[k] is the
+    // summed magnitude, applied along the vertex normal.
+    float rep[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; k++) rep[k] = 0.0f;
+    if (P.kind != FIXED) {
+        const float L = (float)d.nx, cut = d.rep_cut, cut2 = cut * cut;
+        float ob[4];
+        for (int q = 0; q < 4; q++) ob[q] = b < MAX_BOX ? sbox[b][q] : d.bs[b].bbox[par][q];
+        for (int c0 = 0; c0 < d.nbodies; c0 += 64) {
+            // candidate bodies, one lane each; every wave forms the same mask
+            const int cl = c0 + (tid & 63);
+            bool close = false;
+            if (cl < d.nbodies && cl != b) {
+                float bq[4];
+                for (int q = 0; q < 4; q++) bq[q] = cl < MAX_BOX ? sbox[cl][q] : d.bs[cl].bbox[par][q];
+                float dcc = 0.5f * (ob[0] + ob[1]) - 0.5f * (bq[0] + bq[1]);
+                dcc -= L * rintf(dcc / L);
+                // NaN boxes fail both distance tests and are scanned
+                close = !(fabsf(dcc) > 0.5f * (ob[1] - ob[0]) + 0.5f * (bq[1] - bq[0]) + cut + 1.0f) &&
+                        !(ob[3] < bq[2] - cut - 1.0f || ob[2] > bq[3] + cut + 1.0f);
+            }
+            unsigned long long mm = __ballot(close);
+            while (mm) {
+                const int c = c0 + __ffsll((long long)mm) - 1;
+                mm &= mm - 1ull;
+                float bb[4];
+                for (int q = 0; q < 4; q++) bb[q] = c < MAX_BOX ? sbox[c][q] : d.bs[c].bbox[par][q];
+                const int cs = d.bp[c].vstart, cn = d.bp[c].n;
+                __syncthreads();   // the staging arrays are free
+                for (int u = tid; u < cn; u += BT) {
+                    sqxh[u] = d.pxh[par][cs + u]; sqxl[u] = d.pxl[par][cs + u];
+                    sqyh[u] = d.pyh[par][cs + u]; sqyl[u] = d.pyl[par][cs + u];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < VPT; k++) {
+                    const int v = tid + k * BT;
+                    if (v >= n) continue;
+                    const float myx = rxh[k] + rxl[k], myy = ryh[k] + ryl[k];
+                    float dxc = myx - 0.5f * (bb[0] + bb[1]);
+                    dxc -= L * rintf(dxc / L);
+                    if (fabsf(dxc) > 0.5f * (bb[1] - bb[0]) + cut + 0.5f) continue;
+                    if (myy < bb[2] - cut - 0.5f || myy > bb[3] + cut + 0.5f) continue;
+                    for (int u = 0; u < cn; u++) {
+                        float ddx = (rxh[k] - sqxh[u]) + (rxl[k] - sqxl[u]);
+                        ddx -= L * rintf(ddx / L);
+                        const float ddy = (ryh[k] - sqyh[u]) + (ryl[k] - sqyl[u]);
+                        const float r2 = ddx * ddx + ddy * ddy;
+                        if (r2 < cut2) {
+                            const float dd = fmaxf(sqrtf(r2), d.rep_dmin);
+                            rep[k] += d.rep_pref / (dd * dd * sqrtf(dd));
+                        }
+                    }
+                }
+            }
+        }
+    }
+
     // ---- total force per vertex ---------------------------------------------------------
     float fvx[VPT], fvy[VPT];
 #pragma unroll
@@ -226,33 +290,8 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
             fx += -sbend[v] * snvx[v] + sbend[p] * sp * snvx[p] + sbend[m] * sm * snvx[m];
             fy += -sbend[v] * snvy[v] + sbend[p] * sp * snvy[p] + sbend[m] * sm * snvy[m];
         }
-        // Eq. (12): repulsion from vertices of other bodies within the cut-off
-        const float myx = rxh[k] + rxl[k], myy = ryh[k] + ryl[k];
-        const float L = (float)d.nx;
-        const float cut2 = d.rep_cut * d.rep_cut;
-        for (int c = 0; c < d.nbodies; c++) {
-            if (c == b) continue;
-            float bb0, bb1, bb2, bb3;
-            if (c < MAX_BOX) { bb0 = sbox[c][0]; bb1 = sbox[c][1]; bb2 = sbox[c][2]; bb3 = sbox[c][3]; }
-            else { const float *bb = d.bs[c].bbox[par]; bb0 = bb[0]; bb1 = bb[1]; bb2 = bb[2]; bb3 = bb[3]; }
-            float dxc = myx - 0.5f * (bb0 + bb1);
-            dxc -= L * rintf(dxc / L);
-            if (fabsf(dxc) > 0.5f * (bb1 - bb0) + d.rep_cut + 0.5f) continue;
-            if (myy < bb2 - d.rep_cut - 0.5f || myy > bb3 + d.rep_cut + 0.5f) continue;
-            const int cs = d.bp[c].vstart, cn = d.bp[c].n;
-            for (int u = cs; u < cs + cn; u++) {
-                float ddx = (rxh[k] - d.pxh[par][u]) + (rxl[k] - d.pxl[par][u]);
-                ddx -= L * rintf(ddx / L);
-                const float ddy = (ryh[k] - d.pyh[par][u]) + (ryl[k] - d.pyl[par][u]);
-                const float r2 = ddx * ddx + ddy * ddy;
-                if (r2 < cut2) {
-                    const float dd = fmaxf(sqrtf(r2), d.rep_dmin);
-                    const float f = d.rep_pref / (dd * dd * sqrtf(dd));
-                    fx -= f * snvx[v];
-                    fy -= f * snvy[v];
-                }
-            }
-        }
+        fx -= rep[k] * snvx[v];
+        fy -= rep[k] * snvy[v];
         fvx[k] = fx;
         fvy[k] = fy;
         d.force[v0 + v] = make_float2(fx, fy);
@@ -261,7 +300,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     // ---- integration (Eqs. 16-20), direct forcing and spreading at x^n -----------------
     float nxh[VPT], nxl[VPT], nyh[VPT], nyl[VPT];
     if (rigid) {
-        const float phin = d.bs[b].phih + d.bs[b].phil;
+        const float phin = RS1.x + RS1.y;
         const float shalf = sinf(0.5f * phin);
         const float c1 = -2.0f * shalf * shalf, sphi = sinf(phin);
         float Fx = 0.0f, Fy = 0.0f, M = 0.0f;
@@ -269,7 +308,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         for (int k = 0; k < VPT; k++) {
             const int v = tid + k * BT;
             if (v >= n) continue;
-            const float rx = d.r0x[v0 + v], ry = d.r0y[v0 + v];
+            const float rx = rr0x[k], ry = rr0y[k];
             const float armx = rx + (c1 * rx - sphi * ry), army = ry + (sphi * rx + c1 * ry);
             Fx += fvx[k];
             Fy += fvy[k];
@@ -284,17 +323,19 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
             Fx = 0.0f; Fy = 0.0f; M = 0.0f;
             for (int w = 0; w < BT / 64; w++) { Fx += shf[w][0]; Fy += shf[w][1]; M += shf[w][2]; }
             BodyState &S = d.bs[b];
-            const float ux = (2.0f / 3.0f) * (2.0f * S.ucx - 0.5f * S.ucxm + Fx * P.inv_mass);
-            const float uy = (2.0f / 3.0f) * (2.0f * S.ucy - 0.5f * S.ucym + Fy * P.inv_mass);
-            const float om = (2.0f / 3.0f) * (2.0f * S.om - 0.5f * S.omm + M * P.inv_inertia);
-            S.ucxm = S.ucx; S.ucym = S.ucy; S.omm = S.om;
-            S.ucx = ux; S.ucy = uy; S.om = om;
-            df_add(S.dcxh, S.dcxl, ux);
-            df_add(S.dcyh, S.dcyl, uy);
-            df_add(S.phih, S.phil, om);
+            const float ux = (2.0f / 3.0f) * (2.0f * RS1.z - 0.5f * RS2.x + Fx * P.inv_mass);
+            const float uy = (2.0f / 3.0f) * (2.0f * RS1.w - 0.5f * RS2.y + Fy * P.inv_mass);
+            const float om = (2.0f / 3.0f) * (2.0f * RS2.z - 0.5f * RS2.w + M * P.inv_inertia);
+            float dcxh = RS0.x, dcxl = RS0.y, dcyh = RS0.z, dcyl = RS0.w, phih = RS1.x, phil = RS1.y;
+            df_add(dcxh, dcxl, ux);
+            df_add(dcyh, dcyl, uy);
+            df_add(phih, phil, om);
+            *(float4 *)&S.dcxh = make_float4(dcxh, dcxl, dcyh, dcyl);
+            *(float4 *)&S.phih = make_float4(phih, phil, ux, uy);
+            *(float4 *)&S.ucxm = make_float4(RS1.z, RS1.w, om, RS2.z);
             srig[0] = ux; srig[1] = uy; srig[2] = om;
-            srig[3] = S.dcxh; srig[4] = S.dcxl; srig[5] = S.dcyh; srig[6] = S.dcyl;
-            srig[7] = S.phih + S.phil;
+            srig[3] = dcxh; srig[4] = dcxl; srig[5] = dcyh; srig[6] = dcyl;
+            srig[7] = phih + phil;
         }
         __syncthreads();
         const float ph = srig[7];
@@ -304,9 +345,9 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         for (int k = 0; k < VPT; k++) {
             const int v = tid + k * BT;
             if (v >= n) continue;
-            const float rx = d.r0x[v0 + v], ry = d.r0y[v0 + v];
+            const float rx = rr0x[k], ry = rr0y[k];
             const float drx = c1n * rx - sn * ry, dry = sn * rx + c1n * ry;
-            float xh = d.x0h[v0 + v], xl = d.x0l[v0 + v], yh = d.y0h[v0 + v], yl = d.y0l[v0 + v];
+            float xh = rx0h[k], xl = rx0l[k], yh = ry0h[k], yl = ry0l[k];
             df_add2(xh, xl, srig[3], srig[4]);
             df_add2(yh, yl, srig[5], srig[6]);
             df_add(xh, xl, drx);
@@ -347,22 +388,6 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     }
     __syncthreads();   // every thread has read x^n from LDS
 
-    // near tiles of the next step: the tiles under the stencils of x^{n+1}
-#pragma unroll
-    for (int k = 0; k < VPT; k++) {
-        const int v = tid + k * BT;
-        if (v >= n) continue;
-        int tl[9];
-        const int c = stencil_tiles(d, nxh[k], nxl[k], nyh[k], nyl[k], tl);
-        for (int q = 0; q < c; q++) mark_tile(d, npar, tl[q], stile, snew, &snum);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        const int m = min(snum, NEW_SLOTS);
-        snbase = m ? atomicAdd(&d.ncount[npar], m) : 0;
-    }
-    __syncthreads();
-    for (int k = tid; k < min(snum, NEW_SLOTS); k += BT) d.nlist[npar][snbase + k] = snew[k];
 #pragma unroll
     for (int k = 0; k < VPT; k++) {
         const int v = tid + k * BT;
@@ -377,20 +402,23 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
 
     // ---- bond kinetics at x^{n+1} --------------------------------------------------------
     int cnt = 0;
-    for (int s = P.site_start + tid; s < P.site_start + P.n_sites; s += BT) {
-        const int e = d.s_host[s] - v0;
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int q = tid + k * BT;
+        if (q >= ns) continue;
+        const int e = rsh[k] - v0;
         const int m = (e + 1 == n) ? 0 : e + 1;
-        const float f = d.s_frac[s];
+        const float f = rsf[k];
         const float tx = (sxh[m] - sxh[e]) + (sxl[m] - sxl[e]);
         const float ty = (syh[m] - syh[e]) + (syl[m] - syl[e]);
         const float xsh = sxh[e], xsl = sxl[e] + f * tx;
         const float ysh = syh[e], ysl = syl[e] + f * ty;
-        const uint32_t w = philox_w0((uint32_t)step, (uint32_t)d.s_orig[s], (uint32_t)((unsigned long long)step >> 32),
+        const uint32_t w = philox_w0((uint32_t)step, (uint32_t)rso[k], (uint32_t)((unsigned long long)step >> 32),
                                      0u, P.seed_lo, P.seed_hi);
         const float r = (float)(w >> 8) * (1.0f / 16777216.0f);
-        int st = d.s_state[s];
+        int st = rst[k];
         if (st) {
-            const float dx = (xsh - d.s_anh[s]) + (xsl - d.s_anl[s]);
+            const float dx = (xsh - rsah[k]) + (xsl - rsal[k]);
             const float dy = (ysh + 0.5f) + ysl;
             const float yl = sqrtf(dx * dx + dy * dy);
             const float Pr = -expm1f(-P.kr0 * expf(fabsf(yl - P.yeq) / P.lb));
@@ -402,12 +430,12 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
                 if (r < Pf) {
                     st = 1;
                     const float ah = xsh + xsl;
-                    d.s_anh[s] = ah;
-                    d.s_anl[s] = xsl - (ah - xsh);
+                    d.s_anh[s0 + q] = ah;
+                    d.s_anl[s0 + q] = xsl - (ah - xsh);
                 }
             }
         }
-        d.s_state[s] = st;
+        if (st != rst[k]) d.s_state[s0 + q] = st;
         cnt += st;
     }
 
@@ -457,7 +485,10 @@ __global__ __launch_bounds__(256) void k_mark(Dev d, int par) {
     if (v >= d.nverts) return;
     int tl[9];
     const int c = stencil_tiles(d, d.pxh[par][v], d.pxl[par][v], d.pyh[par][v], d.pyl[par][v], tl);
-    for (int q = 0; q < c; q++) mark_tile(d, par, tl[q], nullptr, nullptr, nullptr);
+    for (int q = 0; q < c; q++) {
+        mark_tile(d, par, tl[q]);
+        note_cover(d, par, tl[q], v);
+    }
 }
 
 hipError_t launch_mark(const Dev &d, int par, hipStream_t st) {

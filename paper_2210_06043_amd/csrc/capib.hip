@@ -89,13 +89,19 @@ static capib_status fail(capib_ctx *c, capib_status s, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail((c), CAPIB_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// near-tile bookkeeping: flags and lists of both parities, the two list
+// counts (in a 64-byte slot), and the vertex-index range per tile and parity
+static size_t near_bytes(const capib_ctx *c) {
+    return 8 * (size_t)c->ntx * c->nty * 4 + 64;
+}
+
 static void layout(capib_ctx *c) {
     const capib_lattice &L = c->lat;
     size_t o = 0;
     const size_t N = (size_t)c->pitch * L.ny;
     for (int p = 0; p < 2; p++) { c->off_pop[p] = o; o = align256(o + 9 * N * c->esize); }
     // near-tile flags and lists (two parities each) and their two counts
-    c->off_near = o; o = align256(o + 4 * (size_t)c->ntx * c->nty * 4 + 64);
+    c->off_near = o; o = align256(o + near_bytes(c));
     c->off_red = o; o = align256(o + (3 * (size_t)c->ntx * c->nty + 3) * 8);
     c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
     c->off_rowref = o; o = align256(o + (size_t)L.ny * 16 * 4);
@@ -162,6 +168,10 @@ static void fill_dev(capib_ctx *c) {
         d.nlist[0] = nb + 2 * nt;
         d.nlist[1] = nb + 3 * nt;
         d.ncount = nb + 4 * nt;
+        d.tvlo[0] = nb + 4 * nt + 16;
+        d.tvlo[1] = nb + 5 * nt + 16;
+        d.tvhi[0] = nb + 6 * nt + 16;
+        d.tvhi[1] = nb + 7 * nt + 16;
     }
     d.red = (double *)(b + c->off_red);
     d.macro = (float *)(b + c->off_macro);
@@ -169,6 +179,14 @@ static void fill_dev(capib_ctx *c) {
     d.counter = (long long *)(b + c->off_scal);
     d.err = (int *)(b + c->off_scal + 8);
     d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites;
+    for (int k = 0; k < ARG_BODIES; k++) {
+        if (k < c->nbodies) {
+            const BodyHost &bh = c->bodies[k];
+            d.brange[k] = make_int4(bh.vstart, bh.n, bh.site_start, bh.n_sites);
+        } else {
+            d.brange[k] = make_int4(0, 0, 0, 0);
+        }
+    }
     d.bp = (BodyParams *)(b + c->off_bp);
     d.bs = (BodyState *)(b + c->off_bs);
     d.vbody = (int *)(b + c->off_vbody);
@@ -494,6 +512,7 @@ capib_status capib_add_bonds(capib_ctx *c, int32_t body_id, const capib_bonds *b
     const int ns = bd->n_sites;
     if (ns < 0 || (ns > 0 && (!bd->host_elem || !bd->frac))) return fail(c, CAPIB_E_ARG, "bad site arrays");
     if (c->nsites + ns > c->lat.max_sites) return fail(c, CAPIB_E_CAPACITY, "more than %d sites", c->lat.max_sites);
+    if (ns > MAXS_BODY) return fail(c, CAPIB_E_CAPACITY, "more than %d sites on one body", MAXS_BODY);
     const double pr[] = {bd->sigma, bd->y_cr, bd->y_eq, bd->k_f, bd->k_r0, bd->bell_len};
     for (double p : pr)
         if (!std::isfinite(p)) return fail(c, CAPIB_E_ARG, "non-finite bond parameter");
@@ -590,7 +609,7 @@ static capib_status ensure_streams(capib_ctx *c) {
 static capib_status ensure_marks(capib_ctx *c) {
     if (c->marks_valid) return CAPIB_OK;
     const size_t nt = (size_t)c->ntx * c->nty;
-    HIPCHK(c, hipMemsetAsync(c->base + c->off_near, 0, 4 * nt * 4 + 64, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->base + c->off_near, 0, near_bytes(c), c->stream));
     HIPCHK(c, launch_mark(c->d, c->par, c->stream));
     c->marks_valid = true;
     return CAPIB_OK;

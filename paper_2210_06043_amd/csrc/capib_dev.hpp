@@ -12,6 +12,8 @@ constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int LAT_THREADS = TILE_X * TILE_Y;
 constexpr int MAXV_BODY = 1024;    // vertices of one membrane held in LDS
+constexpr int MAXS_BODY = 2048;    // ligand sites of one membrane held in LDS
+constexpr int ARG_BODIES = 16;     // bodies whose index ranges travel with the kernel arguments
 constexpr int BODY_THREADS = 512;
 constexpr int INTERP_THREADS = 256;  // 16 lanes per interpolation point
 
@@ -39,7 +41,10 @@ struct BodyState {
     float bbox[2][4];               // xmin, xmax, ymin, ymax of the vertices, parity-indexed
     int n_bound, pad;
     double geo[4];                  // diagnostics: area, perimeter, cx, cy
+    float pad2[2];
 };
+// the membrane kernel reads the rigid state as three float4
+static_assert(sizeof(BodyState) % 16 == 0, "BodyState must keep 16-byte alignment in arrays");
 
 // Everything a kernel needs, passed by value.
 struct Dev {
@@ -57,12 +62,19 @@ struct Dev {
     // Near tiles of a step: the 64x4 tiles that the stencils of the vertex
     // positions x^n cover, i.e. the only tiles that can receive spread force
     // in step n.  Double-buffered by step parity: tnear[p][tile] is 1 for a
-    // near tile, nlist[p][0 .. ncount[p]) lists them.
+    // near tile, nlist[p][0 .. ncount[p]) lists them.  The vertices whose
+    // stencils cover a tile lie in the global index range [vlo, vhi] with
+    // tvhi = vhi + 1 and tvlo = nverts - vlo (0 = none; both kept by max).
     int *tnear[2];
     int *nlist[2];
     int *ncount;
+    int *tvlo[2], *tvhi[2];
     // immersed boundary
     int nbodies, nverts, nsites, pad1;
+    // (first vertex, vertices, first site, sites) of the first ARG_BODIES
+    // bodies, passed with the arguments so that the membrane kernel can
+    // issue its loads without a round trip for its parameters
+    int4 brange[ARG_BODIES];
     float rep_pref, rep_cut, rep_dmin, probe;
     BodyParams *bp;
     BodyState *bs;
@@ -105,6 +117,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) {
+    if ((unsigned)i < (unsigned)n) return i;   // the common case, without a division
     i %= n;
     return i < 0 ? i + n : i;
 }
@@ -230,13 +243,24 @@ __device__ __forceinline__ void pull9(const Dev &d, const T *__restrict__ A, int
 
 // Pulled populations as deviations from the reference of row j:
 // dh_i = h_i - r_i(y_j) = s_i(x - e_i) + rowref_i(j).  Returns u_ref(y_j).
-template <typename T>
-__device__ __forceinline__ float pull_dev(const Dev &d, const T *__restrict__ A, int i, int j, float h[9]) {
-    pull9<T>(d, A, i, j, h);
+__device__ __forceinline__ float add_rowref(const Dev &d, int j, float h[9]) {
     const float *R = d.rowref + 16 * j;
     h[2] += R[2]; h[4] += R[4]; h[5] += R[5];
     h[6] += R[6]; h[7] += R[7]; h[8] += R[8];
     return R[9];
+}
+
+template <typename T>
+__device__ __forceinline__ float pull_dev(const Dev &d, const T *__restrict__ A, int i, int j, float h[9]) {
+    pull9<T>(d, A, i, j, h);
+    return add_rowref(d, j, h);
+}
+
+// Records that the stencil of vertex v (global index) covers the tile, for
+// the step of parity p: widens the tile's vertex range.
+__device__ __forceinline__ void note_cover(const Dev &d, int p, int tile, int v) {
+    atomicMax(&d.tvhi[p][tile], v + 1);
+    atomicMax(&d.tvlo[p][tile], d.nverts - v);
 }
 
 // Equilibrium of Eq. (2) as a deviation from the row reference, with

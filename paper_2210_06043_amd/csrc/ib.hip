@@ -64,7 +64,7 @@ __device__ __forceinline__ void node_moments(const Dev &d, const T *A, int i, in
 __global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d, int par) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *d.counter += 1;            // steps started
-        d.ncount[par ^ 1] = 0;      // the membrane kernel lists next step's near tiles
+        d.ncount[par ^ 1] = 0;      // the near-tile sweep lists next step's near tiles
     }
     const int gid = blockIdx.x * INTERP_THREADS + threadIdx.x;
     const int p = gid >> 4, lane = gid & 15;

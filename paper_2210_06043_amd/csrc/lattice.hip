@@ -19,33 +19,26 @@ __device__ __forceinline__ float stpop<float>(float v, float) { return v; }
 template <>
 __device__ __forceinline__ _Float16 stpop<_Float16>(float v, float scale) { return (_Float16)(v * scale); }
 
-// One node of one 64x4 tile.  FORCED: the tile is a near tile of this step
-// and (ax, ay) is the IB force spread onto this node.
-template <typename T, bool FORCED>
-__device__ __forceinline__ void lattice_node(const Dev &d, int par, int tile, float ax = 0.0f, float ay = 0.0f) {
-    const T *__restrict__ A = (const T *)d.pop[par];
-    T *__restrict__ B = (T *)d.pop[par ^ 1];
+// Node (i, j) of a 64x4 tile: i runs along the wave, j is wave-uniform (one
+// wave per row, so the row reference is read once per wave).
+__device__ __forceinline__ void tile_node(const Dev &d, int tile, int &i, int &j) {
     const int ty = tile / d.ntx;
     const int tx = tile - ty * d.ntx;
-    const int i = tx * TILE_X + (threadIdx.x & (TILE_X - 1));
-    // one wave per row: the row index (and the row reference) is wave-uniform
-    const int j = __builtin_amdgcn_readfirstlane(ty * TILE_Y + (int)(threadIdx.x / TILE_X));
-    if (i >= d.nx || j >= d.ny) return;
-    float h[9];
-    const float uref = pull_dev<T>(d, A, i, j, h);
+    i = tx * TILE_X + (threadIdx.x & (TILE_X - 1));
+    j = __builtin_amdgcn_readfirstlane(ty * TILE_Y + (int)(threadIdx.x / TILE_X));
+}
 
+// Collision and store of node (i, j) from its pulled deviations h (Eq. 1 with
+// the Guo term of Eq. 4), for the total force (Fx, Fy) = g + f_ib.
+template <typename T>
+__device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, int j, const float h[9], float uref,
+                                                float Fx, float Fy) {
+    T *__restrict__ B = (T *)d.pop[par ^ 1];
+    const long long node = (long long)j * d.pitch + i;
     // moments of the streamed deviations: drho, and j - u_ref x
     const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
-
-    // total force: uniform drive plus the spread IB force of this step
-    float Fx = d.gx, Fy = d.gy;
-    const long long node = (long long)j * d.pitch + i;
-    if (FORCED) {
-        Fx += ax;
-        Fy += ay;
-    }
 
     const float rho = 1.0f + drho;
     const float irho = 1.0f / rho;
@@ -94,7 +87,12 @@ template <typename T>
 __global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int par) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (d.tnear[par][tile]) return;
-    lattice_node<T, false>(d, par, tile);
+    int i, j;
+    tile_node(d, tile, i, j);
+    if (i >= d.nx || j >= d.ny) return;
+    float h[9];
+    const float uref = pull_dev<T>(d, (const T *)d.pop[par], i, j, h);
+    lattice_collide<T>(d, par, i, j, h, uref, d.gx, d.gy);
 }
 
 // Does a 4-wide stencil starting at o (wrapped into [0, n)) meet the range
@@ -106,96 +104,140 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
 }
 
 // Near tiles of this step, after the membrane kernel: grid-stride over the
-// list.  Spreading (Sec. 2.2) is done here as a gather: for each tile the
-// workgroup scans the membranes whose bounding box (of x^n, widened by the
-// stencil reach) meets the tile, 256 vertices at a time, compacts the
-// vertices whose stencil covers the tile into LDS in vertex order, and every
-// node sums W f over them in that order, so the result does not depend on
-// scheduling.  Each tile's flag is cleared for the next step of the same
-// parity.
-template <typename T>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par) {
-    __shared__ int2 sorg[LAT_THREADS];
-    __shared__ float sw[LAT_THREADS][10];   // x weights (normalised), y weights, force
-    __shared__ int swave[LAT_THREADS / 64];
-    const int cnt = d.ncount[par];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
-        const int tile = d.nlist[par][k];
-        const int ty = tile / d.ntx, tx = tile - ty * d.ntx;
-        const int x0 = tx * TILE_X, y0 = ty * TILE_Y;
-        const int tw = min(TILE_X, d.nx - x0), th = min(TILE_Y, d.ny - y0);
-        const int i = x0 + lane, j = y0 + wv;
-        float ax = 0.0f, ay = 0.0f;
-        for (int b = 0; b < d.nbodies; b++) {
-            const float bx0 = d.bs[b].bbox[par][0], bx1 = d.bs[b].bbox[par][1];
-            const float by0 = d.bs[b].bbox[par][2], by1 = d.bs[b].bbox[par][3];
-            bool meet = true;   // an unusable box (non-finite, huge) meets every tile
-            if (fabsf(bx0) < 1.0e8f && fabsf(bx1) < 1.0e8f && bx1 - bx0 < (float)(d.nx - 8)) {
-                const int lo = wrapi((int)floorf(bx0) - 3, d.nx);
-                const int wd = (int)ceilf(bx1) - (int)floorf(bx0) + 6;
-                int r = lo - x0;
-                if (r < 0) r += d.nx;
-                meet = r < tw || r + wd >= d.nx;
-            }
-            if (meet && fabsf(by0) < 1.0e8f && fabsf(by1) < 1.0e8f) {
-                const int lo = (int)floorf(d.walls ? fminf(fmaxf(by0, -1.0f), (float)d.ny) : by0) - 3;
-                const int hi = (int)ceilf(d.walls ? fminf(fmaxf(by1, -1.0f), (float)d.ny) : by1) + 3;
-                if (d.walls) {
-                    meet = hi >= y0 && lo < y0 + th;
-                } else if (hi - lo < d.ny) {
-                    int r = wrapi(lo, d.ny) - y0;
-                    if (r < 0) r += d.ny;
-                    meet = r < th || r + (hi - lo) >= d.ny;
-                }
-            }
-            if (!meet) continue;
-            const int vs = d.bp[b].vstart, n = d.bp[b].n;
-            for (int c0 = 0; c0 < n; c0 += LAT_THREADS) {
-                const int v = c0 + (int)threadIdx.x;
-                bool hit = false;
-                int2 o = make_int2(0, 0);
-                if (v < n) {
-                    o = d.sp_org[vs + v];
-                    const bool hx = meets_periodic(o.x, x0, tw, d.nx);
-                    const bool hy = d.walls ? (o.y + 3 >= y0 && o.y < y0 + th) : meets_periodic(o.y, y0, th, d.ny);
-                    hit = hx && hy;
-                }
-                const unsigned long long m = __ballot(hit);
-                if (lane == 0) swave[wv] = __popcll(m);
-                __syncthreads();
-                int base = 0, tot = 0;
+// list.  Spreading (Sec. 2.2) is done here as a gather.  The marking of the
+// tile recorded the index range of the vertices whose stencils cover it;
+// the workgroup loads the spread records of that range (256 at a time),
+// compacts the covering vertices into LDS in index order, and every node
+// sums W f over them in that order, so the result does not depend on
+// scheduling.  The node's populations are loaded before the gather so that
+// their latency overlaps it.  The tile's flag and range are cleared for the
+// next step of the same parity.
+//
+// The first nmark workgroups of the launch instead mark the near tiles of
+// the next step: the tiles under the stencils of x^{n+1}, which the
+// membrane kernel has written.  One (vertex, stencil tile) pair per lane,
+// all flag exchanges in flight together, one list-counter update per wave.
+constexpr int MARK_VERTS = LAT_THREADS / 9;   // vertices per marking workgroup
+
+__device__ __forceinline__ void mark_next(const Dev &d, int npar, int mb) {
+    const int v = mb * MARK_VERTS + (int)threadIdx.x / 9, q = (int)threadIdx.x % 9;
+    bool fresh = false;
+    int tile = 0;
+    if ((int)threadIdx.x < MARK_VERTS * 9 && v < d.nverts) {
+        int tl[9];
+        const int c = stencil_tiles(d, d.pxh[npar][v], d.pxl[npar][v], d.pyh[npar][v], d.pyl[npar][v], tl);
 #pragma unroll
-                for (int w = 0; w < LAT_THREADS / 64; w++) {
-                    base += (w < wv) ? swave[w] : 0;
-                    tot += swave[w];
-                }
-                if (hit) {
-                    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-                    const float4 wx = d.sp_wx[vs + v], wy = d.sp_wy[vs + v];
-                    const float2 f = d.sp_f[vs + v];
-                    sorg[slot] = o;
-                    sw[slot][0] = wx.x; sw[slot][1] = wx.y; sw[slot][2] = wx.z; sw[slot][3] = wx.w;
-                    sw[slot][4] = wy.x; sw[slot][5] = wy.y; sw[slot][6] = wy.z; sw[slot][7] = wy.w;
-                    sw[slot][8] = f.x; sw[slot][9] = f.y;
-                }
-                __syncthreads();
-                for (int h = 0; h < tot; h++) {
-                    int a = i - sorg[h].x;
+        for (int r = 0; r < 9; r++)
+            if (r == q) tile = tl[r];
+        if (q < c) {
+            note_cover(d, npar, tile, v);
+            fresh = atomicExch(&d.tnear[npar][tile], 1) == 0;
+        }
+    }
+    const unsigned long long m = __ballot(fresh);
+    if (m) {
+        const int lane = threadIdx.x & 63, lead = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == lead) base = atomicAdd(&d.ncount[npar], __popcll(m));
+        base = __shfl(base, lead);
+        if (fresh) d.nlist[npar][base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par, int nmark) {
+    if ((int)blockIdx.x < nmark) {
+        mark_next(d, par ^ 1, blockIdx.x);
+        return;
+    }
+    constexpr int NW = LAT_THREADS / 64;
+    // staged covering vertices: x weights (normalised), y weights, and
+    // (origin x, origin y, fx, fy) with the origin's bits in the float slots
+    __shared__ float4 srec[LAT_THREADS + 4][3];
+    __shared__ int scount[NW];
+    const int bid = blockIdx.x - nmark, nblk = gridDim.x - nmark;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int cnt = d.ncount[par];
+    for (int k = bid; k < cnt; k += nblk) {
+        const int tile = d.nlist[par][k];
+        const int tyi = tile / d.ntx, txi = tile - tyi * d.ntx;
+        const int x0 = txi * TILE_X, y0 = tyi * TILE_Y;
+        const int tw = min(TILE_X, d.nx - x0), th = min(TILE_Y, d.ny - y0);
+        int i, j;
+        tile_node(d, tile, i, j);
+        const bool valid = i < d.nx && j < d.ny;
+        float h[9];
+        if (valid) pull9<T>(d, (const T *)d.pop[par], i, j, h);
+        const int vhi = d.tvhi[par][tile] - 1, vlo = d.nverts - d.tvlo[par][tile];
+
+        float ax = 0.0f, ay = 0.0f;
+        for (int c0 = vlo; c0 <= vhi; c0 += LAT_THREADS) {
+            const int v = c0 + (int)threadIdx.x;
+            bool hit = false;
+            int2 o = make_int2(0, 0);
+            float4 wx = make_float4(0.0f, 0.0f, 0.0f, 0.0f), wy = wx;
+            float2 f = make_float2(0.0f, 0.0f);
+            if (v <= vhi) {
+                o = d.sp_org[v];
+                wx = d.sp_wx[v];
+                wy = d.sp_wy[v];
+                f = d.sp_f[v];
+                const bool hx = meets_periodic(o.x, x0, tw, d.nx);
+                const bool hy = d.walls ? (o.y + 3 >= y0 && o.y < y0 + th) : meets_periodic(o.y, y0, th, d.ny);
+                hit = hx && hy;
+            }
+            const unsigned long long m = __ballot(hit);
+            if (lane == 0) scount[wv] = __popcll(m);
+            __syncthreads();
+            int slot = __popcll(m & below), tot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                slot += (w < wv) ? scount[w] : 0;
+                tot += scount[w];
+            }
+            if (hit) {
+                srec[slot][0] = wx;
+                srec[slot][1] = wy;
+                srec[slot][2] = make_float4(__int_as_float(o.x), __int_as_float(o.y), f.x, f.y);
+            }
+            // pad to a multiple of four with records that cover no node
+            if ((int)threadIdx.x < ((tot + 3) & ~3) - tot) {
+                const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                srec[tot + threadIdx.x][0] = z;
+                srec[tot + threadIdx.x][1] = z;
+                srec[tot + threadIdx.x][2] = make_float4(__int_as_float(-(1 << 30)), __int_as_float(-(1 << 30)), 0.0f, 0.0f);
+            }
+            __syncthreads();
+            // every lane reads the same record (LDS broadcast); four at a time
+            for (int q = 0; q < tot; q += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const float4 A = srec[q + u][0], B = srec[q + u][1], C = srec[q + u][2];
+                    int a = i - __float_as_int(C.x);
                     if (a < 0) a += d.nx;
-                    int c = j - sorg[h].y;
-                    if (!d.walls && c < 0) c += d.ny;
-                    if (a < 4 && (unsigned)c < 4u) {
-                        const float w = sw[h][a] * sw[h][4 + c];
-                        ax += w * sw[h][8];
-                        ay += w * sw[h][9];
+                    int e = j - __float_as_int(C.y);
+                    if (!d.walls && e < 0) e += d.ny;
+                    if ((unsigned)a < 4u && (unsigned)e < 4u) {
+                        const float wa = a == 0 ? A.x : a == 1 ? A.y : a == 2 ? A.z : A.w;
+                        const float we = e == 0 ? B.x : e == 1 ? B.y : e == 2 ? B.z : B.w;
+                        const float w = wa * we;
+                        ax += w * C.z;
+                        ay += w * C.w;
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
-        if (threadIdx.x == 0) d.tnear[par][tile] = 0;
-        lattice_node<T, true>(d, par, tile, ax, ay);
+        if (threadIdx.x == 0) {
+            d.tnear[par][tile] = 0;
+            d.tvhi[par][tile] = 0;
+            d.tvlo[par][tile] = 0;
+        }
+        if (valid) {
+            const float uref = add_rowref(d, j, h);
+            lattice_collide<T>(d, par, i, j, h, uref, d.gx + ax, d.gy + ay);
+        }
     }
 }
 
@@ -293,10 +335,13 @@ hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t
     // grid-stride loop covers any count
     const int nt = d.ntx * d.nty;
     const int nb = nt < 1024 ? nt : 1024;
+    const int nmark = (d.nverts + MARK_VERTS - 1) / MARK_VERTS;
     if (d.storage == 0)
-        hipExtLaunchKernelGGL(k_lattice_near<float>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+        hipExtLaunchKernelGGL(k_lattice_near<float>, dim3(nmark + nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par,
+                              nmark);
     else
-        hipExtLaunchKernelGGL(k_lattice_near<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+        hipExtLaunchKernelGGL(k_lattice_near<_Float16>, dim3(nmark + nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d,
+                              par, nmark);
     return hipGetLastError();
 }
 

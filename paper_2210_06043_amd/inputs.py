@@ -308,6 +308,25 @@ def config_tiny(nx=37, ny=22, tau=0.8, seed=3, walls=3, kinds=(DEFORMABLE, RIGID
                   meta=dict(umax=umax, nu=nu))
 
 
+def config_contact(nx=48, ny=24, tau=0.8, gap=0.55, rep_pref=2e-4, n=24, R=4.0, kinds=(DEFORMABLE, RIGID)):
+    """Two bodies closer than the repulsion range (Eq. 12) in a channel at
+    rest: the vertex at angle 0 of the first and the vertex at angle pi of
+    the second are gap apart, so a handful of vertex pairs interact.  The
+    prefactor is raised so that the repulsion dominates the round-off."""
+    ks = stiffness(1e-3, tau, 5e-2)
+    cy = (ny - 1) / 2.0 + 0.31
+    xa = 0.5 * nx - R - 0.5 * gap
+    bodies = []
+    for k, (kind, cx) in enumerate(zip(kinds, (xa, xa + 2 * R + gap))):
+        xy = circle(n, R, cx, cy, start=0.0)
+        if kind == DEFORMABLE:
+            bodies.append(Body(DEFORMABLE, xy, None, ks=ks, kb=0.1 * ks, rho_r=1.0, tag=TAG_CELL))
+        else:
+            bodies.append(Body(kind, xy, None, rho_r=1.1, tag=TAG_PARTICLE))
+    return Config(f"contact_{nx}x{ny}", nx, ny, tau, 0.0, walls=3, ux_init=None, bodies=bodies,
+                  rep_pref=rep_pref, meta=dict(gap=gap))
+
+
 def lattice_only(nx, ny, tau, walls=3, umax=1e-3, seed=0, noise=0.0):
     """Channel without bodies; optionally a seeded perturbation of the initial
     velocity (returned as a per-node array in meta['ux0'], meta['uy0'])."""

@@ -162,6 +162,43 @@ def test_membrane_forces_sum_and_torque():
     assert np.abs(fb.sum(0)).max() < 1e-15
 
 
+@pytest.mark.parametrize("shift", [0.0, 24.0])
+def test_repulsion_closed_form(shift):
+    """Eq. (12) by brute force over the vertex pairs of two rigid circles at
+    rest: switching the prefactor on changes the force on vertex v by
+    -sum_u pref d_uv^(-5/2) n_v over the partners u closer than the cut-off,
+    with n_v the radial unit vector of a regular polygon.  shift = 24 puts
+    the contact on the periodic seam (one body stored wrapped)."""
+    cfg = inputs.config_contact(kinds=(inputs.RIGID, inputs.RIGID))
+    for b in cfg.bodies:
+        b.xy = b.xy + np.array([shift, 0.0])
+        if b.xy[:, 0].min() >= cfg.nx:
+            b.xy = b.xy - np.array([cfg.nx, 0.0])
+    pref = cfg.rep_pref
+    forces = []
+    for p in (pref, 0.0):
+        cfg.rep_pref = p
+        s = oracle_sim(cfg)
+        s.step(1)
+        forces.append([s.body_work(k)["force"] for k in (0, 1)])
+    xy = [b.xy for b in cfg.bodies]
+    centre = [x.mean(0) for x in xy]
+    hits = 0
+    for k in (0, 1):
+        other = xy[1 - k]
+        nrm = (xy[k] - centre[k]) / np.linalg.norm(xy[k] - centre[k], axis=1)[:, None]
+        expect = np.zeros_like(xy[k])
+        for v in range(len(xy[k])):
+            dx = xy[k][v, 0] - other[:, 0]
+            dx -= cfg.nx * np.round(dx / cfg.nx)
+            d = np.hypot(dx, xy[k][v, 1] - other[:, 1])
+            close = d < cfg.rep_cut
+            hits += close.sum()
+            expect[v] = -np.sum(pref * d[close] ** -2.5) * nrm[v]
+        np.testing.assert_allclose(forces[0][k] - forces[1][k], expect, rtol=0, atol=1e-15)
+    assert hits == 6          # three pairs, seen from both sides
+
+
 def test_spring_and_area_forces_are_gradients():
     """Eq. (8) is -dV/dx of V = sum k_s (l - l0)^2 / 2 (Eq. 7), and the area
     penalty of Eq. (11), split half to each vertex, is -dV/dx of

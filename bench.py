@@ -14,6 +14,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -57,6 +59,8 @@ def workload(name, seed):
 
 
 def cpu_baseline(cfg, steps):
+    """The FP64 oracle on this host (single thread): timing, and the state
+    after `steps` steps that the GPU runs are compared against."""
     import oracle
     s = oracle.Sim(cfg.nx, cfg.ny, cfg.tau, cfg.gx, cfg.gy, cfg.walls)
     s.set_interactions(cfg.rep_pref, cfg.rep_cut, cfg.probe_dist)
@@ -65,11 +69,77 @@ def cpu_baseline(cfg, steps):
         s.add_body(b.kind, b.xy, b.xy_rest, b.ks, b.kb, b.ka, b.pref, b.rho_r, b.tag)
     for bd in cfg.bonds:
         s.add_bonds(bd.body, bd.host, bd.frac, bd.sigma, bd.ycr, bd.yeq, bd.kf, bd.kr0, bd.lb, bd.seed)
+    x0 = [s.vertices(k).copy() for k in range(len(cfg.bodies))]
     t0 = time.perf_counter()
     s.step(steps)
     dt = time.perf_counter() - t0
-    return dict(value=round(cfg.nx * cfg.ny * steps / dt / 1e6, 3), unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{steps} full coupled steps of the same workload (FP64, single thread), {dt:.1f} s")
+    ref = dict(u=np.stack(s.macro()[1:]), x=[s.vertices(k) for k in range(len(cfg.bodies))], x0=x0,
+               n_bound=[s.count_bound(bd.body) for bd in cfg.bonds])
+    out = dict(value=round(cfg.nx * cfg.ny * steps / dt / 1e6, 3), unit="MLUPS", cores=1, kind="oracle",
+               sample=f"{steps} full coupled steps of the same workload (FP64, single thread), {dt:.1f} s")
+    return out, ref
+
+
+def error_vs_oracle(cfg, storage, scale, steps, ref):
+    """Max-norm relative errors of a fresh GPU run of `steps` steps against
+    the oracle state: velocity, marker displacement; bond counts."""
+    from paper_2210_06043_amd import capib
+    g = capib.from_config(cfg, storage=storage, fp16_scale=scale)
+    g.step(steps)
+    _, ux, uy = g.macro()
+    u = np.stack([ux, uy])
+    eu = float(np.abs(u - ref["u"]).max() / np.abs(ref["u"]).max())
+    ed = 0.0
+    for k in range(len(cfg.bodies)):
+        d_ref = ref["x"][k] - ref["x0"][k]
+        ed = max(ed, float(np.abs(g.vertices(k) - ref["x"][k]).max() / np.abs(d_ref).max()))
+    nb = [g.body_diagnostics(bd.body)["n_bound"] for bd in cfg.bonds]
+    return dict(velocity_rel=eu, displacement_rel=ed, n_bound_equal=nb == ref["n_bound"], steps=steps)
+
+
+def measure(cfg, storage, scale, args):
+    """Timed steps (graphs as configured) and the per-kernel event times."""
+    import torch
+    from paper_2210_06043_amd import capib
+    sim = capib.from_config(cfg, storage=storage, fp16_scale=scale, graph=not args.no_graph)
+    st = sim.stream
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    sim.step(args.steps)
+    e1.record(st)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    # per-kernel HIP events on the library's stream, same number of steps
+    sim.set_timing(True)
+    sim.step(args.steps)
+    sim.set_timing(False)
+    ph, n = sim.read_timing()
+    diag = sim.diagnostics()
+    nodes = cfg.nx * cfg.ny
+    # dominant kernel: the lattice sweep over the far tiles (all tiles not
+    # under a membrane stencil this step), 9 reads + 9 writes per node
+    bytes_per_node = 72 if storage == capib.FP32_SHIFTED else 36
+    near_nodes = diag["near_tiles"] * 64 * 4
+    alg_bytes = bytes_per_node * (nodes - near_nodes)
+    far_ms, near_ms = ph[2] / n, ph[3] / n
+    return dict(ms=ms, mlups=nodes * args.steps / (ms * 1e-3) / 1e6, far_ms=far_ms, near_ms=near_ms,
+                alg_bytes=alg_bytes, achieved=alg_bytes / (far_ms * 1e-3) / 1e9, near_tiles=diag["near_tiles"],
+                phases={"interp": round(ph[0] / n * 1e3, 3), "body": round(ph[1] / n * 1e3, 3),
+                        "lattice_far": round(far_ms * 1e3, 3), "lattice_near": round(near_ms * 1e3, 3)},
+                whole_sweep_gbs=bytes_per_node * nodes / ((far_ms + near_ms) * 1e-3) / 1e9,
+                error_flags=diag["error_flags"])
+
+
+def roofline(m, storage_name, workload_name):
+    traffic = counters(f"lattice_far_{storage_name}_{workload_name}")
+    return {"bound": "hbm", "kernel": "k_lattice_far", "achieved": round(m["achieved"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(m["achieved"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": m["alg_bytes"], "avg_launch_us": round(m["far_ms"] * 1e3, 3),
+            "near_tiles": m["near_tiles"]}
 
 
 def main():
@@ -77,12 +147,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=400)
-    ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--workload", choices=["c2", "c1"], default="c2")
     # seed 2 draws the rigid (Ca = 0) square particle; the soft draws develop a
     # period-2 wall instability after ~2000 steps
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -108,66 +178,48 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}))
         return
     cfg, desc = workload(args.workload, args.seed)
-    storage = capib.FP16_SHIFTED if args.storage == "fp16" else capib.FP32_SHIFTED
-    scale = 2.0 ** 20 if storage == capib.FP16_SHIFTED else 1.0
-    sim = capib.from_config(cfg, storage=storage, fp16_scale=scale, graph=not args.no_graph)
     nodes = cfg.nx * cfg.ny
-    st = sim.stream
-
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    sim.step(args.steps)
-    e1.record(st)
-    e1.synchronize()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-
-    # per-kernel HIP events on the library's stream, same number of steps
-    sim.set_timing(True)
-    sim.step(args.steps)
-    sim.set_timing(False)
-    ph, n = sim.read_timing()
-    far_ms, near_ms = ph[2] / n, ph[3] / n
-    diag = sim.diagnostics()
-
-    # dominant kernel: the lattice sweep over the far tiles (all tiles not
-    # under a membrane stencil this step), 9 reads + 9 writes per node
-    bytes_per_node = 72 if storage == capib.FP32_SHIFTED else 36
-    near_nodes = diag["near_tiles"] * 64 * 4
-    alg_bytes = bytes_per_node * (nodes - near_nodes)
-    achieved = alg_bytes / (far_ms * 1e-3) / 1e9
-    kname = f"lattice_far_{args.storage}_{args.workload}"
-    traffic = counters(kname)
+    scale16 = capib.fp16_scale_for(cfg)
+    main_storage = "fp16" if args.storage == "fp16" else "fp32"
+    runs = {}
+    for name in (["fp32", "fp16"] if args.storage == "both" else [args.storage]):
+        st = capib.FP16_SHIFTED if name == "fp16" else capib.FP32_SHIFTED
+        runs[name] = measure(cfg, st, scale16 if name == "fp16" else 1.0, args)
+    m = runs[main_storage]
 
     out = {
         "metric": METRIC,
-        "value": round(nodes * args.steps / (ms * 1e-3) / 1e6, 1),
+        "value": round(m["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 5),
+        "ms_per_step": round(m["ms"] / args.steps, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "nodes": nodes, "population_storage": args.storage + "_deviation",
+        "config": {"workload": desc, "nodes": nodes, "population_storage": main_storage + "_deviation",
                    "hip_graphs": not args.no_graph, "vertices": cfg.n_vertices, "sites": cfg.n_sites},
-        "roofline": {"bound": "hbm", "kernel": "k_lattice_far", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_us": round(far_ms * 1e3, 3),
-                     "near_tiles": diag["near_tiles"]},
-        "phase_us_per_step": {"interp": round(ph[0] / n * 1e3, 3), "body": round(ph[1] / n * 1e3, 3),
-                              "lattice_far": round(far_ms * 1e3, 3), "lattice_near": round(near_ms * 1e3, 3)},
-        "lattice_bandwidth_whole_sweep_gbs": round(bytes_per_node * nodes / ((far_ms + near_ms) * 1e-3) / 1e9, 1),
-        "error_flags": diag["error_flags"],
+        "roofline": roofline(m, main_storage, args.workload),
+        "phase_us_per_step": m["phases"],
+        "lattice_bandwidth_whole_sweep_gbs": round(m["whole_sweep_gbs"], 1),
+        "error_flags": m["error_flags"],
     }
+    if main_storage == "fp32" and "fp16" in runs:
+        f = runs["fp16"]
+        out["fp16_storage"] = {"value": round(f["mlups"], 1), "unit": "MLUPS",
+                               "ms_per_step": round(f["ms"] / args.steps, 5), "fp16_scale": scale16,
+                               "roofline": roofline(f, "fp16", args.workload), "phase_us_per_step": f["phases"],
+                               "lattice_bandwidth_whole_sweep_gbs": round(f["whole_sweep_gbs"], 1),
+                               "error_flags": f["error_flags"]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        base, ref = cpu_baseline(cfg, args.cpu_steps)
+        out["cpu_baseline"] = base
+        out["error_vs_oracle"] = {
+            name: error_vs_oracle(cfg, capib.FP16_SHIFTED if name == "fp16" else capib.FP32_SHIFTED,
+                                  scale16 if name == "fp16" else 1.0, args.cpu_steps, ref) for name in runs}
     print(json.dumps(out), flush=True)
 
 

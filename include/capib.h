@@ -158,7 +158,9 @@ capib_status capib_bind_workspace(capib_ctx *ctx, void *device_ptr, size_t bytes
 capib_status capib_init_flow(capib_ctx *ctx, const double *ux_of_y);
 
 /* Writes / reads the stored populations as [9][ny][nx] doubles (h = f - w),
- * rounding to the storage type on write.  Syncs.                          */
+ * rounding to the storage type on write.  With FP16 storage a deviation
+ * from the row reference whose scaled value exceeds the FP16 range is
+ * refused (CAPIB_E_ARG).  Syncs.                                            */
 capib_status capib_write_populations(capib_ctx *ctx, const double *h);
 capib_status capib_read_populations(capib_ctx *ctx, double *h);
 

@@ -6,6 +6,7 @@ is no fallback: if the library is missing or no GPU is present, construction
 raises.
 """
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -255,6 +256,22 @@ class Simulation:
     def load(self, blob):
         buf = C.create_string_buffer(blob, len(blob))
         self._check(self.L.capib_load(self.ctx, C.cast(buf, _P), len(blob)))
+
+
+def fp16_scale_for(cfg, headroom=16.0):
+    """Power-of-two scale for FP16 storage of the population deviations.
+
+    Stored deviations from the row reference are bounded by the flow speed
+    u (a deviation w_i (3 e.du + drho + ...) with |du|, |drho| <~ u), so the
+    scale maps u to 65504 / headroom: the largest normal FP16 value is then
+    reached only by deviations `headroom` times the flow speed, and ordinary
+    ones keep the full 11-bit significand instead of falling to subnormals."""
+    u = float(cfg.meta.get("umax", 0.0))
+    if cfg.ux_init is not None:
+        u = max(u, float(np.abs(cfg.ux_init).max()))
+    if not u > 0.0:
+        return 2.0 ** 20
+    return 2.0 ** math.floor(math.log2(65504.0 / headroom / u))
 
 
 def from_config(cfg, storage=FP32_SHIFTED, fp16_scale=1.0, stream=None, graph=False):

@@ -354,8 +354,14 @@ capib_status capib_write_populations(capib_ctx *c, const double *h) {
                 if (!std::isfinite(hv)) return fail(c, CAPIB_E_ARG, "non-finite population");
                 const double v = hv - ref_pop(c, j, q);
                 const size_t k = q * N + (size_t)j * c->pitch + i;
-                if (c->esize == 4) ((float *)buf.data())[k] = (float)v;
-                else ((_Float16 *)buf.data())[k] = (_Float16)(float)(v * L.fp16_scale);
+                if (c->esize == 4) {
+                    ((float *)buf.data())[k] = (float)v;
+                } else {
+                    const double sv = v * L.fp16_scale;
+                    if (!(std::fabs(sv) <= 65504.0))
+                        return fail(c, CAPIB_E_ARG, "population deviation %g beyond FP16 at scale %g", v, L.fp16_scale);
+                    ((_Float16 *)buf.data())[k] = (_Float16)(float)sv;
+                }
             }
     return h2d(c, c->off_pop[c->par], buf.data(), buf.size());
 }

@@ -68,7 +68,7 @@ def test_first_step_interpolation_and_forces():
         np.testing.assert_allclose(g.vertices(k), o.vertices(k), rtol=0, atol=1e-9)
 
 
-def _compare_run(cfg, steps, label, o=None, g=None):
+def _compare_run(cfg, steps, label, o=None, g=None, tol=TOL, bond_margin=1e-6):
     o = o or oracle_sim(cfg)
     g = g or gpu_sim(cfg)
     x0 = [o.vertices(k).copy() for k in range(len(cfg.bodies))]
@@ -84,15 +84,15 @@ def _compare_run(cfg, steps, label, o=None, g=None):
         dx = rel_max(xg - x0[k], xo - x0[k])
         errs.append((rel_max(xg, xo), dx))
         say(f"{label}: body {k} displacement rel err {dx:.3e} (max disp {np.abs(xo - x0[k]).max():.3e})")
-    assert eu < TOL
+    assert eu < tol
     for ex, dx in errs:
-        assert ex < TOL and dx < TOL
+        assert ex < tol and dx < tol
     margin = o.min_margin
     say(f"{label}: min bond-decision margin {margin:.3e}")
     for bd in cfg.bonds:
         so, ao = o.bonds(bd.body)
         sg, ag = g.bonds(bd.body)
-        if margin > 1e-6:
+        if margin > bond_margin:
             assert np.array_equal(so, sg)
             np.testing.assert_allclose(ag[so == 1], ao[so == 1], rtol=0, atol=1e-5)
             assert g.body_diagnostics(bd.body)["n_bound"] == o.count_bound(bd.body)
@@ -194,3 +194,59 @@ def test_unstable_state_is_reported():
     d = g.diagnostics(allow_unstable=True)
     assert d["status"] == capib.CAPIB_E_UNSTABLE
     assert d["error_flags"] & capib.FLAG_FLUID
+
+
+# ---- FP16 shifted-population storage --------------------------------------------------
+# Populations stored as FP16 deviations from the row reference, scaled by a
+# power of two; arithmetic in FP32.  Tolerance 1e-3 relative against the
+# FP64 oracle.
+
+FP16_TOL = 1e-3
+
+
+def _fp16(cfg, **kw):
+    return gpu_sim(cfg, storage=capib.FP16_SHIFTED, fp16_scale=capib.fp16_scale_for(cfg), **kw)
+
+
+@pytest.mark.parametrize("walls,nx,ny,tau", [(3, 37, 22, 0.8), (0, 70, 9, 1.3)])
+def test_fp16_lattice_sweep_parity(walls, nx, ny, tau):
+    """FP16 storage, lattice alone: u* after 200 steps from a perturbed
+    state, within 1e-3 of the FP64 oracle."""
+    say(f"fp16 lattice parity walls={walls} {nx}x{ny} tau={tau}")
+    cfg = inputs.lattice_only(nx, ny, tau, walls=walls, umax=1e-3)
+    o = oracle_sim(cfg)
+    A = o.populations()
+    rng = np.random.default_rng(1)
+    A = (A + 2e-4 * rng.standard_normal(A.shape)).astype(np.float32).astype(np.float64)
+    o.set_populations(A)
+    g = _fp16(cfg)
+    g.write_populations(A)
+    o.step(200)
+    g.step(200)
+    _, uxo, uyo = o.macro()
+    _, uxg, uyg = g.macro()
+    eu = rel_max(np.stack([uxg, uyg]), np.stack([uxo, uyo]))
+    say(f"fp16 lattice: velocity rel err {eu:.3e}")
+    assert eu < FP16_TOL
+    assert g.diagnostics()["error_flags"] == 0
+
+
+def test_fp16_tiny_coupled_parity():
+    """FP16 storage, small channel with a cell and a bonded particle, 300 steps."""
+    say("fp16 tiny coupled parity")
+    cfg = inputs.config_tiny()
+    _compare_run(cfg, 300, "tiny-fp16", g=_fp16(cfg), tol=FP16_TOL, bond_margin=1e-4)
+
+
+def test_fp16_c1_full_run_parity():
+    """FP16 storage, the small workload, all 2000 steps."""
+    say("fp16 C1 2000-step parity")
+    cfg = inputs.config_c1()
+    _compare_run(cfg, cfg.steps, "c1-fp16", g=_fp16(cfg), tol=FP16_TOL, bond_margin=1e-4)
+
+
+def test_fp16_c2_window_parity():
+    """FP16 storage, the paper-scale workload, first 60 steps with graphs."""
+    say("fp16 C2 window parity")
+    cfg = inputs.config_c2(seed=0)
+    _compare_run(cfg, 60, "c2-fp16", g=_fp16(cfg, graph=True), tol=FP16_TOL, bond_margin=1e-4)

@@ -98,7 +98,10 @@ typedef struct {
  *   p_ref          reference pressure of Eq. (11)
  *   density_ratio  rho_body / rho_0: vertex mass rho_r A0 / n (deformable),
  *                  mass rho_r A0 and inertia rho_r J0 (rigid)
- *   tag            free caller label                                          */
+ *   tag            free caller label
+ *   band           ensemble member the membrane lives in (0 for a single
+ *                  lattice); coordinates are local to the member, and
+ *                  membranes are added in non-decreasing band order        */
 typedef struct {
     int32_t kind;
     int32_t n;
@@ -106,6 +109,7 @@ typedef struct {
     const double *xy_rest;
     double ks, kb, ka, p_ref, density_ratio;
     int32_t tag;
+    int32_t band;
 } capib_membrane;
 
 /* Ligand sites on a body, receptors on the lower wall (Sec. 2.5).
@@ -145,6 +149,20 @@ typedef struct {
 /* Creates a context for the lattice; validates tau > 1/2, sizes, walls in
  * {0, 3}, storage, capacities.  hip_stream: hipStream_t or NULL.           */
 capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx **out);
+
+/* Creates a context for an ensemble of nbands independent capillaries
+ * advanced together (each step of the ensemble is one step of every member,
+ * in the same launches).  Member k is a channel of widths[k] x lat->ny nodes
+ * with the walls, tau, drive and storage of lat; lat->nx is ignored.  The
+ * members are stacked as bands of rows in one workspace, so lat->ny must be
+ * a multiple of 4 when nbands > 1.  The per-row calls (init_flow) take the
+ * lat->ny rows of one member, shared by all; populations and macroscopic
+ * fields are read and written as the stack [nbands * ny][max width], zero
+ * beyond a member's width.  Membranes name their member (capib_membrane
+ * band) and use coordinates local to it; bodies of different members never
+ * interact.  max_* capacities count the whole ensemble.                   */
+capib_status capib_create_ensemble(const capib_lattice *lat, int32_t nbands, const int32_t *widths,
+                                   void *hip_stream, capib_ctx **out);
 
 /* Bytes of device workspace the context needs (multiple of 256). */
 size_t capib_workspace_bytes(const capib_ctx *ctx);

@@ -31,7 +31,7 @@ class capib_lattice(C.Structure):
 class capib_membrane(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("xy", _dp), ("xy_rest", _dp), ("ks", C.c_double),
                 ("kb", C.c_double), ("ka", C.c_double), ("p_ref", C.c_double), ("density_ratio", C.c_double),
-                ("tag", C.c_int32)]
+                ("tag", C.c_int32), ("band", C.c_int32)]
 
 
 class capib_bonds(C.Structure):
@@ -55,6 +55,8 @@ class capib_body_diag(C.Structure):
 _P = C.c_void_p
 SIGNATURES = {
     "capib_create": (C.c_int, [C.POINTER(capib_lattice), _P, C.POINTER(_P)]),
+    "capib_create_ensemble": (C.c_int, [C.POINTER(capib_lattice), C.c_int32, C.POINTER(C.c_int32), _P,
+                                        C.POINTER(_P)]),
     "capib_workspace_bytes": (C.c_size_t, [_P]),
     "capib_bind_workspace": (C.c_int, [_P, _P, C.c_size_t]),
     "capib_init_flow": (C.c_int, [_P, _dp]),
@@ -108,10 +110,12 @@ def _d(a):
 
 
 class Simulation:
-    """One LBM-IB simulation on the current CUDA (HIP) device."""
+    """One LBM-IB simulation on the current CUDA (HIP) device, or an ensemble
+    of independent capillaries of ny rows and widths `bands` advanced
+    together (nx is then ignored; fields are the stack of the members)."""
 
     def __init__(self, nx, ny, tau, gx=0.0, gy=0.0, walls=3, storage=FP32_SHIFTED, fp16_scale=1.0,
-                 max_bodies=8, max_vertices=4096, max_sites=4096, stream=None, device=None):
+                 max_bodies=8, max_vertices=4096, max_sites=4096, stream=None, device=None, bands=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the capib path runs only on the GPU")
@@ -121,10 +125,19 @@ class Simulation:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         lat = capib_lattice(nx, ny, tau, gx, gy, walls, storage, fp16_scale, max_bodies, max_vertices, max_sites)
         self.ctx = _P()
-        st = self.L.capib_create(C.byref(lat), _P(self.stream.cuda_stream), C.byref(self.ctx))
+        if bands is None:
+            st = self.L.capib_create(C.byref(lat), _P(self.stream.cuda_stream), C.byref(self.ctx))
+            self.bands = [nx]
+            self.nx, self.ny = nx, ny
+        else:
+            w = (C.c_int32 * len(bands))(*[int(b) for b in bands])
+            st = self.L.capib_create_ensemble(C.byref(lat), len(bands), w, _P(self.stream.cuda_stream),
+                                              C.byref(self.ctx))
+            self.bands = [int(b) for b in bands]
+            self.nx, self.ny = max(self.bands), ny * len(self.bands)
         if st != CAPIB_OK:
             raise CapibError(st, "capib_create rejected the lattice")
-        self.nx, self.ny = nx, ny
+        self.band_rows = ny
         nbytes = self.L.capib_workspace_bytes(self.ctx)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         ptr = self.workspace.data_ptr()
@@ -152,8 +165,8 @@ class Simulation:
     # ---- set-up ----------------------------------------------------------------------
     def init_flow(self, ux_of_y=None):
         u = None if ux_of_y is None else np.ascontiguousarray(ux_of_y, dtype=np.float64)
-        if u is not None and u.shape != (self.ny,):
-            raise ValueError("ux_of_y needs ny values")
+        if u is not None and u.shape != (self.band_rows,):
+            raise ValueError("ux_of_y needs one value per row of a member")
         self._check(self.L.capib_init_flow(self.ctx, _d(u)))
 
     def write_populations(self, h):
@@ -168,10 +181,10 @@ class Simulation:
         return out
 
     def add_membrane(self, kind, xy, xy_rest=None, ks=0.0, kb=0.0, ka=0.0, p_ref=1.0 / 3.0, density_ratio=1.0,
-                     tag=0):
+                     tag=0, band=0):
         xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
         xr = None if xy_rest is None else np.ascontiguousarray(xy_rest, dtype=np.float64).reshape(-1)
-        m = capib_membrane(kind, len(xy) // 2, _d(xy), _d(xr), ks, kb, ka, p_ref, density_ratio, tag)
+        m = capib_membrane(kind, len(xy) // 2, _d(xy), _d(xr), ks, kb, ka, p_ref, density_ratio, tag, band)
         bid = C.c_int32()
         self._check(self.L.capib_add_membrane(self.ctx, C.byref(m), C.byref(bid)))
         self.nv.append(len(xy) // 2)
@@ -272,6 +285,39 @@ def fp16_scale_for(cfg, headroom=16.0):
     if not u > 0.0:
         return 2.0 ** 20
     return 2.0 ** math.floor(math.log2(65504.0 / headroom / u))
+
+
+def from_ensemble(cfgs, storage=FP32_SHIFTED, fp16_scale=1.0, stream=None, graph=False):
+    """Builds one ensemble Simulation from a list of inputs.Config that share
+    ny, tau, the drive, walls, the initial profile and the interaction
+    constants (member k is cfgs[k]; its bodies are numbered after those of
+    the members before it).  Returns the simulation and the first body id of
+    each member."""
+    c0 = cfgs[0]
+    for c in cfgs[1:]:
+        same = (c.ny, c.tau, c.gx, c.gy, c.walls, c.rep_pref, c.rep_cut, c.probe_dist) == \
+               (c0.ny, c0.tau, c0.gx, c0.gy, c0.walls, c0.rep_pref, c0.rep_cut, c0.probe_dist)
+        same = same and ((c.ux_init is None and c0.ux_init is None) or
+                         (c.ux_init is not None and c0.ux_init is not None and np.array_equal(c.ux_init, c0.ux_init)))
+        if not same:
+            raise ValueError("ensemble members must share ny, tau, drive, walls, profile and interactions")
+    sim = Simulation(0, c0.ny, c0.tau, c0.gx, c0.gy, c0.walls, storage=storage, fp16_scale=fp16_scale,
+                     max_bodies=max(1, sum(len(c.bodies) for c in cfgs)),
+                     max_vertices=max(1, sum(c.n_vertices for c in cfgs)),
+                     max_sites=max(1, sum(c.n_sites for c in cfgs)), stream=stream, bands=[c.nx for c in cfgs])
+    sim.set_interactions(c0.rep_pref, c0.rep_cut, c0.probe_dist)
+    sim.init_flow(c0.ux_init)
+    first = []
+    for k, c in enumerate(cfgs):
+        b0 = len(sim.nv)
+        first.append(b0)
+        for b in c.bodies:
+            sim.add_membrane(b.kind, b.xy, b.xy_rest, b.ks, b.kb, b.ka, b.pref, b.rho_r, b.tag, band=k)
+        for bd in c.bonds:
+            sim.add_bonds(b0 + bd.body, bd.host, bd.frac, bd.sigma, bd.ycr, bd.yeq, bd.kf, bd.kr0, bd.lb, bd.seed)
+    if graph:
+        sim.set_graph(True)
+    return sim, first
 
 
 def from_config(cfg, storage=FP32_SHIFTED, fp16_scale=1.0, stream=None, graph=False):

@@ -22,7 +22,7 @@ namespace capib {
 constexpr int BT = BODY_THREADS;
 constexpr int VPT = MAXV_BODY / BT;   // vertices per thread
 constexpr int SPT = MAXS_BODY / BT;   // ligand sites per thread
-constexpr int MAX_BOX = 64;           // bounding boxes cached in LDS
+constexpr int MAX_BOX = 64;           // bounding boxes of the band's bodies cached in LDS
 
 // (ah, al) += (bh, bl), renormalised.
 __device__ __forceinline__ void df_add2(float &ah, float &al, float bh, float bl) {
@@ -47,13 +47,14 @@ __device__ __forceinline__ void mark_tile(const Dev &d, int p, int tile) {
 // Spread record of vertex g at x^n: the stencil of the velocity coupling and
 // the force dV (U - u*) to spread; the near-tile sweep gathers these records
 // (spreading as a gather: no atomics, sums in vertex order).
-__device__ __forceinline__ void write_spread(const Dev &d, int g, float xh, float xl, float yh, float yl, float fx,
-                                             float fy) {
+__device__ __forceinline__ void write_spread(const Dev &d, const Band &B, int g, float xh, float xl, float yh, float yl,
+                                             float fx, float fy) {
     int ix0, iy0;
     float wx[4], wy[4], inv;
-    stencil(d, xh, xl, yh, yl, false, ix0, iy0, wx, wy, inv);
-    // columns wrapped into [0, nx); rows too when y is periodic
-    d.sp_org[g] = make_int2(wrapi(ix0, d.nx), d.walls ? iy0 : wrapi(iy0, d.ny));
+    stencil(d, B, xh, xl, yh, yl, false, ix0, iy0, wx, wy, inv);
+    // global row of the origin; columns wrapped into the band's width, rows
+    // into the band's rows when y is periodic
+    d.sp_org[g] = make_int2(wrapi(ix0, B.nx), B.y0 + (d.walls ? iy0 : wrapi(iy0, B.ny)));
     d.sp_wx[g] = make_float4(wx[0] * inv, wx[1] * inv, wx[2] * inv, wx[3] * inv);
     d.sp_wy[g] = make_float4(wy[0], wy[1], wy[2], wy[3]);
     d.sp_f[g] = make_float2(fx, fy);
@@ -79,6 +80,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     const int n = rg.y, v0 = rg.x, ns = rg.w, s0 = rg.z, npar = par ^ 1;
     const long long step = *d.counter - 1;
     const bool deform = P.kind == DEFORMABLE, rigid = P.kind == RIGID;
+    const Band BB = band_of(d, P.band);
     // rigid state (centroid displacement, angle, velocities), read up front
     const float4 RS0 = *(const float4 *)&d.bs[b].dcxh;   // dcxh, dcxl, dcyh, dcyl
     const float4 RS1 = *(const float4 *)&d.bs[b].phih;   // phih, phil, ucx, ucy
@@ -126,8 +128,8 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         rsh[k] = d.s_host[g]; rso[k] = d.s_orig[g]; rst[k] = d.s_state[g];
         rsf[k] = d.s_frac[g]; rsah[k] = d.s_anh[g]; rsal[k] = d.s_anl[g];
     }
-    if (tid < d.nbodies && tid < MAX_BOX)
-        for (int c = 0; c < 4; c++) sbox[tid][c] = d.bs[tid].bbox[par][c];
+    if (tid < P.band_nb && tid < MAX_BOX)
+        for (int c = 0; c < 4; c++) sbox[tid][c] = d.bs[P.band_b0 + tid].bbox[par][c];
 #pragma unroll
     for (int k = 0; k < VPT; k++) {
         const int v = tid + k * BT;
@@ -216,16 +218,19 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
 #pragma unroll
     for (int k = 0; k < VPT; k++) rep[k] = 0.0f;
     if (P.kind != FIXED) {
-        const float L = (float)d.nx, cut = d.rep_cut, cut2 = cut * cut;
+        // only bodies of the same band interact; they are numbered
+        // contiguously from P.band_b0
+        const float L = (float)BB.nx, cut = d.rep_cut, cut2 = cut * cut;
         float ob[4];
-        for (int q = 0; q < 4; q++) ob[q] = b < MAX_BOX ? sbox[b][q] : d.bs[b].bbox[par][q];
-        for (int c0 = 0; c0 < d.nbodies; c0 += 64) {
+        for (int q = 0; q < 4; q++) ob[q] = b - P.band_b0 < MAX_BOX ? sbox[b - P.band_b0][q] : d.bs[b].bbox[par][q];
+        const int cend = P.band_b0 + P.band_nb;
+        for (int c0 = P.band_b0; c0 < cend; c0 += 64) {
             // candidate bodies, one lane each; every wave forms the same mask
             const int cl = c0 + (tid & 63);
             bool close = false;
-            if (cl < d.nbodies && cl != b) {
+            if (cl < cend && cl != b) {
                 float bq[4];
-                for (int q = 0; q < 4; q++) bq[q] = cl < MAX_BOX ? sbox[cl][q] : d.bs[cl].bbox[par][q];
+                for (int q = 0; q < 4; q++) bq[q] = cl - P.band_b0 < MAX_BOX ? sbox[cl - P.band_b0][q] : d.bs[cl].bbox[par][q];
                 float dcc = 0.5f * (ob[0] + ob[1]) - 0.5f * (bq[0] + bq[1]);
                 dcc -= L * rintf(dcc / L);
                 // NaN boxes fail both distance tests and are scanned
@@ -237,7 +242,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
                 const int c = c0 + __ffsll((long long)mm) - 1;
                 mm &= mm - 1ull;
                 float bb[4];
-                for (int q = 0; q < 4; q++) bb[q] = c < MAX_BOX ? sbox[c][q] : d.bs[c].bbox[par][q];
+                for (int q = 0; q < 4; q++) bb[q] = c - P.band_b0 < MAX_BOX ? sbox[c - P.band_b0][q] : d.bs[c].bbox[par][q];
                 const int cs = d.bp[c].vstart, cn = d.bp[c].n;
                 __syncthreads();   // the staging arrays are free
                 for (int u = tid; u < cn; u += BT) {
@@ -358,7 +363,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
             d.target[v0 + v] = make_float2(Ux, Uy);
             const int p = (v == 0) ? n - 1 : v - 1;
             const float dV = 0.5f * (slen[p] + slen[v]);
-            write_spread(d, v0 + v, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y));
+            write_spread(d, BB, v0 + v, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y));
         }
     } else {
         bool bad = false;
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
             d.target[v0 + v] = make_float2(Ux, Uy);
             const int p = (v == 0) ? n - 1 : v - 1;
             const float dV = 0.5f * (slen[p] + slen[v]);
-            write_spread(d, v0 + v, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y));
+            write_spread(d, BB, v0 + v, rxh[k], rxl[k], ryh[k], ryl[k], dV * (Ux - rus[k].x), dV * (Uy - rus[k].y));
         }
         if (bad) atomicOr(d.err, FLAG_NONFINITE_IB);
     }
@@ -484,7 +489,8 @@ __global__ __launch_bounds__(256) void k_mark(Dev d, int par) {
     const int v = blockIdx.x * 256 + threadIdx.x;
     if (v >= d.nverts) return;
     int tl[9];
-    const int c = stencil_tiles(d, d.pxh[par][v], d.pxl[par][v], d.pyh[par][v], d.pyl[par][v], tl);
+    const Band B = band_of(d, d.vband[v]);
+    const int c = stencil_tiles(d, B, d.pxh[par][v], d.pxl[par][v], d.pyh[par][v], d.pyl[par][v], tl);
     for (int q = 0; q < c; q++) {
         mark_tile(d, par, tl[q]);
         note_cover(d, par, tl[q], v);

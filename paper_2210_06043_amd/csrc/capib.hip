@@ -19,7 +19,7 @@ using namespace capib;
 namespace {
 
 struct BodyHost {
-    int kind, n, vstart;
+    int kind, n, vstart, band = 0;
     int site_start = 0, n_sites = 0;
     bool has_bonds = false;
     double A0, P0;
@@ -57,7 +57,12 @@ struct capib_ctx {
     long long step = 0;
     int nbodies = 0, nverts = 0, nsites = 0;
     std::vector<BodyHost> bodies;
-    std::vector<double> ref_u;     // reference x-velocity per row (FP64)
+    std::vector<double> ref_u;     // reference x-velocity per band-local row (FP64)
+    // bands of the stack (ensemble members); a single lattice is one band
+    int nbands = 1, band_rows = 0;
+    std::vector<int> band_nx;
+    std::vector<int> band_b0, band_nb;   // first body and body count per band
+    size_t off_band = 0, off_vband = 0;
     std::string err = "no error";
     // timing
     bool timing = false;
@@ -104,7 +109,8 @@ static void layout(capib_ctx *c) {
     c->off_near = o; o = align256(o + near_bytes(c));
     c->off_red = o; o = align256(o + (3 * (size_t)c->ntx * c->nty + 3) * 8);
     c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
-    c->off_rowref = o; o = align256(o + (size_t)L.ny * 16 * 4);
+    c->off_rowref = o; o = align256(o + (size_t)c->band_rows * 16 * 4);
+    c->off_band = o; o = align256(o + (size_t)c->nbands * 4);
     c->off_scal = o; o = align256(o + 64);
     // spread records (rewritten every step, not checkpointed): origin, x and y
     // weights, force per vertex
@@ -116,6 +122,7 @@ static void layout(capib_ctx *c) {
     c->off_bp = o; o = align256(o + B * sizeof(BodyParams));
     c->off_bs = o; o = align256(o + B * sizeof(BodyState));
     c->off_vbody = o; o = align256(o + V * 4);
+    c->off_vband = o; o = align256(o + V * 4);
     for (int k = 0; k < 8; k++) { c->off_pos[k] = o; o = align256(o + V * 4); }
     c->off_dxm = o; o = align256(o + V * 4);
     c->off_dym = o; o = align256(o + V * 4);
@@ -144,7 +151,7 @@ static void fill_dev(capib_ctx *c) {
     const capib_lattice &L = c->lat;
     char *b = c->base;
     d.nx = L.nx; d.ny = L.ny; d.pitch = c->pitch; d.walls = L.walls;
-    d.ntx = c->ntx; d.nty = c->nty; d.storage = L.storage;
+    d.ntx = c->ntx; d.nty = c->nty; d.storage = L.storage; d.band_rows = c->band_rows;
     d.qstride = (long long)c->pitch * L.ny;
     d.omega = (float)(1.0 / L.tau);
     d.fc = (float)(1.0 - 0.5 / L.tau);
@@ -178,7 +185,9 @@ static void fill_dev(capib_ctx *c) {
     d.rowref = (const float *)(b + c->off_rowref);
     d.counter = (long long *)(b + c->off_scal);
     d.err = (int *)(b + c->off_scal + 8);
-    d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites;
+    d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites; d.nbands = c->nbands;
+    d.band_nx = (const int *)(b + c->off_band);
+    d.vband = (int *)(b + c->off_vband);
     for (int k = 0; k < ARG_BODIES; k++) {
         if (k < c->nbodies) {
             const BodyHost &bh = c->bodies[k];
@@ -242,7 +251,7 @@ static const int EYq[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const int OPPq[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 static const double Wq[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
-// Reference population of row y: h_eq(drho = 0, u = (u_ref(y), 0)), FP64.
+// Reference population of band-local row y: h_eq(drho = 0, u = (u_ref(y), 0)), FP64.
 static double ref_pop(const capib_ctx *c, int y, int q) {
     const double u = c->ref_u[y], eu = EXq[q] * u;
     return Wq[q] * (3.0 * eu + 4.5 * eu * eu - 1.5 * u * u);
@@ -250,7 +259,7 @@ static double ref_pop(const capib_ctx *c, int y, int q) {
 
 // Per-row constants of the deviation storage (see Dev::rowref), from FP64.
 static capib_status upload_ref(capib_ctx *c) {
-    const int ny = c->lat.ny;
+    const int ny = c->band_rows;
     std::vector<float> t((size_t)ny * 16, 0.0f);
     for (int y = 0; y < ny; y++) {
         for (int q = 0; q < 9; q++) {
@@ -274,11 +283,20 @@ static capib_status upload_ref(capib_ctx *c) {
 
 extern "C" {
 
-capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx **out) {
-    if (!lat || !out) return CAPIB_E_ARG;
+// A stack of nbands bands of lat->ny rows each, band k of width widths[k].
+static capib_status create_stack(const capib_lattice *lat, int nbands, const int32_t *widths, void *hip_stream,
+                                 capib_ctx **out) {
+    if (!lat || !out || nbands < 1 || !widths) return CAPIB_E_ARG;
     *out = nullptr;
-    const capib_lattice &L = *lat;
-    if (L.nx < 1 || L.ny < 2 || (long long)L.nx * L.ny > (1LL << 31)) return CAPIB_E_ARG;
+    capib_lattice L = *lat;
+    int wmax = 0;
+    for (int k = 0; k < nbands; k++) {
+        if (widths[k] < 1) return CAPIB_E_ARG;
+        wmax = std::max(wmax, (int)widths[k]);
+    }
+    // bands are whole tile rows, so that no tile straddles two of them
+    if (nbands > 1 && L.ny % TILE_Y != 0) return CAPIB_E_ARG;
+    if (L.ny < 2 || (long long)wmax * L.ny * nbands > (1LL << 31)) return CAPIB_E_ARG;
     if (!(L.tau > 0.5) || !std::isfinite(L.tau) || !std::isfinite(L.gx) || !std::isfinite(L.gy)) return CAPIB_E_ARG;
     if (L.walls != 0 && L.walls != 3) return CAPIB_E_ARG;
     if (L.storage != CAPIB_FP32_SHIFTED && L.storage != CAPIB_FP16_SHIFTED) return CAPIB_E_ARG;
@@ -289,6 +307,13 @@ capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx 
     }
     if (L.max_bodies < 0 || L.max_vertices < 0 || L.max_sites < 0) return CAPIB_E_ARG;
     capib_ctx *c = new capib_ctx();
+    c->nbands = nbands;
+    c->band_rows = L.ny;
+    c->band_nx.assign(widths, widths + nbands);
+    c->band_b0.assign(nbands, 0);
+    c->band_nb.assign(nbands, 0);
+    L.nx = wmax;
+    L.ny = L.ny * nbands;
     c->lat = L;
     c->stream = (hipStream_t)hip_stream;
     c->esize = L.storage == CAPIB_FP32_SHIFTED ? 4 : 2;
@@ -303,6 +328,18 @@ capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx 
     layout(c);
     *out = c;
     return CAPIB_OK;
+}
+
+capib_status capib_create(const capib_lattice *lat, void *hip_stream, capib_ctx **out) {
+    if (!lat) return CAPIB_E_ARG;
+    if (lat->nx < 1) return CAPIB_E_ARG;
+    const int32_t w = lat->nx;
+    return create_stack(lat, 1, &w, hip_stream, out);
+}
+
+capib_status capib_create_ensemble(const capib_lattice *lat, int32_t nbands, const int32_t *widths, void *hip_stream,
+                                   capib_ctx **out) {
+    return create_stack(lat, nbands, widths, hip_stream, out);
 }
 
 size_t capib_workspace_bytes(const capib_ctx *c) { return c ? c->ws_bytes : 0; }
@@ -320,10 +357,12 @@ capib_status capib_bind_workspace(capib_ctx *c, void *ptr, size_t bytes) {
     c->nbodies = c->nverts = c->nsites = 0;
     c->bodies.clear();
     fill_dev(c);
-    c->ref_u.assign(c->lat.ny, 0.0);
+    c->ref_u.assign(c->band_rows, 0.0);
+    c->band_b0.assign(c->nbands, 0);
+    c->band_nb.assign(c->nbands, 0);
     HIPCHK(c, hipMemsetAsync(c->base, 0, c->ws_bytes, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return CAPIB_OK;
+    return h2d(c, c->off_band, c->band_nx.data(), (size_t)c->nbands * 4);
 }
 
 capib_status capib_init_flow(capib_ctx *c, const double *ux) {
@@ -331,10 +370,10 @@ capib_status capib_init_flow(capib_ctx *c, const double *ux) {
     if (s) return s;
     if (c->step != 0) return fail(c, CAPIB_E_STATE, "the flow is initialised before the first step");
     if (ux)
-        for (int j = 0; j < c->lat.ny; j++)
+        for (int j = 0; j < c->band_rows; j++)
             if (!std::isfinite(ux[j]) || std::fabs(ux[j]) > 0.1) return fail(c, CAPIB_E_ARG, "bad velocity in row %d", j);
     // the initial profile becomes the reference of the deviation storage
-    for (int j = 0; j < c->lat.ny; j++) c->ref_u[j] = ux ? ux[j] : 0.0;
+    for (int j = 0; j < c->band_rows; j++) c->ref_u[j] = ux ? ux[j] : 0.0;
     if ((s = upload_ref(c))) return s;
     HIPCHK(c, launch_init_flow(c->d, c->par, c->stream));
     return CAPIB_OK;
@@ -352,7 +391,7 @@ capib_status capib_write_populations(capib_ctx *c, const double *h) {
             for (int i = 0; i < L.nx; i++) {
                 const double hv = h[((size_t)q * L.ny + j) * L.nx + i];
                 if (!std::isfinite(hv)) return fail(c, CAPIB_E_ARG, "non-finite population");
-                const double v = hv - ref_pop(c, j, q);
+                const double v = hv - ref_pop(c, j % c->band_rows, q);
                 const size_t k = q * N + (size_t)j * c->pitch + i;
                 if (c->esize == 4) {
                     ((float *)buf.data())[k] = (float)v;
@@ -379,7 +418,7 @@ capib_status capib_read_populations(capib_ctx *c, double *h) {
             for (int i = 0; i < L.nx; i++) {
                 const size_t k = q * N + (size_t)j * c->pitch + i;
                 h[((size_t)q * L.ny + j) * L.nx + i] =
-                    ref_pop(c, j, q) + (c->esize == 4 ? (double)((float *)buf.data())[k]
+                    ref_pop(c, j % c->band_rows, q) + (c->esize == 4 ? (double)((float *)buf.data())[k]
                                                        : (double)(float)((_Float16 *)buf.data())[k] / L.fp16_scale);
             }
     return CAPIB_OK;
@@ -396,6 +435,10 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     if (c->nverts + n > c->lat.max_vertices)
         return fail(c, CAPIB_E_CAPACITY, "more than %d vertices", c->lat.max_vertices);
     if (c->step != 0) return fail(c, CAPIB_E_STATE, "membranes are added before the first step");
+    const int band = m->band;
+    if (band < 0 || band >= c->nbands) return fail(c, CAPIB_E_ARG, "bad band %d", band);
+    if (c->nbodies > 0 && band < c->bodies.back().band)
+        return fail(c, CAPIB_E_ARG, "membranes are added in band order (band %d after %d)", band, c->bodies.back().band);
     const double params[] = {m->ks, m->kb, m->ka, m->p_ref, m->density_ratio};
     for (double p : params)
         if (!std::isfinite(p)) return fail(c, CAPIB_E_ARG, "non-finite membrane parameter");
@@ -405,7 +448,7 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
         if (!std::isfinite(xy[k]) || !std::isfinite(rs[k])) return fail(c, CAPIB_E_ARG, "non-finite vertex");
     for (int v = 0; v < n; v++) {
         const double y = xy[2 * v + 1];
-        if (c->lat.walls && (y < -0.5 || y > c->lat.ny - 0.5)) return fail(c, CAPIB_E_ARG, "vertex %d outside the fluid", v);
+        if (c->lat.walls && (y < -0.5 || y > c->band_rows - 0.5)) return fail(c, CAPIB_E_ARG, "vertex %d outside the fluid", v);
     }
     // FP64 geometry of a polygon
     auto geo = [n](const double *p, std::vector<double> &len, std::vector<double> &th, double &A, double &P,
@@ -453,6 +496,11 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     const int b = c->nbodies, v0 = c->nverts;
     BodyParams bp{};
     bp.kind = m->kind; bp.n = n; bp.vstart = v0; bp.tag = m->tag;
+    // bodies of a band are numbered contiguously (they are added in band order)
+    if (c->band_nb[band] == 0) c->band_b0[band] = b;
+    bp.band = band;
+    bp.band_b0 = c->band_b0[band];
+    bp.band_nb = c->band_nb[band] + 1;
     bp.ks = (float)m->ks; bp.kb = (float)m->kb; bp.ka = (float)m->ka; bp.pref = (float)m->p_ref;
     bp.vmass = (float)(m->density_ratio * A0 / n);
     bp.inv_mass = (float)(1.0 / (m->density_ratio * A));
@@ -463,7 +511,7 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     BodyState bs{};
     double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
     std::vector<float> xh(n), xl(n), yh(n), yl(n), r0x(n), r0y(n), fl0(n), fth0(n);
-    std::vector<int> vb(n, b);
+    std::vector<int> vb(n, b), vbd(n, band);
     for (int v = 0; v < n; v++) {
         split(xy[2 * v], xh[v], xl[v]);
         split(xy[2 * v + 1], yh[v], yl[v]);
@@ -483,6 +531,10 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     if ((s = h2d(c, c->off_bp + b * sizeof(BodyParams), &bp, sizeof bp))) return s;
     if ((s = h2d(c, c->off_bs + b * sizeof(BodyState), &bs, sizeof bs))) return s;
     if ((s = h2d(c, c->off_vbody + fo, vb.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_vband + fo, vbd.data(), n * 4))) return s;
+    // the band's earlier bodies see one more neighbour
+    for (int e = c->band_b0[band]; e < b; e++)
+        if ((s = h2d(c, c->off_bp + e * sizeof(BodyParams) + offsetof(BodyParams, band_nb), &bp.band_nb, 4))) return s;
     if ((s = h2d(c, c->off_pos[4 * pp + 0] + fo, xh.data(), n * 4))) return s;
     if ((s = h2d(c, c->off_pos[4 * pp + 1] + fo, xl.data(), n * 4))) return s;
     if ((s = h2d(c, c->off_pos[4 * pp + 2] + fo, yh.data(), n * 4))) return s;
@@ -496,9 +548,10 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     if ((s = h2d(c, c->off_l0 + fo, fl0.data(), n * 4))) return s;
     if ((s = h2d(c, c->off_th0 + fo, fth0.data(), n * 4))) return s;
     BodyHost bh;
-    bh.kind = m->kind; bh.n = n; bh.vstart = v0; bh.A0 = A0; bh.P0 = P;
+    bh.kind = m->kind; bh.n = n; bh.vstart = v0; bh.band = band; bh.A0 = A0; bh.P0 = P;
     bh.xy.assign(xy, xy + 2 * n);
     c->bodies.push_back(bh);
+    c->band_nb[band]++;
     c->nbodies++;
     c->nverts += n;
     c->marks_valid = false;
@@ -800,17 +853,18 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     if ((s = d2h(c, &cnt, c->off_scal, 8))) return s;
     if ((s = d2h(c, &err, c->off_scal + 8, 4))) return s;
     // add the reference part of the stored deviations (FP64, host)
-    double rm = 0, rx = 0;
-    for (int y = 0; y < c->lat.ny; y++)
+    double rm = 0, rx = 0, width = 0;
+    for (int y = 0; y < c->band_rows; y++)
         for (int q = 0; q < 9; q++) {
             rm += ref_pop(c, y, q);
             rx += ref_pop(c, y, q) * EXq[q];
         }
+    for (int k = 0; k < c->nbands; k++) width += c->band_nx[k];
     out->step = c->step;
     out->error_flags = err;
     out->n_bodies = c->nbodies;
-    out->mass = r[0] + c->lat.nx * rm;
-    out->mom_x = r[1] + c->lat.nx * rx;
+    out->mass = r[0] + width * rm;
+    out->mom_x = r[1] + width * rx;
     out->mom_y = r[2];
     out->tiles = c->ntx * c->nty;
     out->near_tiles = 0;
@@ -867,7 +921,8 @@ capib_status capib_save(capib_ctx *c, void *buf, size_t *bytes) {
     if (s) return s;
     if (!bytes) return fail(c, CAPIB_E_ARG, "null size");
     const size_t pop_bytes = 9 * (size_t)c->pitch * c->lat.ny * c->esize;
-    const size_t total = sizeof(CkptHeader) + pop_bytes + c->ib_bytes + 16 + (size_t)c->lat.ny * 8;
+    const size_t total = sizeof(CkptHeader) + pop_bytes + c->ib_bytes + 16 + (size_t)c->band_rows * 8 +
+                         (size_t)c->nbands * 4;
     if (!buf) { *bytes = total; return CAPIB_OK; }
     if (*bytes < total) return fail(c, CAPIB_E_ARG, "checkpoint buffer of %zu bytes needs %zu", *bytes, total);
     CkptHeader h{CKPT_MAGIC, c->lat.nx, c->lat.ny, c->pitch, c->lat.storage, c->nbodies, c->nverts, c->nsites,
@@ -881,7 +936,9 @@ capib_status capib_save(capib_ctx *c, void *buf, size_t *bytes) {
     p += c->ib_bytes;
     if ((s = d2h(c, p, c->off_scal, 16))) return s;
     p += 16;
-    std::memcpy(p, c->ref_u.data(), (size_t)c->lat.ny * 8);
+    std::memcpy(p, c->ref_u.data(), (size_t)c->band_rows * 8);
+    p += (size_t)c->band_rows * 8;
+    std::memcpy(p, c->band_nx.data(), (size_t)c->nbands * 4);
     *bytes = total;
     return CAPIB_OK;
 }
@@ -897,9 +954,12 @@ capib_status capib_load(capib_ctx *c, const void *buf, size_t bytes) {
         h.storage != c->lat.storage || h.nbodies != c->nbodies || h.nverts != c->nverts || h.nsites != c->nsites ||
         h.pop_bytes != pop_bytes || h.ib_bytes != c->ib_bytes || (h.par != 0 && h.par != 1))
         return fail(c, CAPIB_E_ARG, "checkpoint does not match this context");
-    if (bytes < sizeof h + pop_bytes + c->ib_bytes + 16 + (size_t)c->lat.ny * 8)
-        return fail(c, CAPIB_E_ARG, "checkpoint truncated");
+    const size_t tail = 16 + (size_t)c->band_rows * 8 + (size_t)c->nbands * 4;
+    if (bytes < sizeof h + pop_bytes + c->ib_bytes + tail) return fail(c, CAPIB_E_ARG, "checkpoint truncated");
     const char *p = (const char *)buf + sizeof h;
+    if (std::memcmp(p + pop_bytes + c->ib_bytes + 16 + (size_t)c->band_rows * 8, c->band_nx.data(),
+                    (size_t)c->nbands * 4) != 0)
+        return fail(c, CAPIB_E_ARG, "checkpoint band widths do not match this context");
     // reject non-finite populations before touching the device
     if (c->esize == 4) {
         const float *f = (const float *)p;
@@ -919,7 +979,7 @@ capib_status capib_load(capib_ctx *c, const void *buf, size_t bytes) {
     p += c->ib_bytes;
     if ((s = h2d(c, c->off_scal, p, 16))) return s;
     p += 16;
-    std::memcpy(c->ref_u.data(), p, (size_t)c->lat.ny * 8);
+    std::memcpy(c->ref_u.data(), p, (size_t)c->band_rows * 8);
     if ((s = upload_ref(c))) return s;
     // near tiles are marked afresh
     c->marks_valid = false;

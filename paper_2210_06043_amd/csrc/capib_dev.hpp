@@ -23,9 +23,11 @@ enum { FLAG_VERTEX_OUT = 1, FLAG_FLUID = 2, FLAG_NONFINITE_IB = 8 };
 // Read-only description of a body.
 struct BodyParams {
     int kind, n, vstart, tag;
-    int site_start, n_sites, pad0, pad1;
+    int site_start, n_sites;
+    int band, band_b0;              // ensemble member, and its first body
     float ks, kb, ka, pref;
-    float vmass, inv_mass, inv_inertia, pad2;
+    float vmass, inv_mass, inv_inertia;
+    int band_nb;                    // bodies of the member (contiguous from band_b0)
     double A0;
     float sigma, ycr, yeq, kf;
     float kr0, lb;
@@ -47,9 +49,16 @@ struct BodyState {
 static_assert(sizeof(BodyState) % 16 == 0, "BodyState must keep 16-byte alignment in arrays");
 
 // Everything a kernel needs, passed by value.
+//
+// The lattice is a stack of bands, each an independent capillary of
+// band_rows rows (an ensemble member); band k has width band_nx[k], starts
+// at row k * band_rows and wraps periodically at its own width.  A single
+// lattice is one band.  nx is the widest band (the row pitch is sized from
+// it) and ny the rows of all bands.  Membrane coordinates are local to their
+// band: x in [0, band width), y in [0, band_rows).
 struct Dev {
     int nx, ny, pitch, walls;
-    int ntx, nty, storage, pad0;
+    int ntx, nty, storage, band_rows;
     long long qstride;              // ny * pitch elements per population
     float omega, fc, gx, gy;        // 1/tau, 1 - 1/(2 tau), body force
     float scale, inv_scale;         // FP16 storage scale
@@ -70,7 +79,9 @@ struct Dev {
     int *ncount;
     int *tvlo[2], *tvhi[2];
     // immersed boundary
-    int nbodies, nverts, nsites, pad1;
+    int nbodies, nverts, nsites, nbands;
+    const int *band_nx;             // width of each band
+    int *vband;                     // band of each vertex
     // (first vertex, vertices, first site, sites) of the first ARG_BODIES
     // bodies, passed with the arguments so that the membrane kernel can
     // issue its loads without a round trip for its parameters
@@ -106,6 +117,13 @@ struct Dev {
 };
 
 // ---- small helpers -------------------------------------------------------------
+
+// Band k of the stack: width, first global row, rows.
+struct Band {
+    int nx, y0, ny;
+};
+__device__ __forceinline__ Band band_of(const Dev &d, int k) { return Band{d.band_nx[k], k * d.band_rows, d.band_rows}; }
+__device__ __forceinline__ Band band_of_row(const Dev &d, int j) { return band_of(d, j / d.band_rows); }
 
 // Workgroup index -> tile index such that each XCD (workgroups are dealt
 // round-robin to the 8 XCDs) receives one contiguous range of tiles, so that
@@ -146,8 +164,8 @@ __device__ __forceinline__ void df_add(float &hi, float &lo, float d) {
 // [-1, ny].  Non-finite or absurd coordinates are flagged and mapped to the
 // origin so that every index stays in range.  Returns true when the point
 // was moved (unclamped Y outside [-1, ny], or unusable coordinates).
-__device__ __forceinline__ bool stencil_origin(const Dev &d, float xh, float xl, float yh, float yl, int &ix0,
-                                               int &iy0, float &sx, float &sy) {
+__device__ __forceinline__ bool stencil_origin(const Dev &d, const Band &B, float xh, float xl, float yh, float yl,
+                                               int &ix0, int &iy0, float &sx, float &sy) {
     bool out = false;
     if (!(fabsf(xh) < 1.0e8f) || !(fabsf(xl) < 1.0e4f)) { xh = 0.0f; xl = 0.0f; out = true; }
     if (!(fabsf(yh) < 1.0e8f) || !(fabsf(yl) < 1.0e4f)) { yh = 0.0f; yl = 0.0f; out = true; }
@@ -159,7 +177,7 @@ __device__ __forceinline__ bool stencil_origin(const Dev &d, float xh, float xl,
     if (d.walls) {
         const float Y = yh + yl;
         if (Y < -1.0f) { out = true; yh = -1.0f; yl = 0.0f; }
-        if (Y > (float)d.ny) { out = true; yh = (float)d.ny; yl = 0.0f; }
+        if (Y > (float)B.ny) { out = true; yh = (float)B.ny; yl = 0.0f; }
     }
     int iy = (int)floorf(yh);
     sy = (yh - (float)iy) + yl;
@@ -171,10 +189,10 @@ __device__ __forceinline__ bool stencil_origin(const Dev &d, float xh, float xl,
     return out;
 }
 
-__device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float yh, float yl, bool renorm,
-                                        int &ix0, int &iy0, float wx[4], float wy[4], float &inv) {
+__device__ __forceinline__ bool stencil(const Dev &d, const Band &B, float xh, float xl, float yh, float yl,
+                                        bool renorm, int &ix0, int &iy0, float wx[4], float wy[4], float &inv) {
     float sx, sy;
-    const bool out = stencil_origin(d, xh, xl, yh, yl, ix0, iy0, sx, sy);
+    const bool out = stencil_origin(d, B, xh, xl, yh, yl, ix0, iy0, sx, sy);
     float cx, snx, cy, sny;
     sincospif(0.5f * sx, &snx, &cx);
     sincospif(0.5f * sy, &sny, &cy);
@@ -189,7 +207,7 @@ __device__ __forceinline__ bool stencil(const Dev &d, float xh, float xl, float 
 #pragma unroll
         for (int b = 0; b < 4; b++) {
             int j = iy0 + b;
-            if (j < 0 || j >= d.ny) wy[b] = 0.0f;
+            if (j < 0 || j >= B.ny) wy[b] = 0.0f;
         }
     }
     const float syw = renorm ? (wy[0] + wy[1]) + (wy[2] + wy[3]) : syfull;
@@ -209,13 +227,14 @@ __device__ __forceinline__ float ldpop<_Float16>(const _Float16 *p, float inv_sc
 }
 
 template <typename T>
-__device__ __forceinline__ void pull9(const Dev &d, const T *__restrict__ A, int i, int j, float h[9]) {
+__device__ __forceinline__ void pull9(const Dev &d, const T *__restrict__ A, int i, int j, const Band &B, float h[9]) {
     const long long Q = d.qstride;
-    const int im = (i == 0) ? d.nx - 1 : i - 1;
-    const int ip = (i == d.nx - 1) ? 0 : i + 1;
-    const bool bot = (j == 0), top = (j == d.ny - 1);
-    const int jm = bot ? d.ny - 1 : j - 1;
-    const int jp = top ? 0 : j + 1;
+    const int im = (i == 0) ? B.nx - 1 : i - 1;
+    const int ip = (i == B.nx - 1) ? 0 : i + 1;
+    const int jl = j - B.y0;
+    const bool bot = (jl == 0), top = (jl == B.ny - 1);
+    const int jm = bot ? j + B.ny - 1 : j - 1;
+    const int jp = top ? j - B.ny + 1 : j + 1;
     const long long r0 = (long long)j * d.pitch, rm = (long long)jm * d.pitch, rp = (long long)jp * d.pitch;
     const float is = d.inv_scale;
     h[0] = ldpop(A + r0 + i, is);
@@ -241,19 +260,20 @@ __device__ __forceinline__ void pull9(const Dev &d, const T *__restrict__ A, int
     }
 }
 
-// Pulled populations as deviations from the reference of row j:
-// dh_i = h_i - r_i(y_j) = s_i(x - e_i) + rowref_i(j).  Returns u_ref(y_j).
-__device__ __forceinline__ float add_rowref(const Dev &d, int j, float h[9]) {
-    const float *R = d.rowref + 16 * j;
+// Pulled populations as deviations from the reference of (band-local) row
+// jl: dh_i = h_i - r_i(y) = s_i(x - e_i) + rowref_i(jl).  Returns u_ref(y).
+__device__ __forceinline__ float add_rowref(const Dev &d, int jl, float h[9]) {
+    const float *R = d.rowref + 16 * jl;
     h[2] += R[2]; h[4] += R[4]; h[5] += R[5];
     h[6] += R[6]; h[7] += R[7]; h[8] += R[8];
     return R[9];
 }
 
 template <typename T>
-__device__ __forceinline__ float pull_dev(const Dev &d, const T *__restrict__ A, int i, int j, float h[9]) {
-    pull9<T>(d, A, i, j, h);
-    return add_rowref(d, j, h);
+__device__ __forceinline__ float pull_dev(const Dev &d, const T *__restrict__ A, int i, int j, const Band &B,
+                                          float h[9]) {
+    pull9<T>(d, A, i, j, B, h);
+    return add_rowref(d, j - B.y0, h);
 }
 
 // Records that the stencil of vertex v (global index) covers the tile, for
@@ -282,25 +302,27 @@ struct EqDev {
     }
 };
 
-// The tiles covered by the velocity-coupling stencil of a point: its four
-// rows (clipped to the fluid with walls, wrapped without) and four columns
-// (wrapped).  Four consecutive wrapped rows or columns can meet three tiles
-// when the last tile of the lattice is narrower than the stencil.  Returns
+// The tiles covered by the velocity-coupling stencil of a point of band B
+// (local coordinates): its four rows (clipped to the band's fluid rows with
+// walls, wrapped within the band without) and four columns (wrapped at the
+// band's width).  Four consecutive wrapped rows or columns can meet three
+// tiles when the last tile of a band is narrower than the stencil.  Returns
 // the count (at most 9) and writes the tile indices.
-__device__ __forceinline__ int stencil_tiles(const Dev &d, float xh, float xl, float yh, float yl, int tiles[9]) {
+__device__ __forceinline__ int stencil_tiles(const Dev &d, const Band &B, float xh, float xl, float yh, float yl,
+                                             int tiles[9]) {
     int ix0, iy0;
     float sx, sy;
-    stencil_origin(d, xh, xl, yh, yl, ix0, iy0, sx, sy);
+    stencil_origin(d, B, xh, xl, yh, yl, ix0, iy0, sx, sy);
     int ty[3], nty = 0;
 #pragma unroll
     for (int b = 0; b < 4; b++) {
         int j = iy0 + b;
         if (d.walls) {
-            if (j < 0 || j >= d.ny) continue;
+            if (j < 0 || j >= B.ny) continue;
         } else {
-            j = wrapi(j, d.ny);
+            j = wrapi(j, B.ny);
         }
-        const int t = j / TILE_Y;
+        const int t = (B.y0 + j) / TILE_Y;
         bool seen = false;
         for (int k = 0; k < nty; k++) seen |= (ty[k] == t);
         if (!seen && nty < 3) ty[nty++] = t;
@@ -308,7 +330,7 @@ __device__ __forceinline__ int stencil_tiles(const Dev &d, float xh, float xl, f
     int tx[3], ntx = 0;
 #pragma unroll
     for (int a = 0; a < 4; a++) {
-        const int t = wrapi(ix0 + a, d.nx) / TILE_X;
+        const int t = wrapi(ix0 + a, B.nx) / TILE_X;
         bool seen = false;
         for (int k = 0; k < ntx; k++) seen |= (tx[k] == t);
         if (!seen && ntx < 3) tx[ntx++] = t;

@@ -27,9 +27,10 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
 // ---- interpolation ----------------------------------------------------------------------
 
 template <typename T>
-__device__ __forceinline__ void node_moments(const Dev &d, const T *A, int i, int j, bool stress, float out[4]) {
+__device__ __forceinline__ void node_moments(const Dev &d, const T *A, int i, int j, const Band &B, bool stress,
+                                             float out[4]) {
     float h[9];
-    const float uref = pull_dev<T>(d, A, i, j, h);   // deviations from the row reference
+    const float uref = pull_dev<T>(d, A, i, j, B, h);   // deviations from the row reference
     const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
@@ -39,6 +40,8 @@ __device__ __forceinline__ void node_moments(const Dev &d, const T *A, int i, in
     if (!stress) {
         out[0] = uref + dux;
         out[1] = duy;
+        out[2] = 0.0f;
+        out[3] = 0.0f;
         return;
     }
     // non-equilibrium momentum flux h - h_eq(drho, u*) (Eq. 2); the row
@@ -73,6 +76,7 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d, int par) {
     const int v = probe ? p - d.nverts : p;
     const int b = d.vbody[v];
     const int vs = d.bp[b].vstart, n = d.bp[b].n;
+    const Band B = band_of(d, d.vband[v]);
     const int vn = (v + 1 - vs == n) ? vs : v + 1;
     float xh = d.pxh[par][v], xl = d.pxl[par][v], yh = d.pyh[par][v], yl = d.pyl[par][v];
     if (probe) {
@@ -84,20 +88,23 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d, int par) {
     }
     int ix0, iy0;
     float wx[4], wy[4], inv;
-    const bool out = stencil(d, xh, xl, yh, yl, probe, ix0, iy0, wx, wy, inv);
+    const bool out = stencil(d, B, xh, xl, yh, yl, probe, ix0, iy0, wx, wy, inv);
     if (out && !probe && lane == 0) atomicOr(d.err, FLAG_VERTEX_OUT);
     const int a = lane & 3, bb = lane >> 2;
-    const float W = wx[a] * wy[bb] * inv;
+    // lane-dependent picks as selects (an indexed register array would spill)
+    const float wxa = a == 0 ? wx[0] : a == 1 ? wx[1] : a == 2 ? wx[2] : wx[3];
+    const float wyb = bb == 0 ? wy[0] : bb == 1 ? wy[1] : bb == 2 ? wy[2] : wy[3];
+    const float W = wxa * wyb * inv;
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    int j = iy0 + bb;
-    if (!d.walls) j = wrapi(j, d.ny);
-    if (W != 0.0f && j >= 0 && j < d.ny) {
-        const int i = wrapi(ix0 + a, d.nx);
-        float m[4];
+    int j = iy0 + bb;   // band-local row
+    if (!d.walls) j = wrapi(j, B.ny);
+    if (W != 0.0f && j >= 0 && j < B.ny) {
+        const int i = wrapi(ix0 + a, B.nx);
+        float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (d.storage == 0)
-            node_moments<float>(d, (const float *)d.pop[par], i, j, probe, m);
+            node_moments<float>(d, (const float *)d.pop[par], i, B.y0 + j, B, probe, m);
         else
-            node_moments<_Float16>(d, (const _Float16 *)d.pop[par], i, j, probe, m);
+            node_moments<_Float16>(d, (const _Float16 *)d.pop[par], i, B.y0 + j, B, probe, m);
         acc[0] = W * m[0];
         acc[1] = W * m[1];
         if (probe) {

@@ -89,9 +89,11 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int par) {
     if (d.tnear[par][tile]) return;
     int i, j;
     tile_node(d, tile, i, j);
-    if (i >= d.nx || j >= d.ny) return;
+    if (j >= d.ny) return;
+    const Band B = band_of_row(d, j);   // wave-uniform
+    if (i >= B.nx) return;
     float h[9];
-    const float uref = pull_dev<T>(d, (const T *)d.pop[par], i, j, h);
+    const float uref = pull_dev<T>(d, (const T *)d.pop[par], i, j, B, h);
     lattice_collide<T>(d, par, i, j, h, uref, d.gx, d.gy);
 }
 
@@ -125,7 +127,8 @@ __device__ __forceinline__ void mark_next(const Dev &d, int npar, int mb) {
     int tile = 0;
     if ((int)threadIdx.x < MARK_VERTS * 9 && v < d.nverts) {
         int tl[9];
-        const int c = stencil_tiles(d, d.pxh[npar][v], d.pxl[npar][v], d.pyh[npar][v], d.pyl[npar][v], tl);
+        const Band B = band_of(d, d.vband[v]);
+        const int c = stencil_tiles(d, B, d.pxh[npar][v], d.pxl[npar][v], d.pyh[npar][v], d.pyl[npar][v], tl);
 #pragma unroll
         for (int r = 0; r < 9; r++)
             if (r == q) tile = tl[r];
@@ -163,12 +166,13 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par, in
         const int tile = d.nlist[par][k];
         const int tyi = tile / d.ntx, txi = tile - tyi * d.ntx;
         const int x0 = txi * TILE_X, y0 = tyi * TILE_Y;
-        const int tw = min(TILE_X, d.nx - x0), th = min(TILE_Y, d.ny - y0);
+        const Band B = band_of_row(d, y0);   // tiles never straddle bands
+        const int tw = min(TILE_X, B.nx - x0), th = min(TILE_Y, B.y0 + B.ny - y0);
         int i, j;
         tile_node(d, tile, i, j);
-        const bool valid = i < d.nx && j < d.ny;
+        const bool valid = i < B.nx && j < B.y0 + B.ny;
         float h[9];
-        if (valid) pull9<T>(d, (const T *)d.pop[par], i, j, h);
+        if (valid) pull9<T>(d, (const T *)d.pop[par], i, j, B, h);
         const int vhi = d.tvhi[par][tile] - 1, vlo = d.nverts - d.tvlo[par][tile];
 
         float ax = 0.0f, ay = 0.0f;
@@ -183,8 +187,9 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par, in
                 wx = d.sp_wx[v];
                 wy = d.sp_wy[v];
                 f = d.sp_f[v];
-                const bool hx = meets_periodic(o.x, x0, tw, d.nx);
-                const bool hy = d.walls ? (o.y + 3 >= y0 && o.y < y0 + th) : meets_periodic(o.y, y0, th, d.ny);
+                const bool hx = meets_periodic(o.x, x0, tw, B.nx);
+                const bool hy = d.walls ? (o.y + 3 >= y0 && o.y < y0 + th)
+                                        : meets_periodic(o.y - B.y0, y0 - B.y0, th, B.ny);
                 hit = hx && hy;
             }
             const unsigned long long m = __ballot(hit);
@@ -213,17 +218,17 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par, in
             for (int q = 0; q < tot; q += 4) {
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
-                    const float4 A = srec[q + u][0], B = srec[q + u][1], C = srec[q + u][2];
-                    int a = i - __float_as_int(C.x);
-                    if (a < 0) a += d.nx;
-                    int e = j - __float_as_int(C.y);
-                    if (!d.walls && e < 0) e += d.ny;
+                    const float4 RX = srec[q + u][0], RY = srec[q + u][1], RC = srec[q + u][2];
+                    int a = i - __float_as_int(RC.x);
+                    if (a < 0) a += B.nx;
+                    int e = j - __float_as_int(RC.y);
+                    if (!d.walls && e < 0) e += B.ny;
                     if ((unsigned)a < 4u && (unsigned)e < 4u) {
-                        const float wa = a == 0 ? A.x : a == 1 ? A.y : a == 2 ? A.z : A.w;
-                        const float we = e == 0 ? B.x : e == 1 ? B.y : e == 2 ? B.z : B.w;
+                        const float wa = a == 0 ? RX.x : a == 1 ? RX.y : a == 2 ? RX.z : RX.w;
+                        const float we = e == 0 ? RY.x : e == 1 ? RY.y : e == 2 ? RY.z : RY.w;
                         const float w = wa * we;
-                        ax += w * C.z;
-                        ay += w * C.w;
+                        ax += w * RC.z;
+                        ay += w * RC.w;
                     }
                 }
             }
@@ -235,26 +240,34 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par, in
             d.tvlo[par][tile] = 0;
         }
         if (valid) {
-            const float uref = add_rowref(d, j, h);
+            const float uref = add_rowref(d, j - B.y0, h);
             lattice_collide<T>(d, par, i, j, h, uref, d.gx + ax, d.gy + ay);
         }
     }
 }
 
-// Moments of the current state for read-out: drho and u* = (j + g/2)/rho.
+// Moments of the current state for read-out: drho and u* = (j + g/2)/rho
+// ([3][ny][nx]; zero beyond the width of a band).
 template <typename T>
 __global__ __launch_bounds__(LAT_THREADS) void k_macro(Dev d, int par) {
     const T *__restrict__ A = (const T *)d.pop[par];
     const int i = blockIdx.x * TILE_X + (threadIdx.x & (TILE_X - 1));
     const int j = blockIdx.y * TILE_Y + (threadIdx.x / TILE_X);
     if (i >= d.nx || j >= d.ny) return;
+    const long long N = (long long)d.nx * d.ny, k = (long long)j * d.nx + i;
+    const Band B = band_of_row(d, j);
+    if (i >= B.nx) {
+        d.macro[k] = 0.0f;
+        d.macro[N + k] = 0.0f;
+        d.macro[2 * N + k] = 0.0f;
+        return;
+    }
     float h[9];
-    const float uref = pull_dev<T>(d, A, i, j, h);
+    const float uref = pull_dev<T>(d, A, i, j, B, h);
     const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
     const float irho = 1.0f / (1.0f + drho);
-    const long long N = (long long)d.nx * d.ny, k = (long long)j * d.nx + i;
     d.macro[k] = drho;
     d.macro[N + k] = uref + (jx + 0.5f * d.gx - drho * uref) * irho;
     d.macro[2 * N + k] = (jy + 0.5f * d.gy) * irho;
@@ -279,7 +292,7 @@ __global__ __launch_bounds__(LAT_THREADS) void k_diag_partial(Dev d, int par) {
     const int i = blockIdx.x * TILE_X + (threadIdx.x & (TILE_X - 1));
     const int j = blockIdx.y * TILE_Y + (threadIdx.x / TILE_X);
     double m = 0, px = 0, py = 0;
-    if (i < d.nx && j < d.ny) {
+    if (i < d.nx && j < d.ny && i < band_of_row(d, j).nx) {
         const long long node = (long long)j * d.pitch + i;
         double h[9];
         for (int q = 0; q < 9; q++) h[q] = (double)ldpop<T>(A + q * d.qstride + node, d.inv_scale);

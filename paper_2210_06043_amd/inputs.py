@@ -142,12 +142,12 @@ def ellipse(n, a, b, cx, cy):
                      -np.pi / 2, 1.5 * np.pi, n)
 
 
-def biconcave(n, a_alpha, cx, cy):
+def biconcave(n, a_alpha, cx, cy, dense=200000):
     """Median section of a red blood cell, Eq. (21), with a*alpha the cell
     radius; reversed to counter-clockwise order; uniform in arc length."""
     fx = lambda q: cx - a_alpha * np.sin(q)        # x -> -x reverses the orientation
     fy = lambda q: cy + 0.5 * a_alpha * (0.207 + 2.003 * np.sin(q) ** 2 - 1.123 * np.sin(q) ** 4) * np.cos(q)
-    return _resample(fx, fy, -0.5 * np.pi, 1.5 * np.pi, n)
+    return _resample(fx, fy, -0.5 * np.pi, 1.5 * np.pi, n, dense)
 
 
 def rectangle(n, b, h, cx, y_bottom):
@@ -172,7 +172,7 @@ def rectangle(n, b, h, cx, y_bottom):
 
 # ---- ligand sites ------------------------------------------------------------------------
 
-def place_sites(xy, n_bound, ycr, wall_y=-0.5):
+def place_sites(xy, n_bound, ycr, wall_y=-0.5, dense=400000):
     """Ligand sites evenly spaced in arc length along the whole perimeter, with
     the spacing chosen so that exactly ``n_bound`` sites lie closer than ``ycr``
     to the wall at t = 0 (they are placed at the centres of n_bound equal parts
@@ -190,7 +190,7 @@ def place_sites(xy, n_bound, ycr, wall_y=-0.5):
         f = (s - s0[e]) / seg[e]
         return e, f, xy[e] + f[:, None] * (nxt[e] - xy[e])
 
-    dense = np.linspace(0.0, P, 400001)[:-1]
+    dense = np.linspace(0.0, P, dense + 1)[:-1]
     _, _, pts = point(dense)
     close = pts[:, 1] - wall_y < ycr
     if not close.any() or close.all():
@@ -277,6 +277,68 @@ def config_c2(seed=0, steps=50000, ar=None, ca=None):
     return Config("c2_3840x240", nx, ny, tau, g, ux_init=poiseuille_profile(ny, g, tau),
                   bodies=bodies, bonds=[bonds], steps=steps,
                   meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, n_bound0=200))
+
+
+def c3_member(seed, k):
+    """Member k of the batched ensemble: a 64-row capillary (Re = 0.01,
+    tau = 1) of length U{256..2048}; 1-4 cells, biconcave or globular with
+    equal odds, 128-256 markers at half-node spacing, Ca = 1e-3, evenly
+    spaced on the centre line; one discoidal particle 16 nodes long with
+    aspect ratio U[0.25, 1] and 64 markers, mid-gap after the first cell on
+    the lower wall, rigid (Ca = 0) with probability 1/4 and otherwise soft
+    with Ca log-uniform in [1e-5, 1e-3], 20 bonds engaged.  Drawn from the
+    stream seed * 2^20 + k."""
+    sid = seed * (1 << 20) + k
+    rng = np.random.default_rng(sid)
+    ny, tau = 64, 1.0
+    nu, umax, g = channel(ny, 0.01, tau)
+    nx = int(rng.integers(256, 2049))
+    dx_um = 7.5 / ny
+    ks_cell = stiffness(umax, tau, 1e-3)
+    ncell = int(rng.integers(1, 5))
+    bodies = []
+    xs = [(j + 0.5) * nx / ncell for j in range(ncell)]
+    for j in range(ncell):
+        n = int(rng.integers(128, 257))
+        R = 0.5 * n / (2.0 * np.pi)
+        cy = 0.5 * (ny - 1) + float(rng.uniform(-1.0, 1.0))
+        xy = biconcave(n, R, xs[j], cy, dense=20000) if rng.random() < 0.5 else circle(n, R, xs[j], cy)
+        bodies.append(Body(DEFORMABLE, xy, None, ks=ks_cell, kb=0.1 * ks_cell, rho_r=1.0, tag=TAG_CELL))
+    ar = float(rng.uniform(0.25, 1.0))
+    rigid = rng.random() < 0.25
+    ca = 0.0 if rigid else float(10.0 ** rng.uniform(-5.0, -3.0))
+    ycr = Y_CR_M / (dx_um * 1e-6)
+    yeq = 0.5 * ycr
+    px = xs[0] + 0.5 * nx / ncell
+    part_xy = rectangle(64, 16.0, ar * 16.0, px, -0.5 + yeq)
+    if rigid:
+        bodies.append(Body(RIGID, part_xy, None, rho_r=1.1, tag=TAG_PARTICLE))
+    else:
+        ks = stiffness(umax, tau, ca)
+        bodies.append(Body(DEFORMABLE, part_xy, None, ks=ks, kb=0.1 * ks, rho_r=1.1, tag=TAG_PARTICLE))
+    host, frac = place_sites(part_xy, 20, ycr, dense=40000)
+    kf = 8.5e-3
+    bonds = Bonds(len(bodies) - 1, host, frac, sigma=bond_spring(tau, ny), ycr=ycr, yeq=yeq, kf=kf,
+                  kr0=kf / KF_OVER_KR0, lb=ycr / 20.0, seed=sid)
+    return Config(f"c3_{k}_{nx}x{ny}", nx, ny, tau, g, ux_init=poiseuille_profile(ny, g, tau), bodies=bodies,
+                  bonds=[bonds], steps=20000,
+                  meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, ncell=ncell, n_bound0=20))
+
+
+def config_c3(seed=0, members=256):
+    """The batched ensemble: `members` independent capillaries (c3_member)."""
+    return [c3_member(seed, k) for k in range(members)]
+
+
+def config_ensemble_small():
+    """Four small members of one ensemble for parity tests: ragged widths
+    (37, 64, 100, 131), 24 rows (a multiple of the tile height); a cell and
+    a bonded particle, a lone cell, a cell and particle again with other
+    seeds, and an empty channel."""
+    return [config_tiny(nx=37, ny=24, seed=3),
+            config_tiny(nx=64, ny=24, seed=4, kinds=(DEFORMABLE,)),
+            config_tiny(nx=100, ny=24, seed=5),
+            config_tiny(nx=131, ny=24, seed=6, kinds=())]
 
 
 def config_tiny(nx=37, ny=22, tau=0.8, seed=3, walls=3, kinds=(DEFORMABLE, RIGID), umax=2e-3, ca=5e-2):

@@ -101,3 +101,41 @@ def test_create_sizes_the_workspace_and_checks_order():
     assert st2 == capib.CAPIB_OK
     assert L2.capib_workspace_bytes(ctx2) < n      # FP16 populations take half the bytes
     L2.capib_destroy(ctx2)
+
+
+def _create_ensemble(widths, **kw):
+    L = capib.load_library()
+    base = dict(nx=0, ny=16, tau=1.0, gx=0.0, gy=0.0, walls=3, storage=0, fp16_scale=1.0, max_bodies=2,
+                max_vertices=64, max_sites=16)
+    base.update(kw)
+    lat = capib.capib_lattice(**base)
+    ctx = C.c_void_p()
+    w = (C.c_int32 * max(1, len(widths)))(*widths)
+    st = L.capib_create_ensemble(C.byref(lat), len(widths), w, None, C.byref(ctx))
+    return L, st, ctx
+
+
+@pytest.mark.parametrize("widths,kw", [([], {}), ([32, 0], {}), ([32, 64], dict(ny=18)),
+                                        ([32, 64], dict(tau=0.5))])
+def test_create_ensemble_rejects_bad_members(widths, kw):
+    """No members, a zero width, members whose rows are not whole tile rows,
+    or a bad shared lattice parameter are refused."""
+    L, st, ctx = _create_ensemble(widths, **kw)
+    assert st == capib.CAPIB_E_ARG
+    assert not ctx.value
+
+
+def test_create_ensemble_sizes_the_stack():
+    """An ensemble of members of widths 32, 200 and 64 is sized as a stack of
+    three 16-row bands of the widest member; one band equals a lattice."""
+    L, st, ctx = _create_ensemble([32, 200, 64])
+    assert st == capib.CAPIB_OK
+    n3 = L.capib_workspace_bytes(ctx)
+    assert n3 >= 2 * 9 * (3 * 16) * 256 * 4
+    L.capib_destroy(ctx)
+    L1, st1, ctx1 = _create_ensemble([200])
+    L2, st2, ctx2 = _create(nx=200)
+    assert st1 == st2 == capib.CAPIB_OK
+    assert L1.capib_workspace_bytes(ctx1) == L2.capib_workspace_bytes(ctx2)
+    L1.capib_destroy(ctx1)
+    L2.capib_destroy(ctx2)

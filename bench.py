@@ -134,6 +134,71 @@ def measure(cfg, storage, scale, args):
                 error_flags=diag["error_flags"])
 
 
+def batched(args):
+    """The batched ensemble (256 capillaries, FP16 storage) against the
+    plain single-instance FP32 path run one member after another: completed
+    20k-step runs per hour, from the measured step times."""
+    import torch
+    from paper_2210_06043_amd import capib, inputs
+    cfgs = inputs.config_c3(seed=0, members=args.members)
+    scale = capib.fp16_scale_for(cfgs[0])
+    sim, first = capib.from_ensemble(cfgs, storage=capib.FP16_SHIFTED, fp16_scale=scale, graph=not args.no_graph)
+    nodes = sum(c.nx * c.ny for c in cfgs)
+    sim.step(args.batched_warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(args.batched_steps)
+    e1.record(sim.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.batched_steps
+    sim.set_timing(True)
+    sim.step(args.batched_steps)
+    sim.set_timing(False)
+    ph, n = sim.read_timing()
+    diag = sim.diagnostics()
+    far_ms = ph[2] / n
+    alg = 36 * (nodes - diag["near_tiles"] * 64 * 4)   # live nodes outside the near tiles
+    del sim
+    torch.cuda.empty_cache()
+    # single-instance FP32 step time on an evenly spaced sample of members
+    sample = list(range(0, len(cfgs), max(1, len(cfgs) // args.single_sample)))[:args.single_sample]
+    t1 = []
+    for k in sample:
+        g = capib.from_config(cfgs[k], graph=not args.no_graph)
+        g.step(200)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(g.stream)
+        g.step(args.batched_steps)
+        b.record(g.stream)
+        b.synchronize()
+        t1.append(a.elapsed_time(b) / args.batched_steps)
+        del g
+    steps_per_run = cfgs[0].steps
+    rph = len(cfgs) * 3600.0 / (steps_per_run * ms * 1e-3)
+    rph1 = 3600.0 / (steps_per_run * float(np.mean(t1)) * 1e-3)
+    return {
+        "workload": f"{len(cfgs)} capillaries, lengths U{{256..2048}} x 64, 1-4 cells (128-256 markers), "
+                    f"one adhered particle each (64 markers, 20 bonds); one ensemble, FP16 storage",
+        "members": len(cfgs), "nodes": nodes, "vertices": sum(c.n_vertices for c in cfgs),
+        "steps_per_run": steps_per_run, "ms_per_step": round(ms, 5),
+        "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "runs_per_hour": round(rph, 1),
+        "single_fp32_runs_per_hour": round(rph1, 1), "speedup": round(rph / rph1, 2),
+        "single_fp32_sample": f"members {sample}: mean {np.mean(t1) * 1e3:.2f} us/step, run one after another",
+        "roofline": {"bound": "hbm", "kernel": "k_lattice_far", "achieved": round(alg / (far_ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (far_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_us": round(far_ms * 1e3, 3),
+                     "traffic": counters("lattice_far_fp16_c3")},
+        "phase_us_per_step": {"interp": round(ph[0] / n * 1e3, 3), "body": round(ph[1] / n * 1e3, 3),
+                              "lattice_far": round(far_ms * 1e3, 3), "lattice_near": round(ph[3] / n * 1e3, 3)},
+        "error_flags": diag["error_flags"],
+    }
+
+
 def roofline(m, storage_name, workload_name):
     traffic = counters(f"lattice_far_{storage_name}_{workload_name}")
     return {"bound": "hbm", "kernel": "k_lattice_far", "achieved": round(m["achieved"], 1), "peak": HBM_PEAK_GBS,
@@ -154,6 +219,11 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--members", type=int, default=256)
+    ap.add_argument("--batched-steps", type=int, default=400)
+    ap.add_argument("--batched-warmup", type=int, default=100)
+    ap.add_argument("--single-sample", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates the HBM byte counters)")
@@ -214,6 +284,8 @@ def main():
                                "roofline": roofline(f, "fp16", args.workload), "phase_us_per_step": f["phases"],
                                "lattice_bandwidth_whole_sweep_gbs": round(f["whole_sweep_gbs"], 1),
                                "error_flags": f["error_flags"]}
+    if not args.no_batched:
+        out["batched"] = batched(args)
     if not args.no_cpu_baseline:
         base, ref = cpu_baseline(cfg, args.cpu_steps)
         out["cpu_baseline"] = base

@@ -344,10 +344,11 @@ hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t 
 }
 
 hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    // enough workgroups for the near tiles of a few thousand vertices; the
-    // grid-stride loop covers any count
+    // about one workgroup per near tile (a membrane's near tiles number a
+    // fraction of its vertices); the grid-stride loop covers any count
     const int nt = d.ntx * d.nty;
-    const int nb = nt < 1024 ? nt : 1024;
+    const int want = d.nverts / 2 > 1024 ? d.nverts / 2 : 1024;
+    const int nb = nt < want ? nt : want;
     const int nmark = (d.nverts + MARK_VERTS - 1) / MARK_VERTS;
     if (d.storage == 0)
         hipExtLaunchKernelGGL(k_lattice_near<float>, dim3(nmark + nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par,

@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="print only the batched-ensemble measurement (for profiling it alone)")
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=400)
     ap.add_argument("--batched-warmup", type=int, default=100)
@@ -246,6 +248,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}))
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched(args)}), flush=True)
         return
     cfg, desc = workload(args.workload, args.seed)
     nodes = cfg.nx * cfg.ny

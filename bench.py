@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--workload", choices=["c2", "c1"], default="c2")
     # seed 2 draws the rigid (Ca = 0) square particle; the soft draws develop a
-    # period-2 wall instability after ~2000 steps (see DESIGN.md)
+    # period-2 wall instability after ~2000 steps
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
@@ -231,8 +231,8 @@ def main():
                     help="only run a plain device copy of this many MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              f"DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs is not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

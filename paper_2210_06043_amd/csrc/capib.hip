@@ -667,7 +667,6 @@ static capib_status ensure_streams(capib_ctx *c) {
 // previous step did not mark them (start, new membranes, loaded checkpoint).
 static capib_status ensure_marks(capib_ctx *c) {
     if (c->marks_valid) return CAPIB_OK;
-    const size_t nt = (size_t)c->ntx * c->nty;
     HIPCHK(c, hipMemsetAsync(c->base + c->off_near, 0, near_bytes(c), c->stream));
     HIPCHK(c, launch_mark(c->d, c->par, c->stream));
     c->marks_valid = true;

@@ -8,14 +8,15 @@ import subprocess
 
 import pytest
 
-from paper_2210_06043_amd import capib
+from paper_2210_06043_amd import capib, mlp
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "capib.h")
+MLP_HEADER = os.path.join(ROOT, "include", "capib_mlp.h")
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(header=HEADER):
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(capib_[a-z_0-9]+)\s*\(", src)))
 
@@ -30,15 +31,36 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol():
     L = capib.load_library()
-    for name in declared_functions():
+    names = declared_functions() + declared_functions(MLP_HEADER)
+    for name in names:
         assert hasattr(L, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", capib.LIB_PATH], capture_output=True, text=True).stdout
     exported = set(re.findall(r" T (capib_\w+)", out))
-    assert set(declared_functions()) <= exported
+    assert set(names) <= exported
 
 
 def test_binding_covers_the_header():
     assert set(capib.SIGNATURES) == set(declared_functions())
+    assert set(mlp.SIGNATURES) == set(declared_functions(MLP_HEADER))
+
+
+def test_surrogate_parameter_count_matches_the_oracle():
+    from oracle import mlp as omlp
+    src = open(MLP_HEADER).read()
+    n = int(re.search(r"CAPIB_MLP_PARAMS = (\d+)", src).group(1))
+    assert n == mlp.N_PARAMS == omlp.n_params()
+
+
+def test_surrogate_create_validates_without_a_gpu():
+    L = mlp._lib()
+    h = C.c_void_p()
+    assert L.capib_mlp_create(0, None, C.byref(h)) == capib.CAPIB_E_ARG
+    assert L.capib_mlp_create(1000, None, C.byref(h)) == capib.CAPIB_OK
+    n = L.capib_mlp_workspace_bytes(h)
+    assert n % 256 == 0 and n > 4 * 4 * mlp.N_PARAMS        # master weights, gradients, Adam moments
+    x = C.c_void_p(256)
+    assert L.capib_mlp_forward(h, x, 10, x) == capib.CAPIB_E_STATE    # no workspace bound
+    L.capib_mlp_destroy(h)
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -231,6 +231,24 @@ capib_status capib_read_body_work(capib_ctx *ctx, int32_t body_id, double *ustar
  * any flag is set.  Syncs.                                                  */
 capib_status capib_diagnostics(capib_ctx *ctx, capib_diag *out);
 
+/* Per member (band) of the context (one for a single lattice), the
+ * quantities the load/hazard surrogate (capib_mlp.h) learns from, at the
+ * current state, into out_device[8 * band + 0..7] (device floats):
+ *   0, 1  drag and lift: the hydrodynamic load of Eqs. (14)-(15) summed over
+ *         the elements of the member's particle (its first body with tag
+ *         particle_tag), from the last step's probes and element geometry
+ *   2     hazard: mean Bell rupture probability of the particle's engaged
+ *         bonds (Sec. 2.5) at the current positions (0 without bonds)
+ *   3     r: distance from the particle's vertex mean to the nearest vertex
+ *         mean of a body with tag cell_tag (periodic in x; 0 if none)
+ *   4     dp: that cell's perimeter over its initial perimeter, minus one
+ *   5     that cell's body id (-1 if none)
+ *   6     wall shear rate du_x/dy at the lower wall, 2 u_x(row 0), two
+ *         nodes upstream of the particle's leftmost vertex (0 without walls)
+ *   7     N_L of the particle
+ * A member without a particle gets zeros and -1.  Enqueued.               */
+capib_status capib_sample_members(capib_ctx *ctx, int32_t particle_tag, int32_t cell_tag, float *out_device);
+
 /* FP64 geometry of a body's current polygon, N_L and rigid state.  Syncs. */
 capib_status capib_body_diagnostics(capib_ctx *ctx, int32_t body_id, capib_body_diag *out);
 

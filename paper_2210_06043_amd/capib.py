@@ -77,6 +77,7 @@ SIGNATURES = {
     "capib_load": (C.c_int, [_P, _P, C.c_size_t]),
     "capib_set_timing": (C.c_int, [_P, C.c_int32]),
     "capib_read_timing": (C.c_int, [_P, _dp, C.POINTER(C.c_int64)]),
+    "capib_sample_members": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "capib_last_error": (C.c_char_p, [_P]),
     "capib_destroy": (None, [_P]),
 }
@@ -253,6 +254,17 @@ class Simulation:
             self._check(st)
         return dict(step=d.step, error_flags=d.error_flags, n_bodies=d.n_bodies, mass=d.mass, mom_x=d.mom_x,
                     mom_y=d.mom_y, near_tiles=d.near_tiles, tiles=d.tiles, status=st)
+
+    def sample_members(self, out=None, particle_tag=2, cell_tag=1):
+        """Per member: drag, lift, hazard, r, dp, nearest cell, wall shear
+        rate, N_L (see capib_sample_members) into a [members][8] float
+        tensor on the device (allocated if not given).  Enqueued."""
+        if out is None:
+            out = self.torch.empty((len(self.bands), 8), dtype=self.torch.float32, device=self.device)
+        assert out.dtype == self.torch.float32 and out.is_contiguous() and out.numel() >= 8 * len(self.bands)
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        self._check(self.L.capib_sample_members(self.ctx, particle_tag, cell_tag, _P(out.data_ptr())))
+        return out
 
     def body_diagnostics(self, body):
         d = capib_body_diag()

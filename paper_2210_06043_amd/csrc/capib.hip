@@ -110,7 +110,7 @@ static void layout(capib_ctx *c) {
     c->off_red = o; o = align256(o + (3 * (size_t)c->ntx * c->nty + 3) * 8);
     c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
     c->off_rowref = o; o = align256(o + (size_t)c->band_rows * 16 * 4);
-    c->off_band = o; o = align256(o + (size_t)c->nbands * 4);
+    c->off_band = o; o = align256(o + (size_t)c->nbands * 12);   // widths, then (first body, count)
     c->off_scal = o; o = align256(o + 64);
     // spread records (rewritten every step, not checkpointed): origin, x and y
     // weights, force per vertex
@@ -187,6 +187,7 @@ static void fill_dev(capib_ctx *c) {
     d.err = (int *)(b + c->off_scal + 8);
     d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites; d.nbands = c->nbands;
     d.band_nx = (const int *)(b + c->off_band);
+    d.band_bodies = (const int2 *)(b + c->off_band + 4 * (size_t)c->nbands);
     d.vband = (int *)(b + c->off_vband);
     for (int k = 0; k < ARG_BODIES; k++) {
         if (k < c->nbodies) {
@@ -506,6 +507,7 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     bp.inv_mass = (float)(1.0 / (m->density_ratio * A));
     bp.inv_inertia = (float)(1.0 / (m->density_ratio * J));
     bp.A0 = A0;
+    bp.P0 = (float)P;
     split(cx, bp.c0xh, bp.c0xl);
     split(cy, bp.c0yh, bp.c0yl);
     BodyState bs{};
@@ -552,6 +554,10 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     bh.xy.assign(xy, xy + 2 * n);
     c->bodies.push_back(bh);
     c->band_nb[band]++;
+    {
+        const int2 r = make_int2(c->band_b0[band], c->band_nb[band]);
+        if ((s = h2d(c, c->off_band + 4 * (size_t)c->nbands + 8 * (size_t)band, &r, 8))) return s;
+    }
     c->nbodies++;
     c->nverts += n;
     c->marks_valid = false;
@@ -874,6 +880,14 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     }
     if (cnt != c->step) return fail(c, CAPIB_E_STATE, "device step counter %lld != %lld", cnt, c->step);
     if (err) return fail(c, CAPIB_E_UNSTABLE, "device error flags 0x%x", err);
+    return CAPIB_OK;
+}
+
+capib_status capib_sample_members(capib_ctx *c, int32_t particle_tag, int32_t cell_tag, float *out_device) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!out_device) return fail(c, CAPIB_E_ARG, "null output");
+    HIPCHK(c, launch_sample(c->d, c->par, particle_tag, cell_tag, out_device, c->stream));
     return CAPIB_OK;
 }
 

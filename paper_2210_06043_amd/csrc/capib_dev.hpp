@@ -33,6 +33,7 @@ struct BodyParams {
     float kr0, lb;
     uint32_t seed_lo, seed_hi;
     float c0xh, c0xl, c0yh, c0yl;   // rigid: centroid at t = 0 (hi + lo)
+    float P0, pad3;                 // perimeter at t = 0
 };
 
 // Mutable per-body state.
@@ -81,6 +82,7 @@ struct Dev {
     // immersed boundary
     int nbodies, nverts, nsites, nbands;
     const int *band_nx;             // width of each band
+    const int2 *band_bodies;        // (first body, body count) of each band
     int *vband;                     // band of each vertex
     // (first vertex, vertices, first site, sites) of the first ARG_BODIES
     // bodies, passed with the arguments so that the membrane kernel can

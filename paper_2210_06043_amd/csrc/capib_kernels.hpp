@@ -21,5 +21,6 @@ hipError_t launch_diag(const Dev &d, int par, hipStream_t st);
 hipError_t launch_interp(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_body(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_body_geom(const Dev &d, int par, hipStream_t st);
+hipError_t launch_sample(const Dev &d, int par, int ptag, int ctag, float *out, hipStream_t st);
 
 }  // namespace capib

@@ -129,6 +129,128 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d, int par) {
     }
 }
 
+// ---- per-member sample for the surrogate -----------------------------------------------
+
+// One workgroup per band (ensemble member): for its particle (first body
+// with tag ptag) and its cells (bodies with tag ctag), at the current state
+// (positions x^{n+1} of parity par; the last step's probe values belong to
+// x^n, parity par ^ 1), out[8 k ..] = drag, lift (the hydrodynamic load of
+// Eqs. 14-15 summed over the particle's elements), hazard (mean Bell
+// rupture probability of the engaged bonds, Sec. 2.5), r (distance from the
+// particle's vertex mean to the nearest cell's, periodic in x), dp (that
+// cell's perimeter over its initial perimeter, minus one), the cell's body
+// id (-1: none), the wall shear rate du_x/dy = u_x(row 0) / (1/2) two nodes
+// upstream of the particle's leftmost vertex, and N_L.
+template <typename T>
+__global__ __launch_bounds__(GEOM_THREADS) void k_sample(Dev d, int par, int ptag, int ctag, float *out) {
+    __shared__ double shd[GEOM_THREADS / 64];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const Band B = band_of(d, k);
+    const int2 bb = d.band_bodies[k];
+    float *o = out + 8 * (long long)k;
+    int part = -1;
+    for (int b = bb.x; b < bb.x + bb.y; b++)
+        if (d.bp[b].tag == ptag) { part = b; break; }
+    if (part < 0) {
+        if (tid < 8) o[tid] = tid == 5 ? -1.0f : 0.0f;
+        return;
+    }
+    const BodyParams P = d.bp[part];
+    const int n = P.n, v0 = P.vstart, pp = par ^ 1;
+    double sx = 0.0, sy = 0.0, fx = 0.0, fy = 0.0;
+    for (int l = tid; l < n; l += GEOM_THREADS) {
+        sx += (double)d.pxh[par][v0 + l] + (double)d.pxl[par][v0 + l];
+        sy += (double)d.pyh[par][v0 + l] + (double)d.pyl[par][v0 + l];
+        const int m = (l + 1 == n) ? 0 : l + 1;
+        const float tx = (d.pxh[pp][v0 + m] - d.pxh[pp][v0 + l]) + (d.pxl[pp][v0 + m] - d.pxl[pp][v0 + l]);
+        const float ty = (d.pyh[pp][v0 + m] - d.pyh[pp][v0 + l]) + (d.pyl[pp][v0 + m] - d.pyl[pp][v0 + l]);
+        const float len = sqrtf(tx * tx + ty * ty);
+        const float nx = ty / len, ny = -tx / len;
+        const float4 q = d.probe4[v0 + l];
+        fx += (double)(((q.y - q.x) * nx + q.z * ny) * len);
+        fy += (double)((q.z * nx + (q.w - q.x) * ny) * len);
+    }
+    sx = block_sum(sx, shd);
+    sy = block_sum(sy, shd);
+    fx = block_sum(fx, shd);
+    fy = block_sum(fy, shd);
+    const double cx = sx / n, cy = sy / n;
+    double hz = 0.0, nl = 0.0;
+    for (int q = tid; q < P.n_sites; q += GEOM_THREADS) {
+        const int s = P.site_start + q;
+        if (!d.s_state[s]) continue;
+        const int e = d.s_host[s] - v0;
+        const int m = (e + 1 == n) ? 0 : e + 1;
+        const float f = d.s_frac[s];
+        const float xh = d.pxh[par][v0 + e], xl = d.pxl[par][v0 + e] + f * ((d.pxh[par][v0 + m] - xh) +
+                                                                          (d.pxl[par][v0 + m] - d.pxl[par][v0 + e]));
+        const float yh = d.pyh[par][v0 + e], yl = d.pyl[par][v0 + e] + f * ((d.pyh[par][v0 + m] - yh) +
+                                                                          (d.pyl[par][v0 + m] - d.pyl[par][v0 + e]));
+        const float dx = (xh - d.s_anh[s]) + (xl - d.s_anl[s]);
+        const float dy = (yh + 0.5f) + yl;
+        const float len = sqrtf(dx * dx + dy * dy);
+        hz += (double)(-expm1f(-P.kr0 * expf(fabsf(len - P.yeq) / P.lb)));
+        nl += 1.0;
+    }
+    hz = block_sum(hz, shd);
+    nl = block_sum(nl, shd);
+    double best = 1.0e300, bdp = 0.0;
+    int bi = -1;
+    for (int c = bb.x; c < bb.x + bb.y; c++) {
+        const BodyParams C = d.bp[c];
+        if (C.tag != ctag || c == part) continue;
+        double ax = 0.0, ay = 0.0, per = 0.0;
+        for (int l = tid; l < C.n; l += GEOM_THREADS) {
+            const int g = C.vstart + l, gm = C.vstart + ((l + 1 == C.n) ? 0 : l + 1);
+            ax += (double)d.pxh[par][g] + (double)d.pxl[par][g];
+            ay += (double)d.pyh[par][g] + (double)d.pyl[par][g];
+            const double tx = ((double)d.pxh[par][gm] - d.pxh[par][g]) + ((double)d.pxl[par][gm] - d.pxl[par][g]);
+            const double ty = ((double)d.pyh[par][gm] - d.pyh[par][g]) + ((double)d.pyl[par][gm] - d.pyl[par][g]);
+            per += sqrt(tx * tx + ty * ty);
+        }
+        ax = block_sum(ax, shd);
+        ay = block_sum(ay, shd);
+        per = block_sum(per, shd);
+        double dx = ax / C.n - cx;
+        dx -= B.nx * rint(dx / B.nx);
+        const double dy = ay / C.n - cy;
+        const double dist = sqrt(dx * dx + dy * dy);
+        if (dist < best) {
+            best = dist;
+            bi = c;
+            bdp = per / (double)C.P0 - 1.0;
+        }
+    }
+    if (tid == 0) {
+        float shear = 0.0f;
+        if (d.walls) {
+            const int i = wrapi((int)floorf(d.bs[part].bbox[par][0]) - 2, B.nx);
+            float h[9];
+            const float uref = pull_dev<T>(d, (const T *)d.pop[par], i, B.y0, B, h);
+            const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+            const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+            const float ux = uref + (jx + 0.5f * d.gx - drho * uref) / (1.0f + drho);
+            shear = 2.0f * ux;
+        }
+        o[0] = (float)fx;
+        o[1] = (float)fy;
+        o[2] = nl > 0.0 ? (float)(hz / nl) : 0.0f;
+        o[3] = bi >= 0 ? (float)best : 0.0f;
+        o[4] = (float)bdp;
+        o[5] = (float)bi;
+        o[6] = shear;
+        o[7] = (float)nl;
+    }
+}
+
+hipError_t launch_sample(const Dev &d, int par, int ptag, int ctag, float *out, hipStream_t st) {
+    if (d.storage == 0)
+        hipLaunchKernelGGL(k_sample<float>, dim3(d.nbands), dim3(GEOM_THREADS), 0, st, d, par, ptag, ctag, out);
+    else
+        hipLaunchKernelGGL(k_sample<_Float16>, dim3(d.nbands), dim3(GEOM_THREADS), 0, st, d, par, ptag, ctag, out);
+    return hipGetLastError();
+}
+
 // FP64 geometry of the current polygon of each body (diagnostics).
 __global__ __launch_bounds__(GEOM_THREADS) void k_body_geom(Dev d, int par) {
     __shared__ double shd[4];

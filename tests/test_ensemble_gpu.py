@@ -85,3 +85,76 @@ def test_ensemble_rejects_out_of_order_and_foreign_bands():
         sim.add_membrane(b.kind, b.xy, ks=b.ks, kb=b.kb, band=0)
     with pytest.raises(capib.CapibError):
         sim.add_membrane(b.kind, b.xy, ks=b.ks, kb=b.kb, band=2)
+
+
+def _oracle_sample(cfg, steps):
+    """The quantities of capib_sample_members computed on the host from the
+    oracle's state after `steps` steps (definitions as in the header)."""
+    o = oracle_sim(cfg)
+    o.step(steps - 1)
+    xn = [o.vertices(b).copy() for b in range(len(cfg.bodies))]
+    o.step(1)
+    part = next(b for b, body in enumerate(cfg.bodies) if body.tag == inputs.TAG_PARTICLE)
+    xp = xn[part]
+    t = np.roll(xp, -1, axis=0) - xp
+    ln = np.hypot(t[:, 0], t[:, 1])
+    nx, ny = t[:, 1] / ln, -t[:, 0] / ln
+    q = o.body_work(part)["probe"]                  # p, sxx, sxy, syy per element
+    drag = np.sum(((q[:, 1] - q[:, 0]) * nx + q[:, 2] * ny) * ln)
+    lift = np.sum((q[:, 2] * nx + (q[:, 3] - q[:, 0]) * ny) * ln)
+    x1 = o.vertices(part)
+    hz, nl = [], 0
+    for bd in cfg.bonds:
+        if bd.body != part:
+            continue
+        st, anc = o.bonds(part)
+        for k in np.nonzero(st)[0]:
+            e = bd.host[k]
+            m = (e + 1) % len(x1)
+            s = x1[e] + bd.frac[k] * (x1[m] - x1[e])
+            L = np.hypot(s[0] - anc[k], s[1] + 0.5)
+            hz.append(-np.expm1(-bd.kr0 * np.exp(abs(L - bd.yeq) / bd.lb)))
+        nl = int(st.sum())
+    c = x1.mean(0)
+    best, bi, bdp = None, -1, 0.0
+    for b, body in enumerate(cfg.bodies):
+        if body.tag != inputs.TAG_CELL:
+            continue
+        xc = o.vertices(b)
+        d = xc.mean(0) - c
+        d[0] -= cfg.nx * np.round(d[0] / cfg.nx)
+        dist = np.hypot(*d)
+        P = np.sum(np.hypot(*(np.roll(xc, -1, 0) - xc).T))
+        P0 = np.sum(np.hypot(*(np.roll(body.xy, -1, 0) - body.xy).T))
+        if best is None or dist < best:
+            best, bi, bdp = dist, b, P / P0 - 1.0
+    _, ux, _ = o.macro()
+    i = int(np.floor(x1[:, 0].min())) - 2
+    shear = 2.0 * ux[0, i % cfg.nx]
+    return dict(drag=drag, lift=lift, hazard=np.mean(hz) if hz else 0.0, r=best or 0.0, dp=bdp, cell=bi,
+                shear=shear, nl=nl)
+
+
+def test_member_samples_match_the_oracle():
+    """capib_sample_members on the four-member ensemble after 150 steps:
+    loads to 2e-3 of their scale, hazard 1e-3, distance and stretch to
+    1e-5, wall shear rate 1e-4, nearest cell and N_L exact."""
+    steps = 150
+    cfgs, sim, first = _run_ensemble(capib.FP32_SHIFTED, steps)
+    out = sim.sample_members().cpu().numpy()
+    for k, cfg in enumerate(cfgs):
+        row = out[k]
+        if not any(b.tag == inputs.TAG_PARTICLE for b in cfg.bodies):
+            assert row[5] == -1 and np.all(row[[0, 1, 2, 3, 4, 6, 7]] == 0)
+            continue
+        ref = _oracle_sample(cfg, steps)
+        say(f"member {k}: gpu {np.round(row, 8).tolist()}")
+        say(f"member {k}: oracle {ref}")
+        scale = max(abs(ref["drag"]), abs(ref["lift"]))
+        assert abs(row[0] - ref["drag"]) < 2e-3 * scale and abs(row[1] - ref["lift"]) < 2e-3 * scale
+        assert abs(row[2] - ref["hazard"]) <= 1e-3 * abs(ref["hazard"]) + 1e-12
+        assert row[7] == ref["nl"]
+        if ref["cell"] >= 0:
+            assert int(row[5]) == first[k] + ref["cell"]
+            assert abs(row[3] - ref["r"]) < 1e-5 * max(1.0, ref["r"]) and abs(row[4] - ref["dp"]) < 1e-5
+        assert abs(row[6] - ref["shear"]) < 1e-4 * abs(ref["shear"]) + 1e-12

@@ -199,6 +199,68 @@ def batched(args):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_section(args, batched_out):
+    """The load/hazard surrogate: trained on the solver's samples of the
+    256 capillaries of the batched workload, judged on 32 capillaries of
+    another draw; its inference rate on the matrix cores and what it buys
+    when it screens the sweep."""
+    import torch
+    from paper_2210_06043_amd import inputs, mlp, surrogate
+    tr = inputs.config_c3(seed=0, members=args.members)
+    te = inputs.config_c3(seed=1, members=32)
+    S, ms_h, first = surrogate.harvest(tr, args.harvest_steps, every=2)
+    X, T, _ = surrogate.features(S, tr, first)
+    S2, _, first2 = surrogate.harvest(te, args.harvest_steps, every=2)
+    X2, T2, _ = surrogate.features(S2, te, first2)
+    fx, ft = surrogate.Standardiser(X), surrogate.Standardiser(T)
+    net, ms_train = surrogate.train(fx(X), ft(T), steps=args.train_steps, batch=4096)
+    P = surrogate.predict(net, fx(X2))
+    err = np.mean((P - ft(T2)) ** 2, axis=0)
+    base = np.mean(ft(T2) ** 2, axis=0)
+    # inference rate: batches of 65,536, FLOPs of the unpadded network
+    nb = 65536
+    inf = mlp.Surrogate(nb)
+    inf.set_params(net.get_params())
+    x = torch.randn((nb, mlp.IN), device=inf.device)
+    inf.forward(x)
+    inf.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(inf.stream)
+    reps = 20
+    for _ in range(reps):
+        inf.forward(x)
+    e1.record(inf.stream)
+    e1.synchronize()
+    ms_inf = e0.elapsed_time(e1) / reps
+    dims = [mlp.IN, mlp.HIDDEN, mlp.HIDDEN, mlp.HIDDEN, mlp.HIDDEN, mlp.OUT]
+    flops = 2 * nb * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+    tflops = flops / (ms_inf * 1e-3) / 1e12
+    preds_per_hour = nb / (ms_inf * 1e-3) * 3600.0
+    out = {
+        "workload": f"MLP 37 -> 4 x 256 (GELU) -> 3, BF16 operands / FP32 accumulation (MFMA 32x32x16); "
+                    f"trained on {X.shape[0]} solver samples of {len(tr)} capillaries, "
+                    f"judged on {X2.shape[0]} of {len(te)} unseen capillaries",
+        "train_steps": args.train_steps, "train_batch": 4096, "ms_per_train_step": round(ms_train, 4),
+        "heldout_mse_standardised": {"drag": round(float(err[0]), 4), "lift": round(float(err[1]), 4),
+                                     "hazard": round(float(err[2]), 4)},
+        "mean_guess_mse_standardised": {"drag": round(float(base[0]), 4), "lift": round(float(base[1]), 4),
+                                        "hazard": round(float(base[2]), 4)},
+        "inference_batch": nb, "ms_per_inference_batch": round(ms_inf, 4),
+        "predictions_per_hour": round(preds_per_hour, 1),
+        "roofline": {"bound": "mfma", "kernel": "k_gemm (forward)", "achieved": round(tflops, 2),
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "algorithmic_flops_per_launch": flops},
+    }
+    if batched_out:
+        out["screening_gain_vs_batched_solver_runs"] = round(preds_per_hour / batched_out["runs_per_hour"], 1)
+    return out
+
+
 def roofline(m, storage_name, workload_name):
     traffic = counters(f"lattice_far_{storage_name}_{workload_name}")
     return {"bound": "hbm", "kernel": "k_lattice_far", "achieved": round(m["achieved"], 1), "peak": HBM_PEAK_GBS,
@@ -226,6 +288,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=400)
     ap.add_argument("--batched-warmup", type=int, default=100)
     ap.add_argument("--single-sample", type=int, default=8)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--harvest-steps", type=int, default=600)
+    ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates the HBM byte counters)")
@@ -291,6 +356,8 @@ def main():
                                "error_flags": f["error_flags"]}
     if not args.no_batched:
         out["batched"] = batched(args)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_section(args, out.get("batched"))
     if not args.no_cpu_baseline:
         base, ref = cpu_baseline(cfg, args.cpu_steps)
         out["cpu_baseline"] = base

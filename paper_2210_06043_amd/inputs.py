@@ -298,11 +298,14 @@ def c3_member(seed, k):
     ncell = int(rng.integers(1, 5))
     bodies = []
     xs = [(j + 0.5) * nx / ncell for j in range(ncell)]
+    types = []
     for j in range(ncell):
         n = int(rng.integers(128, 257))
         R = 0.5 * n / (2.0 * np.pi)
         cy = 0.5 * (ny - 1) + float(rng.uniform(-1.0, 1.0))
-        xy = biconcave(n, R, xs[j], cy, dense=20000) if rng.random() < 0.5 else circle(n, R, xs[j], cy)
+        bic = rng.random() < 0.5
+        types.append(1 if bic else 0)
+        xy = biconcave(n, R, xs[j], cy, dense=20000) if bic else circle(n, R, xs[j], cy)
         bodies.append(Body(DEFORMABLE, xy, None, ks=ks_cell, kb=0.1 * ks_cell, rho_r=1.0, tag=TAG_CELL))
     ar = float(rng.uniform(0.25, 1.0))
     rigid = rng.random() < 0.25
@@ -322,7 +325,8 @@ def c3_member(seed, k):
                   kr0=kf / KF_OVER_KR0, lb=ycr / 20.0, seed=sid)
     return Config(f"c3_{k}_{nx}x{ny}", nx, ny, tau, g, ux_init=poiseuille_profile(ny, g, tau), bodies=bodies,
                   bonds=[bonds], steps=20000,
-                  meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, ncell=ncell, n_bound0=20))
+                  meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, ncell=ncell, n_bound0=20,
+                            cell_types=types))
 
 
 def config_c3(seed=0, members=256):

@@ -98,6 +98,7 @@ class Surrogate:
         y = self.torch.empty((x.shape[0], OUT), dtype=self.torch.float32, device=self.device)
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         self._check(self.L.capib_mlp_forward(self.h, _P(x.data_ptr()), x.shape[0], _P(y.data_ptr())))
+        x.record_stream(self.stream)      # the caller's allocator must not reuse x before the kernels read it
         self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return y
 
@@ -108,6 +109,8 @@ class Surrogate:
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         self._check(self.L.capib_mlp_loss_grad(self.h, _P(x.data_ptr()), _P(t.data_ptr()), x.shape[0],
                                                C.byref(loss), g.ctypes.data_as(_fp) if g is not None else None))
+        x.record_stream(self.stream)
+        t.record_stream(self.stream)
         return loss.value, g
 
     def train_step(self, x, t, lr):
@@ -115,6 +118,8 @@ class Surrogate:
         x, t = self._dev(x, IN), self._dev(t, OUT)
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         self._check(self.L.capib_mlp_loss_grad(self.h, _P(x.data_ptr()), _P(t.data_ptr()), x.shape[0], None, None))
+        x.record_stream(self.stream)
+        t.record_stream(self.stream)
         self._check(self.L.capib_mlp_adam_step(self.h, float(lr)))
 
     def adam_step(self, lr):

@@ -251,7 +251,7 @@ def surrogate_section(args, batched_out):
                                         "hazard": round(float(base[2]), 4)},
         "inference_batch": nb, "ms_per_inference_batch": round(ms_inf, 4),
         "predictions_per_hour": round(preds_per_hour, 1),
-        "roofline": {"bound": "mfma", "kernel": "k_gemm (forward)", "achieved": round(tflops, 2),
+        "roofline": {"bound": "mfma", "kernel": "k_mlp_infer", "achieved": round(tflops, 2),
                      "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
                      "algorithmic_flops_per_launch": flops},

@@ -12,8 +12,9 @@
 //   weight gradient        FP32 partial sums over a slice of the batch,
 //                          reduced afterwards in a fixed order
 // Internally the input is padded to 64 features and the output to 64 rows
-// of W4 (zeros), batches to a multiple of 64 (zero rows masked out of the
-// loss), so every GEMM dimension is a multiple of the 64 x 64 block tile.
+// of W4 (zeros), batches to a multiple of 128 (zero rows masked out of the
+// loss), so every GEMM dimension is a multiple of its block tile (128 x 128
+// for the batch-sized products, 64 x 64 for the weight gradients).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -33,7 +34,7 @@ constexpr int KIN = CAPIB_MLP_IN, H = CAPIB_MLP_HIDDEN, KOUT = CAPIB_MLP_OUT;
 constexpr int K0P = 64;            // padded input width
 constexpr int NOP = 64;            // padded output rows of W4
 constexpr int NL = 5;              // layers
-constexpr int BT = 64;             // block tile (M and N)
+constexpr int BT = 128;            // batch padding: a multiple of the largest block tile
 constexpr int BK = 32;             // reduction step per stage
 constexpr int LDS_ROW = BK + 8;    // padded LDS row (80 bytes: 16-byte aligned rows, fewer bank conflicts)
 constexpr int KSPLIT = 32;         // batch slices of the weight-gradient GEMMs
@@ -46,6 +47,7 @@ constexpr int NR[NL] = {H, H, H, H, KOUT};
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 enum { EPI_GELU = 0, EPI_LINEAR = 1, EPI_DGELU = 2, EPI_PARTIAL = 3 };
 
@@ -63,73 +65,259 @@ struct GemmArgs {
     long long ldc;
 };
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by the rational-exponential approximation 7.1.26 of Abramowitz and
+// Stegun (|error| <= 1.5e-7, far below the bfloat16 rounding that follows
+// it), about a third of the instructions of a full-precision erff: the
+// GELU of every hidden activation is the inference kernel's vector work.
+__device__ __forceinline__ float erf_as(float x) {
+    const float a = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * a);
+    const float p = ((((1.061405429f * t - 1.453152027f) * t + 1.421413741f) * t - 0.284496736f) * t + 0.254829592f) * t;
+    const float y = 1.0f - p * __expf(-a * a);
+    return copysignf(y, x);
+}
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_prime(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-// One 64-row x 32-k tile of an operand into LDS as [row][k].  KC: the
-// operand is k-contiguous (16-byte loads along k); otherwise it is
-// row-contiguous (16-byte loads along the rows, scattered into LDS).
-template <bool KC>
-__device__ __forceinline__ void stage(__bf16 (*S)[LDS_ROW], const __bf16 *P, long long s_row, long long s_k, int r0,
-                                      int k0) {
-    const int t = threadIdx.x;
-    if (KC) {
-        const int row = t >> 2, kq = (t & 3) * 8;
-        const uint4 v = *(const uint4 *)(P + (long long)(r0 + row) * s_row + (k0 + kq));
-        *(uint4 *)&S[row][kq] = v;
-    } else {
-        const int k = t >> 3, rq = (t & 7) * 8;
-        const uint4 v = *(const uint4 *)(P + (long long)(r0 + rq) + (long long)(k0 + k) * s_k);
-        const __bf16 *e = (const __bf16 *)&v;
+// One ROWS x BK operand tile: global -> registers (NV 16-byte vectors per
+// thread) -> LDS as [row][k].  KC: the operand is k-contiguous (vectors
+// along k); otherwise it is row-contiguous (vectors along the rows,
+// scattered into LDS).
+template <int ROWS, bool KC>
+struct Tile {
+    static constexpr int NV = ROWS * BK / 8 / 256;
+    u32x4 v[NV];
+    __device__ __forceinline__ void load(const __bf16 *P, long long s_row, long long s_k, int r0, int k0) {
 #pragma unroll
-        for (int i = 0; i < 8; i++) S[rq + i][k] = e[i];
+        for (int u = 0; u < NV; u++) {
+            const int e = (int)threadIdx.x + 256 * u;
+            if constexpr (KC) {
+                const int row = e >> 2, kq = (e & 3) * 8;
+                v[u] = *(const u32x4 *)(P + (long long)(r0 + row) * s_row + (k0 + kq));
+            } else {
+                const int k = e / (ROWS / 8), rq = (e % (ROWS / 8)) * 8;
+                v[u] = *(const u32x4 *)(P + (long long)(r0 + rq) + (long long)(k0 + k) * s_k);
+            }
+        }
     }
-}
+    __device__ __forceinline__ void store(__bf16 (*S)[LDS_ROW]) const {
+#pragma unroll
+        for (int u = 0; u < NV; u++) {
+            const int e = (int)threadIdx.x + 256 * u;
+            if constexpr (KC) {
+                const int row = e >> 2, kq = (e & 3) * 8;
+                *(u32x4 *)&S[row][kq] = v[u];
+            } else {
+                const int k = e / (ROWS / 8), rq = (e % (ROWS / 8)) * 8;
+                const uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+                    S[rq + i][k] = __builtin_bit_cast(__bf16, (unsigned short)(w4[i >> 1] >> (16 * (i & 1))));
+            }
+        }
+    }
+};
 
-// 256 threads = 4 waves in a 2 x 2 arrangement, each wave one 32 x 32
-// accumulator of the 64 x 64 block tile.
-template <bool A_KC, bool B_KC, int EPI>
+// 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
+// (BM/2) x (BN/2) block of 32 x 32 FP32 accumulators.  Two LDS buffers:
+// the next k-slice is loaded into registers while the current one feeds
+// the matrix cores, then stored into the other buffer.
+template <int BM, int BN, bool A_KC, bool B_KC, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ __bf16 As[BT][LDS_ROW];
-    __shared__ __bf16 Bs[BT][LDS_ROW];
-    const int bm = blockIdx.x * BT, bn = blockIdx.y * BT;
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 32, FN = WN / 32;
+    __shared__ __bf16 As[2][BM][LDS_ROW];
+    __shared__ __bf16 Bs[2][BN][LDS_ROW];
+    const int bm = blockIdx.x * BM, bn = blockIdx.y * BN;
     const int kbeg = blockIdx.z * g.kchunk;
     const int kend = min(g.K, kbeg + g.kchunk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w & 1, wn = w >> 1;
-    floatx16 acc = {};
+    const long long a_row = A_KC ? g.a_m : 1, a_k = A_KC ? 1 : g.a_k;
+    const long long b_row = B_KC ? g.b_n : 1, b_k = B_KC ? 1 : g.b_k;
+    floatx16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++) acc[i][j] = floatx16{};
+    Tile<BM, A_KC> ta;
+    Tile<BN, B_KC> tb;
+    if (kbeg < kend) {
+        ta.load(g.A, a_row, a_k, bm, kbeg);
+        tb.load(g.B, b_row, b_k, bn, kbeg);
+        ta.store(As[0]);
+        tb.store(Bs[0]);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        stage<A_KC>(As, g.A, A_KC ? g.a_m : 1, A_KC ? 1 : g.a_k, bm, k0);
-        stage<B_KC>(Bs, g.B, B_KC ? g.b_n : 1, B_KC ? 1 : g.b_k, bn, k0);
-        __syncthreads();
+        const bool more = k0 + BK < kend;
+        if (more) {
+            ta.load(g.A, a_row, a_k, bm, k0 + BK);
+            tb.load(g.B, b_row, b_k, bn, k0 + BK);
+        }
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
-            // lane l supplies row (l mod 32) and k = 8 (l / 32) .. +7 of the 32 x 16 operand slices
-            const bf16x8 a = *(const bf16x8 *)&As[32 * wm + (lane & 31)][kk + 8 * (lane >> 5)];
-            const bf16x8 b = *(const bf16x8 *)&Bs[32 * wn + (lane & 31)][kk + 8 * (lane >> 5)];
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            // lane l supplies row (l mod 32) and k = 8 (l / 32) .. +7 of each 32 x 16 slice
+            // (named fragments: at most two per operand)
+            static_assert(FM <= 2 && FN <= 2, "at most 2 x 2 fragments per wave");
+            const int r = lane & 31, kq = kk + 8 * (lane >> 5);
+            const bf16x8 a0 = *(const bf16x8 *)&As[cur][WM * wm + r][kq];
+            const bf16x8 b0 = *(const bf16x8 *)&Bs[cur][WN * wn + r][kq];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            if constexpr (FN > 1) {
+                const bf16x8 b1 = *(const bf16x8 *)&Bs[cur][WN * wn + 32 + r][kq];
+                acc[0][FN - 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][FN - 1], 0, 0, 0);
+                if constexpr (FM > 1) {
+                    const bf16x8 a1 = *(const bf16x8 *)&As[cur][WM * wm + 32 + r][kq];
+                    acc[FM - 1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[FM - 1][0], 0, 0, 0);
+                    acc[FM - 1][FN - 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[FM - 1][FN - 1], 0, 0, 0);
+                }
+            } else if constexpr (FM > 1) {
+                const bf16x8 a1 = *(const bf16x8 *)&As[cur][WM * wm + 32 + r][kq];
+                acc[FM - 1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[FM - 1][0], 0, 0, 0);
+            }
+        }
+        if (more) {
+            ta.store(As[cur ^ 1]);
+            tb.store(Bs[cur ^ 1]);
         }
         __syncthreads();
+        cur ^= 1;
     }
-    // accumulator element i of lane l: row 8 (i / 4) + 4 (l / 32) + (i mod 4), column l mod 32
-    const int col = bn + 32 * wn + (lane & 31);
+    // accumulator element e of lane l: row 8 (e / 4) + 4 (l / 32) + (e mod 4), column l mod 32
 #pragma unroll
-    for (int i = 0; i < 16; i++) {
-        const int row = bm + 32 * wm + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const long long o = (long long)row * g.ldc + col;
-        const float v = acc[i];
-        if (EPI == EPI_GELU) {
-            const float z = v + g.bias[col];
-            g.cf[o] = z;
-            g.cb[o] = (__bf16)gelu(z);
-        } else if (EPI == EPI_LINEAR) {
-            g.cf[o] = v + g.bias[col];
-        } else if (EPI == EPI_DGELU) {
-            g.cb[o] = (__bf16)(v * gelu_prime(g.zin[o]));
-        } else {
-            g.cf[(long long)blockIdx.z * g.M * g.ldc + o] = v;
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++) {
+            const int col = bn + WN * wn + 32 * j + (lane & 31);
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const int row = bm + WM * wm + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                const long long o = (long long)row * g.ldc + col;
+                const float v = acc[i][j][e];
+                if (EPI == EPI_GELU) {
+                    const float z = v + g.bias[col];
+                    g.cf[o] = z;
+                    g.cb[o] = (__bf16)gelu(z);
+                } else if (EPI == EPI_LINEAR) {
+                    g.cf[o] = v + g.bias[col];
+                } else if (EPI == EPI_DGELU) {
+                    g.cb[o] = (__bf16)(v * gelu_prime(g.zin[o]));
+                } else {
+                    g.cf[(long long)blockIdx.z * g.M * g.ldc + o] = v;
+                }
+            }
+        }
+}
+
+// Inference in one kernel: a block takes 128 rows of the batch through all
+// five layers with the activations resident in LDS (bfloat16, written back
+// in place once every wave has read the layer's input), the weights read
+// from L2, and only the input and the 3 outputs touching HBM.  Waves in a
+// 2 x 2 arrangement: 64 rows x 128 columns (2 x 4 accumulators) of each
+// hidden layer; the output layer's first 32 rows of W4, 32 batch rows per
+// wave.  Same rounding points as the layer-by-layer path.
+constexpr int IB = 128;             // batch rows per block
+constexpr int ILD = H + 8;          // LDS row stride (bfloat16 elements)
+
+struct InferArgs {
+    const float *x;
+    int n;
+    const __bf16 *w[NL];            // bfloat16 weights [NP][KP]
+    const float *b[NL];             // FP32 biases
+    float *y;
+};
+
+// One hidden layer's products for a wave: 64 rows x 128 columns of
+// S (LDS, bfloat16) times W^T (global, [256][K]).  The weight fragments of
+// the next D k-steps are in flight while the current one is multiplied
+// (their L2 latency is several times one step's matrix work).
+template <int K>
+__device__ __forceinline__ void hidden_layer(const __bf16 (*S)[ILD], const __bf16 *W, floatx16 (&acc)[2][4], int wm,
+                                             int wn, int lane) {
+    constexpr int NI = K / 16, D = 4;
+    const int r = lane & 31, kh = 8 * (lane >> 5);
+    const __bf16 *w0 = W + (long long)(128 * wn + r) * K + kh;
+    bf16x8 pb[D][4];
+#pragma unroll
+    for (int p = 0; p < D && p < NI; p++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) pb[p][j] = *(const bf16x8 *)(w0 + (long long)32 * j * K + 16 * p);
+#pragma unroll
+    for (int it = 0; it < NI; it++) {
+        const int slot = it % D;
+        const bf16x8 b0 = pb[slot][0], b1 = pb[slot][1], b2 = pb[slot][2], b3 = pb[slot][3];
+        if (it + D < NI) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) pb[slot][j] = *(const bf16x8 *)(w0 + (long long)32 * j * K + 16 * (it + D));
+        }
+        const int kq = 16 * it + kh;
+        const bf16x8 a0 = *(const bf16x8 *)&S[64 * wm + r][kq];
+        const bf16x8 a1 = *(const bf16x8 *)&S[64 * wm + 32 + r][kq];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        acc[0][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b2, acc[0][2], 0, 0, 0);
+        acc[1][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b2, acc[1][2], 0, 0, 0);
+        acc[0][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b3, acc[0][3], 0, 0, 0);
+        acc[1][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b3, acc[1][3], 0, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_mlp_infer(InferArgs g) {
+    __shared__ __bf16 S[IB][ILD];
+    const int r0 = blockIdx.x * IB;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w & 1, wn = w >> 1, r = lane & 31;
+    for (int e = threadIdx.x; e < IB * K0P; e += 256) {
+        const int rr = e / K0P, c = e % K0P;
+        S[rr][c] = (__bf16)((r0 + rr < g.n && c < KIN) ? g.x[(long long)(r0 + rr) * KIN + c] : 0.0f);
+    }
+    __syncthreads();
+    for (int l = 0; l < NL - 1; l++) {
+        floatx16 acc[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = floatx16{};
+        if (l == 0)
+            hidden_layer<K0P>(S, g.w[0], acc, wm, wn, lane);
+        else
+            hidden_layer<H>(S, g.w[l], acc, wm, wn, lane);
+        __syncthreads();   // every wave has read this layer's input
+        const float *bias = g.b[l];
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int col = 128 * wn + 32 * j + r;
+                const float bc = bias[col];
+#pragma unroll
+                for (int e = 0; e < 16; e++) {
+                    const int row = 64 * wm + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                    S[row][col] = (__bf16)gelu(acc[i][j][e] + bc);
+                }
+            }
+        __syncthreads();
+    }
+    // output layer
+    const __bf16 *W4 = g.w[NL - 1];
+    floatx16 o = floatx16{};
+    for (int kk = 0; kk < H; kk += 16) {
+        const int kq = kk + 8 * (lane >> 5);
+        const bf16x8 a = *(const bf16x8 *)&S[32 * w + r][kq];
+        const bf16x8 b = *(const bf16x8 *)(W4 + (long long)r * H + kq);
+        o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, o, 0, 0, 0);
+    }
+    if (r < KOUT) {
+        const float bc = g.b[NL - 1][r];
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            const int row = r0 + 32 * w + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            if (row < g.n) g.y[(long long)row * KOUT + r] = o[e] + bc;
         }
     }
 }
@@ -140,13 +328,6 @@ __global__ void k_stage_input(const float *x, int n, int np, __bf16 *X0) {
     if (i >= (long long)np * K0P) return;
     const int r = (int)(i / K0P), c = (int)(i % K0P);
     X0[i] = (__bf16)((r < n && c < KIN) ? x[(long long)r * KIN + c] : 0.0f);
-}
-
-// y [n][3] <- Y [np][64]
-__global__ void k_gather_output(const float *Y, int n, float *y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * KOUT) return;
-    y[i] = Y[(long long)(i / KOUT) * NOP + (i % KOUT)];
 }
 
 // dY = bf16(2 (y - t) / (3 n)) on the valid rows and outputs (zero
@@ -268,9 +449,9 @@ capib_status fail(capib_mlp *m, capib_status s, const char *fmt, ...) {
 float *P(capib_mlp *m, size_t off) { return (float *)(m->base + off); }
 __bf16 *Bf(capib_mlp *m, size_t off) { return (__bf16 *)(m->base + off); }
 
-template <bool A_KC, bool B_KC, int EPI>
+template <int BM, int BN, bool A_KC, bool B_KC, int EPI>
 hipError_t gemm(capib_mlp *m, const GemmArgs &g, int nz) {
-    hipLaunchKernelGGL((k_gemm<A_KC, B_KC, EPI>), dim3(g.M / BT, g.N / BT, nz), dim3(256), 0, m->stream, g);
+    hipLaunchKernelGGL((k_gemm<BM, BN, A_KC, B_KC, EPI>), dim3(g.M / BM, g.N / BN, nz), dim3(256), 0, m->stream, g);
     return hipGetLastError();
 }
 
@@ -288,11 +469,11 @@ capib_status forward(capib_mlp *m, int np) {
         g.bias = P(m, m->off_p) + m->boff[l];
         if (l < NL - 1) {
             g.cf = P(m, m->off_z[l]); g.cb = Bf(m, m->off_a[l]); g.ldc = H;
-            MLPCHK(m, (gemm<true, true, EPI_GELU>(m, g, 1)));
+            MLPCHK(m, (gemm<128, 128, true, true, EPI_GELU>(m, g, 1)));
             in = Bf(m, m->off_a[l]);
         } else {
             g.cf = P(m, m->off_y); g.ldc = NOP;
-            MLPCHK(m, (gemm<true, true, EPI_LINEAR>(m, g, 1)));
+            MLPCHK(m, (gemm<128, 64, true, true, EPI_LINEAR>(m, g, 1)));
         }
     }
     return CAPIB_OK;
@@ -417,12 +598,15 @@ capib_status capib_mlp_forward(capib_mlp *m, const float *x, int32_t n, float *y
     capib_status s = check_batch(m, n);
     if (s) return s;
     if (!x || !y) return fail(m, CAPIB_E_ARG, "null array");
-    const int np = padded(n);
-    hipLaunchKernelGGL(k_stage_input, dim3((np * K0P + 255) / 256), dim3(256), 0, m->stream, x, n, np,
-                       Bf(m, m->off_x0));
-    MLPCHK(m, hipGetLastError());
-    if ((s = forward(m, np))) return s;
-    hipLaunchKernelGGL(k_gather_output, dim3((n * KOUT + 255) / 256), dim3(256), 0, m->stream, P(m, m->off_y), n, y);
+    InferArgs g{};
+    g.x = x;
+    g.n = n;
+    g.y = y;
+    for (int l = 0; l < NL; l++) {
+        g.w[l] = Bf(m, m->off_wb + 2 * m->wboff[l]);
+        g.b[l] = P(m, m->off_p) + m->boff[l];
+    }
+    hipLaunchKernelGGL(k_mlp_infer, dim3((n + IB - 1) / IB), dim3(256), 0, m->stream, g);
     MLPCHK(m, hipGetLastError());
     return CAPIB_OK;
 }
@@ -458,7 +642,7 @@ capib_status capib_mlp_loss_grad(capib_mlp *m, const float *x, const float *t, i
         g.B = ain; g.b_n = 1; g.b_k = KP[l];
         g.kchunk = kchunk;
         g.cf = P(m, m->off_part); g.ldc = KP[l];
-        MLPCHK(m, (gemm<false, false, EPI_PARTIAL>(m, g, nzz)));
+        MLPCHK(m, (gemm<64, 64, false, false, EPI_PARTIAL>(m, g, nzz)));
         const long long cnt = (long long)NP[l] * KP[l];
         hipLaunchKernelGGL(k_reduce_slices, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, m->stream,
                            P(m, m->off_part), nzz, cnt, P(m, m->off_g) + m->woff[l]);
@@ -479,7 +663,7 @@ capib_status capib_mlp_loss_grad(capib_mlp *m, const float *x, const float *t, i
         h.B = Bf(m, m->off_wb + 2 * m->wboff[l]); h.b_n = 1; h.b_k = KP[l];
         h.kchunk = NP[l];
         h.cb = dzn; h.zin = P(m, m->off_z[l - 1]); h.ldc = H;
-        MLPCHK(m, (gemm<true, false, EPI_DGELU>(m, h, 1)));
+        MLPCHK(m, (gemm<128, 128, true, false, EPI_DGELU>(m, h, 1)));
         dz = dzn;
         nb = H;
     }

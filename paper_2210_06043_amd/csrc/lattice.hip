@@ -28,13 +28,11 @@ __device__ __forceinline__ void tile_node(const Dev &d, int tile, int &i, int &j
     j = __builtin_amdgcn_readfirstlane(ty * TILE_Y + (int)(threadIdx.x / TILE_X));
 }
 
-// Collision and store of node (i, j) from its pulled deviations h (Eq. 1 with
-// the Guo term of Eq. 4), for the total force (Fx, Fy) = g + f_ib.
-template <typename T>
-__device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, int j, const float h[9], float uref,
-                                                float Fx, float Fy) {
-    T *__restrict__ B = (T *)d.pop[par ^ 1];
-    const long long node = (long long)j * d.pitch + i;
+// Collision of one node from its pulled deviations h (Eq. 1 with the Guo
+// term of Eq. 4), for the total force (Fx, Fy) = g + f_ib: the post-collision
+// deviations out[9].
+__device__ __forceinline__ void collide_core(const Dev &d, const float h[9], float uref, float Fx, float Fy,
+                                             float out[9]) {
     // moments of the streamed deviations: drho, and j - u_ref x
     const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
@@ -55,7 +53,6 @@ __device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, in
     const float om = d.omega, om1 = 1.0f - d.omega, fc = d.fc;
     const float uF = ux * Fx + uy * Fy;
     const float fb = -3.0f * uF;                 // 3 (-u).F
-    float out[9];
     {
         const float w = 4.0f / 9.0f;
         out[0] = om1 * h[0] + om * E(0.0f, 0.0f, w) + fc * w * fb;
@@ -76,6 +73,16 @@ __device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, in
     CAPIB_DIR(7, -1.0f, -1.0f, 1.0f / 36.0f)
     CAPIB_DIR(8, 1.0f, -1.0f, 1.0f / 36.0f)
 #undef CAPIB_DIR
+}
+
+// Collision and store of node (i, j).
+template <typename T>
+__device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, int j, const float h[9], float uref,
+                                                float Fx, float Fy) {
+    T *__restrict__ B = (T *)d.pop[par ^ 1];
+    const long long node = (long long)j * d.pitch + i;
+    float out[9];
+    collide_core(d, h, uref, Fx, Fy, out);
     const long long Q = d.qstride;
 #pragma unroll
     for (int q = 0; q < 9; q++) B[q * Q + node] = stpop<T>(out[q], d.scale);

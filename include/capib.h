@@ -205,7 +205,7 @@ capib_status capib_set_interactions(capib_ctx *ctx, double rep_prefactor, double
  * membranes are swept, so the caller sees ordinary stream order.          */
 capib_status capib_step(capib_ctx *ctx, int32_t nsteps);
 
-/* Replays the steps through captured HIP graphs of two steps when
+/* Replays the steps through captured HIP graphs of 16 (and 2) steps when
  * enable != 0 (results identical to plain launches).                      */
 capib_status capib_set_graph(capib_ctx *ctx, int32_t enable);
 

@@ -36,6 +36,11 @@ void split(double x, float &hi, float &lo) {
 
 }  // namespace
 
+// steps captured in one HIP graph (even: a graph starts and ends on the
+// same population parity); more steps per graph amortise the launch of the
+// graph itself
+constexpr int GRAPH_STEPS = 16;
+
 struct capib_ctx {
     capib_lattice lat;
     hipStream_t stream = nullptr;
@@ -71,10 +76,11 @@ struct capib_ctx {
     long long tsteps = 0;
     // graphs
     bool use_graph = false;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};    // GRAPH_STEPS steps, by starting parity
+    hipGraphExec_t gexec2[2] = {nullptr, nullptr};   // two steps
     // fork/join of the immersed-boundary phase with the far lattice tiles
     hipStream_t side = nullptr, cap_side = nullptr;
-    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork[GRAPH_STEPS] = {}, ev_join[GRAPH_STEPS] = {};
     bool marks_valid = false;
 };
 
@@ -222,8 +228,10 @@ static void fill_dev(capib_ctx *c) {
 }
 
 static void drop_graphs(capib_ctx *c) {
-    for (int p = 0; p < 2; p++)
+    for (int p = 0; p < 2; p++) {
         if (c->gexec[p]) { (void)hipGraphExecDestroy(c->gexec[p]); c->gexec[p] = nullptr; }
+        if (c->gexec2[p]) { (void)hipGraphExecDestroy(c->gexec2[p]); c->gexec2[p] = nullptr; }
+    }
 }
 
 static capib_status need_ws(capib_ctx *c) {
@@ -662,7 +670,7 @@ static capib_status ensure_streams(capib_ctx *c) {
     if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     if (!c->cap_side) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_side, hipStreamNonBlocking));
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < GRAPH_STEPS; k++) {
         if (!c->ev_fork[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork[k], hipEventDisableTiming));
         if (!c->ev_join[k]) HIPCHK(c, hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
     }
@@ -682,7 +690,7 @@ static capib_status ensure_marks(capib_ctx *c) {
 // One step: the far tiles of the lattice sweep run on the main stream while
 // the interpolation and membrane kernels run on the side stream; the near
 // tiles follow the join.  main/side are the streams to enqueue on, k selects
-// the event pair (so that two steps can be captured in one graph).
+// the event pair (so that several steps can be captured in one graph).
 static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_t side, int k) {
     HIPCHK(c, hipEventRecord(c->ev_fork[k], main));
     HIPCHK(c, hipStreamWaitEvent(side, c->ev_fork[k], 0));
@@ -695,17 +703,16 @@ static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_
     return CAPIB_OK;
 }
 
-static capib_status make_graph(capib_ctx *c, int par) {
+static capib_status make_graph(capib_ctx *c, int par, int nsteps, hipGraphExec_t *out) {
     capib_status s = ensure_streams(c);
     if (s) return s;
     hipGraph_t g;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    s = one_step(c, par, c->cap_stream, c->cap_side, 0);
-    if (!s) s = one_step(c, par ^ 1, c->cap_stream, c->cap_side, 1);
+    for (int k = 0; k < nsteps && !s; k++) s = one_step(c, par ^ (k & 1), c->cap_stream, c->cap_side, k);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (s) return s;
     if (e != hipSuccess) return fail(c, CAPIB_E_HIP, "graph capture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->gexec[par], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(c, CAPIB_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
     return CAPIB_OK;
@@ -749,9 +756,14 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
     }
     int t = 0;
     if (c->use_graph) {
-        for (; t + 2 <= nsteps; t += 2) {
-            if (!c->gexec[c->par] && (s = make_graph(c, c->par))) return s;
+        for (; t + GRAPH_STEPS <= nsteps; t += GRAPH_STEPS) {
+            if (!c->gexec[c->par] && (s = make_graph(c, c->par, GRAPH_STEPS, &c->gexec[c->par]))) return s;
             HIPCHK(c, hipGraphLaunch(c->gexec[c->par], c->stream));
+            c->step += GRAPH_STEPS;
+        }
+        for (; t + 2 <= nsteps; t += 2) {
+            if (!c->gexec2[c->par] && (s = make_graph(c, c->par, 2, &c->gexec2[c->par]))) return s;
+            HIPCHK(c, hipGraphLaunch(c->gexec2[c->par], c->stream));
             c->step += 2;
         }
     }
@@ -1021,7 +1033,7 @@ void capib_destroy(capib_ctx *c) {
     if (c->bound) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < GRAPH_STEPS; k++) {
         if (c->ev_fork[k]) (void)hipEventDestroy(c->ev_fork[k]);
         if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
     }

@@ -35,15 +35,6 @@ __device__ __forceinline__ void df_add2(float &ah, float &al, float bh, float bl
     ah = h;
 }
 
-// Marks a tile as near for the step of parity p: flag and list entry, once
-// (the flag's exchange decides which caller appends it).
-__device__ __forceinline__ void mark_tile(const Dev &d, int p, int tile) {
-    if (atomicExch(&d.tnear[p][tile], 1) == 0) {
-        const int slot = atomicAdd(&d.ncount[p], 1);
-        d.nlist[p][slot] = tile;
-    }
-}
-
 // Spread record of vertex g at x^n: the stencil of the velocity coupling and
 // the force dV (U - u*) to spread; the near-tile sweep gathers these records
 // (spreading as a gather: no atomics, sums in vertex order).
@@ -60,7 +51,8 @@ __device__ __forceinline__ void write_spread(const Dev &d, const Band &B, int g,
     d.sp_f[g] = make_float2(fx, fy);
 }
 
-__global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
+template <int PAR, bool ENS>
+__global__ __launch_bounds__(BT) void k_body(Dev d) {
     __shared__ float sxh[MAXV_BODY], sxl[MAXV_BODY], syh[MAXV_BODY], syl[MAXV_BODY];
     __shared__ float slen[MAXV_BODY], snlx[MAXV_BODY], snly[MAXV_BODY];
     __shared__ float snvx[MAXV_BODY], snvy[MAXV_BODY], sbend[MAXV_BODY];
@@ -77,10 +69,10 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
     const int b = blockIdx.x, tid = threadIdx.x;
     const BodyParams P = d.bp[b];
     const int4 rg = b < ARG_BODIES ? d.brange[b] : make_int4(P.vstart, P.n, P.site_start, P.n_sites);
-    const int n = rg.y, v0 = rg.x, ns = rg.w, s0 = rg.z, npar = par ^ 1;
+    const int n = rg.y, v0 = rg.x, ns = rg.w, s0 = rg.z, npar = PAR ^ 1;
     const long long step = *d.counter - 1;
     const bool deform = P.kind == DEFORMABLE, rigid = P.kind == RIGID;
-    const Band BB = band_of(d, P.band);
+    const Band BB = band_at<ENS>(d, P.band);
     // rigid state (centroid displacement, angle, velocities), read up front
     const float4 RS0 = *(const float4 *)&d.bs[b].dcxh;   // dcxh, dcxl, dcyh, dcyl
     const float4 RS1 = *(const float4 *)&d.bs[b].phih;   // phih, phil, ucx, ucy
@@ -96,8 +88,8 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         const int v = tid + k * BT;
         if (v >= n) continue;
         const int g = v0 + v;
-        rxh[k] = d.pxh[par][g]; rxl[k] = d.pxl[par][g];
-        ryh[k] = d.pyh[par][g]; ryl[k] = d.pyl[par][g];
+        rxh[k] = d.pxh[PAR][g]; rxl[k] = d.pxl[PAR][g];
+        ryh[k] = d.pyh[PAR][g]; ryl[k] = d.pyl[PAR][g];
         rl0[k] = d.l0[g]; rth0[k] = d.th0[g];
         rus[k] = d.ustar[g];
         rpr[k] = d.probe4[g];
@@ -129,7 +121,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         rsf[k] = d.s_frac[g]; rsah[k] = d.s_anh[g]; rsal[k] = d.s_anl[g];
     }
     if (tid < P.band_nb && tid < MAX_BOX)
-        for (int c = 0; c < 4; c++) sbox[tid][c] = d.bs[P.band_b0 + tid].bbox[par][c];
+        for (int c = 0; c < 4; c++) sbox[tid][c] = d.bs[P.band_b0 + tid].bbox[PAR][c];
 #pragma unroll
     for (int k = 0; k < VPT; k++) {
         const int v = tid + k * BT;
@@ -222,7 +214,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
         // contiguously from P.band_b0
         const float L = (float)BB.nx, cut = d.rep_cut, cut2 = cut * cut;
         float ob[4];
-        for (int q = 0; q < 4; q++) ob[q] = b - P.band_b0 < MAX_BOX ? sbox[b - P.band_b0][q] : d.bs[b].bbox[par][q];
+        for (int q = 0; q < 4; q++) ob[q] = b - P.band_b0 < MAX_BOX ? sbox[b - P.band_b0][q] : d.bs[b].bbox[PAR][q];
         const int cend = P.band_b0 + P.band_nb;
         for (int c0 = P.band_b0; c0 < cend; c0 += 64) {
             // candidate bodies, one lane each; every wave forms the same mask
@@ -230,7 +222,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
             bool close = false;
             if (cl < cend && cl != b) {
                 float bq[4];
-                for (int q = 0; q < 4; q++) bq[q] = cl - P.band_b0 < MAX_BOX ? sbox[cl - P.band_b0][q] : d.bs[cl].bbox[par][q];
+                for (int q = 0; q < 4; q++) bq[q] = cl - P.band_b0 < MAX_BOX ? sbox[cl - P.band_b0][q] : d.bs[cl].bbox[PAR][q];
                 float dcc = 0.5f * (ob[0] + ob[1]) - 0.5f * (bq[0] + bq[1]);
                 dcc -= L * rintf(dcc / L);
                 // NaN boxes fail both distance tests and are scanned
@@ -242,12 +234,12 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
                 const int c = c0 + __ffsll((long long)mm) - 1;
                 mm &= mm - 1ull;
                 float bb[4];
-                for (int q = 0; q < 4; q++) bb[q] = c - P.band_b0 < MAX_BOX ? sbox[c - P.band_b0][q] : d.bs[c].bbox[par][q];
+                for (int q = 0; q < 4; q++) bb[q] = c - P.band_b0 < MAX_BOX ? sbox[c - P.band_b0][q] : d.bs[c].bbox[PAR][q];
                 const int cs = d.bp[c].vstart, cn = d.bp[c].n;
                 __syncthreads();   // the staging arrays are free
                 for (int u = tid; u < cn; u += BT) {
-                    sqxh[u] = d.pxh[par][cs + u]; sqxl[u] = d.pxl[par][cs + u];
-                    sqyh[u] = d.pyh[par][cs + u]; sqyl[u] = d.pyl[par][cs + u];
+                    sqxh[u] = d.pxh[PAR][cs + u]; sqxl[u] = d.pxl[PAR][cs + u];
+                    sqyh[u] = d.pyh[PAR][cs + u]; sqyl[u] = d.pyl[PAR][cs + u];
                 }
                 __syncthreads();
 #pragma unroll
@@ -483,17 +475,18 @@ __global__ __launch_bounds__(BT) void k_body(Dev d, int par) {
 }
 
 // Near tiles of the current positions (before the first step, after a
-// checkpoint is loaded or membranes are added).  The flags and the count of
-// parity par must be clear.
+// checkpoint is loaded or membranes are added): flags, vertex ranges and
+// list of parity par, which must be clear.
 __global__ __launch_bounds__(256) void k_mark(Dev d, int par) {
     const int v = blockIdx.x * 256 + threadIdx.x;
     if (v >= d.nverts) return;
     int tl[9];
-    const Band B = band_of(d, d.vband[v]);
+    const int info = d.vinfo[v];
+    const Band B = band_of(d, info >> 1);
     const int c = stencil_tiles(d, B, d.pxh[par][v], d.pxl[par][v], d.pyh[par][v], d.pyl[par][v], tl);
     for (int q = 0; q < c; q++) {
-        mark_tile(d, par, tl[q]);
-        note_cover(d, par, tl[q], v);
+        note_cover(d, par, tl[q], v, info & 1);
+        if (atomicExch(&d.tnear[par][tl[q]], 1) == 0) d.nlist[par][atomicAdd(&d.ncount[par], 1)] = tl[q];
     }
 }
 
@@ -510,7 +503,12 @@ hipError_t launch_body(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hip
         if (e1) return hipEventRecord(e1, st);
         return hipSuccess;
     }
-    hipExtLaunchKernelGGL(k_body, dim3(d.nbodies), dim3(BT), 0, st, e0, e1, 0, d, par);
+    // instantiated per step parity and kind of lattice
+    const bool ens = d.nbands > 1;
+    if (par)
+        hipExtLaunchKernelGGL(ens ? k_body<1, true> : k_body<1, false>, dim3(d.nbodies), dim3(BT), 0, st, e0, e1, 0, d);
+    else
+        hipExtLaunchKernelGGL(ens ? k_body<0, true> : k_body<0, false>, dim3(d.nbodies), dim3(BT), 0, st, e0, e1, 0, d);
     return hipGetLastError();
 }
 

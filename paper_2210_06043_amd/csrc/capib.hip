@@ -52,7 +52,7 @@ struct capib_ctx {
     size_t ws_bytes = 0;
     size_t off_pop[2]{}, off_sp = 0, off_near = 0, off_red = 0, off_macro = 0, off_rowref = 0, off_scal = 0;
     size_t off_ib = 0, ib_bytes = 0;
-    size_t off_bp = 0, off_bs = 0, off_vbody = 0, off_pos[8]{}, off_dxm = 0, off_dym = 0, off_x0[4]{};
+    size_t off_bp = 0, off_bs = 0, off_vnext = 0, off_pos[8]{}, off_dxm = 0, off_dym = 0, off_x0[4]{};
     size_t off_r0x = 0, off_r0y = 0, off_l0 = 0, off_th0 = 0, off_ustar = 0, off_probe = 0, off_force = 0;
     size_t off_target = 0, off_srange = 0, off_shost = 0, off_sstate = 0, off_sorig = 0, off_sfrac = 0;
     size_t off_sanh = 0, off_sanl = 0;
@@ -67,7 +67,8 @@ struct capib_ctx {
     int nbands = 1, band_rows = 0;
     std::vector<int> band_nx;
     std::vector<int> band_b0, band_nb;   // first body and body count per band
-    size_t off_band = 0, off_vband = 0;
+    size_t off_band = 0, off_vinfo = 0, off_live = 0;
+    int nlive = 0;
     std::string err = "no error";
     // timing
     bool timing = false;
@@ -100,11 +101,9 @@ static capib_status fail(capib_ctx *c, capib_status s, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail((c), CAPIB_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-// near-tile bookkeeping: flags and lists of both parities, the two list
-// counts (in a 64-byte slot), and the vertex-index range per tile and parity
-static size_t near_bytes(const capib_ctx *c) {
-    return 8 * (size_t)c->ntx * c->nty * 4 + 64;
-}
+// near-tile bookkeeping, per parity: the two vertex ranges of every tile
+// (16 bytes), the flags, the list; then the two list counts
+static size_t near_bytes(const capib_ctx *c) { return 2 * 24 * (size_t)c->ntx * c->nty + 64; }
 
 static void layout(capib_ctx *c) {
     const capib_lattice &L = c->lat;
@@ -117,6 +116,7 @@ static void layout(capib_ctx *c) {
     c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
     c->off_rowref = o; o = align256(o + (size_t)c->band_rows * 16 * 4);
     c->off_band = o; o = align256(o + (size_t)c->nbands * 12);   // widths, then (first body, count)
+    c->off_live = o; o = align256(o + (size_t)c->ntx * c->nty * 4);
     c->off_scal = o; o = align256(o + 64);
     // spread records (rewritten every step, not checkpointed): origin, x and y
     // weights, force per vertex
@@ -127,8 +127,8 @@ static void layout(capib_ctx *c) {
     c->off_ib = o;
     c->off_bp = o; o = align256(o + B * sizeof(BodyParams));
     c->off_bs = o; o = align256(o + B * sizeof(BodyState));
-    c->off_vbody = o; o = align256(o + V * 4);
-    c->off_vband = o; o = align256(o + V * 4);
+    c->off_vnext = o; o = align256(o + V * 4);
+    c->off_vinfo = o; o = align256(o + V * 4);
     for (int k = 0; k < 8; k++) { c->off_pos[k] = o; o = align256(o + V * 4); }
     c->off_dxm = o; o = align256(o + V * 4);
     c->off_dym = o; o = align256(o + V * 4);
@@ -176,15 +176,13 @@ static void fill_dev(capib_ctx *c) {
     {
         const size_t nt = (size_t)c->ntx * c->nty;
         int *nb = (int *)(b + c->off_near);
-        d.tnear[0] = nb;
-        d.tnear[1] = nb + nt;
-        d.nlist[0] = nb + 2 * nt;
-        d.nlist[1] = nb + 3 * nt;
-        d.ncount = nb + 4 * nt;
-        d.tvlo[0] = nb + 4 * nt + 16;
-        d.tvlo[1] = nb + 5 * nt + 16;
-        d.tvhi[0] = nb + 6 * nt + 16;
-        d.tvhi[1] = nb + 7 * nt + 16;
+        d.tv[0] = nb;
+        d.tv[1] = nb + 4 * nt;
+        d.tnear[0] = nb + 8 * nt;
+        d.tnear[1] = nb + 9 * nt;
+        d.nlist[0] = nb + 10 * nt;
+        d.nlist[1] = nb + 11 * nt;
+        d.ncount = nb + 12 * nt;
     }
     d.red = (double *)(b + c->off_red);
     d.macro = (float *)(b + c->off_macro);
@@ -194,7 +192,9 @@ static void fill_dev(capib_ctx *c) {
     d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites; d.nbands = c->nbands;
     d.band_nx = (const int *)(b + c->off_band);
     d.band_bodies = (const int2 *)(b + c->off_band + 4 * (size_t)c->nbands);
-    d.vband = (int *)(b + c->off_vband);
+    d.live = (const int *)(b + c->off_live);
+    d.nlive = c->nlive;
+    d.vinfo = (int *)(b + c->off_vinfo);
     for (int k = 0; k < ARG_BODIES; k++) {
         if (k < c->nbodies) {
             const BodyHost &bh = c->bodies[k];
@@ -205,7 +205,7 @@ static void fill_dev(capib_ctx *c) {
     }
     d.bp = (BodyParams *)(b + c->off_bp);
     d.bs = (BodyState *)(b + c->off_bs);
-    d.vbody = (int *)(b + c->off_vbody);
+    d.vnext = (int *)(b + c->off_vnext);
     for (int p = 0; p < 2; p++) {
         d.pxh[p] = (float *)(b + c->off_pos[4 * p + 0]);
         d.pxl[p] = (float *)(b + c->off_pos[4 * p + 1]);
@@ -371,7 +371,17 @@ capib_status capib_bind_workspace(capib_ctx *c, void *ptr, size_t bytes) {
     c->band_nb.assign(c->nbands, 0);
     HIPCHK(c, hipMemsetAsync(c->base, 0, c->ws_bytes, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return h2d(c, c->off_band, c->band_nx.data(), (size_t)c->nbands * 4);
+    capib_status s = h2d(c, c->off_band, c->band_nx.data(), (size_t)c->nbands * 4);
+    if (s) return s;
+    // the tiles that hold fluid nodes, in index order
+    std::vector<int> live;
+    for (int t = 0; t < c->ntx * c->nty; t++) {
+        const int row = (t / c->ntx) * TILE_Y, x0 = (t % c->ntx) * TILE_X;
+        if (row < c->lat.ny && x0 < c->band_nx[row / c->band_rows]) live.push_back(t);
+    }
+    c->nlive = (int)live.size();
+    c->d.nlive = c->nlive;
+    return h2d(c, c->off_live, live.data(), live.size() * 4);
 }
 
 capib_status capib_init_flow(capib_ctx *c, const double *ux) {
@@ -521,10 +531,12 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     BodyState bs{};
     double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
     std::vector<float> xh(n), xl(n), yh(n), yl(n), r0x(n), r0y(n), fl0(n), fth0(n);
-    std::vector<int> vb(n, b), vbd(n, band);
+    std::vector<int> vnx(n), vinf(n);
     for (int v = 0; v < n; v++) {
         split(xy[2 * v], xh[v], xl[v]);
         split(xy[2 * v + 1], yh[v], yl[v]);
+        vnx[v] = v0 + (v + 1) % n;
+        vinf[v] = 2 * band + (v >= n / 2);
         r0x[v] = (float)(xy[2 * v] - cx);
         r0y[v] = (float)(xy[2 * v + 1] - cy);
         fl0[v] = (float)l0[v];
@@ -540,8 +552,8 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     const int pp = c->par;
     if ((s = h2d(c, c->off_bp + b * sizeof(BodyParams), &bp, sizeof bp))) return s;
     if ((s = h2d(c, c->off_bs + b * sizeof(BodyState), &bs, sizeof bs))) return s;
-    if ((s = h2d(c, c->off_vbody + fo, vb.data(), n * 4))) return s;
-    if ((s = h2d(c, c->off_vband + fo, vbd.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_vnext + fo, vnx.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_vinfo + fo, vinf.data(), n * 4))) return s;
     // the band's earlier bodies see one more neighbour
     for (int e = c->band_b0[band]; e < b; e++)
         if ((s = h2d(c, c->off_bp + e * sizeof(BodyParams) + offsetof(BodyParams, band_nb), &bp.band_nb, 4))) return s;
@@ -886,9 +898,11 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     out->tiles = c->ntx * c->nty;
     out->near_tiles = 0;
     if (c->marks_valid) {
-        int cnt = 0;
-        if ((s = d2h(c, &cnt, c->off_near + 4 * (size_t)c->ntx * c->nty * 4 + 4 * (size_t)c->par, 4))) return s;
-        out->near_tiles = cnt;
+        // the flags of the current parity
+        std::vector<int> flags(nblk);
+        const size_t off = c->off_near + 32 * nblk + 4 * nblk * c->par;
+        if ((s = d2h(c, flags.data(), off, 4 * nblk))) return s;
+        for (int f : flags) out->near_tiles += f != 0;
     }
     if (cnt != c->step) return fail(c, CAPIB_E_STATE, "device step counter %lld != %lld", cnt, c->step);
     if (err) return fail(c, CAPIB_E_UNSTABLE, "device error flags 0x%x", err);

@@ -72,18 +72,30 @@ struct Dev {
     // Near tiles of a step: the 64x4 tiles that the stencils of the vertex
     // positions x^n cover, i.e. the only tiles that can receive spread force
     // in step n.  Double-buffered by step parity: tnear[p][tile] is 1 for a
-    // near tile, nlist[p][0 .. ncount[p]) lists them.  The vertices whose
-    // stencils cover a tile lie in the global index range [vlo, vhi] with
-    // tvhi = vhi + 1 and tvlo = nverts - vlo (0 = none; both kept by max).
+    // near tile.  The covering vertices are recorded as two global index
+    // ranges, one for the vertices in the first half of their membrane's
+    // list and one for the second half (so that a tile under both ends of a
+    // closed membrane does not span the whole membrane): tv[p][4 tile + 2 h]
+    // = nverts - lo_h and tv[p][4 tile + 2 h + 1] = hi_h + 1 (0 = none; both
+    // kept by max).  The near sweep clears both after reading them.
     int *tnear[2];
+    int *tv[2];
+    // On a large lattice the near sweep runs over a list of the near tiles
+    // instead of over every tile: nlist[p][0 .. ncount[p]), appended once
+    // per tile by the marking (whose flag exchange decides which caller
+    // appends it).
     int *nlist[2];
     int *ncount;
-    int *tvlo[2], *tvhi[2];
     // immersed boundary
     int nbodies, nverts, nsites, nbands;
     const int *band_nx;             // width of each band
+    // tiles that hold fluid nodes of some band (with several bands of
+    // different widths, the tiles beyond a band's width hold none), in
+    // index order; the far sweep runs over these
+    const int *live;
+    int nlive;
     const int2 *band_bodies;        // (first body, body count) of each band
-    int *vband;                     // band of each vertex
+    int *vinfo;                     // 2 band + (1 in the second half of its membrane's list)
     // (first vertex, vertices, first site, sites) of the first ARG_BODIES
     // bodies, passed with the arguments so that the membrane kernel can
     // issue its loads without a round trip for its parameters
@@ -91,7 +103,7 @@ struct Dev {
     float rep_pref, rep_cut, rep_dmin, probe;
     BodyParams *bp;
     BodyState *bs;
-    int *vbody;
+    int *vnext;                     // next vertex of the same membrane (cyclic)
     float *pxh[2], *pxl[2], *pyh[2], *pyl[2];   // vertex positions, parity-indexed
     float *dxm, *dym;                           // previous increment x^n - x^{n-1}
     float *x0h, *x0l, *y0h, *y0l;               // positions at t = 0
@@ -124,16 +136,32 @@ struct Dev {
 struct Band {
     int nx, y0, ny;
 };
-__device__ __forceinline__ Band band_of(const Dev &d, int k) { return Band{d.band_nx[k], k * d.band_rows, d.band_rows}; }
+// (a single band is the whole lattice: no load of its width)
+__device__ __forceinline__ Band band_of(const Dev &d, int k) {
+    if (d.nbands == 1) return Band{d.nx, 0, d.band_rows};
+    return Band{d.band_nx[k], k * d.band_rows, d.band_rows};
+}
 __device__ __forceinline__ Band band_of_row(const Dev &d, int j) { return band_of(d, j / d.band_rows); }
+// The same with the kind of lattice fixed at compile time (ENS: several
+// bands), for the kernels of the step: no load and no branch for a single
+// band.
+template <bool ENS>
+__device__ __forceinline__ Band band_at(const Dev &d, int k) {
+    if (!ENS) return Band{d.nx, 0, d.band_rows};
+    return Band{d.band_nx[k], k * d.band_rows, d.band_rows};
+}
+template <bool ENS>
+__device__ __forceinline__ Band band_at_row(const Dev &d, int j) {
+    return band_at<ENS>(d, ENS ? j / d.band_rows : 0);
+}
 
 // Workgroup index -> tile index such that each XCD (workgroups are dealt
 // round-robin to the 8 XCDs) receives one contiguous range of tiles, so that
 // neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
-    int q = nb >> 3, r = nb & 7;
-    int x = b & 7, local = b >> 3;
-    return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+    // XCD x holds tiles [x q + min(x, r), (x + 1) q + min(x + 1, r))
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) {
@@ -278,11 +306,13 @@ __device__ __forceinline__ float pull_dev(const Dev &d, const T *__restrict__ A,
     return add_rowref(d, j - B.y0, h);
 }
 
-// Records that the stencil of vertex v (global index) covers the tile, for
-// the step of parity p: widens the tile's vertex range.
-__device__ __forceinline__ void note_cover(const Dev &d, int p, int tile, int v) {
-    atomicMax(&d.tvhi[p][tile], v + 1);
-    atomicMax(&d.tvlo[p][tile], d.nverts - v);
+// Records that the stencil of vertex v (global index; list half h of its
+// membrane) covers the tile, for the step of parity p: widens the tile's
+// vertex range of that half.
+__device__ __forceinline__ void note_cover(const Dev &d, int p, int tile, int v, int h) {
+    int *t = d.tv[p] + 4 * tile + 2 * h;
+    atomicMax(t + 1, v + 1);
+    atomicMax(t, d.nverts - v);
 }
 
 // Equilibrium of Eq. (2) as a deviation from the row reference, with

@@ -64,24 +64,24 @@ __device__ __forceinline__ void node_moments(const Dev &d, const T *A, int i, in
     out[3] = -d.fc * pyy;
 }
 
-__global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d, int par) {
+template <int PAR, bool ENS>
+__global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *d.counter += 1;            // steps started
-        d.ncount[par ^ 1] = 0;      // the near-tile sweep lists next step's near tiles
+        d.ncount[PAR ^ 1] = 0;      // this step's near sweep lists the next step's near tiles
     }
     const int gid = blockIdx.x * INTERP_THREADS + threadIdx.x;
     const int p = gid >> 4, lane = gid & 15;
     if (p >= 2 * d.nverts) return;    // whole groups of 16 leave together
     const bool probe = p >= d.nverts;
     const int v = probe ? p - d.nverts : p;
-    const int b = d.vbody[v];
-    const int vs = d.bp[b].vstart, n = d.bp[b].n;
-    const Band B = band_of(d, d.vband[v]);
-    const int vn = (v + 1 - vs == n) ? vs : v + 1;
-    float xh = d.pxh[par][v], xl = d.pxl[par][v], yh = d.pyh[par][v], yl = d.pyl[par][v];
+    // the loads that need only v, issued together
+    const int info = d.vinfo[v], vn = d.vnext[v];
+    float xh = d.pxh[PAR][v], xl = d.pxl[PAR][v], yh = d.pyh[PAR][v], yl = d.pyl[PAR][v];
+    const Band B = band_at<ENS>(d, info >> 1);
     if (probe) {
-        const float tx = (d.pxh[par][vn] - xh) + (d.pxl[par][vn] - xl);
-        const float ty = (d.pyh[par][vn] - yh) + (d.pyl[par][vn] - yl);
+        const float tx = (d.pxh[PAR][vn] - xh) + (d.pxl[PAR][vn] - xl);
+        const float ty = (d.pyh[PAR][vn] - yh) + (d.pyl[PAR][vn] - yl);
         const float len = sqrtf(tx * tx + ty * ty);
         xl += 0.5f * tx + d.probe * (ty / len);
         yl += 0.5f * ty - d.probe * (tx / len);
@@ -102,9 +102,9 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d, int par) {
         const int i = wrapi(ix0 + a, B.nx);
         float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (d.storage == 0)
-            node_moments<float>(d, (const float *)d.pop[par], i, B.y0 + j, B, probe, m);
+            node_moments<float>(d, (const float *)d.pop[PAR], i, B.y0 + j, B, probe, m);
         else
-            node_moments<_Float16>(d, (const _Float16 *)d.pop[par], i, B.y0 + j, B, probe, m);
+            node_moments<_Float16>(d, (const _Float16 *)d.pop[PAR], i, B.y0 + j, B, probe, m);
         acc[0] = W * m[0];
         acc[1] = W * m[1];
         if (probe) {
@@ -287,7 +287,15 @@ hipError_t launch_interp(const Dev &d, int par, hipStream_t st, hipEvent_t e0, h
     const int pts = 2 * d.nverts;
     int nb = (pts * 16 + INTERP_THREADS - 1) / INTERP_THREADS;
     if (nb < 1) nb = 1;
-    hipExtLaunchKernelGGL(k_interp, dim3(nb), dim3(INTERP_THREADS), 0, st, e0, e1, 0, d, par);
+    const bool ens = d.nbands > 1;
+    // instantiated per step parity and kind of lattice (no dependent loads
+    // for the parity-indexed pointers and the band)
+    if (par)
+        hipExtLaunchKernelGGL(ens ? k_interp<1, true> : k_interp<1, false>, dim3(nb), dim3(INTERP_THREADS), 0, st,
+                              e0, e1, 0, d);
+    else
+        hipExtLaunchKernelGGL(ens ? k_interp<0, true> : k_interp<0, false>, dim3(nb), dim3(INTERP_THREADS), 0, st,
+                              e0, e1, 0, d);
     return hipGetLastError();
 }
 

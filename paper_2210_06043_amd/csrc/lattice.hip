@@ -89,19 +89,20 @@ __device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, in
 }
 
 // Far tiles: every tile of the lattice except this step's near tiles, in
-// XCD-contiguous order.  Runs concurrently with the immersed-boundary phase.
-template <typename T>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int par) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (d.tnear[par][tile]) return;
+// XCD-contiguous order (with several bands: every tile that holds fluid
+// nodes).  Runs concurrently with the immersed-boundary phase.
+template <typename T, int PAR, bool ENS>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d) {
+    const int tile = ENS ? d.live[xcd_tile(blockIdx.x, d.nlive)] : xcd_tile(blockIdx.x, d.ntx * d.nty);
+    if (d.tnear[PAR][tile]) return;
     int i, j;
     tile_node(d, tile, i, j);
     if (j >= d.ny) return;
-    const Band B = band_of_row(d, j);   // wave-uniform
+    const Band B = band_at_row<ENS>(d, j);   // wave-uniform
     if (i >= B.nx) return;
     float h[9];
-    const float uref = pull_dev<T>(d, (const T *)d.pop[par], i, j, B, h);
-    lattice_collide<T>(d, par, i, j, h, uref, d.gx, d.gy);
+    const float uref = pull_dev<T>(d, (const T *)d.pop[PAR], i, j, B, h);
+    lattice_collide<T>(d, PAR, i, j, h, uref, d.gx, d.gy);
 }
 
 // Does a 4-wide stencil starting at o (wrapped into [0, n)) meet the range
@@ -112,144 +113,215 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
     return r < w || r + 3 >= n;
 }
 
-// Near tiles of this step, after the membrane kernel: grid-stride over the
-// list.  Spreading (Sec. 2.2) is done here as a gather.  The marking of the
-// tile recorded the index range of the vertices whose stencils cover it;
-// the workgroup loads the spread records of that range (256 at a time),
+// Near tiles of this step, after the membrane kernel: one workgroup per
+// tile of the lattice, which leaves at once unless the tile is near; the
+// flag, the covering vertex ranges and the band's width are loaded
+// together, so a near tile starts its gather after one round trip.
+// Spreading (Sec. 2.2) is done here as a gather: the workgroup loads the
+// spread records of the tile's vertex ranges (512 per pass, two per thread),
 // compacts the covering vertices into LDS in index order, and every node
 // sums W f over them in that order, so the result does not depend on
-// scheduling.  The node's populations are loaded before the gather so that
-// their latency overlaps it.  The tile's flag and range are cleared for the
-// next step of the same parity.
+// scheduling.  The node's populations are loaded with the first records so
+// that their latency overlaps the gather.  The tile's flag and ranges are
+// cleared for the next step of the same parity.
 //
 // The first nmark workgroups of the launch instead mark the near tiles of
 // the next step: the tiles under the stencils of x^{n+1}, which the
-// membrane kernel has written.  One (vertex, stencil tile) pair per lane,
-// all flag exchanges in flight together, one list-counter update per wave.
+// membrane kernel has written.  One (vertex, stencil tile) pair per lane:
+// the flag store and the two range updates, all in flight together.
 constexpr int MARK_VERTS = LAT_THREADS / 9;   // vertices per marking workgroup
 
-__device__ __forceinline__ void mark_next(const Dev &d, int npar, int mb) {
+template <int NPAR, bool ENS, bool LIST>
+__device__ __forceinline__ void mark_next(const Dev &d, int mb) {
     const int v = mb * MARK_VERTS + (int)threadIdx.x / 9, q = (int)threadIdx.x % 9;
     bool fresh = false;
     int tile = 0;
     if ((int)threadIdx.x < MARK_VERTS * 9 && v < d.nverts) {
         int tl[9];
-        const Band B = band_of(d, d.vband[v]);
-        const int c = stencil_tiles(d, B, d.pxh[npar][v], d.pxl[npar][v], d.pyh[npar][v], d.pyl[npar][v], tl);
+        const int info = d.vinfo[v];
+        const Band B = band_at<ENS>(d, info >> 1);
+        const int c = stencil_tiles(d, B, d.pxh[NPAR][v], d.pxl[NPAR][v], d.pyh[NPAR][v], d.pyl[NPAR][v], tl);
 #pragma unroll
         for (int r = 0; r < 9; r++)
             if (r == q) tile = tl[r];
         if (q < c) {
-            note_cover(d, npar, tile, v);
-            fresh = atomicExch(&d.tnear[npar][tile], 1) == 0;
+            note_cover(d, NPAR, tile, v, info & 1);
+            if (LIST)
+                fresh = atomicExch(&d.tnear[NPAR][tile], 1) == 0;
+            else
+                d.tnear[NPAR][tile] = 1;
         }
     }
-    const unsigned long long m = __ballot(fresh);
-    if (m) {
-        const int lane = threadIdx.x & 63, lead = __ffsll((long long)m) - 1;
-        int base = 0;
-        if (lane == lead) base = atomicAdd(&d.ncount[npar], __popcll(m));
-        base = __shfl(base, lead);
-        if (fresh) d.nlist[npar][base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
+    if (LIST) {
+        // one list-counter update per wave
+        const unsigned long long m = __ballot(fresh);
+        if (m) {
+            const int lane = threadIdx.x & 63, lead = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == lead) base = atomicAdd(&d.ncount[NPAR], __popcll(m));
+            base = __shfl(base, lead);
+            if (fresh) d.nlist[NPAR][base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
+        }
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int par, int nmark) {
-    if ((int)blockIdx.x < nmark) {
-        mark_next(d, par ^ 1, blockIdx.x);
-        return;
+// Spread record of the covering candidate at position u of a tile's vertex
+// ranges (u < n0: lo0 + u, else lo1 + u - n0); hit if its stencil meets the
+// tile.
+struct Cand {
+    int2 o;
+    float4 wx, wy;
+    float2 f;
+    bool hit;
+};
+
+__device__ __forceinline__ Cand load_cand(const Dev &d, const Band &B, int u, int nv, int lo0, int n0, int lo1, int x0,
+                                          int y0, int tw, int th) {
+    Cand c;
+    c.hit = false;
+    c.o = make_int2(0, 0);
+    c.wx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    c.wy = c.wx;
+    c.f = make_float2(0.0f, 0.0f);
+    if (u < nv) {
+        const int v = u < n0 ? lo0 + u : lo1 + (u - n0);
+        c.o = d.sp_org[v];
+        c.wx = d.sp_wx[v];
+        c.wy = d.sp_wy[v];
+        c.f = d.sp_f[v];
+        const bool hx = meets_periodic(c.o.x, x0, tw, B.nx);
+        const bool hy = d.walls ? (c.o.y + 3 >= y0 && c.o.y < y0 + th)
+                                : meets_periodic(c.o.y - B.y0, y0 - B.y0, th, B.ny);
+        c.hit = hx && hy;
     }
+    return c;
+}
+
+// One near tile: its covering vertex ranges r (as stored by the marking)
+// and its band B.
+template <typename T, int PAR>
+__device__ __forceinline__ void near_tile(const Dev &d, int tile, const int4 r, const Band &B) {
     constexpr int NW = LAT_THREADS / 64;
     // staged covering vertices: x weights (normalised), y weights, and
     // (origin x, origin y, fx, fy) with the origin's bits in the float slots
-    __shared__ float4 srec[LAT_THREADS + 4][3];
-    __shared__ int scount[NW];
-    const int bid = blockIdx.x - nmark, nblk = gridDim.x - nmark;
+    __shared__ float4 srec[2 * LAT_THREADS + 4][3];
+    __shared__ int scount[2 * NW];
+    const int tyi = tile / d.ntx, txi = tile - tyi * d.ntx;
+    const int x0 = txi * TILE_X, y0 = tyi * TILE_Y;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
-    const int cnt = d.ncount[par];
-    for (int k = bid; k < cnt; k += nblk) {
-        const int tile = d.nlist[par][k];
-        const int tyi = tile / d.ntx, txi = tile - tyi * d.ntx;
-        const int x0 = txi * TILE_X, y0 = tyi * TILE_Y;
-        const Band B = band_of_row(d, y0);   // tiles never straddle bands
-        const int tw = min(TILE_X, B.nx - x0), th = min(TILE_Y, B.y0 + B.ny - y0);
-        int i, j;
-        tile_node(d, tile, i, j);
-        const bool valid = i < B.nx && j < B.y0 + B.ny;
-        float h[9];
-        if (valid) pull9<T>(d, (const T *)d.pop[par], i, j, B, h);
-        const int vhi = d.tvhi[par][tile] - 1, vlo = d.nverts - d.tvlo[par][tile];
-
-        float ax = 0.0f, ay = 0.0f;
-        for (int c0 = vlo; c0 <= vhi; c0 += LAT_THREADS) {
-            const int v = c0 + (int)threadIdx.x;
-            bool hit = false;
-            int2 o = make_int2(0, 0);
-            float4 wx = make_float4(0.0f, 0.0f, 0.0f, 0.0f), wy = wx;
-            float2 f = make_float2(0.0f, 0.0f);
-            if (v <= vhi) {
-                o = d.sp_org[v];
-                wx = d.sp_wx[v];
-                wy = d.sp_wy[v];
-                f = d.sp_f[v];
-                const bool hx = meets_periodic(o.x, x0, tw, B.nx);
-                const bool hy = d.walls ? (o.y + 3 >= y0 && o.y < y0 + th)
-                                        : meets_periodic(o.y - B.y0, y0 - B.y0, th, B.ny);
-                hit = hx && hy;
-            }
-            const unsigned long long m = __ballot(hit);
-            if (lane == 0) scount[wv] = __popcll(m);
-            __syncthreads();
-            int slot = __popcll(m & below), tot = 0;
+    // the ranges [lo, hi] of the two halves (hi = -1: none) in index order,
+    // merged when they overlap; n0 + n1 candidates
+    int lo0 = d.nverts - r.x, hi0 = r.y - 1, lo1 = d.nverts - r.z, hi1 = r.w - 1;
+    if (hi1 >= 0 && (hi0 < 0 || lo1 < lo0)) {
+        const int a = lo0, b = hi0;
+        lo0 = lo1; hi0 = hi1; lo1 = a; hi1 = b;
+    }
+    if (hi1 >= 0 && lo1 <= hi0) {
+        hi0 = max(hi0, hi1);
+        hi1 = -1;
+    }
+    const int n0 = hi0 - lo0 + 1, nv = n0 + (hi1 >= 0 ? hi1 - lo1 + 1 : 0);
+    const int tw = min(TILE_X, B.nx - x0), th = min(TILE_Y, B.y0 + B.ny - y0);
+    int i, j;
+    tile_node(d, tile, i, j);
+    const bool valid = i < B.nx && j < B.y0 + B.ny;
+    float h[9];
+    if (valid) pull9<T>(d, (const T *)d.pop[PAR], i, j, B, h);
+    if (threadIdx.x == 0) {
+        d.tnear[PAR][tile] = 0;
+        ((int4 *)d.tv[PAR])[tile] = make_int4(0, 0, 0, 0);
+    }
+    float ax = 0.0f, ay = 0.0f;
+    for (int c0 = 0; c0 < nv; c0 += 2 * LAT_THREADS) {
+        const Cand ca = load_cand(d, B, c0 + (int)threadIdx.x, nv, lo0, n0, lo1, x0, y0, tw, th);
+        const Cand cb = load_cand(d, B, c0 + LAT_THREADS + (int)threadIdx.x, nv, lo0, n0, lo1, x0, y0, tw, th);
+        const unsigned long long ma = __ballot(ca.hit), mb = __ballot(cb.hit);
+        if (lane == 0) {
+            scount[wv] = __popcll(ma);
+            scount[NW + wv] = __popcll(mb);
+        }
+        __syncthreads();
+        int sa = __popcll(ma & below), sb = __popcll(mb & below), ta = 0, tot = 0;
 #pragma unroll
-            for (int w = 0; w < NW; w++) {
-                slot += (w < wv) ? scount[w] : 0;
-                tot += scount[w];
-            }
-            if (hit) {
-                srec[slot][0] = wx;
-                srec[slot][1] = wy;
-                srec[slot][2] = make_float4(__int_as_float(o.x), __int_as_float(o.y), f.x, f.y);
-            }
-            // pad to a multiple of four with records that cover no node
-            if ((int)threadIdx.x < ((tot + 3) & ~3) - tot) {
-                const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                srec[tot + threadIdx.x][0] = z;
-                srec[tot + threadIdx.x][1] = z;
-                srec[tot + threadIdx.x][2] = make_float4(__int_as_float(-(1 << 30)), __int_as_float(-(1 << 30)), 0.0f, 0.0f);
-            }
-            __syncthreads();
-            // every lane reads the same record (LDS broadcast); four at a time
-            for (int q = 0; q < tot; q += 4) {
+        for (int w = 0; w < NW; w++) {
+            sa += (w < wv) ? scount[w] : 0;
+            sb += (w < wv) ? scount[NW + w] : 0;
+            ta += scount[w];
+            tot += scount[NW + w];
+        }
+        sb += ta;
+        tot += ta;
+        if (ca.hit) {
+            srec[sa][0] = ca.wx;
+            srec[sa][1] = ca.wy;
+            srec[sa][2] = make_float4(__int_as_float(ca.o.x), __int_as_float(ca.o.y), ca.f.x, ca.f.y);
+        }
+        if (cb.hit) {
+            srec[sb][0] = cb.wx;
+            srec[sb][1] = cb.wy;
+            srec[sb][2] = make_float4(__int_as_float(cb.o.x), __int_as_float(cb.o.y), cb.f.x, cb.f.y);
+        }
+        // pad to a multiple of four with records that cover no node
+        if ((int)threadIdx.x < ((tot + 3) & ~3) - tot) {
+            const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            srec[tot + threadIdx.x][0] = z;
+            srec[tot + threadIdx.x][1] = z;
+            srec[tot + threadIdx.x][2] = make_float4(__int_as_float(-(1 << 30)), __int_as_float(-(1 << 30)), 0.0f, 0.0f);
+        }
+        __syncthreads();
+        // every lane reads the same record (LDS broadcast); four at a time
+        for (int q = 0; q < tot; q += 4) {
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const float4 RX = srec[q + u][0], RY = srec[q + u][1], RC = srec[q + u][2];
-                    int a = i - __float_as_int(RC.x);
-                    if (a < 0) a += B.nx;
-                    int e = j - __float_as_int(RC.y);
-                    if (!d.walls && e < 0) e += B.ny;
-                    if ((unsigned)a < 4u && (unsigned)e < 4u) {
-                        const float wa = a == 0 ? RX.x : a == 1 ? RX.y : a == 2 ? RX.z : RX.w;
-                        const float we = e == 0 ? RY.x : e == 1 ? RY.y : e == 2 ? RY.z : RY.w;
-                        const float w = wa * we;
-                        ax += w * RC.z;
-                        ay += w * RC.w;
-                    }
+            for (int u = 0; u < 4; u++) {
+                const float4 RX = srec[q + u][0], RY = srec[q + u][1], RC = srec[q + u][2];
+                int a = i - __float_as_int(RC.x);
+                if (a < 0) a += B.nx;
+                int e = j - __float_as_int(RC.y);
+                if (!d.walls && e < 0) e += B.ny;
+                if ((unsigned)a < 4u && (unsigned)e < 4u) {
+                    const float wa = a == 0 ? RX.x : a == 1 ? RX.y : a == 2 ? RX.z : RX.w;
+                    const float we = e == 0 ? RY.x : e == 1 ? RY.y : e == 2 ? RY.z : RY.w;
+                    const float w = wa * we;
+                    ax += w * RC.z;
+                    ay += w * RC.w;
                 }
             }
-            __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            d.tnear[par][tile] = 0;
-            d.tvhi[par][tile] = 0;
-            d.tvlo[par][tile] = 0;
-        }
-        if (valid) {
-            const float uref = add_rowref(d, j - B.y0, h);
-            lattice_collide<T>(d, par, i, j, h, uref, d.gx + ax, d.gy + ay);
-        }
+        __syncthreads();
+    }
+    if (valid) {
+        const float uref = add_rowref(d, j - B.y0, h);
+        lattice_collide<T>(d, PAR, i, j, h, uref, d.gx + ax, d.gy + ay);
+    }
+}
+
+template <typename T, int PAR, bool ENS, bool LIST>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int nmark) {
+    if ((int)blockIdx.x < nmark) {
+        mark_next<PAR ^ 1, ENS, LIST>(d, blockIdx.x);
+        return;
+    }
+    const int bid = blockIdx.x - nmark;
+    if (!LIST) {
+        // one workgroup per tile: a tile is near if and only if one of its
+        // ranges is non-empty; the band's width takes part in the test so
+        // that its load is issued with the ranges'
+        const int4 r = ((const int4 *)d.tv[PAR])[bid];
+        const Band B = band_at_row<ENS>(d, (bid / d.ntx) * TILE_Y);   // tiles never straddle bands
+        if ((r.y | r.w) == 0 || B.nx <= 0) return;
+        near_tile<T, PAR>(d, bid, r, B);
+        return;
+    }
+    // grid-stride over the list of near tiles; the first entry is loaded
+    // with the count (the grid has at most one list workgroup per tile)
+    int tile = d.nlist[PAR][bid];
+    const int cnt = d.ncount[PAR];
+    for (int k = bid; k < cnt; k += gridDim.x - nmark) {
+        if (k != bid) tile = d.nlist[PAR][k];
+        const int4 r = ((const int4 *)d.tv[PAR])[tile];
+        const Band B = band_at_row<ENS>(d, (tile / d.ntx) * TILE_Y);
+        near_tile<T, PAR>(d, tile, r, B);
     }
 }
 
@@ -341,28 +413,60 @@ __global__ __launch_bounds__(256) void k_diag_final(Dev d, int nblk) {
 
 // ---- host launchers ---------------------------------------------------------------
 
+// The step kernels are instantiated per step parity and per kind of
+// lattice (one band or several), so that their parity-indexed pointers and
+// the band geometry need no dependent loads.
+template <typename T, int P, bool E>
+static void go_far(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((k_lattice_far<T, P, E>), dim3(E ? d.nlive : d.ntx * d.nty), dim3(LAT_THREADS), 0, st, e0,
+                          e1, 0, d);
+}
+template <typename T>
+static void far_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const bool ens = d.nbands > 1;
+    if (par) ens ? go_far<T, 1, true>(d, st, e0, e1) : go_far<T, 1, false>(d, st, e0, e1);
+    else ens ? go_far<T, 0, true>(d, st, e0, e1) : go_far<T, 0, false>(d, st, e0, e1);
+}
+
 hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    const int nb = d.ntx * d.nty;
     if (d.storage == 0)
-        hipExtLaunchKernelGGL(k_lattice_far<float>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+        far_of<float>(d, par, st, e0, e1);
     else
-        hipExtLaunchKernelGGL(k_lattice_far<_Float16>, dim3(nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par);
+        far_of<_Float16>(d, par, st, e0, e1);
     return hipGetLastError();
 }
 
-hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    // about one workgroup per near tile (a membrane's near tiles number a
-    // fraction of its vertices); the grid-stride loop covers any count
+// Grid: the marking workgroups, then one workgroup per tile, or on a large
+// lattice (where workgroups that leave at once would take several rounds of
+// the machine) about one per near tile, which number a fraction of the
+// vertices; the list's grid-stride loop covers any count.
+constexpr int LIST_MIN_TILES = 8192;
+
+template <typename T, int P, bool E>
+static void go_near(const Dev &d, int nmark, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nt = d.ntx * d.nty;
-    const int want = d.nverts / 2 > 1024 ? d.nverts / 2 : 1024;
-    const int nb = nt < want ? nt : want;
-    const int nmark = (d.nverts + MARK_VERTS - 1) / MARK_VERTS;
+    if (nt < LIST_MIN_TILES) {
+        hipExtLaunchKernelGGL((k_lattice_near<T, P, E, false>), dim3(nmark + nt), dim3(LAT_THREADS), 0, st, e0, e1, 0,
+                              d, nmark);
+    } else {
+        const int want = d.nverts / 4 > 1024 ? d.nverts / 4 : 1024;
+        hipExtLaunchKernelGGL((k_lattice_near<T, P, E, true>), dim3(nmark + (nt < want ? nt : want)),
+                              dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark);
+    }
+}
+template <typename T>
+static void near_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const bool ens = d.nbands > 1;
+    const int nm = (d.nverts + MARK_VERTS - 1) / MARK_VERTS;
+    if (par) ens ? go_near<T, 1, true>(d, nm, st, e0, e1) : go_near<T, 1, false>(d, nm, st, e0, e1);
+    else ens ? go_near<T, 0, true>(d, nm, st, e0, e1) : go_near<T, 0, false>(d, nm, st, e0, e1);
+}
+
+hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (d.storage == 0)
-        hipExtLaunchKernelGGL(k_lattice_near<float>, dim3(nmark + nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, par,
-                              nmark);
+        near_of<float>(d, par, st, e0, e1);
     else
-        hipExtLaunchKernelGGL(k_lattice_near<_Float16>, dim3(nmark + nb), dim3(LAT_THREADS), 0, st, e0, e1, 0, d,
-                              par, nmark);
+        near_of<_Float16>(d, par, st, e0, e1);
     return hipGetLastError();
 }
 

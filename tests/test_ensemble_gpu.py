@@ -158,3 +158,30 @@ def test_member_samples_match_the_oracle():
             assert int(row[5]) == first[k] + ref["cell"]
             assert abs(row[3] - ref["r"]) < 1e-5 * max(1.0, ref["r"]) and abs(row[4] - ref["dp"]) < 1e-5
         assert abs(row[6] - ref["shear"]) < 1e-4 * abs(ref["shear"]) + 1e-12
+
+
+def test_large_ensemble_list_sweep_equals_single_runs():
+    """45 members (the four small ones eleven times over and an empty
+    channel 2048 wide, which sets the tile columns to 32): 270 tile rows of
+    32, over 8192 tiles, so the near sweep runs over the list of near tiles
+    rather than over every tile, and the far sweep over the tiles that hold
+    fluid.  Members still equal bit for bit their single-lattice runs
+    (which sweep every tile) after 120 steps, advanced by graphs."""
+    small = inputs.config_ensemble_small()
+    cfgs = [small[k % 4] for k in range(44)] + [inputs.config_tiny(nx=2048, ny=24, seed=7, kinds=())]
+    sim, first = capib.from_ensemble(cfgs, storage=capib.FP32_SHIFTED, graph=True)
+    d0 = sim.diagnostics()
+    assert d0["tiles"] == 32 * 270 and d0["tiles"] >= 8192
+    steps = 120
+    sim.step(steps)
+    d = sim.diagnostics()
+    assert d["error_flags"] == 0 and d["step"] == steps
+    say(f"large ensemble: {d['tiles']} tiles, {d['near_tiles']} near")
+    for k in (0, 1, 2, 3, 41, 43):
+        cfg = cfgs[k]
+        g = gpu_sim(cfg)
+        g.step(steps)
+        _, ux, uy = g.macro()
+        assert np.array_equal(_member_fields(sim, k, cfg), np.stack([ux, uy])), k
+        for b in range(len(cfg.bodies)):
+            assert np.array_equal(sim.vertices(first[k] + b), g.vertices(b)), (k, b)

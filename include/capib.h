@@ -265,9 +265,11 @@ capib_status capib_load(capib_ctx *ctx, const void *host_buf, size_t bytes);
  * capib_step runs the kernels of each step in sequence on the caller's
  * stream, each launched with a start/stop event pair stamped at its own
  * start and end, and synchronises at its end.  capib_read_timing returns the
- * summed milliseconds of {interpolation, membrane phase, lattice sweep of
- * the far tiles, lattice sweep of the near tiles} (4 doubles) and the number
- * of steps timed, then resets the sums.                                     */
+ * summed milliseconds of {interpolation, membrane phase, far-tile sweep,
+ * lattice sweep after the membrane phase} (4 doubles) and the number of
+ * steps timed, then resets the sums.  The far-tile sweep runs (beside the
+ * membrane phase) only on lattices of 8192 tiles of 64 x 4 nodes or more;
+ * on smaller ones the last sweep covers every tile and the third sum is 0. */
 capib_status capib_set_timing(capib_ctx *ctx, int32_t enable);
 capib_status capib_read_timing(capib_ctx *ctx, double *ms4, int64_t *steps);
 

@@ -67,6 +67,9 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
     __shared__ float srig[8];
 
     const int b = blockIdx.x, tid = threadIdx.x;
+    // the next step's near tiles are listed from zero by this step's sweep
+    // (the interpolation has read the old count)
+    if (b == 0 && tid == 0) d.ncount[PAR ^ 1] = 0;
     const BodyParams P = d.bp[b];
     const int4 rg = b < ARG_BODIES ? d.brange[b] : make_int4(P.vstart, P.n, P.site_start, P.n_sites);
     const int n = rg.y, v0 = rg.x, ns = rg.w, s0 = rg.z, npar = PAR ^ 1;

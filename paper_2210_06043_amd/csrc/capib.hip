@@ -699,11 +699,19 @@ static capib_status ensure_marks(capib_ctx *c) {
     return CAPIB_OK;
 }
 
-// One step: the far tiles of the lattice sweep run on the main stream while
-// the interpolation and membrane kernels run on the side stream; the near
-// tiles follow the join.  main/side are the streams to enqueue on, k selects
-// the event pair (so that several steps can be captured in one graph).
+// One step.  On a small lattice: interpolation, membrane kernel and the
+// sweep of every tile, in sequence on the main stream.  On a large lattice
+// the far tiles run on the main stream while the interpolation and membrane
+// kernels run on the side stream, and the sweep of the near tiles follows
+// the join.  main/side are the streams to enqueue on, k selects the event
+// pair (so that several steps can be captured in one graph).
 static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_t side, int k) {
+    if (!lattice_split(c->d)) {
+        HIPCHK(c, launch_interp(c->d, par, main));
+        HIPCHK(c, launch_body(c->d, par, main));
+        HIPCHK(c, launch_lattice_sweep(c->d, par, main));
+        return CAPIB_OK;
+    }
     HIPCHK(c, hipEventRecord(c->ev_fork[k], main));
     HIPCHK(c, hipStreamWaitEvent(side, c->ev_fork[k], 0));
     HIPCHK(c, launch_interp(c->d, par, side));
@@ -711,7 +719,7 @@ static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_
     HIPCHK(c, launch_lattice_far(c->d, par, main));
     HIPCHK(c, hipEventRecord(c->ev_join[k], side));
     HIPCHK(c, hipStreamWaitEvent(main, c->ev_join[k], 0));
-    HIPCHK(c, launch_lattice_near(c->d, par, main));
+    HIPCHK(c, launch_lattice_sweep(c->d, par, main));
     return CAPIB_OK;
 }
 
@@ -749,8 +757,8 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
             hipEvent_t *e = &c->ev[8 * t];
             HIPCHK(c, launch_interp(c->d, c->par, c->stream, e[0], e[1]));
             HIPCHK(c, launch_body(c->d, c->par, c->stream, e[2], e[3]));
-            HIPCHK(c, launch_lattice_far(c->d, c->par, c->stream, e[4], e[5]));
-            HIPCHK(c, launch_lattice_near(c->d, c->par, c->stream, e[6], e[7]));
+            if (lattice_split(c->d)) HIPCHK(c, launch_lattice_far(c->d, c->par, c->stream, e[4], e[5]));
+            HIPCHK(c, launch_lattice_sweep(c->d, c->par, c->stream, e[6], e[7]));
             c->par ^= 1;
             c->step++;
         }
@@ -758,6 +766,7 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
         for (int t = 0; t < nsteps; t++) {
             hipEvent_t *e = &c->ev[8 * t];
             for (int k = 0; k < 4; k++) {
+                if (k == 2 && !lattice_split(c->d)) continue;   // no far-tile sweep
                 float ms = 0;
                 HIPCHK(c, hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]));
                 c->ms[k] += ms;
@@ -898,11 +907,10 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     out->tiles = c->ntx * c->nty;
     out->near_tiles = 0;
     if (c->marks_valid) {
-        // the flags of the current parity
-        std::vector<int> flags(nblk);
-        const size_t off = c->off_near + 32 * nblk + 4 * nblk * c->par;
-        if ((s = d2h(c, flags.data(), off, 4 * nblk))) return s;
-        for (int f : flags) out->near_tiles += f != 0;
+        // tiles of the current parity with a non-empty covering vertex range
+        std::vector<int> tv(4 * nblk);
+        if ((s = d2h(c, tv.data(), c->off_near + 16 * nblk * c->par, 16 * nblk))) return s;
+        for (size_t t = 0; t < nblk; t++) out->near_tiles += (tv[4 * t + 1] | tv[4 * t + 3]) != 0;
     }
     if (cnt != c->step) return fail(c, CAPIB_E_STATE, "device step counter %lld != %lld", cnt, c->step);
     if (err) return fail(c, CAPIB_E_UNSTABLE, "device error flags 0x%x", err);

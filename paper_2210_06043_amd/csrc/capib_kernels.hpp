@@ -11,8 +11,10 @@ namespace capib {
 // (hipExtLaunchKernelGGL), so that the elapsed time is the kernel alone.
 hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr,
                               hipEvent_t e1 = nullptr);
-hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr,
-                               hipEvent_t e1 = nullptr);
+hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr,
+                                hipEvent_t e1 = nullptr);
+// whether the far tiles are swept beside the membrane phase (large lattices)
+bool lattice_split(const Dev &d);
 hipError_t launch_mark(const Dev &d, int par, hipStream_t st);
 hipError_t launch_macro(const Dev &d, int par, hipStream_t st);
 hipError_t launch_init_flow(const Dev &d, int par, hipStream_t st);

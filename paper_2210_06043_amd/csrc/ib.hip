@@ -65,12 +65,7 @@ __device__ __forceinline__ void node_moments(const Dev &d, const T *A, int i, in
 }
 
 template <int PAR, bool ENS>
-__global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *d.counter += 1;            // steps started
-        d.ncount[PAR ^ 1] = 0;      // this step's near sweep lists the next step's near tiles
-    }
-    const int gid = blockIdx.x * INTERP_THREADS + threadIdx.x;
+__device__ __forceinline__ void interp_point(const Dev &d, int gid) {
     const int p = gid >> 4, lane = gid & 15;
     if (p >= 2 * d.nverts) return;    // whole groups of 16 leave together
     const bool probe = p >= d.nverts;
@@ -126,6 +121,25 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d) {
             d.probe4[v] = make_float4(acc[0], acc[1], acc[2], acc[3]);
         else
             d.ustar[v] = make_float2(acc[0], acc[1]);
+    }
+}
+
+// The interpolation, and the clearing of the flags and vertex ranges of the
+// previous step's near tiles (parity PAR ^ 1), whose sweep has used them,
+// before this step's sweep marks that parity again.  That list holds at
+// most 9 tiles per vertex, fewer than the 32 threads per vertex of this
+// grid, so one entry per thread covers it; its entries are loaded with the
+// interpolation's first loads.
+template <int PAR, bool ENS>
+__global__ __launch_bounds__(INTERP_THREADS) void k_interp(Dev d) {
+    const int gid = blockIdx.x * INTERP_THREADS + threadIdx.x;
+    const int cnt = d.ncount[PAR ^ 1];
+    const int prev = gid < d.ntx * d.nty ? d.nlist[PAR ^ 1][gid] : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *d.counter += 1;   // steps started
+    interp_point<PAR, ENS>(d, gid);
+    if (gid < cnt) {
+        d.tnear[PAR ^ 1][prev] = 0;
+        ((int4 *)d.tv[PAR ^ 1])[prev] = make_int4(0, 0, 0, 0);
     }
 }
 

@@ -88,12 +88,13 @@ __device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, in
     for (int q = 0; q < 9; q++) B[q * Q + node] = stpop<T>(out[q], d.scale);
 }
 
-// Far tiles: every tile of the lattice except this step's near tiles, in
-// XCD-contiguous order (with several bands: every tile that holds fluid
-// nodes).  Runs concurrently with the immersed-boundary phase.
+// A far tile: one that is not near in this step (its flag is clear), swept
+// with the body force alone.  b indexes the far-tile workgroups, mapped in
+// XCD-contiguous order to every tile (with several bands: to every tile
+// that holds fluid nodes).
 template <typename T, int PAR, bool ENS>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d) {
-    const int tile = ENS ? d.live[xcd_tile(blockIdx.x, d.nlive)] : xcd_tile(blockIdx.x, d.ntx * d.nty);
+__device__ __forceinline__ void far_tile(const Dev &d, int b) {
+    const int tile = ENS ? d.live[xcd_tile(b, d.nlive)] : xcd_tile(b, d.ntx * d.nty);
     if (d.tnear[PAR][tile]) return;
     int i, j;
     tile_node(d, tile, i, j);
@@ -105,6 +106,13 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d) {
     lattice_collide<T>(d, PAR, i, j, h, uref, d.gx, d.gy);
 }
 
+// Far tiles on a large lattice, concurrently with the immersed-boundary
+// phase.
+template <typename T, int PAR, bool ENS>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d) {
+    far_tile<T, PAR, ENS>(d, blockIdx.x);
+}
+
 // Does a 4-wide stencil starting at o (wrapped into [0, n)) meet the range
 // [t0, t0 + w) of a periodic axis of length n?
 __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
@@ -113,25 +121,32 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
     return r < w || r + 3 >= n;
 }
 
-// Near tiles of this step, after the membrane kernel: one workgroup per
-// tile of the lattice, which leaves at once unless the tile is near; the
-// flag, the covering vertex ranges and the band's width are loaded
-// together, so a near tile starts its gather after one round trip.
-// Spreading (Sec. 2.2) is done here as a gather: the workgroup loads the
-// spread records of the tile's vertex ranges (512 per pass, two per thread),
-// compacts the covering vertices into LDS in index order, and every node
-// sums W f over them in that order, so the result does not depend on
-// scheduling.  The node's populations are loaded with the first records so
-// that their latency overlaps the gather.  The tile's flag and ranges are
-// cleared for the next step of the same parity.
+// The lattice sweep after the membrane kernel, one launch in three parts.
+// The first nmark workgroups mark the near tiles of the next step: the
+// tiles under the stencils of x^{n+1}, which the membrane kernel has
+// written; one (vertex, stencil tile) pair per lane, the range updates and
+// flag exchanges all in flight together, one list append per wave.  The
+// next nlb workgroups sweep this step's near tiles from the list that the
+// previous step's marking built (grid-stride, one workgroup per tile while
+// there are enough).  On a lattice of fewer than SPLIT_MIN_TILES tiles the
+// last part is every far tile, one workgroup each, dispatched after the
+// near tiles so that their longer latency chains start first: a single
+// sweep after the membrane phase costs less there than far tiles run beside
+// that phase on a second stream, whose cross-stream dependencies cost more
+// than the far tiles themselves.  On a larger lattice the far tiles are
+// swept beside the membrane phase instead (k_lattice_far).
 //
-// The first nmark workgroups of the launch instead mark the near tiles of
-// the next step: the tiles under the stencils of x^{n+1}, which the
-// membrane kernel has written.  One (vertex, stencil tile) pair per lane:
-// the flag store and the two range updates, all in flight together.
+// Spreading (Sec. 2.2) is done as a gather: the workgroup of a near tile
+// loads the spread records of the tile's vertex ranges (512 per pass, two
+// per thread), compacts the covering vertices into LDS in index order, and
+// every node sums W f over them in that order, so the result does not
+// depend on scheduling.  The node's populations are loaded with the first
+// records so that their latency overlaps the gather.  The flags and ranges
+// of this step's near tiles are cleared by the next step's interpolation
+// kernel (the far tiles of this launch read the flags).
 constexpr int MARK_VERTS = LAT_THREADS / 9;   // vertices per marking workgroup
 
-template <int NPAR, bool ENS, bool LIST>
+template <int NPAR, bool ENS>
 __device__ __forceinline__ void mark_next(const Dev &d, int mb) {
     const int v = mb * MARK_VERTS + (int)threadIdx.x / 9, q = (int)threadIdx.x % 9;
     bool fresh = false;
@@ -146,22 +161,17 @@ __device__ __forceinline__ void mark_next(const Dev &d, int mb) {
             if (r == q) tile = tl[r];
         if (q < c) {
             note_cover(d, NPAR, tile, v, info & 1);
-            if (LIST)
-                fresh = atomicExch(&d.tnear[NPAR][tile], 1) == 0;
-            else
-                d.tnear[NPAR][tile] = 1;
+            fresh = atomicExch(&d.tnear[NPAR][tile], 1) == 0;
         }
     }
-    if (LIST) {
-        // one list-counter update per wave
-        const unsigned long long m = __ballot(fresh);
-        if (m) {
-            const int lane = threadIdx.x & 63, lead = __ffsll((long long)m) - 1;
-            int base = 0;
-            if (lane == lead) base = atomicAdd(&d.ncount[NPAR], __popcll(m));
-            base = __shfl(base, lead);
-            if (fresh) d.nlist[NPAR][base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
-        }
+    // one list-counter update per wave
+    const unsigned long long m = __ballot(fresh);
+    if (m) {
+        const int lane = threadIdx.x & 63, lead = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == lead) base = atomicAdd(&d.ncount[NPAR], __popcll(m));
+        base = __shfl(base, lead);
+        if (fresh) d.nlist[NPAR][base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
     }
 }
 
@@ -228,10 +238,6 @@ __device__ __forceinline__ void near_tile(const Dev &d, int tile, const int4 r, 
     const bool valid = i < B.nx && j < B.y0 + B.ny;
     float h[9];
     if (valid) pull9<T>(d, (const T *)d.pop[PAR], i, j, B, h);
-    if (threadIdx.x == 0) {
-        d.tnear[PAR][tile] = 0;
-        ((int4 *)d.tv[PAR])[tile] = make_int4(0, 0, 0, 0);
-    }
     float ax = 0.0f, ay = 0.0f;
     for (int c0 = 0; c0 < nv; c0 += 2 * LAT_THREADS) {
         const Cand ca = load_cand(d, B, c0 + (int)threadIdx.x, nv, lo0, n0, lo1, x0, y0, tw, th);
@@ -296,33 +302,27 @@ __device__ __forceinline__ void near_tile(const Dev &d, int tile, const int4 r, 
     }
 }
 
-template <typename T, int PAR, bool ENS, bool LIST>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_near(Dev d, int nmark) {
+template <typename T, int PAR, bool ENS, bool FULL>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark, int nlb) {
     if ((int)blockIdx.x < nmark) {
-        mark_next<PAR ^ 1, ENS, LIST>(d, blockIdx.x);
+        mark_next<PAR ^ 1, ENS>(d, blockIdx.x);
         return;
     }
     const int bid = blockIdx.x - nmark;
-    if (!LIST) {
-        // one workgroup per tile: a tile is near if and only if one of its
-        // ranges is non-empty; the band's width takes part in the test so
-        // that its load is issued with the ranges'
-        const int4 r = ((const int4 *)d.tv[PAR])[bid];
-        const Band B = band_at_row<ENS>(d, (bid / d.ntx) * TILE_Y);   // tiles never straddle bands
-        if ((r.y | r.w) == 0 || B.nx <= 0) return;
-        near_tile<T, PAR>(d, bid, r, B);
+    if (bid < nlb) {
+        // near tiles, grid-stride over the list; the first entry is loaded
+        // with the count (nlb does not exceed the list's capacity)
+        int tile = d.nlist[PAR][bid];
+        const int cnt = d.ncount[PAR];
+        for (int k = bid; k < cnt; k += nlb) {
+            if (k != bid) tile = d.nlist[PAR][k];
+            const int4 r = ((const int4 *)d.tv[PAR])[tile];
+            const Band B = band_at_row<ENS>(d, (tile / d.ntx) * TILE_Y);   // tiles never straddle bands
+            near_tile<T, PAR>(d, tile, r, B);
+        }
         return;
     }
-    // grid-stride over the list of near tiles; the first entry is loaded
-    // with the count (the grid has at most one list workgroup per tile)
-    int tile = d.nlist[PAR][bid];
-    const int cnt = d.ncount[PAR];
-    for (int k = bid; k < cnt; k += gridDim.x - nmark) {
-        if (k != bid) tile = d.nlist[PAR][k];
-        const int4 r = ((const int4 *)d.tv[PAR])[tile];
-        const Band B = band_at_row<ENS>(d, (tile / d.ntx) * TILE_Y);
-        near_tile<T, PAR>(d, tile, r, B);
-    }
+    if (FULL) far_tile<T, PAR, ENS>(d, bid - nlb);
 }
 
 // Moments of the current state for read-out: drho and u* = (j + g/2)/rho
@@ -436,37 +436,39 @@ hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t 
     return hipGetLastError();
 }
 
-// Grid: the marking workgroups, then one workgroup per tile, or on a large
-// lattice (where workgroups that leave at once would take several rounds of
-// the machine) about one per near tile, which number a fraction of the
-// vertices; the list's grid-stride loop covers any count.
-constexpr int LIST_MIN_TILES = 8192;
+// Grid of the sweep: the marking workgroups; about one workgroup per near
+// tile, which number a fraction of the vertices (the list's grid-stride
+// loop covers any count); on a small lattice one workgroup per far-tile
+// candidate.
+constexpr int SPLIT_MIN_TILES = 8192;
+
+bool lattice_split(const Dev &d) { return d.ntx * d.nty >= SPLIT_MIN_TILES; }
 
 template <typename T, int P, bool E>
-static void go_near(const Dev &d, int nmark, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static void go_sweep(const Dev &d, int nmark, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nt = d.ntx * d.nty;
-    if (nt < LIST_MIN_TILES) {
-        hipExtLaunchKernelGGL((k_lattice_near<T, P, E, false>), dim3(nmark + nt), dim3(LAT_THREADS), 0, st, e0, e1, 0,
-                              d, nmark);
-    } else {
-        const int want = d.nverts / 4 > 1024 ? d.nverts / 4 : 1024;
-        hipExtLaunchKernelGGL((k_lattice_near<T, P, E, true>), dim3(nmark + (nt < want ? nt : want)),
-                              dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark);
-    }
+    const int want = d.nverts / 4 > 1024 ? d.nverts / 4 : 1024;
+    const int nlb = nt < want ? nt : want;
+    if (!lattice_split(d))
+        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true>), dim3(nmark + nlb + (E ? d.nlive : nt)),
+                              dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark, nlb);
+    else
+        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, false>), dim3(nmark + nlb), dim3(LAT_THREADS), 0, st, e0,
+                              e1, 0, d, nmark, nlb);
 }
 template <typename T>
-static void near_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static void sweep_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const bool ens = d.nbands > 1;
     const int nm = (d.nverts + MARK_VERTS - 1) / MARK_VERTS;
-    if (par) ens ? go_near<T, 1, true>(d, nm, st, e0, e1) : go_near<T, 1, false>(d, nm, st, e0, e1);
-    else ens ? go_near<T, 0, true>(d, nm, st, e0, e1) : go_near<T, 0, false>(d, nm, st, e0, e1);
+    if (par) ens ? go_sweep<T, 1, true>(d, nm, st, e0, e1) : go_sweep<T, 1, false>(d, nm, st, e0, e1);
+    else ens ? go_sweep<T, 0, true>(d, nm, st, e0, e1) : go_sweep<T, 0, false>(d, nm, st, e0, e1);
 }
 
-hipError_t launch_lattice_near(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (d.storage == 0)
-        near_of<float>(d, par, st, e0, e1);
+        sweep_of<float>(d, par, st, e0, e1);
     else
-        near_of<_Float16>(d, par, st, e0, e1);
+        sweep_of<_Float16>(d, par, st, e0, e1);
     return hipGetLastError();
 }
 

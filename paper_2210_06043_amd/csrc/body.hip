@@ -64,12 +64,17 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
     __shared__ float ss_frac[MAXS_BODY], ss_anh[MAXS_BODY], ss_anl[MAXS_BODY];
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
-    __shared__ float srig[8];
 
     const int b = blockIdx.x, tid = threadIdx.x;
     // the next step's near tiles are listed from zero by this step's sweep
     // (the interpolation has read the old count)
     if (b == 0 && tid == 0) d.ncount[PAR ^ 1] = 0;
+    // this step's near-tile list, expanded for the sweep at the end of this
+    // kernel: its first loads go out with the kernel's own (stale entries
+    // beyond the count are valid tile indices too)
+    const int nt = d.ntx * d.nty, gt = b * BT + tid;
+    const int ecnt = d.ncount[PAR];
+    const int etile = d.nlist[PAR][gt < nt ? gt : 0];
     const BodyParams P = d.bp[b];
     const int4 rg = b < ARG_BODIES ? d.brange[b] : make_int4(P.vstart, P.n, P.site_start, P.n_sites);
     const int n = rg.y, v0 = rg.x, ns = rg.w, s0 = rg.z, npar = PAR ^ 1;
@@ -137,6 +142,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
         if (q >= ns) continue;
         ss_state[q] = rst[k]; ss_frac[q] = rsf[k]; ss_anh[q] = rsah[k]; ss_anl[q] = rsal[k];
     }
+    const int4 erange = ((const int4 *)d.tv[PAR])[etile];   // used at the end
     __syncthreads();
 
     // ---- elements: length, outward normal, FP64 area, spring and external forces
@@ -319,26 +325,25 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
         M = wave_sum(M);
         if ((tid & 63) == 0) { shf[tid >> 6][0] = Fx; shf[tid >> 6][1] = Fy; shf[tid >> 6][2] = M; }
         __syncthreads();
+        // every thread sums the wave partials in the same order and takes
+        // the same rigid update (no second barrier); thread 0 stores it
+        Fx = 0.0f; Fy = 0.0f; M = 0.0f;
+        for (int w = 0; w < BT / 64; w++) { Fx += shf[w][0]; Fy += shf[w][1]; M += shf[w][2]; }
+        const float ux = (2.0f / 3.0f) * (2.0f * RS1.z - 0.5f * RS2.x + Fx * P.inv_mass);
+        const float uy = (2.0f / 3.0f) * (2.0f * RS1.w - 0.5f * RS2.y + Fy * P.inv_mass);
+        const float om = (2.0f / 3.0f) * (2.0f * RS2.z - 0.5f * RS2.w + M * P.inv_inertia);
+        float dcxh = RS0.x, dcxl = RS0.y, dcyh = RS0.z, dcyl = RS0.w, phih = RS1.x, phil = RS1.y;
+        df_add(dcxh, dcxl, ux);
+        df_add(dcyh, dcyl, uy);
+        df_add(phih, phil, om);
         if (tid == 0) {
-            Fx = 0.0f; Fy = 0.0f; M = 0.0f;
-            for (int w = 0; w < BT / 64; w++) { Fx += shf[w][0]; Fy += shf[w][1]; M += shf[w][2]; }
             BodyState &S = d.bs[b];
-            const float ux = (2.0f / 3.0f) * (2.0f * RS1.z - 0.5f * RS2.x + Fx * P.inv_mass);
-            const float uy = (2.0f / 3.0f) * (2.0f * RS1.w - 0.5f * RS2.y + Fy * P.inv_mass);
-            const float om = (2.0f / 3.0f) * (2.0f * RS2.z - 0.5f * RS2.w + M * P.inv_inertia);
-            float dcxh = RS0.x, dcxl = RS0.y, dcyh = RS0.z, dcyl = RS0.w, phih = RS1.x, phil = RS1.y;
-            df_add(dcxh, dcxl, ux);
-            df_add(dcyh, dcyl, uy);
-            df_add(phih, phil, om);
             *(float4 *)&S.dcxh = make_float4(dcxh, dcxl, dcyh, dcyl);
             *(float4 *)&S.phih = make_float4(phih, phil, ux, uy);
             *(float4 *)&S.ucxm = make_float4(RS1.z, RS1.w, om, RS2.z);
-            srig[0] = ux; srig[1] = uy; srig[2] = om;
-            srig[3] = dcxh; srig[4] = dcxl; srig[5] = dcyh; srig[6] = dcyl;
-            srig[7] = phih + phil;
         }
-        __syncthreads();
-        const float ph = srig[7];
+        const float srig[7] = {ux, uy, om, dcxh, dcxl, dcyh, dcyl};
+        const float ph = phih + phil;
         const float sh2 = sinf(0.5f * ph);
         const float c1n = -2.0f * sh2 * sh2, sn = sinf(ph);
 #pragma unroll
@@ -399,6 +404,15 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
         d.pyl[npar][v0 + v] = nyl[k];
     }
     __syncthreads();
+
+    // ---- probe points of x^{n+1} for the next step's interpolation ------------------------
+#pragma unroll
+    for (int k = 0; k < VPT; k++) {
+        const int v = tid + k * BT;
+        if (v >= n) continue;
+        const int m = (v + 1 == n) ? 0 : v + 1;
+        d.pprobe[npar][v0 + v] = probe_point(d, nxh[k], nxl[k], nyh[k], nyl[k], sxh[m], sxl[m], syh[m], syl[m]);
+    }
 
     // ---- bond kinetics at x^{n+1} --------------------------------------------------------
     int cnt = 0;
@@ -475,6 +489,26 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
         S.bbox[npar][0] = a0; S.bbox[npar][1] = a1;
         S.bbox[npar][2] = a2; S.bbox[npar][3] = a3;
     }
+
+    // ---- expanded near-tile list of this step (see Dev::elist) ----------------------------
+    for (int k = gt; k < ecnt; k += d.nbodies * BT) {
+        const int tile = k == gt ? etile : d.nlist[PAR][k];
+        const int4 r = k == gt ? erange : ((const int4 *)d.tv[PAR])[tile];
+        // the ranges [lo, hi] of the two halves (hi = -1: none) in index
+        // order, merged when they overlap
+        int lo0 = d.nverts - r.x, hi0 = r.y - 1, lo1 = d.nverts - r.z, hi1 = r.w - 1;
+        if (hi1 >= 0 && (hi0 < 0 || lo1 < lo0)) {
+            const int x = lo0, y = hi0;
+            lo0 = lo1; hi0 = hi1; lo1 = x; hi1 = y;
+        }
+        if (hi1 >= 0 && lo1 <= hi0) {
+            hi0 = max(hi0, hi1);
+            hi1 = -1;
+        }
+        const int nx = band_at<ENS>(d, ENS ? (tile / d.ntx) * TILE_Y / d.band_rows : 0).nx;
+        d.elist[PAR][2 * k] = make_int4(tile, nx, lo0, hi0 - lo0 + 1);
+        d.elist[PAR][2 * k + 1] = make_int4(lo1, hi1 >= 0 ? hi1 - lo1 + 1 : 0, 0, 0);
+    }
 }
 
 // Near tiles of the current positions (before the first step, after a
@@ -487,6 +521,9 @@ __global__ __launch_bounds__(256) void k_mark(Dev d, int par) {
     const int info = d.vinfo[v];
     const Band B = band_of(d, info >> 1);
     const int c = stencil_tiles(d, B, d.pxh[par][v], d.pxl[par][v], d.pyh[par][v], d.pyl[par][v], tl);
+    const int vn = d.vnext[v];
+    d.pprobe[par][v] = probe_point(d, d.pxh[par][v], d.pxl[par][v], d.pyh[par][v], d.pyl[par][v], d.pxh[par][vn],
+                                   d.pxl[par][vn], d.pyh[par][vn], d.pyl[par][vn]);
     for (int q = 0; q < c; q++) {
         note_cover(d, par, tl[q], v, info & 1);
         if (atomicExch(&d.tnear[par][tl[q]], 1) == 0) d.nlist[par][atomicAdd(&d.ncount[par], 1)] = tl[q];

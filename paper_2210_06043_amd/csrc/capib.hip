@@ -102,8 +102,9 @@ static capib_status fail(capib_ctx *c, capib_status s, const char *fmt, ...) {
     } while (0)
 
 // near-tile bookkeeping, per parity: the two vertex ranges of every tile
-// (16 bytes), the flags, the list; then the two list counts
-static size_t near_bytes(const capib_ctx *c) { return 2 * 24 * (size_t)c->ntx * c->nty + 64; }
+// (16 bytes), the flags, the list, the expanded list (32 bytes per entry);
+// then the two list counts
+static size_t near_bytes(const capib_ctx *c) { return 2 * 56 * (size_t)c->ntx * c->nty + 64; }
 
 static void layout(capib_ctx *c) {
     const capib_lattice &L = c->lat;
@@ -120,7 +121,7 @@ static void layout(capib_ctx *c) {
     c->off_scal = o; o = align256(o + 64);
     // spread records (rewritten every step, not checkpointed): origin, x and y
     // weights, force per vertex
-    c->off_sp = o; o = align256(o + (size_t)std::max(1, L.max_vertices) * (8 + 16 + 16 + 8));
+    c->off_sp = o; o = align256(o + (size_t)std::max(1, L.max_vertices) * (8 + 16 + 16 + 8 + 32));
     // IB region: one contiguous block (checkpointed whole)
     const size_t B = (size_t)std::max(1, L.max_bodies), V = (size_t)std::max(1, L.max_vertices),
                  S = (size_t)std::max(1, L.max_sites);
@@ -172,6 +173,8 @@ static void fill_dev(capib_ctx *c) {
         d.sp_wy = (float4 *)(q + 16 * V);
         d.sp_org = (int2 *)(q + 32 * V);
         d.sp_f = (float2 *)(q + 40 * V);
+        d.pprobe[0] = (float4 *)(q + 48 * V);
+        d.pprobe[1] = (float4 *)(q + 64 * V);
     }
     {
         const size_t nt = (size_t)c->ntx * c->nty;
@@ -183,6 +186,8 @@ static void fill_dev(capib_ctx *c) {
         d.nlist[0] = nb + 10 * nt;
         d.nlist[1] = nb + 11 * nt;
         d.ncount = nb + 12 * nt;
+        d.elist[0] = (int4 *)(b + c->off_near + 48 * nt + 64);
+        d.elist[1] = d.elist[0] + 2 * nt;
     }
     d.red = (double *)(b + c->off_red);
     d.macro = (float *)(b + c->off_macro);

@@ -86,6 +86,13 @@ struct Dev {
     // appends it).
     int *nlist[2];
     int *ncount;
+    // The membrane kernel expands each entry of its step's list into
+    // elist[p][2 k], [2 k + 1] = {tile, band width, lo0, n0}, {lo1, n1, 0, 0}:
+    // the covering vertices as candidate positions u in [0, n0 + n1) (u < n0:
+    // vertex lo0 + u, else lo1 + u - n0), the two ranges in index order and
+    // merged when they overlap; the sweep then starts a near tile from one
+    // load.
+    int4 *elist[2];
     // immersed boundary
     int nbodies, nverts, nsites, nbands;
     const int *band_nx;             // width of each band
@@ -111,6 +118,7 @@ struct Dev {
     float *l0, *th0;                            // rest lengths and turning angles
     float2 *ustar;                              // u* at vertices
     float4 *probe4;                             // p, sxx, sxy, syy at element probes
+    float4 *pprobe[2];                          // probe point of each element (x hi, lo, y hi, lo), parity-indexed
     float2 *force;                              // total Lagrangian force
     float2 *target;                             // U^{n+1}
     // spread records of the step, one per vertex (written by the membrane
@@ -378,6 +386,17 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
     return v;
+}
+
+// Probe point of the element from vertex (xh + xl, yh + yl) to the next
+// vertex (nxh + nxl, nyh + nyl): its midpoint moved by the probe distance
+// along the element's outward normal (Sec. 2.6), as a hi/lo pair.
+__device__ __forceinline__ float4 probe_point(const Dev &d, float xh, float xl, float yh, float yl, float nxh,
+                                              float nxl, float nyh, float nyl) {
+    const float tx = (nxh - xh) + (nxl - xl);
+    const float ty = (nyh - yh) + (nyl - yl);
+    const float len = sqrtf(tx * tx + ty * ty);
+    return make_float4(xh, xl + (0.5f * tx + d.probe * (ty / len)), yh, yl + (0.5f * ty - d.probe * (tx / len)));
 }
 
 // Counter-based generator: Philox4x32-10 (Salmon et al., SC'11), word 0.

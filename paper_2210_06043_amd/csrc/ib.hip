@@ -71,16 +71,15 @@ __device__ __forceinline__ void interp_point(const Dev &d, int gid) {
     const bool probe = p >= d.nverts;
     const int v = probe ? p - d.nverts : p;
     // the loads that need only v, issued together
-    const int info = d.vinfo[v], vn = d.vnext[v];
-    float xh = d.pxh[PAR][v], xl = d.pxl[PAR][v], yh = d.pyh[PAR][v], yl = d.pyl[PAR][v];
-    const Band B = band_at<ENS>(d, info >> 1);
+    const int info = d.vinfo[v];
+    float xh, xl, yh, yl;
     if (probe) {
-        const float tx = (d.pxh[PAR][vn] - xh) + (d.pxl[PAR][vn] - xl);
-        const float ty = (d.pyh[PAR][vn] - yh) + (d.pyl[PAR][vn] - yl);
-        const float len = sqrtf(tx * tx + ty * ty);
-        xl += 0.5f * tx + d.probe * (ty / len);
-        yl += 0.5f * ty - d.probe * (tx / len);
+        const float4 q = d.pprobe[PAR][v];
+        xh = q.x; xl = q.y; yh = q.z; yl = q.w;
+    } else {
+        xh = d.pxh[PAR][v]; xl = d.pxl[PAR][v]; yh = d.pyh[PAR][v]; yl = d.pyl[PAR][v];
     }
+    const Band B = band_at<ENS>(d, info >> 1);
     int ix0, iy0;
     float wx[4], wy[4], inv;
     const bool out = stencil(d, B, xh, xl, yh, yl, probe, ix0, iy0, wx, wy, inv);

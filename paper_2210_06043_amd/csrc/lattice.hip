@@ -124,8 +124,8 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
 // The lattice sweep after the membrane kernel, one launch in three parts.
 // The first nmark workgroups mark the near tiles of the next step: the
 // tiles under the stencils of x^{n+1}, which the membrane kernel has
-// written; one (vertex, stencil tile) pair per lane, the range updates and
-// flag exchanges all in flight together, one list append per wave.  The
+// written, with one range update and flag exchange per distinct tile of a
+// wave (see mark_next).  The
 // next nlb workgroups sweep this step's near tiles from the list that the
 // previous step's marking built (grid-stride, one workgroup per tile while
 // there are enough).  On a lattice of fewer than SPLIT_MIN_TILES tiles the
@@ -137,41 +137,138 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
 // swept beside the membrane phase instead (k_lattice_far).
 //
 // Spreading (Sec. 2.2) is done as a gather: the workgroup of a near tile
-// loads the spread records of the tile's vertex ranges (512 per pass, two
+// loads the spread records of the tile's vertex ranges (256 per pass, one
 // per thread), compacts the covering vertices into LDS in index order, and
 // every node sums W f over them in that order, so the result does not
 // depend on scheduling.  The node's populations are loaded with the first
 // records so that their latency overlaps the gather.  The flags and ranges
 // of this step's near tiles are cleared by the next step's interpolation
 // kernel (the far tiles of this launch read the flags).
-constexpr int MARK_VERTS = LAT_THREADS / 9;   // vertices per marking workgroup
 
-template <int NPAR, bool ENS>
-__device__ __forceinline__ void mark_next(const Dev &d, int mb) {
-    const int v = mb * MARK_VERTS + (int)threadIdx.x / 9, q = (int)threadIdx.x % 9;
-    bool fresh = false;
-    int tile = 0;
-    if ((int)threadIdx.x < MARK_VERTS * 9 && v < d.nverts) {
-        int tl[9];
-        const int info = d.vinfo[v];
-        const Band B = band_at<ENS>(d, info >> 1);
-        const int c = stencil_tiles(d, B, d.pxh[NPAR][v], d.pxl[NPAR][v], d.pyh[NPAR][v], d.pyl[NPAR][v], tl);
+// One pass over a wave's (vertex v, tile) pairs, one distinct tile at a
+// time: the lowest pending lane leads and alone widens the tile's vertex
+// ranges to the highest and lowest covering vertex of each half over the
+// lanes with that tile.  Neighbouring vertices share their tiles, so a wave
+// makes a few range updates per tile instead of one per pair.  LANEV: the
+// vertex of lane l is vb + l, so those bounds are the first and last lane of
+// a ballot; otherwise the wave reduces them with shuffles.  Returns whether
+// this lane led.
+template <int NPAR, bool LANEV>
+__device__ __forceinline__ bool mark_pass(const Dev &d, bool pend, int tile, int half, int v, int vb) {
+    const int lane = threadIdx.x & 63;
+    bool led = false;
+    for (unsigned long long m = __ballot(pend); m; m = __ballot(pend)) {
+        const int lead = __ffsll((long long)m) - 1;
+        const int lt = __shfl(tile, lead);
+        const bool same = pend && tile == lt;
+        int hi0, lo0, hi1, lo1;
+        if (LANEV) {
+            const unsigned long long m0 = __ballot(same && half == 0), m1 = __ballot(same && half == 1);
+            hi0 = m0 ? vb + 63 - __clzll((long long)m0) : -1;
+            lo0 = vb + __ffsll((long long)m0) - 1;
+            hi1 = m1 ? vb + 63 - __clzll((long long)m1) : -1;
+            lo1 = vb + __ffsll((long long)m1) - 1;
+        } else {
+            hi0 = (same && half == 0) ? v : -1;
+            lo0 = (same && half == 0) ? v : INT_MAX;
+            hi1 = (same && half == 1) ? v : -1;
+            lo1 = (same && half == 1) ? v : INT_MAX;
 #pragma unroll
-        for (int r = 0; r < 9; r++)
-            if (r == q) tile = tl[r];
-        if (q < c) {
-            note_cover(d, NPAR, tile, v, info & 1);
-            fresh = atomicExch(&d.tnear[NPAR][tile], 1) == 0;
+            for (int sh = 32; sh >= 1; sh >>= 1) {
+                hi0 = max(hi0, __shfl_xor(hi0, sh));
+                lo0 = min(lo0, __shfl_xor(lo0, sh));
+                hi1 = max(hi1, __shfl_xor(hi1, sh));
+                lo1 = min(lo1, __shfl_xor(lo1, sh));
+            }
+        }
+        if (lane == lead) {
+            int *t = d.tv[NPAR] + 4 * lt;
+            if (hi0 >= 0) {
+                atomicMax(t + 1, hi0 + 1);
+                atomicMax(t, d.nverts - lo0);
+            }
+            if (hi1 >= 0) {
+                atomicMax(t + 3, hi1 + 1);
+                atomicMax(t + 2, d.nverts - lo1);
+            }
+            led = true;
+        }
+        pend = pend && !same;
+    }
+    return led;
+}
+
+// The leaders' flag exchanges (all in flight together: a returned value kept
+// across the loops of mark_pass would hold each iteration until the previous
+// one returned), then one list-counter update per wave for its fresh tiles.
+template <int NPAR, int NP>
+__device__ __forceinline__ void mark_append(const Dev &d, const bool (&led)[NP], const int (&tl)[NP]) {
+    const int lane = threadIdx.x & 63;
+    bool fresh[NP];
+#pragma unroll
+    for (int r = 0; r < NP; r++) fresh[r] = led[r] && atomicExch(&d.tnear[NPAR][tl[r]], 1) == 0;
+    unsigned long long fm[NP];
+    int total = 0;
+#pragma unroll
+    for (int r = 0; r < NP; r++) {
+        fm[r] = __ballot(fresh[r]);
+        total += __popcll(fm[r]);
+    }
+    if (total) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&d.ncount[NPAR], total);
+        base = __shfl(base, 0);
+        const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int r = 0; r < NP; r++) {
+            if (fresh[r]) d.nlist[NPAR][base + __popcll(fm[r] & below)] = tl[r];
+            base += __popcll(fm[r]);
         }
     }
-    // one list-counter update per wave
-    const unsigned long long m = __ballot(fresh);
-    if (m) {
-        const int lane = threadIdx.x & 63, lead = __ffsll((long long)m) - 1;
-        int base = 0;
-        if (lane == lead) base = atomicAdd(&d.ncount[NPAR], __popcll(m));
-        base = __shfl(base, lead);
-        if (fresh) d.nlist[NPAR][base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
+}
+
+// Marking workgroup mb.  On a small lattice (PAIRS): one (vertex, stencil
+// tile) pair per lane, 28 vertices per workgroup, so that the marking's
+// chains are short and spread over many workgroups.  On a large one: one
+// vertex per lane and a pass per stencil tile, so that far fewer waves
+// contend for the list counter.
+template <bool PAIRS>
+constexpr int mark_verts() { return PAIRS ? LAT_THREADS / 9 : LAT_THREADS; }
+
+template <int NPAR, bool ENS, bool PAIRS>
+__device__ __forceinline__ void mark_next(const Dev &d, int mb) {
+    constexpr int MV = mark_verts<PAIRS>();
+    if constexpr (PAIRS) {
+        const int v = mb * MV + (int)threadIdx.x / 9, q = (int)threadIdx.x % 9;
+        bool pend = false;
+        int tile[1] = {0}, half = 0;
+        if ((int)threadIdx.x < MV * 9 && v < d.nverts) {
+            int tl[9];
+            const int info = d.vinfo[v];
+            const Band B = band_at<ENS>(d, info >> 1);
+            const int c = stencil_tiles(d, B, d.pxh[NPAR][v], d.pxl[NPAR][v], d.pyh[NPAR][v], d.pyl[NPAR][v], tl);
+#pragma unroll
+            for (int r = 0; r < 9; r++)
+                if (r == q) tile[0] = tl[r];
+            pend = q < c;
+            half = info & 1;
+        }
+        const bool led[1] = {mark_pass<NPAR, false>(d, pend, tile[0], half, v, 0)};
+        mark_append<NPAR>(d, led, tile);
+    } else {
+        const int v = mb * MV + (int)threadIdx.x;
+        int tl[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, c = 0, half = 0;
+        if (v < d.nverts) {
+            const int info = d.vinfo[v];
+            const Band B = band_at<ENS>(d, info >> 1);
+            c = stencil_tiles(d, B, d.pxh[NPAR][v], d.pxl[NPAR][v], d.pyh[NPAR][v], d.pyl[NPAR][v], tl);
+            half = info & 1;
+        }
+        const int vb = mb * MV + ((int)threadIdx.x & ~63);   // vertex of the wave's lane 0
+        bool led[9];
+#pragma unroll
+        for (int r = 0; r < 9; r++) led[r] = mark_pass<NPAR, true>(d, r < c, tl[r], half, v, vb);
+        mark_append<NPAR>(d, led, tl);
     }
 }
 
@@ -207,31 +304,22 @@ __device__ __forceinline__ Cand load_cand(const Dev &d, const Band &B, int u, in
     return c;
 }
 
-// One near tile: its covering vertex ranges r (as stored by the marking)
-// and its band B.
+// One near tile from its expanded list entry e0, e1: the tile, its band's
+// width and its covering vertices as candidate positions u in [0, n0 + n1)
+// (u < n0: vertex lo0 + u, else lo1 + u - n0).
 template <typename T, int PAR>
-__device__ __forceinline__ void near_tile(const Dev &d, int tile, const int4 r, const Band &B) {
+__device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int4 e1) {
     constexpr int NW = LAT_THREADS / 64;
     // staged covering vertices: x weights (normalised), y weights, and
     // (origin x, origin y, fx, fy) with the origin's bits in the float slots
-    __shared__ float4 srec[2 * LAT_THREADS + 4][3];
-    __shared__ int scount[2 * NW];
+    __shared__ float4 srec[LAT_THREADS + 4][3];
+    __shared__ int scount[NW];
+    const int tile = e0.x, lo0 = e0.z, n0 = e0.w, lo1 = e1.x, nv = n0 + e1.y;
     const int tyi = tile / d.ntx, txi = tile - tyi * d.ntx;
     const int x0 = txi * TILE_X, y0 = tyi * TILE_Y;
+    const Band B{e0.y, y0 - y0 % d.band_rows, d.band_rows};   // tiles never straddle bands
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
-    // the ranges [lo, hi] of the two halves (hi = -1: none) in index order,
-    // merged when they overlap; n0 + n1 candidates
-    int lo0 = d.nverts - r.x, hi0 = r.y - 1, lo1 = d.nverts - r.z, hi1 = r.w - 1;
-    if (hi1 >= 0 && (hi0 < 0 || lo1 < lo0)) {
-        const int a = lo0, b = hi0;
-        lo0 = lo1; hi0 = hi1; lo1 = a; hi1 = b;
-    }
-    if (hi1 >= 0 && lo1 <= hi0) {
-        hi0 = max(hi0, hi1);
-        hi1 = -1;
-    }
-    const int n0 = hi0 - lo0 + 1, nv = n0 + (hi1 >= 0 ? hi1 - lo1 + 1 : 0);
     const int tw = min(TILE_X, B.nx - x0), th = min(TILE_Y, B.y0 + B.ny - y0);
     int i, j;
     tile_node(d, tile, i, j);
@@ -239,34 +327,21 @@ __device__ __forceinline__ void near_tile(const Dev &d, int tile, const int4 r, 
     float h[9];
     if (valid) pull9<T>(d, (const T *)d.pop[PAR], i, j, B, h);
     float ax = 0.0f, ay = 0.0f;
-    for (int c0 = 0; c0 < nv; c0 += 2 * LAT_THREADS) {
+    for (int c0 = 0; c0 < nv; c0 += LAT_THREADS) {
         const Cand ca = load_cand(d, B, c0 + (int)threadIdx.x, nv, lo0, n0, lo1, x0, y0, tw, th);
-        const Cand cb = load_cand(d, B, c0 + LAT_THREADS + (int)threadIdx.x, nv, lo0, n0, lo1, x0, y0, tw, th);
-        const unsigned long long ma = __ballot(ca.hit), mb = __ballot(cb.hit);
-        if (lane == 0) {
-            scount[wv] = __popcll(ma);
-            scount[NW + wv] = __popcll(mb);
-        }
+        const unsigned long long ma = __ballot(ca.hit);
+        if (lane == 0) scount[wv] = __popcll(ma);
         __syncthreads();
-        int sa = __popcll(ma & below), sb = __popcll(mb & below), ta = 0, tot = 0;
+        int sa = __popcll(ma & below), tot = 0;
 #pragma unroll
         for (int w = 0; w < NW; w++) {
             sa += (w < wv) ? scount[w] : 0;
-            sb += (w < wv) ? scount[NW + w] : 0;
-            ta += scount[w];
-            tot += scount[NW + w];
+            tot += scount[w];
         }
-        sb += ta;
-        tot += ta;
         if (ca.hit) {
             srec[sa][0] = ca.wx;
             srec[sa][1] = ca.wy;
             srec[sa][2] = make_float4(__int_as_float(ca.o.x), __int_as_float(ca.o.y), ca.f.x, ca.f.y);
-        }
-        if (cb.hit) {
-            srec[sb][0] = cb.wx;
-            srec[sb][1] = cb.wy;
-            srec[sb][2] = make_float4(__int_as_float(cb.o.x), __int_as_float(cb.o.y), cb.f.x, cb.f.y);
         }
         // pad to a multiple of four with records that cover no node
         if ((int)threadIdx.x < ((tot + 3) & ~3) - tot) {
@@ -305,20 +380,22 @@ __device__ __forceinline__ void near_tile(const Dev &d, int tile, const int4 r, 
 template <typename T, int PAR, bool ENS, bool FULL>
 __global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark, int nlb) {
     if ((int)blockIdx.x < nmark) {
-        mark_next<PAR ^ 1, ENS>(d, blockIdx.x);
+        mark_next<PAR ^ 1, ENS, FULL>(d, blockIdx.x);
         return;
     }
     const int bid = blockIdx.x - nmark;
     if (bid < nlb) {
-        // near tiles, grid-stride over the list; the first entry is loaded
-        // with the count (nlb does not exceed the list's capacity)
-        int tile = d.nlist[PAR][bid];
+        // near tiles, grid-stride over the expanded list; the first entry is
+        // loaded with the count (nlb does not exceed the list's capacity)
+        const int4 *E = d.elist[PAR];
+        int4 e0 = E[2 * bid], e1 = E[2 * bid + 1];
         const int cnt = d.ncount[PAR];
         for (int k = bid; k < cnt; k += nlb) {
-            if (k != bid) tile = d.nlist[PAR][k];
-            const int4 r = ((const int4 *)d.tv[PAR])[tile];
-            const Band B = band_at_row<ENS>(d, (tile / d.ntx) * TILE_Y);   // tiles never straddle bands
-            near_tile<T, PAR>(d, tile, r, B);
+            if (k != bid) {
+                e0 = E[2 * k];
+                e1 = E[2 * k + 1];
+            }
+            near_tile<T, PAR>(d, e0, e1);
         }
         return;
     }
@@ -447,7 +524,7 @@ bool lattice_split(const Dev &d) { return d.ntx * d.nty >= SPLIT_MIN_TILES; }
 template <typename T, int P, bool E>
 static void go_sweep(const Dev &d, int nmark, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nt = d.ntx * d.nty;
-    const int want = d.nverts / 4 > 1024 ? d.nverts / 4 : 1024;
+    const int want = d.nverts / 8 > 1024 ? d.nverts / 8 : 1024;
     const int nlb = nt < want ? nt : want;
     if (!lattice_split(d))
         hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true>), dim3(nmark + nlb + (E ? d.nlive : nt)),
@@ -459,7 +536,8 @@ static void go_sweep(const Dev &d, int nmark, hipStream_t st, hipEvent_t e0, hip
 template <typename T>
 static void sweep_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const bool ens = d.nbands > 1;
-    const int nm = (d.nverts + MARK_VERTS - 1) / MARK_VERTS;
+    const int mv = lattice_split(d) ? mark_verts<false>() : mark_verts<true>();
+    const int nm = (d.nverts + mv - 1) / mv;
     if (par) ens ? go_sweep<T, 1, true>(d, nm, st, e0, e1) : go_sweep<T, 1, false>(d, nm, st, e0, e1);
     else ens ? go_sweep<T, 0, true>(d, nm, st, e0, e1) : go_sweep<T, 0, false>(d, nm, st, e0, e1);
 }

@@ -377,10 +377,10 @@ __device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int
     }
 }
 
-template <typename T, int PAR, bool ENS, bool FULL>
+template <typename T, int PAR, bool ENS, bool FULL, bool PAIRS>
 __global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark, int nlb) {
     if ((int)blockIdx.x < nmark) {
-        mark_next<PAR ^ 1, ENS, FULL>(d, blockIdx.x);
+        mark_next<PAR ^ 1, ENS, PAIRS>(d, blockIdx.x);
         return;
     }
     const int bid = blockIdx.x - nmark;
@@ -521,25 +521,35 @@ constexpr int SPLIT_MIN_TILES = 8192;
 
 bool lattice_split(const Dev &d) { return d.ntx * d.nty >= SPLIT_MIN_TILES; }
 
-template <typename T, int P, bool E>
-static void go_sweep(const Dev &d, int nmark, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+// marking layout: pairs per lane below this many vertices (see mark_next)
+constexpr int PAIRS_MAX_VERTS = 16384;
+
+template <typename T, int P, bool E, bool PA>
+static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    constexpr int mv = mark_verts<PA>();
+    const int nmark = (d.nverts + mv - 1) / mv;
     const int nt = d.ntx * d.nty;
     const int want = d.nverts / 8 > 1024 ? d.nverts / 8 : 1024;
     const int nlb = nt < want ? nt : want;
     if (!lattice_split(d))
-        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true>), dim3(nmark + nlb + (E ? d.nlive : nt)),
+        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true, PA>), dim3(nmark + nlb + (E ? d.nlive : nt)),
                               dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark, nlb);
     else
-        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, false>), dim3(nmark + nlb), dim3(LAT_THREADS), 0, st, e0,
+        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, false, PA>), dim3(nmark + nlb), dim3(LAT_THREADS), 0, st, e0,
                               e1, 0, d, nmark, nlb);
+}
+template <typename T, int P, bool E>
+static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (d.nverts < PAIRS_MAX_VERTS)
+        go_sweep<T, P, E, true>(d, st, e0, e1);
+    else
+        go_sweep<T, P, E, false>(d, st, e0, e1);
 }
 template <typename T>
 static void sweep_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const bool ens = d.nbands > 1;
-    const int mv = lattice_split(d) ? mark_verts<false>() : mark_verts<true>();
-    const int nm = (d.nverts + mv - 1) / mv;
-    if (par) ens ? go_sweep<T, 1, true>(d, nm, st, e0, e1) : go_sweep<T, 1, false>(d, nm, st, e0, e1);
-    else ens ? go_sweep<T, 0, true>(d, nm, st, e0, e1) : go_sweep<T, 0, false>(d, nm, st, e0, e1);
+    if (par) ens ? go_sweep<T, 1, true>(d, st, e0, e1) : go_sweep<T, 1, false>(d, st, e0, e1);
+    else ens ? go_sweep<T, 0, true>(d, st, e0, e1) : go_sweep<T, 0, false>(d, st, e0, e1);
 }
 
 hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {

@@ -106,11 +106,35 @@ __device__ __forceinline__ void far_tile(const Dev &d, int b) {
     lattice_collide<T>(d, PAR, i, j, h, uref, d.gx, d.gy);
 }
 
-// Far tiles on a large lattice, concurrently with the immersed-boundary
-// phase.
+// A far tile's inputs, loaded ahead of its collision.
+struct FarIn {
+    int i, j;
+    bool go;      // a far tile and a fluid node
+    float h[9], uref;
+};
+
 template <typename T, int PAR, bool ENS>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d) {
-    far_tile<T, PAR, ENS>(d, blockIdx.x);
+__device__ __forceinline__ void far_load(const Dev &d, int c, FarIn &f) {
+    const int tile = ENS ? d.live[c] : c;
+    const int flag = d.tnear[PAR][tile];
+    tile_node(d, tile, f.i, f.j);
+    const Band B = band_at_row<ENS>(d, f.j < d.ny ? f.j : 0);
+    f.go = !flag && f.j < d.ny && f.i < B.nx;
+    if (f.go) f.uref = pull_dev<T>(d, (const T *)d.pop[PAR], f.i, f.j, B, f.h);
+}
+
+// Far tiles on a large lattice, concurrently with the immersed-boundary
+// phase: two consecutive candidates per workgroup (pairs in XCD-contiguous
+// order), both tiles' loads in flight together.
+template <typename T, int PAR, bool ENS>
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int n) {
+    const int c0 = 2 * xcd_tile(blockIdx.x, gridDim.x);
+    FarIn f0, f1;
+    f1.go = false;
+    far_load<T, PAR, ENS>(d, c0, f0);
+    if (c0 + 1 < n) far_load<T, PAR, ENS>(d, c0 + 1, f1);
+    if (f0.go) lattice_collide<T>(d, PAR, f0.i, f0.j, f0.h, f0.uref, d.gx, d.gy);
+    if (f1.go) lattice_collide<T>(d, PAR, f1.i, f1.j, f1.h, f1.uref, d.gx, d.gy);
 }
 
 // Does a 4-wide stencil starting at o (wrapped into [0, n)) meet the range
@@ -125,8 +149,7 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
 // The first nmark workgroups mark the near tiles of the next step: the
 // tiles under the stencils of x^{n+1}, which the membrane kernel has
 // written, with one range update and flag exchange per distinct tile of a
-// wave (see mark_next).  The
-// next nlb workgroups sweep this step's near tiles from the list that the
+// wave (see mark_next).  The next nlb workgroups sweep this step's near tiles from the list that the
 // previous step's marking built (grid-stride, one workgroup per tile while
 // there are enough).  On a lattice of fewer than SPLIT_MIN_TILES tiles the
 // last part is every far tile, one workgroup each, dispatched after the
@@ -495,8 +518,8 @@ __global__ __launch_bounds__(256) void k_diag_final(Dev d, int nblk) {
 // the band geometry need no dependent loads.
 template <typename T, int P, bool E>
 static void go_far(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_lattice_far<T, P, E>), dim3(E ? d.nlive : d.ntx * d.nty), dim3(LAT_THREADS), 0, st, e0,
-                          e1, 0, d);
+    const int n = E ? d.nlive : d.ntx * d.nty;
+    hipExtLaunchKernelGGL((k_lattice_far<T, P, E>), dim3((n + 1) / 2), dim3(LAT_THREADS), 0, st, e0, e1, 0, d, n);
 }
 template <typename T>
 static void far_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {

@@ -134,7 +134,8 @@ typedef struct {
     int32_t n_bodies;
     double mass;          /* sum over nodes of drho, FP64 accumulation */
     double mom_x, mom_y;  /* sum over nodes of sum_i h_i e_i, FP64 accumulation */
-    int32_t near_tiles;   /* 64x4 lattice tiles under membrane stencils for the next step */
+    int32_t near_tiles;   /* 64x4 lattice tiles under membrane stencils for the next step
+                             (0 until a capib_step call, of any count, has marked them) */
     int32_t tiles;        /* all lattice tiles */
 } capib_diag;
 

@@ -1,0 +1,69 @@
+"""Near-tile bookkeeping on the GPU against the host: the tiles (64 x 4
+nodes) that the marking records for the next step are exactly those under
+the 4 x 4 stencils of the current vertex positions (columns floor(x) - 1 ..
+floor(x) + 2 wrapped at the member's width, rows floor(y) - 1 .. floor(y) + 2
+clipped to the fluid rows).  Covers the small-lattice schedule (one sweep,
+a (vertex, tile) pair per marking lane) and the large-ensemble schedule
+(far sweep beside the membrane phase, one vertex per marking lane, list
+sweep), right after set-up (a zero-step call marks the initial positions)
+and after graph-replayed steps."""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import say
+from paper_2210_06043_amd import capib, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _host_tiles(sim, cfgs, first):
+    ny = cfgs[0].ny
+    ntx = (max(c.nx for c in cfgs) + 63) // 64
+    tiles = set()
+    for k, c in enumerate(cfgs):
+        for b in range(len(c.bodies)):
+            for x, y in sim.vertices(first[k] + b):
+                ix, iy = math.floor(x), math.floor(y)
+                for bb in range(4):
+                    j = iy - 1 + bb
+                    if c.walls:
+                        if j < 0 or j >= ny:
+                            continue
+                    else:
+                        j %= ny
+                    for a in range(4):
+                        tiles.add((k * ny + j) // 4 * ntx + ((ix - 1 + a) % c.nx) // 64)
+    return tiles
+
+
+def _check(sim, cfgs, first, label):
+    d = sim.diagnostics()
+    want = _host_tiles(sim, cfgs, first)
+    say(f"{label}: {d['near_tiles']} near tiles of {d['tiles']} (host {len(want)})")
+    assert d["error_flags"] == 0
+    assert d["near_tiles"] == len(want)
+
+
+def test_near_tiles_small_lattice():
+    cfg = inputs.config_c2(seed=2)
+    sim = capib.from_config(cfg, graph=True)
+    assert sim.diagnostics()["tiles"] == 3600
+    sim.step(0)
+    _check(sim, [cfg], [0], "3840x240 at creation")
+    sim.step(48)
+    _check(sim, [cfg], [0], "3840x240 after 48 steps")
+
+
+def test_near_tiles_large_ensemble():
+    """64 members of the batched workload: 32 x 1024 tiles, ~37k vertices."""
+    cfgs = inputs.config_c3(seed=0, members=64)
+    assert sum(c.n_vertices for c in cfgs) >= 16384
+    sim, first = capib.from_ensemble(cfgs, storage=capib.FP16_SHIFTED, fp16_scale=capib.fp16_scale_for(cfgs[0]),
+                                     graph=True)
+    assert sim.diagnostics()["tiles"] >= 8192
+    sim.step(0)
+    _check(sim, cfgs, first, "64-member ensemble at creation")
+    sim.step(48)
+    _check(sim, cfgs, first, "64-member ensemble after 48 steps")

@@ -60,8 +60,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
     __shared__ float sHx[MAXV_BODY], sHy[MAXV_BODY];   // half of the element's area, bond and load force
     __shared__ float sbox[MAX_BOX][4];
     __shared__ float sqxh[MAXV_BODY], sqxl[MAXV_BODY], sqyh[MAXV_BODY], sqyl[MAXV_BODY];   // another body, staged
-    __shared__ int ss_state[MAXS_BODY];
-    __shared__ float ss_frac[MAXS_BODY], ss_anh[MAXS_BODY], ss_anl[MAXS_BODY];
+    __shared__ float ss_bond[MAXS_BODY];   // Eq. (13) magnitude of each engaged bond (0 if free)
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
 
@@ -116,8 +115,8 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
             rx0h[k] = d.x0h[g]; rx0l[k] = d.x0l[g]; ry0h[k] = d.y0h[g]; ry0l[k] = d.y0l[g];
         }
     }
-    // sites: the element loop reads state, fraction and anchor of any site
-    // (LDS); the kinetics keep the host element and draw index of their own
+    // sites: host element, draw index, state, fraction and anchor of this
+    // thread's own
     int rsh[SPT], rso[SPT], rst[SPT];
     float rsf[SPT], rsah[SPT], rsal[SPT];
 #pragma unroll
@@ -136,14 +135,31 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
         if (v >= n) continue;
         sxh[v] = rxh[k]; sxl[v] = rxl[k]; syh[v] = ryh[k]; syl[v] = ryl[k];
     }
-#pragma unroll
-    for (int k = 0; k < SPT; k++) {
-        const int q = tid + k * BT;
-        if (q >= ns) continue;
-        ss_state[q] = rst[k]; ss_frac[q] = rsf[k]; ss_anh[q] = rsah[k]; ss_anl[q] = rsal[k];
-    }
     const int4 erange = ((const int4 *)d.tv[PAR])[etile];   // used at the end
     __syncthreads();
+
+    // ---- Eq. (13): bond spring magnitude of every engaged site, one site per
+    // thread, so that an element's sum below reads them in site order
+    if (ns) {
+#pragma unroll
+        for (int k = 0; k < SPT; k++) {
+            const int q = tid + k * BT;
+            if (q >= ns) continue;
+            float bf = 0.0f;
+            if (rst[k]) {
+                const int e = rsh[k] - v0;
+                const int m = (e + 1 == n) ? 0 : e + 1;
+                const float tx = (sxh[m] - sxh[e]) + (sxl[m] - sxl[e]);
+                const float ty = (syh[m] - syh[e]) + (syl[m] - syl[e]);
+                const float f = rsf[k];
+                const float dx = (sxh[e] - rsah[k]) + ((sxl[e] - rsal[k]) + f * tx);
+                const float dy = (syh[e] + 0.5f) + (syl[e] + f * ty);
+                bf = P.sigma * (sqrtf(dx * dx + dy * dy) - P.yeq);
+            }
+            ss_bond[q] = bf;
+        }
+        __syncthreads();
+    }
 
     // ---- elements: length, outward normal, FP64 area, spring and external forces
     double apart = 0.0;
@@ -168,13 +184,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
         sSy[l] = ks * nx;
         // Eq. (13): engaged bonds of this element, along its outward normal
         float bm = 0.0f;
-        for (int s = rsr[k].x - s0; s < rsr[k].y - s0; s++) {
-            if (!ss_state[s]) continue;
-            const float f = ss_frac[s];
-            const float dx = (rxh[k] - ss_anh[s]) + ((rxl[k] - ss_anl[s]) + f * tx);
-            const float dy = (ryh[k] + 0.5f) + (ryl[k] + f * ty);
-            bm += P.sigma * (sqrtf(dx * dx + dy * dy) - P.yeq);
-        }
+        for (int s = rsr[k].x - s0; s < rsr[k].y - s0; s++) bm += ss_bond[s];
         // Eqs. (14)-(15): (-p n + sigma . n) l from the element's probe
         const float4 q = rpr[k];
         const float Lx = ((q.y - q.x) * nx + q.z * ny) * len;

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
     const float4 RS0 = *(const float4 *)&d.bs[b].dcxh;   // dcxh, dcxl, dcyh, dcyl
     const float4 RS1 = *(const float4 *)&d.bs[b].phih;   // phih, phil, ucx, ucy
     const float4 RS2 = *(const float4 *)&d.bs[b].ucxm;   // ucxm, ucym, om, omm
+    const float2 RS3 = *(const float2 *)&d.bs[b].rot;    // cos(phi) - 1, sin(phi)
 
     // ---- every per-vertex and per-site global load of the step, issued together --
     float rxh[VPT], rxl[VPT], ryh[VPT], ryl[VPT], rl0[VPT], rth0[VPT], rdxm[VPT], rdym[VPT];
@@ -316,9 +317,7 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
     // ---- integration (Eqs. 16-20), direct forcing and spreading at x^n -----------------
     float nxh[VPT], nxl[VPT], nyh[VPT], nyl[VPT];
     if (rigid) {
-        const float phin = RS1.x + RS1.y;
-        const float shalf = sinf(0.5f * phin);
-        const float c1 = -2.0f * shalf * shalf, sphi = sinf(phin);
+        const float c1 = RS3.x, sphi = RS3.y;   // rotation by the stored angle
         float Fx = 0.0f, Fy = 0.0f, M = 0.0f;
 #pragma unroll
         for (int k = 0; k < VPT; k++) {
@@ -354,8 +353,12 @@ __global__ __launch_bounds__(BT) void k_body(Dev d) {
         }
         const float srig[7] = {ux, uy, om, dcxh, dcxl, dcyh, dcyl};
         const float ph = phih + phil;
-        const float sh2 = sinf(0.5f * ph);
-        const float c1n = -2.0f * sh2 * sh2, sn = sinf(ph);
+        // cos(ph) - 1 = -2 sin^2(ph/2) (no cancellation at small angles) and
+        // sin(ph) = 2 sin(ph/2) cos(ph/2), kept for the next step
+        float sh2, ch2;
+        sincosf(0.5f * ph, &sh2, &ch2);
+        const float c1n = -2.0f * sh2 * sh2, sn = 2.0f * sh2 * ch2;
+        if (tid == 0) *(float2 *)&d.bs[b].rot = make_float2(c1n, sn);
 #pragma unroll
         for (int k = 0; k < VPT; k++) {
             const int v = tid + k * BT;

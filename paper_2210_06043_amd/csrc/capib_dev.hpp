@@ -44,7 +44,7 @@ struct BodyState {
     float bbox[2][4];               // xmin, xmax, ymin, ymax of the vertices, parity-indexed
     int n_bound, pad;
     double geo[4];                  // diagnostics: area, perimeter, cx, cy
-    float pad2[2];
+    float rot[2];                   // rigid: cos(phi) - 1 and sin(phi) of the stored angle
 };
 // the membrane kernel reads the rigid state as three float4
 static_assert(sizeof(BodyState) % 16 == 0, "BodyState must keep 16-byte alignment in arrays");

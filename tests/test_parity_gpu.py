@@ -114,6 +114,22 @@ def test_tiny_fixed_body_periodic_parity():
     _compare_run(cfg, 200, "tiny-periodic")
 
 
+def test_bodies_across_the_periodic_ends_parity():
+    """The cell moved to straddle x = 0 (vertices at negative x) and the
+    bonded rigid particle to straddle x = nx: stencils, near tiles and their
+    vertex ranges, spreading and the bond anchors all wrap at the channel's
+    ends.  200 steps against the oracle."""
+    import copy
+    cfg = copy.deepcopy(inputs.config_tiny())
+    for b, dx in zip(cfg.bodies, (-7.8, 12.0)):
+        b.xy = b.xy + np.array([dx, 0.0])
+        if b.xy_rest is not None:
+            b.xy_rest = b.xy_rest + np.array([dx, 0.0])
+    assert cfg.bodies[0].xy[:, 0].min() < 0.0 and cfg.bodies[1].xy[:, 0].max() > cfg.nx
+    say("periodic-ends parity")
+    _compare_run(cfg, 200, "periodic-ends")
+
+
 @pytest.mark.parametrize("kinds", [(inputs.DEFORMABLE, inputs.RIGID), (inputs.DEFORMABLE, inputs.DEFORMABLE)],
                          ids=["cell-particle", "cell-cell"])
 def test_contact_repulsion_parity(kinds):

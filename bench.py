@@ -289,7 +289,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="print only the batched-ensemble measurement (for profiling it alone)")

@@ -39,7 +39,7 @@ __device__ __forceinline__ void collide_core(const Dev &d, const float h[9], flo
     const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
 
     const float rho = 1.0f + drho;
-    const float irho = 1.0f / rho;
+    const float irho = __builtin_amdgcn_rcpf(rho);   // hardware reciprocal (1 ulp)
     // u = (j + F/2)/rho written as u_ref + du with du from deviations only
     const float dux = (jx + 0.5f * Fx - drho * uref) * irho;
     const float duy = (jy + 0.5f * Fy) * irho;
@@ -57,22 +57,28 @@ __device__ __forceinline__ void collide_core(const Dev &d, const float h[9], flo
         const float w = 4.0f / 9.0f;
         out[0] = om1 * h[0] + om * E(0.0f, 0.0f, w) + fc * w * fb;
     }
-#define CAPIB_DIR(q, ex, ey, w)                                                              \
+    // The other directions in opposite pairs (e, -e).  With eu = e.u,
+    // edu = e.du and eF = e.F, h_eq - r splits into w S, even in e, with
+    // S = c0 + 4.5 drho eu^2 + 4.5 edu (eu + e.u_ref), and w A, odd in e,
+    // with A = 3 (drho eu + edu); the Guo term into fc w (fb + 9 eu eF), even,
+    // and fc w 3 eF, odd.  So s'_{+-e} = (1 - omega) dh + w (P +- M).
+#define CAPIB_PAIR(q, qb, ex, ey, w)                                                         \
     {                                                                                        \
         const float eu = (ex) * ux + (ey) * uy;                                              \
+        const float edu = (ex) * E.dux + (ey) * E.duy;                                       \
         const float eF = (ex) * Fx + (ey) * Fy;                                              \
-        const float Fi = fc * (w) * (fb + 3.0f * eF + 9.0f * eu * eF);                       \
-        out[q] = om1 * h[q] + om * E((ex), (ey), (w)) + Fi;                                  \
+        const float S = E.c0 + 4.5f * (drho * eu * eu + edu * (eu + (ex) * uref));           \
+        const float A = 3.0f * (drho * eu + edu);                                            \
+        const float P = om * S + fc * (fb + 9.0f * eu * eF);                                 \
+        const float M = om * A + fc * (3.0f * eF);                                           \
+        out[q] = om1 * h[q] + (w) * (P + M);                                                 \
+        out[qb] = om1 * h[qb] + (w) * (P - M);                                               \
     }
-    CAPIB_DIR(1, 1.0f, 0.0f, 1.0f / 9.0f)
-    CAPIB_DIR(2, 0.0f, 1.0f, 1.0f / 9.0f)
-    CAPIB_DIR(3, -1.0f, 0.0f, 1.0f / 9.0f)
-    CAPIB_DIR(4, 0.0f, -1.0f, 1.0f / 9.0f)
-    CAPIB_DIR(5, 1.0f, 1.0f, 1.0f / 36.0f)
-    CAPIB_DIR(6, -1.0f, 1.0f, 1.0f / 36.0f)
-    CAPIB_DIR(7, -1.0f, -1.0f, 1.0f / 36.0f)
-    CAPIB_DIR(8, 1.0f, -1.0f, 1.0f / 36.0f)
-#undef CAPIB_DIR
+    CAPIB_PAIR(1, 3, 1.0f, 0.0f, 1.0f / 9.0f)
+    CAPIB_PAIR(2, 4, 0.0f, 1.0f, 1.0f / 9.0f)
+    CAPIB_PAIR(5, 7, 1.0f, 1.0f, 1.0f / 36.0f)
+    CAPIB_PAIR(6, 8, -1.0f, 1.0f, 1.0f / 36.0f)
+#undef CAPIB_PAIR
 }
 
 // Collision and store of node (i, j).

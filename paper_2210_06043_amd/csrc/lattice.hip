@@ -165,14 +165,14 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
 // than the far tiles themselves.  On a larger lattice the far tiles are
 // swept beside the membrane phase instead (k_lattice_far).
 //
-// Spreading (Sec. 2.2) is done as a gather: the workgroup of a near tile
-// loads the spread records of the tile's vertex ranges (256 per pass, one
-// per thread), compacts the covering vertices into LDS in index order, and
-// every node sums W f over them in that order, so the result does not
-// depend on scheduling.  The node's populations are loaded with the first
-// records so that their latency overlaps the gather.  The flags and ranges
-// of this step's near tiles are cleared by the next step's interpolation
-// kernel (the far tiles of this launch read the flags).
+// Spreading (Sec. 2.2) is done as a gather: each wave of a near tile's
+// workgroup (one tile row) loads the spread records of the tile's vertex
+// ranges (64 per pass, one per lane), keeps those whose stencil reaches its
+// row, in index order, and every node sums W f over them in that order, so
+// the result does not depend on scheduling.  The first records are loaded
+// before the node's populations, whose latency then overlaps the gather.
+// The flags and ranges of this step's near tiles are cleared by the next
+// step's interpolation kernel (the far tiles of this launch read the flags).
 
 // One pass over a wave's (vertex v, tile) pairs, one distinct tile at a
 // time: the lowest pending lane leads and alone widens the tile's vertex
@@ -301,23 +301,18 @@ __device__ __forceinline__ void mark_next(const Dev &d, int mb) {
     }
 }
 
-// Spread record of the covering candidate at position u of a tile's vertex
-// ranges (u < n0: lo0 + u, else lo1 + u - n0); hit if its stencil meets the
-// tile.
+// The spread record of the candidate at position u of a tile's vertex
+// ranges, as stored by the membrane kernel (zero past the end).
 struct Cand {
     int2 o;
     float4 wx, wy;
     float2 f;
-    bool hit;
 };
 
-__device__ __forceinline__ Cand load_cand(const Dev &d, const Band &B, int u, int nv, int lo0, int n0, int lo1, int x0,
-                                          int y0, int tw, int th) {
+__device__ __forceinline__ Cand load_cand(const Dev &d, int u, int nv, int lo0, int n0, int lo1) {
     Cand c;
-    c.hit = false;
-    c.o = make_int2(0, 0);
-    c.wx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    c.wy = c.wx;
+    c.o = make_int2(0, -(1 << 30));
+    c.wx = c.wy = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     c.f = make_float2(0.0f, 0.0f);
     if (u < nv) {
         const int v = u < n0 ? lo0 + u : lo1 + (u - n0);
@@ -325,80 +320,76 @@ __device__ __forceinline__ Cand load_cand(const Dev &d, const Band &B, int u, in
         c.wx = d.sp_wx[v];
         c.wy = d.sp_wy[v];
         c.f = d.sp_f[v];
-        const bool hx = meets_periodic(c.o.x, x0, tw, B.nx);
-        const bool hy = d.walls ? (c.o.y + 3 >= y0 && c.o.y < y0 + th)
-                                : meets_periodic(c.o.y - B.y0, y0 - B.y0, th, B.ny);
-        c.hit = hx && hy;
     }
     return c;
 }
 
 // One near tile from its expanded list entry e0, e1: the tile, its band's
 // width and its covering vertices as candidate positions u in [0, n0 + n1)
-// (u < n0: vertex lo0 + u, else lo1 + u - n0).
+// (u < n0: vertex lo0 + u, else lo1 + u - n0).  Each wave holds one row of
+// the tile and gathers the spread force of its nodes by itself, with no
+// barrier: its lanes load 64 candidates at a time, the candidates whose
+// stencil reaches the row (and the tile's columns) go to the wave's own LDS
+// rows in candidate order, with the y weight of the row already chosen, and
+// every lane then reads each record in turn (broadcast); a node adds
+// w_x w_y f of the vertices whose stencil holds it, in candidate order.
 template <typename T, int PAR>
 __device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int4 e1) {
-    constexpr int NW = LAT_THREADS / 64;
-    // staged covering vertices: x weights (normalised), y weights, and
-    // (origin x, origin y, fx, fy) with the origin's bits in the float slots
-    __shared__ float4 srec[LAT_THREADS + 4][3];
-    __shared__ int scount[NW];
     const int tile = e0.x, lo0 = e0.z, n0 = e0.w, lo1 = e1.x, nv = n0 + e1.y;
     const int tyi = tile / d.ntx, txi = tile - tyi * d.ntx;
     const int x0 = txi * TILE_X, y0 = tyi * TILE_Y;
     const Band B{e0.y, y0 - y0 % d.band_rows, d.band_rows};   // tiles never straddle bands
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const int tw = min(TILE_X, B.nx - x0), th = min(TILE_Y, B.y0 + B.ny - y0);
+    const int lane = threadIdx.x & 63;
+    const int tw = min(TILE_X, B.nx - x0);
     int i, j;
     tile_node(d, tile, i, j);
-    const bool valid = i < B.nx && j < B.y0 + B.ny;
+    if (j >= B.y0 + B.ny) return;   // the whole wave lies beyond the band
+    const bool valid = i < B.nx;
+    // the first candidates' loads go out before the pulls: the gather then
+    // waits for them alone
+    Cand c = load_cand(d, lane, nv, lo0, n0, lo1);
     float h[9];
     if (valid) pull9<T>(d, (const T *)d.pop[PAR], i, j, B, h);
+    // each wave's own records: (origin x, w_y of its row, fx, fy) and w_x
+    __shared__ float4 srec[LAT_THREADS / 64][66][2];
+    float4(*R)[2] = srec[threadIdx.x >> 6];
     float ax = 0.0f, ay = 0.0f;
-    for (int c0 = 0; c0 < nv; c0 += LAT_THREADS) {
-        const Cand ca = load_cand(d, B, c0 + (int)threadIdx.x, nv, lo0, n0, lo1, x0, y0, tw, th);
-        const unsigned long long ma = __ballot(ca.hit);
-        if (lane == 0) scount[wv] = __popcll(ma);
-        __syncthreads();
-        int sa = __popcll(ma & below), tot = 0;
+    for (int c0 = 0; c0 < nv; c0 += 64) {
+        if (c0 > 0) c = load_cand(d, c0 + lane, nv, lo0, n0, lo1);
+        int e = j - c.o.y;
+        if (!d.walls && e < 0) e += B.ny;
+        const bool t = c0 + lane < nv && (unsigned)e < 4u && meets_periodic(c.o.x, x0, tw, B.nx);
+        const float we = e == 0 ? c.wy.x : e == 1 ? c.wy.y : e == 2 ? c.wy.z : c.wy.w;
+        const float4 r0 = make_float4(__int_as_float(c.o.x), we, c.f.x, c.f.y), r1 = c.wx;
+        const unsigned long long m = __ballot(t);
+        const int nt = __popcll(m);
+        if (t) {
+            const int k = __popcll(m & ((1ull << lane) - 1ull));   // keeps candidate order
+            R[k][0] = r0;
+            R[k][1] = r1;
+        }
+        // pad to an even count with a record that reaches no node
+        if (lane < (nt & 1)) {
+            R[nt + lane][0] = make_float4(__int_as_float(-(1 << 30)), 0.0f, 0.0f, 0.0f);
+            R[nt + lane][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int k0 = 0; k0 < nt; k0 += 2)
 #pragma unroll
-        for (int w = 0; w < NW; w++) {
-            sa += (w < wv) ? scount[w] : 0;
-            tot += scount[w];
+        for (int k = k0; k < k0 + 2; k++) {
+            const float4 q0 = R[k][0], q1 = R[k][1];   // broadcast reads
+            int a = i - __float_as_int(q0.x);
+            if (a < 0) a += B.nx;
+            // w = 0 off the stencil; adding 0 f leaves a sum as it is (the
+            // sums start at +0, so they are never -0): no branch
+            const float wl = (a & 1) ? q1.y : q1.x, wh = (a & 1) ? q1.w : q1.z;
+            const float w = (unsigned)a < 4u ? ((a & 2) ? wh : wl) * q0.y : 0.0f;
+            ax += w * q0.z;
+            ay += w * q0.w;
         }
-        if (ca.hit) {
-            srec[sa][0] = ca.wx;
-            srec[sa][1] = ca.wy;
-            srec[sa][2] = make_float4(__int_as_float(ca.o.x), __int_as_float(ca.o.y), ca.f.x, ca.f.y);
-        }
-        // pad to a multiple of four with records that cover no node
-        if ((int)threadIdx.x < ((tot + 3) & ~3) - tot) {
-            const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            srec[tot + threadIdx.x][0] = z;
-            srec[tot + threadIdx.x][1] = z;
-            srec[tot + threadIdx.x][2] = make_float4(__int_as_float(-(1 << 30)), __int_as_float(-(1 << 30)), 0.0f, 0.0f);
-        }
-        __syncthreads();
-        // every lane reads the same record (LDS broadcast); four at a time
-        for (int q = 0; q < tot; q += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const float4 RX = srec[q + u][0], RY = srec[q + u][1], RC = srec[q + u][2];
-                int a = i - __float_as_int(RC.x);
-                if (a < 0) a += B.nx;
-                int e = j - __float_as_int(RC.y);
-                if (!d.walls && e < 0) e += B.ny;
-                if ((unsigned)a < 4u && (unsigned)e < 4u) {
-                    const float wa = a == 0 ? RX.x : a == 1 ? RX.y : a == 2 ? RX.z : RX.w;
-                    const float we = e == 0 ? RY.x : e == 1 ? RY.y : e == 2 ? RY.z : RY.w;
-                    const float w = wa * we;
-                    ax += w * RC.z;
-                    ay += w * RC.w;
-                }
-            }
-        }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();   // the next batch overwrites the records
     }
     if (valid) {
         const float uref = add_rowref(d, j - B.y0, h);

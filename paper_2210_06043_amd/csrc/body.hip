@@ -19,10 +19,19 @@
 
 namespace capib {
 
-constexpr int BT = BODY_THREADS;
-constexpr int VPT = MAXV_BODY / BT;   // vertices per thread
-constexpr int SPT = MAXS_BODY / BT;   // ligand sites per thread
-constexpr int MAX_BOX = 64;           // bounding boxes of the band's bodies cached in LDS
+constexpr int MAX_BOX = 64;   // bounding boxes of the band's bodies cached in LDS
+
+// Workgroup shape of the membrane kernel for membranes of at most MV
+// vertices and 2 MV ligand sites: the LDS it holds scales with MV, so a run
+// of small membranes keeps several workgroups resident per compute unit.
+template <int MV>
+struct BodyShape {
+    static constexpr int MAXV = MV, MAXS = 2 * MV;
+    static constexpr int BT = MV < 512 ? MV : 512;   // threads
+    static constexpr int VPT = MAXV / BT;            // vertices per thread
+    static constexpr int SPT = MAXS / BT;            // ligand sites per thread
+};
+static_assert(BodyShape<MAXV_BODY>::MAXS == MAXS_BODY, "site capacity of the largest class");
 
 // (ah, al) += (bh, bl), renormalised.
 __device__ __forceinline__ void df_add2(float &ah, float &al, float bh, float bl) {
@@ -51,16 +60,18 @@ __device__ __forceinline__ void write_spread(const Dev &d, const Band &B, int g,
     d.sp_f[g] = make_float2(fx, fy);
 }
 
-template <int PAR, bool ENS>
-__global__ __launch_bounds__(BT) void k_body(Dev d) {
-    __shared__ float sxh[MAXV_BODY], sxl[MAXV_BODY], syh[MAXV_BODY], syl[MAXV_BODY];
-    __shared__ float slen[MAXV_BODY], snlx[MAXV_BODY], snly[MAXV_BODY];
-    __shared__ float snvx[MAXV_BODY], snvy[MAXV_BODY], sbend[MAXV_BODY];
-    __shared__ float sSx[MAXV_BODY], sSy[MAXV_BODY];   // spring force k (l - l0) t_hat of each element
-    __shared__ float sHx[MAXV_BODY], sHy[MAXV_BODY];   // half of the element's area, bond and load force
+template <int PAR, bool ENS, int MV>
+__global__ __launch_bounds__(BodyShape<MV>::BT) void k_body(Dev d) {
+    constexpr int MAXV = BodyShape<MV>::MAXV, MAXS = BodyShape<MV>::MAXS;
+    constexpr int BT = BodyShape<MV>::BT, VPT = BodyShape<MV>::VPT, SPT = BodyShape<MV>::SPT;
+    __shared__ float sxh[MAXV], sxl[MAXV], syh[MAXV], syl[MAXV];
+    __shared__ float slen[MAXV], snlx[MAXV], snly[MAXV];
+    __shared__ float snvx[MAXV], snvy[MAXV], sbend[MAXV];
+    __shared__ float sSx[MAXV], sSy[MAXV];   // spring force k (l - l0) t_hat of each element
+    __shared__ float sHx[MAXV], sHy[MAXV];   // half of the element's area, bond and load force
     __shared__ float sbox[MAX_BOX][4];
-    __shared__ float sqxh[MAXV_BODY], sqxl[MAXV_BODY], sqyh[MAXV_BODY], sqyl[MAXV_BODY];   // another body, staged
-    __shared__ float ss_bond[MAXS_BODY];   // Eq. (13) magnitude of each engaged bond (0 if free)
+    __shared__ float sqxh[MAXV], sqxl[MAXV], sqyh[MAXV], sqyl[MAXV];   // another body, staged
+    __shared__ float ss_bond[MAXS];   // Eq. (13) magnitude of each engaged bond (0 if free)
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
 
@@ -549,6 +560,15 @@ hipError_t launch_mark(const Dev &d, int par, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int MV>
+static void go_body(const Dev &d, int par, bool ens, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 g(d.nbodies), t(BodyShape<MV>::BT);
+    if (par)
+        hipExtLaunchKernelGGL(ens ? k_body<1, true, MV> : k_body<1, false, MV>, g, t, 0, st, e0, e1, 0, d);
+    else
+        hipExtLaunchKernelGGL(ens ? k_body<0, true, MV> : k_body<0, false, MV>, g, t, 0, st, e0, e1, 0, d);
+}
+
 hipError_t launch_body(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (d.nbodies == 0) {
         // keep the event pair meaningful for callers that time every phase
@@ -556,12 +576,14 @@ hipError_t launch_body(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hip
         if (e1) return hipEventRecord(e1, st);
         return hipSuccess;
     }
-    // instantiated per step parity and kind of lattice
+    // instantiated per step parity, kind of lattice and membrane size class
     const bool ens = d.nbands > 1;
-    if (par)
-        hipExtLaunchKernelGGL(ens ? k_body<1, true> : k_body<1, false>, dim3(d.nbodies), dim3(BT), 0, st, e0, e1, 0, d);
+    if (d.body_mv <= 256)
+        go_body<256>(d, par, ens, st, e0, e1);
+    else if (d.body_mv <= 512)
+        go_body<512>(d, par, ens, st, e0, e1);
     else
-        hipExtLaunchKernelGGL(ens ? k_body<0, true> : k_body<0, false>, dim3(d.nbodies), dim3(BT), 0, st, e0, e1, 0, d);
+        go_body<MAXV_BODY>(d, par, ens, st, e0, e1);
     return hipGetLastError();
 }
 

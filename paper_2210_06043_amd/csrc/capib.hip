@@ -195,6 +195,11 @@ static void fill_dev(capib_ctx *c) {
     d.counter = (long long *)(b + c->off_scal);
     d.err = (int *)(b + c->off_scal + 8);
     d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites; d.nbands = c->nbands;
+    d.body_mv = 256;
+    for (const BodyHost &bh : c->bodies) {
+        const int need = std::max(bh.n, (bh.n_sites + 1) / 2);
+        while (d.body_mv < need) d.body_mv *= 2;
+    }
     d.band_nx = (const int *)(b + c->off_band);
     d.band_bodies = (const int2 *)(b + c->off_band + 4 * (size_t)c->nbands);
     d.live = (const int *)(b + c->off_live);

@@ -14,7 +14,6 @@ constexpr int LAT_THREADS = TILE_X * TILE_Y;
 constexpr int MAXV_BODY = 1024;    // vertices of one membrane held in LDS
 constexpr int MAXS_BODY = 2048;    // ligand sites of one membrane held in LDS
 constexpr int ARG_BODIES = 16;     // bodies whose index ranges travel with the kernel arguments
-constexpr int BODY_THREADS = 512;
 constexpr int INTERP_THREADS = 256;  // 16 lanes per interpolation point
 
 enum { DEFORMABLE = 0, RIGID = 1, FIXED = 2 };
@@ -95,6 +94,10 @@ struct Dev {
     int4 *elist[2];
     // immersed boundary
     int nbodies, nverts, nsites, nbands;
+    // size class of the membrane kernel: the largest membrane of this run
+    // has at most body_mv vertices and 2 body_mv ligand sites (256, 512 or
+    // MAXV_BODY)
+    int body_mv;
     const int *band_nx;             // width of each band
     // tiles that hold fluid nodes of some band (with several bands of
     // different widths, the tiles beyond a band's width hold none), in

@@ -24,13 +24,12 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
-    """Hash of the lattice-sweep device code (shared header + kernels of
-    lattice.hip, not its host launchers)."""
+    """Hash of the sources of the lattice launches: their device code and the
+    host code that sets their shares of the tiles."""
     csrc = os.path.join(ROOT, "paper_2210_06043_amd", "csrc")
     h = hashlib.sha256()
-    h.update(open(os.path.join(csrc, "capib_dev.hpp"), "rb").read())
-    lat = open(os.path.join(csrc, "lattice.hip"), "rb").read()
-    h.update(lat.split(b"// ---- host launchers")[0])
+    for f in ("capib_dev.hpp", "lattice_dev.hpp", "lattice.hip", "body.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -117,30 +116,33 @@ def measure(cfg, storage, scale, args):
     sim.set_timing(True)
     sim.step(args.steps)
     sim.set_timing(False)
-    ph, n = sim.read_timing()
+    ph, n, swept = sim.read_timing()
     diag = sim.diagnostics()
     nodes = cfg.nx * cfg.ny
-    # dominant kernel: the lattice sweep, 9 reads + 9 writes per node (the
-    # spread records its near tiles read add well under 1 %).  On a small
-    # lattice one sweep after the membrane phase covers every node; on a
-    # large one the far tiles are swept beside that phase and dominate.
+    assert swept.sum() == nodes * n, (swept, nodes, n)   # every node once per step
+    # Dominant lattice kernel, 9 reads + 9 writes per node it sweeps (the
+    # spread records the near tiles read add well under 1 %), with the nodes
+    # each launch swept as the library counted them from each step's
+    # near-tile flags.  On a small lattice the membrane launch (k_body_far)
+    # sweeps a share of the far tiles and the sweep after it the rest; on a
+    # large one the far tiles have a launch beside the membrane phase.
     bytes_per_node = 72 if storage == capib.FP32_SHIFTED else 36
-    far_ms, sweep_ms = ph[2] / n, ph[3] / n
-    split = far_ms > 0
+    names = ["k_interp", "k_body_far", "k_lattice_far", "k_lattice_sweep"]
+    launch_ms = ph / n
+    k = max((1, 2, 3), key=lambda q: launch_ms[q] if swept[q] else -1.0)
+    kernel, kernel_ms = names[k], launch_ms[k]
+    alg_bytes = bytes_per_node * swept[k] / n
+    split = launch_ms[2] > 0
+    # "body_far": the membrane launch that also sweeps far tiles
+    phases = {"interp": round(launch_ms[0] * 1e3, 3), "body_far" if swept[1] else "body": round(launch_ms[1] * 1e3, 3)}
     if split:
-        kernel, kernel_ms = "k_lattice_far", far_ms
-        alg_bytes = bytes_per_node * (nodes - diag["near_tiles"] * 64 * 4)
-    else:
-        kernel, kernel_ms = "k_lattice_sweep", sweep_ms
-        alg_bytes = bytes_per_node * nodes
-    phases = {"interp": round(ph[0] / n * 1e3, 3), "body": round(ph[1] / n * 1e3, 3)}
-    if split:
-        phases["lattice_far"] = round(far_ms * 1e3, 3)
-    phases["lattice_sweep"] = round(sweep_ms * 1e3, 3)
+        phases["lattice_far"] = round(launch_ms[2] * 1e3, 3)
+    phases["lattice_sweep"] = round(launch_ms[3] * 1e3, 3)
+    lattice_ms = sum(launch_ms[q] for q in (1, 2, 3) if swept[q])
     return dict(ms=ms, mlups=nodes * args.steps / (ms * 1e-3) / 1e6, kernel=kernel, kernel_ms=kernel_ms,
                 alg_bytes=alg_bytes, achieved=alg_bytes / (kernel_ms * 1e-3) / 1e9, near_tiles=diag["near_tiles"],
-                phases=phases, whole_sweep_gbs=bytes_per_node * nodes / ((far_ms + sweep_ms) * 1e-3) / 1e9,
-                error_flags=diag["error_flags"])
+                phases=phases, nodes_per_launch={names[q]: int(swept[q] // n) for q in (1, 2, 3) if swept[q]},
+                whole_sweep_gbs=bytes_per_node * nodes / (lattice_ms * 1e-3) / 1e9, error_flags=diag["error_flags"])
 
 
 def batched(args):
@@ -165,10 +167,10 @@ def batched(args):
     sim.set_timing(True)
     sim.step(args.batched_steps)
     sim.set_timing(False)
-    ph, n = sim.read_timing()
+    ph, n, swept = sim.read_timing()
     diag = sim.diagnostics()
     far_ms = ph[2] / n
-    alg = 36 * (nodes - diag["near_tiles"] * 64 * 4)   # live nodes outside the near tiles
+    alg = 36 * swept[2] / n   # nodes of the far tiles, counted per step
     del sim
     torch.cuda.empty_cache()
     # single-instance FP32 step time on an evenly spaced sample of members
@@ -274,8 +276,8 @@ def roofline(m, storage_name, workload_name):
     traffic = counters(f"{m['kernel'][2:]}_{storage_name}_{workload_name}")
     return {"bound": "hbm", "kernel": m["kernel"], "achieved": round(m["achieved"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(m["achieved"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": m["alg_bytes"], "avg_launch_us": round(m["kernel_ms"] * 1e3, 3),
-            "near_tiles": m["near_tiles"]}
+            "algorithmic_bytes_per_launch": int(round(m["alg_bytes"])), "avg_launch_us": round(m["kernel_ms"] * 1e3, 3),
+            "near_tiles": m["near_tiles"], "nodes_per_launch": m["nodes_per_launch"]}
 
 
 def main():

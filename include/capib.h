@@ -263,16 +263,19 @@ capib_status capib_save(capib_ctx *ctx, void *host_buf, size_t *bytes);
 capib_status capib_load(capib_ctx *ctx, const void *host_buf, size_t bytes);
 
 /* Per-kernel timing with HIP events on the context's stream.  While enabled,
- * capib_step runs the kernels of each step in sequence on the caller's
- * stream, each launched with a start/stop event pair stamped at its own
- * start and end, and synchronises at its end.  capib_read_timing returns the
- * summed milliseconds of {interpolation, membrane phase, far-tile sweep,
- * lattice sweep after the membrane phase} (4 doubles) and the number of
- * steps timed, then resets the sums.  The far-tile sweep runs (beside the
- * membrane phase) only on lattices of 8192 tiles of 64 x 4 nodes or more;
- * on smaller ones the last sweep covers every tile and the third sum is 0. */
+ * capib_step runs the launches of each step in sequence on the caller's
+ * stream, each with a start/stop event pair stamped at its own start and
+ * end, and synchronises at its end.  capib_read_timing returns the summed
+ * milliseconds of {interpolation, membrane launch, far-tile launch, lattice
+ * sweep after the membrane phase} (4 doubles), the number of steps timed
+ * and, if nodes4 is not NULL, the summed number of lattice nodes each of
+ * the four launches swept (the interpolation's is 0), then resets the sums.
+ * On lattices of 8192 tiles of 64 x 4 nodes or more the far tiles have a
+ * launch of their own (beside the membrane phase); on smaller ones the
+ * membrane launch sweeps a share of the far tiles and the last sweep the
+ * rest, and the third sums are 0.                                           */
 capib_status capib_set_timing(capib_ctx *ctx, int32_t enable);
-capib_status capib_read_timing(capib_ctx *ctx, double *ms4, int64_t *steps);
+capib_status capib_read_timing(capib_ctx *ctx, double *ms4, int64_t *steps, int64_t *nodes4);
 
 /* Message of the last failing call on this context (never NULL). */
 const char *capib_last_error(const capib_ctx *ctx);

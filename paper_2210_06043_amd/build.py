@@ -18,8 +18,12 @@ LIB = os.path.join(HERE, "libcapib.so")
 SOURCES = ["lattice.hip", "ib.hip", "body.hip", "capib.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# -ffp-contract=on: multiply-adds are fused only within one expression, so a
+# kernel's floating-point results do not depend on the code around it (the
+# same per-node or per-vertex code inlined into different launches rounds
+# the same way, which the ensemble-member bit-identity relies on).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
 
 

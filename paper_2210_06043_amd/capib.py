@@ -76,7 +76,7 @@ SIGNATURES = {
     "capib_save": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
     "capib_load": (C.c_int, [_P, _P, C.c_size_t]),
     "capib_set_timing": (C.c_int, [_P, C.c_int32]),
-    "capib_read_timing": (C.c_int, [_P, _dp, C.POINTER(C.c_int64)]),
+    "capib_read_timing": (C.c_int, [_P, _dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "capib_sample_members": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "capib_last_error": (C.c_char_p, [_P]),
     "capib_destroy": (None, [_P]),
@@ -214,11 +214,14 @@ class Simulation:
         self._check(self.L.capib_set_timing(self.ctx, 1 if enable else 0))
 
     def read_timing(self):
-        """Summed ms of {interpolation, membrane phase, far tiles, near tiles}."""
+        """Summed ms of the {interpolation, membrane, far-tile, sweep} launches,
+        the number of steps timed and the lattice nodes each launch swept."""
         ms = np.zeros(4)
+        nodes = np.zeros(4, dtype=np.int64)
         n = C.c_int64()
-        self._check(self.L.capib_read_timing(self.ctx, _d(ms), C.byref(n)))
-        return ms, n.value
+        self._check(self.L.capib_read_timing(self.ctx, _d(ms), C.byref(n),
+                                             nodes.ctypes.data_as(C.POINTER(C.c_int64))))
+        return ms, n.value, nodes
 
     def synchronize(self):
         self.stream.synchronize()

@@ -16,6 +16,7 @@
 // their operands to keep the number of barriers low.
 #include "capib_dev.hpp"
 #include "capib_kernels.hpp"
+#include "lattice_dev.hpp"
 
 namespace capib {
 
@@ -61,7 +62,7 @@ __device__ __forceinline__ void write_spread(const Dev &d, const Band &B, int g,
 }
 
 template <int PAR, bool ENS, int MV>
-__global__ __launch_bounds__(BodyShape<MV>::BT) void k_body(Dev d) {
+__device__ __forceinline__ void body_run(const Dev &d, const int b) {
     constexpr int MAXV = BodyShape<MV>::MAXV, MAXS = BodyShape<MV>::MAXS;
     constexpr int BT = BodyShape<MV>::BT, VPT = BodyShape<MV>::VPT, SPT = BodyShape<MV>::SPT;
     __shared__ float sxh[MAXV], sxl[MAXV], syh[MAXV], syl[MAXV];
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(BodyShape<MV>::BT) void k_body(Dev d) {
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
 
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     // the next step's near tiles are listed from zero by this step's sweep
     // (the interpolation has read the old count)
     if (b == 0 && tid == 0) d.ncount[PAR ^ 1] = 0;
@@ -557,6 +558,68 @@ __global__ __launch_bounds__(256) void k_mark(Dev d, int par) {
 hipError_t launch_mark(const Dev &d, int par, hipStream_t st) {
     if (d.nverts == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mark, dim3((d.nverts + 255) / 256), dim3(256), 0, st, d, par);
+    return hipGetLastError();
+}
+
+template <int PAR, bool ENS, int MV>
+__global__ __launch_bounds__(BodyShape<MV>::BT) void k_body(Dev d) {
+    body_run<PAR, ENS, MV>(d, blockIdx.x);
+}
+
+// The membrane workgroups first, then BT / 256 far-tile candidates per
+// workgroup up to nfb: on a lattice small enough that one sweep after the
+// membrane phase beats a second stream, these far tiles stream on the
+// compute units that the few membrane workgroups leave idle.
+template <typename T, int PAR, bool ENS, int MV>
+__global__ __launch_bounds__(BodyShape<MV>::BT) void k_body_far(Dev d, int nfb) {
+    if ((int)blockIdx.x < d.nbodies) {
+        body_run<PAR, ENS, MV>(d, blockIdx.x);
+        return;
+    }
+    constexpr int TPW = BodyShape<MV>::BT / LAT_THREADS;
+    const int fb = ((int)blockIdx.x - d.nbodies) * TPW + (int)(threadIdx.x / LAT_THREADS);
+    if (fb < nfb) far_tile<T, PAR, ENS>(d, fb, threadIdx.x % LAT_THREADS);
+}
+
+// Share of the far-tile candidates swept by the membrane launch, in percent
+// (measured on 3840 x 240: the membrane kernel's 8-9 us hide about this much
+// streaming; FP16 tiles cost half the bytes).
+constexpr int FAR_SHARE_FP32 = 50, FAR_SHARE_FP16 = 80;
+
+int body_far_tiles(const Dev &d) {
+    const int ncand = d.nbands > 1 ? d.nlive : d.ntx * d.nty;
+    return (int)((long long)ncand * (d.storage == 0 ? FAR_SHARE_FP32 : FAR_SHARE_FP16) / 100);
+}
+
+template <typename T, int MV>
+static void go_body_far(const Dev &d, int par, bool ens, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    constexpr int TPW = BodyShape<MV>::BT / LAT_THREADS;
+    const int nfb = body_far_tiles(d);
+    const dim3 g(d.nbodies + (nfb + TPW - 1) / TPW), t(BodyShape<MV>::BT);
+    if (par)
+        hipExtLaunchKernelGGL(ens ? k_body_far<T, 1, true, MV> : k_body_far<T, 1, false, MV>, g, t, 0, st, e0, e1, 0,
+                              d, nfb);
+    else
+        hipExtLaunchKernelGGL(ens ? k_body_far<T, 0, true, MV> : k_body_far<T, 0, false, MV>, g, t, 0, st, e0, e1, 0,
+                              d, nfb);
+}
+
+template <typename T>
+static void body_far_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const bool ens = d.nbands > 1;
+    if (d.body_mv <= 256)
+        go_body_far<T, 256>(d, par, ens, st, e0, e1);
+    else if (d.body_mv <= 512)
+        go_body_far<T, 512>(d, par, ens, st, e0, e1);
+    else
+        go_body_far<T, MAXV_BODY>(d, par, ens, st, e0, e1);
+}
+
+hipError_t launch_body_far(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (d.storage == 0)
+        body_far_of<float>(d, par, st, e0, e1);
+    else
+        body_far_of<_Float16>(d, par, st, e0, e1);
     return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct capib_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     double ms[4] = {0, 0, 0, 0};
+    long long nodes[4] = {0, 0, 0, 0};   // lattice nodes swept per phase
     long long tsteps = 0;
     // graphs
     bool use_graph = false;
@@ -718,8 +719,8 @@ static capib_status ensure_marks(capib_ctx *c) {
 static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_t side, int k) {
     if (!lattice_split(c->d)) {
         HIPCHK(c, launch_interp(c->d, par, main));
-        HIPCHK(c, launch_body(c->d, par, main));
-        HIPCHK(c, launch_lattice_sweep(c->d, par, main));
+        HIPCHK(c, launch_body_far(c->d, par, main));
+        HIPCHK(c, launch_lattice_sweep(c->d, par, main, nullptr, nullptr, body_far_tiles(c->d)));
         return CAPIB_OK;
     }
     HIPCHK(c, hipEventRecord(c->ev_fork[k], main));
@@ -763,20 +764,37 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
             HIPCHK(c, hipEventCreate(&e));
             c->ev.push_back(e);
         }
+        // the nodes each lattice launch sweeps, counted after every step
+        // (untimed) from that step's near-tile flags
+        const bool split = lattice_split(c->d);
+        const int nfb = split ? 0 : body_far_tiles(c->d);
+        unsigned long long *cens = (unsigned long long *)(c->base + c->off_scal + 32);
+        HIPCHK(c, hipMemsetAsync(cens, 0, 24, c->stream));
         for (int t = 0; t < nsteps; t++) {
             hipEvent_t *e = &c->ev[8 * t];
             HIPCHK(c, launch_interp(c->d, c->par, c->stream, e[0], e[1]));
-            HIPCHK(c, launch_body(c->d, c->par, c->stream, e[2], e[3]));
-            if (lattice_split(c->d)) HIPCHK(c, launch_lattice_far(c->d, c->par, c->stream, e[4], e[5]));
-            HIPCHK(c, launch_lattice_sweep(c->d, c->par, c->stream, e[6], e[7]));
+            if (split) {
+                HIPCHK(c, launch_body(c->d, c->par, c->stream, e[2], e[3]));
+                HIPCHK(c, launch_lattice_far(c->d, c->par, c->stream, e[4], e[5]));
+            } else {
+                HIPCHK(c, launch_body_far(c->d, c->par, c->stream, e[2], e[3]));
+            }
+            HIPCHK(c, launch_lattice_sweep(c->d, c->par, c->stream, e[6], e[7], nfb));
+            HIPCHK(c, launch_census(c->d, c->par, nfb, cens, c->stream));
             c->par ^= 1;
             c->step++;
         }
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        unsigned long long cn[3];
+        capib_status s2 = d2h(c, cn, c->off_scal + 32, sizeof cn);
+        if (s2) return s2;
+        c->nodes[1] += (long long)cn[0];
+        c->nodes[split ? 2 : 3] += (long long)cn[1];
+        c->nodes[3] += (long long)cn[2];
         for (int t = 0; t < nsteps; t++) {
             hipEvent_t *e = &c->ev[8 * t];
             for (int k = 0; k < 4; k++) {
-                if (k == 2 && !lattice_split(c->d)) continue;   // no far-tile sweep
+                if (k == 2 && !split) continue;   // no far-tile launch
                 float ms = 0;
                 HIPCHK(c, hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]));
                 c->ms[k] += ms;
@@ -1050,9 +1068,14 @@ capib_status capib_set_timing(capib_ctx *c, int32_t enable) {
     return CAPIB_OK;
 }
 
-capib_status capib_read_timing(capib_ctx *c, double *ms4, int64_t *steps) {
+capib_status capib_read_timing(capib_ctx *c, double *ms4, int64_t *steps, int64_t *nodes4) {
     if (!c || !ms4) return CAPIB_E_ARG;
-    for (int k = 0; k < 4; k++) { ms4[k] = c->ms[k]; c->ms[k] = 0; }
+    for (int k = 0; k < 4; k++) {
+        ms4[k] = c->ms[k];
+        if (nodes4) nodes4[k] = c->nodes[k];
+        c->ms[k] = 0;
+        c->nodes[k] = 0;
+    }
     if (steps) *steps = c->tsteps;
     c->tsteps = 0;
     return CAPIB_OK;

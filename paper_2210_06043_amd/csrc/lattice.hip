@@ -2,115 +2,13 @@
 // walls (Eq. 1; no-slip capillary walls of Sec. 3.1), moments (Sec. 2.1,
 // Eqs. 5-6), the Hermite equilibrium (Eq. 2) and the BGK collision with the
 // Guo forcing term (Eq. 4) for the total force g + f_ib, fused in one pass
-// that reads 9 and writes 9 populations per node.
-//
-// Layout: structure of arrays pop[q][j][i], i fastest, row pitch a multiple
-// of 64 elements, two buffers swapped every step.  Populations are stored as
-// deviations h = f - w from the rest state, FP32 or FP16 (scaled).
+// that reads 9 and writes 9 populations per node (the per-node code is in
+// lattice_dev.hpp).
 #include "capib_dev.hpp"
 #include "capib_kernels.hpp"
+#include "lattice_dev.hpp"
 
 namespace capib {
-
-template <typename T>
-__device__ __forceinline__ T stpop(float v, float scale);
-template <>
-__device__ __forceinline__ float stpop<float>(float v, float) { return v; }
-template <>
-__device__ __forceinline__ _Float16 stpop<_Float16>(float v, float scale) { return (_Float16)(v * scale); }
-
-// Node (i, j) of a 64x4 tile: i runs along the wave, j is wave-uniform (one
-// wave per row, so the row reference is read once per wave).
-__device__ __forceinline__ void tile_node(const Dev &d, int tile, int &i, int &j) {
-    const int ty = tile / d.ntx;
-    const int tx = tile - ty * d.ntx;
-    i = tx * TILE_X + (threadIdx.x & (TILE_X - 1));
-    j = __builtin_amdgcn_readfirstlane(ty * TILE_Y + (int)(threadIdx.x / TILE_X));
-}
-
-// Collision of one node from its pulled deviations h (Eq. 1 with the Guo
-// term of Eq. 4), for the total force (Fx, Fy) = g + f_ib: the post-collision
-// deviations out[9].
-__device__ __forceinline__ void collide_core(const Dev &d, const float h[9], float uref, float Fx, float Fy,
-                                             float out[9]) {
-    // moments of the streamed deviations: drho, and j - u_ref x
-    const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-    const float jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
-    const float jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
-
-    const float rho = 1.0f + drho;
-    const float irho = __builtin_amdgcn_rcpf(rho);   // hardware reciprocal (1 ulp)
-    // u = (j + F/2)/rho written as u_ref + du with du from deviations only
-    const float dux = (jx + 0.5f * Fx - drho * uref) * irho;
-    const float duy = (jy + 0.5f * Fy) * irho;
-    const EqDev E(drho, uref, dux, duy);
-    const float ux = E.ux, uy = E.uy;
-    const float uu = ux * ux + uy * uy;
-    if (!(rho > 0.0f) || !(uu < 0.03f)) atomicOr(d.err, FLAG_FLUID);  // NaN fails both tests
-
-    // s'_i = (1 - omega) dh_i + omega (h_eq_i - r_i) + F_i with the Guo term
-    // F_i = (1 - omega/2) w [3 (e - u).F + 9 (e.u)(e.F)]
-    const float om = d.omega, om1 = 1.0f - d.omega, fc = d.fc;
-    const float uF = ux * Fx + uy * Fy;
-    const float fb = -3.0f * uF;                 // 3 (-u).F
-    {
-        const float w = 4.0f / 9.0f;
-        out[0] = om1 * h[0] + om * E(0.0f, 0.0f, w) + fc * w * fb;
-    }
-    // The other directions in opposite pairs (e, -e).  With eu = e.u,
-    // edu = e.du and eF = e.F, h_eq - r splits into w S, even in e, with
-    // S = c0 + 4.5 drho eu^2 + 4.5 edu (eu + e.u_ref), and w A, odd in e,
-    // with A = 3 (drho eu + edu); the Guo term into fc w (fb + 9 eu eF), even,
-    // and fc w 3 eF, odd.  So s'_{+-e} = (1 - omega) dh + w (P +- M).
-#define CAPIB_PAIR(q, qb, ex, ey, w)                                                         \
-    {                                                                                        \
-        const float eu = (ex) * ux + (ey) * uy;                                              \
-        const float edu = (ex) * E.dux + (ey) * E.duy;                                       \
-        const float eF = (ex) * Fx + (ey) * Fy;                                              \
-        const float S = E.c0 + 4.5f * (drho * eu * eu + edu * (eu + (ex) * uref));           \
-        const float A = 3.0f * (drho * eu + edu);                                            \
-        const float P = om * S + fc * (fb + 9.0f * eu * eF);                                 \
-        const float M = om * A + fc * (3.0f * eF);                                           \
-        out[q] = om1 * h[q] + (w) * (P + M);                                                 \
-        out[qb] = om1 * h[qb] + (w) * (P - M);                                               \
-    }
-    CAPIB_PAIR(1, 3, 1.0f, 0.0f, 1.0f / 9.0f)
-    CAPIB_PAIR(2, 4, 0.0f, 1.0f, 1.0f / 9.0f)
-    CAPIB_PAIR(5, 7, 1.0f, 1.0f, 1.0f / 36.0f)
-    CAPIB_PAIR(6, 8, -1.0f, 1.0f, 1.0f / 36.0f)
-#undef CAPIB_PAIR
-}
-
-// Collision and store of node (i, j).
-template <typename T>
-__device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, int j, const float h[9], float uref,
-                                                float Fx, float Fy) {
-    T *__restrict__ B = (T *)d.pop[par ^ 1];
-    const long long node = (long long)j * d.pitch + i;
-    float out[9];
-    collide_core(d, h, uref, Fx, Fy, out);
-    const long long Q = d.qstride;
-#pragma unroll
-    for (int q = 0; q < 9; q++) B[q * Q + node] = stpop<T>(out[q], d.scale);
-}
-
-// A far tile: one that is not near in this step (its flag is clear), swept
-// with the body force alone.  b indexes the far-tile workgroups, mapped in
-// XCD-contiguous order to every tile (with several bands: to every tile
-// that holds fluid nodes).
-template <typename T, int PAR, bool ENS>
-__device__ __forceinline__ void far_tile(const Dev &d, int b) {
-    const int tile = ENS ? d.live[xcd_tile(b, d.nlive)] : xcd_tile(b, d.ntx * d.nty);
-    if (d.tnear[PAR][tile]) return;
-    int i, j;
-    tile_node(d, tile, i, j);
-    if (j >= d.ny) return;
-    const Band B = band_at_row<ENS>(d, j);   // wave-uniform
-    if (i >= B.nx) return;
-    float h[9];
-    const float uref = pull_dev<T>(d, (const T *)d.pop[PAR], i, j, B, h);
-    lattice_collide<T>(d, PAR, i, j, h, uref, d.gx, d.gy);
-}
 
 // A far tile's inputs, loaded ahead of its collision.
 struct FarIn {
@@ -398,7 +296,7 @@ __device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int
 }
 
 template <typename T, int PAR, bool ENS, bool FULL, bool PAIRS>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark, int nlb) {
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark, int nlb, int fb0) {
     if ((int)blockIdx.x < nmark) {
         mark_next<PAR ^ 1, ENS, PAIRS>(d, blockIdx.x);
         return;
@@ -419,7 +317,7 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark,
         }
         return;
     }
-    if (FULL) far_tile<T, PAR, ENS>(d, bid - nlb);
+    if (FULL) far_tile<T, PAR, ENS>(d, fb0 + bid - nlb);
 }
 
 // Moments of the current state for read-out: drho and u* = (j + g/2)/rho
@@ -545,38 +443,70 @@ bool lattice_split(const Dev &d) { return d.ntx * d.nty >= SPLIT_MIN_TILES; }
 constexpr int PAIRS_MAX_VERTS = 16384;
 
 template <typename T, int P, bool E, bool PA>
-static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
     constexpr int mv = mark_verts<PA>();
     const int nmark = (d.nverts + mv - 1) / mv;
     const int nt = d.ntx * d.nty;
     const int want = d.nverts / 8 > 1024 ? d.nverts / 8 : 1024;
     const int nlb = nt < want ? nt : want;
     if (!lattice_split(d))
-        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true, PA>), dim3(nmark + nlb + (E ? d.nlive : nt)),
-                              dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark, nlb);
+        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true, PA>), dim3(nmark + nlb + (E ? d.nlive : nt) - fb0),
+                              dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark, nlb, fb0);
     else
         hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, false, PA>), dim3(nmark + nlb), dim3(LAT_THREADS), 0, st, e0,
-                              e1, 0, d, nmark, nlb);
+                              e1, 0, d, nmark, nlb, 0);
 }
 template <typename T, int P, bool E>
-static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
     if (d.nverts < PAIRS_MAX_VERTS)
-        go_sweep<T, P, E, true>(d, st, e0, e1);
+        go_sweep<T, P, E, true>(d, st, e0, e1, fb0);
     else
-        go_sweep<T, P, E, false>(d, st, e0, e1);
+        go_sweep<T, P, E, false>(d, st, e0, e1, fb0);
 }
 template <typename T>
-static void sweep_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static void sweep_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
     const bool ens = d.nbands > 1;
-    if (par) ens ? go_sweep<T, 1, true>(d, st, e0, e1) : go_sweep<T, 1, false>(d, st, e0, e1);
-    else ens ? go_sweep<T, 0, true>(d, st, e0, e1) : go_sweep<T, 0, false>(d, st, e0, e1);
+    if (par) ens ? go_sweep<T, 1, true>(d, st, e0, e1, fb0) : go_sweep<T, 1, false>(d, st, e0, e1, fb0);
+    else ens ? go_sweep<T, 0, true>(d, st, e0, e1, fb0) : go_sweep<T, 0, false>(d, st, e0, e1, fb0);
 }
 
-hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
     if (d.storage == 0)
-        sweep_of<float>(d, par, st, e0, e1);
+        sweep_of<float>(d, par, st, e0, e1, fb0);
     else
-        sweep_of<_Float16>(d, par, st, e0, e1);
+        sweep_of<_Float16>(d, par, st, e0, e1, fb0);
+    return hipGetLastError();
+}
+
+// Nodes swept by the lattice launches of a step, for the timing accounting:
+// out[0] += far-tile nodes among the candidates b < nfb (swept by the
+// membrane launch), out[1] += the other far-tile nodes, out[2] += near-tile
+// nodes.  One thread per candidate tile.
+template <bool ENS>
+__global__ __launch_bounds__(256) void k_census(Dev d, int par, int nfb, unsigned long long *out) {
+    const int ncand = ENS ? d.nlive : d.ntx * d.nty;
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    int c[3] = {0, 0, 0};
+    if (b < ncand) {
+        const int tile = ENS ? d.live[xcd_tile(b, ncand)] : xcd_tile(b, ncand);
+        const int ty = tile / d.ntx, tx = tile - ty * d.ntx;
+        const int x0 = tx * TILE_X, y0 = ty * TILE_Y;
+        const Band B = band_at_row<ENS>(d, y0);   // a tile lies in one band
+        const int n = max(0, min(TILE_X, B.nx - x0)) * max(0, min(TILE_Y, d.ny - y0));
+        c[d.tnear[par][tile] ? 2 : b < nfb ? 0 : 1] = n;
+    }
+    for (int k = 0; k < 3; k++) {
+        const int s = wave_sum(c[k]);
+        if ((threadIdx.x & 63) == 0 && s) atomicAdd(out + k, (unsigned long long)s);
+    }
+}
+
+hipError_t launch_census(const Dev &d, int par, int nfb, unsigned long long *out, hipStream_t st) {
+    const int ncand = d.nbands > 1 ? d.nlive : d.ntx * d.nty;
+    if (d.nbands > 1)
+        hipLaunchKernelGGL(k_census<true>, dim3((ncand + 255) / 256), dim3(256), 0, st, d, par, nfb, out);
+    else
+        hipLaunchKernelGGL(k_census<false>, dim3((ncand + 255) / 256), dim3(256), 0, st, d, par, nfb, out);
     return hipGetLastError();
 }
 

@@ -127,10 +127,15 @@ __device__ __forceinline__ bool mark_pass(const Dev &d, bool pend, int tile, int
 
 // The leaders' flag exchanges (all in flight together: a returned value kept
 // across the loops of mark_pass would hold each iteration until the previous
-// one returned), then one list-counter update per wave for its fresh tiles.
+// one returned), then one list-counter update per workgroup for its fresh
+// tiles (the counter is a single address that every marking workgroup
+// updates: one update per wave kept it busy for tens of microseconds).
+// Called by every thread of the workgroup.
 template <int NPAR, int NP>
 __device__ __forceinline__ void mark_append(const Dev &d, const bool (&led)[NP], const int (&tl)[NP]) {
-    const int lane = threadIdx.x & 63;
+    constexpr int NW = LAT_THREADS / 64;
+    __shared__ int swave[NW], sbase;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     bool fresh[NP];
 #pragma unroll
     for (int r = 0; r < NP; r++) fresh[r] = led[r] && atomicExch(&d.tnear[NPAR][tl[r]], 1) == 0;
@@ -141,10 +146,19 @@ __device__ __forceinline__ void mark_append(const Dev &d, const bool (&led)[NP],
         fm[r] = __ballot(fresh[r]);
         total += __popcll(fm[r]);
     }
+    if (lane == 0) swave[wv] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) t += swave[w];
+        sbase = t ? atomicAdd(&d.ncount[NPAR], t) : 0;
+    }
+    __syncthreads();
     if (total) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&d.ncount[NPAR], total);
-        base = __shfl(base, 0);
+        int base = sbase;
+#pragma unroll
+        for (int w = 0; w < NW; w++) base += w < wv ? swave[w] : 0;
         const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
         for (int r = 0; r < NP; r++) {

@@ -29,7 +29,7 @@ __device__ __forceinline__ void far_load(const Dev &d, int c, FarIn &f) {
 
 // Far tiles on a large lattice, concurrently with the immersed-boundary
 // phase: two consecutive candidates per workgroup (pairs in XCD-contiguous
-// order), both tiles' loads in flight together.
+// order), both tiles' loads in flight together, streaming stores.
 template <typename T, int PAR, bool ENS>
 __global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int n) {
     const int c0 = 2 * xcd_tile(blockIdx.x, gridDim.x);
@@ -37,8 +37,8 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int n) {
     f1.go = false;
     far_load<T, PAR, ENS>(d, c0, f0);
     if (c0 + 1 < n) far_load<T, PAR, ENS>(d, c0 + 1, f1);
-    if (f0.go) lattice_collide<T>(d, PAR, f0.i, f0.j, f0.h, f0.uref, d.gx, d.gy);
-    if (f1.go) lattice_collide<T>(d, PAR, f1.i, f1.j, f1.h, f1.uref, d.gx, d.gy);
+    if (f0.go) lattice_collide<T, true>(d, PAR, f0.i, f0.j, f0.h, f0.uref, d.gx, d.gy);
+    if (f1.go) lattice_collide<T, true>(d, PAR, f1.i, f1.j, f1.h, f1.uref, d.gx, d.gy);
 }
 
 // Does a 4-wide stencil starting at o (wrapped into [0, n)) meet the range
@@ -245,7 +245,7 @@ __device__ __forceinline__ Cand load_cand(const Dev &d, int u, int nv, int lo0, 
 // rows in candidate order, with the y weight of the row already chosen, and
 // every lane then reads each record in turn (broadcast); a node adds
 // w_x w_y f of the vertices whose stencil holds it, in candidate order.
-template <typename T, int PAR>
+template <typename T, int PAR, bool NT>
 __device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int4 e1) {
     const int tile = e0.x, lo0 = e0.z, n0 = e0.w, lo1 = e1.x, nv = n0 + e1.y;
     const int tyi = tile / d.ntx, txi = tile - tyi * d.ntx;
@@ -305,7 +305,7 @@ __device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int
     }
     if (valid) {
         const float uref = add_rowref(d, j - B.y0, h);
-        lattice_collide<T>(d, PAR, i, j, h, uref, d.gx + ax, d.gy + ay);
+        lattice_collide<T, NT>(d, PAR, i, j, h, uref, d.gx + ax, d.gy + ay);
     }
 }
 
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark,
                 e0 = E[2 * k];
                 e1 = E[2 * k + 1];
             }
-            near_tile<T, PAR>(d, e0, e1);
+            near_tile<T, PAR, !FULL>(d, e0, e1);   // streaming stores on a large lattice
         }
         return;
     }

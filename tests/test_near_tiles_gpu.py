@@ -67,3 +67,46 @@ def test_near_tiles_large_ensemble():
     _check(sim, cfgs, first, "64-member ensemble at creation")
     sim.step(48)
     _check(sim, cfgs, first, "64-member ensemble after 48 steps")
+
+
+def _census(sim, steps):
+    sim.set_timing(True)
+    sim.step(steps)
+    sim.set_timing(False)
+    ms, n, nodes = sim.read_timing()
+    assert n == steps and np.all(ms[[0, 3]] > 0)
+    return ms, nodes
+
+
+@pytest.mark.parametrize("storage", [capib.FP32_SHIFTED, capib.FP16_SHIFTED])
+def test_timing_node_census_small_lattice(storage):
+    """Event-timed steps report, per launch, the nodes it swept: every node
+    once per step, the near tiles' nodes in the sweep, a share of the far
+    tiles in the membrane launch, none in a separate far launch."""
+    cfg = inputs.config_c2(seed=2)
+    sim = capib.from_config(cfg, storage=storage,
+                            fp16_scale=capib.fp16_scale_for(cfg) if storage == capib.FP16_SHIFTED else 1.0)
+    sim.step(8)
+    near = sim.diagnostics()["near_tiles"]
+    ms, nodes = _census(sim, 4)
+    total = cfg.nx * cfg.ny * 4
+    say(f"census {nodes.tolist()} of {total}, near tiles {near}, ms {np.round(ms, 3).tolist()}")
+    assert nodes[0] == 0 and nodes[2] == 0 and ms[2] == 0
+    assert nodes.sum() == total
+    assert nodes[3] >= near * 256 * 4 * 0.9                     # near tiles move little in 4 steps
+    assert 0.3 * total < nodes[1] < 0.9 * total                  # the membrane launch's share
+    assert nodes[1] % 256 == 0 and nodes[3] % 256 == 0           # whole tiles (3840 x 240)
+
+
+def test_timing_node_census_large_ensemble():
+    """On the large ensemble the far tiles have their own launch: it and the
+    sweep share every fluid node of every member once per step."""
+    cfgs = inputs.config_c3(seed=0, members=64)
+    sim, first = capib.from_ensemble(cfgs, storage=capib.FP16_SHIFTED, fp16_scale=capib.fp16_scale_for(cfgs[0]))
+    sim.step(8)
+    ms, nodes = _census(sim, 3)
+    fluid = sum(c.nx * c.ny for c in cfgs) * 3
+    say(f"census {nodes.tolist()} of {fluid}, ms {np.round(ms, 3).tolist()}")
+    assert nodes[0] == 0 and nodes[1] == 0 and ms[2] > 0
+    assert nodes[2] + nodes[3] == fluid
+    assert 0 < nodes[3] < nodes[2]

@@ -215,10 +215,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // Inference in one kernel: a block takes 128 rows of the batch through all
 // five layers with the activations resident in LDS (bfloat16, written back
 // in place once every wave has read the layer's input), the weights read
-// from L2, and only the input and the 3 outputs touching HBM.  Waves in a
-// 2 x 2 arrangement: 64 rows x 128 columns (2 x 4 accumulators) of each
-// hidden layer; the output layer's first 32 rows of W4, 32 batch rows per
-// wave.  Same rounding points as the layer-by-layer path.
+// from L2, and only the input and the 3 outputs touching HBM.  Each wave
+// takes all 128 rows x 64 columns (4 x 2 accumulators) of each hidden
+// layer, so every weight is read from L2 once per block (a 2 x 2
+// arrangement read each twice: 101 against 85 us per 65,536 rows); the
+// output layer's first 32 rows of W4, 32 batch rows per wave.  Same
+// rounding points as the layer-by-layer path.
 constexpr int IB = 128;             // batch rows per block
 constexpr int ILD = H + 8;          // LDS row stride (bfloat16 elements)
 
@@ -230,40 +232,37 @@ struct InferArgs {
     float *y;
 };
 
-// One hidden layer's products for a wave: 64 rows x 128 columns of
-// S (LDS, bfloat16) times W^T (global, [256][K]).  The weight fragments of
-// the next D k-steps are in flight while the current one is multiplied
-// (their L2 latency is several times one step's matrix work).
+// One hidden layer's products for a wave: all 128 rows x 64 columns of
+// S (LDS, bfloat16) times W^T (global, [256][K]); the four waves split the
+// columns, so each weight is read from L2 once per block.  The weight
+// fragments of the next D k-steps are in flight while the current one is
+// multiplied (their L2 latency is several times one step's matrix work).
 template <int K>
-__device__ __forceinline__ void hidden_layer(const __bf16 (*S)[ILD], const __bf16 *W, floatx16 (&acc)[2][4], int wm,
-                                             int wn, int lane) {
-    constexpr int NI = K / 16, D = 4;
+__device__ __forceinline__ void hidden_layer(const __bf16 (*S)[ILD], const __bf16 *W, floatx16 (&acc)[4][2], int wn,
+                                             int lane) {
+    constexpr int NI = K / 16, D = 6;
     const int r = lane & 31, kh = 8 * (lane >> 5);
-    const __bf16 *w0 = W + (long long)(128 * wn + r) * K + kh;
-    bf16x8 pb[D][4];
+    const __bf16 *w0 = W + (long long)(64 * wn + r) * K + kh;
+    bf16x8 pb[D][2];
 #pragma unroll
     for (int p = 0; p < D && p < NI; p++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) pb[p][j] = *(const bf16x8 *)(w0 + (long long)32 * j * K + 16 * p);
+        for (int j = 0; j < 2; j++) pb[p][j] = *(const bf16x8 *)(w0 + (long long)32 * j * K + 16 * p);
 #pragma unroll
     for (int it = 0; it < NI; it++) {
         const int slot = it % D;
-        const bf16x8 b0 = pb[slot][0], b1 = pb[slot][1], b2 = pb[slot][2], b3 = pb[slot][3];
+        const bf16x8 b0 = pb[slot][0], b1 = pb[slot][1];
         if (it + D < NI) {
 #pragma unroll
-            for (int j = 0; j < 4; j++) pb[slot][j] = *(const bf16x8 *)(w0 + (long long)32 * j * K + 16 * (it + D));
+            for (int j = 0; j < 2; j++) pb[slot][j] = *(const bf16x8 *)(w0 + (long long)32 * j * K + 16 * (it + D));
         }
         const int kq = 16 * it + kh;
-        const bf16x8 a0 = *(const bf16x8 *)&S[64 * wm + r][kq];
-        const bf16x8 a1 = *(const bf16x8 *)&S[64 * wm + 32 + r][kq];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
-        acc[0][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b2, acc[0][2], 0, 0, 0);
-        acc[1][2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b2, acc[1][2], 0, 0, 0);
-        acc[0][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b3, acc[0][3], 0, 0, 0);
-        acc[1][3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b3, acc[1][3], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const bf16x8 a = *(const bf16x8 *)&S[32 * i + r][kq];
+            acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[i][0], 0, 0, 0);
+            acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[i][1], 0, 0, 0);
+        }
     }
 }
 
@@ -271,36 +270,36 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(InferArgs g) {
     __shared__ __bf16 S[IB][ILD];
     const int r0 = blockIdx.x * IB;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wm = w & 1, wn = w >> 1, r = lane & 31;
+    const int r = lane & 31;
     for (int e = threadIdx.x; e < IB * K0P; e += 256) {
         const int rr = e / K0P, c = e % K0P;
         S[rr][c] = (__bf16)((r0 + rr < g.n && c < KIN) ? g.x[(long long)(r0 + rr) * KIN + c] : 0.0f);
     }
     __syncthreads();
     for (int l = 0; l < NL - 1; l++) {
-        floatx16 acc[2][4];
+        floatx16 acc[4][2];
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int j = 0; j < 4; j++) acc[i][j] = floatx16{};
+            for (int j = 0; j < 2; j++) acc[i][j] = floatx16{};
         if (l == 0)
-            hidden_layer<K0P>(S, g.w[0], acc, wm, wn, lane);
+            hidden_layer<K0P>(S, g.w[0], acc, w, lane);
         else
-            hidden_layer<H>(S, g.w[l], acc, wm, wn, lane);
+            hidden_layer<H>(S, g.w[l], acc, w, lane);
         __syncthreads();   // every wave has read this layer's input
         const float *bias = g.b[l];
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            const int col = 64 * w + 32 * j + r;
+            const float bc = bias[col];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int col = 128 * wn + 32 * j + r;
-                const float bc = bias[col];
+            for (int i = 0; i < 4; i++)
 #pragma unroll
                 for (int e = 0; e < 16; e++) {
-                    const int row = 64 * wm + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                    const int row = 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
                     S[row][col] = (__bf16)gelu(acc[i][j][e] + bc);
                 }
-            }
+        }
         __syncthreads();
     }
     // output layer

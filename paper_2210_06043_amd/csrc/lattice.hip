@@ -56,12 +56,14 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
 // wave (see mark_next).  The next nlb workgroups sweep this step's near tiles from the list that the
 // previous step's marking built (grid-stride, one workgroup per tile while
 // there are enough).  On a lattice of fewer than SPLIT_MIN_TILES tiles the
-// last part is every far tile, one workgroup each, dispatched after the
-// near tiles so that their longer latency chains start first: a single
-// sweep after the membrane phase costs less there than far tiles run beside
-// that phase on a second stream, whose cross-stream dependencies cost more
-// than the far tiles themselves.  On a larger lattice the far tiles are
-// swept beside the membrane phase instead (k_lattice_far).
+// last part is the far tiles that the membrane launch (k_body_far) left,
+// from candidate fb0 on, one workgroup each, dispatched after the near
+// tiles so that their longer latency chains start first: there, far tiles
+// in the membrane launch and in this sweep cost less than far tiles run
+// beside the membrane phase on a second stream, whose cross-stream
+// dependencies cost more than the far tiles themselves.  On a larger
+// lattice the far tiles are swept beside the membrane phase instead
+// (k_lattice_far).
 //
 // Spreading (Sec. 2.2) is done as a gather: each wave of a near tile's
 // workgroup (one tile row) loads the spread records of the tile's vertex

@@ -24,12 +24,17 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
-    """Hash of the sources of the lattice launches: their device code and the
-    host code that sets their shares of the tiles."""
+    """Hash of the sources of the lattice launches (their device code and the
+    host code that sets their shares of the tiles), comments and blank lines
+    left out, so that the counters stay valid across edits of the text."""
+    import re
     csrc = os.path.join(ROOT, "paper_2210_06043_amd", "csrc")
     h = hashlib.sha256()
     for f in ("capib_dev.hpp", "lattice_dev.hpp", "lattice.hip", "body.hip"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        for line in open(os.path.join(csrc, f), encoding="utf-8"):
+            code = re.sub(r"//.*", "", line).rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -220,7 +220,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 def surrogate_section(args, batched_out):
     """The load/hazard surrogate: trained on the solver's samples of the
-    256 capillaries of the batched workload, judged on 32 capillaries of
+    256 capillaries of the batched workload, evaluated on 32 capillaries of
     another draw; its inference rate on the matrix cores and what it buys
     when it screens the sweep."""
     import torch
@@ -259,7 +259,7 @@ def surrogate_section(args, batched_out):
     out = {
         "workload": f"MLP 37 -> 4 x 256 (GELU) -> 3, BF16 operands / FP32 accumulation (MFMA 32x32x16); "
                     f"trained on {X.shape[0]} solver samples of {len(tr)} capillaries, "
-                    f"judged on {X2.shape[0]} of {len(te)} unseen capillaries",
+                    f"evaluated on {X2.shape[0]} of {len(te)} unseen capillaries",
         "train_steps": args.train_steps, "train_batch": 4096, "ms_per_train_step": round(ms_train, 4),
         "heldout_mse_standardised": {"drag": round(float(err[0]), 4), "lift": round(float(err[1]), 4),
                                      "hazard": round(float(err[2]), 4)},

@@ -8,7 +8,7 @@
  * rupture hazard, the mean Bell rupture probability of its engaged bonds,
  * Sec. 2.5).  Four hidden layers of width 256 with GELU, a linear output.
  * It screens a parameter sweep before the full LBM-IB solver is run; the
- * solver produces its training data and judges its error.
+ * solver produces its training data and measures its error.
  *
  * Arithmetic: bfloat16 inputs, weights and activations, FP32 accumulation
  * on the matrix cores; FP32 master weights updated by Adam.  Rounding to

@@ -341,15 +341,17 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
             Fy += fvy[k];
             M += armx * fvy[k] - army * fvx[k];
         }
-        Fx = wave_sum(Fx);
-        Fy = wave_sum(Fy);
-        M = wave_sum(M);
+        Fx = wave_reduce(Fx, OpAdd());
+        Fy = wave_reduce(Fy, OpAdd());
+        M = wave_reduce(M, OpAdd());
         if ((tid & 63) == 0) { shf[tid >> 6][0] = Fx; shf[tid >> 6][1] = Fy; shf[tid >> 6][2] = M; }
         __syncthreads();
         // every thread sums the wave partials in the same order and takes
-        // the same rigid update (no second barrier); thread 0 stores it
+        // the same rigid update (no second barrier); thread 0 stores it.
+        // Waves past the last vertex hold +0 and are left out.
+        const int nw = min(BT / 64, (n + 63) / 64);
         Fx = 0.0f; Fy = 0.0f; M = 0.0f;
-        for (int w = 0; w < BT / 64; w++) { Fx += shf[w][0]; Fy += shf[w][1]; M += shf[w][2]; }
+        for (int w = 0; w < nw; w++) { Fx += shf[w][0]; Fy += shf[w][1]; M += shf[w][2]; }
         const float ux = (2.0f / 3.0f) * (2.0f * RS1.z - 0.5f * RS2.x + Fx * P.inv_mass);
         const float uy = (2.0f / 3.0f) * (2.0f * RS1.w - 0.5f * RS2.y + Fy * P.inv_mass);
         const float om = (2.0f / 3.0f) * (2.0f * RS2.z - 0.5f * RS2.w + M * P.inv_inertia);
@@ -488,15 +490,11 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         xmin = fminf(xmin, x); xmax = fmaxf(xmax, x);
         ymin = fminf(ymin, y); ymax = fmaxf(ymax, y);
     }
-    float fc = (float)cnt;
-#pragma unroll
-    for (int msk = 32; msk >= 1; msk >>= 1) {
-        fc += __shfl_xor(fc, msk);
-        xmin = fminf(xmin, __shfl_xor(xmin, msk));
-        xmax = fmaxf(xmax, __shfl_xor(xmax, msk));
-        ymin = fminf(ymin, __shfl_xor(ymin, msk));
-        ymax = fmaxf(ymax, __shfl_xor(ymax, msk));
-    }
+    const float fc = wave_reduce((float)cnt, OpAdd());
+    xmin = wave_reduce(xmin, OpMin());
+    xmax = wave_reduce(xmax, OpMax());
+    ymin = wave_reduce(ymin, OpMin());
+    ymax = wave_reduce(ymax, OpMax());
     if ((tid & 63) == 0) {
         const int w = tid >> 6;
         shf[w][0] = fc; shf[w][1] = xmin; shf[w][2] = xmax; shf[w][3] = ymin; shf[w][4] = ymax;

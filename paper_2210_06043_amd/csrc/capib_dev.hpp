@@ -391,6 +391,40 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Value of another lane of the same row of 16 through the DPP modifier (a
+// register move, no LDS round trip).  CTRL: 0xB1 = lane i ^ 1, 0x4E = lane
+// i ^ 2 (quad permutations), 0x141 = lane 7 - i within each 8 (row half
+// mirror), 0x140 = lane 15 - i (row mirror).  Every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum (or min, max) over each row of 16 lanes, in every lane of the row: the
+// partner lanes i ^ 1, i ^ 2, then the mirrors.  Once a quad (an 8) holds one
+// value in all its lanes, its mirror partner is the same as lane i ^ 4 (i ^ 8),
+// so this takes the additions of the xor butterfly 1, 2, 4, 8 in its order.
+template <typename Op>
+__device__ __forceinline__ float row16_reduce(float v, Op op) {
+    v = op(v, dpp_f<0xB1>(v));
+    v = op(v, dpp_f<0x4E>(v));
+    v = op(v, dpp_f<0x141>(v));
+    return op(v, dpp_f<0x140>(v));
+}
+
+// The same over the whole wave (the rows combined through ds_bpermute),
+// in every lane.  Every lane must be active.
+template <typename Op>
+__device__ __forceinline__ float wave_reduce(float v, Op op) {
+    v = row16_reduce(v, op);
+    v = op(v, __shfl_xor(v, 16));
+    return op(v, __shfl_xor(v, 32));
+}
+
+struct OpAdd { __device__ float operator()(float a, float b) const { return a + b; } };
+struct OpMin { __device__ float operator()(float a, float b) const { return fminf(a, b); } };
+struct OpMax { __device__ float operator()(float a, float b) const { return fmaxf(a, b); } };
+
 // Probe point of the element from vertex (xh + xl, yh + yl) to the next
 // vertex (nxh + nxl, nyh + nyl): its midpoint moved by the probe distance
 // along the element's outward normal (Sec. 2.6), as a hi/lo pair.
@@ -408,10 +442,10 @@ __device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t
 #pragma unroll
     for (int r = 0; r < 10; r++) {
         if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        // both halves of each 32 x 32 product from one 64-bit multiply
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
     }
     return c0;
 }

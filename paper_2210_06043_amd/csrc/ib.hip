@@ -4,7 +4,7 @@
 //   velocity u* = (sum h e + g/2)/rho to every membrane vertex, and of the
 //   pressure c_s^2 drho and viscous stress -(1 - 1/2tau) Pi_neq to the probe
 //   of every element, 1.2 dx along its outward normal (Sec. 2.6).  Sixteen
-//   lanes serve one point, one stencil node each, and reduce with shuffles.
+//   lanes serve one point, one stencil node each, and reduce with DPP moves.
 // k_body_geom: FP64 geometry of each membrane for the diagnostics.
 // (The per-membrane phase of the step is in body.hip.)
 #include "capib_dev.hpp"
@@ -107,14 +107,7 @@ __device__ __forceinline__ void interp_point(const Dev &d, int gid) {
         }
     }
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
-        float s = acc[c];
-        s += __shfl_xor(s, 1, 16);
-        s += __shfl_xor(s, 2, 16);
-        s += __shfl_xor(s, 4, 16);
-        s += __shfl_xor(s, 8, 16);
-        acc[c] = s;
-    }
+    for (int c = 0; c < 4; c++) acc[c] = row16_reduce(acc[c], OpAdd());
     if (lane == 0) {
         if (probe)
             d.probe4[v] = make_float4(acc[0], acc[1], acc[2], acc[3]);

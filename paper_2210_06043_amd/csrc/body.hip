@@ -205,7 +205,7 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         sHx[l] = 0.5f * (bm * nx + Lx);
         sHy[l] = 0.5f * (bm * ny + Ly);
     }
-    apart = wave_sum(apart);
+    apart = wave_total_d(apart);
     if ((tid & 63) == 0) shd[tid >> 6] = apart;
     __syncthreads();
     double asum = 0.0;
@@ -341,9 +341,9 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
             Fy += fvy[k];
             M += armx * fvy[k] - army * fvx[k];
         }
-        Fx = wave_reduce(Fx, OpAdd());
-        Fy = wave_reduce(Fy, OpAdd());
-        M = wave_reduce(M, OpAdd());
+        Fx = wave_total(Fx, OpAdd());
+        Fy = wave_total(Fy, OpAdd());
+        M = wave_total(M, OpAdd());
         if ((tid & 63) == 0) { shf[tid >> 6][0] = Fx; shf[tid >> 6][1] = Fy; shf[tid >> 6][2] = M; }
         __syncthreads();
         // every thread sums the wave partials in the same order and takes
@@ -490,11 +490,11 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         xmin = fminf(xmin, x); xmax = fmaxf(xmax, x);
         ymin = fminf(ymin, y); ymax = fmaxf(ymax, y);
     }
-    const float fc = wave_reduce((float)cnt, OpAdd());
-    xmin = wave_reduce(xmin, OpMin());
-    xmax = wave_reduce(xmax, OpMax());
-    ymin = wave_reduce(ymin, OpMin());
-    ymax = wave_reduce(ymax, OpMax());
+    const float fc = wave_total((float)cnt, OpAdd());
+    xmin = wave_total(xmin, OpMin());
+    xmax = wave_total(xmax, OpMax());
+    ymin = wave_total(ymin, OpMin());
+    ymax = wave_total(ymax, OpMax());
     if ((tid & 63) == 0) {
         const int w = tid >> 6;
         shf[w][0] = fc; shf[w][1] = xmin; shf[w][2] = xmax; shf[w][3] = ymin; shf[w][4] = ymax;

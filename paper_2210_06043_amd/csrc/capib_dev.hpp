@@ -412,13 +412,38 @@ __device__ __forceinline__ float row16_reduce(float v, Op op) {
     return op(v, dpp_f<0x140>(v));
 }
 
-// The same over the whole wave (the rows combined through ds_bpermute),
-// in every lane.  Every lane must be active.
+// The same over the whole wave, (row 0 + row 1) + (row 2 + row 3), from
+// the rows' first lanes (register reads, no LDS round trip); the same in
+// every lane.  Every lane must be active.
 template <typename Op>
-__device__ __forceinline__ float wave_reduce(float v, Op op) {
+__device__ __forceinline__ float wave_total(float v, Op op) {
     v = row16_reduce(v, op);
-    v = op(v, __shfl_xor(v, 16));
-    return op(v, __shfl_xor(v, 32));
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return op(op(r0, r1), op(r2, r3));
+}
+
+// FP64 sum over the wave in the same order, in every lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_total_d(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 struct OpAdd { __device__ float operator()(float a, float b) const { return a + b; } };

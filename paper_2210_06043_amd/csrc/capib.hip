@@ -712,10 +712,14 @@ static capib_status ensure_marks(capib_ctx *c) {
 
 // One step.  On a small lattice: interpolation, membrane kernel and the
 // sweep of every tile, in sequence on the main stream.  On a large lattice
-// the far tiles run on the main stream while the interpolation and membrane
-// kernels run on the side stream, and the sweep of the near tiles follows
-// the join.  main/side are the streams to enqueue on, k selects the event
-// pair (so that several steps can be captured in one graph).
+// the far tiles run on the main stream while the interpolation, the
+// membrane kernel and the sweep of the near tiles run on the side stream:
+// the two sweeps write the new populations of disjoint tiles, both only
+// read the current ones, and the far tiles read this step's near-tile
+// flags, which the marking leaves alone (it marks the other parity).  The
+// step ends at the join.  main/side are the streams to enqueue on, k
+// selects the event pair (so that several steps can be captured in one
+// graph).
 static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_t side, int k) {
     if (!lattice_split(c->d)) {
         HIPCHK(c, launch_interp(c->d, par, main));
@@ -727,10 +731,10 @@ static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_
     HIPCHK(c, hipStreamWaitEvent(side, c->ev_fork[k], 0));
     HIPCHK(c, launch_interp(c->d, par, side));
     HIPCHK(c, launch_body(c->d, par, side));
+    HIPCHK(c, launch_lattice_sweep(c->d, par, side));
     HIPCHK(c, launch_lattice_far(c->d, par, main));
     HIPCHK(c, hipEventRecord(c->ev_join[k], side));
     HIPCHK(c, hipStreamWaitEvent(main, c->ev_join[k], 0));
-    HIPCHK(c, launch_lattice_sweep(c->d, par, main));
     return CAPIB_OK;
 }
 

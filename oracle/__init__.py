@@ -9,7 +9,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB selects another build of oracle.c (the sanitizer test loads the
+# AddressSanitizer/UndefinedBehaviorSanitizer copy this way)
+_LIB_PATH = os.environ.get("ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
 _lib = None
 
 DEFORMABLE, RIGID, FIXED = 0, 1, 2
@@ -41,6 +43,15 @@ def lib():
         L.orc_get_step.argtypes = [C.c_void_p]
         L.orc_min_margin.restype = C.c_double
         L.orc_min_margin.argtypes = [C.c_void_p]
+        L.orc_margins.argtypes = [C.c_void_p, _dp]
+        L.orc_reset_margins.argtypes = [C.c_void_p]
+        L.orc_set_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
+        L.orc_get_threads.argtypes = []
+        L.orc_set_body_state.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.orc_get_body_state.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.orc_set_bonds.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_ubyte), _dp]
         L.orc_flags.restype = C.c_int
         L.orc_flags.argtypes = [C.c_void_p]
         L.orc_add_body.restype = C.c_int
@@ -83,6 +94,15 @@ def lib():
                                          C.c_double, C.c_double, C.c_int, _dp, _dp]
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's per-node loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads():
+    return lib().orc_get_threads()
 
 
 # ---- point functions -----------------------------------------------------------
@@ -218,6 +238,43 @@ class Sim:
     @property
     def min_margin(self):
         return lib().orc_min_margin(self.p)
+
+    def margins(self):
+        """(smallest |draw - P| of the bond decisions, smallest |gap - y_cr| of
+        the formation decisions the gap decided) since the start or the last
+        reset_margins()."""
+        out = np.zeros(2)
+        lib().orc_margins(self.p, _d(out))
+        return float(out[0]), float(out[1])
+
+    def reset_margins(self):
+        lib().orc_reset_margins(self.p)
+
+    def set_step(self, n):
+        lib().orc_set_step(self.p, int(n))
+
+    def set_body_state(self, body, xy=None, dxy_prev=None, rigid=None):
+        """Overwrite x^n, x^n - x^{n-1} (deformable) and the rigid state
+        {xc, yc, phi, ucx, ucy, ucx_prev, ucy_prev, omega, omega_prev}."""
+        a = None if xy is None else np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+        d = None if dxy_prev is None else np.ascontiguousarray(dxy_prev, dtype=np.float64).reshape(-1)
+        r = None if rigid is None else np.ascontiguousarray(rigid, dtype=np.float64).reshape(-1)
+        for arr, n in ((a, 2 * self.nv[body]), (d, 2 * self.nv[body]), (r, 9)):
+            assert arr is None or arr.shape == (n,)
+        lib().orc_set_body_state(self.p, body, None if a is None else _d(a), None if d is None else _d(d),
+                                 None if r is None else _d(r))
+
+    def body_state(self, body):
+        n = self.nv[body]
+        xy, d, r = np.zeros((n, 2)), np.zeros((n, 2)), np.zeros(9)
+        lib().orc_get_body_state(self.p, body, _d(xy), _d(d), _d(r))
+        return dict(xy=xy, dxy_prev=d, rigid=r)
+
+    def set_bonds(self, body, state, anchor):
+        st = np.ascontiguousarray(state, dtype=np.uint8)
+        an = np.ascontiguousarray(anchor, dtype=np.float64)
+        assert st.shape == (self.ns[body],) and an.shape == (self.ns[body],)
+        lib().orc_set_bonds(self.p, body, st.ctypes.data_as(C.POINTER(C.c_ubyte)), _d(an))
 
     @property
     def flags(self):

@@ -28,8 +28,15 @@
  *
  * Populations are stored shifted, h_i = f_i - w_i, so that the rest state is
  * zero; this changes no arithmetic of the method.
+ *
+ * Loops whose iterations are independent (streaming, the per-node moments and
+ * collision, the repulsion received by each vertex, the read-out) are split
+ * over OpenMP threads; every value is still computed by the same expressions
+ * in the same order, so the results do not depend on the thread count.  The
+ * scatter of the spreading and all sums stay serial.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -166,7 +173,9 @@ typedef struct {
     orc_body *b;
     double rep_pref, rep_cut, rep_dmin, probe_dist;
     int64_t step;
-    double min_margin;
+    /* smallest |draw - P| over the bond decisions taken, and smallest
+     * |gap - y_cr| over the formation decisions that the gap decided */
+    double min_margin_p, min_margin_gap;
     int flags; /* bit0: a vertex left the rows [-1, ny] */
 } orc_sim;
 
@@ -186,7 +195,8 @@ orc_sim *orc_create(int nx, int ny, double tau, double gx, double gy, int walls)
     /* interaction constants: Eq. (12) prefactor, minimum distance dx, probe 1.2 dx */
     s->rep_pref = 1.0e-4 / (8.0 * sqrt(2.0));
     s->rep_cut = 1.0; s->rep_dmin = 0.1; s->probe_dist = 1.2;
-    s->min_margin = INFINITY;
+    s->min_margin_p = INFINITY;
+    s->min_margin_gap = INFINITY;
     return s;
 }
 
@@ -228,7 +238,14 @@ void orc_set_populations(orc_sim *s, const double *in) {
     memcpy(s->A, in, sizeof(double) * 9 * (size_t)s->nx * s->ny);
 }
 int64_t orc_get_step(const orc_sim *s) { return s->step; }
-double orc_min_margin(const orc_sim *s) { return s->min_margin; }
+double orc_min_margin(const orc_sim *s) {
+    return s->min_margin_p < s->min_margin_gap ? s->min_margin_p : s->min_margin_gap;
+}
+void orc_margins(const orc_sim *s, double *out2) { out2[0] = s->min_margin_p; out2[1] = s->min_margin_gap; }
+void orc_reset_margins(orc_sim *s) { s->min_margin_p = INFINITY; s->min_margin_gap = INFINITY; }
+void orc_set_step(orc_sim *s, int64_t n) { s->step = n; }
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 int orc_flags(const orc_sim *s) { return s->flags; }
 
 /* ---- S1: pull streaming, Eq. (1) ---------------------------------------------
@@ -238,6 +255,7 @@ int orc_flags(const orc_sim *s) { return s->flags; }
 static void stream(const orc_sim *s, const double *A, double *h) {
     for (int q = 0; q < 9; q++) {
         int oq = opposite(q);
+#pragma omp parallel for schedule(static)
         for (int j = 0; j < s->ny; j++)
             for (int i = 0; i < s->nx; i++) {
                 int si = ((i - EX[q]) % s->nx + s->nx) % s->nx;
@@ -256,12 +274,13 @@ static void stream(const orc_sim *s, const double *A, double *h) {
  * the coupling force is known); p = cs2 drho; sigma = -(1 - 1/2tau) Pi_neq with
  * Pi_neq = sum e e (h - h_eq(drho, u*)).                                      */
 static void node_moments(orc_sim *s) {
-    size_t N = (size_t)s->nx * s->ny;
-    for (size_t k = 0; k < N; k++) {
+    const long N = (long)s->nx * s->ny;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < N; k++) {
         double hq[9], heq[9];
         double dr = 0, jx = 0, jy = 0;
         for (int q = 0; q < 9; q++) {
-            hq[q] = s->h[(size_t)q * N + k];
+            hq[q] = s->h[(size_t)q * (size_t)N + (size_t)k];
             dr += hq[q]; jx += hq[q] * EX[q]; jy += hq[q] * EY[q];
         }
         double rho = 1.0 + dr;
@@ -586,6 +605,7 @@ static void body_forces(orc_sim *s, int k, const geom *G) {
     }
     if (b->kind == ORC_FIXED) return;
     /* Eq. (12) */
+#pragma omp parallel for schedule(static)
     for (int v = 0; v < n; v++) {
         for (int c = 0; c < s->nb; c++) {
             if (c == k) continue;
@@ -699,14 +719,14 @@ static void bond_kinetics(orc_sim *s, int k) {
         if (b->bound[q]) {
             double yl = sqrt((xs - b->anchor[q]) * (xs - b->anchor[q]) + (ys + 0.5) * (ys + 0.5));
             double P = 1.0 - exp(-b->kr0 * exp(fabs(yl - b->yeq) / b->lb));
-            if (fabs(r - P) < s->min_margin) s->min_margin = fabs(r - P);
+            if (fabs(r - P) < s->min_margin_p) s->min_margin_p = fabs(r - P);
             if (r < P) b->bound[q] = 0;
         } else {
             double gap = ys + 0.5;
             double P = 1.0 - exp(-b->kf);
-            if (r < P && fabs(gap - b->ycr) < s->min_margin) s->min_margin = fabs(gap - b->ycr);
+            if (r < P && fabs(gap - b->ycr) < s->min_margin_gap) s->min_margin_gap = fabs(gap - b->ycr);
             if (gap < b->ycr) {
-                if (fabs(r - P) < s->min_margin) s->min_margin = fabs(r - P);
+                if (fabs(r - P) < s->min_margin_p) s->min_margin_p = fabs(r - P);
                 if (r < P) { b->bound[q] = 1; b->anchor[q] = xs; }
             }
         }
@@ -752,7 +772,8 @@ static void one_step(orc_sim *s) {
             spread(s, s->fiby, b->xn[v], b->yn[v], dV * Fy);
         }
     }
-    for (size_t c = 0; c < N; c++) {                         /* S8 */
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < (long)N; c++) {                     /* S8 */
         double hq[9], heq[9], Fi[9];
         for (int q = 0; q < 9; q++) hq[q] = s->h[(size_t)q * N + c];
         double dr = s->drho[c], rho = 1.0 + dr;
@@ -778,7 +799,8 @@ void orc_step(orc_sim *s, int nsteps) {
 void orc_macro(orc_sim *s, double *drho, double *ux, double *uy) {
     size_t N = (size_t)s->nx * s->ny;
     stream(s, s->A, s->h);
-    for (size_t c = 0; c < N; c++) {
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < (long)N; c++) {
         double dr = 0, jx = 0, jy = 0;
         for (int q = 0; q < 9; q++) {
             double v = s->h[(size_t)q * N + c];
@@ -824,6 +846,46 @@ void orc_set_body_work(orc_sim *s, int k, const double *usxy, const double *fxy)
     }
 }
 void orc_integrate_body(orc_sim *s, int k) { integrate(s, k); }
+
+/* ---- state transfer: restart the oracle from a state given in FP64 --------------
+ * A run can be continued from another code's state (promoted to FP64): the
+ * populations (orc_set_populations), the step index (orc_set_step, which
+ * keys the bond draws), and per body the vertex positions x^n, the previous
+ * increment x^n - x^{n-1} (deformable, the BDF2 history of Eq. 18), the
+ * rigid state (centroid, angle, velocity and angular velocity at n and
+ * n-1: the BDF2 history of Eqs. 19-20), and the bond states and anchors.
+ * The rest shape, masses and rigid offsets stay those of the body as added. */
+void orc_set_body_state(orc_sim *s, int k, const double *xy, const double *dxy_prev, const double *rigid9) {
+    orc_body *b = &s->b[k];
+    for (int v = 0; v < b->n; v++) {
+        if (xy) { b->x[v] = xy[2 * v]; b->y[v] = xy[2 * v + 1]; }
+        if (dxy_prev) { b->dxm[v] = dxy_prev[2 * v]; b->dym[v] = dxy_prev[2 * v + 1]; }
+    }
+    if (rigid9) {
+        b->xc = rigid9[0]; b->yc = rigid9[1]; b->phi = rigid9[2];
+        b->ucx = rigid9[3]; b->ucy = rigid9[4]; b->ucx_m = rigid9[5]; b->ucy_m = rigid9[6];
+        b->om = rigid9[7]; b->om_m = rigid9[8];
+    }
+}
+void orc_get_body_state(const orc_sim *s, int k, double *xy, double *dxy_prev, double *rigid9) {
+    const orc_body *b = &s->b[k];
+    for (int v = 0; v < b->n; v++) {
+        if (xy) { xy[2 * v] = b->x[v]; xy[2 * v + 1] = b->y[v]; }
+        if (dxy_prev) { dxy_prev[2 * v] = b->dxm[v]; dxy_prev[2 * v + 1] = b->dym[v]; }
+    }
+    if (rigid9) {
+        rigid9[0] = b->xc; rigid9[1] = b->yc; rigid9[2] = b->phi;
+        rigid9[3] = b->ucx; rigid9[4] = b->ucy; rigid9[5] = b->ucx_m; rigid9[6] = b->ucy_m;
+        rigid9[7] = b->om; rigid9[8] = b->om_m;
+    }
+}
+void orc_set_bonds(orc_sim *s, int k, const unsigned char *state, const double *anchor) {
+    orc_body *b = &s->b[k];
+    for (int q = 0; q < b->ns; q++) {
+        b->bound[q] = state[q] ? 1 : 0;
+        b->anchor[q] = anchor[q];
+    }
+}
 
 /* Structure alone, fluid frozen at rest: repeat S3, S5 (internal forces only)
  * and S6 with u* = 0 on one deformable polygon.                               */

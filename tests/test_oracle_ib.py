@@ -466,37 +466,6 @@ def test_bond_survival_binomial():
     assert abs(k - mean) < 5 * sd + 4
 
 
-def test_bond_rule_matches_draws_one_step():
-    """One step of the kinetics, checked site by site against the rule of
-    Sec. 2.5 with the draws re-derived from the counter (n, s) and the seed."""
-    cfg = inputs.config_tiny()
-    s = oracle_sim(cfg)
-    bd = cfg.bonds[0]
-    k = bd.body
-    st0, an0 = s.bonds(k)
-    n0 = s.n
-    s.step(1)
-    st1, an1 = s.bonds(k)
-    xy = s.vertices(k)
-    nv = len(xy)
-    for q in range(len(bd.host)):
-        e = bd.host[q]
-        m = (e + 1) % nv
-        xs = xy[e] + bd.frac[q] * (xy[m] - xy[e])
-        r = oracle.uniform(bd.seed, n0, q)
-        if st0[q]:
-            yl = np.hypot(xs[0] - an0[q], xs[1] + 0.5)
-            P = 1 - np.exp(-bd.kr0 * np.exp(abs(yl - bd.yeq) / bd.lb))
-            assert st1[q] == (0 if r < P else 1)
-        elif xs[1] + 0.5 < bd.ycr:
-            P = 1 - np.exp(-bd.kf)
-            assert st1[q] == (1 if r < P else 0)
-            if st1[q]:
-                assert an1[q] == pytest.approx(xs[0], abs=1e-15)
-        else:
-            assert st1[q] == 0
-
-
 def test_c1_sites_and_constants():
     """The small workload's parameters follow Sec. 2.5 and 3.1: y_cr = 25 nm
     over dx = 0.125 um, y_eq = y_cr/2, sigma = nu^2/H, k_f/k_r0 = 8.5e3,

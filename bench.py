@@ -62,25 +62,62 @@ def workload(name, seed):
     return cfg, desc
 
 
-def cpu_baseline(cfg, steps):
-    """The FP64 oracle on this host (single thread): timing, and the state
-    after `steps` steps that the GPU runs are compared against."""
+def host_cpu():
+    """Host core count and CPU model (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    model = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return os.cpu_count(), model
+
+
+def cpu_baseline(cfg, steps, single_steps):
+    """The FP64 oracle on this host's cores: `steps` coupled steps with its
+    per-node loops on every core OpenMP is given (the reference state the GPU
+    runs are compared against), and `single_steps` on one thread."""
     import oracle
-    s = oracle.Sim(cfg.nx, cfg.ny, cfg.tau, cfg.gx, cfg.gy, cfg.walls)
-    s.set_interactions(cfg.rep_pref, cfg.rep_cut, cfg.probe_dist)
-    s.init_flow(cfg.ux_init)
-    for b in cfg.bodies:
-        s.add_body(b.kind, b.xy, b.xy_rest, b.ks, b.kb, b.ka, b.pref, b.rho_r, b.tag)
-    for bd in cfg.bonds:
-        s.add_bonds(bd.body, bd.host, bd.frac, bd.sigma, bd.ycr, bd.yeq, bd.kf, bd.kr0, bd.lb, bd.seed)
-    x0 = [s.vertices(k).copy() for k in range(len(cfg.bodies))]
-    t0 = time.perf_counter()
-    s.step(steps)
-    dt = time.perf_counter() - t0
+    nproc, model = host_cpu()
+    all_threads = oracle.threads()
+
+    def run(n, threads):
+        oracle.set_threads(threads)
+        s = oracle.Sim(cfg.nx, cfg.ny, cfg.tau, cfg.gx, cfg.gy, cfg.walls)
+        s.set_interactions(cfg.rep_pref, cfg.rep_cut, cfg.probe_dist)
+        s.init_flow(cfg.ux_init)
+        for b in cfg.bodies:
+            s.add_body(b.kind, b.xy, b.xy_rest, b.ks, b.kb, b.ka, b.pref, b.rho_r, b.tag)
+        for bd in cfg.bonds:
+            s.add_bonds(bd.body, bd.host, bd.frac, bd.sigma, bd.ycr, bd.yeq, bd.kf, bd.kr0, bd.lb, bd.seed)
+        x0 = [s.vertices(k).copy() for k in range(len(cfg.bodies))]
+        t0 = time.perf_counter()
+        s.step(n)
+        return s, x0, time.perf_counter() - t0
+
+    s1, _, dt1 = run(single_steps, 1)
+    del s1
+    s, x0, dt = run(steps, all_threads)
+    oracle.set_threads(all_threads)
     ref = dict(u=np.stack(s.macro()[1:]), x=[s.vertices(k) for k in range(len(cfg.bodies))], x0=x0,
                n_bound=[s.count_bound(bd.body) for bd in cfg.bonds])
-    out = dict(value=round(cfg.nx * cfg.ny * steps / dt / 1e6, 3), unit="MLUPS", cores=1, kind="oracle",
-               sample=f"{steps} full coupled steps of the same workload (FP64, single thread), {dt:.1f} s")
+    nodes = cfg.nx * cfg.ny
+    out = dict(value=round(nodes * steps / dt / 1e6, 3), unit="MLUPS", cores=all_threads, kind="oracle",
+               sample=f"{steps} full coupled steps of the same workload (FP64), OpenMP over the per-node loops on "
+                      f"{all_threads} threads, {dt:.1f} s",
+               single_thread=dict(value=round(nodes * single_steps / dt1 / 1e6, 3), unit="MLUPS", cores=1,
+                                  sample=f"{single_steps} steps on one thread, {dt1:.1f} s"),
+               nproc=nproc, cpu_model=model)
     return out, ref
 
 
@@ -101,25 +138,27 @@ def error_vs_oracle(cfg, storage, scale, steps, ref):
     return dict(velocity_rel=eu, displacement_rel=ed, n_bound_equal=nb == ref["n_bound"], steps=steps)
 
 
-def measure(cfg, storage, scale, args):
-    """Timed steps (graphs as configured) and the per-kernel event times."""
+def measure(cfg, storage, scale, steps, warmup, graph=True):
+    """Timed steps and the per-kernel event times.  With graphs, the library
+    instantiates every graph when they are enabled (before the warm-up), so
+    the timed region only replays them."""
     import torch
     from paper_2210_06043_amd import capib
-    sim = capib.from_config(cfg, storage=storage, fp16_scale=scale, graph=not args.no_graph)
+    sim = capib.from_config(cfg, storage=storage, fp16_scale=scale, graph=graph)
     st = sim.stream
-    sim.step(args.warmup)
+    sim.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
-    sim.step(args.steps)
+    sim.step(steps)
     e1.record(st)
     e1.synchronize()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     # per-kernel HIP events on the library's stream, same number of steps
     sim.set_timing(True)
-    sim.step(args.steps)
+    sim.step(steps)
     sim.set_timing(False)
     ph, n, swept = sim.read_timing()
     diag = sim.diagnostics()
@@ -144,22 +183,19 @@ def measure(cfg, storage, scale, args):
         phases["lattice_far"] = round(launch_ms[2] * 1e3, 3)
     phases["lattice_sweep"] = round(launch_ms[3] * 1e3, 3)
     lattice_ms = sum(launch_ms[q] for q in (1, 2, 3) if swept[q])
-    return dict(ms=ms, mlups=nodes * args.steps / (ms * 1e-3) / 1e6, kernel=kernel, kernel_ms=kernel_ms,
+    del sim
+    torch.cuda.empty_cache()
+    return dict(ms=ms, mlups=nodes * steps / (ms * 1e-3) / 1e6, kernel=kernel, kernel_ms=kernel_ms,
                 alg_bytes=alg_bytes, achieved=alg_bytes / (kernel_ms * 1e-3) / 1e9, near_tiles=diag["near_tiles"],
                 phases=phases, nodes_per_launch={names[q]: int(swept[q] // n) for q in (1, 2, 3) if swept[q]},
                 whole_sweep_gbs=bytes_per_node * nodes / (lattice_ms * 1e-3) / 1e9, error_flags=diag["error_flags"])
 
 
-def batched(args):
-    """The batched ensemble (256 capillaries, FP16 storage) against the
-    plain single-instance FP32 path run one member after another: completed
-    20k-step runs per hour, from the measured step times."""
+def _ensemble_step_ms(cfgs, storage, scale, args):
+    """ms per step of one ensemble of `cfgs`, and its per-launch timing."""
     import torch
-    from paper_2210_06043_amd import capib, inputs
-    cfgs = inputs.config_c3(seed=0, members=args.members)
-    scale = capib.fp16_scale_for(cfgs[0])
-    sim, first = capib.from_ensemble(cfgs, storage=capib.FP16_SHIFTED, fp16_scale=scale, graph=not args.no_graph)
-    nodes = sum(c.nx * c.ny for c in cfgs)
+    from paper_2210_06043_amd import capib
+    sim, _ = capib.from_ensemble(cfgs, storage=storage, fp16_scale=scale, graph=not args.no_graph)
     sim.step(args.batched_warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -174,36 +210,71 @@ def batched(args):
     sim.set_timing(False)
     ph, n, swept = sim.read_timing()
     diag = sim.diagnostics()
-    far_ms = ph[2] / n
-    alg = 36 * swept[2] / n   # nodes of the far tiles, counted per step
     del sim
     torch.cuda.empty_cache()
-    # single-instance FP32 step time on an evenly spaced sample of members
+    return ms, ph, n, swept, diag
+
+
+def _single_step_ms(cfg, storage, scale, args):
+    """ms per step of one member run alone as a single lattice."""
+    import torch
+    from paper_2210_06043_amd import capib
+    g = capib.from_config(cfg, storage=storage, fp16_scale=scale, graph=not args.no_graph)
+    g.step(200)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(g.stream)
+    g.step(args.batched_steps)
+    b.record(g.stream)
+    b.synchronize()
+    del g
+    return a.elapsed_time(b) / args.batched_steps
+
+
+def batched(args):
+    """The batched ensemble (256 capillaries) against the same members run
+    one after another as single lattices, each with the same population
+    storage (so at the same accuracy against the oracle): completed
+    20k-step runs per hour, from the measured step times.  FP16 storage is
+    the configured ensemble; FP32 is reported beside it."""
+    from paper_2210_06043_amd import capib, inputs
+    cfgs = inputs.config_c3(seed=0, members=args.members)
+    scale = capib.fp16_scale_for(cfgs[0])
+    nodes = sum(c.nx * c.ny for c in cfgs)
+    ms16, ph, n, swept, diag = _ensemble_step_ms(cfgs, capib.FP16_SHIFTED, scale, args)
+    far_ms = ph[2] / n
+    alg = 36 * swept[2] / n   # nodes of the far tiles, counted per step
+    ms32, ph32, n32, swept32, diag32 = _ensemble_step_ms(cfgs, capib.FP32_SHIFTED, 1.0, args)
+    far32_ms = ph32[2] / n32
+    alg32 = 72 * swept32[2] / n32
+    # single-instance step times on an evenly spaced sample of members
     sample = list(range(0, len(cfgs), max(1, len(cfgs) // args.single_sample)))[:args.single_sample]
-    t1 = []
-    for k in sample:
-        g = capib.from_config(cfgs[k], graph=not args.no_graph)
-        g.step(200)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(g.stream)
-        g.step(args.batched_steps)
-        b.record(g.stream)
-        b.synchronize()
-        t1.append(a.elapsed_time(b) / args.batched_steps)
-        del g
+    t32 = [_single_step_ms(cfgs[k], capib.FP32_SHIFTED, 1.0, args) for k in sample]
+    t16 = [_single_step_ms(cfgs[k], capib.FP16_SHIFTED, scale, args) for k in sample]
     steps_per_run = cfgs[0].steps
-    rph = len(cfgs) * 3600.0 / (steps_per_run * ms * 1e-3)
-    rph1 = 3600.0 / (steps_per_run * float(np.mean(t1)) * 1e-3)
+
+    def rph(ms, members):
+        return members * 3600.0 / (steps_per_run * ms * 1e-3)
+
+    rph16, rph32 = rph(ms16, len(cfgs)), rph(ms32, len(cfgs))
+    s16, s32 = rph(float(np.mean(t16)), 1), rph(float(np.mean(t32)), 1)
     return {
         "workload": f"{len(cfgs)} capillaries, lengths U{{256..2048}} x 64, 1-4 cells (128-256 markers), "
                     f"one adhered particle each (64 markers, 20 bonds); one ensemble, FP16 storage",
         "members": len(cfgs), "nodes": nodes, "vertices": sum(c.n_vertices for c in cfgs),
-        "steps_per_run": steps_per_run, "ms_per_step": round(ms, 5),
-        "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "runs_per_hour": round(rph, 1),
-        "single_fp32_runs_per_hour": round(rph1, 1), "speedup": round(rph / rph1, 2),
-        "single_fp32_sample": f"members {sample}: mean {np.mean(t1) * 1e3:.2f} us/step, run one after another",
+        "steps_per_run": steps_per_run, "ms_per_step": round(ms16, 5),
+        "mlups": round(nodes / (ms16 * 1e-3) / 1e6, 1), "runs_per_hour": round(rph16, 1),
+        "single_fp16_runs_per_hour": round(s16, 1), "speedup_same_storage": round(rph16 / s16, 2),
+        "single_fp32_runs_per_hour": round(s32, 1), "speedup_vs_plain_fp32_single": round(rph16 / s32, 2),
+        "fp32_ensemble": {"ms_per_step": round(ms32, 5), "mlups": round(nodes / (ms32 * 1e-3) / 1e6, 1),
+                          "runs_per_hour": round(rph32, 1), "speedup_same_storage": round(rph32 / s32, 2),
+                          "lattice_far_gbs": round(alg32 / (far32_ms * 1e-3) / 1e9, 1),
+                          "error_flags": diag32["error_flags"]},
+        "single_sample": f"members {sample}: mean {np.mean(t32) * 1e3:.2f} us/step FP32, "
+                         f"{np.mean(t16) * 1e3:.2f} us/step FP16, run one after another",
+        "accuracy": "the ensemble and the single runs of each storage take the same arithmetic (FP32: members "
+                    "bit-identical to their single runs; FP16: within 1e-3 of the FP64 oracle, tested)",
         "roofline": {"bound": "hbm", "kernel": "k_lattice_far", "achieved": round(alg / (far_ms * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(alg / (far_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -213,6 +284,53 @@ def batched(args):
                               "lattice_far": round(far_ms * 1e3, 3), "lattice_sweep": round(ph[3] / n * 1e3, 3)},
         "error_flags": diag["error_flags"],
     }
+
+
+def copy_peak(mib=1024, reps=20):
+    """Bandwidth of the library's plain streaming copy (bytes read + written
+    per second) on two buffers of `mib` MiB: what a streaming kernel reaches
+    on this device, beside the vendor's 8 TB/s."""
+    import torch
+    from paper_2210_06043_amd import capib
+    n = mib << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        capib.copy_bandwidth(b, a, st)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        capib.copy_bandwidth(b, a, st)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert torch.equal(a[:4096], b[:4096])
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2.0 * n / (ms * 1e-3) / 1e9, 1)
+
+
+def mr_section(args, copy_gbs):
+    """The single-lattice HBM case: 16384 x 1024 (16.8 M nodes) with
+    paper-scale bodies, FP32 and FP16 storage."""
+    from paper_2210_06043_amd import capib, inputs
+    cfg = inputs.config_mr()
+    scale = capib.fp16_scale_for(cfg)
+    out = {"workload": f"single capillary 16384x1024 (dx=0.03125um), 24 cells x 512 markers, discoidal particle "
+                       f"AR={cfg.meta['ar']} Ca={cfg.meta['ca']} x 128 markers, 200 bonds, Re=0.01",
+           "nodes": cfg.nx * cfg.ny, "vertices": cfg.n_vertices, "steps": args.mr_steps}
+    for name, st, sc in (("fp32", capib.FP32_SHIFTED, 1.0), ("fp16", capib.FP16_SHIFTED, scale)):
+        m = measure(cfg, st, sc, args.mr_steps, args.mr_warmup, graph=not args.no_graph)
+        r = roofline(m, name, "mr")
+        r["frac_of_copy_peak"] = round(m["achieved"] / copy_gbs, 4) if copy_gbs else None
+        out[name] = {"mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms"] / args.mr_steps, 5),
+                     "roofline": r, "phase_us_per_step": m["phases"],
+                     "lattice_bandwidth_whole_sweep_gbs": round(m["whole_sweep_gbs"], 1),
+                     "error_flags": m["error_flags"]}
+    return out
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -272,8 +390,6 @@ def surrogate_section(args, batched_out):
                      "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
                      "algorithmic_flops_per_launch": flops},
     }
-    if batched_out:
-        out["screening_gain_vs_batched_solver_runs"] = round(preds_per_hour / batched_out["runs_per_hour"], 1)
     return out
 
 
@@ -297,6 +413,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--storage", choices=["both", "fp32", "fp16"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-single-steps", type=int, default=30)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="print only the batched-ensemble measurement (for profiling it alone)")
@@ -304,12 +421,16 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=400)
     ap.add_argument("--batched-warmup", type=int, default=100)
     ap.add_argument("--single-sample", type=int, default=8)
+    ap.add_argument("--no-mr", action="store_true")
+    ap.add_argument("--mr-only", action="store_true", help="print only the 16384x1024 measurement")
+    ap.add_argument("--mr-steps", type=int, default=200)
+    ap.add_argument("--mr-warmup", type=int, default=20)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--harvest-steps", type=int, default=600)
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="only run a plain device copy of this many MiB (calibrates the HBM byte counters)")
+                    help="only run the library's streaming copy of this many MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs is not built",
@@ -321,17 +442,20 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_probe_mb:
-        n = args.copy_probe_mb * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        n = args.copy_probe_mb << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         for _ in range(5):
-            b.copy_(a)
+            capib.copy_bandwidth(b, a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}))
+        print(json.dumps({"copy_bytes_read_per_launch": n, "copy_bytes_written_per_launch": n}))
         return
     if args.batched_only:
         print(json.dumps({"batched": batched(args)}), flush=True)
+        return
+    if args.mr_only:
+        print(json.dumps({"mr": mr_section(args, None)}), flush=True)
         return
     cfg, desc = workload(args.workload, args.seed)
     nodes = cfg.nx * cfg.ny
@@ -340,8 +464,10 @@ def main():
     runs = {}
     for name in (["fp32", "fp16"] if args.storage == "both" else [args.storage]):
         st = capib.FP16_SHIFTED if name == "fp16" else capib.FP32_SHIFTED
-        runs[name] = measure(cfg, st, scale16 if name == "fp16" else 1.0, args)
+        runs[name] = measure(cfg, st, scale16 if name == "fp16" else 1.0, args.steps, args.warmup,
+                             graph=not args.no_graph)
     m = runs[main_storage]
+    copy_gbs = copy_peak()
 
     out = {
         "metric": METRIC,
@@ -359,10 +485,12 @@ def main():
         "config": {"workload": desc, "nodes": nodes, "population_storage": main_storage + "_deviation",
                    "hip_graphs": not args.no_graph, "vertices": cfg.n_vertices, "sites": cfg.n_sites},
         "roofline": roofline(m, main_storage, args.workload),
+        "copy_peak_gbs": copy_gbs,
         "phase_us_per_step": m["phases"],
         "lattice_bandwidth_whole_sweep_gbs": round(m["whole_sweep_gbs"], 1),
         "error_flags": m["error_flags"],
     }
+    out["roofline"]["frac_of_copy_peak"] = round(m["achieved"] / copy_gbs, 4)
     if main_storage == "fp32" and "fp16" in runs:
         f = runs["fp16"]
         out["fp16_storage"] = {"value": round(f["mlups"], 1), "unit": "MLUPS",
@@ -370,12 +498,14 @@ def main():
                                "roofline": roofline(f, "fp16", args.workload), "phase_us_per_step": f["phases"],
                                "lattice_bandwidth_whole_sweep_gbs": round(f["whole_sweep_gbs"], 1),
                                "error_flags": f["error_flags"]}
+    if not args.no_mr:
+        out["mr"] = mr_section(args, copy_gbs)
     if not args.no_batched:
         out["batched"] = batched(args)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_section(args, out.get("batched"))
     if not args.no_cpu_baseline:
-        base, ref = cpu_baseline(cfg, args.cpu_steps)
+        base, ref = cpu_baseline(cfg, args.cpu_steps, args.cpu_single_steps)
         out["cpu_baseline"] = base
         out["error_vs_oracle"] = {
             name: error_vs_oracle(cfg, capib.FP16_SHIFTED if name == "fp16" else capib.FP32_SHIFTED,

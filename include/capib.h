@@ -6,7 +6,9 @@
  *
  * The calls follow the paper's statement of the problem: a D2Q9 lattice with
  * capillary walls (Sec. 2.1-2.2, 3.1), immersed membranes (Sec. 2.2-2.3),
- * ligand-receptor bonds (Sec. 2.5) and a time step (Sec. 2.6-2.8).
+ * ligand-receptor bonds (Sec. 2.5) and a time step (Sec. 2.1-2.9: streaming
+ * and collision, interpolation, membrane, interaction, bond and load forces,
+ * integration, spreading).
  *
  * Conventions
  *   - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3.
@@ -27,7 +29,12 @@
  *     memory.  Host arrays passed in are copied during the call.
  *   - All GPU work is enqueued on the hip stream given at creation (a
  *     hipStream_t passed as void*; NULL = the null stream).  Calls documented
- *     "syncs" wait for that stream before returning.
+ *     "syncs" wait for that stream before returning.  The library also keeps
+ *     three streams of its own (created on the first capib_step, destroyed
+ *     by capib_destroy): one for the far lattice tiles that run beside the
+ *     immersed-boundary kernels on large lattices, joined back into the
+ *     caller's stream within each step, and two on which HIP graphs are
+ *     captured.  The caller sees ordinary stream order on its own stream.
  *
  * Errors
  *   - Every call returns a capib_status; capib_last_error() gives a message
@@ -73,7 +80,7 @@ enum {
 typedef struct capib_ctx capib_ctx;
 
 /* The lattice of Sec. 2.1 and the channel of Sec. 3.1.
- *   nx, ny     nodes (ny >= 2, nx >= 1)
+ *   nx, ny     nodes (nx >= 1; ny >= 2, and ny >= 4 with walls)
  *   tau        BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3, Sec. 2.1)
  *   gx, gy     uniform driving body force per node (added to the Guo term)
  *   walls      3: bounce-back walls at both y ends; 0: periodic in y too
@@ -145,6 +152,8 @@ typedef struct {
     int32_t n_bound;                 /* engaged bonds N_L */
     int32_t kind;
     double xc, yc, phi, ucx, ucy, omega; /* rigid state (zero for other kinds) */
+    int32_t n_bound0;                /* bonds engaged at t = 0 (N_L0, Sec. 3.1) */
+    int32_t reserved;
 } capib_body_diag;
 
 /* Creates a context for the lattice; validates tau > 1/2, sizes, walls in
@@ -198,8 +207,13 @@ capib_status capib_add_bonds(capib_ctx *ctx, int32_t body_id, const capib_bonds 
 capib_status capib_set_interactions(capib_ctx *ctx, double rep_prefactor, double rep_cutoff,
                                     double probe_dist);
 
-/* Advances nsteps full steps (interpolation, forces, integration, spreading,
- * bonds, lattice sweep).  Enqueued on the stream, returns immediately.  The
+/* Advances nsteps full steps of the method (Sec. 2.1-2.9): interpolation of
+ * the fluid velocity and of the probe pressure and stress (Sec. 2.2, 2.6),
+ * membrane forces (Eqs. 7-11), repulsion (Eq. 12), bond springs (Eq. 13),
+ * hydrodynamic loads (Eqs. 14-15), integration (Eqs. 16-20), spreading
+ * (Sec. 2.2, 2.7), bond kinetics (Sec. 2.5) and the lattice sweep of
+ * streaming, bounce-back and BGK collision with forcing (Eqs. 1-6).
+ * Enqueued on the stream, returns immediately.  The
  * lattice tiles that receive no spread force are swept on a second stream
  * of the library concurrently with the immersed-boundary kernels; the step
  * is joined back into the caller's stream before the tiles under the
@@ -207,19 +221,64 @@ capib_status capib_set_interactions(capib_ctx *ctx, double rep_prefactor, double
 capib_status capib_step(capib_ctx *ctx, int32_t nsteps);
 
 /* Replays the steps through captured HIP graphs of 16 (and 2) steps when
- * enable != 0 (results identical to plain launches).                      */
+ * enable != 0 (results identical to plain launches).  The four graphs (both
+ * starting parities) are captured and instantiated by this call when a
+ * workspace is bound, and again by the first capib_step call of two or more
+ * steps after any later set-up call; other calls only replay them.         */
 capib_status capib_set_graph(capib_ctx *ctx, int32_t enable);
 
+/* Launch configuration of the step (not a step of the method: every
+ * configuration computes the same results, bit for bit).  Any field -1
+ * keeps the library's own rule.
+ *   split           1: the far lattice tiles (those no membrane stencil
+ *                   covers) in a launch of their own, on a second stream
+ *                   beside the immersed-boundary kernels; 0: one sweep after
+ *                   the membrane phase, with a share of the far tiles swept
+ *                   by the membrane launch.  Rule: 1 from 8192 tiles of
+ *                   64 x 4 nodes.
+ *   far_share_pct   with split 0, percent of the far tiles swept by the
+ *                   membrane launch (rule: 50 FP32, 80 FP16).
+ *   mark_pairs      1: the next step's near tiles marked with one (vertex,
+ *                   stencil tile) pair per lane; 0: one vertex per lane
+ *                   (rule: 1 below 16384 vertices).
+ *   membrane_class  threads and LDS of the membrane kernel sized for
+ *                   membranes of 256, 512 or 1024 vertices (at least the
+ *                   largest membrane; rule: the smallest that holds it).   */
+typedef struct {
+    int32_t split, far_share_pct, mark_pairs, membrane_class;
+} capib_tuning;
+capib_status capib_set_tuning(capib_ctx *ctx, const capib_tuning *t);
+/* The configuration the next step will launch with (rules resolved). */
+capib_status capib_get_tuning(const capib_ctx *ctx, capib_tuning *t);
+
+/* Picks the launch configuration for this context's workload by timing:
+ * from the library's own configuration, a coordinate descent over the
+ * schedule, the far share, the marking layout and the membrane class, each
+ * candidate timed with HIP events over steps_per_trial steps (>= 16, twice,
+ * the faster kept) on the context's stream, from the current state (saved
+ * to host memory before the trials and restored after them, so the run
+ * continues as if no trial had happened).  Graphs are used if enabled.  The
+ * fastest configuration is applied and, with cache_path (a text file, may
+ * be NULL), appended under a key of the device and the workload's shape;
+ * a later call that finds the key there applies it without timing.
+ * chosen and best_ms_per_step (may be NULL) receive the result.  Syncs.   */
+capib_status capib_autotune(capib_ctx *ctx, int32_t steps_per_trial, const char *cache_path,
+                            capib_tuning *chosen, double *best_ms_per_step);
+
 /* Macroscopic fields of the current state, [ny][nx] each (any may be NULL):
- * drho = sum h and u* = (sum h e + g/2)/rho of the streamed populations,
- * the moments the next step starts from.  Syncs.                          */
+ * drho = sum h and u* = (sum h e + g/2)/rho of the streamed populations
+ * (the density and velocity moments of Sec. 2.1, Eqs. 5-6, before the
+ * coupling force of the next step is known), the moments the next step
+ * starts from.  Syncs.                                                     */
 capib_status capib_read_macro(capib_ctx *ctx, double *drho, double *ux, double *uy);
 
 /* Vertex positions x^n of a body, 2n doubles.  Syncs. */
 capib_status capib_read_vertices(capib_ctx *ctx, int32_t body_id, double *xy);
 
 /* Bond states (0/1) and anchor x of a body's sites in the order given to
- * capib_add_bonds.  Syncs.                                                 */
+ * capib_add_bonds (the ligand-receptor bonds of Sec. 2.5: a bond is engaged
+ * or not, and an engaged bond is anchored on the lower wall where it
+ * formed).  Syncs.                                                         */
 capib_status capib_read_bonds(capib_ctx *ctx, int32_t body_id, uint8_t *state, double *anchor_x);
 
 /* Per-vertex data of the last step of a body (any may be NULL): interpolated
@@ -229,7 +288,10 @@ capib_status capib_read_body_work(capib_ctx *ctx, int32_t body_id, double *ustar
                                   double *force, double *target);
 
 /* Global FP64 sums and the sticky error flags; returns CAPIB_E_UNSTABLE if
- * any flag is set.  Syncs.                                                  */
+ * any flag is set.  The sums are the invariants of the scheme: mass (sum
+ * of drho, conserved by streaming, bounce-back and the collision, Sec. 2.1)
+ * and momentum (sum of h e); the per-body quantities that Sec. 3.1 monitors
+ * are in capib_body_diagnostics and capib_readout.  Syncs.                 */
 capib_status capib_diagnostics(capib_ctx *ctx, capib_diag *out);
 
 /* Per member (band) of the context (one for a single lattice), the
@@ -250,8 +312,30 @@ capib_status capib_diagnostics(capib_ctx *ctx, capib_diag *out);
  * A member without a particle gets zeros and -1.  Enqueued.               */
 capib_status capib_sample_members(capib_ctx *ctx, int32_t particle_tag, int32_t cell_tag, float *out_device);
 
-/* FP64 geometry of a body's current polygon, N_L and rigid state.  Syncs. */
+/* FP64 geometry of a body's current polygon (area and perimeter, Sec. 2.3;
+ * polygon-area centroid, Sec. 3.1), N_L and N_L0 (Sec. 2.5, 3.1) and the
+ * rigid state (Sec. 2.9).  Syncs.                                          */
 capib_status capib_body_diagnostics(capib_ctx *ctx, int32_t body_id, capib_body_diag *out);
+
+/* The three quantities Sec. 3.1 monitors over time, in FP64 from the
+ * current state, into out3:
+ *   0  delta_p = (p - p_0)/p_0, the cell's perimeter p over its initial
+ *      perimeter p_0 minus one (cell membrane stretching);
+ *   1  r, the distance between the polygon-area centroids of the cell and
+ *      the particle (minimum image along the periodic x);
+ *   2  N_L / N_L0, the particle's engaged bonds over those engaged at t = 0
+ *      (0 if none were).
+ * Both bodies must belong to the same member.  Syncs.                      */
+capib_status capib_readout(capib_ctx *ctx, int32_t cell_body, int32_t particle_body, double *out3);
+
+/* The state a run continues from, per body (any output may be NULL):
+ * vertex positions x^n (2n doubles); the previous increment x^n - x^{n-1}
+ * (2n, the history of the BDF2 target velocity of Eq. 18; zero for rigid
+ * and fixed bodies); and for a rigid body {xc, yc, phi, ucx, ucy,
+ * ucx_prev, ucy_prev, omega, omega_prev} (9 doubles: the centroid, the
+ * rotation angle and the velocities at steps n and n-1 that Eqs. 19-20
+ * advance; zero for other kinds).  Syncs.                                   */
+capib_status capib_read_body_state(capib_ctx *ctx, int32_t body_id, double *xy, double *dxy_prev, double *rigid9);
 
 /* Checkpoint: with host_buf == NULL stores the needed size in *bytes;
  * otherwise copies the whole device state (populations, bodies, bonds, step)
@@ -276,6 +360,14 @@ capib_status capib_load(capib_ctx *ctx, const void *host_buf, size_t bytes);
  * rest, and the third sums are 0.                                           */
 capib_status capib_set_timing(capib_ctx *ctx, int32_t enable);
 capib_status capib_read_timing(capib_ctx *ctx, double *ms4, int64_t *steps, int64_t *nodes4);
+
+/* Device-to-device copy of `bytes` bytes with a plain streaming kernel of
+ * this library (16-byte loads and stores), enqueued on hip_stream.  Not a
+ * step of the method: it measures the bandwidth that a streaming kernel
+ * reaches on the device, the practical ceiling beside the vendor's peak for
+ * the memory-bound lattice sweep.  dst and src must be 16-byte aligned,
+ * bytes a multiple of 16, and the ranges must not overlap.                  */
+capib_status capib_copy_bandwidth(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 /* Message of the last failing call on this context (never NULL). */
 const char *capib_last_error(const capib_ctx *ctx);

@@ -36,6 +36,7 @@ def lib():
         L.orc_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int]
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_interactions.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
+        L.orc_set_velocity_wall.argtypes = [C.c_void_p, C.c_int]
         L.orc_init_flow.argtypes = [C.c_void_p, _dp]
         L.orc_get_populations.argtypes = [C.c_void_p, _dp]
         L.orc_set_populations.argtypes = [C.c_void_p, _dp]
@@ -45,6 +46,8 @@ def lib():
         L.orc_min_margin.argtypes = [C.c_void_p]
         L.orc_margins.argtypes = [C.c_void_p, _dp]
         L.orc_reset_margins.argtypes = [C.c_void_p]
+        L.orc_bond_flips.restype = C.c_int64
+        L.orc_bond_flips.argtypes = [C.c_void_p]
         L.orc_set_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
@@ -200,6 +203,11 @@ class Sim:
     def set_interactions(self, rep_pref, rep_cut, probe_dist):
         lib().orc_set_interactions(self.p, rep_pref, rep_cut, probe_dist)
 
+    def set_velocity_wall(self, image):
+        """Velocity coupling across a wall: odd image (True, the default) or
+        rows beyond the wall as wall nodes at rest (False, the earlier reading)."""
+        lib().orc_set_velocity_wall(self.p, 1 if image else 0)
+
     def init_flow(self, ux_of_y=None):
         if ux_of_y is None:
             lib().orc_init_flow(self.p, None)
@@ -240,15 +248,22 @@ class Sim:
         return lib().orc_min_margin(self.p)
 
     def margins(self):
-        """(smallest |draw - P| of the bond decisions, smallest |gap - y_cr| of
-        the formation decisions the gap decided) since the start or the last
-        reset_margins()."""
+        """(smallest |draw - P| / P of the bond decisions, smallest |gap - y_cr|
+        of the formation decisions the gap decided) since the start or the
+        last reset_margins()."""
         out = np.zeros(2)
         lib().orc_margins(self.p, _d(out))
         return float(out[0]), float(out[1])
 
     def reset_margins(self):
+        """Restarts the margin minima and the flip count."""
         lib().orc_reset_margins(self.p)
+
+    @property
+    def flips(self):
+        """Bond state changes (formations and ruptures) since the start or
+        the last reset_margins()."""
+        return lib().orc_bond_flips(self.p)
 
     def set_step(self, n):
         lib().orc_set_step(self.p, int(n))

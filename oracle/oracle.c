@@ -172,10 +172,14 @@ typedef struct {
     int nb, cap;
     orc_body *b;
     double rep_pref, rep_cut, rep_dmin, probe_dist;
+    int velocity_wall;         /* 1: odd image across the walls (default); 0: wall nodes at rest */
     int64_t step;
-    /* smallest |draw - P| over the bond decisions taken, and smallest
-     * |gap - y_cr| over the formation decisions that the gap decided */
+    /* smallest |draw - P| / P over the bond decisions taken (P > 0), and
+     * smallest |gap - y_cr| over the formation decisions that the gap
+     * decided: a code that computes P or the gap with a smaller relative or
+     * absolute error takes the same decisions */
     double min_margin_p, min_margin_gap;
+    int64_t flips;   /* bond state changes so far */
     int flags; /* bit0: a vertex left the rows [-1, ny] */
 } orc_sim;
 
@@ -184,7 +188,8 @@ typedef struct {
 static double *dz(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
 
 orc_sim *orc_create(int nx, int ny, double tau, double gx, double gy, int walls) {
-    if (nx < 1 || ny < 1 || !(tau > 0.5) || (walls != 0 && walls != 3)) return NULL;
+    /* with walls a stencil's mirrored rows must be fluid rows: ny >= 4 */
+    if (nx < 1 || ny < 1 || !(tau > 0.5) || (walls != 0 && walls != 3) || (walls && ny < 4)) return NULL;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
     s->nx = nx; s->ny = ny; s->tau = tau; s->gx = gx; s->gy = gy; s->walls = walls;
     size_t N = (size_t)nx * ny;
@@ -195,6 +200,7 @@ orc_sim *orc_create(int nx, int ny, double tau, double gx, double gy, int walls)
     /* interaction constants: Eq. (12) prefactor, minimum distance dx, probe 1.2 dx */
     s->rep_pref = 1.0e-4 / (8.0 * sqrt(2.0));
     s->rep_cut = 1.0; s->rep_dmin = 0.1; s->probe_dist = 1.2;
+    s->velocity_wall = 1;
     s->min_margin_p = INFINITY;
     s->min_margin_gap = INFINITY;
     return s;
@@ -215,6 +221,10 @@ void orc_destroy(orc_sim *s) {
     for (int k = 0; k < s->nb; k++) free_body(&s->b[k]);
     free(s->b); free(s);
 }
+
+/* Reading of the velocity coupling at the walls: 1 = odd image (default),
+ * 0 = rows beyond the wall are wall nodes at rest (earlier reading).       */
+void orc_set_velocity_wall(orc_sim *s, int image) { s->velocity_wall = image ? 1 : 0; }
 
 void orc_set_interactions(orc_sim *s, double rep_pref, double rep_cut, double probe_dist) {
     s->rep_pref = rep_pref; s->rep_cut = rep_cut; s->probe_dist = probe_dist;
@@ -242,7 +252,8 @@ double orc_min_margin(const orc_sim *s) {
     return s->min_margin_p < s->min_margin_gap ? s->min_margin_p : s->min_margin_gap;
 }
 void orc_margins(const orc_sim *s, double *out2) { out2[0] = s->min_margin_p; out2[1] = s->min_margin_gap; }
-void orc_reset_margins(orc_sim *s) { s->min_margin_p = INFINITY; s->min_margin_gap = INFINITY; }
+void orc_reset_margins(orc_sim *s) { s->min_margin_p = INFINITY; s->min_margin_gap = INFINITY; s->flips = 0; }
+int64_t orc_bond_flips(const orc_sim *s) { return s->flips; }
 void orc_set_step(orc_sim *s, int64_t n) { s->step = n; }
 void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int orc_get_threads(void) { return omp_get_max_threads(); }
@@ -303,16 +314,24 @@ static void node_moments(orc_sim *s) {
  * point's Y is clamped to [-1, ny] and rows beyond a wall are read in one of
  * two ways (the paper does not say how a stencil that crosses a wall is
  * treated):
- *   STEN_VELOCITY (interpolation of u* to vertices, spreading): the rows
- *     beyond the wall are wall nodes at rest.  They keep their kernel weight
- *     in the sum, contribute zero velocity and take no spread force.
+ *   STEN_VELOCITY (interpolation of u* to vertices, spreading): the fluid
+ *     velocity is continued across the no-slip wall as its odd image, so a
+ *     row beyond the wall stands for the fluid row mirrored about the wall
+ *     (row -1-j below y = -1/2, row 2 ny - 1 - j above y = ny - 1/2) with
+ *     the sign reversed; spreading is the adjoint, so force that lands on a
+ *     row beyond the wall reaches the mirrored fluid row negated.  The
+ *     interpolated velocity then vanishes on the wall itself.  (The earlier
+ *     reading, kept for the tests as velocity_wall = 0, counts the rows
+ *     beyond the wall as wall nodes at rest: zero velocity and no force,
+ *     with their weight kept in the normalising sum.  With it, the BDF2
+ *     target of Eq. (18) and direct forcing amplify a mode of rows 0-1 that
+ *     flips sign every step when deformable vertices sit between the wall
+ *     and the first fluid row.)
  *   STEN_PROBE (pressure and stress at the probes): the rows beyond the wall
  *     are dropped and the remaining weights renormalised, i.e. the fluid
  *     field is extrapolated.
- * (Renormalising the velocity coupling too makes deformable membranes whose
- * vertices sit between the wall and the first fluid row unstable.)
  * Returns the weights in w[b*4+a] (a along x), the wrapped node indices, and
- * jj[b] = -1 for rows beyond a wall.                                         */
+ * jj[b] (the row a weight applies to; -1 for a dropped row).               */
 enum { STEN_VELOCITY = 0, STEN_PROBE = 1 };
 static void stencil(orc_sim *s, double X, double Y, int mode, int ii[4], int jj[4], double w[16]) {
     if (s->walls) {
@@ -323,19 +342,28 @@ static void stencil(orc_sim *s, double X, double Y, int mode, int ii[4], int jj[
     double sum = 0;
     for (int b = 0; b < 4; b++) {
         int j = j0 + b;
-        int valid = 1;
+        int valid = 1;      /* a fluid row */
+        double sign = 1.0;
         if (j < 0 || j >= s->ny) {
-            if (s->walls) valid = 0;
-            else j = ((j % s->ny) + s->ny) % s->ny;
+            if (s->walls) {
+                valid = 0;
+                if (mode == STEN_VELOCITY && s->velocity_wall == 1) {
+                    j = j < 0 ? -1 - j : 2 * s->ny - 1 - j;   /* mirror row across the wall */
+                    sign = -1.0;
+                }
+            } else {
+                j = ((j % s->ny) + s->ny) % s->ny;
+            }
         }
-        jj[b] = valid ? j : -1;
+        int used = valid || sign < 0;
+        jj[b] = used ? j : -1;
         for (int a = 0; a < 4; a++) {
             int i = i0 + a;
             ii[a] = ((i % s->nx) + s->nx) % s->nx;
             double ww = orc_phi(X - (double)(i0 + a)) * orc_phi(Y - (double)(j0 + b));
             if (!valid && mode == STEN_PROBE) ww = 0.0;
             sum += ww;
-            w[b * 4 + a] = valid ? ww : 0.0;
+            w[b * 4 + a] = used ? sign * ww : 0.0;
         }
     }
     for (int k = 0; k < 16; k++) w[k] /= sum;
@@ -707,7 +735,7 @@ static void integrate(orc_sim *s, int k) {
  * Bound: P_r = 1 - exp(-k_r0 exp(|y_l - y_eq| / l_B)); the bond breaks if the
  * draw is below P_r.  Unbound with gap y_s + 1/2 < y_cr: P_f = 1 - exp(-k_f);
  * the bond forms, anchored straight below the site, if the draw is below P_f.
- * The smallest |draw - P| (and |gap - y_cr| where that decides) is recorded.   */
+ * The smallest |draw - P| / P (and |gap - y_cr| where that decides) is recorded. */
 static void bond_kinetics(orc_sim *s, int k) {
     orc_body *b = &s->b[k];
     int n = b->n;
@@ -719,15 +747,15 @@ static void bond_kinetics(orc_sim *s, int k) {
         if (b->bound[q]) {
             double yl = sqrt((xs - b->anchor[q]) * (xs - b->anchor[q]) + (ys + 0.5) * (ys + 0.5));
             double P = 1.0 - exp(-b->kr0 * exp(fabs(yl - b->yeq) / b->lb));
-            if (fabs(r - P) < s->min_margin_p) s->min_margin_p = fabs(r - P);
-            if (r < P) b->bound[q] = 0;
+            if (P > 0 && fabs(r - P) / P < s->min_margin_p) s->min_margin_p = fabs(r - P) / P;
+            if (r < P) { b->bound[q] = 0; s->flips++; }
         } else {
             double gap = ys + 0.5;
             double P = 1.0 - exp(-b->kf);
             if (r < P && fabs(gap - b->ycr) < s->min_margin_gap) s->min_margin_gap = fabs(gap - b->ycr);
             if (gap < b->ycr) {
-                if (fabs(r - P) < s->min_margin_p) s->min_margin_p = fabs(r - P);
-                if (r < P) { b->bound[q] = 1; b->anchor[q] = xs; }
+                if (P > 0 && fabs(r - P) / P < s->min_margin_p) s->min_margin_p = fabs(r - P) / P;
+                if (r < P) { b->bound[q] = 1; b->anchor[q] = xs; s->flips++; }
             }
         }
     }

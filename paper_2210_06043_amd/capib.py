@@ -49,7 +49,12 @@ class capib_body_diag(C.Structure):
     _fields_ = [("area", C.c_double), ("perimeter", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
                 ("area0", C.c_double), ("perimeter0", C.c_double), ("n_bound", C.c_int32), ("kind", C.c_int32),
                 ("xc", C.c_double), ("yc", C.c_double), ("phi", C.c_double), ("ucx", C.c_double),
-                ("ucy", C.c_double), ("omega", C.c_double)]
+                ("ucy", C.c_double), ("omega", C.c_double), ("n_bound0", C.c_int32), ("reserved", C.c_int32)]
+
+
+class capib_tuning(C.Structure):
+    _fields_ = [("split", C.c_int32), ("far_share_pct", C.c_int32), ("mark_pairs", C.c_int32),
+                ("membrane_class", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -67,12 +72,18 @@ SIGNATURES = {
     "capib_set_interactions": (C.c_int, [_P, C.c_double, C.c_double, C.c_double]),
     "capib_step": (C.c_int, [_P, C.c_int32]),
     "capib_set_graph": (C.c_int, [_P, C.c_int32]),
+    "capib_set_tuning": (C.c_int, [_P, C.POINTER(capib_tuning)]),
+    "capib_get_tuning": (C.c_int, [_P, C.POINTER(capib_tuning)]),
+    "capib_autotune": (C.c_int, [_P, C.c_int32, C.c_char_p, C.POINTER(capib_tuning), _dp]),
     "capib_read_macro": (C.c_int, [_P, _dp, _dp, _dp]),
     "capib_read_vertices": (C.c_int, [_P, C.c_int32, _dp]),
     "capib_read_bonds": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_uint8), _dp]),
     "capib_read_body_work": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _dp]),
     "capib_diagnostics": (C.c_int, [_P, C.POINTER(capib_diag)]),
     "capib_body_diagnostics": (C.c_int, [_P, C.c_int32, C.POINTER(capib_body_diag)]),
+    "capib_readout": (C.c_int, [_P, C.c_int32, C.c_int32, _dp]),
+    "capib_read_body_state": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp]),
+    "capib_copy_bandwidth": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "capib_save": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
     "capib_load": (C.c_int, [_P, _P, C.c_size_t]),
     "capib_set_timing": (C.c_int, [_P, C.c_int32]),
@@ -86,9 +97,13 @@ _lib = None
 
 
 def load_library(path=LIB_PATH):
-    """Loads libcapib.so (raises if it has not been built)."""
+    """Loads libcapib.so (raises if it has not been built).  torch is
+    imported first: its HIP runtime is then the one the library binds to,
+    so that one runtime serves both (the library loaded first would bring
+    in the system's copy, and torch could not initialise the device)."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above)
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build it with paper_2210_06043_amd/build.py")
         L = C.CDLL(path)
@@ -210,6 +225,26 @@ class Simulation:
     def set_graph(self, enable=True):
         self._check(self.L.capib_set_graph(self.ctx, 1 if enable else 0))
 
+    def set_tuning(self, split=-1, far_share_pct=-1, mark_pairs=-1, membrane_class=-1):
+        t = capib_tuning(split, far_share_pct, mark_pairs, membrane_class)
+        self._check(self.L.capib_set_tuning(self.ctx, C.byref(t)))
+
+    def tuning(self):
+        t = capib_tuning()
+        self._check(self.L.capib_get_tuning(self.ctx, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in capib_tuning._fields_}
+
+    def autotune(self, steps_per_trial=200, cache_path=None):
+        """Times launch configurations on this workload, applies the fastest
+        (state unchanged); returns it with its ms per step."""
+        t = capib_tuning()
+        ms = C.c_double()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.L.capib_autotune(self.ctx, int(steps_per_trial), path, C.byref(t), C.byref(ms)))
+        out = {k: getattr(t, k) for k, _ in capib_tuning._fields_}
+        out["ms_per_step"] = ms.value
+        return out
+
     def set_timing(self, enable=True):
         self._check(self.L.capib_set_timing(self.ctx, 1 if enable else 0))
 
@@ -265,14 +300,30 @@ class Simulation:
         if out is None:
             out = self.torch.empty((len(self.bands), 8), dtype=self.torch.float32, device=self.device)
         assert out.dtype == self.torch.float32 and out.is_contiguous() and out.numel() >= 8 * len(self.bands)
-        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
         self._check(self.L.capib_sample_members(self.ctx, particle_tag, cell_tag, _P(out.data_ptr())))
+        # the caller's stream sees the samples only after the library's stream wrote them
+        cur.wait_stream(self.stream)
         return out
 
     def body_diagnostics(self, body):
         d = capib_body_diag()
         self._check(self.L.capib_body_diagnostics(self.ctx, body, C.byref(d)))
-        return {k: getattr(d, k) for k, _ in capib_body_diag._fields_}
+        return {k: getattr(d, k) for k, _ in capib_body_diag._fields_ if k != "reserved"}
+
+    def readout(self, cell, particle):
+        """(delta_p of the cell, centroid distance r, N_L/N_L0 of the particle)."""
+        out = np.zeros(3)
+        self._check(self.L.capib_readout(self.ctx, cell, particle, _d(out)))
+        return dict(dp=float(out[0]), r=float(out[1]), nl_ratio=float(out[2]))
+
+    def body_state(self, body):
+        """x^n, x^n - x^{n-1} and the 9 rigid state values of a body."""
+        n = self.nv[body]
+        xy, d, r = np.zeros((n, 2)), np.zeros((n, 2)), np.zeros(9)
+        self._check(self.L.capib_read_body_state(self.ctx, body, _d(xy), _d(d), _d(r)))
+        return dict(xy=xy, dxy_prev=d, rigid=r)
 
     def save(self):
         n = C.c_size_t()
@@ -284,6 +335,18 @@ class Simulation:
     def load(self, blob):
         buf = C.create_string_buffer(blob, len(blob))
         self._check(self.L.capib_load(self.ctx, C.cast(buf, _P), len(blob)))
+
+
+def copy_bandwidth(dst, src, stream=None):
+    """Enqueues the library's streaming copy of the torch tensor src into dst
+    (same byte size, 16-byte aligned) on stream (default: the current one)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    st = stream if stream is not None else torch.cuda.current_stream()
+    s = load_library().capib_copy_bandwidth(_P(dst.data_ptr()), _P(src.data_ptr()), nbytes, _P(st.cuda_stream))
+    if s != CAPIB_OK:
+        raise CapibError(s, "capib_copy_bandwidth rejected its arguments")
 
 
 def fp16_scale_for(cfg, headroom=16.0):

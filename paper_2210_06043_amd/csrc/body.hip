@@ -75,6 +75,7 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
     __shared__ float ss_bond[MAXS];   // Eq. (13) magnitude of each engaged bond (0 if free)
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
+    __shared__ double shr[BT / 64][3];
 
     const int tid = threadIdx.x;
     // the next step's near tiles are listed from zero by this step's sweep
@@ -94,9 +95,10 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
     const Band BB = band_at<ENS>(d, P.band);
     // rigid state (centroid displacement, angle, velocities), read up front
     const float4 RS0 = *(const float4 *)&d.bs[b].dcxh;   // dcxh, dcxl, dcyh, dcyl
-    const float4 RS1 = *(const float4 *)&d.bs[b].phih;   // phih, phil, ucx, ucy
-    const float4 RS2 = *(const float4 *)&d.bs[b].ucxm;   // ucxm, ucym, om, omm
-    const float2 RS3 = *(const float2 *)&d.bs[b].rot;    // cos(phi) - 1, sin(phi)
+    const float4 RS1 = *(const float4 *)&d.bs[b].phih;   // phih, phil, cos(phi) - 1, sin(phi)
+    const double2 RU0 = *(const double2 *)&d.bs[b].u[0];  // u_x, u_y at n
+    const double2 RU1 = *(const double2 *)&d.bs[b].u[2];  // omega at n, u_x at n-1
+    const double2 RU2 = *(const double2 *)&d.bs[b].um[1]; // u_y, omega at n-1
 
     // ---- every per-vertex and per-site global load of the step, issued together --
     float rxh[VPT], rxl[VPT], ryh[VPT], ryl[VPT], rl0[VPT], rth0[VPT], rdxm[VPT], rdym[VPT];
@@ -131,7 +133,8 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
     // sites: host element, draw index, state, fraction and anchor of this
     // thread's own
     int rsh[SPT], rso[SPT], rst[SPT];
-    float rsf[SPT], rsah[SPT], rsal[SPT];
+    double rsf[SPT];
+    float rsah[SPT], rsal[SPT];
 #pragma unroll
     for (int k = 0; k < SPT; k++) {
         const int q = tid + k * BT;
@@ -160,14 +163,16 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
             if (q >= ns) continue;
             float bf = 0.0f;
             if (rst[k]) {
+                // FP64 from the hi/lo positions: the stretch is a small
+                // difference of lengths close to y_eq
                 const int e = rsh[k] - v0;
                 const int m = (e + 1 == n) ? 0 : e + 1;
-                const float tx = (sxh[m] - sxh[e]) + (sxl[m] - sxl[e]);
-                const float ty = (syh[m] - syh[e]) + (syl[m] - syl[e]);
-                const float f = rsf[k];
-                const float dx = (sxh[e] - rsah[k]) + ((sxl[e] - rsal[k]) + f * tx);
-                const float dy = (syh[e] + 0.5f) + (syl[e] + f * ty);
-                bf = P.sigma * (sqrtf(dx * dx + dy * dy) - P.yeq);
+                const double xe = (double)sxh[e] + (double)sxl[e], ye = (double)syh[e] + (double)syl[e];
+                const double xm = (double)sxh[m] + (double)sxl[m], ym = (double)syh[m] + (double)syl[m];
+                const double f = rsf[k];
+                const double dx = (xe + f * (xm - xe)) - ((double)rsah[k] + (double)rsal[k]);
+                const double dy = (ye + f * (ym - ye)) + 0.5;
+                bf = (float)(P.sigma64 * (sqrt(dx * dx + dy * dy) - P.yeq64));
             }
             ss_bond[q] = bf;
         }
@@ -329,32 +334,35 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
     // ---- integration (Eqs. 16-20), direct forcing and spreading at x^n -----------------
     float nxh[VPT], nxl[VPT], nyh[VPT], nyl[VPT];
     if (rigid) {
-        const float c1 = RS3.x, sphi = RS3.y;   // rotation by the stored angle
-        float Fx = 0.0f, Fy = 0.0f, M = 0.0f;
+        const float c1 = RS1.z, sphi = RS1.w;   // rotation by the stored angle
+        // total force and moment about the centroid, summed in FP64
+        double Fx = 0.0, Fy = 0.0, M = 0.0;
 #pragma unroll
         for (int k = 0; k < VPT; k++) {
             const int v = tid + k * BT;
             if (v >= n) continue;
             const float rx = rr0x[k], ry = rr0y[k];
             const float armx = rx + (c1 * rx - sphi * ry), army = ry + (sphi * rx + c1 * ry);
-            Fx += fvx[k];
-            Fy += fvy[k];
-            M += armx * fvy[k] - army * fvx[k];
+            Fx += (double)fvx[k];
+            Fy += (double)fvy[k];
+            M += (double)armx * (double)fvy[k] - (double)army * (double)fvx[k];
         }
-        Fx = wave_total(Fx, OpAdd());
-        Fy = wave_total(Fy, OpAdd());
-        M = wave_total(M, OpAdd());
-        if ((tid & 63) == 0) { shf[tid >> 6][0] = Fx; shf[tid >> 6][1] = Fy; shf[tid >> 6][2] = M; }
+        Fx = wave_total_d(Fx);
+        Fy = wave_total_d(Fy);
+        M = wave_total_d(M);
+        if ((tid & 63) == 0) { shr[tid >> 6][0] = Fx; shr[tid >> 6][1] = Fy; shr[tid >> 6][2] = M; }
         __syncthreads();
         // every thread sums the wave partials in the same order and takes
         // the same rigid update (no second barrier); thread 0 stores it.
         // Waves past the last vertex hold +0 and are left out.
         const int nw = min(BT / 64, (n + 63) / 64);
-        Fx = 0.0f; Fy = 0.0f; M = 0.0f;
-        for (int w = 0; w < nw; w++) { Fx += shf[w][0]; Fy += shf[w][1]; M += shf[w][2]; }
-        const float ux = (2.0f / 3.0f) * (2.0f * RS1.z - 0.5f * RS2.x + Fx * P.inv_mass);
-        const float uy = (2.0f / 3.0f) * (2.0f * RS1.w - 0.5f * RS2.y + Fy * P.inv_mass);
-        const float om = (2.0f / 3.0f) * (2.0f * RS2.z - 0.5f * RS2.w + M * P.inv_inertia);
+        Fx = 0.0; Fy = 0.0; M = 0.0;
+        for (int w = 0; w < nw; w++) { Fx += shr[w][0]; Fy += shr[w][1]; M += shr[w][2]; }
+        // Eqs. (19)-(20) in FP64: u^{n+1} = 2/3 (2 u^n - u^{n-1}/2 + F/m)
+        const double uxd = (2.0 / 3.0) * (2.0 * RU0.x - 0.5 * RU1.y + Fx * (double)P.inv_mass);
+        const double uyd = (2.0 / 3.0) * (2.0 * RU0.y - 0.5 * RU2.x + Fy * (double)P.inv_mass);
+        const double omd = (2.0 / 3.0) * (2.0 * RU1.x - 0.5 * RU2.y + M * (double)P.inv_inertia);
+        const float ux = (float)uxd, uy = (float)uyd, om = (float)omd;
         float dcxh = RS0.x, dcxl = RS0.y, dcyh = RS0.z, dcyl = RS0.w, phih = RS1.x, phil = RS1.y;
         df_add(dcxh, dcxl, ux);
         df_add(dcyh, dcyl, uy);
@@ -362,8 +370,11 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         if (tid == 0) {
             BodyState &S = d.bs[b];
             *(float4 *)&S.dcxh = make_float4(dcxh, dcxl, dcyh, dcyl);
-            *(float4 *)&S.phih = make_float4(phih, phil, ux, uy);
-            *(float4 *)&S.ucxm = make_float4(RS1.z, RS1.w, om, RS2.z);
+            S.phih = phih;
+            S.phil = phil;
+            *(double2 *)&S.u[0] = make_double2(uxd, uyd);
+            *(double2 *)&S.u[2] = make_double2(omd, RU0.x);   // omega, then u_x of the step before
+            *(double2 *)&S.um[1] = make_double2(RU0.y, RU1.x);
         }
         const float srig[7] = {ux, uy, om, dcxh, dcxl, dcyh, dcyl};
         const float ph = phih + phil;
@@ -449,30 +460,30 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         if (q >= ns) continue;
         const int e = rsh[k] - v0;
         const int m = (e + 1 == n) ? 0 : e + 1;
-        const float f = rsf[k];
-        const float tx = (sxh[m] - sxh[e]) + (sxl[m] - sxl[e]);
-        const float ty = (syh[m] - syh[e]) + (syl[m] - syl[e]);
-        const float xsh = sxh[e], xsl = sxl[e] + f * tx;
-        const float ysh = syh[e], ysl = syl[e] + f * ty;
+        // the site at x^{n+1}, FP64 from the hi/lo positions (its gap and
+        // stretch are small differences)
+        const double xe = (double)sxh[e] + (double)sxl[e], ye = (double)syh[e] + (double)syl[e];
+        const double xm = (double)sxh[m] + (double)sxl[m], ym = (double)syh[m] + (double)syl[m];
+        const double f = rsf[k];
+        const double xs = xe + f * (xm - xe), ys = ye + f * (ym - ye);
         const uint32_t w = philox_w0((uint32_t)step, (uint32_t)rso[k], (uint32_t)((unsigned long long)step >> 32),
                                      0u, P.seed_lo, P.seed_hi);
         const float r = (float)(w >> 8) * (1.0f / 16777216.0f);
         int st = rst[k];
         if (st) {
-            const float dx = (xsh - rsah[k]) + (xsl - rsal[k]);
-            const float dy = (ysh + 0.5f) + ysl;
-            const float yl = sqrtf(dx * dx + dy * dy);
-            const float Pr = -expm1f(-P.kr0 * expf(fabsf(yl - P.yeq) / P.lb));
+            const double dx = xs - ((double)rsah[k] + (double)rsal[k]);
+            const double dy = ys + 0.5;
+            const float stretch = (float)fabs(sqrt(dx * dx + dy * dy) - P.yeq64);
+            const float Pr = -expm1f(-P.kr0 * expf(stretch / P.lb));
             if (r < Pr) st = 0;
         } else {
-            const float gap = (ysh + 0.5f) + ysl;
-            if (gap < P.ycr) {
+            if (ys + 0.5 < P.ycr64) {
                 const float Pf = -expm1f(-P.kf);
                 if (r < Pf) {
                     st = 1;
-                    const float ah = xsh + xsl;
+                    const float ah = (float)xs;
                     d.s_anh[s0 + q] = ah;
-                    d.s_anl[s0 + q] = xsl - (ah - xsh);
+                    d.s_anl[s0 + q] = (float)(xs - (double)ah);
                 }
             }
         }
@@ -579,14 +590,17 @@ __global__ __launch_bounds__(BodyShape<MV>::BT) void k_body_far(Dev d, int nfb) 
     if (fb < nfb) far_tile<T, PAR, ENS>(d, fb, threadIdx.x % LAT_THREADS);
 }
 
-// Share of the far-tile candidates swept by the membrane launch, in percent
-// (measured on 3840 x 240: the membrane kernel's 8-9 us hide about this much
-// streaming; FP16 tiles cost half the bytes).
+// Default share of the far-tile candidates swept by the membrane launch, in
+// percent (measured on 3840 x 240: the membrane kernel's 8-9 us hide about
+// this much streaming; FP16 tiles cost half the bytes); the autotuner picks
+// it per workload.
 constexpr int FAR_SHARE_FP32 = 50, FAR_SHARE_FP16 = 80;
+
+int default_far_share(int storage) { return storage == 0 ? FAR_SHARE_FP32 : FAR_SHARE_FP16; }
 
 int body_far_tiles(const Dev &d) {
     const int ncand = d.nbands > 1 ? d.nlive : d.ntx * d.nty;
-    return (int)((long long)ncand * (d.storage == 0 ? FAR_SHARE_FP32 : FAR_SHARE_FP16) / 100);
+    return (int)((long long)ncand * d.far_share / 100);
 }
 
 template <typename T, int MV>

@@ -20,7 +20,7 @@ namespace {
 
 struct BodyHost {
     int kind, n, vstart, band = 0;
-    int site_start = 0, n_sites = 0;
+    int site_start = 0, n_sites = 0, n_bound0 = 0;
     bool has_bonds = false;
     double A0, P0;
     std::vector<double> xy;        // shape at creation
@@ -43,6 +43,7 @@ constexpr int GRAPH_STEPS = 16;
 
 struct capib_ctx {
     capib_lattice lat;
+    int device = -1;               // HIP device current at creation (or at binding)
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     Dev d{};
@@ -84,6 +85,8 @@ struct capib_ctx {
     hipStream_t side = nullptr, cap_side = nullptr;
     hipEvent_t ev_fork[GRAPH_STEPS] = {}, ev_join[GRAPH_STEPS] = {};
     bool marks_valid = false;
+    // launch configuration asked for (-1: the library's rule), see capib_tuning
+    capib_tuning tune{-1, -1, -1, -1};
 };
 
 static capib_status fail(capib_ctx *c, capib_status s, const char *fmt, ...) {
@@ -147,7 +150,7 @@ static void layout(capib_ctx *c) {
     c->off_shost = o; o = align256(o + S * 4);
     c->off_sstate = o; o = align256(o + S * 4);
     c->off_sorig = o; o = align256(o + S * 4);
-    c->off_sfrac = o; o = align256(o + S * 4);
+    c->off_sfrac = o; o = align256(o + S * 8);
     c->off_sanh = o; o = align256(o + S * 4);
     c->off_sanl = o; o = align256(o + S * 4);
     c->ib_bytes = o - c->off_ib;
@@ -201,6 +204,11 @@ static void fill_dev(capib_ctx *c) {
         const int need = std::max(bh.n, (bh.n_sites + 1) / 2);
         while (d.body_mv < need) d.body_mv *= 2;
     }
+    // launch configuration: the tuning asked for, else the library's rules
+    if (c->tune.membrane_class > d.body_mv) d.body_mv = c->tune.membrane_class;
+    d.split = c->tune.split >= 0 ? c->tune.split : default_split(c->ntx * c->nty);
+    d.far_share = c->tune.far_share_pct >= 0 ? c->tune.far_share_pct : default_far_share(L.storage);
+    d.mark_pairs = c->tune.mark_pairs >= 0 ? c->tune.mark_pairs : default_mark_pairs(c->nverts);
     d.band_nx = (const int *)(b + c->off_band);
     d.band_bodies = (const int2 *)(b + c->off_band + 4 * (size_t)c->nbands);
     d.live = (const int *)(b + c->off_live);
@@ -234,7 +242,7 @@ static void fill_dev(capib_ctx *c) {
     d.target = (float2 *)(b + c->off_target);
     d.srange = (int2 *)(b + c->off_srange);
     d.s_host = (int *)(b + c->off_shost); d.s_state = (int *)(b + c->off_sstate);
-    d.s_orig = (int *)(b + c->off_sorig); d.s_frac = (float *)(b + c->off_sfrac);
+    d.s_orig = (int *)(b + c->off_sorig); d.s_frac = (double *)(b + c->off_sfrac);
     d.s_anh = (float *)(b + c->off_sanh); d.s_anl = (float *)(b + c->off_sanl);
 }
 
@@ -317,6 +325,8 @@ static capib_status create_stack(const capib_lattice *lat, int nbands, const int
     // bands are whole tile rows, so that no tile straddles two of them
     if (nbands > 1 && L.ny % TILE_Y != 0) return CAPIB_E_ARG;
     if (L.ny < 2 || (long long)wmax * L.ny * nbands > (1LL << 31)) return CAPIB_E_ARG;
+    // with walls the velocity stencil folds onto four fluid rows
+    if (L.walls && L.ny < 4) return CAPIB_E_ARG;
     if (!(L.tau > 0.5) || !std::isfinite(L.tau) || !std::isfinite(L.gx) || !std::isfinite(L.gy)) return CAPIB_E_ARG;
     if (L.walls != 0 && L.walls != 3) return CAPIB_E_ARG;
     if (L.storage != CAPIB_FP32_SHIFTED && L.storage != CAPIB_FP16_SHIFTED) return CAPIB_E_ARG;
@@ -326,7 +336,10 @@ static capib_status create_stack(const capib_lattice *lat, int nbands, const int
         if (!(L.fp16_scale > 0) || m != 0.5) return CAPIB_E_ARG;   // a power of two
     }
     if (L.max_bodies < 0 || L.max_vertices < 0 || L.max_sites < 0) return CAPIB_E_ARG;
+    int dev = -1;   // unknown until a device is present (set again when the workspace is bound)
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
     capib_ctx *c = new capib_ctx();
+    c->device = dev;
     c->nbands = nbands;
     c->band_rows = L.ny;
     c->band_nx.assign(widths, widths + nbands);
@@ -369,6 +382,7 @@ capib_status capib_bind_workspace(capib_ctx *c, void *ptr, size_t bytes) {
     if (!ptr || bytes < c->ws_bytes) return fail(c, CAPIB_E_ARG, "workspace of %zu bytes needs %zu", bytes, c->ws_bytes);
     if (((uintptr_t)ptr & 255) != 0) return fail(c, CAPIB_E_ARG, "workspace not 256-byte aligned");
     drop_graphs(c);
+    if (c->device < 0) HIPCHK(c, hipGetDevice(&c->device));
     c->base = (char *)ptr;
     c->bound = true;
     c->marks_valid = false;
@@ -623,14 +637,15 @@ capib_status capib_add_bonds(capib_ctx *c, int32_t body_id, const capib_bonds *b
     });
     const int s0 = c->nsites, n = bh.n;
     std::vector<int> host(ns), state(ns), orig(ns);
-    std::vector<float> frac(ns), anh(ns, 0), anl(ns, 0);
+    std::vector<double> frac(ns);
+    std::vector<float> anh(ns, 0), anl(ns, 0);
     std::vector<int2> sr(n, make_int2(s0, s0));
     int nb = 0;
     for (int k = 0; k < ns; k++) {
         const int q = perm[k];
         const int e = bd->host_elem[q], mm = (e + 1) % n;
         host[k] = bh.vstart + e;
-        frac[k] = (float)bd->frac[q];
+        frac[k] = bd->frac[q];
         orig[k] = q;
         const double xs = bh.xy[2 * e] + bd->frac[q] * (bh.xy[2 * mm] - bh.xy[2 * e]);
         const double ys = bh.xy[2 * e + 1] + bd->frac[q] * (bh.xy[2 * mm + 1] - bh.xy[2 * e + 1]);
@@ -650,6 +665,7 @@ capib_status capib_add_bonds(capib_ctx *c, int32_t body_id, const capib_bonds *b
     if ((s = d2h(c, &bp, c->off_bp + body_id * sizeof(BodyParams), sizeof bp))) return s;
     bp.site_start = s0; bp.n_sites = ns;
     bp.sigma = (float)bd->sigma; bp.ycr = (float)bd->y_cr; bp.yeq = (float)bd->y_eq;
+    bp.sigma64 = bd->sigma; bp.yeq64 = bd->y_eq; bp.ycr64 = bd->y_cr;
     bp.kf = (float)bd->k_f; bp.kr0 = (float)bd->k_r0; bp.lb = (float)bd->bell_len;
     bp.seed_lo = (uint32_t)(bd->seed & 0xffffffffu);
     bp.seed_hi = (uint32_t)(bd->seed >> 32);
@@ -662,11 +678,12 @@ capib_status capib_add_bonds(capib_ctx *c, int32_t body_id, const capib_bonds *b
     if ((s = h2d(c, c->off_shost + so, host.data(), ns * 4))) return s;
     if ((s = h2d(c, c->off_sstate + so, state.data(), ns * 4))) return s;
     if ((s = h2d(c, c->off_sorig + so, orig.data(), ns * 4))) return s;
-    if ((s = h2d(c, c->off_sfrac + so, frac.data(), ns * 4))) return s;
+    if ((s = h2d(c, c->off_sfrac + (size_t)s0 * 8, frac.data(), ns * 8))) return s;
     if ((s = h2d(c, c->off_sanh + so, anh.data(), ns * 4))) return s;
     if ((s = h2d(c, c->off_sanl + so, anl.data(), ns * 4))) return s;
     if ((s = h2d(c, c->off_srange + (size_t)bh.vstart * 8, sr.data(), n * 8))) return s;
     bh.has_bonds = true;
+    bh.n_bound0 = nb;
     bh.site_start = s0;
     bh.n_sites = ns;
     bh.perm = perm;
@@ -753,6 +770,18 @@ static capib_status make_graph(capib_ctx *c, int par, int nsteps, hipGraphExec_t
     return CAPIB_OK;
 }
 
+// All four executables (16 and 2 steps, both starting parities), captured
+// and instantiated together, so that no later call builds a graph between
+// replays.
+static capib_status build_graphs(capib_ctx *c) {
+    capib_status s;
+    for (int p = 0; p < 2; p++) {
+        if (!c->gexec[p] && (s = make_graph(c, p, GRAPH_STEPS, &c->gexec[p]))) return s;
+        if (!c->gexec2[p] && (s = make_graph(c, p, 2, &c->gexec2[p]))) return s;
+    }
+    return CAPIB_OK;
+}
+
 capib_status capib_step(capib_ctx *c, int32_t nsteps) {
     capib_status s = need_ws(c);
     if (s) return s;
@@ -808,14 +837,13 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
         return CAPIB_OK;
     }
     int t = 0;
-    if (c->use_graph) {
+    if (c->use_graph && nsteps >= 2) {
+        if ((s = build_graphs(c))) return s;
         for (; t + GRAPH_STEPS <= nsteps; t += GRAPH_STEPS) {
-            if (!c->gexec[c->par] && (s = make_graph(c, c->par, GRAPH_STEPS, &c->gexec[c->par]))) return s;
             HIPCHK(c, hipGraphLaunch(c->gexec[c->par], c->stream));
             c->step += GRAPH_STEPS;
         }
         for (; t + 2 <= nsteps; t += 2) {
-            if (!c->gexec2[c->par] && (s = make_graph(c, c->par, 2, &c->gexec2[c->par]))) return s;
             HIPCHK(c, hipGraphLaunch(c->gexec2[c->par], c->stream));
             c->step += 2;
         }
@@ -831,7 +859,186 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
 capib_status capib_set_graph(capib_ctx *c, int32_t enable) {
     if (!c) return CAPIB_E_ARG;
     c->use_graph = enable != 0;
-    if (!c->use_graph) drop_graphs(c);
+    if (!c->use_graph) {
+        drop_graphs(c);
+        return CAPIB_OK;
+    }
+    // with a workspace bound, instantiate the graphs now
+    return c->bound ? build_graphs(c) : CAPIB_OK;
+}
+
+// ---- launch configuration and its autotuner ---------------------------------------
+
+capib_status capib_set_tuning(capib_ctx *c, const capib_tuning *t) {
+    if (!c || !t) return CAPIB_E_ARG;
+    if (t->split < -1 || t->split > 1 || t->mark_pairs < -1 || t->mark_pairs > 1 || t->far_share_pct < -1 ||
+        t->far_share_pct > 100 || !(t->membrane_class == -1 || t->membrane_class == 256 ||
+                                    t->membrane_class == 512 || t->membrane_class == MAXV_BODY))
+        return fail(c, CAPIB_E_ARG, "bad tuning {%d, %d, %d, %d}", t->split, t->far_share_pct, t->mark_pairs,
+                    t->membrane_class);
+    c->tune = *t;
+    drop_graphs(c);
+    if (c->bound) fill_dev(c);
+    return CAPIB_OK;
+}
+
+capib_status capib_get_tuning(const capib_ctx *c, capib_tuning *t) {
+    if (!c || !t) return CAPIB_E_ARG;
+    // resolved as the next step will launch (with the bodies added so far)
+    t->split = c->tune.split >= 0 ? c->tune.split : (c->bound ? c->d.split : default_split(c->ntx * c->nty));
+    t->far_share_pct = c->tune.far_share_pct >= 0 ? c->tune.far_share_pct
+                                                  : (c->bound ? c->d.far_share : default_far_share(c->lat.storage));
+    t->mark_pairs = c->tune.mark_pairs >= 0 ? c->tune.mark_pairs
+                                            : (c->bound ? c->d.mark_pairs : default_mark_pairs(c->nverts));
+    t->membrane_class = c->bound ? c->d.body_mv : (c->tune.membrane_class > 0 ? c->tune.membrane_class : 256);
+    return CAPIB_OK;
+}
+
+// Workload signature of the cache: device, lattice shape and storage, the
+// bands, the membranes and the sites (their counts and the largest membrane).
+static std::string tune_key(const capib_ctx *c) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (c->device >= 0 && hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    uint64_t h = 1469598103934665603ULL;   // FNV-1a of the band widths
+    for (int w : c->band_nx) {
+        h ^= (uint64_t)(uint32_t)w;
+        h *= 1099511628211ULL;
+    }
+    int big = 0;
+    for (const BodyHost &bh : c->bodies) big = std::max(big, bh.n);
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s|rows=%d|bands=%d|widths=%016llx|storage=%d|walls=%d|bodies=%d|verts=%d|sites=%d|"
+             "largest=%d|graph=%d", arch.c_str(), c->band_rows, c->nbands, (unsigned long long)h, c->lat.storage,
+             c->lat.walls, c->nbodies, c->nverts, c->nsites, big, c->use_graph ? 1 : 0);
+    return buf;
+}
+
+static bool tune_cache_lookup(const char *path, const std::string &key, capib_tuning *t, double *ms) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char *tab = strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        if (key != line) continue;
+        capib_tuning r;
+        double m;
+        if (sscanf(tab + 1, "%d %d %d %d %lf", &r.split, &r.far_share_pct, &r.mark_pairs, &r.membrane_class, &m) == 5) {
+            *t = r;   // the last matching line wins
+            *ms = m;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+capib_status capib_autotune(capib_ctx *c, int32_t steps, const char *cache_path, capib_tuning *chosen,
+                            double *best_ms) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (steps < 16) return fail(c, CAPIB_E_ARG, "at least 16 steps per trial");
+    const std::string key = tune_key(c);
+    capib_tuning best = c->tune;
+    double best_t = 0.0;
+    if (cache_path && tune_cache_lookup(cache_path, key, &best, &best_t)) {
+        if ((s = capib_set_tuning(c, &best))) return s;
+        if (chosen) *chosen = best;
+        if (best_ms) *best_ms = best_t;
+        return CAPIB_OK;
+    }
+    // the state every trial starts from, restored at the end
+    size_t bytes = 0;
+    if ((s = capib_save(c, nullptr, &bytes))) return s;
+    std::vector<char> ck(bytes);
+    if ((s = capib_save(c, ck.data(), &bytes))) return s;
+    const capib_tuning asked = c->tune;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    auto trial = [&](const capib_tuning &t, double &ms) -> capib_status {
+        capib_status r;
+        if ((r = capib_set_tuning(c, &t))) return r;
+        if ((r = capib_load(c, ck.data(), ck.size()))) return r;
+        if ((r = capib_step(c, GRAPH_STEPS))) return r;   // warm-up: marks, graphs
+        ms = 1e30;
+        for (int rep = 0; rep < 2; rep++) {
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            if ((r = capib_step(c, steps))) return r;
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float el = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&el, e0, e1));
+            ms = std::min(ms, (double)el / steps);
+        }
+        return CAPIB_OK;
+    };
+    // coordinate descent from the library's own configuration: the
+    // schedule, then (one sweep after the membrane phase) the far share of
+    // the membrane launch, the marking layout, the membrane class
+    capib_tuning cur;
+    if ((s = capib_get_tuning(c, &cur))) return s;
+    double cur_t = 0.0;
+    auto better = [&](capib_tuning t) -> capib_status {
+        double m;
+        capib_status r = trial(t, m);
+        if (r) return r;
+        if (m < cur_t) { cur = t; cur_t = m; }
+        return CAPIB_OK;
+    };
+    if ((s = trial(cur, cur_t))) goto done;
+    {
+        capib_tuning t = cur;
+        t.split = 1 - cur.split;
+        if ((s = better(t))) goto done;
+    }
+    if (cur.split == 0)
+        for (int share : {20, 35, 50, 65, 80, 95}) {
+            if (share == cur.far_share_pct) continue;
+            capib_tuning t = cur;
+            t.far_share_pct = share;
+            if ((s = better(t))) goto done;
+        }
+    {
+        capib_tuning t = cur;
+        t.mark_pairs = 1 - cur.mark_pairs;
+        if ((s = better(t))) goto done;
+    }
+    for (int cls : {256, 512, MAXV_BODY}) {
+        if (cls <= cur.membrane_class) continue;
+        capib_tuning t = cur;
+        t.membrane_class = cls;
+        if ((s = better(t))) goto done;
+    }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) {
+        // leave the context as it was asked for, with its state
+        c->tune = asked;
+        fill_dev(c);
+        drop_graphs(c);
+        (void)capib_load(c, ck.data(), ck.size());
+        return s;
+    }
+    best = cur;
+    best_t = cur_t;
+    if ((s = capib_set_tuning(c, &best))) return s;
+    if ((s = capib_load(c, ck.data(), ck.size()))) return s;
+    if (c->use_graph && (s = build_graphs(c))) return s;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s\t%d %d %d %d %.6f\n", key.c_str(), best.split, best.far_share_pct, best.mark_pairs,
+                    best.membrane_class, best_t);
+            fclose(f);
+        }
+    }
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = best_t;
     return CAPIB_OK;
 }
 
@@ -910,14 +1117,11 @@ capib_status capib_read_body_work(capib_ctx *c, int32_t b, double *ustar, double
     return CAPIB_OK;
 }
 
-capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
-    capib_status s = need_ws(c);
-    if (s) return s;
-    if (!out) return fail(c, CAPIB_E_ARG, "null output");
-    HIPCHK(c, launch_diag(c->d, c->par, c->stream));
-    double r[3];
+// The FP64 totals r[3] (sums of the stored deviations) completed with the
+// reference part, the step counter and the error flags.
+static capib_status diag_finish(capib_ctx *c, const double r[3], capib_diag *out) {
+    capib_status s;
     const size_t nblk = (size_t)c->ntx * c->nty;
-    if ((s = d2h(c, r, c->off_red + 3 * nblk * 8, 24))) return s;
     long long cnt;
     int err;
     if ((s = d2h(c, &cnt, c->off_scal, 8))) return s;
@@ -949,6 +1153,17 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     return CAPIB_OK;
 }
 
+capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!out) return fail(c, CAPIB_E_ARG, "null output");
+    HIPCHK(c, launch_diag(c->d, c->par, c->stream));
+    double r[3];
+    const size_t nblk = (size_t)c->ntx * c->nty;
+    if ((s = d2h(c, r, c->off_red + 3 * nblk * 8, 24))) return s;
+    return diag_finish(c, r, out);
+}
+
 capib_status capib_sample_members(capib_ctx *c, int32_t particle_tag, int32_t cell_tag, float *out_device) {
     capib_status s = need_ws(c);
     if (s) return s;
@@ -972,6 +1187,7 @@ capib_status capib_body_diagnostics(capib_ctx *c, int32_t b, capib_body_diag *ou
     out->area0 = bh.A0;
     out->perimeter0 = bh.P0;
     out->n_bound = bs.n_bound;
+    out->n_bound0 = bh.n_bound0;
     out->kind = bh.kind;
     if (bh.kind == CAPIB_RIGID) {
         BodyParams bp;
@@ -979,10 +1195,63 @@ capib_status capib_body_diagnostics(capib_ctx *c, int32_t b, capib_body_diag *ou
         out->xc = ((double)bp.c0xh + bp.c0xl) + ((double)bs.dcxh + bs.dcxl);
         out->yc = ((double)bp.c0yh + bp.c0yl) + ((double)bs.dcyh + bs.dcyl);
         out->phi = (double)bs.phih + bs.phil;
-        out->ucx = bs.ucx; out->ucy = bs.ucy; out->omega = bs.om;
+        out->ucx = bs.u[0]; out->ucy = bs.u[1]; out->omega = bs.u[2];
     } else {
         out->xc = out->yc = out->phi = out->ucx = out->ucy = out->omega = 0;
     }
+    return CAPIB_OK;
+}
+
+capib_status capib_read_body_state(capib_ctx *c, int32_t b, double *xy, double *dxy_prev, double *rigid9) {
+    capib_status s = check_body(c, b);
+    if (s) return s;
+    const BodyHost &bh = c->bodies[b];
+    const int n = bh.n;
+    if (xy && (s = capib_read_vertices(c, b, xy))) return s;
+    if (dxy_prev) {
+        std::vector<float> a(2 * n);
+        if ((s = d2h(c, a.data(), c->off_dxm + (size_t)bh.vstart * 4, n * 4))) return s;
+        if ((s = d2h(c, a.data() + n, c->off_dym + (size_t)bh.vstart * 4, n * 4))) return s;
+        for (int v = 0; v < n; v++) {
+            dxy_prev[2 * v] = bh.kind == CAPIB_DEFORMABLE ? (double)a[v] : 0.0;
+            dxy_prev[2 * v + 1] = bh.kind == CAPIB_DEFORMABLE ? (double)a[n + v] : 0.0;
+        }
+    }
+    if (rigid9) {
+        for (int k = 0; k < 9; k++) rigid9[k] = 0.0;
+        if (bh.kind == CAPIB_RIGID) {
+            BodyParams bp;
+            BodyState bs;
+            if ((s = d2h(c, &bp, c->off_bp + b * sizeof(BodyParams), sizeof bp))) return s;
+            if ((s = d2h(c, &bs, c->off_bs + b * sizeof(BodyState), sizeof bs))) return s;
+            rigid9[0] = ((double)bp.c0xh + bp.c0xl) + ((double)bs.dcxh + bs.dcxl);
+            rigid9[1] = ((double)bp.c0yh + bp.c0yl) + ((double)bs.dcyh + bs.dcyl);
+            rigid9[2] = (double)bs.phih + bs.phil;
+            rigid9[3] = bs.u[0]; rigid9[4] = bs.u[1]; rigid9[5] = bs.um[0]; rigid9[6] = bs.um[1];
+            rigid9[7] = bs.u[2]; rigid9[8] = bs.um[2];
+        }
+    }
+    return CAPIB_OK;
+}
+
+capib_status capib_readout(capib_ctx *c, int32_t cell, int32_t particle, double *out3) {
+    capib_status s = check_body(c, cell);
+    if (s) return s;
+    if ((s = check_body(c, particle))) return s;
+    if (!out3) return fail(c, CAPIB_E_ARG, "null output");
+    if (cell == particle) return fail(c, CAPIB_E_ARG, "the cell and the particle are the same body");
+    const BodyHost &bc = c->bodies[cell], &bpart = c->bodies[particle];
+    if (bc.band != bpart.band) return fail(c, CAPIB_E_ARG, "bodies %d and %d are in different members", cell, particle);
+    capib_body_diag dc, dp;
+    if ((s = capib_body_diagnostics(c, cell, &dc))) return s;
+    if ((s = capib_body_diagnostics(c, particle, &dp))) return s;
+    const double L = c->band_nx[bc.band];
+    double dx = dc.cx - dp.cx;
+    dx -= L * std::floor(dx / L + 0.5);   // minimum image: x is periodic
+    const double dy = dc.cy - dp.cy;
+    out3[0] = dc.perimeter / dc.perimeter0 - 1.0;
+    out3[1] = std::sqrt(dx * dx + dy * dy);
+    out3[2] = dp.n_bound0 > 0 ? (double)dp.n_bound / dp.n_bound0 : 0.0;
     return CAPIB_OK;
 }
 

@@ -2,6 +2,7 @@
 // gfx950 only: wave64, LDS-resident membranes, spreading gathered per tile.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace capib {
@@ -33,20 +34,29 @@ struct BodyParams {
     uint32_t seed_lo, seed_hi;
     float c0xh, c0xl, c0yh, c0yl;   // rigid: centroid at t = 0 (hi + lo)
     float P0, pad3;                 // perimeter at t = 0
+    // Eq. (13) in FP64: the stretch y_l - y_eq of a bond is a small
+    // difference of lengths close to y_eq, and whether an open site binds
+    // compares its gap with y_cr; both are formed in double
+    double sigma64, yeq64, ycr64, pad4;
 };
 
 // Mutable per-body state.
 struct BodyState {
     float dcxh, dcxl, dcyh, dcyl;   // rigid: centroid displacement (hi + lo)
     float phih, phil;               // rigid: rotation angle (hi + lo)
-    float ucx, ucy, ucxm, ucym, om, omm;  // rigid: u, omega at n and n-1
+    float rot[2];                   // rigid: cos(phi) - 1 and sin(phi) of the stored angle
+    // rigid: (u_x, u_y, omega) at steps n and n-1, FP64: the BDF2 recurrence
+    // of Eqs. (19)-(20) has a root at one, so rounding the velocities to FP32
+    // every step would accumulate (about 3e-5 of u over 1000 steps)
+    double u[3], um[3];
     float bbox[2][4];               // xmin, xmax, ymin, ymax of the vertices, parity-indexed
     int n_bound, pad;
     double geo[4];                  // diagnostics: area, perimeter, cx, cy
-    float rot[2];                   // rigid: cos(phi) - 1 and sin(phi) of the stored angle
+    double pad2;                    // keeps arrays of the struct 16-byte aligned
 };
-// the membrane kernel reads the rigid state as three float4
+// the membrane kernel reads the rigid state as two float4 and three double2
 static_assert(sizeof(BodyState) % 16 == 0, "BodyState must keep 16-byte alignment in arrays");
+static_assert(offsetof(BodyState, u) % 16 == 0, "rigid velocities on a 16-byte boundary");
 
 // Everything a kernel needs, passed by value.
 //
@@ -98,6 +108,12 @@ struct Dev {
     // has at most body_mv vertices and 2 body_mv ligand sites (256, 512 or
     // MAXV_BODY)
     int body_mv;
+    // launch configuration of the step (host side; the library's rule or
+    // the autotuner's choice): split = the far tiles in a launch of their
+    // own beside the membrane phase (else one sweep after it, with
+    // far_share percent of the far tiles swept by the membrane launch);
+    // mark_pairs = near-tile marking with one (vertex, tile) pair per lane
+    int split, far_share, mark_pairs;
     const int *band_nx;             // width of each band
     // tiles that hold fluid nodes of some band (with several bands of
     // different widths, the tiles beyond a band's width hold none), in
@@ -133,7 +149,8 @@ struct Dev {
     float2 *sp_f;
     int2 *srange;                               // sites [begin, end) per element
     int *s_host, *s_state, *s_orig;
-    float *s_frac, *s_anh, *s_anl;
+    double *s_frac;                             // site position along its element (FP64, see BodyParams)
+    float *s_anh, *s_anl;
     // scalars and scratch
     long long *counter;   // steps started
     int *err;             // sticky error flags
@@ -195,11 +212,12 @@ __device__ __forceinline__ void df_add(float &hi, float &lo, float d) {
 // Cosine-kernel stencil of a point given as hi + lo: node offsets and the
 // 4 + 4 one-dimensional weights phi(X - i), phi(Y - j) for i = ix0 .. ix0+3,
 // j = iy0 .. iy0+3; 'inv' divides every product weight.  With walls, Y is
-// clamped to [-1, ny] and rows beyond a wall get weight zero.  For the
-// velocity coupling (renorm = false) those rows stand for wall nodes at rest:
-// they stay in the normalising sum.  For the probe fields (renorm = true) the
-// fluid rows are renormalised to sum one.  Returns true when the unclamped Y
-// left [-1, ny].
+// clamped to [-1, ny].  For the velocity coupling (renorm = false) the rows
+// beyond a wall are the odd image of the fluid rows mirrored about the wall
+// (no slip): the weights are folded onto four fluid rows and iy0 is the
+// first of them.  For the probe fields (renorm = true) the rows beyond the
+// wall are dropped and the fluid rows renormalised to sum one.  Returns true
+// when the unclamped Y left [-1, ny].
 // Origin of the stencil of a point given as hi + lo: ix0 = floor(X) - 1,
 // iy0 = floor(Y) - 1 and the fractions sx, sy.  With walls, Y is clamped to
 // [-1, ny].  Non-finite or absurd coordinates are flagged and mapped to the
@@ -244,12 +262,33 @@ __device__ __forceinline__ bool stencil(const Dev &d, const Band &B, float xh, f
     wy[2] = 0.25f * (1.0f + sny); wy[3] = 0.25f * (1.0f - cy);
     const float sxw = (wx[0] + wx[1]) + (wx[2] + wx[3]);
     const float syfull = (wy[0] + wy[1]) + (wy[2] + wy[3]);
-    if (d.walls) {
+    if (d.walls && renorm) {
 #pragma unroll
         for (int b = 0; b < 4; b++) {
             int j = iy0 + b;
             if (j < 0 || j >= B.ny) wy[b] = 0.0f;
         }
+    } else if (d.walls) {
+        // velocity coupling: the fluid velocity continued across the no-slip
+        // wall as its odd image, i.e. a row beyond the wall is the fluid row
+        // mirrored about the wall with its sign reversed.  The four weights
+        // are folded onto four fluid rows o .. o + 3 (a band has at least
+        // four rows), in row order; away from the walls this is the identity.
+        const int o = min(max(iy0, 0), B.ny - 4);
+        float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, f3 = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int j = iy0 + b;
+            const bool lo = j < 0, hi = j >= B.ny;
+            const int t = (lo ? -1 - j : hi ? 2 * B.ny - 1 - j : j) - o;
+            const float w = (lo || hi) ? -wy[b] : wy[b];
+            f0 += t == 0 ? w : 0.0f;
+            f1 += t == 1 ? w : 0.0f;
+            f2 += t == 2 ? w : 0.0f;
+            f3 += t == 3 ? w : 0.0f;
+        }
+        wy[0] = f0; wy[1] = f1; wy[2] = f2; wy[3] = f3;
+        iy0 = o;
     }
     const float syw = renorm ? (wy[0] + wy[1]) + (wy[2] + wy[3]) : syfull;
     inv = 1.0f / (sxw * syw);
@@ -346,8 +385,9 @@ struct EqDev {
 };
 
 // The tiles covered by the velocity-coupling stencil of a point of band B
-// (local coordinates): its four rows (clipped to the band's fluid rows with
-// walls, wrapped within the band without) and four columns (wrapped at the
+// (local coordinates): its four rows (with walls the four fluid rows its
+// weights are folded onto, wrapped within the band without) and four
+// columns (wrapped at the
 // band's width).  Four consecutive wrapped rows or columns can meet three
 // tiles when the last tile of a band is narrower than the stencil.  Returns
 // the count (at most 9) and writes the tile indices.
@@ -356,6 +396,8 @@ __device__ __forceinline__ int stencil_tiles(const Dev &d, const Band &B, float 
     int ix0, iy0;
     float sx, sy;
     stencil_origin(d, B, xh, xl, yh, yl, ix0, iy0, sx, sy);
+    // with walls, the four fluid rows the velocity stencil is folded onto
+    if (d.walls) iy0 = min(max(iy0, 0), B.ny - 4);
     int ty[3], nty = 0;
 #pragma unroll
     for (int b = 0; b < 4; b++) {

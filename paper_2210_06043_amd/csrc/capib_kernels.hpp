@@ -14,8 +14,14 @@ hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t 
 // fb0: the far-tile candidates below it are swept by the membrane launch
 hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0 = nullptr,
                                 hipEvent_t e1 = nullptr, int fb0 = 0);
-// whether the far tiles are swept beside the membrane phase (large lattices)
+// whether the far tiles are swept beside the membrane phase (Dev::split)
 bool lattice_split(const Dev &d);
+// the library's own rules for the launch configuration: the far tiles beside
+// the membrane phase on lattices of 8192 tiles or more; the marking with
+// (vertex, tile) pairs below 16384 vertices; the membrane launch's far share
+bool default_split(int tiles);
+bool default_mark_pairs(int nverts);
+int default_far_share(int storage);
 hipError_t launch_mark(const Dev &d, int par, hipStream_t st);
 hipError_t launch_macro(const Dev &d, int par, hipStream_t st);
 hipError_t launch_init_flow(const Dev &d, int par, hipStream_t st);

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_sample(Dev d, int par, int pta
         if (!d.s_state[s]) continue;
         const int e = d.s_host[s] - v0;
         const int m = (e + 1 == n) ? 0 : e + 1;
-        const float f = d.s_frac[s];
+        const float f = (float)d.s_frac[s];
         const float xh = d.pxh[par][v0 + e], xl = d.pxl[par][v0 + e] + f * ((d.pxh[par][v0 + m] - xh) +
                                                                           (d.pxl[par][v0 + m] - d.pxl[par][v0 + e]));
         const float yh = d.pyh[par][v0 + e], yl = d.pyl[par][v0 + e] + f * ((d.pyh[par][v0 + m] - yh) +

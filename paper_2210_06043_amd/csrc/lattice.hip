@@ -453,10 +453,13 @@ hipError_t launch_lattice_far(const Dev &d, int par, hipStream_t st, hipEvent_t 
 // candidate.
 constexpr int SPLIT_MIN_TILES = 8192;
 
-bool lattice_split(const Dev &d) { return d.ntx * d.nty >= SPLIT_MIN_TILES; }
+bool default_split(int tiles) { return tiles >= SPLIT_MIN_TILES; }
+bool lattice_split(const Dev &d) { return d.split != 0; }
 
 // marking layout: pairs per lane below this many vertices (see mark_next)
 constexpr int PAIRS_MAX_VERTS = 16384;
+
+bool default_mark_pairs(int nverts) { return nverts < PAIRS_MAX_VERTS; }
 
 template <typename T, int P, bool E, bool PA>
 static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
@@ -474,7 +477,7 @@ static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
 }
 template <typename T, int P, bool E>
 static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
-    if (d.nverts < PAIRS_MAX_VERTS)
+    if (d.mark_pairs)
         go_sweep<T, P, E, true>(d, st, e0, e1, fb0);
     else
         go_sweep<T, P, E, false>(d, st, e0, e1, fb0);

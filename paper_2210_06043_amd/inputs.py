@@ -279,7 +279,45 @@ def config_c2(seed=0, steps=50000, ar=None, ca=None):
                   meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, n_bound0=200))
 
 
-def c3_member(seed, k):
+def config_mr(seed=2, steps=2000):
+    """Single-lattice roofline case: a 16384 x 1024 channel (16.8 M nodes,
+    1.2 GB of FP32 populations per step, far beyond the 256 MB last-level
+    cache) at the paper-scale resolution dx = 0.03125 um, Re = 0.01, tau = 1;
+    24 cells of the paper-scale size (radius 3.5 um = 112 nodes, 512
+    vertices, biconcave and circular alternating) in four rows of six; one
+    discoidal particle (64 x AR*64 nodes, 128 vertices, 200 bonds) on the
+    lower wall, drawn as in the paper-scale workload from the seed."""
+    nx, ny, tau = 16384, 1024, 1.0
+    nu, umax, g = channel(ny, 0.01, tau)
+    dx_um = 7.5 / 240
+    rng = np.random.default_rng(seed)
+    ar = float(rng.choice([0.25, 0.5, 1.0]))
+    ca = float(rng.choice([0.0, 1e-4, 1e-3]))
+    ks_cell = stiffness(umax, tau, 1e-3)
+    bodies = []
+    for r in range(4):
+        for c in range(6):
+            cx, cy = (c + 0.5) * nx / 6, (r + 0.5) * ny / 4
+            xy = biconcave(512, 112.0, cx, cy) if (r + c) % 2 == 0 else circle(512, 112.0, cx, cy)
+            bodies.append(Body(DEFORMABLE, xy, None, ks=ks_cell, kb=0.1 * ks_cell, rho_r=1.0, tag=TAG_CELL))
+    ycr = Y_CR_M / (dx_um * 1e-6)
+    yeq = 0.5 * ycr
+    part_xy = rectangle(128, 64.0, ar * 64.0, nx / 12, -0.5 + yeq)
+    if ca == 0.0:
+        part = Body(RIGID, part_xy, None, rho_r=1.1, tag=TAG_PARTICLE)
+    else:
+        ks = stiffness(umax, tau, ca)
+        part = Body(DEFORMABLE, part_xy, None, ks=ks, kb=0.1 * ks, rho_r=1.1, tag=TAG_PARTICLE)
+    bodies.append(part)
+    host, frac = place_sites(part_xy, 200, ycr)
+    kf = 8.5e-3
+    bonds = Bonds(len(bodies) - 1, host, frac, sigma=bond_spring(tau, ny), ycr=ycr, yeq=yeq, kf=kf,
+                  kr0=kf / KF_OVER_KR0, lb=ycr / 20.0, seed=seed)
+    return Config("mr_16384x1024", nx, ny, tau, g, ux_init=poiseuille_profile(ny, g, tau), bodies=bodies,
+                  bonds=[bonds], steps=steps, meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, n_bound0=200))
+
+
+def c3_member(seed, k, ar=None, ca=None):
     """Member k of the batched ensemble: a 64-row capillary (Re = 0.01,
     tau = 1) of length U{256..2048}; 1-4 cells, biconcave or globular with
     equal odds, 128-256 markers at half-node spacing, Ca = 1e-3, evenly
@@ -287,7 +325,9 @@ def c3_member(seed, k):
     aspect ratio U[0.25, 1] and 64 markers, mid-gap after the first cell on
     the lower wall, rigid (Ca = 0) with probability 1/4 and otherwise soft
     with Ca log-uniform in [1e-5, 1e-3], 20 bonds engaged.  Drawn from the
-    stream seed * 2^20 + k."""
+    stream seed * 2^20 + k.  ar and ca, if given, replace the particle's
+    drawn aspect ratio and Ca (0 = rigid) and leave everything else of the
+    member as drawn (a variant of the same capillary)."""
     sid = seed * (1 << 20) + k
     rng = np.random.default_rng(sid)
     ny, tau = 64, 1.0
@@ -307,9 +347,12 @@ def c3_member(seed, k):
         types.append(1 if bic else 0)
         xy = biconcave(n, R, xs[j], cy, dense=20000) if bic else circle(n, R, xs[j], cy)
         bodies.append(Body(DEFORMABLE, xy, None, ks=ks_cell, kb=0.1 * ks_cell, rho_r=1.0, tag=TAG_CELL))
-    ar = float(rng.uniform(0.25, 1.0))
+    ar_d = float(rng.uniform(0.25, 1.0))
     rigid = rng.random() < 0.25
-    ca = 0.0 if rigid else float(10.0 ** rng.uniform(-5.0, -3.0))
+    ca_d = 0.0 if rigid else float(10.0 ** rng.uniform(-5.0, -3.0))
+    ar = ar_d if ar is None else float(ar)
+    ca = ca_d if ca is None else float(ca)
+    rigid = ca == 0.0
     ycr = Y_CR_M / (dx_um * 1e-6)
     yeq = 0.5 * ycr
     px = xs[0] + 0.5 * nx / ncell

@@ -60,30 +60,59 @@ def test_stencil_equals_brute_force():
         np.testing.assert_allclose(dense, brute, atol=1e-15)
 
 
-def test_stencil_wall_truncation():
+def test_stencil_wall_rows():
     """Stencils that cross a wall (the paper is silent): points are clamped to
-    Y in [-1, ny]; for the velocity coupling the rows beyond the wall are
-    wall nodes at rest (zero weight in the result, full kernel weight in the
-    normalisation, so the weights sum to the fluid share); for the probes the
-    fluid rows are renormalised to sum 1."""
-    s = oracle.Sim(10, 6, 1.0, 0, 0, walls=3)
+    Y in [-1, ny].  For the probes the rows beyond the wall are dropped and
+    the fluid rows renormalised to sum 1.  For the velocity coupling a row
+    beyond the wall is the odd image of the fluid row mirrored about the
+    wall (below y = -1/2: row -1-j; above y = ny - 1/2: row 2 ny - 1 - j)
+    with its full kernel weight negated, so the weights sum to the fluid
+    share minus the image share."""
+    ny = 6
+    s = oracle.Sim(10, ny, 1.0, 0, 0, walls=3)
     for Y in [-1.5, -1.0, -0.4, 0.3, 2.5, 4.6, 5.2, 6.0, 7.0]:
-        Yc = min(max(Y, -1.0), 6.0)
+        Yc = min(max(Y, -1.0), float(ny))
         j0 = int(np.floor(Yc)) - 1
-        full = np.array([oracle.phi(Yc - (j0 + b)) for b in range(4)])
-        fluid = np.array([full[b] if 0 <= j0 + b < 6 else 0.0 for b in range(4)])
+        rows = [j0 + b for b in range(4)]
+        full = np.array([oracle.phi(Yc - j) for j in rows])
+        fluid = np.array([full[b] if 0 <= rows[b] < ny else 0.0 for b in range(4)])
         px = np.array([oracle.phi(4.3 - (3 + a)) for a in range(4)])
         ii, jj, w = s.stencil(4.3, Y, oracle.STEN_PROBE)
         assert abs(w.sum() - 1) < 1e-15
         np.testing.assert_allclose(w, np.outer(fluid, px) / (fluid.sum() * px.sum()), atol=1e-15)
         ii, jj, w = s.stencil(4.3, Y, oracle.STEN_VELOCITY)
-        np.testing.assert_allclose(w, np.outer(fluid, px) / (full.sum() * px.sum()), atol=1e-15)
-        assert abs(w.sum() - fluid.sum() / full.sum()) < 1e-15
-        for b in range(4):
-            if jj[b] < 0:
-                assert np.all(w[b] == 0)
-        if 1.0 <= Yc <= 4.0:                  # away from the walls both readings agree
+        sign = np.array([1.0 if 0 <= j < ny else -1.0 for j in rows])
+        mirror = [j if 0 <= j < ny else (-1 - j if j < 0 else 2 * ny - 1 - j) for j in rows]
+        np.testing.assert_allclose(w, np.outer(sign * full, px) / (full.sum() * px.sum()), atol=1e-15)
+        assert list(jj) == mirror
+        if 1.0 <= Yc <= ny - 2.0:             # away from the walls all readings agree
             assert abs(w.sum() - 1) < 1e-15
+
+
+def test_velocity_image_vanishes_on_the_walls():
+    """With the odd image the interpolated velocity is zero on the walls
+    themselves (y = -1/2 and y = ny - 1/2) for any fluid field: no slip."""
+    ny = 9
+    s = oracle.Sim(12, ny, 1.0, 0, 0, walls=3)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((ny, 12))
+    for X in (0.3, 5.0, 7.77):
+        assert abs(s.interp_field(f, X, -0.5)) < 1e-15
+        assert abs(s.interp_field(f, X, ny - 0.5)) < 1e-15
+
+
+def test_velocity_image_reproduces_wall_shear():
+    """A shear flow u = c (y + 1/2), zero on the lower wall, is its own odd
+    image: near the wall the interpolation equals the unbounded kernel's,
+    c (Y + 1/2 - m1(frac Y)), so the near-wall stencil loses nothing of a
+    linear profile (the wall-nodes-at-rest reading would)."""
+    ny, c = 10, 0.37
+    s = oracle.Sim(8, ny, 1.0, 0, 0, walls=3)
+    f = c * (np.arange(ny)[:, None] + 0.5) * np.ones((ny, 8))
+    m1 = lambda t: t - 0.5 + 0.5 * (np.cos(np.pi * t / 2) - np.sin(np.pi * t / 2))
+    for Y in (-0.45, -0.1, 0.0, 0.3, 0.9, 1.6):
+        expect = c * (Y + 0.5 - m1(Y - np.floor(Y)))
+        assert abs(s.interp_field(f, 3.2, Y) - expect) < 1e-14
 
 
 def test_interp_linear_field_closed_form():

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import gpu_sim, oracle_sim, rel_max, say
+from helpers import check_bonds, gpu_sim, load_gpu_state_into, oracle_steps, oracle_sim, rel_max, say
 from paper_2210_06043_amd import capib, inputs
 
 pytestmark = pytest.mark.gpu
@@ -68,12 +68,12 @@ def test_first_step_interpolation_and_forces():
         np.testing.assert_allclose(g.vertices(k), o.vertices(k), rtol=0, atol=1e-9)
 
 
-def _compare_run(cfg, steps, label, o=None, g=None, tol=TOL, bond_margin=1e-6):
+def _compare_run(cfg, steps, label, o=None, g=None, tol=TOL, require_flips=False):
     o = o or oracle_sim(cfg)
     g = g or gpu_sim(cfg)
     x0 = [o.vertices(k).copy() for k in range(len(cfg.bodies))]
-    o.step(steps)
     g.step(steps)
+    oracle_steps(o, steps, label)
     _, uxo, uyo = o.macro()
     _, uxg, uyg = g.macro()
     eu = rel_max(np.stack([uxg, uyg]), np.stack([uxo, uyo]))
@@ -87,15 +87,7 @@ def _compare_run(cfg, steps, label, o=None, g=None, tol=TOL, bond_margin=1e-6):
     assert eu < tol
     for ex, dx in errs:
         assert ex < tol and dx < tol
-    margin = o.min_margin
-    say(f"{label}: min bond-decision margin {margin:.3e}")
-    for bd in cfg.bonds:
-        so, ao = o.bonds(bd.body)
-        sg, ag = g.bonds(bd.body)
-        if margin > bond_margin:
-            assert np.array_equal(so, sg)
-            np.testing.assert_allclose(ag[so == 1], ao[so == 1], rtol=0, atol=1e-5)
-            assert g.body_diagnostics(bd.body)["n_bound"] == o.count_bound(bd.body)
+    check_bonds(o, g, cfg, label, require_flips=require_flips)
     d = g.diagnostics()
     assert d["error_flags"] == 0
     return o, g
@@ -104,7 +96,7 @@ def _compare_run(cfg, steps, label, o=None, g=None, tol=TOL, bond_margin=1e-6):
 def test_tiny_coupled_parity():
     """Small channel, deformable cell and bonded rigid particle, 300 steps."""
     say("tiny coupled parity")
-    _compare_run(inputs.config_tiny(), 300, "tiny")
+    _compare_run(inputs.config_tiny(), 300, "tiny", require_flips=True)
 
 
 def test_tiny_fixed_body_periodic_parity():
@@ -145,17 +137,40 @@ def test_c1_full_run_parity():
     """The small workload (480x60, cell + bonded rigid ellipse), all 2000 steps."""
     say("C1 2000-step parity")
     cfg = inputs.config_c1()
-    _compare_run(cfg, cfg.steps, "c1")
+    _compare_run(cfg, cfg.steps, "c1", require_flips=True)
 
 
+@pytest.mark.timeout(900)
 def test_c2_window_parity():
-    """The paper-scale workload (3840x240, six cells, particle, 200 bonds) at
-    full size, first 60 steps, in the launch configuration the benchmark
-    times (graphs on)."""
-    say("C2 window parity")
-    cfg = inputs.config_c2(seed=0)
+    """The paper-scale workload (3840x240, six cells, particle, 200 bonds) as
+    the benchmark times it (the rigid draw, seed 2; graphs on), the first
+    1000 steps against the oracle."""
+    say("C2 1000-step window parity")
+    cfg = inputs.config_c2(seed=2)
     g = gpu_sim(cfg, graph=True)
-    _compare_run(cfg, 60, "c2", g=g)
+    _compare_run(cfg, 1000, "c2", g=g, require_flips=True)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("seed", [2, 0], ids=["rigid", "soft-Ca1e-4"])
+def test_c2_late_window_parity(seed):
+    """The last window of the configured paper-scale run (50k steps): the
+    GPU advances 49,000 steps, the oracle restarts from its state promoted
+    to FP64 (populations, step, positions, BDF2 histories, rigid state,
+    bonds) and both run the last 1000 steps: velocity and marker
+    displacement over the window within 1e-5, bonds exact.  For the rigid
+    draw the benchmark times (seed 2) and a soft one (seed 0, Ca = 1e-4,
+    adhered with its lower side between the wall and the first fluid row)."""
+    say(f"C2 late-window parity, seed {seed} (49000 + 1000 steps)")
+    cfg = inputs.config_c2(seed=seed)
+    g = gpu_sim(cfg, graph=True)
+    g.step(49000)
+    d = g.diagnostics()
+    assert d["error_flags"] == 0 and d["step"] == 49000
+    o = oracle_sim(cfg)
+    load_gpu_state_into(o, g, cfg)
+    assert o.n == 49000
+    _compare_run(cfg, 1000, f"c2-late-seed{seed}", o=o, g=g)
 
 
 def test_determinism_and_graph_equivalence():
@@ -251,18 +266,20 @@ def test_fp16_tiny_coupled_parity():
     """FP16 storage, small channel with a cell and a bonded particle, 300 steps."""
     say("fp16 tiny coupled parity")
     cfg = inputs.config_tiny()
-    _compare_run(cfg, 300, "tiny-fp16", g=_fp16(cfg), tol=FP16_TOL, bond_margin=1e-4)
+    _compare_run(cfg, 300, "tiny-fp16", g=_fp16(cfg), tol=FP16_TOL, require_flips=True)
 
 
 def test_fp16_c1_full_run_parity():
     """FP16 storage, the small workload, all 2000 steps."""
     say("fp16 C1 2000-step parity")
     cfg = inputs.config_c1()
-    _compare_run(cfg, cfg.steps, "c1-fp16", g=_fp16(cfg), tol=FP16_TOL, bond_margin=1e-4)
+    _compare_run(cfg, cfg.steps, "c1-fp16", g=_fp16(cfg), tol=FP16_TOL, require_flips=True)
 
 
+@pytest.mark.timeout(900)
 def test_fp16_c2_window_parity():
-    """FP16 storage, the paper-scale workload, first 60 steps with graphs."""
+    """FP16 storage, the paper-scale workload as the benchmark runs it (seed
+    2, graphs), first 300 steps."""
     say("fp16 C2 window parity")
-    cfg = inputs.config_c2(seed=0)
-    _compare_run(cfg, 60, "c2-fp16", g=_fp16(cfg, graph=True), tol=FP16_TOL, bond_margin=1e-4)
+    cfg = inputs.config_c2(seed=2)
+    _compare_run(cfg, 300, "c2-fp16", g=_fp16(cfg, graph=True), tol=FP16_TOL)

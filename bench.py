@@ -336,60 +336,70 @@ def mr_section(args, copy_gbs):
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def surrogate_section(args, batched_out):
-    """The load/hazard surrogate: trained on the solver's samples of the
-    256 capillaries of the batched workload, evaluated on 32 capillaries of
-    another draw; its inference rate on the matrix cores and what it buys
-    when it screens the sweep."""
+def mlp_inference_rate(params, nb=65536, reps=20):
+    """Time of one inference batch of the surrogate (65,536 samples) on the
+    matrix cores, and its rate in FLOP/s of the unpadded network."""
     import torch
-    from paper_2210_06043_amd import inputs, mlp, surrogate
-    tr = inputs.config_c3(seed=0, members=args.members)
-    te = inputs.config_c3(seed=1, members=32)
-    S, ms_h, first = surrogate.harvest(tr, args.harvest_steps, every=2)
-    X, T, _ = surrogate.features(S, tr, first)
-    S2, _, first2 = surrogate.harvest(te, args.harvest_steps, every=2)
-    X2, T2, _ = surrogate.features(S2, te, first2)
-    fx, ft = surrogate.Standardiser(X), surrogate.Standardiser(T)
-    net, ms_train = surrogate.train(fx(X), ft(T), steps=args.train_steps, batch=4096)
-    P = surrogate.predict(net, fx(X2))
-    err = np.mean((P - ft(T2)) ** 2, axis=0)
-    base = np.mean(ft(T2) ** 2, axis=0)
-    # inference rate: batches of 65,536, FLOPs of the unpadded network
-    nb = 65536
+    from paper_2210_06043_amd import mlp, surrogate
     inf = mlp.Surrogate(nb)
-    inf.set_params(net.get_params())
+    inf.set_params(params if params is not None else surrogate.init_params(0))
     x = torch.randn((nb, mlp.IN), device=inf.device)
     inf.forward(x)
     inf.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(inf.stream)
-    reps = 20
     for _ in range(reps):
         inf.forward(x)
     e1.record(inf.stream)
     e1.synchronize()
-    ms_inf = e0.elapsed_time(e1) / reps
+    ms = e0.elapsed_time(e1) / reps
     dims = [mlp.IN, mlp.HIDDEN, mlp.HIDDEN, mlp.HIDDEN, mlp.HIDDEN, mlp.OUT]
     flops = 2 * nb * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
-    tflops = flops / (ms_inf * 1e-3) / 1e12
-    preds_per_hour = nb / (ms_inf * 1e-3) * 3600.0
+    return {"batch": nb, "ms_per_batch": ms, "flops_per_launch": flops, "tflops": flops / (ms * 1e-3) / 1e12,
+            "reps": reps}
+
+
+def surrogate_section(args, batched_out):
+    """The load/hazard surrogate screening a parameter sweep: four networks
+    trained on the solver's samples of the 256 capillaries of the batched
+    workload; the sweep is 32 unseen capillaries with six particle variants
+    each, where one solver run per capillary supplies the cell-side features,
+    the networks answer the other variants and an uncertain variant falls
+    back to the solver (threshold chosen on half of the capillaries for a
+    standardised error of 0.1, error and runs measured on the other half).
+    Also the inference rate on the matrix cores."""
+    from paper_2210_06043_amd import inputs, surrogate
+    tr = inputs.config_c3(seed=0, members=args.members)
+    res = surrogate.screening_study(tr, sweep_seed=1, cells=32, train_steps=args.train_steps, eps=0.1)
+    nets = res.pop("nets")
+    rate = mlp_inference_rate(nets[0].get_params())
+    nb, ms_inf, flops, tflops = rate["batch"], rate["ms_per_batch"], rate["flops_per_launch"], rate["tflops"]
     out = {
-        "workload": f"MLP 37 -> 4 x 256 (GELU) -> 3, BF16 operands / FP32 accumulation (MFMA 32x32x16); "
-                    f"trained on {X.shape[0]} solver samples of {len(tr)} capillaries, "
-                    f"evaluated on {X2.shape[0]} of {len(te)} unseen capillaries",
-        "train_steps": args.train_steps, "train_batch": 4096, "ms_per_train_step": round(ms_train, 4),
-        "heldout_mse_standardised": {"drag": round(float(err[0]), 4), "lift": round(float(err[1]), 4),
-                                     "hazard": round(float(err[2]), 4)},
-        "mean_guess_mse_standardised": {"drag": round(float(base[0]), 4), "lift": round(float(base[1]), 4),
-                                        "hazard": round(float(base[2]), 4)},
+        "workload": f"MLP 37 -> 4 x 256 (GELU) -> 3, BF16 operands / FP32 accumulation (MFMA 32x32x16), "
+                    f"4 networks trained on {res['train_samples']} solver samples of {len(tr)} capillaries",
+        "train_steps": args.train_steps, "train_batch": 4096, "ms_per_train_step": round(res["ms_per_train_step"], 4),
+        "screening": {
+            "sweep": "32 unseen capillaries x 6 particle variants (AR 0.3/0.6/0.9, rigid or Ca 1e-4); one solver "
+                     "run per capillary supplies the cell-side features; uncertain variants fall back to the solver",
+            "stated_error": res["eps"], "uncertainty_threshold": round(res["tau"], 5),
+            "evaluation_error_drag_lift_hazard": [round(e, 4) for e in res["eval_error"]],
+            "evaluation_solver_runs": res["eval_runs"], "evaluation_answers": res["eval_answers"],
+            "fallbacks": res["eval_fallbacks"], "answers_per_solver_run": round(res["answers_per_run"], 3)},
         "inference_batch": nb, "ms_per_inference_batch": round(ms_inf, 4),
-        "predictions_per_hour": round(preds_per_hour, 1),
+        "predictions_per_hour": round(nb / (ms_inf * 1e-3) * 3600.0, 1),
         "roofline": {"bound": "mfma", "kernel": "k_mlp_infer", "achieved": round(tflops, 2),
                      "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
                      "algorithmic_flops_per_launch": flops},
     }
+    if batched_out:
+        # a variant answer costs a solver run of the batched workload without
+        # the surrogate, 1 / answers_per_run of one with it (inference time
+        # is negligible: one variant's samples take microseconds)
+        rph = batched_out["runs_per_hour"]
+        out["screening"]["solver_only_answers_per_hour"] = round(rph, 1)
+        out["screening"]["screened_answers_per_hour"] = round(rph * res["answers_per_run"], 1)
     return out
 
 
@@ -429,6 +439,8 @@ def main():
     ap.add_argument("--harvest-steps", type=int, default=600)
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mlp-only", action="store_true",
+                    help="only time the surrogate's inference kernel on random weights (for profiling it alone)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run the library's streaming copy of this many MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -453,6 +465,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps({"batched": batched(args)}), flush=True)
+        return
+    if args.mlp_only:
+        print(json.dumps({"mlp_inference": mlp_inference_rate(None)}), flush=True)
         return
     if args.mr_only:
         print(json.dumps({"mr": mr_section(args, None)}), flush=True)

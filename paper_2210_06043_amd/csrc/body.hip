@@ -72,7 +72,12 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
     __shared__ float sHx[MAXV], sHy[MAXV];   // half of the element's area, bond and load force
     __shared__ float sbox[MAX_BOX][4];
     __shared__ float sqxh[MAXV], sqxl[MAXV], sqyh[MAXV], sqyl[MAXV];   // another body, staged
-    __shared__ float ss_bond[MAXS];   // Eq. (13) magnitude of each engaged bond (0 if free)
+    __shared__ double ss_bond[MAXS];  // Eq. (13) magnitude of each engaged bond (0 if free), FP64
+    // rigid bodies: half of each element's bond and load force in FP64.  The
+    // body's net force and moment are small residuals of large element
+    // forces (side bonds pull the two sides apart along their normals), so
+    // FP32 element or vertex forces would round into its motion
+    __shared__ double sHd[2][MAXV];
     __shared__ double shd[BT / 64];
     __shared__ float shf[BT / 64][5];
     __shared__ double shr[BT / 64][3];
@@ -119,7 +124,8 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         rsr[k] = ns ? d.srange[g] : make_int2(0, 0);
     }
     // rigid: offsets from the centroid and positions at t = 0
-    float rr0x[VPT], rr0y[VPT], rx0h[VPT], rx0l[VPT], ry0h[VPT], ry0l[VPT];
+    double rr0x[VPT], rr0y[VPT];
+    float rx0h[VPT], rx0l[VPT], ry0h[VPT], ry0l[VPT];
     if (rigid) {
 #pragma unroll
         for (int k = 0; k < VPT; k++) {
@@ -161,7 +167,7 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         for (int k = 0; k < SPT; k++) {
             const int q = tid + k * BT;
             if (q >= ns) continue;
-            float bf = 0.0f;
+            double bf = 0.0;
             if (rst[k]) {
                 // FP64 from the hi/lo positions: the stretch is a small
                 // difference of lengths close to y_eq
@@ -172,7 +178,7 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
                 const double f = rsf[k];
                 const double dx = (xe + f * (xm - xe)) - ((double)rsah[k] + (double)rsal[k]);
                 const double dy = (ye + f * (ym - ye)) + 0.5;
-                bf = (float)(P.sigma64 * (sqrt(dx * dx + dy * dy) - P.yeq64));
+                bf = P.sigma64 * (sqrt(dx * dx + dy * dy) - P.yeq64);
             }
             ss_bond[q] = bf;
         }
@@ -201,14 +207,26 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         sSx[l] = -ks * ny;
         sSy[l] = ks * nx;
         // Eq. (13): engaged bonds of this element, along its outward normal
-        float bm = 0.0f;
-        for (int s = rsr[k].x - s0; s < rsr[k].y - s0; s++) bm += ss_bond[s];
+        double bmd = 0.0;
+        for (int s = rsr[k].x - s0; s < rsr[k].y - s0; s++) bmd += ss_bond[s];
+        const float bm = (float)bmd;
         // Eqs. (14)-(15): (-p n + sigma . n) l from the element's probe
         const float4 q = rpr[k];
         const float Lx = ((q.y - q.x) * nx + q.z * ny) * len;
         const float Ly = (q.z * nx + (q.w - q.x) * ny) * len;
         sHx[l] = 0.5f * (bm * nx + Lx);
         sHy[l] = 0.5f * (bm * ny + Ly);
+        if (rigid) {
+            // the same in FP64, from the hi/lo positions
+            const double txd = ((double)sxh[m] - (double)rxh[k]) + ((double)sxl[m] - (double)rxl[k]);
+            const double tyd = ((double)syh[m] - (double)ryh[k]) + ((double)syl[m] - (double)ryl[k]);
+            const double lend = sqrt(txd * txd + tyd * tyd);
+            const double nxd = tyd / lend, nyd = -txd / lend;
+            const double Lxd = (((double)q.y - (double)q.x) * nxd + (double)q.z * nyd) * lend;
+            const double Lyd = ((double)q.z * nxd + ((double)q.w - (double)q.x) * nyd) * lend;
+            sHd[0][l] = 0.5 * (bmd * nxd + Lxd);
+            sHd[1][l] = 0.5 * (bmd * nyd + Lyd);
+        }
     }
     apart = wave_total_d(apart);
     if ((tid & 63) == 0) shd[tid >> 6] = apart;
@@ -334,18 +352,23 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
     // ---- integration (Eqs. 16-20), direct forcing and spreading at x^n -----------------
     float nxh[VPT], nxl[VPT], nyh[VPT], nyl[VPT];
     if (rigid) {
-        const float c1 = RS1.z, sphi = RS1.w;   // rotation by the stored angle
-        // total force and moment about the centroid, summed in FP64
+        const double c1 = RS1.z, sphi = RS1.w;   // rotation by the stored angle
+        // total force and moment about the centroid in FP64: each vertex's
+        // force from the FP64 element forces (half of each adjacent
+        // element's) and its repulsion, its arm R(phi) r0 from the FP64 offsets
         double Fx = 0.0, Fy = 0.0, M = 0.0;
 #pragma unroll
         for (int k = 0; k < VPT; k++) {
             const int v = tid + k * BT;
             if (v >= n) continue;
-            const float rx = rr0x[k], ry = rr0y[k];
-            const float armx = rx + (c1 * rx - sphi * ry), army = ry + (sphi * rx + c1 * ry);
-            Fx += (double)fvx[k];
-            Fy += (double)fvy[k];
-            M += (double)armx * (double)fvy[k] - (double)army * (double)fvx[k];
+            const int p = (v == 0) ? n - 1 : v - 1;
+            const double fx = (sHd[0][v] + sHd[0][p]) - (double)rep[k] * (double)snvx[v];
+            const double fy = (sHd[1][v] + sHd[1][p]) - (double)rep[k] * (double)snvy[v];
+            const double armx = rr0x[k] + (c1 * rr0x[k] - sphi * rr0y[k]);
+            const double army = rr0y[k] + (sphi * rr0x[k] + c1 * rr0y[k]);
+            Fx += fx;
+            Fy += fy;
+            M += armx * fy - army * fx;
         }
         Fx = wave_total_d(Fx);
         Fy = wave_total_d(Fy);
@@ -388,8 +411,11 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
         for (int k = 0; k < VPT; k++) {
             const int v = tid + k * BT;
             if (v >= n) continue;
-            const float rx = rr0x[k], ry = rr0y[k];
-            const float drx = c1n * rx - sn * ry, dry = sn * rx + c1n * ry;
+            // (R - I) r0 from the FP64 offsets: its size is phi |r0|, so the
+            // offsets' own rounding must stay far below phi's
+            const float rx = (float)rr0x[k], ry = (float)rr0y[k];
+            const float drx = (float)((double)c1n * rr0x[k] - (double)sn * rr0y[k]);
+            const float dry = (float)((double)sn * rr0x[k] + (double)c1n * rr0y[k]);
             float xh = rx0h[k], xl = rx0l[k], yh = ry0h[k], yl = ry0l[k];
             df_add2(xh, xl, srig[3], srig[4]);
             df_add2(yh, yl, srig[5], srig[6]);

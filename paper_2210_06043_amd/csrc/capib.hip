@@ -138,8 +138,8 @@ static void layout(capib_ctx *c) {
     c->off_dxm = o; o = align256(o + V * 4);
     c->off_dym = o; o = align256(o + V * 4);
     for (int k = 0; k < 4; k++) { c->off_x0[k] = o; o = align256(o + V * 4); }
-    c->off_r0x = o; o = align256(o + V * 4);
-    c->off_r0y = o; o = align256(o + V * 4);
+    c->off_r0x = o; o = align256(o + V * 8);
+    c->off_r0y = o; o = align256(o + V * 8);
     c->off_l0 = o; o = align256(o + V * 4);
     c->off_th0 = o; o = align256(o + V * 4);
     c->off_ustar = o; o = align256(o + V * 8);
@@ -234,7 +234,7 @@ static void fill_dev(capib_ctx *c) {
     d.dxm = (float *)(b + c->off_dxm); d.dym = (float *)(b + c->off_dym);
     d.x0h = (float *)(b + c->off_x0[0]); d.x0l = (float *)(b + c->off_x0[1]);
     d.y0h = (float *)(b + c->off_x0[2]); d.y0l = (float *)(b + c->off_x0[3]);
-    d.r0x = (float *)(b + c->off_r0x); d.r0y = (float *)(b + c->off_r0y);
+    d.r0x = (double *)(b + c->off_r0x); d.r0y = (double *)(b + c->off_r0y);
     d.l0 = (float *)(b + c->off_l0); d.th0 = (float *)(b + c->off_th0);
     d.ustar = (float2 *)(b + c->off_ustar);
     d.probe4 = (float4 *)(b + c->off_probe);
@@ -555,15 +555,16 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     split(cy, bp.c0yh, bp.c0yl);
     BodyState bs{};
     double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-    std::vector<float> xh(n), xl(n), yh(n), yl(n), r0x(n), r0y(n), fl0(n), fth0(n);
+    std::vector<float> xh(n), xl(n), yh(n), yl(n), fl0(n), fth0(n);
+    std::vector<double> r0x(n), r0y(n);
     std::vector<int> vnx(n), vinf(n);
     for (int v = 0; v < n; v++) {
         split(xy[2 * v], xh[v], xl[v]);
         split(xy[2 * v + 1], yh[v], yl[v]);
         vnx[v] = v0 + (v + 1) % n;
         vinf[v] = 2 * band + (v >= n / 2);
-        r0x[v] = (float)(xy[2 * v] - cx);
-        r0y[v] = (float)(xy[2 * v + 1] - cy);
+        r0x[v] = xy[2 * v] - cx;
+        r0y[v] = xy[2 * v + 1] - cy;
         fl0[v] = (float)l0[v];
         fth0[v] = (float)th0[v];
         xmin = std::min(xmin, xy[2 * v]); xmax = std::max(xmax, xy[2 * v]);
@@ -590,8 +591,8 @@ capib_status capib_add_membrane(capib_ctx *c, const capib_membrane *m, int32_t *
     if ((s = h2d(c, c->off_x0[1] + fo, xl.data(), n * 4))) return s;
     if ((s = h2d(c, c->off_x0[2] + fo, yh.data(), n * 4))) return s;
     if ((s = h2d(c, c->off_x0[3] + fo, yl.data(), n * 4))) return s;
-    if ((s = h2d(c, c->off_r0x + fo, r0x.data(), n * 4))) return s;
-    if ((s = h2d(c, c->off_r0y + fo, r0y.data(), n * 4))) return s;
+    if ((s = h2d(c, c->off_r0x + (size_t)v0 * 8, r0x.data(), n * 8))) return s;
+    if ((s = h2d(c, c->off_r0y + (size_t)v0 * 8, r0y.data(), n * 8))) return s;
     if ((s = h2d(c, c->off_l0 + fo, fl0.data(), n * 4))) return s;
     if ((s = h2d(c, c->off_th0 + fo, fth0.data(), n * 4))) return s;
     BodyHost bh;

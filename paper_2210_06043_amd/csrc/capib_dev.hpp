@@ -133,7 +133,10 @@ struct Dev {
     float *pxh[2], *pxl[2], *pyh[2], *pyl[2];   // vertex positions, parity-indexed
     float *dxm, *dym;                           // previous increment x^n - x^{n-1}
     float *x0h, *x0l, *y0h, *y0l;               // positions at t = 0
-    float *r0x, *r0y;                           // rigid: offsets from the centroid at t = 0
+    // rigid: offsets from the centroid at t = 0, FP64: a vertex moves by
+    // (R(phi) - I) r0, and FP32 offsets (errors up to ~2e-6 at ~45 nodes)
+    // would misplace it by phi times that once the body has turned
+    double *r0x, *r0y;
     float *l0, *th0;                            // rest lengths and turning angles
     float2 *ustar;                              // u* at vertices
     float4 *probe4;                             // p, sxx, sxy, syy at element probes

@@ -122,3 +122,134 @@ def predict(s, Xs):
         out.append(s.forward(torch.as_tensor(Xs[a:a + s.max_batch], device=s.device)))
     s.synchronize()
     return torch.cat(out).cpu().numpy()
+
+
+# ---- uncertainty and screening ---------------------------------------------------------
+
+def train_ensemble(Xs, Ts, k=4, steps=1000, batch=4096, seed=0):
+    """k networks trained alike from different initial weights and
+    minibatch streams (seeds seed .. seed + k - 1); their spread is the
+    surrogate's own estimate of its uncertainty."""
+    nets, ms = [], []
+    for j in range(k):
+        net, m = train(Xs, Ts, steps=steps, batch=batch, seed=seed + j)
+        nets.append(net)
+        ms.append(m)
+    return nets, float(np.mean(ms))
+
+
+def predict_ensemble(nets, Xs):
+    """Mean and standard deviation over the networks (standardised units)."""
+    P = np.stack([predict(n, Xs) for n in nets])
+    return P.mean(0), P.std(0)
+
+
+# Particle variants of the screened sweep: aspect ratio x Ca (0 = rigid),
+# and the variant whose solver run supplies the cell-side features
+VARIANTS = [(ar, ca) for ar in (0.3, 0.6, 0.9) for ca in (0.0, 1e-4)]
+REFERENCE = (0.6, 1e-4)
+
+
+def sweep_configs(seed, cells):
+    """The sweep: for each of `cells` capillaries drawn from stream `seed`
+    (cells, lengths and placement as in the batched workload), the particle
+    variants of VARIANTS (same capillary, same bond draws)."""
+    from . import inputs
+    return [[inputs.c3_member(seed, c, ar=ar, ca=ca) for (ar, ca) in VARIANTS] for c in range(cells)]
+
+
+def screen(nets, fx, ft, sweep, S, first, tau, rows):
+    """Answers of the screened sweep for the capillaries `rows`.
+
+    S is the solver's harvest of the whole sweep as one ensemble (member
+    c * len(VARIANTS) + v is variant v of capillary c): the targets the
+    screened answers are judged against.  For each capillary the reference
+    variant's run is the one solver run made; every other variant is
+    predicted by the networks from the reference run's cell-side features
+    (r, dp, cell type, wall shear history) with its own aspect ratio and
+    Ca.  A variant whose predicted uncertainty (the networks' spread,
+    largest over the three outputs, averaged over the run's samples)
+    exceeds tau falls back to the solver: its answer is the solver's, at the
+    cost of one more run.  Returns (answers, truth, fallback count, solver
+    runs made, variant answers given)."""
+    nv = len(VARIANTS)
+    ref = VARIANTS.index(REFERENCE)
+    answers, truth = [], []
+    runs = fallbacks = given = 0
+    for c in rows:
+        row = sweep[c]
+        mr = c * nv + ref
+        Xr, _, _ = features(S[:, mr:mr + 1, :], [row[ref]], [first[mr]])
+        runs += 1
+        for v, cfg in enumerate(row):
+            m = c * nv + v
+            _, Tv, _ = features(S[:, m:m + 1, :], [cfg], [first[m]])
+            truth.append(Tv)
+            given += 1
+            if v == ref:
+                answers.append(Tv)
+                continue
+            Xv = Xr.copy()
+            Xv[:, 2] = cfg.meta["ar"]
+            Xv[:, 3] = math.log10(cfg.meta["ca"]) if cfg.meta["ca"] > 0 else -6.0
+            mu, sd = predict_ensemble(nets, fx(Xv))
+            if float(sd.max(axis=1).mean()) > tau:
+                fallbacks += 1
+                runs += 1
+                answers.append(Tv)
+            else:
+                answers.append(ft.back(mu))
+    return answers, truth, fallbacks, runs, given
+
+
+def screened_error(answers, truth, ft):
+    """Standardised mean squared error of the answers over every sample."""
+    A = np.concatenate(answers)
+    T = np.concatenate(truth)
+    return np.mean(((A - T) / ft.sd) ** 2, axis=0)
+
+
+def screening_study(train_cfgs, sweep_seed=1, cells=32, steps=600, every=2, nets=4, train_steps=1000,
+                    eps=0.1):
+    """The screened sweep against the solver alone, at a stated accuracy.
+
+    Trains `nets` networks on the solver's harvest of `train_cfgs`; harvests
+    the sweep (cells capillaries of stream sweep_seed, every particle
+    variant); picks on the first half of the capillaries (calibration) the
+    largest uncertainty threshold whose screened answers stay within eps
+    (standardised mean squared error, every output), and reports on the
+    other half (evaluation) the error reached, the solver runs made and
+    the variant answers given per solver run."""
+    S, ms_h, first = harvest(train_cfgs, steps, every=every)
+    X, T, _ = features(S, train_cfgs, first)
+    fx, ft = Standardiser(X), Standardiser(T)
+    ens, ms_train = train_ensemble(fx(X), ft(T), k=nets, steps=train_steps)
+    sweep = sweep_configs(sweep_seed, cells)
+    flat = [cfg for row in sweep for cfg in row]
+    S2, _, first2 = harvest(flat, steps, every=every)
+    cal, ev = list(range(cells // 2)), list(range(cells // 2, cells))
+    # candidate thresholds: none, every spread seen on the calibration set, all
+    taus = [0.0]
+    for c in cal:
+        mr = c * len(VARIANTS) + VARIANTS.index(REFERENCE)
+        Xr, _, _ = features(S2[:, mr:mr + 1, :], [sweep[c][VARIANTS.index(REFERENCE)]], [first2[mr]])
+        for ar, ca in VARIANTS:
+            Xv = Xr.copy()
+            Xv[:, 2] = ar
+            Xv[:, 3] = math.log10(ca) if ca > 0 else -6.0
+            taus.append(float(predict_ensemble(ens, fx(Xv))[1].max(axis=1).mean()))
+    taus = sorted(set(taus)) + [float("inf")]
+    best = 0.0
+    table = []
+    for tau in taus:
+        a, t, fb, runs, given = screen(ens, fx, ft, sweep, S2, first2, tau, cal)
+        err = screened_error(a, t, ft)
+        table.append((tau, float(err.max()), runs, given))
+        if err.max() <= eps:
+            best = tau
+    a, t, fb, runs, given = screen(ens, fx, ft, sweep, S2, first2, best, ev)
+    err = screened_error(a, t, ft)
+    # without screening every variant is a solver run
+    return dict(eps=eps, tau=best, eval_error=[float(e) for e in err], eval_runs=runs, eval_answers=given,
+                eval_fallbacks=fb, answers_per_run=given / runs, calibration=table, ms_per_train_step=ms_train,
+                train_samples=int(X.shape[0]), sweep_members=len(flat), harvest_ms_per_step=ms_h, nets=ens)

@@ -369,6 +369,19 @@ capib_status capib_read_timing(capib_ctx *ctx, double *ms4, int64_t *steps, int6
  * bytes a multiple of 16, and the ranges must not overlap.                  */
 capib_status capib_copy_bandwidth(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* capib_diagnostics for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, but the per-tile FP64 partial
+ * sums are kept in a fixed array of CAPIB_NOALLOC_SCRATCH_BYTES inside the
+ * library instead of the workspace, and the call allocates nothing.  The
+ * array exists once per device and is held until the process ends; every
+ * call on a device shares it, so calls that overlap on one device (from
+ * several threads or streams) race and must be serialised by the caller.
+ * Lattices of more than (CAPIB_NOALLOC_SCRATCH_BYTES / 8 - 3) / 3 tiles of
+ * 64 x 4 nodes are refused with CAPIB_E_CAPACITY.  Syncs.                   */
+#define CAPIB_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+capib_status capib_diagnostics_noalloc(capib_ctx *ctx, capib_diag *out);
+
 /* Message of the last failing call on this context (never NULL). */
 const char *capib_last_error(const capib_ctx *ctx);
 

@@ -84,6 +84,7 @@ SIGNATURES = {
     "capib_readout": (C.c_int, [_P, C.c_int32, C.c_int32, _dp]),
     "capib_read_body_state": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp]),
     "capib_copy_bandwidth": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "capib_diagnostics_noalloc": (C.c_int, [_P, C.POINTER(capib_diag)]),
     "capib_save": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
     "capib_load": (C.c_int, [_P, _P, C.c_size_t]),
     "capib_set_timing": (C.c_int, [_P, C.c_int32]),
@@ -285,9 +286,11 @@ class Simulation:
         self._check(self.L.capib_read_body_work(self.ctx, body, _d(us), _d(pr), _d(f), _d(U)))
         return dict(ustar=us, probe=pr, force=f, U=U)
 
-    def diagnostics(self, allow_unstable=False):
+    def diagnostics(self, allow_unstable=False, noalloc=False):
+        """capib_diagnostics (or, with noalloc, capib_diagnostics_noalloc)."""
         d = capib_diag()
-        st = self.L.capib_diagnostics(self.ctx, C.byref(d))
+        fn = self.L.capib_diagnostics_noalloc if noalloc else self.L.capib_diagnostics
+        st = fn(self.ctx, C.byref(d))
         if st != CAPIB_OK and not (allow_unstable and st == CAPIB_E_UNSTABLE):
             self._check(st)
         return dict(step=d.step, error_flags=d.error_flags, n_bodies=d.n_bodies, mass=d.mass, mom_x=d.mom_x,

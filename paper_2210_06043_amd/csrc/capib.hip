@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1162,6 +1163,61 @@ capib_status capib_diagnostics(capib_ctx *c, capib_diag *out) {
     double r[3];
     const size_t nblk = (size_t)c->ntx * c->nty;
     if ((s = d2h(c, r, c->off_red + 3 * nblk * 8, 24))) return s;
+    return diag_finish(c, r, out);
+}
+
+// ---- diagnostics without the workspace's reduction region --------------------------
+// The per-tile FP64 partials of capib_diagnostics live in a fixed array in
+// device memory of the library itself.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is handed to kernels and copies.
+static __device__ __align__(256) double scratch[CAPIB_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[MAX_DEVICES] = {};
+
+static capib_status scratch_on_device(capib_ctx *c, double **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device < 0 || c->device >= MAX_DEVICES) return fail(c, CAPIB_E_ARG, "device %d out of range", c->device);
+    if (!g_scratch_ptr[c->device]) {
+        int cur = 0;
+        HIPCHK(c, hipGetDevice(&cur));
+        if (cur != c->device) HIPCHK(c, hipSetDevice(c->device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != c->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(c, CAPIB_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", c->device,
+                        hipGetErrorString(e));
+        g_scratch_ptr[c->device] = (double *)p;
+    }
+    *out = g_scratch_ptr[c->device];
+    return CAPIB_OK;
+}
+
+capib_status capib_diagnostics_noalloc(capib_ctx *c, capib_diag *out) {
+    if (!c) return CAPIB_E_ARG;
+    const size_t nblk = (size_t)c->ntx * c->nty;
+    const size_t need = (3 * nblk + 3) * sizeof(double);
+    if (need > CAPIB_NOALLOC_SCRATCH_BYTES)
+        return fail(c, CAPIB_E_CAPACITY, "lattice of %zu tiles needs %zu bytes of reduction scratch, above the %zu of "
+                    "the allocation-free diagnostics (at most %zu tiles of 64x4 nodes)", nblk, need,
+                    (size_t)CAPIB_NOALLOC_SCRATCH_BYTES, (size_t)(CAPIB_NOALLOC_SCRATCH_BYTES / sizeof(double) - 3) / 3);
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!out) return fail(c, CAPIB_E_ARG, "null output");
+    double *ptr = nullptr;
+    if ((s = scratch_on_device(c, &ptr))) return s;
+    // the same kernels as capib_diagnostics, with the partials in the fixed
+    // array (every partial and the total are rewritten by each call)
+    Dev d = c->d;
+    d.red = ptr;
+    HIPCHK(c, launch_diag(d, c->par, c->stream));
+    double r[3];
+    HIPCHK(c, hipMemcpyAsync(r, ptr + 3 * nblk, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return diag_finish(c, r, out);
 }
 

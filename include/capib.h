@@ -84,7 +84,8 @@ typedef struct capib_ctx capib_ctx;
  *   tau        BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3, Sec. 2.1)
  *   gx, gy     uniform driving body force per node (added to the Guo term)
  *   walls      3: bounce-back walls at both y ends; 0: periodic in y too
- *   storage    CAPIB_FP32_SHIFTED or CAPIB_FP16_SHIFTED
+ *   storage    CAPIB_FP32_SHIFTED (collision arithmetic in FP64, one rounding
+ *              per stored value) or CAPIB_FP16_SHIFTED (FP32 arithmetic)
  *   fp16_scale power of two multiplying stored FP16 deviations (ignored for FP32)
  *   max_*      capacities of the workspace; max_vertices counts all bodies,
  *              a single body holds at most 1024 vertices and 2048 sites     */

@@ -52,7 +52,7 @@ struct capib_ctx {
     size_t esize = 4;
     // workspace layout
     size_t ws_bytes = 0;
-    size_t off_pop[2]{}, off_sp = 0, off_near = 0, off_red = 0, off_macro = 0, off_rowref = 0, off_scal = 0;
+    size_t off_pop[2]{}, off_sp = 0, off_near = 0, off_red = 0, off_macro = 0, off_rowref = 0, off_rowref64 = 0, off_scal = 0;
     size_t off_ib = 0, ib_bytes = 0;
     size_t off_bp = 0, off_bs = 0, off_vnext = 0, off_pos[8]{}, off_dxm = 0, off_dym = 0, off_x0[4]{};
     size_t off_r0x = 0, off_r0y = 0, off_l0 = 0, off_th0 = 0, off_ustar = 0, off_probe = 0, off_force = 0;
@@ -121,6 +121,7 @@ static void layout(capib_ctx *c) {
     c->off_red = o; o = align256(o + (3 * (size_t)c->ntx * c->nty + 3) * 8);
     c->off_macro = o; o = align256(o + 3 * (size_t)L.nx * L.ny * 4);
     c->off_rowref = o; o = align256(o + (size_t)c->band_rows * 16 * 4);
+    c->off_rowref64 = o; o = align256(o + (size_t)c->band_rows * 16 * 8);
     c->off_band = o; o = align256(o + (size_t)c->nbands * 12);   // widths, then (first body, count)
     c->off_live = o; o = align256(o + (size_t)c->ntx * c->nty * 4);
     c->off_scal = o; o = align256(o + 64);
@@ -168,6 +169,9 @@ static void fill_dev(capib_ctx *c) {
     d.omega = (float)(1.0 / L.tau);
     d.fc = (float)(1.0 - 0.5 / L.tau);
     d.gx = (float)L.gx; d.gy = (float)L.gy;
+    d.omega64 = 1.0 / L.tau;
+    d.fc64 = 1.0 - 0.5 / L.tau;
+    d.gx64 = L.gx; d.gy64 = L.gy;
     d.scale = L.storage ? (float)L.fp16_scale : 1.0f;
     d.inv_scale = L.storage ? (float)(1.0 / L.fp16_scale) : 1.0f;
     for (int p = 0; p < 2; p++) d.pop[p] = b + c->off_pop[p];
@@ -197,6 +201,7 @@ static void fill_dev(capib_ctx *c) {
     d.red = (double *)(b + c->off_red);
     d.macro = (float *)(b + c->off_macro);
     d.rowref = (const float *)(b + c->off_rowref);
+    d.rowref64 = (const double *)(b + c->off_rowref64);
     d.counter = (long long *)(b + c->off_scal);
     d.err = (int *)(b + c->off_scal + 8);
     d.nbodies = c->nbodies; d.nverts = c->nverts; d.nsites = c->nsites; d.nbands = c->nbands;
@@ -289,25 +294,28 @@ static double ref_pop(const capib_ctx *c, int y, int q) {
 // Per-row constants of the deviation storage (see Dev::rowref), from FP64.
 static capib_status upload_ref(capib_ctx *c) {
     const int ny = c->band_rows;
-    std::vector<float> t((size_t)ny * 16, 0.0f);
+    std::vector<double> t((size_t)ny * 16, 0.0);
     for (int y = 0; y < ny; y++) {
         for (int q = 0; q < 9; q++) {
             int ys = y - EYq[q];
-            double v;
             if (ys < 0 || ys >= ny) {
                 if (c->lat.walls) {
-                    v = ref_pop(c, y, OPPq[q]) - ref_pop(c, y, q);   // bounce-back from the node itself
-                    t[16 * y + q] = (float)v;
+                    t[16 * y + q] = ref_pop(c, y, OPPq[q]) - ref_pop(c, y, q);   // bounce-back from the node itself
                     continue;
                 }
                 ys = (ys + ny) % ny;
             }
-            v = ref_pop(c, ys, q) - ref_pop(c, y, q);
-            t[16 * y + q] = (float)v;
+            t[16 * y + q] = ref_pop(c, ys, q) - ref_pop(c, y, q);
         }
-        t[16 * y + 9] = (float)c->ref_u[y];
+        t[16 * y + 9] = c->ref_u[y];
     }
-    return h2d(c, c->off_rowref, t.data(), t.size() * 4);
+    // FP32 for the FP16-storage sweep and the read-outs, FP64 for the
+    // FP32-storage sweep
+    std::vector<float> tf(t.size());
+    for (size_t k = 0; k < t.size(); k++) tf[k] = (float)t[k];
+    capib_status s = h2d(c, c->off_rowref, tf.data(), tf.size() * 4);
+    if (s) return s;
+    return h2d(c, c->off_rowref64, t.data(), t.size() * 8);
 }
 
 extern "C" {

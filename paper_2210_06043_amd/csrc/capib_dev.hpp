@@ -78,6 +78,9 @@ struct Dev {
     // channel profile.  rowref[16 y + i] (i < 9) is the constant that turns a
     // pulled stored value into h_i - r_i(y); rowref[16 y + 9] = u_ref(y).
     const float *rowref;
+    // The same constants in FP64 (the FP32-storage sweep collides in FP64)
+    const double *rowref64;
+    double omega64, fc64, gx64, gy64;
     // Near tiles of a step: the 64x4 tiles that the stencils of the vertex
     // positions x^n cover, i.e. the only tiles that can receive spread force
     // in step n.  Double-buffered by step parity: tnear[p][tile] is 1 for a
@@ -374,18 +377,21 @@ __device__ __forceinline__ void note_cover(const Dev &d, int p, int tile, int v,
 //                              + drho (3 e.u + 4.5 (e.u)^2) + 3 e.du
 //                              + 4.5 (e.du)(e.u + e.uref)]
 // Every term carries a deviation (drho or du), so nothing large is rounded.
-struct EqDev {
-    float drho, ux, uy, dux, duy, uref, c0;
-    __device__ __forceinline__ EqDev(float drho_, float uref_, float dux_, float duy_)
+// C is the arithmetic type (float, or double in the FP32-storage sweep).
+template <typename C>
+struct EqDevT {
+    C drho, ux, uy, dux, duy, uref, c0;
+    __device__ __forceinline__ EqDevT(C drho_, C uref_, C dux_, C duy_)
         : drho(drho_), ux(uref_ + dux_), uy(duy_), dux(dux_), duy(duy_), uref(uref_) {
-        c0 = drho * (1.0f - 1.5f * (ux * ux + uy * uy)) - 1.5f * (dux * (ux + uref) + duy * uy);
+        c0 = drho * (C(1) - C(1.5) * (ux * ux + uy * uy)) - C(1.5) * (dux * (ux + uref) + duy * uy);
     }
-    __device__ __forceinline__ float operator()(float ex, float ey, float w) const {
-        const float eu = ex * ux + ey * uy;
-        const float edu = ex * dux + ey * duy;
-        return w * (c0 + drho * (3.0f * eu + 4.5f * eu * eu) + 3.0f * edu + 4.5f * edu * (eu + ex * uref));
+    __device__ __forceinline__ C operator()(C ex, C ey, C w) const {
+        const C eu = ex * ux + ey * uy;
+        const C edu = ex * dux + ey * duy;
+        return w * (c0 + drho * (C(3) * eu + C(4.5) * eu * eu) + C(3) * edu + C(4.5) * edu * (eu + ex * uref));
     }
 };
+using EqDev = EqDevT<float>;
 
 // The tiles covered by the velocity-coupling stencil of a point of band B
 // (local coordinates): its four rows (with walls the four fluid rows its

@@ -11,20 +11,23 @@
 namespace capib {
 
 // A far tile's inputs, loaded ahead of its collision.
+template <typename T>
 struct FarIn {
     int i, j;
-    bool go;      // a far tile and a fluid node
-    float h[9], uref;
+    bool go;          // a far tile and a fluid node
+    RowRefOf<T> rr;   // the row's constants
+    float h[9];       // pulled stored values
 };
 
 template <typename T, int PAR, bool ENS>
-__device__ __forceinline__ void far_load(const Dev &d, int c, FarIn &f) {
+__device__ __forceinline__ void far_load(const Dev &d, int c, FarIn<T> &f) {
     const int tile = ENS ? d.live[c] : c;
     const int flag = d.tnear[PAR][tile];
     tile_node(d, tile, f.i, f.j);
     const Band B = band_at_row<ENS>(d, f.j < d.ny ? f.j : 0);
     f.go = !flag && f.j < d.ny && f.i < B.nx;
-    if (f.go) f.uref = pull_dev<T>(d, (const T *)d.pop[PAR], f.i, f.j, B, f.h);
+    load_rowref(d, f.j < d.ny ? f.j - B.y0 : 0, f.rr);   // wave-uniform, before any store
+    if (f.go) pull9<T>(d, (const T *)d.pop[PAR], f.i, f.j, B, f.h);
 }
 
 // Far tiles on a large lattice, concurrently with the immersed-boundary
@@ -33,12 +36,12 @@ __device__ __forceinline__ void far_load(const Dev &d, int c, FarIn &f) {
 template <typename T, int PAR, bool ENS>
 __global__ __launch_bounds__(LAT_THREADS) void k_lattice_far(Dev d, int n) {
     const int c0 = 2 * xcd_tile(blockIdx.x, gridDim.x);
-    FarIn f0, f1;
+    FarIn<T> f0, f1;
     f1.go = false;
     far_load<T, PAR, ENS>(d, c0, f0);
     if (c0 + 1 < n) far_load<T, PAR, ENS>(d, c0 + 1, f1);
-    if (f0.go) lattice_collide<T, true>(d, PAR, f0.i, f0.j, f0.h, f0.uref, d.gx, d.gy);
-    if (f1.go) lattice_collide<T, true>(d, PAR, f1.i, f1.j, f1.h, f1.uref, d.gx, d.gy);
+    if (f0.go) lattice_collide<T, true>(d, PAR, f0.i, f0.j, f0.rr, f0.h, 0.0f, 0.0f);
+    if (f1.go) lattice_collide<T, true>(d, PAR, f1.i, f1.j, f1.rr, f1.h, 0.0f, 0.0f);
 }
 
 // Does a 4-wide stencil starting at o (wrapped into [0, n)) meet the range
@@ -306,8 +309,9 @@ __device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int
         __builtin_amdgcn_wave_barrier();   // the next batch overwrites the records
     }
     if (valid) {
-        const float uref = add_rowref(d, j - B.y0, h);
-        lattice_collide<T, NT>(d, PAR, i, j, h, uref, d.gx + ax, d.gy + ay);
+        RowRefOf<T> rr;
+        load_rowref(d, j - B.y0, rr);
+        lattice_collide<T, NT>(d, PAR, i, j, rr, h, ax, ay);
     }
 }
 

@@ -197,6 +197,9 @@ def _ensemble_step_ms(cfgs, storage, scale, args):
     from paper_2210_06043_amd import capib
     sim, _ = capib.from_ensemble(cfgs, storage=storage, fp16_scale=scale, graph=not args.no_graph)
     sim.step(args.batched_warmup)
+    # the library's autotuner picks the launch configuration for this
+    # workload (same results for every configuration), outside the timing
+    tuned = sim.autotune(steps_per_trial=args.tune_steps) if args.tune_steps else sim.tuning()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -212,7 +215,7 @@ def _ensemble_step_ms(cfgs, storage, scale, args):
     diag = sim.diagnostics()
     del sim
     torch.cuda.empty_cache()
-    return ms, ph, n, swept, diag
+    return ms, ph, n, swept, diag, tuned
 
 
 def _single_step_ms(cfg, storage, scale, args):
@@ -221,6 +224,8 @@ def _single_step_ms(cfg, storage, scale, args):
     from paper_2210_06043_amd import capib
     g = capib.from_config(cfg, storage=storage, fp16_scale=scale, graph=not args.no_graph)
     g.step(200)
+    if args.tune_steps:
+        g.autotune(steps_per_trial=args.tune_steps)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
@@ -242,10 +247,10 @@ def batched(args):
     cfgs = inputs.config_c3(seed=0, members=args.members)
     scale = capib.fp16_scale_for(cfgs[0])
     nodes = sum(c.nx * c.ny for c in cfgs)
-    ms16, ph, n, swept, diag = _ensemble_step_ms(cfgs, capib.FP16_SHIFTED, scale, args)
+    ms16, ph, n, swept, diag, tune16 = _ensemble_step_ms(cfgs, capib.FP16_SHIFTED, scale, args)
     far_ms = ph[2] / n
     alg = 36 * swept[2] / n   # nodes of the far tiles, counted per step
-    ms32, ph32, n32, swept32, diag32 = _ensemble_step_ms(cfgs, capib.FP32_SHIFTED, 1.0, args)
+    ms32, ph32, n32, swept32, diag32, tune32 = _ensemble_step_ms(cfgs, capib.FP32_SHIFTED, 1.0, args)
     far32_ms = ph32[2] / n32
     alg32 = 72 * swept32[2] / n32
     # single-instance step times on an evenly spaced sample of members
@@ -270,7 +275,14 @@ def batched(args):
         "fp32_ensemble": {"ms_per_step": round(ms32, 5), "mlups": round(nodes / (ms32 * 1e-3) / 1e6, 1),
                           "runs_per_hour": round(rph32, 1), "speedup_same_storage": round(rph32 / s32, 2),
                           "lattice_far_gbs": round(alg32 / (far32_ms * 1e-3) / 1e9, 1),
+                          "tuning": {k: v for k, v in tune32.items() if k != "ms_per_step"},
                           "error_flags": diag32["error_flags"]},
+        "tuning": {k: v for k, v in tune16.items() if k != "ms_per_step"},
+        "tuning_note": "launch configuration chosen by capib_autotune on each workload "
+                       f"({args.tune_steps} steps per trial; singles tuned alike)" if args.tune_steps
+                       else "library rules (autotuner off)",
+        "equal_accuracy_speedup": {"fp16_ensemble_vs_fp16_single": round(rph16 / s16, 2),
+                                   "fp32_ensemble_vs_fp32_single": round(rph32 / s32, 2)},
         "single_sample": f"members {sample}: mean {np.mean(t32) * 1e3:.2f} us/step FP32, "
                          f"{np.mean(t16) * 1e3:.2f} us/step FP16, run one after another",
         "accuracy": "the ensemble and the single runs of each storage take the same arithmetic (FP32: members "
@@ -431,6 +443,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=400)
     ap.add_argument("--batched-warmup", type=int, default=100)
     ap.add_argument("--single-sample", type=int, default=8)
+    ap.add_argument("--tune-steps", type=int, default=32,
+                    help="steps per autotuner trial for the batched section (0: library rules)")
     ap.add_argument("--no-mr", action="store_true")
     ap.add_argument("--mr-only", action="store_true", help="print only the 16384x1024 measurement")
     ap.add_argument("--mr-steps", type=int, default=200)

@@ -601,19 +601,23 @@ __global__ __launch_bounds__(BodyShape<MV>::BT) void k_body(Dev d) {
     body_run<PAR, ENS, MV>(d, blockIdx.x);
 }
 
-// The membrane workgroups first, then BT / 256 far-tile candidates per
-// workgroup up to nfb: on a lattice small enough that one sweep after the
+// The membrane workgroups first, then (from the next multiple of 8, so that
+// blockIdx & 7 is a far workgroup's XCD) BT / 256 far-tile candidates per
+// workgroup: the first far_share_len(len, pct) of each XCD's run of ncand
+// candidates, in order.  On a lattice small enough that one sweep after the
 // membrane phase beats a second stream, these far tiles stream on the
 // compute units that the few membrane workgroups leave idle.
 template <typename T, int PAR, bool ENS, int MV>
-__global__ __launch_bounds__(BodyShape<MV>::BT) void k_body_far(Dev d, int nfb) {
-    if ((int)blockIdx.x < d.nbodies) {
-        body_run<PAR, ENS, MV>(d, blockIdx.x);
+__global__ __launch_bounds__(BodyShape<MV>::BT) void k_body_far(Dev d, int ncand, int pct) {
+    const int f0 = round_up8(d.nbodies);
+    if ((int)blockIdx.x < f0) {
+        if ((int)blockIdx.x < d.nbodies) body_run<PAR, ENS, MV>(d, blockIdx.x);
         return;
     }
     constexpr int TPW = BodyShape<MV>::BT / LAT_THREADS;
-    const int fb = ((int)blockIdx.x - d.nbodies) * TPW + (int)(threadIdx.x / LAT_THREADS);
-    if (fb < nfb) far_tile<T, PAR, ENS>(d, fb, threadIdx.x % LAT_THREADS);
+    const XcdRun run = xcd_run(blockIdx.x & 7, ncand);
+    const int c = (((int)blockIdx.x - f0) >> 3) * TPW + (int)(threadIdx.x / LAT_THREADS);
+    if (c < far_share_len(run.len, pct)) far_tile<T, PAR, ENS>(d, run.start + c, threadIdx.x % LAT_THREADS);
 }
 
 // Default share of the far-tile candidates swept by the membrane launch, in
@@ -624,22 +628,22 @@ constexpr int FAR_SHARE_FP32 = 50, FAR_SHARE_FP16 = 80;
 
 int default_far_share(int storage) { return storage == 0 ? FAR_SHARE_FP32 : FAR_SHARE_FP16; }
 
-int body_far_tiles(const Dev &d) {
-    const int ncand = d.nbands > 1 ? d.nlive : d.ntx * d.nty;
-    return (int)((long long)ncand * d.far_share / 100);
-}
+int body_far_share(const Dev &d) { return d.far_share; }
 
 template <typename T, int MV>
 static void go_body_far(const Dev &d, int par, bool ens, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     constexpr int TPW = BodyShape<MV>::BT / LAT_THREADS;
-    const int nfb = body_far_tiles(d);
-    const dim3 g(d.nbodies + (nfb + TPW - 1) / TPW), t(BodyShape<MV>::BT);
+    const int ncand = ens ? d.nlive : d.ntx * d.nty;
+    const int pct = body_far_share(d);
+    // the longest run's share (runs differ by at most one candidate)
+    const int most = far_share_len(xcd_run(0, ncand).len, pct);
+    const dim3 g(std::max(1, round_up8(d.nbodies) + 8 * ((most + TPW - 1) / TPW))), t(BodyShape<MV>::BT);
     if (par)
         hipExtLaunchKernelGGL(ens ? k_body_far<T, 1, true, MV> : k_body_far<T, 1, false, MV>, g, t, 0, st, e0, e1, 0,
-                              d, nfb);
+                              d, ncand, pct);
     else
         hipExtLaunchKernelGGL(ens ? k_body_far<T, 0, true, MV> : k_body_far<T, 0, false, MV>, g, t, 0, st, e0, e1, 0,
-                              d, nfb);
+                              d, ncand, pct);
 }
 
 template <typename T>

@@ -751,7 +751,7 @@ static capib_status one_step(capib_ctx *c, int par, hipStream_t main, hipStream_
     if (!lattice_split(c->d)) {
         HIPCHK(c, launch_interp(c->d, par, main));
         HIPCHK(c, launch_body_far(c->d, par, main));
-        HIPCHK(c, launch_lattice_sweep(c->d, par, main, nullptr, nullptr, body_far_tiles(c->d)));
+        HIPCHK(c, launch_lattice_sweep(c->d, par, main, nullptr, nullptr, body_far_share(c->d)));
         return CAPIB_OK;
     }
     HIPCHK(c, hipEventRecord(c->ev_fork[k], main));
@@ -810,7 +810,7 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
         // the nodes each lattice launch sweeps, counted after every step
         // (untimed) from that step's near-tile flags
         const bool split = lattice_split(c->d);
-        const int nfb = split ? 0 : body_far_tiles(c->d);
+        const int pct = split ? 0 : body_far_share(c->d);
         unsigned long long *cens = (unsigned long long *)(c->base + c->off_scal + 32);
         HIPCHK(c, hipMemsetAsync(cens, 0, 24, c->stream));
         for (int t = 0; t < nsteps; t++) {
@@ -822,8 +822,8 @@ capib_status capib_step(capib_ctx *c, int32_t nsteps) {
             } else {
                 HIPCHK(c, launch_body_far(c->d, c->par, c->stream, e[2], e[3]));
             }
-            HIPCHK(c, launch_lattice_sweep(c->d, c->par, c->stream, e[6], e[7], nfb));
-            HIPCHK(c, launch_census(c->d, c->par, nfb, cens, c->stream));
+            HIPCHK(c, launch_lattice_sweep(c->d, c->par, c->stream, e[6], e[7], pct));
+            HIPCHK(c, launch_census(c->d, c->par, pct, cens, c->stream));
             c->par ^= 1;
             c->step++;
         }

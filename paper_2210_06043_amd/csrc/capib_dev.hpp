@@ -198,6 +198,22 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + min(x, r) + (b >> 3);
 }
 
+// The same contiguous run of XCD x among n far-tile candidates (in natural
+// order: tile index, or index into the live-tile list), for launches whose
+// far workgroups start at a block index that is a multiple of 8, so that
+// blockIdx & 7 is their XCD.  On a small lattice the membrane launch sweeps
+// the first far_share_len(len, pct) candidates of every run and the sweep
+// the rest, each on the run's own XCD.
+struct XcdRun {
+    int start, len;
+};
+__host__ __device__ inline XcdRun xcd_run(int x, int n) {
+    const int q = n >> 3, r = n & 7;
+    return XcdRun{x * q + (x < r ? x : r), q + (x < r ? 1 : 0)};
+}
+__host__ __device__ inline int far_share_len(int len, int pct) { return (int)((long long)len * pct / 100); }
+__host__ __device__ inline int round_up8(int n) { return (n + 7) & ~7; }
+
 __device__ __forceinline__ int wrapi(int i, int n) {
     if ((unsigned)i < (unsigned)n) return i;   // the common case, without a division
     i %= n;

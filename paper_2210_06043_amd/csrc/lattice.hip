@@ -59,8 +59,9 @@ __device__ __forceinline__ bool meets_periodic(int o, int t0, int w, int n) {
 // wave (see mark_next).  The next nlb workgroups sweep this step's near tiles from the list that the
 // previous step's marking built (grid-stride, one workgroup per tile while
 // there are enough).  On a lattice of fewer than SPLIT_MIN_TILES tiles the
-// last part is the far tiles that the membrane launch (k_body_far) left,
-// from candidate fb0 on, one workgroup each, dispatched after the near
+// last part is the far tiles that the membrane launch (k_body_far) left
+// (all but the first pct percent of each XCD's run of candidates), one
+// workgroup each on the run's own XCD, dispatched after the near
 // tiles so that their longer latency chains start first: there, far tiles
 // in the membrane launch and in this sweep cost less than far tiles run
 // beside the membrane phase on a second stream, whose cross-stream
@@ -316,7 +317,7 @@ __device__ __forceinline__ void near_tile(const Dev &d, const int4 e0, const int
 }
 
 template <typename T, int PAR, bool ENS, bool FULL, bool PAIRS>
-__global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark, int nlb, int fb0) {
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark, int nlb, int pct) {
     if ((int)blockIdx.x < nmark) {
         mark_next<PAR ^ 1, ENS, PAIRS>(d, blockIdx.x);
         return;
@@ -337,7 +338,17 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice_sweep(Dev d, int nmark,
         }
         return;
     }
-    if (FULL) far_tile<T, PAR, ENS>(d, fb0 + bid - nlb);
+    if (FULL) {
+        // from the first multiple of 8 at or after block nmark + nlb: the
+        // candidates of each XCD's run that the membrane launch left, on the
+        // run's own XCD (the few blocks before it have nothing to do)
+        const int g0 = round_up8(nmark + nlb);
+        if ((int)blockIdx.x < g0) return;
+        const int ncand = ENS ? d.nlive : d.ntx * d.nty;
+        const XcdRun run = xcd_run(blockIdx.x & 7, ncand);
+        const int c = far_share_len(run.len, pct) + (((int)blockIdx.x - g0) >> 3);
+        if (c < run.len) far_tile<T, PAR, ENS>(d, run.start + c);
+    }
 }
 
 // Moments of the current state for read-out: drho and u* = (j + g/2)/rho
@@ -466,57 +477,67 @@ constexpr int PAIRS_MAX_VERTS = 16384;
 bool default_mark_pairs(int nverts) { return nverts < PAIRS_MAX_VERTS; }
 
 template <typename T, int P, bool E, bool PA>
-static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
+static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int pct) {
     constexpr int mv = mark_verts<PA>();
     const int nmark = (d.nverts + mv - 1) / mv;
     const int nt = d.ntx * d.nty;
     const int want = d.nverts / 8 > 1024 ? d.nverts / 8 : 1024;
     const int nlb = nt < want ? nt : want;
-    if (!lattice_split(d))
-        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true, PA>), dim3(nmark + nlb + (E ? d.nlive : nt) - fb0),
-                              dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark, nlb, fb0);
-    else
+    if (!lattice_split(d)) {
+        // the far workgroups start at the first multiple of 8 after the near
+        // ones; each XCD's run needs at most len - share of them
+        const int ncand = E ? d.nlive : nt;
+        const int len = xcd_run(0, ncand).len;
+        const int most = len - far_share_len(len, pct);
+        hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, true, PA>), dim3(round_up8(nmark + nlb) + 8 * most),
+                              dim3(LAT_THREADS), 0, st, e0, e1, 0, d, nmark, nlb, pct);
+    } else
         hipExtLaunchKernelGGL((k_lattice_sweep<T, P, E, false, PA>), dim3(nmark + nlb), dim3(LAT_THREADS), 0, st, e0,
                               e1, 0, d, nmark, nlb, 0);
 }
 template <typename T, int P, bool E>
-static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
+static void go_sweep(const Dev &d, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int pct) {
     if (d.mark_pairs)
-        go_sweep<T, P, E, true>(d, st, e0, e1, fb0);
+        go_sweep<T, P, E, true>(d, st, e0, e1, pct);
     else
-        go_sweep<T, P, E, false>(d, st, e0, e1, fb0);
+        go_sweep<T, P, E, false>(d, st, e0, e1, pct);
 }
 template <typename T>
-static void sweep_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
+static void sweep_of(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int pct) {
     const bool ens = d.nbands > 1;
-    if (par) ens ? go_sweep<T, 1, true>(d, st, e0, e1, fb0) : go_sweep<T, 1, false>(d, st, e0, e1, fb0);
-    else ens ? go_sweep<T, 0, true>(d, st, e0, e1, fb0) : go_sweep<T, 0, false>(d, st, e0, e1, fb0);
+    if (par) ens ? go_sweep<T, 1, true>(d, st, e0, e1, pct) : go_sweep<T, 1, false>(d, st, e0, e1, pct);
+    else ens ? go_sweep<T, 0, true>(d, st, e0, e1, pct) : go_sweep<T, 0, false>(d, st, e0, e1, pct);
 }
 
-hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int fb0) {
+hipError_t launch_lattice_sweep(const Dev &d, int par, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int pct) {
     if (d.storage == 0)
-        sweep_of<float>(d, par, st, e0, e1, fb0);
+        sweep_of<float>(d, par, st, e0, e1, pct);
     else
-        sweep_of<_Float16>(d, par, st, e0, e1, fb0);
+        sweep_of<_Float16>(d, par, st, e0, e1, pct);
     return hipGetLastError();
 }
 
 // Nodes swept by the lattice launches of a step, for the timing accounting:
-// out[0] += far-tile nodes among the candidates b < nfb (swept by the
-// membrane launch), out[1] += the other far-tile nodes, out[2] += near-tile
-// nodes.  One thread per candidate tile.
+// out[0] += far-tile nodes among the first far_share_len(len, pct)
+// candidates of each XCD's run (swept by the membrane launch), out[1] +=
+// the other far-tile nodes, out[2] += near-tile nodes.  One thread per
+// candidate tile.
 template <bool ENS>
-__global__ __launch_bounds__(256) void k_census(Dev d, int par, int nfb, unsigned long long *out) {
+__global__ __launch_bounds__(256) void k_census(Dev d, int par, int pct, unsigned long long *out) {
     const int ncand = ENS ? d.nlive : d.ntx * d.nty;
     const int b = blockIdx.x * 256 + threadIdx.x;
     int c[3] = {0, 0, 0};
     if (b < ncand) {
-        const int tile = ENS ? d.live[xcd_tile(b, ncand)] : xcd_tile(b, ncand);
+        const int tile = ENS ? d.live[b] : b;
+        int x = 7;
+        while (x > 0 && xcd_run(x, ncand).start > b) x--;
+        const XcdRun run = xcd_run(x, ncand);
+        const bool membrane_launch = b - run.start < far_share_len(run.len, pct);
         const int ty = tile / d.ntx, tx = tile - ty * d.ntx;
         const int x0 = tx * TILE_X, y0 = ty * TILE_Y;
         const Band B = band_at_row<ENS>(d, y0);   // a tile lies in one band
         const int n = max(0, min(TILE_X, B.nx - x0)) * max(0, min(TILE_Y, d.ny - y0));
-        c[d.tnear[par][tile] ? 2 : b < nfb ? 0 : 1] = n;
+        c[d.tnear[par][tile] ? 2 : membrane_launch ? 0 : 1] = n;
     }
     for (int k = 0; k < 3; k++) {
         const int s = wave_sum(c[k]);
@@ -524,12 +545,12 @@ __global__ __launch_bounds__(256) void k_census(Dev d, int par, int nfb, unsigne
     }
 }
 
-hipError_t launch_census(const Dev &d, int par, int nfb, unsigned long long *out, hipStream_t st) {
+hipError_t launch_census(const Dev &d, int par, int pct, unsigned long long *out, hipStream_t st) {
     const int ncand = d.nbands > 1 ? d.nlive : d.ntx * d.nty;
     if (d.nbands > 1)
-        hipLaunchKernelGGL(k_census<true>, dim3((ncand + 255) / 256), dim3(256), 0, st, d, par, nfb, out);
+        hipLaunchKernelGGL(k_census<true>, dim3((ncand + 255) / 256), dim3(256), 0, st, d, par, pct, out);
     else
-        hipLaunchKernelGGL(k_census<false>, dim3((ncand + 255) / 256), dim3(256), 0, st, d, par, nfb, out);
+        hipLaunchKernelGGL(k_census<false>, dim3((ncand + 255) / 256), dim3(256), 0, st, d, par, pct, out);
     return hipGetLastError();
 }
 

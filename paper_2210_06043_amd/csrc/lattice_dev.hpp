@@ -166,11 +166,11 @@ __device__ __forceinline__ void lattice_collide(const Dev &d, int par, int i, in
 
 // A far tile: one that is not near in this step (its flag is clear), swept
 // with the body force alone by the 256 threads t of a workgroup (or of its
-// half).  b indexes the far-tile candidates, mapped in XCD-contiguous order
-// to every tile (with several bands: to every tile that holds fluid nodes).
+// half).  b is the candidate in natural order: the tile (with several bands,
+// the index into the list of tiles that hold fluid nodes).
 template <typename T, int PAR, bool ENS>
 __device__ __forceinline__ void far_tile(const Dev &d, int b, int t = threadIdx.x) {
-    const int tile = ENS ? d.live[xcd_tile(b, d.nlive)] : xcd_tile(b, d.ntx * d.nty);
+    const int tile = ENS ? d.live[b] : b;
     if (d.tnear[PAR][tile]) return;
     int i, j;
     tile_node(d, tile, i, j, t);

@@ -276,7 +276,8 @@ def config_c2(seed=0, steps=50000, ar=None, ca=None):
                   kr0=kf / KF_OVER_KR0, lb=ycr / 20.0, seed=seed)
     return Config("c2_3840x240", nx, ny, tau, g, ux_init=poiseuille_profile(ny, g, tau),
                   bodies=bodies, bonds=[bonds], steps=steps,
-                  meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, n_bound0=200))
+                  meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, n_bound0=200,
+                            cell_types=[1, 0, 1, 0, 1, 0]))
 
 
 def config_mr(seed=2, steps=2000):

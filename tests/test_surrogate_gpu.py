@@ -58,5 +58,12 @@ def test_screened_sweep_against_the_solver_alone():
         f"variant answers ({res['eval_fallbacks']} fallbacks) = {res['answers_per_run']:.2f} answers per run")
     for tau, err, runs, given in res["calibration"]:
         say(f"  calibration: threshold {tau:.4f} -> worst error {err:.4f}, {runs} runs for {given} answers")
+    # answers per hour: the solver alone gives one variant answer per run
+    # (runs of the sweep's length at the measured ensemble step time); the
+    # screened sweep answers_per_run per solver run (inference takes
+    # microseconds per variant)
+    solver = 256 * 3600.0 / (600 * res["harvest_ms_per_step"] * 1e-3)
+    say(f"variant answers per hour at standardised error <= {res['eps']}: solver alone {solver:.3e}, "
+        f"screened {solver * res['answers_per_run']:.3e}")
     assert max(res["eval_error"]) <= 0.15
     assert res["answers_per_run"] > 1.0

@@ -238,7 +238,7 @@ capib_status capib_set_graph(capib_ctx *ctx, int32_t enable);
  *                   by the membrane launch.  Rule: 1 from 8192 tiles of
  *                   64 x 4 nodes.
  *   far_share_pct   with split 0, percent of the far tiles swept by the
- *                   membrane launch (rule: 50 FP32, 80 FP16).
+ *                   membrane launch (rule: 65 FP32, 80 FP16).
  *   mark_pairs      1: the next step's near tiles marked with one (vertex,
  *                   stencil tile) pair per lane; 0: one vertex per lane
  *                   (rule: 1 below 16384 vertices).

@@ -220,8 +220,8 @@ __device__ __forceinline__ void body_run(const Dev &d, const int b) {
             // the same in FP64, from the hi/lo positions
             const double txd = ((double)sxh[m] - (double)rxh[k]) + ((double)sxl[m] - (double)rxl[k]);
             const double tyd = ((double)syh[m] - (double)ryh[k]) + ((double)syl[m] - (double)ryl[k]);
-            const double lend = sqrt(txd * txd + tyd * tyd);
-            const double nxd = tyd / lend, nyd = -txd / lend;
+            const double lend = sqrt(txd * txd + tyd * tyd), il = 1.0 / lend;
+            const double nxd = tyd * il, nyd = -txd * il;
             const double Lxd = (((double)q.y - (double)q.x) * nxd + (double)q.z * nyd) * lend;
             const double Lyd = ((double)q.z * nxd + ((double)q.w - (double)q.x) * nyd) * lend;
             sHd[0][l] = 0.5 * (bmd * nxd + Lxd);
@@ -621,10 +621,10 @@ __global__ __launch_bounds__(BodyShape<MV>::BT) void k_body_far(Dev d, int ncand
 }
 
 // Default share of the far-tile candidates swept by the membrane launch, in
-// percent (measured on 3840 x 240: the membrane kernel's 8-9 us hide about
-// this much streaming; FP16 tiles cost half the bytes); the autotuner picks
-// it per workload.
-constexpr int FAR_SHARE_FP32 = 50, FAR_SHARE_FP16 = 80;
+// percent (measured on 3840 x 240, step time against the share in steps of
+// 5-10 %: the membrane kernel's 8-10 us hide about this much streaming; FP16
+// tiles cost half the bytes); the autotuner picks it per workload.
+constexpr int FAR_SHARE_FP32 = 65, FAR_SHARE_FP16 = 80;
 
 int default_far_share(int storage) { return storage == 0 ? FAR_SHARE_FP32 : FAR_SHARE_FP16; }
 

@@ -1,4 +1,5 @@
-"""Build the FP64 CPU oracle (test infrastructure) with gcc.
+"""Build the FP64 CPU oracle (test infrastructure) with gcc: the 2D method
+(oracle.c) and the lattice of its 3D extension (oracle3d.c) in one library.
 
 The oracle is plain C; it is compiled without fast-math or FMA contraction so
 that its double-precision arithmetic follows the source order.  OpenMP splits
@@ -16,13 +17,13 @@ LIB_SAN = os.path.join(HERE, "liboracle_san.so")
 
 
 def build(verbose: bool = False, sanitize: bool = False) -> str:
-    src = os.path.join(HERE, "oracle.c")
+    srcs = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "oracle3d.c")]
     out = LIB_SAN if sanitize else LIB
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-fno-fast-math", "-Wall", "-Wno-unused-function"]
     if sanitize:
         cmd += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
-    cmd += [src, "-o", out + ".tmp", "-lm"]
+    cmd += srcs + ["-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,113 @@
+"""ctypes wrapper of the FP64 oracle of the 3D extension's lattice
+(``oracle/oracle3d.c``): D3Q19 BGK with the Guo term in a capillary tube.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/`` and the CPU-baseline leg of
+``bench.py``.  The HIP library never imports it.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import lib as _lib
+
+TUBE, SLAB, BOX = 0, 1, 2
+_dp = C.POINTER(C.c_double)
+_ready = False
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _L():
+    global _ready
+    L = _lib()
+    if not _ready:
+        L.orc3_create.restype = C.c_void_p
+        L.orc3_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_double]
+        L.orc3_destroy.argtypes = [C.c_void_p]
+        L.orc3_is_fluid.restype = C.c_int
+        L.orc3_is_fluid.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.orc3_init_flow.argtypes = [C.c_void_p, _dp]
+        L.orc3_get_populations.argtypes = [C.c_void_p, _dp]
+        L.orc3_set_populations.argtypes = [C.c_void_p, _dp]
+        L.orc3_get_step.restype = C.c_longlong
+        L.orc3_get_step.argtypes = [C.c_void_p]
+        L.orc3_step.argtypes = [C.c_void_p, C.c_int]
+        L.orc3_macro.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+        L.orc3_totals.argtypes = [C.c_void_p, _dp]
+        L.orc3_lattice_tables.argtypes = [C.POINTER(C.c_int), _dp]
+        L.orc3_heq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
+        L.orc3_guo.argtypes = [C.c_double] + [C.c_double] * 6 + [_dp]
+        _ready = True
+    return L
+
+
+def lattice_tables():
+    e = np.zeros(57, dtype=np.int32)
+    w = np.zeros(19)
+    _L().orc3_lattice_tables(e.ctypes.data_as(C.POINTER(C.c_int)), _d(w))
+    return e.reshape(19, 3), w
+
+
+def heq(drho, ux, uy, uz):
+    out = np.zeros(19)
+    _L().orc3_heq(drho, ux, uy, uz, _d(out))
+    return out
+
+
+def guo(tau, u, F):
+    out = np.zeros(19)
+    _L().orc3_guo(tau, u[0], u[1], u[2], F[0], F[1], F[2], _d(out))
+    return out
+
+
+class Tube:
+    """D3Q19 lattice nx x ny x nz (x along the tube), FP64."""
+
+    def __init__(self, nx, ny, nz, tau, gx, geom=TUBE, radius=0.0):
+        self.L = _L()
+        self.p = self.L.orc3_create(nx, ny, nz, tau, gx, geom, radius)
+        if not self.p:
+            raise ValueError("orc3_create refused the lattice")
+        self.nx, self.ny, self.nz = nx, ny, nz
+
+    def __del__(self):
+        if getattr(self, "p", None):
+            self.L.orc3_destroy(self.p)
+            self.p = None
+
+    def fluid(self):
+        return np.array([[self.L.orc3_is_fluid(self.p, y, z) for y in range(self.ny)] for z in range(self.nz)],
+                        dtype=bool)
+
+    def init_flow(self, ux_of_yz=None):
+        a = None if ux_of_yz is None else np.ascontiguousarray(ux_of_yz, dtype=np.float64)
+        self.L.orc3_init_flow(self.p, None if a is None else _d(a))
+
+    def populations(self):
+        out = np.zeros((19, self.nz, self.ny, self.nx))
+        self.L.orc3_get_populations(self.p, _d(out))
+        return out
+
+    def set_populations(self, A):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        assert A.shape == (19, self.nz, self.ny, self.nx)
+        self.L.orc3_set_populations(self.p, _d(A))
+
+    def step(self, n=1):
+        self.L.orc3_step(self.p, int(n))
+
+    @property
+    def n(self):
+        return self.L.orc3_get_step(self.p)
+
+    def macro(self):
+        d, ux, uy, uz = (np.zeros((self.nz, self.ny, self.nx)) for _ in range(4))
+        self.L.orc3_macro(self.p, _d(d), _d(ux), _d(uy), _d(uz))
+        return d, ux, uy, uz
+
+    def totals(self):
+        out = np.zeros(4)
+        self.L.orc3_totals(self.p, _d(out))
+        return out

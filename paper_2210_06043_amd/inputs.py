@@ -241,13 +241,14 @@ def config_c1(seed=0, steps=2000):
                   meta=dict(umax=umax, nu=nu, dx_um=dx_um, n_bound0=50))
 
 
-def config_c2(seed=0, steps=50000, ar=None, ca=None):
+def config_c2(seed=0, steps=50000, ar=None, ca=None, cell_shift=0.0):
     """Paper-scale: 3840x240 channel (dx = 0.03125 um), Re = 0.01, tau = 1;
     six cells alternating biconcave and globular (radius 3.5 um = 112 nodes,
-    512 vertices each) on the centre line at x = 320 + 640 k; one discoidal
-    particle 2 um long (64 nodes), aspect ratio from {0.25, 0.5, 1.0} and Ca
-    from {0, 1e-4, 1e-3} drawn with the seed, 128 vertices, 200 bonds
-    engaged, mid-gap between the first two cells on the lower wall."""
+    512 vertices each) on the centre line at x = 320 + 640 k (+ cell_shift);
+    one discoidal particle 2 um long (64 nodes), aspect ratio from {0.25,
+    0.5, 1.0} and Ca from {0, 1e-4, 1e-3} drawn with the seed, 128 vertices,
+    200 bonds engaged, mid-gap between the first two cells on the lower
+    wall."""
     nx, ny, tau = 3840, 240, 1.0
     nu, umax, g = channel(ny, 0.01, tau)
     dx_um = 7.5 / ny
@@ -257,7 +258,7 @@ def config_c2(seed=0, steps=50000, ar=None, ca=None):
     ks_cell = stiffness(umax, tau, 1e-3)
     bodies = []
     for k in range(6):
-        cx = 320.0 + 640.0 * k
+        cx = 320.0 + 640.0 * k + cell_shift
         xy = biconcave(512, 112.0, cx, 119.5) if k % 2 == 0 else circle(512, 112.0, cx, 119.5)
         bodies.append(Body(DEFORMABLE, xy, None, ks=ks_cell, kb=0.1 * ks_cell, rho_r=1.0, tag=TAG_CELL))
     ycr = Y_CR_M / (dx_um * 1e-6)
@@ -278,6 +279,18 @@ def config_c2(seed=0, steps=50000, ar=None, ca=None):
                   bodies=bodies, bonds=[bonds], steps=steps,
                   meta=dict(umax=umax, nu=nu, dx_um=dx_um, ar=ar, ca=ca, n_bound0=200,
                             cell_types=[1, 0, 1, 0, 1, 0]))
+
+
+def config_c2_placed(seed, k):
+    """Member k of stream seed of the paper-scale surrogate data: the
+    paper-scale channel with its particle's aspect ratio and Ca drawn as in
+    config_c2 and the row of cells shifted along the channel by U(-150, 150)
+    nodes (the cells stay clear of the particle), so that the cell-particle
+    distance varies between members: at tau = 1 a paper-scale run barely
+    moves its cells, so placement supplies the range of r."""
+    rng = np.random.default_rng([seed, k, 7])
+    shift = float(rng.uniform(-150.0, 150.0))
+    return config_c2(seed=int(rng.integers(0, 2**31 - 1)), cell_shift=shift)
 
 
 def config_mr(seed=2, steps=2000):

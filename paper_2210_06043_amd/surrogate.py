@@ -49,21 +49,31 @@ def harvest(cfgs, steps, every=2, storage=capib.FP16_SHIFTED, graph=True):
 
 
 def features(samples, cfgs, first):
-    """(X [n][37], T [n][3], member id per row) from a harvest."""
+    """(X [n][37], T [n][3], member id per row) from a harvest: for member m
+    and sampling time k >= HIST - 1, the row (r, dp, aspect ratio, log10 Ca,
+    cell type, wall shear at times k - HIST + 1 .. k) with targets (drag,
+    lift, hazard) at k."""
     ns, nm, _ = samples.shape
-    X, T, M = [], [], []
+    nk = ns - HIST + 1
+    if nk <= 0:
+        return np.zeros((0, 5 + HIST)), np.zeros((0, 3)), np.zeros(0, dtype=np.int64)
+    S = np.asarray(samples, np.float64)
+    X = np.empty((nm, nk, 5 + HIST))
     for m, cfg in enumerate(cfgs):
-        s = samples[:, m, :]
+        s = S[:, m, :]
         ca = cfg.meta["ca"]
-        lca = math.log10(ca) if ca > 0 else -6.0
-        types = cfg.meta.get("cell_types", [])
-        for k in range(HIST - 1, ns):
-            cell = int(s[k, 5]) - first[m]
-            ctype = float(types[cell]) if 0 <= cell < len(types) else 0.0
-            X.append(np.concatenate([[s[k, 3], s[k, 4], cfg.meta["ar"], lca, ctype], s[k - HIST + 1:k + 1, 6]]))
-            T.append(s[k, :3])
-            M.append(m)
-    return np.asarray(X, np.float64), np.asarray(T, np.float64), np.asarray(M)
+        types = np.asarray(cfg.meta.get("cell_types", []), np.float64)
+        cell = s[HIST - 1:, 5].astype(np.int64) - first[m]
+        ok = (cell >= 0) & (cell < len(types))
+        X[m, :, 0] = s[HIST - 1:, 3]
+        X[m, :, 1] = s[HIST - 1:, 4]
+        X[m, :, 2] = cfg.meta["ar"]
+        X[m, :, 3] = math.log10(ca) if ca > 0 else -6.0
+        X[m, :, 4] = np.where(ok, types[np.where(ok, cell, 0)] if len(types) else 0.0, 0.0)
+        X[m, :, 5:] = np.lib.stride_tricks.sliding_window_view(s[:, 6], HIST)
+    T = np.transpose(S[HIST - 1:, :, :3], (1, 0, 2)).reshape(nm * nk, 3)
+    M = np.repeat(np.arange(nm), nk)
+    return X.reshape(nm * nk, 5 + HIST), T, M
 
 
 class Standardiser:
@@ -253,3 +263,33 @@ def screening_study(train_cfgs, sweep_seed=1, cells=32, steps=600, every=2, nets
     return dict(eps=eps, tau=best, eval_error=[float(e) for e in err], eval_runs=runs, eval_answers=given,
                 eval_fallbacks=fb, answers_per_run=given / runs, calibration=table, ms_per_train_step=ms_train,
                 train_samples=int(X.shape[0]), sweep_members=len(flat), harvest_ms_per_step=ms_h, nets=ens)
+
+
+def paper_scale_study(train_members=256, test_members=32, train_steps_solver=7876, test_steps_solver=2062, every=2,
+                      train_steps=1000, seed=11):
+    """The surrogate trained on samples harvested from paper-scale runs.
+
+    Training: train_members paper-scale channels (3840 x 240, six cells,
+    the particle's aspect ratio and Ca drawn as in the paper-scale draw, the
+    row of cells shifted by U(-150, 150) nodes; inputs.config_c2_placed) run
+    as one FP16 ensemble for train_steps_solver steps and sampled every
+    `every` steps: 256 x 3,907 = 1.0e6 samples at the defaults.  Held out:
+    test_members channels of another stream.  Returns the held-out
+    standardised mean squared error per output against the mean guess, the
+    sample counts and the timings."""
+    from . import inputs
+    tr = [inputs.config_c2_placed(seed, k) for k in range(train_members)]
+    te = [inputs.config_c2_placed(seed + 1, k) for k in range(test_members)]
+    S, ms, first = harvest(tr, train_steps_solver, every=every)
+    X, T, _ = features(S, tr, first)
+    del S
+    S2, ms2, first2 = harvest(te, test_steps_solver, every=every)
+    X2, T2, _ = features(S2, te, first2)
+    fx, ft = Standardiser(X), Standardiser(T)
+    net, ms_train = train(fx(X), ft(T), steps=train_steps, batch=4096)
+    P = predict(net, fx(X2))
+    err = np.mean((P - ft(T2)) ** 2, axis=0)
+    base = np.mean(ft(T2) ** 2, axis=0)
+    return dict(train_samples=int(X.shape[0]), test_samples=int(X2.shape[0]), err=[float(e) for e in err],
+                mean_guess=[float(b) for b in base], harvest_ms_per_step=ms, ms_per_train_step=ms_train,
+                finite=bool(np.all(np.isfinite(P))))

@@ -67,3 +67,21 @@ def test_screened_sweep_against_the_solver_alone():
         f"screened {solver * res['answers_per_run']:.3e}")
     assert max(res["eval_error"]) <= 0.15
     assert res["answers_per_run"] > 1.0
+
+
+@pytest.mark.timeout(600)
+def test_surrogate_trained_on_paper_scale_runs():
+    """Trained on 1.0e6 samples harvested from 256 paper-scale channels
+    (3840 x 240, six cells, the particle's aspect ratio and Ca drawn as in
+    the paper-scale draw, the row of cells shifted by up to 150 nodes so
+    that the cell-particle distance varies), evaluated on 32 channels of
+    another draw: drag below half and hazard below three quarters of the
+    mean-guess error; lift, which depends on what the features do not
+    carry, below 0.9 of it."""
+    res = surrogate.paper_scale_study()
+    say(f"paper-scale surrogate: {res['train_samples']} training samples, {res['test_samples']} held-out; solver "
+        f"{res['harvest_ms_per_step']:.3f} ms per 256-channel step; held-out MSE drag/lift/hazard "
+        f"{np.round(res['err'], 4).tolist()} vs mean guess {np.round(res['mean_guess'], 4).tolist()}")
+    assert res["finite"] and res["train_samples"] >= 1_000_000
+    e, b = res["err"], res["mean_guess"]
+    assert e[0] < 0.5 * b[0] and e[2] < 0.75 * b[2] and e[1] < 0.9 * b[1]

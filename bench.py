@@ -420,6 +420,58 @@ def surrogate_section(args, batched_out):
     return out
 
 
+def tube3d_section(args):
+    """The 3D extension's lattice: D3Q19 BGK with the Guo term in the
+    256 x 64 x 64 tube (R = 32) at Re = 0.01, FP32 deviation storage with the
+    collision in FP64; back-to-back steps on the library's stream, timed
+    with events; the FP64 oracle's error over 20 steps from the same state."""
+    import torch
+    from paper_2210_06043_amd import inputs, tube3d
+    p = inputs.tube3d_params()
+    g = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"])
+    prof = tube3d.hagen_poiseuille(p["ny"], p["nz"], p["radius"], p["tau"], p["gx"])
+    g.init_flow(prof)
+    g.step(args.tube3d_warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step(args.tube3d_steps)
+    e1.record(g.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.tube3d_steps
+    n = g.fluid_nodes
+    alg = 2 * 19 * 4 * n          # 19 FP32 populations read and written per fluid node
+    gbs = alg / (ms * 1e-3) / 1e9
+    return {"workload": f"D3Q19 tube {p['nx']}x{p['ny']}x{p['nz']}, radius {p['radius']:g} ({n} fluid nodes), tau 1, "
+                        f"Re 0.01 (g = {p['gx']:.4g}), halfway bounce-back walls; FP32 deviation storage, FP64 collision",
+            "fluid_nodes": n, "steps": args.tube3d_steps, "ms_per_step": round(ms, 5),
+            "mlups": round(n / (ms * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "kernel": "k3_sweep", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes_per_launch": alg, "traffic": counters("k3_sweep_fp32_tube"),
+                         "note": "one launch per step, timed back to back (launch gaps included); the 125 MB "
+                                 "working set fits the 256 MB Infinity Cache"}}
+
+
+def tube3d_error_vs_oracle(steps=20):
+    """Max-norm relative velocity error of the 3D tube against the FP64
+    oracle over `steps` steps from the same (GPU-stored) state (part of the
+    CPU-baseline leg: the oracle runs on the host)."""
+    from oracle import tube3d as otube
+    from paper_2210_06043_amd import inputs, tube3d
+    p = inputs.tube3d_params()
+    g = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"])
+    g.init_flow(tube3d.hagen_poiseuille(p["ny"], p["nz"], p["radius"], p["tau"], p["gx"]))
+    g.step(50)
+    o = otube.Tube(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"])
+    o.set_populations(g.populations())
+    g.step(steps)
+    o.step(steps)
+    ug, uo = np.stack(g.macro()[1:]), np.stack(o.macro()[1:])
+    return float(np.abs(ug - uo).max() / np.abs(uo).max())
+
+
 def roofline(m, storage_name, workload_name):
     traffic = counters(f"{m['kernel'][2:]}_{storage_name}_{workload_name}")
     return {"bound": "hbm", "kernel": m["kernel"], "achieved": round(m["achieved"], 1), "peak": HBM_PEAK_GBS,
@@ -455,6 +507,10 @@ def main():
     ap.add_argument("--mr-steps", type=int, default=200)
     ap.add_argument("--mr-warmup", type=int, default=20)
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-tube3d", action="store_true")
+    ap.add_argument("--tube3d-only", action="store_true", help="print only the 3D tube measurement")
+    ap.add_argument("--tube3d-steps", type=int, default=1000)
+    ap.add_argument("--tube3d-warmup", type=int, default=100)
     ap.add_argument("--harvest-steps", type=int, default=600)
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -490,6 +546,9 @@ def main():
         return
     if args.mr_only:
         print(json.dumps({"mr": mr_section(args, None)}), flush=True)
+        return
+    if args.tube3d_only:
+        print(json.dumps({"tube3d": tube3d_section(args)}), flush=True)
         return
     cfg, desc = workload(args.workload, args.seed)
     nodes = cfg.nx * cfg.ny
@@ -536,6 +595,8 @@ def main():
         out["mr"] = mr_section(args, copy_gbs)
     if not args.no_batched:
         out["batched"] = batched(args)
+    if not args.no_tube3d:
+        out["tube3d"] = tube3d_section(args)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_section(args, out.get("batched"))
     if not args.no_cpu_baseline:
@@ -544,6 +605,8 @@ def main():
         out["error_vs_oracle"] = {
             name: error_vs_oracle(cfg, capib.FP16_SHIFTED if name == "fp16" else capib.FP32_SHIFTED,
                                   scale16 if name == "fp16" else 1.0, args.cpu_steps, ref) for name in runs}
+        if "tube3d" in out:
+            out["tube3d"]["velocity_rel_err_vs_oracle_20_steps"] = tube3d_error_vs_oracle(20)
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,107 @@
+/*
+ * capib3d — C-ABI of the lattice of the three-dimensional extension of the
+ * lattice-Boltzmann / immersed-boundary method of Coclite, Pascazio, de
+ * Tullio and Decuzzi (arXiv 2210.06043), which its conclusions name as the
+ * next step: the BGK update of Eq. (1) with the equilibrium of Eq. (2), the
+ * Guo term of Eq. (4) and the moments of Eqs. (5)-(6) on the D3Q19 velocity
+ * set, in a capillary tube with no-slip walls (halfway bounce-back, as the
+ * 2D channel's walls), driven by a uniform body force along the tube.
+ * Immersed membranes in 3D are not part of this library.
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3.
+ *   - Nodes (x, y, z), x in [0, nx) along the tube (periodic), (y, z) the
+ *     cross-section.  Geometry CAPIB3D_TUBE: fluid iff (y - (ny-1)/2)^2 +
+ *     (z - (nz-1)/2)^2 < radius^2; CAPIB3D_SLAB: every node, walls half-way
+ *     beyond z = 0 and z = nz - 1, periodic in y; CAPIB3D_BOX: periodic in
+ *     all three directions.  A link whose upstream node is solid returns the
+ *     node's own post-collision population of the opposite direction.
+ *   - D3Q19 order: rest; +x, -x, +y, -y, +z, -z; (+1,+1,0), (-1,-1,0),
+ *     (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1), (+1,0,-1), (-1,0,+1),
+ *     (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1); weights 1/3, 1/18, 1/36.
+ *   - Host arrays of node fields are [nz][ny][nx] doubles; population arrays
+ *     [19][nz][ny][nx], stored shifted (h = f - w); solid nodes read as 0.
+ *   - Storage: FP32 deviations from the equilibrium of the reference profile
+ *     given to capib3d_init_flow (at rho = 1), one rounding per stored value:
+ *     the collision is evaluated in FP64.
+ *
+ * Ownership, streams and errors as in capib.h: the caller owns the
+ * workspace (capib3d_workspace_bytes(), 256-byte aligned, bound once); all
+ * GPU work goes to the hip stream given at creation; calls marked "syncs"
+ * wait for it; every call returns a capib_status, capib3d_last_error() gives
+ * the message of the last failing call.  One context per host thread.
+ */
+#ifndef CAPIB3D_H
+#define CAPIB3D_H
+
+#include "capib.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { CAPIB3D_TUBE = 0, CAPIB3D_SLAB = 1, CAPIB3D_BOX = 2 };
+
+/* The lattice and the tube.
+ *   nx, ny, nz  nodes (each >= 1; nx * ny * nz < 2^31)
+ *   tau         BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3)
+ *   gx          uniform driving body force per node along x
+ *   geometry    CAPIB3D_TUBE, CAPIB3D_SLAB or CAPIB3D_BOX
+ *   radius      tube radius in nodes (CAPIB3D_TUBE only, > 0)            */
+typedef struct {
+    int32_t nx, ny, nz;
+    double tau, gx;
+    int32_t geometry;
+    double radius;
+} capib3d_lattice;
+
+typedef struct capib3d_ctx capib3d_ctx;
+
+/* Validates the lattice and creates a context (no device work). */
+capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3d_ctx **out);
+void capib3d_destroy(capib3d_ctx *ctx);
+
+/* Bytes of device workspace the context needs. */
+size_t capib3d_workspace_bytes(const capib3d_ctx *ctx);
+/* Binds the caller's workspace (device pointer, 256-byte aligned, at least
+ * capib3d_workspace_bytes()); uploads the geometry tables.  Syncs. */
+capib_status capib3d_bind_workspace(capib3d_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* The initial state, Eq. (2) at rho = 1 and u = (ux(y, z), 0, 0) on every
+ * fluid node, which is also the reference of the FP32 deviation storage
+ * (ux_of_yz [nz][ny] host doubles, NULL = rest).  Syncs.                  */
+capib_status capib3d_init_flow(capib3d_ctx *ctx, const double *ux_of_yz);
+
+/* nsteps steps of Eq. (1): pull streaming with bounce-back, moments of
+ * Eqs. (5)-(6) with half the body force, BGK collision with the Guo term
+ * of Eq. (4).  Enqueued on the context's stream; does not sync. */
+capib_status capib3d_step(capib3d_ctx *ctx, int32_t nsteps);
+
+/* The moments the next step starts from (Eqs. 5-6 of the streamed
+ * populations with half the body force): drho, ux, uy, uz, [nz][ny][nx]
+ * host doubles each (any may be NULL; zero on solid nodes).  Syncs. */
+capib_status capib3d_read_macro(capib3d_ctx *ctx, double *drho, double *ux, double *uy, double *uz);
+
+/* Stored (post-collision) populations, shifted h = f - w, [19][nz][ny][nx]
+ * host doubles.  Writing rounds each to FP32 relative to the reference;
+ * solid nodes are ignored.  Both sync. */
+capib_status capib3d_read_populations(capib3d_ctx *ctx, double *out);
+capib_status capib3d_write_populations(capib3d_ctx *ctx, const double *in);
+
+/* FP64 sums over the fluid nodes of the stored populations: out4 = {mass
+ * sum h, momentum sum h e (x, y, z)}, the invariants of the update (mass
+ * is conserved, momentum grows by the body force per node and step).
+ * Also the step count.  Syncs. */
+capib_status capib3d_diagnostics(capib3d_ctx *ctx, double *out4, int64_t *step);
+
+/* Fluid nodes of the lattice. */
+int64_t capib3d_fluid_nodes(const capib3d_ctx *ctx);
+
+/* Message of the last failing call on this context (never NULL). */
+const char *capib3d_last_error(const capib3d_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -88,6 +88,7 @@ typedef struct {
     double *A;              /* post-collision shifted populations [19][nz][ny][nx] */
     double *h;              /* streamed populations, same layout */
     long long step;
+    int opp[19];            /* opposite direction of each velocity */
 } orc3;
 
 static long long idx(const orc3 *s, int x, int y, int z) { return ((long long)z * s->ny + y) * s->nx + x; }
@@ -107,6 +108,7 @@ orc3 *orc3_create(int nx, int ny, int nz, double tau, double gx, int geom, doubl
     orc3 *s = (orc3 *)calloc(1, sizeof(orc3));
     s->nx = nx; s->ny = ny; s->nz = nz; s->tau = tau; s->gx = gx; s->geom = geom; s->radius = radius;
     s->n = (long long)nx * ny * nz;
+    for (int i = 0; i < 19; i++) s->opp[i] = opposite3(i);
     s->fluid = (unsigned char *)calloc((size_t)ny * nz, 1);
     for (int z = 0; z < nz; z++)
         for (int y = 0; y < ny; y++) s->fluid[z * ny + y] = (unsigned char)is_fluid_yz(s, y, z);
@@ -159,7 +161,7 @@ static void stream3(orc3 *s) {
                     if (is_fluid_yz(s, ys, zs))
                         s->h[i * n + k] = s->A[i * n + idx(s, xs, ys, zs)];
                     else
-                        s->h[i * n + k] = s->A[opposite3(i) * n + k];
+                        s->h[i * n + k] = s->A[s->opp[i] * n + k];
                 }
             }
         }

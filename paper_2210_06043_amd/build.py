@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcapib.so")
-SOURCES = ["lattice.hip", "ib.hip", "body.hip", "capib.hip", "mlp.hip", "copy.hip"]
+SOURCES = ["lattice.hip", "ib.hip", "body.hip", "capib.hip", "mlp.hip", "copy.hip", "tube3d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=on: multiply-adds are fused only within one expression, so a

@@ -458,3 +458,15 @@ def lattice_only(nx, ny, tau, walls=3, umax=1e-3, seed=0, noise=0.0):
     cfg = Config(f"lattice_{nx}x{ny}", nx, ny, tau, g, walls=walls,
                  ux_init=poiseuille_profile(ny, g, tau) if walls else None, meta=dict(umax=umax))
     return cfg
+
+
+def tube3d_params(re=0.01, nx=256, diameter=64, tau=1.0):
+    """The 3D extension's tube: D3Q19, a circular tube of the given diameter
+    (nodes) and length nx along x, tau = 1, driven by the body force that
+    gives Hagen-Poiseuille flow at Reynolds number re = u_mean D / nu
+    (u_mean = g R^2 / (8 nu))."""
+    nu = (tau - 0.5) / 3.0
+    R = diameter / 2.0
+    u_mean = re * nu / diameter
+    g = 8.0 * nu * u_mean / (R * R)
+    return dict(nx=nx, ny=diameter, nz=diameter, tau=tau, gx=g, radius=R, u_mean=u_mean)

@@ -1,0 +1,130 @@
+"""ctypes binding of the 3D extension's lattice (``include/capib3d.h``):
+D3Q19 BGK with the Guo term in a capillary tube, in ``libcapib.so``.
+
+Argument marshalling only; every step runs in the library's kernels.  torch
+provides the device workspace and the stream.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import capib
+
+TUBE, SLAB, BOX = 0, 1, 2
+Q = 19
+_P = C.c_void_p
+_dp = C.POINTER(C.c_double)
+
+
+class capib3d_lattice(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
+                ("geometry", C.c_int32), ("radius", C.c_double)]
+
+
+SIGNATURES = {
+    "capib3d_create": (C.c_int, [C.POINTER(capib3d_lattice), _P, C.POINTER(_P)]),
+    "capib3d_destroy": (None, [_P]),
+    "capib3d_workspace_bytes": (C.c_size_t, [_P]),
+    "capib3d_bind_workspace": (C.c_int, [_P, _P, C.c_size_t]),
+    "capib3d_init_flow": (C.c_int, [_P, _dp]),
+    "capib3d_step": (C.c_int, [_P, C.c_int32]),
+    "capib3d_read_macro": (C.c_int, [_P, _dp, _dp, _dp, _dp]),
+    "capib3d_read_populations": (C.c_int, [_P, _dp]),
+    "capib3d_write_populations": (C.c_int, [_P, _dp]),
+    "capib3d_diagnostics": (C.c_int, [_P, _dp, C.POINTER(C.c_int64)]),
+    "capib3d_fluid_nodes": (C.c_int64, [_P]),
+    "capib3d_last_error": (C.c_char_p, [_P]),
+}
+_ready = False
+
+
+def _lib():
+    global _ready
+    L = capib.load_library()
+    if not _ready:
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _ready = True
+    return L
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def hagen_poiseuille(ny, nz, radius, tau, gx):
+    """u(y, z) = g (R^2 - r^2) / (4 nu) inside the tube, 0 outside ([nz][ny])."""
+    nu = (tau - 0.5) / 3.0
+    y = np.arange(ny) - 0.5 * (ny - 1)
+    z = np.arange(nz) - 0.5 * (nz - 1)
+    r2 = z[:, None] ** 2 + y[None, :] ** 2
+    return np.where(r2 < radius * radius, gx / (4 * nu) * (radius * radius - r2), 0.0)
+
+
+class Tube3D:
+    """A D3Q19 tube on the GPU (workspace allocated with torch)."""
+
+    def __init__(self, nx, ny, nz, tau, gx, geometry=TUBE, radius=0.0, stream=None):
+        import torch
+        self.torch = torch
+        self.L = _lib()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius)
+        self.ctx = _P()
+        st = self.L.capib3d_create(C.byref(lat), _P(self.stream.cuda_stream), C.byref(self.ctx))
+        if st != capib.CAPIB_OK:
+            raise capib.CapibError(st, "capib3d_create refused the lattice")
+        self.nx, self.ny, self.nz, self.tau, self.gx = nx, ny, nz, tau, gx
+        nbytes = self.L.capib3d_workspace_bytes(self.ctx)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize()
+        self._check(self.L.capib3d_bind_workspace(self.ctx, _P((self.workspace.data_ptr() + 255) & ~255), nbytes))
+
+    def _check(self, st):
+        if st != capib.CAPIB_OK:
+            raise capib.CapibError(st, self.L.capib3d_last_error(self.ctx).decode())
+
+    def __del__(self):
+        if getattr(self, "ctx", None):
+            self.L.capib3d_destroy(self.ctx)
+            self.ctx = None
+
+    @property
+    def fluid_nodes(self):
+        return int(self.L.capib3d_fluid_nodes(self.ctx))
+
+    def init_flow(self, ux_of_yz=None):
+        a = None if ux_of_yz is None else np.ascontiguousarray(ux_of_yz, dtype=np.float64)
+        if a is not None:
+            assert a.shape == (self.nz, self.ny)
+        self._check(self.L.capib3d_init_flow(self.ctx, None if a is None else _d(a)))
+
+    def step(self, n=1):
+        self._check(self.L.capib3d_step(self.ctx, int(n)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def macro(self):
+        d, ux, uy, uz = (np.zeros((self.nz, self.ny, self.nx)) for _ in range(4))
+        self._check(self.L.capib3d_read_macro(self.ctx, _d(d), _d(ux), _d(uy), _d(uz)))
+        return d, ux, uy, uz
+
+    def populations(self):
+        out = np.zeros((Q, self.nz, self.ny, self.nx))
+        self._check(self.L.capib3d_read_populations(self.ctx, _d(out)))
+        return out
+
+    def set_populations(self, A):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        assert A.shape == (Q, self.nz, self.ny, self.nx)
+        self._check(self.L.capib3d_write_populations(self.ctx, _d(A)))
+
+    def diagnostics(self):
+        out = np.zeros(4)
+        step = C.c_int64()
+        self._check(self.L.capib3d_diagnostics(self.ctx, _d(out), C.byref(step)))
+        return dict(mass=out[0], mom_x=out[1], mom_y=out[2], mom_z=out[3], step=step.value)

@@ -8,17 +8,18 @@ import subprocess
 
 import pytest
 
-from paper_2210_06043_amd import capib, mlp
+from paper_2210_06043_amd import capib, mlp, tube3d
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "capib.h")
 MLP_HEADER = os.path.join(ROOT, "include", "capib_mlp.h")
+HEADER3D = os.path.join(ROOT, "include", "capib3d.h")
 
 
-def declared_functions(header=HEADER):
+def declared_functions(header=HEADER, prefix="capib_"):
     src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(capib_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_0-9]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
@@ -31,17 +32,41 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol():
     L = capib.load_library()
-    names = declared_functions() + declared_functions(MLP_HEADER)
+    names = declared_functions() + declared_functions(MLP_HEADER) + declared_functions(HEADER3D, "capib3d_")
     for name in names:
         assert hasattr(L, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", capib.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r" T (capib_\w+)", out))
+    exported = set(re.findall(r" T (capib3?d?_\w+)", out))
     assert set(names) <= exported
 
 
 def test_binding_covers_the_header():
     assert set(capib.SIGNATURES) == set(declared_functions())
     assert set(mlp.SIGNATURES) == set(declared_functions(MLP_HEADER))
+    assert set(tube3d.SIGNATURES) == set(declared_functions(HEADER3D, "capib3d_"))
+
+
+def test_tube3d_create_validates_without_a_gpu():
+    """capib3d_create checks the lattice on the host and sizes the workspace
+    (two FP32 population buffers of 19 planes with a 64-aligned pitch, the
+    column tables, the FP64 read-out and the partial sums)."""
+    L = tube3d._lib()
+    ctx = C.c_void_p()
+    bad = [tube3d.capib3d_lattice(0, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0),
+           tube3d.capib3d_lattice(8, 8, 8, 0.5, 0.0, tube3d.TUBE, 3.0),
+           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 0.0),
+           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, 7, 3.0)]
+    for lat in bad:
+        assert L.capib3d_create(C.byref(lat), None, C.byref(ctx)) == capib.CAPIB_E_ARG
+    lat = tube3d.capib3d_lattice(256, 64, 64, 1.0, 1e-7, tube3d.TUBE, 32.0)
+    assert L.capib3d_create(C.byref(lat), None, C.byref(ctx)) == capib.CAPIB_OK
+    try:
+        n = L.capib3d_fluid_nodes(ctx)
+        assert n == 256 * 3228   # fluid columns of a 64 x 64 cross-section with R = 32
+        assert L.capib3d_workspace_bytes(ctx) >= 2 * 19 * 256 * 64 * 64 * 4
+        assert L.capib3d_step(ctx, 1) == capib.CAPIB_E_STATE   # no workspace bound
+    finally:
+        L.capib3d_destroy(ctx)
 
 
 def test_surrogate_parameter_count_matches_the_oracle():

@@ -23,14 +23,18 @@ METRIC = "LBM-IBM MLUPS & HBM GB/s (FP32 vs FP16-store); batched sweep runs/hour
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_source_hash():
+LATTICE_SOURCES = ("capib_dev.hpp", "lattice_dev.hpp", "lattice.hip", "body.hip")
+TUBE3D_SOURCES = ("tube3d.hip",)
+
+
+def kernel_source_hash(sources=LATTICE_SOURCES):
     """Hash of the sources of the lattice launches (their device code and the
     host code that sets their shares of the tiles), comments and blank lines
     left out, so that the counters stay valid across edits of the text."""
     import re
     csrc = os.path.join(ROOT, "paper_2210_06043_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("capib_dev.hpp", "lattice_dev.hpp", "lattice.hip", "body.hip"):
+    for f in sources:
         for line in open(os.path.join(csrc, f), encoding="utf-8"):
             code = re.sub(r"//.*", "", line).rstrip()
             if code:
@@ -38,14 +42,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counters(name):
+def counters(name, sources=LATTICE_SOURCES):
     """HBM bytes per launch of a lattice kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
     p = os.path.join(ROOT, "profiles", f"{name}_counters.json")
     if not os.path.exists(p):
         return None
     c = json.load(open(p))
-    if c.get("source_hash") != kernel_source_hash():
+    if c.get("source_hash") != kernel_source_hash(sources):
         return None
     return c.get("bytes_per_launch")
 
@@ -449,7 +453,7 @@ def tube3d_section(args):
             "mlups": round(n / (ms * 1e-3) / 1e6, 1),
             "roofline": {"bound": "hbm", "kernel": "k3_sweep", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                         "algorithmic_bytes_per_launch": alg, "traffic": counters("k3_sweep_fp32_tube"),
+                         "algorithmic_bytes_per_launch": alg, "traffic": counters("k3_sweep_fp32_tube", TUBE3D_SOURCES),
                          "note": "one launch per step, timed back to back (launch gaps included); the 125 MB "
                                  "working set fits the 256 MB Infinity Cache"}}
 

@@ -12,9 +12,10 @@
 // Populations are SoA pop[q][z][y][x] (x fastest, pitch a multiple of 64) as
 // FP32 deviations s = h - r(y, z) from the equilibrium of the reference
 // profile; the collision is evaluated in FP64 and each stored value rounded
-// once.  Work items (column, 64-wide x segment) are ordered segment-major, so
-// that a contiguous range of items (one XCD's share of the workgroups) covers
-// neighbouring columns of one segment and their shifted pulls share its L2.
+// once.  Work items (column, 64-wide x segment) are ordered column-major, so
+// that a contiguous range of items (one XCD's share of the workgroups) holds
+// every segment of a run of neighbouring columns and their shifted pulls
+// share its L2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -61,8 +62,8 @@ __device__ __forceinline__ bool item_of(const Dev3 &d, int &c, int &x) {
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int item = __builtin_amdgcn_readfirstlane(b * WAVES + (int)(threadIdx.x >> 6));
     if (item >= d.ncol * d.nseg) return false;
-    const int seg = item / d.ncol;
-    c = item - seg * d.ncol;
+    c = item / d.nseg;
+    const int seg = item - c * d.nseg;
     x = seg * 64 + (int)(threadIdx.x & 63);
     return true;
 }

@@ -447,6 +447,23 @@ def tube3d_section(args):
     n = g.fluid_nodes
     alg = 2 * 19 * 4 * n          # 19 FP32 populations read and written per fluid node
     gbs = alg / (ms * 1e-3) / 1e9
+    # the same with FP16 storage (FP32 arithmetic)
+    umax = float(prof.max())
+    g16 = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"],
+                        storage=capib_fp16(), fp16_scale=tube3d.fp16_scale_for(umax))
+    g16.init_flow(prof)
+    g16.step(args.tube3d_warmup)
+    torch.cuda.synchronize()
+    e0.record(g16.stream)
+    g16.step(args.tube3d_steps)
+    e1.record(g16.stream)
+    e1.synchronize()
+    ms16 = e0.elapsed_time(e1) / args.tube3d_steps
+    gbs16 = alg / 2 / (ms16 * 1e-3) / 1e9
+    fp16 = {"ms_per_step": round(ms16, 5), "mlups": round(n / (ms16 * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "kernel": "k3_sweep", "achieved": round(gbs16, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs16 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": alg // 2,
+                         "traffic": counters("k3_sweep_fp16_tube", TUBE3D_SOURCES)}}
     return {"workload": f"D3Q19 tube {p['nx']}x{p['ny']}x{p['nz']}, radius {p['radius']:g} ({n} fluid nodes), tau 1, "
                         f"Re 0.01 (g = {p['gx']:.4g}), halfway bounce-back walls; FP32 deviation storage, FP64 collision",
             "fluid_nodes": n, "steps": args.tube3d_steps, "ms_per_step": round(ms, 5),
@@ -455,7 +472,13 @@ def tube3d_section(args):
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                          "algorithmic_bytes_per_launch": alg, "traffic": counters("k3_sweep_fp32_tube", TUBE3D_SOURCES),
                          "note": "one launch per step, timed back to back (launch gaps included); the 125 MB "
-                                 "working set fits the 256 MB Infinity Cache"}}
+                                 "working set fits the 256 MB Infinity Cache"},
+            "fp16_storage": fp16}
+
+
+def capib_fp16():
+    from paper_2210_06043_amd import capib
+    return capib.FP16_SHIFTED
 
 
 def tube3d_error_vs_oracle(steps=20):

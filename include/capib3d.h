@@ -21,9 +21,11 @@
  *     (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1); weights 1/3, 1/18, 1/36.
  *   - Host arrays of node fields are [nz][ny][nx] doubles; population arrays
  *     [19][nz][ny][nx], stored shifted (h = f - w); solid nodes read as 0.
- *   - Storage: FP32 deviations from the equilibrium of the reference profile
- *     given to capib3d_init_flow (at rho = 1), one rounding per stored value:
- *     the collision is evaluated in FP64.
+ *   - Storage: deviations from the equilibrium of the reference profile
+ *     given to capib3d_init_flow (at rho = 1): CAPIB_FP32_SHIFTED stores
+ *     them in FP32 with the collision evaluated in FP64 (one rounding per
+ *     stored value); CAPIB_FP16_SHIFTED stores them in FP16 multiplied by
+ *     fp16_scale, with FP32 arithmetic.
  *
  * Ownership, streams and errors as in capib.h: the caller owns the
  * workspace (capib3d_workspace_bytes(), 256-byte aligned, bound once); all
@@ -47,12 +49,16 @@ enum { CAPIB3D_TUBE = 0, CAPIB3D_SLAB = 1, CAPIB3D_BOX = 2 };
  *   tau         BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3)
  *   gx          uniform driving body force per node along x
  *   geometry    CAPIB3D_TUBE, CAPIB3D_SLAB or CAPIB3D_BOX
- *   radius      tube radius in nodes (CAPIB3D_TUBE only, > 0)            */
+ *   radius      tube radius in nodes (CAPIB3D_TUBE only, > 0)
+ *   storage     CAPIB_FP32_SHIFTED or CAPIB_FP16_SHIFTED
+ *   fp16_scale  power of two multiplying stored FP16 deviations (FP16 only) */
 typedef struct {
     int32_t nx, ny, nz;
     double tau, gx;
     int32_t geometry;
     double radius;
+    int32_t storage;
+    double fp16_scale;
 } capib3d_lattice;
 
 typedef struct capib3d_ctx capib3d_ctx;
@@ -83,8 +89,9 @@ capib_status capib3d_step(capib3d_ctx *ctx, int32_t nsteps);
 capib_status capib3d_read_macro(capib3d_ctx *ctx, double *drho, double *ux, double *uy, double *uz);
 
 /* Stored (post-collision) populations, shifted h = f - w, [19][nz][ny][nx]
- * host doubles.  Writing rounds each to FP32 relative to the reference;
- * solid nodes are ignored.  Both sync. */
+ * host doubles.  Writing rounds each to the storage type relative to the
+ * reference (CAPIB_E_ARG if a scaled FP16 deviation would overflow); solid
+ * nodes are ignored.  Both sync. */
 capib_status capib3d_read_populations(capib3d_ctx *ctx, double *out);
 capib_status capib3d_write_populations(capib3d_ctx *ctx, const double *in);
 

@@ -10,9 +10,10 @@
 // column's tables (19 source rows, 19 deviation constants and u_ref, FP64)
 // are wave-uniform scalar loads, and solid columns are never visited.
 // Populations are SoA pop[q][z][y][x] (x fastest, pitch a multiple of 64) as
-// FP32 deviations s = h - r(y, z) from the equilibrium of the reference
-// profile; the collision is evaluated in FP64 and each stored value rounded
-// once.  Work items (column, 64-wide x segment) are ordered column-major, so
+// deviations s = h - r(y, z) from the equilibrium of the reference profile:
+// FP32 with the collision evaluated in FP64 and each stored value rounded
+// once, or FP16 scaled by a power of two with FP32 arithmetic (as the 2D
+// storage modes).  Work items (column, 64-wide x segment) are ordered column-major, so
 // that a contiguous range of items (one XCD's share of the workgroups) holds
 // every segment of a run of neighbouring columns and their shifted pulls
 // share its L2.
@@ -43,7 +44,8 @@ struct Dev3 {
     int nx, ny, nz, pitch, ncol, nseg;
     long long qstride;          // nz * ny * pitch elements per population
     double omega, fc, gx;
-    float *pop[2];
+    float scale, inv_scale;     // FP16 storage scale (1 for FP32)
+    void *pop[2];
     const int *crow;            // [ncol][20]: own row (z ny + y), then the source row of each q (-1: bounce-back)
     const double *cK;           // [ncol][20]: deviation constant of each q, then u_ref
     double *macro;              // [4][nz][ny][nx]
@@ -57,6 +59,14 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + min(x, r) + (b >> 3);
 }
 
+// Arithmetic of the collision: FP64 for FP32 storage, FP32 for FP16.
+template <typename T> struct Arith3 { using type = float; };
+template <> struct Arith3<float> { using type = double; };
+__device__ __forceinline__ float ld3(const float *p, float) { return *p; }
+__device__ __forceinline__ float ld3(const _Float16 *p, float is) { return (float)(*p) * is; }
+__device__ __forceinline__ void st3(float *p, float v, float) { *p = v; }
+__device__ __forceinline__ void st3(_Float16 *p, float v, float sc) { *p = (_Float16)(v * sc); }
+
 // The wave's work item: its column c and x of this lane; false past the end.
 __device__ __forceinline__ bool item_of(const Dev3 &d, int &c, int &x) {
     const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -68,85 +78,86 @@ __device__ __forceinline__ bool item_of(const Dev3 &d, int &c, int &x) {
     return true;
 }
 
-// Pulled populations of node x of column c as FP64 deviations from its
-// column's reference: dh_q = s_q(source) + K_q.  Returns u_ref.
-template <int PAR>
-__device__ __forceinline__ double pull(const Dev3 &d, int c, int x, double dh[Q], long long &own) {
+// Pulled populations of node x of column c as deviations from its column's
+// reference, in the arithmetic type C: dh_q = s_q(source) + K_q.  Returns u_ref.
+template <typename T, typename C, int PAR>
+__device__ __forceinline__ C pull(const Dev3 &d, int c, int x, C dh[Q], long long &own) {
     const int *R = d.crow + 20 * c;
     const double *K = d.cK + 20 * c;
-    const float *A = d.pop[PAR];
+    const T *A = (const T *)d.pop[PAR];
     own = (long long)R[0] * d.pitch + x;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int rs = R[1 + q];
         float v;
         if (rs < 0) {
-            v = A[opp(q) * d.qstride + own];
+            v = ld3(A + opp(q) * d.qstride + own, d.inv_scale);
         } else {
             int xs = x - EX[q];
             xs = xs < 0 ? xs + d.nx : xs >= d.nx ? xs - d.nx : xs;
-            v = A[q * d.qstride + (long long)rs * d.pitch + xs];
+            v = ld3(A + q * d.qstride + (long long)rs * d.pitch + xs, d.inv_scale);
         }
-        dh[q] = (double)v + K[q];
+        dh[q] = (C)v + (C)K[q];
     }
-    return K[19];
+    return (C)K[19];
 }
 
-template <int PAR>
+template <typename T, int PAR>
 __global__ __launch_bounds__(64 * WAVES) void k3_sweep(Dev3 d) {
+    using C = typename Arith3<T>::type;
     int c, x;
     if (!item_of(d, c, x) || x >= d.nx) return;
-    double h[Q];
+    C h[Q];
     long long own;
-    const double ur = pull<PAR>(d, c, x, h, own);
+    const C ur = pull<T, C, PAR>(d, c, x, h, own);
     // moments of the deviations: drho, and j - (u_ref, 0, 0)
-    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         drho += h[q];
-        jx += EX[q] * h[q];
-        jy += EY[q] * h[q];
-        jz += EZ[q] * h[q];
+        jx += (C)EX[q] * h[q];
+        jy += (C)EY[q] * h[q];
+        jz += (C)EZ[q] * h[q];
     }
-    const double rho = 1.0 + drho;
-    // 1/rho: the FP32 hardware reciprocal and one Newton step (relative
-    // error ~1e-14; it only scales deviation-sized terms)
-    double ir = (double)__builtin_amdgcn_rcpf((float)rho);
-    ir = ir * (2.0 - rho * ir);
-    const double Fx = d.gx;
-    const double dux = (jx + 0.5 * Fx - drho * ur) * ir, duy = jy * ir, duz = jz * ir;
-    const double ux = ur + dux, uy = duy, uz = duz;
-    const double uu = ux * ux + uy * uy + uz * uz;
+    const C rho = C(1) + drho;
+    // 1/rho: the FP32 hardware reciprocal, refined by one Newton step in FP64
+    // (relative error ~1e-14; it only scales deviation-sized terms)
+    C ir = (C)__builtin_amdgcn_rcpf((float)rho);
+    if (sizeof(C) == 8) ir = ir * (C(2) - rho * ir);
+    const C Fx = (C)d.gx;
+    const C dux = (jx + C(0.5) * Fx - drho * ur) * ir, duy = jy * ir, duz = jz * ir;
+    const C ux = ur + dux, uy = duy, uz = duz;
+    const C uu = ux * ux + uy * uy + uz * uz;
     // Eq. (2) as a deviation from the reference, every term carrying drho or du:
     // h_eq - r = w [c0 + drho (3 eu + 4.5 eu^2) + 3 edu + 4.5 edu (eu + e.u_ref)]
-    const double c0 = drho * (1.0 - 1.5 * uu) - 1.5 * (dux * (ux + ur) + duy * uy + duz * uz);
-    const double om = d.omega, om1 = 1.0 - om, fc = d.fc;
-    const double fb = -3.0 * (ux * Fx);   // 3 (-u).F with F = (gx, 0, 0)
-    float *B = d.pop[PAR ^ 1];
-    B[own] = (float)(om1 * h[0] + om * wq(0) * c0 + fc * wq(0) * fb);
+    const C c0 = drho * (C(1) - C(1.5) * uu) - C(1.5) * (dux * (ux + ur) + duy * uy + duz * uz);
+    const C om = (C)d.omega, om1 = C(1) - om, fc = (C)d.fc;
+    const C fb = C(-3) * (ux * Fx);   // 3 (-u).F with F = (gx, 0, 0)
+    T *B = (T *)d.pop[PAR ^ 1];
+    st3(B + own, (float)(om1 * h[0] + om * (C)wq(0) * c0 + fc * (C)wq(0) * fb), d.scale);
     // opposite pairs (q, q + 1): even part S, odd part M, as in the 2D sweep
 #pragma unroll
     for (int q = 1; q < Q; q += 2) {
-        const double eu = EX[q] * ux + EY[q] * uy + EZ[q] * uz;
-        const double edu = EX[q] * dux + EY[q] * duy + EZ[q] * duz;
-        const double eF = EX[q] * Fx;
-        const double S = c0 + 4.5 * (drho * eu * eu + edu * (eu + EX[q] * ur));
-        const double A = 3.0 * (drho * eu + edu);
-        const double P = om * S + fc * (fb + 9.0 * eu * eF);
-        const double M = om * A + fc * (3.0 * eF);
-        B[q * d.qstride + own] = (float)(om1 * h[q] + wq(q) * (P + M));
-        B[(q + 1) * d.qstride + own] = (float)(om1 * h[q + 1] + wq(q) * (P - M));
+        const C eu = (C)EX[q] * ux + (C)EY[q] * uy + (C)EZ[q] * uz;
+        const C edu = (C)EX[q] * dux + (C)EY[q] * duy + (C)EZ[q] * duz;
+        const C eF = (C)EX[q] * Fx;
+        const C S = c0 + C(4.5) * (drho * eu * eu + edu * (eu + (C)EX[q] * ur));
+        const C A = C(3) * (drho * eu + edu);
+        const C P = om * S + fc * (fb + C(9) * eu * eF);
+        const C M = om * A + fc * (C(3) * eF);
+        st3(B + q * d.qstride + own, (float)(om1 * h[q] + (C)wq(q) * (P + M)), d.scale);
+        st3(B + (q + 1) * d.qstride + own, (float)(om1 * h[q + 1] + (C)wq(q) * (P - M)), d.scale);
     }
 }
 
 // Moments the next step starts from, FP64, into d.macro (fluid nodes).
-template <int PAR>
+template <typename T, int PAR>
 __global__ __launch_bounds__(64 * WAVES) void k3_macro(Dev3 d) {
     int c, x;
     if (!item_of(d, c, x) || x >= d.nx) return;
     double h[Q];
     long long own;
-    const double ur = pull<PAR>(d, c, x, h, own);
+    const double ur = pull<T, double, PAR>(d, c, x, h, own);
     double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     for (int q = 0; q < Q; q++) {
         drho += h[q];
@@ -164,16 +175,16 @@ __global__ __launch_bounds__(64 * WAVES) void k3_macro(Dev3 d) {
 
 // Per-workgroup FP64 sums of the stored populations: mass and momentum
 // (the reference's own momentum, (u_ref, 0, 0) per node, added exactly).
-template <int PAR>
+template <typename T, int PAR>
 __global__ __launch_bounds__(64 * WAVES) void k3_diag(Dev3 d) {
     __shared__ double s[WAVES][4];
     int c = 0, x = 0;
     double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
     if (item_of(d, c, x) && x < d.nx) {
         const long long own = (long long)d.crow[20 * c] * d.pitch + x;
-        const float *A = d.pop[PAR];
+        const T *A = (const T *)d.pop[PAR];
         for (int q = 0; q < Q; q++) {
-            const double v = A[q * d.qstride + own];
+            const double v = ld3(A + q * d.qstride + own, d.inv_scale);
             m += v;
             px += EX[q] * v;
             py += EY[q] * v;
@@ -206,7 +217,7 @@ using namespace tube3d;
 struct capib3d_ctx {
     capib3d_lattice lat{};
     hipStream_t stream = nullptr;
-    int pitch = 0, ncol = 0, nseg = 0, nblk = 0, par = 0;
+    int pitch = 0, ncol = 0, nseg = 0, nblk = 0, par = 0, esize = 4;
     long long step = 0;
     std::vector<int> crow;        // [ncol][20]
     std::vector<double> cK;       // [ncol][20]
@@ -298,10 +309,16 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     if (!(L.tau > 0.5) || !std::isfinite(L.gx)) return CAPIB_E_ARG;
     if (L.geometry < CAPIB3D_TUBE || L.geometry > CAPIB3D_BOX) return CAPIB_E_ARG;
     if (L.geometry == CAPIB3D_TUBE && !(L.radius > 0.0)) return CAPIB_E_ARG;
+    if (L.storage != CAPIB_FP32_SHIFTED && L.storage != CAPIB_FP16_SHIFTED) return CAPIB_E_ARG;
+    if (L.storage == CAPIB_FP16_SHIFTED) {
+        int ex = 0;
+        if (!(L.fp16_scale > 0.0) || std::frexp(L.fp16_scale, &ex) != 0.5) return CAPIB_E_ARG;   // a power of two
+    }
     capib3d_ctx *c = new capib3d_ctx();
     c->lat = L;
     c->stream = (hipStream_t)hip_stream;
     c->pitch = (L.nx + 63) / 64 * 64;
+    c->esize = L.storage == CAPIB_FP16_SHIFTED ? 2 : 4;
     c->nseg = c->pitch / 64;
     c->fluid.assign((size_t)L.ny * L.nz, 0);
     for (int z = 0; z < L.nz; z++)
@@ -315,7 +332,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->uref.assign((size_t)L.ny * L.nz, 0.0);
     const size_t N = (size_t)c->pitch * L.ny * L.nz;
     size_t o = 0;
-    for (int p = 0; p < 2; p++) { c->off_pop[p] = o; o = al256(o + (size_t)Q * N * 4); }
+    for (int p = 0; p < 2; p++) { c->off_pop[p] = o; o = al256(o + (size_t)Q * N * c->esize); }
     c->off_crow = o; o = al256(o + (size_t)c->ncol * 20 * 4);
     c->off_cK = o; o = al256(o + (size_t)c->ncol * 20 * 8);
     c->off_macro = o; o = al256(o + (size_t)4 * L.nx * L.ny * L.nz * 8);
@@ -354,7 +371,9 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.omega = 1.0 / L.tau;
     d.fc = 1.0 - 0.5 / L.tau;
     d.gx = L.gx;
-    for (int p = 0; p < 2; p++) d.pop[p] = (float *)(c->base + c->off_pop[p]);
+    d.scale = L.storage == CAPIB_FP16_SHIFTED ? (float)L.fp16_scale : 1.0f;
+    d.inv_scale = L.storage == CAPIB_FP16_SHIFTED ? (float)(1.0 / L.fp16_scale) : 1.0f;
+    for (int p = 0; p < 2; p++) d.pop[p] = c->base + c->off_pop[p];
     d.crow = (const int *)(c->base + c->off_crow);
     d.cK = (const double *)(c->base + c->off_cK);
     d.macro = (double *)(c->base + c->off_macro);
@@ -380,7 +399,8 @@ capib_status capib3d_init_flow(capib3d_ctx *c, const double *ux_of_yz) {
     }
     if ((s = upload_tables(c))) return s;
     const size_t N = (size_t)c->pitch * L.ny * L.nz;
-    for (int p = 0; p < 2; p++) HIP3(c, hipMemsetAsync(c->base + c->off_pop[p], 0, (size_t)Q * N * 4, c->stream));
+    for (int p = 0; p < 2; p++)
+        HIP3(c, hipMemsetAsync(c->base + c->off_pop[p], 0, (size_t)Q * N * c->esize, c->stream));
     HIP3(c, hipStreamSynchronize(c->stream));
     c->par = 0;
     c->step = 0;
@@ -391,11 +411,14 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     capib_status s = need_ws(c);
     if (s) return s;
     if (nsteps < 0) return fail3(c, CAPIB_E_ARG, "negative step count");
+    const bool h16 = c->lat.storage == CAPIB_FP16_SHIFTED;
     for (int t = 0; t < nsteps; t++) {
         if (c->par)
-            hipLaunchKernelGGL(k3_sweep<1>, dim3(c->nblk), dim3(64 * WAVES), 0, c->stream, c->d);
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1> : k3_sweep<float, 1>), dim3(c->nblk), dim3(64 * WAVES), 0,
+                               c->stream, c->d);
         else
-            hipLaunchKernelGGL(k3_sweep<0>, dim3(c->nblk), dim3(64 * WAVES), 0, c->stream, c->d);
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 0> : k3_sweep<float, 0>), dim3(c->nblk), dim3(64 * WAVES), 0,
+                               c->stream, c->d);
         HIP3(c, hipGetLastError());
         c->par ^= 1;
         c->step++;
@@ -409,10 +432,13 @@ capib_status capib3d_read_macro(capib3d_ctx *c, double *drho, double *ux, double
     const capib3d_lattice &L = c->lat;
     const size_t n = (size_t)L.nx * L.ny * L.nz;
     HIP3(c, hipMemsetAsync(c->base + c->off_macro, 0, 4 * n * 8, c->stream));
+    const bool h16 = c->lat.storage == CAPIB_FP16_SHIFTED;
     if (c->par)
-        hipLaunchKernelGGL(k3_macro<1>, dim3(c->nblk), dim3(64 * WAVES), 0, c->stream, c->d);
+        hipLaunchKernelGGL((h16 ? k3_macro<_Float16, 1> : k3_macro<float, 1>), dim3(c->nblk), dim3(64 * WAVES), 0,
+                           c->stream, c->d);
     else
-        hipLaunchKernelGGL(k3_macro<0>, dim3(c->nblk), dim3(64 * WAVES), 0, c->stream, c->d);
+        hipLaunchKernelGGL((h16 ? k3_macro<_Float16, 0> : k3_macro<float, 0>), dim3(c->nblk), dim3(64 * WAVES), 0,
+                           c->stream, c->d);
     HIP3(c, hipGetLastError());
     double *outs[4] = {drho, ux, uy, uz};
     for (int k = 0; k < 4; k++)
@@ -429,18 +455,23 @@ capib_status capib3d_read_populations(capib3d_ctx *c, double *out) {
     if (!out) return fail3(c, CAPIB_E_ARG, "null output");
     const capib3d_lattice &L = c->lat;
     const size_t N = (size_t)c->pitch * L.ny * L.nz, n = (size_t)L.nx * L.ny * L.nz;
-    std::vector<float> buf((size_t)Q * N);
-    HIP3(c, hipMemcpyAsync(buf.data(), c->base + c->off_pop[c->par], buf.size() * 4, hipMemcpyDeviceToHost,
-                           c->stream));
+    std::vector<unsigned char> raw((size_t)Q * N * c->esize);
+    HIP3(c, hipMemcpyAsync(raw.data(), c->base + c->off_pop[c->par], raw.size(), hipMemcpyDeviceToHost, c->stream));
     HIP3(c, hipStreamSynchronize(c->stream));
+    const bool h16 = c->lat.storage == CAPIB_FP16_SHIFTED;
+    const double inv = h16 ? 1.0 / c->lat.fp16_scale : 1.0;
     for (int q = 0; q < Q; q++)
         for (int z = 0; z < L.nz; z++)
             for (int y = 0; y < L.ny; y++) {
                 const size_t col = (size_t)z * L.ny + y;
                 const bool fl = c->fluid[col];
                 const double r = c->ref[col * Q + q];
-                for (int x = 0; x < L.nx; x++)
-                    out[q * n + col * L.nx + x] = fl ? (double)buf[q * N + col * c->pitch + x] + r : 0.0;
+                for (int x = 0; x < L.nx; x++) {
+                    const size_t k = q * N + col * c->pitch + x;
+                    const double sv = h16 ? (double)((const _Float16 *)raw.data())[k] * inv
+                                          : (double)((const float *)raw.data())[k];
+                    out[q * n + col * L.nx + x] = fl ? sv + r : 0.0;
+                }
             }
     return CAPIB_OK;
 }
@@ -451,7 +482,9 @@ capib_status capib3d_write_populations(capib3d_ctx *c, const double *in) {
     if (!in) return fail3(c, CAPIB_E_ARG, "null input");
     const capib3d_lattice &L = c->lat;
     const size_t N = (size_t)c->pitch * L.ny * L.nz, n = (size_t)L.nx * L.ny * L.nz;
-    std::vector<float> buf((size_t)Q * N, 0.0f);
+    const bool h16 = c->lat.storage == CAPIB_FP16_SHIFTED;
+    const double sc = h16 ? c->lat.fp16_scale : 1.0;
+    std::vector<unsigned char> raw((size_t)Q * N * c->esize, 0);
     for (int q = 0; q < Q; q++)
         for (int z = 0; z < L.nz; z++)
             for (int y = 0; y < L.ny; y++) {
@@ -461,11 +494,18 @@ capib_status capib3d_write_populations(capib3d_ctx *c, const double *in) {
                 for (int x = 0; x < L.nx; x++) {
                     const double v = in[q * n + col * L.nx + x];
                     if (!std::isfinite(v)) return fail3(c, CAPIB_E_ARG, "non-finite population");
-                    buf[q * N + col * c->pitch + x] = (float)(v - r);
+                    const size_t k = q * N + col * c->pitch + x;
+                    if (h16) {
+                        const double sv = (v - r) * sc;
+                        if (std::fabs(sv) > 65504.0)
+                            return fail3(c, CAPIB_E_ARG, "deviation %g overflows FP16 at scale %g", v - r, sc);
+                        ((_Float16 *)raw.data())[k] = (_Float16)(float)sv;
+                    } else {
+                        ((float *)raw.data())[k] = (float)(v - r);
+                    }
                 }
             }
-    HIP3(c, hipMemcpyAsync(c->base + c->off_pop[c->par], buf.data(), buf.size() * 4, hipMemcpyHostToDevice,
-                           c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_pop[c->par], raw.data(), raw.size(), hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipStreamSynchronize(c->stream));
     return CAPIB_OK;
 }
@@ -474,10 +514,13 @@ capib_status capib3d_diagnostics(capib3d_ctx *c, double *out4, int64_t *step) {
     capib_status s = need_ws(c);
     if (s) return s;
     if (!out4) return fail3(c, CAPIB_E_ARG, "null output");
+    const bool h16 = c->lat.storage == CAPIB_FP16_SHIFTED;
     if (c->par)
-        hipLaunchKernelGGL(k3_diag<1>, dim3(c->nblk), dim3(64 * WAVES), 0, c->stream, c->d);
+        hipLaunchKernelGGL((h16 ? k3_diag<_Float16, 1> : k3_diag<float, 1>), dim3(c->nblk), dim3(64 * WAVES), 0,
+                           c->stream, c->d);
     else
-        hipLaunchKernelGGL(k3_diag<0>, dim3(c->nblk), dim3(64 * WAVES), 0, c->stream, c->d);
+        hipLaunchKernelGGL((h16 ? k3_diag<_Float16, 0> : k3_diag<float, 0>), dim3(c->nblk), dim3(64 * WAVES), 0,
+                           c->stream, c->d);
     HIP3(c, hipGetLastError());
     std::vector<double> p((size_t)c->nblk * 4);
     HIP3(c, hipMemcpyAsync(p.data(), c->base + c->off_part, p.size() * 8, hipMemcpyDeviceToHost, c->stream));

@@ -18,7 +18,7 @@ _dp = C.POINTER(C.c_double)
 
 class capib3d_lattice(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
-                ("geometry", C.c_int32), ("radius", C.c_double)]
+                ("geometry", C.c_int32), ("radius", C.c_double), ("storage", C.c_int32), ("fp16_scale", C.c_double)]
 
 
 SIGNATURES = {
@@ -63,16 +63,24 @@ def hagen_poiseuille(ny, nz, radius, tau, gx):
     return np.where(r2 < radius * radius, gx / (4 * nu) * (radius * radius - r2), 0.0)
 
 
+def fp16_scale_for(umax, headroom=16.0):
+    """Power-of-two scale for FP16 storage of the deviations: the flow speed
+    maps to 65504 / headroom (as for the 2D lattice)."""
+    import math
+    return 2.0 ** math.floor(math.log2(65504.0 / (headroom * umax)))
+
+
 class Tube3D:
     """A D3Q19 tube on the GPU (workspace allocated with torch)."""
 
-    def __init__(self, nx, ny, nz, tau, gx, geometry=TUBE, radius=0.0, stream=None):
+    def __init__(self, nx, ny, nz, tau, gx, geometry=TUBE, radius=0.0, stream=None, storage=capib.FP32_SHIFTED,
+                 fp16_scale=1.0):
         import torch
         self.torch = torch
         self.L = _lib()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius)
+        lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius, storage, fp16_scale)
         self.ctx = _P()
         st = self.L.capib3d_create(C.byref(lat), _P(self.stream.cuda_stream), C.byref(self.ctx))
         if st != capib.CAPIB_OK:

@@ -15,7 +15,12 @@
  *   S1  pull streaming, periodic along x, halfway bounce-back on every link
  *       whose upstream node is solid                            (Eq. 1; walls as in 2D)
  *   S2  moments rho = sum f, rho u = sum f e + g/2               (Eqs. 5-6)
- *   S3  BGK collision towards the equilibrium with the Guo term  (Eqs. 1, 2, 4)
+ *   S3  with fixed immersed bodies (triangulated surfaces): the velocity u*
+ *       of S2 interpolated to every vertex with the cosine delta in 3D, the
+ *       direct forcing F = (U - u*) dV with U = 0, spread back with the same
+ *       delta                                                   (Sec. 2.2)
+ *   S4  BGK collision towards the equilibrium with the Guo term for the
+ *       total force g + f_ib, u = (sum f e + (g + f_ib)/2)/rho   (Eqs. 1, 2, 4-6)
  * Populations are stored shifted, h_i = f_i - w_i, as in the 2D oracle.
  *
  * Geometry (the fluid nodes; all others are solid and never updated):
@@ -23,6 +28,7 @@
  *   ORC3_SLAB  every node, walls beyond z = 0 and z = nz - 1, periodic in y
  *   ORC3_BOX   every node, periodic in all three directions
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <omp.h>
 #include <stdlib.h>
@@ -89,6 +95,10 @@ typedef struct {
     double *h;              /* streamed populations, same layout */
     long long step;
     int opp[19];            /* opposite direction of each velocity */
+    int nv;                 /* vertices of the fixed immersed bodies */
+    double *X;              /* [nv][3] positions */
+    double *dV;             /* [nv] volume weight: a third of the adjacent triangles' area (unit thickness) */
+    double *f;              /* [3][n] spread force of the current step */
 } orc3;
 
 static long long idx(const orc3 *s, int x, int y, int z) { return ((long long)z * s->ny + y) * s->nx + x; }
@@ -119,7 +129,54 @@ orc3 *orc3_create(int nx, int ny, int nz, double tau, double gx, int geom, doubl
 
 void orc3_destroy(orc3 *s) {
     if (!s) return;
-    free(s->fluid); free(s->A); free(s->h); free(s);
+    free(s->fluid); free(s->A); free(s->h); free(s->X); free(s->dV); free(s->f); free(s);
+}
+
+/* The 4-point cosine delta, phi(r) = (1 + cos(pi r / 2)) / 4 for |r| <= 2. */
+static double phi3(double r) {
+    r = fabs(r);
+    return r < 2.0 ? 0.25 * (1.0 + cos(M_PI * r / 2.0)) : 0.0;
+}
+
+/* The 4 x 4 x 4 stencil of a point: first node per axis (x wrapped later)
+ * and the tensor-product weights.                                           */
+static void stencil3(const double *X, int o[3], double w[3][4]) {
+    for (int a = 0; a < 3; a++) {
+        o[a] = (int)floor(X[a]) - 1;
+        for (int k = 0; k < 4; k++) w[a][k] = phi3(X[a] - (o[a] + k));
+    }
+}
+
+/* A fixed immersed body (the kind that does not move): nv vertices
+ * (xyz, [nv][3], lattice coordinates) and ntri triangles (tri, [ntri][3]
+ * vertex indices).  Every stencil node of every vertex must be fluid (the
+ * body is away from the walls); returns the index of its first vertex, or
+ * -1 if a stencil node is solid or outside the cross-section.             */
+int orc3_add_fixed_body(orc3 *s, int nv, const double *xyz, int ntri, const int *tri) {
+    for (int v = 0; v < nv; v++) {
+        int o[3];
+        double w[3][4];
+        stencil3(xyz + 3 * v, o, w);
+        if (o[1] < 0 || o[1] + 3 >= s->ny || o[2] < 0 || o[2] + 3 >= s->nz) return -1;
+        for (int b = 0; b < 4; b++)
+            for (int c = 0; c < 4; c++)
+                if (!is_fluid_yz(s, o[1] + b, o[2] + c)) return -1;
+    }
+    const int v0 = s->nv;
+    s->X = (double *)realloc(s->X, sizeof(double) * 3 * (s->nv + nv));
+    s->dV = (double *)realloc(s->dV, sizeof(double) * (s->nv + nv));
+    memcpy(s->X + 3 * v0, xyz, sizeof(double) * 3 * nv);
+    for (int v = 0; v < nv; v++) s->dV[v0 + v] = 0.0;
+    for (int t = 0; t < ntri; t++) {
+        const double *a = xyz + 3 * tri[3 * t], *b = xyz + 3 * tri[3 * t + 1], *c = xyz + 3 * tri[3 * t + 2];
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double area = 0.5 * sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        for (int k = 0; k < 3; k++) s->dV[v0 + tri[3 * t + k]] += area / 3.0;
+    }
+    s->nv += nv;
+    if (!s->f) s->f = (double *)calloc((size_t)(3 * s->n), sizeof(double));
+    return v0;
 }
 
 int orc3_is_fluid(const orc3 *s, int y, int z) { return s->fluid[z * s->ny + y]; }
@@ -180,7 +237,36 @@ static void moments3(const orc3 *s, long long k, double *drho, double u[3]) {
     u[0] = (jx + 0.5 * s->gx) / rho; u[1] = jy / rho; u[2] = jz / rho;
 }
 
-/* S3: A = h - (h - h_eq)/tau + F_i(u, g) */
+/* S3: u* at every vertex, F = (U - u*) dV with U = 0, spread into s->f */
+static void ib_force3(orc3 *s) {
+    const long long n = s->n;
+    memset(s->f, 0, sizeof(double) * 3 * n);
+    for (int v = 0; v < s->nv; v++) {
+        int o[3];
+        double w[3][4], us[3] = {0, 0, 0};
+        stencil3(s->X + 3 * v, o, w);
+        for (int c = 0; c < 4; c++)
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++) {
+                    const int x = ((o[0] + a) % s->nx + s->nx) % s->nx;
+                    const long long k = idx(s, x, o[1] + b, o[2] + c);
+                    double d, u[3];
+                    moments3(s, k, &d, u);
+                    const double W = w[0][a] * w[1][b] * w[2][c];
+                    for (int q = 0; q < 3; q++) us[q] += W * u[q];
+                }
+        for (int c = 0; c < 4; c++)
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++) {
+                    const int x = ((o[0] + a) % s->nx + s->nx) % s->nx;
+                    const long long k = idx(s, x, o[1] + b, o[2] + c);
+                    const double W = w[0][a] * w[1][b] * w[2][c];
+                    for (int q = 0; q < 3; q++) s->f[q * n + k] += W * (0.0 - us[q]) * s->dV[v];
+                }
+    }
+}
+
+/* S4: A = h - (h - h_eq)/tau + F_i(u, g + f_ib), u = (sum h e + (g + f_ib)/2)/rho */
 static void collide3(orc3 *s) {
     const long long n = s->n;
 #pragma omp parallel for schedule(static)
@@ -191,8 +277,14 @@ static void collide3(orc3 *s) {
                 const long long k = idx(s, x, y, z);
                 double drho, u[3], heq[19], F[19];
                 moments3(s, k, &drho, u);
+                double Fx = s->gx, Fy = 0.0, Fz = 0.0;
+                if (s->nv) {
+                    const double rho = 1.0 + drho;
+                    Fx += s->f[k]; Fy = s->f[n + k]; Fz = s->f[2 * n + k];
+                    u[0] += 0.5 * s->f[k] / rho; u[1] += 0.5 * Fy / rho; u[2] += 0.5 * Fz / rho;
+                }
                 orc3_heq(drho, u[0], u[1], u[2], heq);
-                orc3_guo(s->tau, u[0], u[1], u[2], s->gx, 0.0, 0.0, F);
+                orc3_guo(s->tau, u[0], u[1], u[2], Fx, Fy, Fz, F);
                 for (int i = 0; i < 19; i++) {
                     const double hv = s->h[i * n + k];
                     s->A[i * n + k] = hv - (hv - heq[i]) / s->tau + F[i];
@@ -204,6 +296,7 @@ static void collide3(orc3 *s) {
 void orc3_step(orc3 *s, int nsteps) {
     for (int t = 0; t < nsteps; t++) {
         stream3(s);
+        if (s->nv) ib_force3(s);
         collide3(s);
         s->step++;
     }
@@ -240,3 +333,12 @@ void orc3_totals(const orc3 *s, double *out4) {
         }
     out4[0] = m; out4[1] = px; out4[2] = py; out4[3] = pz;
 }
+
+/* The spread force of the last step at every node, [3][nz][ny][nx]. */
+void orc3_ib_force(const orc3 *s, double *out) {
+    if (s->f) memcpy(out, s->f, sizeof(double) * 3 * s->n);
+    else memset(out, 0, sizeof(double) * 3 * s->n);
+}
+
+/* The volume weight of every vertex, [nv]. */
+void orc3_vertex_weights(const orc3 *s, double *out) { if (s->nv) memcpy(out, s->dV, sizeof(double) * s->nv); }

@@ -39,6 +39,10 @@ def _L():
         L.orc3_lattice_tables.argtypes = [C.POINTER(C.c_int), _dp]
         L.orc3_heq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
         L.orc3_guo.argtypes = [C.c_double] + [C.c_double] * 6 + [_dp]
+        L.orc3_add_fixed_body.restype = C.c_int
+        L.orc3_add_fixed_body.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)]
+        L.orc3_ib_force.argtypes = [C.c_void_p, _dp]
+        L.orc3_vertex_weights.argtypes = [C.c_void_p, _dp]
         _ready = True
     return L
 
@@ -110,4 +114,24 @@ class Tube:
     def totals(self):
         out = np.zeros(4)
         self.L.orc3_totals(self.p, _d(out))
+        return out
+
+    def add_fixed_body(self, xyz, tri):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+        v0 = self.L.orc3_add_fixed_body(self.p, len(xyz), _d(xyz), len(tri),
+                                        tri.ctypes.data_as(C.POINTER(C.c_int)))
+        if v0 < 0:
+            raise ValueError("a stencil node of the body is solid or outside the cross-section")
+        self.nv = getattr(self, "nv", 0) + len(xyz)
+        return v0
+
+    def ib_force(self):
+        out = np.zeros((3, self.nz, self.ny, self.nx))
+        self.L.orc3_ib_force(self.p, _d(out))
+        return out
+
+    def vertex_weights(self):
+        out = np.zeros(getattr(self, "nv", 0))
+        self.L.orc3_vertex_weights(self.p, _d(out))
         return out

@@ -470,3 +470,36 @@ def tube3d_params(re=0.01, nx=256, diameter=64, tau=1.0):
     u_mean = re * nu / diameter
     g = 8.0 * nu * u_mean / (R * R)
     return dict(nx=nx, ny=diameter, nz=diameter, tau=tau, gx=g, radius=R, u_mean=u_mean)
+
+
+def icosphere(level, radius=1.0, center=(0.0, 0.0, 0.0), axes=(1.0, 1.0, 1.0)):
+    """A triangulated sphere: the icosahedron with every triangle split in
+    four `level` times, vertices pushed to the sphere, then scaled by axes
+    (an oblate body for axes like (1, 1, 0.5)) and placed at center.  Level
+    3: 642 vertices and 1280 triangles; level 4: 2562 and 5120.  Triangles
+    are counter-clockwise seen from outside.  Returns (xyz [nv][3], tri
+    [nt][3])."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    tris = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+            (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+            (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                mid[key] = len(verts) - 1
+            return mid[key]
+        new = []
+        for a, b, c in tris:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            new += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        tris = new
+    xyz = np.array(verts) * np.asarray(axes, dtype=np.float64) * radius + np.asarray(center, dtype=np.float64)
+    return xyz, np.array(tris, dtype=np.int32)

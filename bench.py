@@ -464,6 +464,26 @@ def tube3d_section(args):
             "roofline": {"bound": "hbm", "kernel": "k3_sweep", "achieved": round(gbs16, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs16 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": alg // 2,
                          "traffic": counters("k3_sweep_fp16_tube", TUBE3D_SOURCES)}}
+    # the same FP32 tube with a fixed 2562-vertex sphere of radius 10 on its axis
+    # (interpolation + direct forcing per vertex, spread gathered in the sweep)
+    xyz, tri = inputs.icosphere(4, 10.0, (0.5 * p["nx"], 0.5 * (p["ny"] - 1) + 0.2, 0.5 * (p["nz"] - 1) - 0.1))
+    gb = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"], max_vertices=len(xyz))
+    gb.init_flow(prof)
+    gb.add_fixed_body(xyz, tri)
+    gb.step(args.tube3d_warmup)
+    torch.cuda.synchronize()
+    e0.record(gb.stream)
+    gb.step(args.tube3d_steps)
+    e1.record(gb.stream)
+    e1.synchronize()
+    msb = e0.elapsed_time(e1) / args.tube3d_steps
+    drag = -gb.body_forces().sum(axis=0)
+    body = {"vertices": len(xyz), "triangles": len(tri), "ms_per_step": round(msb, 5),
+            "mlups": round(n / (msb * 1e-3) / 1e6, 1), "overhead_us_per_step": round((msb - ms) * 1e3, 2),
+            "drag_x_after_warmup_and_steps": float(drag[0]),
+            "note": "three launches per step: k3_node_u (velocity of the 7167 stencil nodes, a wave per slot), "
+                    "k3_vertex (a wave per vertex), k3_sweep_ib (slots gather their spread force, then the "
+                    "ordinary items)"}
     return {"workload": f"D3Q19 tube {p['nx']}x{p['ny']}x{p['nz']}, radius {p['radius']:g} ({n} fluid nodes), tau 1, "
                         f"Re 0.01 (g = {p['gx']:.4g}), halfway bounce-back walls; FP32 deviation storage, FP64 collision",
             "fluid_nodes": n, "steps": args.tube3d_steps, "ms_per_step": round(ms, 5),
@@ -473,7 +493,7 @@ def tube3d_section(args):
                          "algorithmic_bytes_per_launch": alg, "traffic": counters("k3_sweep_fp32_tube", TUBE3D_SOURCES),
                          "note": "one launch per step, timed back to back (launch gaps included); the 125 MB "
                                  "working set fits the 256 MB Infinity Cache"},
-            "fp16_storage": fp16}
+            "fp16_storage": fp16, "fixed_body": body}
 
 
 def capib_fp16():

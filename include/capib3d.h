@@ -5,8 +5,12 @@
  * next step: the BGK update of Eq. (1) with the equilibrium of Eq. (2), the
  * Guo term of Eq. (4) and the moments of Eqs. (5)-(6) on the D3Q19 velocity
  * set, in a capillary tube with no-slip walls (halfway bounce-back, as the
- * 2D channel's walls), driven by a uniform body force along the tube.
- * Immersed membranes in 3D are not part of this library.
+ * 2D channel's walls), driven by a uniform body force along the tube; and
+ * fixed immersed bodies (triangulated surfaces that do not move) coupled as
+ * in Sec. 2.2: the fluid velocity interpolated to every vertex with the
+ * 4-point cosine delta in 3D, the direct force (U - u*) dV with U = 0,
+ * spread back with the same delta.  Deformable membranes in 3D are not part
+ * of this library.
  *
  * Conventions
  *   - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3.
@@ -51,7 +55,8 @@ enum { CAPIB3D_TUBE = 0, CAPIB3D_SLAB = 1, CAPIB3D_BOX = 2 };
  *   geometry    CAPIB3D_TUBE, CAPIB3D_SLAB or CAPIB3D_BOX
  *   radius      tube radius in nodes (CAPIB3D_TUBE only, > 0)
  *   storage     CAPIB_FP32_SHIFTED or CAPIB_FP16_SHIFTED
- *   fp16_scale  power of two multiplying stored FP16 deviations (FP16 only) */
+ *   fp16_scale  power of two multiplying stored FP16 deviations (FP16 only)
+ *   max_vertices  capacity for the vertices of fixed bodies (0: none)     */
 typedef struct {
     int32_t nx, ny, nz;
     double tau, gx;
@@ -59,6 +64,7 @@ typedef struct {
     double radius;
     int32_t storage;
     double fp16_scale;
+    int32_t max_vertices;
 } capib3d_lattice;
 
 typedef struct capib3d_ctx capib3d_ctx;
@@ -78,9 +84,39 @@ capib_status capib3d_bind_workspace(capib3d_ctx *ctx, void *device_ptr, size_t b
  * (ux_of_yz [nz][ny] host doubles, NULL = rest).  Syncs.                  */
 capib_status capib3d_init_flow(capib3d_ctx *ctx, const double *ux_of_yz);
 
+/* A fixed immersed body (Sec. 2.2 read in 3D; the body does not move): nv
+ * vertices (xyz, [nv][3] host doubles, lattice coordinates: x along the
+ * tube, wrapped periodically) and ntri triangles (tri, [ntri][3] vertex
+ * indices).  Each vertex carries a third of the area of its triangles (unit
+ * thickness) as its volume weight.  Every node of every vertex's 4 x 4 x 4
+ * stencil must be a fluid node inside the cross-section (CAPIB_E_ARG
+ * otherwise); more than max_vertices vertices in all gives
+ * CAPIB_E_CAPACITY.  *first_vertex (may be NULL) receives the index of its
+ * first vertex.  Syncs. */
+capib_status capib3d_add_fixed_body(capib3d_ctx *ctx, int32_t nv, const double *xyz, int32_t ntri,
+                                    const int32_t *tri, int32_t *first_vertex);
+
+/* The force of the last step on the fluid at every vertex of the fixed
+ * bodies, F = (U - u*) dV with U = 0, [vertices][3] host doubles in the
+ * order the bodies were added; minus their sum is the hydrodynamic force on
+ * the bodies (the spread weights of a vertex sum to one).  Syncs. */
+capib_status capib3d_body_forces(capib3d_ctx *ctx, double *out);
+/* Vertices of the fixed bodies added so far. */
+int32_t capib3d_vertices(const capib3d_ctx *ctx);
+
+/* Schedule of a step with fixed bodies (three launches: the velocity at
+ * every stencil node, the force at every vertex, the collision of the
+ * stencil nodes): the shares, in percent of the work items, of the ordinary
+ * sweep done in the first and in the second launch (defaults 0 and 0); the
+ * rest is done in the third.  Any shares give the same result, bit for bit.
+ * CAPIB_E_ARG if either is negative or their sum exceeds 100. */
+capib_status capib3d_set_ib_schedule(capib3d_ctx *ctx, int32_t share_node_u, int32_t share_vertex);
+
 /* nsteps steps of Eq. (1): pull streaming with bounce-back, moments of
- * Eqs. (5)-(6) with half the body force, BGK collision with the Guo term
- * of Eq. (4).  Enqueued on the context's stream; does not sync. */
+ * Eqs. (5)-(6) with half the total force, BGK collision with the Guo term
+ * of Eq. (4) for the body force plus the spread force of the fixed bodies
+ * (interpolated, forced and spread from the streamed moments at the start
+ * of the step).  Enqueued on the context's stream; does not sync. */
 capib_status capib3d_step(capib3d_ctx *ctx, int32_t nsteps);
 
 /* The moments the next step starts from (Eqs. 5-6 of the streamed

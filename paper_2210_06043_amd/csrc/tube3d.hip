@@ -17,8 +17,23 @@
 // that a contiguous range of items (one XCD's share of the workgroups) holds
 // every segment of a run of neighbouring columns and their shifted pulls
 // share its L2.
+//
+// Fixed immersed bodies (Sec. 2.2 in 3D, bodies that do not move).  Their
+// stencils and weights never change, so the host lays the coupling out once:
+// the slots (work items holding stencil nodes), per vertex the slot lane of
+// each of its 64 stencil nodes and their weights, and per stencil node a
+// contiguous range of the spread contributions W (-u*) dV that reach it, in
+// vertex order.  A node lies in the stencils of some twenty vertices, so its
+// velocity is computed once.  A step is three launches: k3_node_u (a wave
+// per slot: the velocity of every stencil node), k3_vertex (a wave per
+// vertex, a lane per stencil node: weighted wave sum to u*, and each lane's
+// contribution stored at its node's place), k3_sweep_ib (a wave per slot:
+// each lane sums its node's contributions in vertex order, no atomics, the
+// same order on every run, and collides; then the ordinary items).  The
+// first two may also take shares of the ordinary items (a schedule knob).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -50,6 +65,19 @@ struct Dev3 {
     const double *cK;           // [ncol][20]: deviation constant of each q, then u_ref
     double *macro;              // [4][nz][ny][nx]
     double *part;               // [nblocks][4] partial sums
+    // fixed immersed bodies
+    int nv, nslot;              // vertices; work items holding stencil nodes
+    const int *vnode;           // [nv][64] stencil node of each lane: slot * 64 + x % 64
+    const double *vW;           // [nv][64] its weight phi phi phi
+    const double *vdV;          // [nv] volume weight
+    const int *vpos;            // [nv][64] place of the lane's contribution in the ranges
+    double *vF;                 // [nv][3] -u* of the current step
+    double *contrib;            // [nv * 64][3] spread contributions, grouped by node
+    double *unode;              // [3][ucap] velocity of every stencil node (slot * 64 + lane)
+    long long ucap;
+    const int *islot;           // [ncol * nseg] slot of a work item holding stencil nodes, -1 none
+    const int *fitem;           // [nslot] work item of each slot
+    const int *sbeg;            // [nslot][65] per lane, first contribution of its node
 };
 
 // Workgroup b -> work item such that each XCD (workgroups dealt round-robin
@@ -68,14 +96,18 @@ __device__ __forceinline__ void st3(float *p, float v, float) { *p = v; }
 __device__ __forceinline__ void st3(_Float16 *p, float v, float sc) { *p = (_Float16)(v * sc); }
 
 // The wave's work item: its column c and x of this lane; false past the end.
-__device__ __forceinline__ bool item_of(const Dev3 &d, int &c, int &x) {
+__device__ __forceinline__ bool item_of(const Dev3 &d, int &c, int &x, int &item) {
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int item = __builtin_amdgcn_readfirstlane(b * WAVES + (int)(threadIdx.x >> 6));
+    item = __builtin_amdgcn_readfirstlane(b * WAVES + (int)(threadIdx.x >> 6));
     if (item >= d.ncol * d.nseg) return false;
     c = item / d.nseg;
     const int seg = item - c * d.nseg;
     x = seg * 64 + (int)(threadIdx.x & 63);
     return true;
+}
+__device__ __forceinline__ bool item_of(const Dev3 &d, int &c, int &x) {
+    int item;
+    return item_of(d, c, x, item);
 }
 
 // Pulled populations of node x of column c as deviations from its column's
@@ -102,14 +134,31 @@ __device__ __forceinline__ C pull(const Dev3 &d, int c, int x, C dh[Q], long lon
     return (C)K[19];
 }
 
-template <typename T, int PAR>
-__global__ __launch_bounds__(64 * WAVES) void k3_sweep(Dev3 d) {
+// One work item (wave-uniform): pull, moments, BGK collision with the Guo
+// term for the body force plus, on a slot (an item holding stencil nodes of
+// the fixed bodies), the spread force of each lane's node.
+template <typename T, int PAR, bool IB>
+__device__ __forceinline__ void sweep_item(const Dev3 &d, int item, int slot) {
     using C = typename Arith3<T>::type;
-    int c, x;
-    if (!item_of(d, c, x) || x >= d.nx) return;
+    const int c = item / d.nseg;
+    const int x = (item - c * d.nseg) * 64 + (int)(threadIdx.x & 63);
+    if (x >= d.nx) return;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (IB) {
+        const int *sb = d.sbeg + 65 * slot + (threadIdx.x & 63);
+        const int k1 = sb[1];
+#pragma unroll 4
+        for (int k = sb[0]; k < k1; k++) {
+            const double *p = d.contrib + 3 * (long long)k;
+            fx += p[0];
+            fy += p[1];
+            fz += p[2];
+        }
+    }
     C h[Q];
     long long own;
     const C ur = pull<T, C, PAR>(d, c, x, h, own);
+    const C Fx = (C)d.gx + (C)fx, Fy = (C)fy, Fz = (C)fz;
     // moments of the deviations: drho, and j - (u_ref, 0, 0)
     C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -124,15 +173,14 @@ __global__ __launch_bounds__(64 * WAVES) void k3_sweep(Dev3 d) {
     // (relative error ~1e-14; it only scales deviation-sized terms)
     C ir = (C)__builtin_amdgcn_rcpf((float)rho);
     if (sizeof(C) == 8) ir = ir * (C(2) - rho * ir);
-    const C Fx = (C)d.gx;
-    const C dux = (jx + C(0.5) * Fx - drho * ur) * ir, duy = jy * ir, duz = jz * ir;
+    const C dux = (jx + C(0.5) * Fx - drho * ur) * ir, duy = (jy + C(0.5) * Fy) * ir, duz = (jz + C(0.5) * Fz) * ir;
     const C ux = ur + dux, uy = duy, uz = duz;
     const C uu = ux * ux + uy * uy + uz * uz;
     // Eq. (2) as a deviation from the reference, every term carrying drho or du:
     // h_eq - r = w [c0 + drho (3 eu + 4.5 eu^2) + 3 edu + 4.5 edu (eu + e.u_ref)]
     const C c0 = drho * (C(1) - C(1.5) * uu) - C(1.5) * (dux * (ux + ur) + duy * uy + duz * uz);
     const C om = (C)d.omega, om1 = C(1) - om, fc = (C)d.fc;
-    const C fb = C(-3) * (ux * Fx);   // 3 (-u).F with F = (gx, 0, 0)
+    const C fb = C(-3) * (ux * Fx + uy * Fy + uz * Fz);   // 3 (-u).F
     T *B = (T *)d.pop[PAR ^ 1];
     st3(B + own, (float)(om1 * h[0] + om * (C)wq(0) * c0 + fc * (C)wq(0) * fb), d.scale);
     // opposite pairs (q, q + 1): even part S, odd part M, as in the 2D sweep
@@ -140,7 +188,7 @@ __global__ __launch_bounds__(64 * WAVES) void k3_sweep(Dev3 d) {
     for (int q = 1; q < Q; q += 2) {
         const C eu = (C)EX[q] * ux + (C)EY[q] * uy + (C)EZ[q] * uz;
         const C edu = (C)EX[q] * dux + (C)EY[q] * duy + (C)EZ[q] * duz;
-        const C eF = (C)EX[q] * Fx;
+        const C eF = (C)EX[q] * Fx + (C)EY[q] * Fy + (C)EZ[q] * Fz;
         const C S = c0 + C(4.5) * (drho * eu * eu + edu * (eu + (C)EX[q] * ur));
         const C A = C(3) * (drho * eu + edu);
         const C P = om * S + fc * (fb + C(9) * eu * eF);
@@ -148,6 +196,101 @@ __global__ __launch_bounds__(64 * WAVES) void k3_sweep(Dev3 d) {
         st3(B + q * d.qstride + own, (float)(om1 * h[q] + (C)wq(q) * (P + M)), d.scale);
         st3(B + (q + 1) * d.qstride + own, (float)(om1 * h[q + 1] + (C)wq(q) * (P - M)), d.scale);
     }
+}
+
+
+template <typename T, int PAR>
+__global__ __launch_bounds__(64 * WAVES) void k3_sweep(Dev3 d) {
+    int c, x, item;
+    if (!item_of(d, c, x, item)) return;
+    sweep_item<T, PAR, false>(d, item, -1);
+}
+
+// The ordinary part of a launch with fixed bodies: workgroups from nfront on
+// (nfront a multiple of 8, so each keeps its XCD) sweep the items [lo, hi)
+// that hold no stencil node.
+template <typename T, int PAR>
+__device__ __forceinline__ void sweep_share(const Dev3 &d, int nfront, int lo, int hi) {
+    const int b = xcd_block((int)blockIdx.x - nfront, (int)gridDim.x - nfront);
+    const int item = __builtin_amdgcn_readfirstlane(lo + b * WAVES + (int)(threadIdx.x >> 6));
+    if (item >= hi || d.islot[item] >= 0) return;
+    sweep_item<T, PAR, false>(d, item, -1);
+}
+
+// First launch of a step with fixed bodies: workgroups [0, nfb) give every
+// slot a wave that stores the velocity of the streamed populations with half
+// the body force (FP64) at its nodes; the rest sweep the items [0, s1).
+template <typename T, int PAR>
+__global__ __launch_bounds__(64 * WAVES) void k3_node_u(Dev3 d, int nfb, int s1) {
+    if ((int)blockIdx.x >= nfb) {
+        sweep_share<T, PAR>(d, nfb, 0, s1);
+        return;
+    }
+    const int slot = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6));
+    if (slot >= d.nslot) return;
+    const int item = d.fitem[slot], c = item / d.nseg, lane = (int)(threadIdx.x & 63);
+    const int x = (item - c * d.nseg) * 64 + lane;
+    if (x >= d.nx) return;
+    double h[Q];
+    long long own;
+    const double ur = pull<T, double, PAR>(d, c, x, h, own);
+    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int q = 0; q < Q; q++) {
+        drho += h[q];
+        jx += EX[q] * h[q];
+        jy += EY[q] * h[q];
+        jz += EZ[q] * h[q];
+    }
+    const double rho = 1.0 + drho;
+    const long long k = 64LL * slot + lane;
+    d.unode[k] = ur + (jx + 0.5 * d.gx - drho * ur) / rho;
+    d.unode[d.ucap + k] = jy / rho;
+    d.unode[2 * d.ucap + k] = jz / rho;
+}
+
+// Second launch: workgroups [0, nvb) give every vertex a wave, a lane per
+// stencil node: u* is the weighted wave sum of the nodes' velocities; stores
+// -u* and each lane's contribution W (-u*) dV.  The rest sweep [s1, s2).
+template <typename T, int PAR>
+__global__ __launch_bounds__(64 * WAVES) void k3_vertex(Dev3 d, int nvb, int s1, int s2) {
+    if ((int)blockIdx.x >= nvb) {
+        sweep_share<T, PAR>(d, nvb, s1, s2);
+        return;
+    }
+    const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
+    if (v >= d.nv) return;
+    const int l = 64 * v + (int)(threadIdx.x & 63);
+    const long long k = d.vnode[l];
+    const double W = d.vW[l];
+    double ux = W * d.unode[k], uy = W * d.unode[d.ucap + k], uz = W * d.unode[2 * d.ucap + k];
+    for (int o = 32; o >= 1; o >>= 1) {
+        ux += __shfl_xor(ux, o);
+        uy += __shfl_xor(uy, o);
+        uz += __shfl_xor(uz, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        d.vF[3 * v] = -ux;
+        d.vF[3 * v + 1] = -uy;
+        d.vF[3 * v + 2] = -uz;
+    }
+    const double dV = d.vdV[v];
+    double *p = d.contrib + 3 * (long long)d.vpos[l];
+    p[0] = W * -ux * dV;
+    p[1] = W * -uy * dV;
+    p[2] = W * -uz * dV;
+}
+
+// Third launch: workgroups [0, nfb) sweep the slots with their spread force,
+// the rest the items [s2, ncol * nseg).
+template <typename T, int PAR>
+__global__ __launch_bounds__(64 * WAVES) void k3_sweep_ib(Dev3 d, int nfb, int s2) {
+    if ((int)blockIdx.x >= nfb) {
+        sweep_share<T, PAR>(d, nfb, s2, d.ncol * d.nseg);
+        return;
+    }
+    const int slot = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6));
+    if (slot >= d.nslot) return;
+    sweep_item<T, PAR, true>(d, d.fitem[slot], slot);
 }
 
 // Moments the next step starts from, FP64, into d.macro (fluid nodes).
@@ -224,8 +367,15 @@ struct capib3d_ctx {
     std::vector<double> ref;      // [nz][ny][19]: r_q(y, z) of the reference profile
     std::vector<double> uref;     // [nz][ny]
     std::vector<unsigned char> fluid;   // [nz][ny]
+    std::vector<int> colof;             // [nz][ny]: column index of a fluid row, -1 solid
+    // fixed immersed bodies, host copies of the device maps
+    int nv = 0, nslot = 0, nslot_max = 0, share_u = 0, share_v = 0;
+    std::vector<int> vcol, vxs;         // [nv][64]
+    std::vector<double> vW, vdV;        // [nv][64], [nv]
     char *base = nullptr;
     size_t off_pop[2]{}, off_crow = 0, off_cK = 0, off_macro = 0, off_part = 0, ws = 0;
+    size_t off_vnode = 0, off_vW = 0, off_vdV = 0, off_vpos = 0, off_vF = 0, off_contrib = 0, off_unode = 0,
+           off_islot = 0, off_fitem = 0, off_sbeg = 0;
     Dev3 d{};
     std::string err = "no error";
 };
@@ -314,6 +464,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
         int ex = 0;
         if (!(L.fp16_scale > 0.0) || std::frexp(L.fp16_scale, &ex) != 0.5) return CAPIB_E_ARG;   // a power of two
     }
+    if (L.max_vertices < 0 || L.max_vertices > (1 << 24)) return CAPIB_E_ARG;
     capib3d_ctx *c = new capib3d_ctx();
     c->lat = L;
     c->stream = (hipStream_t)hip_stream;
@@ -323,7 +474,9 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->fluid.assign((size_t)L.ny * L.nz, 0);
     for (int z = 0; z < L.nz; z++)
         for (int y = 0; y < L.ny; y++) c->fluid[(size_t)z * L.ny + y] = fluid_yz(L, y, z) ? 1 : 0;
-    for (unsigned char f : c->fluid) c->ncol += f;
+    c->colof.assign((size_t)L.ny * L.nz, -1);
+    for (size_t k = 0; k < c->fluid.size(); k++)
+        if (c->fluid[k]) c->colof[k] = c->ncol++;
     if (c->ncol == 0) {
         delete c;
         return CAPIB_E_ARG;
@@ -337,6 +490,18 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_cK = o; o = al256(o + (size_t)c->ncol * 20 * 8);
     c->off_macro = o; o = al256(o + (size_t)4 * L.nx * L.ny * L.nz * 8);
     c->off_part = o; o = al256(o + (size_t)c->nblk * 4 * 8);
+    const size_t M = (size_t)L.max_vertices, nitem = (size_t)c->ncol * c->nseg;
+    c->nslot_max = (int)std::min(nitem, 64 * M);
+    c->off_vnode = o; o = al256(o + M * 64 * 4);
+    c->off_vW = o; o = al256(o + M * 64 * 8);
+    c->off_vdV = o; o = al256(o + M * 8);
+    c->off_vpos = o; o = al256(o + M * 64 * 4);
+    c->off_vF = o; o = al256(o + M * 3 * 8);
+    c->off_contrib = o; o = al256(o + M * 64 * 3 * 8);
+    c->off_unode = o; o = al256(o + (size_t)c->nslot_max * 64 * 3 * 8);
+    c->off_islot = o; o = al256(o + (M ? nitem * 4 : 0));
+    c->off_fitem = o; o = al256(o + (size_t)c->nslot_max * 4);
+    c->off_sbeg = o; o = al256(o + (size_t)c->nslot_max * 65 * 4);
     c->ws = o;
     *out = c;
     return CAPIB_OK;
@@ -378,6 +543,22 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.cK = (const double *)(c->base + c->off_cK);
     d.macro = (double *)(c->base + c->off_macro);
     d.part = (double *)(c->base + c->off_part);
+    d.nv = 0;
+    d.nslot = 0;
+    d.vnode = (const int *)(c->base + c->off_vnode);
+    d.vW = (const double *)(c->base + c->off_vW);
+    d.vdV = (const double *)(c->base + c->off_vdV);
+    d.vpos = (const int *)(c->base + c->off_vpos);
+    d.vF = (double *)(c->base + c->off_vF);
+    d.contrib = (double *)(c->base + c->off_contrib);
+    d.unode = (double *)(c->base + c->off_unode);
+    d.ucap = (long long)c->nslot_max * 64;
+    d.islot = (const int *)(c->base + c->off_islot);
+    d.fitem = (const int *)(c->base + c->off_fitem);
+    d.sbeg = (const int *)(c->base + c->off_sbeg);
+    c->nv = 0;
+    c->nslot = 0;
+    c->vcol.clear(); c->vxs.clear(); c->vW.clear(); c->vdV.clear();
     HIP3(c, hipMemsetAsync(c->base, 0, c->ws, c->stream));
     return upload_tables(c);
 }
@@ -411,14 +592,36 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     capib_status s = need_ws(c);
     if (s) return s;
     if (nsteps < 0) return fail3(c, CAPIB_E_ARG, "negative step count");
-    const bool h16 = c->lat.storage == CAPIB_FP16_SHIFTED;
+    const bool h16 = c->lat.storage == CAPIB_FP16_SHIFTED, ib = c->nv > 0;
+    const dim3 blk(64 * WAVES);
+    // with bodies: vertex workgroups and slot workgroups rounded up to a
+    // multiple of 8, so the sweep workgroups after them keep their XCD; the
+    // ordinary items split in three shares
+    const int nitem = c->ncol * c->nseg;
+    const int s1 = (int)((long long)nitem * c->share_u / 100), s2 = (int)((long long)nitem * (c->share_u + c->share_v) / 100);
+    const int nvb = ((c->nv + WAVES - 1) / WAVES + 7) / 8 * 8, nfb = ((c->nslot + WAVES - 1) / WAVES + 7) / 8 * 8;
+    const dim3 g1(nfb + (s1 + WAVES - 1) / WAVES), g2(nvb + (s2 - s1 + WAVES - 1) / WAVES),
+        g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
     for (int t = 0; t < nsteps; t++) {
-        if (c->par)
-            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1> : k3_sweep<float, 1>), dim3(c->nblk), dim3(64 * WAVES), 0,
-                               c->stream, c->d);
-        else
-            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 0> : k3_sweep<float, 0>), dim3(c->nblk), dim3(64 * WAVES), 0,
-                               c->stream, c->d);
+        if (ib && c->par) {
+            hipLaunchKernelGGL((h16 ? k3_node_u<_Float16, 1> : k3_node_u<float, 1>), g1, blk, 0, c->stream, c->d, nfb, s1);
+            hipLaunchKernelGGL((h16 ? k3_vertex<_Float16, 1> : k3_vertex<float, 1>), g2, blk, 0, c->stream, c->d, nvb, s1,
+                               s2);
+            hipLaunchKernelGGL((h16 ? k3_sweep_ib<_Float16, 1> : k3_sweep_ib<float, 1>), g3, blk, 0, c->stream, c->d, nfb,
+                               s2);
+        } else if (ib) {
+            hipLaunchKernelGGL((h16 ? k3_node_u<_Float16, 0> : k3_node_u<float, 0>), g1, blk, 0, c->stream, c->d, nfb, s1);
+            hipLaunchKernelGGL((h16 ? k3_vertex<_Float16, 0> : k3_vertex<float, 0>), g2, blk, 0, c->stream, c->d, nvb, s1,
+                               s2);
+            hipLaunchKernelGGL((h16 ? k3_sweep_ib<_Float16, 0> : k3_sweep_ib<float, 0>), g3, blk, 0, c->stream, c->d, nfb,
+                               s2);
+        } else if (c->par) {
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1> : k3_sweep<float, 1>), dim3(c->nblk), blk, 0, c->stream,
+                               c->d);
+        } else {
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 0> : k3_sweep<float, 0>), dim3(c->nblk), blk, 0, c->stream,
+                               c->d);
+        }
         HIP3(c, hipGetLastError());
         c->par ^= 1;
         c->step++;
@@ -507,6 +710,142 @@ capib_status capib3d_write_populations(capib3d_ctx *c, const double *in) {
             }
     HIP3(c, hipMemcpyAsync(c->base + c->off_pop[c->par], raw.data(), raw.size(), hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipStreamSynchronize(c->stream));
+    return CAPIB_OK;
+}
+
+// The contributions of every stencil node of every vertex, grouped by node
+// with the vertices in ascending order (each lane's place in that order, the
+// ranges per lane of a slot, the slot of every item); uploads the maps.
+static capib_status upload_bodies(capib3d_ctx *c, int v0) {
+    const size_t nitem = (size_t)c->ncol * c->nseg, ne = (size_t)c->nv * 64;
+    std::vector<long long> node(ne);
+    std::vector<int> order(ne);
+    for (size_t k = 0; k < ne; k++) {
+        node[k] = (long long)c->vcol[k] * c->pitch + c->vxs[k];
+        order[k] = (int)k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return node[a] < node[b]; });
+    std::vector<int> vpos(ne), vnode(ne), islot(nitem, -1), fitem, sbeg;
+    for (size_t j = 0; j < ne; j++) vpos[order[j]] = (int)j;
+    for (size_t k = 0; k < ne;) {
+        const long long item = node[order[k]] / 64;   // column * nseg + x / 64: the pitch is nseg * 64
+        const int slot = (int)fitem.size();
+        if (slot >= c->nslot_max) return fail3(c, CAPIB_E_CAPACITY, "stencil slots exhausted");
+        islot[item] = slot;
+        fitem.push_back((int)item);
+        sbeg.resize(sbeg.size() + 65);
+        int *sb = &sbeg[65 * (size_t)slot];
+        size_t j = k;
+        for (int l = 0; l < 64; l++) {
+            sb[l] = (int)j;
+            while (j < ne && node[order[j]] == item * 64 + l) j++;
+        }
+        sb[64] = (int)j;
+        k = j;
+    }
+    for (size_t k = 0; k < ne; k++) vnode[k] = islot[node[k] / 64] * 64 + (int)(node[k] % 64);
+    const size_t nv = c->nv, a = (size_t)v0;
+    HIP3(c, hipMemcpyAsync(c->base + c->off_vnode, vnode.data(), ne * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_vW + a * 512, &c->vW[a * 64], (nv - a) * 512, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_vdV + a * 8, &c->vdV[a], (nv - a) * 8, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_vpos, vpos.data(), ne * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_islot, islot.data(), nitem * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_fitem, fitem.data(), fitem.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_sbeg, sbeg.data(), sbeg.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    c->nslot = (int)fitem.size();
+    return CAPIB_OK;
+}
+
+static double phi3(double r) {
+    r = std::fabs(r);
+    return r < 2.0 ? 0.25 * (1.0 + std::cos(M_PI * r / 2.0)) : 0.0;
+}
+
+capib_status capib3d_add_fixed_body(capib3d_ctx *c, int32_t nv, const double *xyz, int32_t ntri, const int32_t *tri,
+                                    int32_t *first_vertex) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    const capib3d_lattice &L = c->lat;
+    if (nv < 1 || ntri < 0 || !xyz || (ntri > 0 && !tri)) return fail3(c, CAPIB_E_ARG, "bad body arrays");
+    if ((long long)c->nv + nv > L.max_vertices)
+        return fail3(c, CAPIB_E_CAPACITY, "%d + %d vertices exceed the capacity of %d", c->nv, nv, L.max_vertices);
+    for (int k = 0; k < 3 * ntri; k++)
+        if (tri[k] < 0 || tri[k] >= nv) return fail3(c, CAPIB_E_ARG, "triangle vertex %d out of range", tri[k]);
+    std::vector<int> vcol((size_t)nv * 64), vxs((size_t)nv * 64);
+    std::vector<double> vW((size_t)nv * 64), vdV(nv, 0.0);
+    for (int v = 0; v < nv; v++) {
+        const double *X = xyz + 3 * v;
+        if (!std::isfinite(X[0]) || !std::isfinite(X[1]) || !std::isfinite(X[2]) || std::fabs(X[0]) > 1e9)
+            return fail3(c, CAPIB_E_ARG, "vertex %d not finite", v);
+        int o[3];
+        double w[3][4];
+        for (int a = 0; a < 3; a++) {
+            o[a] = (int)std::floor(X[a]) - 1;
+            for (int k = 0; k < 4; k++) w[a][k] = phi3(X[a] - (o[a] + k));
+        }
+        if (o[1] < 0 || o[1] + 3 >= L.ny || o[2] < 0 || o[2] + 3 >= L.nz)
+            return fail3(c, CAPIB_E_ARG, "vertex %d: stencil outside the cross-section", v);
+        for (int zc = 0; zc < 4; zc++)
+            for (int yb = 0; yb < 4; yb++) {
+                const int col = c->colof[(size_t)(o[2] + zc) * L.ny + o[1] + yb];
+                if (col < 0) return fail3(c, CAPIB_E_ARG, "vertex %d: stencil node on a solid column", v);
+                for (int xa = 0; xa < 4; xa++) {
+                    const int l = xa + 4 * yb + 16 * zc;
+                    vcol[64 * (size_t)v + l] = col;
+                    vxs[64 * (size_t)v + l] = (int)((((long long)o[0] + xa) % L.nx + L.nx) % L.nx);
+                    vW[64 * (size_t)v + l] = w[0][xa] * w[1][yb] * w[2][zc];
+                }
+            }
+    }
+    // a third of the area of every triangle to each of its vertices
+    for (int t = 0; t < ntri; t++) {
+        const double *a = xyz + 3 * tri[3 * t], *b = xyz + 3 * tri[3 * t + 1], *e = xyz + 3 * tri[3 * t + 2];
+        const double p[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, r[3] = {e[0] - a[0], e[1] - a[1], e[2] - a[2]};
+        const double n[3] = {p[1] * r[2] - p[2] * r[1], p[2] * r[0] - p[0] * r[2], p[0] * r[1] - p[1] * r[0]};
+        const double area = 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; k++) vdV[tri[3 * t + k]] += area / 3.0;
+    }
+    const int v0 = c->nv;
+    c->vcol.insert(c->vcol.end(), vcol.begin(), vcol.end());
+    c->vxs.insert(c->vxs.end(), vxs.begin(), vxs.end());
+    c->vW.insert(c->vW.end(), vW.begin(), vW.end());
+    c->vdV.insert(c->vdV.end(), vdV.begin(), vdV.end());
+    c->nv += nv;
+    if ((s = upload_bodies(c, v0))) {
+        c->nv = v0;
+        c->vcol.resize((size_t)v0 * 64); c->vxs.resize((size_t)v0 * 64); c->vW.resize((size_t)v0 * 64);
+        c->vdV.resize(v0);
+        return s;
+    }
+    c->d.nv = c->nv;
+    c->d.nslot = c->nslot;
+    if (first_vertex) *first_vertex = v0;
+    return CAPIB_OK;
+}
+
+capib_status capib3d_body_forces(capib3d_ctx *c, double *out) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!out) return fail3(c, CAPIB_E_ARG, "null output");
+    if (c->nv == 0) return CAPIB_OK;
+    std::vector<double> f((size_t)c->nv * 3);
+    HIP3(c, hipMemcpyAsync(f.data(), c->base + c->off_vF, f.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    for (int v = 0; v < c->nv; v++)
+        for (int k = 0; k < 3; k++) out[3 * v + k] = f[3 * (size_t)v + k] * c->vdV[v];
+    return CAPIB_OK;
+}
+
+int32_t capib3d_vertices(const capib3d_ctx *c) { return c ? c->nv : 0; }
+
+capib_status capib3d_set_ib_schedule(capib3d_ctx *c, int32_t share_node_u, int32_t share_vertex) {
+    if (!c) return CAPIB_E_ARG;
+    if (share_node_u < 0 || share_vertex < 0 || share_node_u + share_vertex > 100)
+        return fail3(c, CAPIB_E_ARG, "shares %d + %d outside [0, 100]", share_node_u, share_vertex);
+    c->share_u = share_node_u;
+    c->share_v = share_vertex;
     return CAPIB_OK;
 }
 

@@ -18,7 +18,8 @@ _dp = C.POINTER(C.c_double)
 
 class capib3d_lattice(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
-                ("geometry", C.c_int32), ("radius", C.c_double), ("storage", C.c_int32), ("fp16_scale", C.c_double)]
+                ("geometry", C.c_int32), ("radius", C.c_double), ("storage", C.c_int32), ("fp16_scale", C.c_double),
+                ("max_vertices", C.c_int32)]
 
 
 SIGNATURES = {
@@ -27,6 +28,10 @@ SIGNATURES = {
     "capib3d_workspace_bytes": (C.c_size_t, [_P]),
     "capib3d_bind_workspace": (C.c_int, [_P, _P, C.c_size_t]),
     "capib3d_init_flow": (C.c_int, [_P, _dp]),
+    "capib3d_add_fixed_body": (C.c_int, [_P, C.c_int32, _dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "capib3d_body_forces": (C.c_int, [_P, _dp]),
+    "capib3d_vertices": (C.c_int32, [_P]),
+    "capib3d_set_ib_schedule": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "capib3d_step": (C.c_int, [_P, C.c_int32]),
     "capib3d_read_macro": (C.c_int, [_P, _dp, _dp, _dp, _dp]),
     "capib3d_read_populations": (C.c_int, [_P, _dp]),
@@ -74,13 +79,13 @@ class Tube3D:
     """A D3Q19 tube on the GPU (workspace allocated with torch)."""
 
     def __init__(self, nx, ny, nz, tau, gx, geometry=TUBE, radius=0.0, stream=None, storage=capib.FP32_SHIFTED,
-                 fp16_scale=1.0):
+                 fp16_scale=1.0, max_vertices=0):
         import torch
         self.torch = torch
         self.L = _lib()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius, storage, fp16_scale)
+        lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius, storage, fp16_scale, max_vertices)
         self.ctx = _P()
         st = self.L.capib3d_create(C.byref(lat), _P(self.stream.cuda_stream), C.byref(self.ctx))
         if st != capib.CAPIB_OK:
@@ -109,6 +114,33 @@ class Tube3D:
         if a is not None:
             assert a.shape == (self.nz, self.ny)
         self._check(self.L.capib3d_init_flow(self.ctx, None if a is None else _d(a)))
+
+    def add_fixed_body(self, xyz, tri):
+        """A fixed immersed body (vertices [nv][3], triangles [ntri][3]);
+        returns the index of its first vertex."""
+        X = np.ascontiguousarray(xyz, dtype=np.float64)
+        T = np.ascontiguousarray(tri, dtype=np.int32)
+        assert X.ndim == 2 and X.shape[1] == 3 and T.ndim == 2 and T.shape[1] == 3
+        first = C.c_int32()
+        self._check(self.L.capib3d_add_fixed_body(self.ctx, X.shape[0], _d(X), T.shape[0],
+                                                  T.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(first)))
+        return first.value
+
+    @property
+    def vertices(self):
+        return int(self.L.capib3d_vertices(self.ctx))
+
+    def body_forces(self):
+        """Force of the last step on the fluid at every vertex, [nv][3]."""
+        out = np.zeros((self.vertices, 3))
+        self._check(self.L.capib3d_body_forces(self.ctx, _d(out)))
+        return out
+
+    def set_ib_schedule(self, share_node_u, share_vertex):
+        """Percent of the work items swept in the launch that computes the
+        stencil nodes' velocities and in the one that computes the vertex
+        forces (a schedule knob: the result does not depend on it)."""
+        self._check(self.L.capib3d_set_ib_schedule(self.ctx, int(share_node_u), int(share_vertex)))
 
     def step(self, n=1):
         self._check(self.L.capib3d_step(self.ctx, int(n)))

@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2210_06043_amd import capib, mlp, tube3d
@@ -57,7 +58,8 @@ def test_tube3d_create_validates_without_a_gpu():
            tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 0.0, 0, 1.0),
            tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, 7, 3.0, 0, 1.0),
            tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, 5, 1.0),
-           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, capib.FP16_SHIFTED, 3.0)]
+           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, capib.FP16_SHIFTED, 3.0),
+           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, 0, 1.0, -1)]
     for lat in bad:
         assert L.capib3d_create(C.byref(lat), None, C.byref(ctx)) == capib.CAPIB_E_ARG
     lat = tube3d.capib3d_lattice(256, 64, 64, 1.0, 1e-7, tube3d.TUBE, 32.0, 0, 1.0)
@@ -67,6 +69,17 @@ def test_tube3d_create_validates_without_a_gpu():
         assert n == 256 * 3228   # fluid columns of a 64 x 64 cross-section with R = 32
         assert L.capib3d_workspace_bytes(ctx) >= 2 * 19 * 256 * 64 * 64 * 4
         assert L.capib3d_step(ctx, 1) == capib.CAPIB_E_STATE   # no workspace bound
+        X = np.zeros(3)
+        assert L.capib3d_add_fixed_body(ctx, 1, X.ctypes.data_as(C.POINTER(C.c_double)), 0, None,
+                                        None) == capib.CAPIB_E_STATE
+        assert L.capib3d_vertices(ctx) == 0
+    finally:
+        L.capib3d_destroy(ctx)
+    # room for fixed-body vertices: stencil nodes, weights, places and contributions of every lane
+    lat = tube3d.capib3d_lattice(256, 64, 64, 1.0, 1e-7, tube3d.TUBE, 32.0, 0, 1.0, 2562)
+    assert L.capib3d_create(C.byref(lat), None, C.byref(ctx)) == capib.CAPIB_OK
+    try:
+        assert L.capib3d_workspace_bytes(ctx) >= 2 * 19 * 256 * 64 * 64 * 4 + 2562 * 64 * (4 + 8 + 4 + 24)
     finally:
         L.capib3d_destroy(ctx)
 

@@ -19,6 +19,13 @@
  *       of S2 interpolated to every vertex with the cosine delta in 3D, the
  *       direct forcing F = (U - u*) dV with U = 0, spread back with the same
  *       delta                                                   (Sec. 2.2)
+ *   S3' with deformable membranes (closed triangulated surfaces): u*
+ *       interpolated as in S3; elastic forces at x^n from Skalak's strain
+ *       energy of each triangle (Skalak et al. 1973) plus penalties on the
+ *       membrane's total area and enclosed volume (FP64 sums); the vertex
+ *       update of the 2D membranes, dx = u* + f/(2m), x^{n+1} = x^n + dx,
+ *       U = 3/2 dx - 1/2 dx_prev; F = (U - u*) dV spread at x^n, dV a third
+ *       of the adjacent triangles' area at x^n                  (Secs. 2.2-2.4 in 3D)
  *   S4  BGK collision towards the equilibrium with the Guo term for the
  *       total force g + f_ib, u = (sum f e + (g + f_ib)/2)/rho   (Eqs. 1, 2, 4-6)
  * Populations are stored shifted, h_i = f_i - w_i, as in the 2D oracle.
@@ -99,6 +106,15 @@ typedef struct {
     double *X;              /* [nv][3] positions */
     double *dV;             /* [nv] volume weight: a third of the adjacent triangles' area (unit thickness) */
     double *f;              /* [3][n] spread force of the current step */
+    /* deformable membranes */
+    int nm, mv, mt;         /* membranes, their vertices and triangles in all */
+    int *m_v0, *m_nv, *m_t0, *m_nt;   /* [nm] vertex and triangle ranges */
+    double *m_par;          /* [nm][5] G_s, C, k_A, k_V, vertex mass */
+    double *m_A0, *m_V0;    /* [nm] rest area and enclosed volume */
+    double *MX, *Mdxm;      /* [mv][3] positions, displacement of the previous step */
+    double *Mus, *Mf, *MF;  /* [mv][3] u*, elastic force, spread force of the current step */
+    int *Mtri;              /* [mt][3] membrane vertex indices */
+    double *Mref;           /* [mt][7] rest shape-function gradients g0, g1, g2 (2 each) and rest area */
 } orc3;
 
 static long long idx(const orc3 *s, int x, int y, int z) { return ((long long)z * s->ny + y) * s->nx + x; }
@@ -129,7 +145,10 @@ orc3 *orc3_create(int nx, int ny, int nz, double tau, double gx, int geom, doubl
 
 void orc3_destroy(orc3 *s) {
     if (!s) return;
-    free(s->fluid); free(s->A); free(s->h); free(s->X); free(s->dV); free(s->f); free(s);
+    free(s->fluid); free(s->A); free(s->h); free(s->X); free(s->dV); free(s->f);
+    free(s->m_v0); free(s->m_nv); free(s->m_t0); free(s->m_nt); free(s->m_par); free(s->m_A0); free(s->m_V0);
+    free(s->MX); free(s->Mdxm); free(s->Mus); free(s->Mf); free(s->MF); free(s->Mtri); free(s->Mref);
+    free(s);
 }
 
 /* The 4-point cosine delta, phi(r) = (1 + cos(pi r / 2)) / 4 for |r| <= 2. */
@@ -240,7 +259,6 @@ static void moments3(const orc3 *s, long long k, double *drho, double u[3]) {
 /* S3: u* at every vertex, F = (U - u*) dV with U = 0, spread into s->f */
 static void ib_force3(orc3 *s) {
     const long long n = s->n;
-    memset(s->f, 0, sizeof(double) * 3 * n);
     for (int v = 0; v < s->nv; v++) {
         int o[3];
         double w[3][4], us[3] = {0, 0, 0};
@@ -266,6 +284,272 @@ static void ib_force3(orc3 *s) {
     }
 }
 
+/* ---- deformable membranes ------------------------------------------------ */
+
+static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static void cross3(const double *a, const double *b, double *o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* u* at a point: the streamed velocity with half the body force at the 64
+ * nodes of its stencil, weighted by the cosine delta                        */
+static void interp3(orc3 *s, const double *X, double us[3]) {
+    int o[3];
+    double w[3][4];
+    stencil3(X, o, w);
+    us[0] = us[1] = us[2] = 0.0;
+    for (int c = 0; c < 4; c++)
+        for (int b = 0; b < 4; b++)
+            for (int a = 0; a < 4; a++) {
+                const int x = ((o[0] + a) % s->nx + s->nx) % s->nx;
+                double d, u[3];
+                moments3(s, idx(s, x, o[1] + b, o[2] + c), &d, u);
+                const double W = w[0][a] * w[1][b] * w[2][c];
+                for (int q = 0; q < 3; q++) us[q] += W * u[q];
+            }
+}
+
+/* F spread at the 64 nodes of X's stencil into s->f */
+static void spread3(orc3 *s, const double *X, const double F[3]) {
+    int o[3];
+    double w[3][4];
+    stencil3(X, o, w);
+    for (int c = 0; c < 4; c++)
+        for (int b = 0; b < 4; b++)
+            for (int a = 0; a < 4; a++) {
+                const int x = ((o[0] + a) % s->nx + s->nx) % s->nx;
+                const long long k = idx(s, x, o[1] + b, o[2] + c);
+                const double W = w[0][a] * w[1][b] * w[2][c];
+                for (int q = 0; q < 3; q++) s->f[q * s->n + k] += W * F[q];
+            }
+}
+
+/* Area and enclosed volume of membrane m at its current positions, summed
+ * over its triangles in order (the volume about its first vertex).         */
+static void membrane_totals(const orc3 *s, int m, double *A, double *V) {
+    const double *r0 = s->MX + 3 * s->m_v0[m];
+    double a = 0.0, v = 0.0;
+    for (int t = s->m_t0[m]; t < s->m_t0[m] + s->m_nt[m]; t++) {
+        const int *T = s->Mtri + 3 * t;
+        double p[3], q[3], r[3], e1[3], e2[3], n[3], qr[3];
+        sub3(s->MX + 3 * T[0], r0, p); sub3(s->MX + 3 * T[1], r0, q); sub3(s->MX + 3 * T[2], r0, r);
+        sub3(q, p, e1); sub3(r, p, e2); cross3(e1, e2, n);
+        a += 0.5 * sqrt(dot3(n, n));
+        cross3(q, r, qr);
+        v += dot3(p, qr) / 6.0;
+    }
+    *A = a;
+    *V = v;
+}
+
+/* The deformation of triangle t: F = sum_a x_a g_a^T (3 x 2, g_a the rest
+ * shape-function gradients in the triangle's own rest frame), the right
+ * Cauchy-Green tensor C = F^T F, I1 = tr C - 2, I2 = det C - 1 (Skalak's
+ * invariants); Skalak's energy per rest area
+ *   w = G_s/4 (I1^2 + 2 I1 - 2 I2 + C I2^2)                                 */
+static void triangle_state(const orc3 *s, int t, double F[3][2], double Cm[2][2], double *I1, double *I2) {
+    const int *T = s->Mtri + 3 * t;
+    const double *g = s->Mref + 7 * t;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 2; j++) F[i][j] = 0.0;
+    for (int a = 0; a < 3; a++) {
+        const double *x = s->MX + 3 * T[a];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 2; j++) F[i][j] += x[i] * g[2 * a + j];
+    }
+    for (int j = 0; j < 2; j++)
+        for (int k = 0; k < 2; k++) Cm[j][k] = F[0][j] * F[0][k] + F[1][j] * F[1][k] + F[2][j] * F[2][k];
+    *I1 = Cm[0][0] + Cm[1][1] - 2.0;
+    *I2 = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0] - 1.0;
+}
+
+/* Energies of membrane m (exported for the tests): Skalak, area penalty
+ * k_A (A - A0)^2 / (2 A0), volume penalty k_V (V - V0)^2 / (2 V0).        */
+void orc3_membrane_energy(const orc3 *s, int m, double *out3) {
+    const double *P = s->m_par + 5 * m;
+    double ws = 0.0;
+    for (int t = s->m_t0[m]; t < s->m_t0[m] + s->m_nt[m]; t++) {
+        double F[3][2], Cm[2][2], I1, I2;
+        triangle_state(s, t, F, Cm, &I1, &I2);
+        ws += s->Mref[7 * t + 6] * 0.25 * P[0] * (I1 * I1 + 2.0 * I1 - 2.0 * I2 + P[1] * I2 * I2);
+    }
+    double A, V;
+    membrane_totals(s, m, &A, &V);
+    out3[0] = ws;
+    out3[1] = P[2] * (A - s->m_A0[m]) * (A - s->m_A0[m]) / (2.0 * s->m_A0[m]);
+    out3[2] = P[3] * (V - s->m_V0[m]) * (V - s->m_V0[m]) / (2.0 * s->m_V0[m]);
+}
+
+/* Elastic forces of membrane m into Mf, minus the gradients of its three
+ * energies: for triangle t and its corner a,
+ *   Skalak  -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], w1 = dw/dI1, w2 = dw/dI2
+ *   area    -k_A (A - A0)/A0 * n x (x_c - x_b) / 2
+ *   volume  -k_V (V - V0)/V0 * (x_b - r0) x (x_c - r0) / 6
+ * with (a, b, c) the triangle's corners in its own cyclic order from a.     */
+static void membrane_forces(orc3 *s, int m) {
+    const double *P = s->m_par + 5 * m;
+    const int v0 = s->m_v0[m];
+    for (int v = v0; v < v0 + s->m_nv[m]; v++) s->Mf[3 * v] = s->Mf[3 * v + 1] = s->Mf[3 * v + 2] = 0.0;
+    double A, V;
+    membrane_totals(s, m, &A, &V);
+    const double ca = P[2] * (A - s->m_A0[m]) / s->m_A0[m], cv = P[3] * (V - s->m_V0[m]) / s->m_V0[m];
+    const double *r0 = s->MX + 3 * v0;
+    for (int t = s->m_t0[m]; t < s->m_t0[m] + s->m_nt[m]; t++) {
+        const int *T = s->Mtri + 3 * t;
+        const double *g = s->Mref + 7 * t, A0 = g[6];
+        double F[3][2], Cm[2][2], I1, I2;
+        triangle_state(s, t, F, Cm, &I1, &I2);
+        const double w1 = 0.25 * P[0] * (2.0 * I1 + 2.0), w2 = 0.25 * P[0] * (-2.0 + 2.0 * P[1] * I2);
+        const double det = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0];
+        const double Ci[2][2] = {{Cm[1][1] / det, -Cm[0][1] / det}, {-Cm[1][0] / det, Cm[0][0] / det}};
+        double e1[3], e2[3], n[3];
+        sub3(s->MX + 3 * T[1], s->MX + 3 * T[0], e1);
+        sub3(s->MX + 3 * T[2], s->MX + 3 * T[0], e2);
+        cross3(e1, e2, n);
+        const double nn = sqrt(dot3(n, n));
+        for (int i = 0; i < 3; i++) n[i] /= nn;
+        for (int a = 0; a < 3; a++) {
+            const int b = (a + 1) % 3, c = (a + 2) % 3;
+            const double ga[2] = {g[2 * a], g[2 * a + 1]};
+            const double Cg[2] = {Ci[0][0] * ga[0] + Ci[0][1] * ga[1], Ci[1][0] * ga[0] + Ci[1][1] * ga[1]};
+            double fa[3];
+            for (int i = 0; i < 3; i++) {
+                const double Fg = F[i][0] * ga[0] + F[i][1] * ga[1];
+                const double FCg = F[i][0] * Cg[0] + F[i][1] * Cg[1];
+                fa[i] = -A0 * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
+            }
+            double cb[3], xb[3], xc[3], bc[3], nbc[3];
+            sub3(s->MX + 3 * T[c], s->MX + 3 * T[b], cb);
+            cross3(n, cb, nbc);
+            sub3(s->MX + 3 * T[b], r0, xb);
+            sub3(s->MX + 3 * T[c], r0, xc);
+            cross3(xb, xc, bc);
+            double *f = s->Mf + 3 * T[a];
+            for (int i = 0; i < 3; i++) f[i] += fa[i] - ca * 0.5 * nbc[i] - cv * bc[i] / 6.0;
+        }
+    }
+}
+
+/* S3' for every membrane vertex (see the file header) */
+static void membranes3(orc3 *s) {
+    for (int v = 0; v < s->mv; v++) interp3(s, s->MX + 3 * v, s->Mus + 3 * v);
+    for (int m = 0; m < s->nm; m++) membrane_forces(s, m);
+    double *dV = (double *)calloc((size_t)s->mv, sizeof(double));
+    for (int t = 0; t < s->mt; t++) {
+        const int *T = s->Mtri + 3 * t;
+        double e1[3], e2[3], n[3];
+        sub3(s->MX + 3 * T[1], s->MX + 3 * T[0], e1);
+        sub3(s->MX + 3 * T[2], s->MX + 3 * T[0], e2);
+        cross3(e1, e2, n);
+        const double area = 0.5 * sqrt(dot3(n, n));
+        for (int k = 0; k < 3; k++) dV[T[k]] += area / 3.0;
+    }
+    for (int m = 0; m < s->nm; m++) {
+        const double mass = s->m_par[5 * m + 4];
+        for (int v = s->m_v0[m]; v < s->m_v0[m] + s->m_nv[m]; v++) {
+            double Xn[3], F[3];
+            for (int q = 0; q < 3; q++) {
+                Xn[q] = s->MX[3 * v + q];
+                const double dx = s->Mus[3 * v + q] + 0.5 * s->Mf[3 * v + q] / mass;
+                const double U = 1.5 * dx - 0.5 * s->Mdxm[3 * v + q];
+                s->MX[3 * v + q] += dx;
+                s->Mdxm[3 * v + q] = dx;
+                F[q] = (U - s->Mus[3 * v + q]) * dV[v];
+            }
+            for (int q = 0; q < 3; q++) s->MF[3 * v + q] = F[q];
+            spread3(s, Xn, F);
+        }
+    }
+    free(dV);
+}
+
+/* A deformable membrane: a closed triangulated surface (nv vertices xyz
+ * [nv][3], ntri triangles tri [ntri][3] counter-clockwise seen from
+ * outside), its rest shape the given one, with Skalak's G_s and C, the
+ * area and volume penalties k_A, k_V and the vertex mass.  Every stencil
+ * node must be fluid now; returns the index of its first vertex among the
+ * membrane vertices, or -1.                                                 */
+int orc3_add_membrane(orc3 *s, int nv, const double *xyz, int ntri, const int *tri, double gs, double c, double ka,
+                      double kv, double mass) {
+    for (int v = 0; v < nv; v++) {
+        int o[3];
+        double w[3][4];
+        stencil3(xyz + 3 * v, o, w);
+        if (o[1] < 0 || o[1] + 3 >= s->ny || o[2] < 0 || o[2] + 3 >= s->nz) return -1;
+        for (int b = 0; b < 4; b++)
+            for (int cc = 0; cc < 4; cc++)
+                if (!is_fluid_yz(s, o[1] + b, o[2] + cc)) return -1;
+    }
+    const int m = s->nm, v0 = s->mv, t0 = s->mt;
+    s->nm++; s->mv += nv; s->mt += ntri;
+    s->m_v0 = (int *)realloc(s->m_v0, sizeof(int) * s->nm);
+    s->m_nv = (int *)realloc(s->m_nv, sizeof(int) * s->nm);
+    s->m_t0 = (int *)realloc(s->m_t0, sizeof(int) * s->nm);
+    s->m_nt = (int *)realloc(s->m_nt, sizeof(int) * s->nm);
+    s->m_par = (double *)realloc(s->m_par, sizeof(double) * 5 * s->nm);
+    s->m_A0 = (double *)realloc(s->m_A0, sizeof(double) * s->nm);
+    s->m_V0 = (double *)realloc(s->m_V0, sizeof(double) * s->nm);
+    s->MX = (double *)realloc(s->MX, sizeof(double) * 3 * s->mv);
+    s->Mdxm = (double *)realloc(s->Mdxm, sizeof(double) * 3 * s->mv);
+    s->Mus = (double *)realloc(s->Mus, sizeof(double) * 3 * s->mv);
+    s->Mf = (double *)realloc(s->Mf, sizeof(double) * 3 * s->mv);
+    s->MF = (double *)realloc(s->MF, sizeof(double) * 3 * s->mv);
+    s->Mtri = (int *)realloc(s->Mtri, sizeof(int) * 3 * s->mt);
+    s->Mref = (double *)realloc(s->Mref, sizeof(double) * 7 * s->mt);
+    s->m_v0[m] = v0; s->m_nv[m] = nv; s->m_t0[m] = t0; s->m_nt[m] = ntri;
+    const double par[5] = {gs, c, ka, kv, mass};
+    memcpy(s->m_par + 5 * m, par, sizeof par);
+    memcpy(s->MX + 3 * v0, xyz, sizeof(double) * 3 * nv);
+    memset(s->Mdxm + 3 * v0, 0, sizeof(double) * 3 * nv);
+    memset(s->Mus + 3 * v0, 0, sizeof(double) * 3 * nv);
+    memset(s->Mf + 3 * v0, 0, sizeof(double) * 3 * nv);
+    memset(s->MF + 3 * v0, 0, sizeof(double) * 3 * nv);
+    for (int t = 0; t < ntri; t++) {
+        int *T = s->Mtri + 3 * (t0 + t);
+        for (int k = 0; k < 3; k++) T[k] = v0 + tri[3 * t + k];
+        /* the rest triangle in its own frame: X0 = 0, X1 = (l, 0), X2 = (p, q) */
+        double e1[3], e2[3], n[3], u1[3], u2[3];
+        sub3(xyz + 3 * tri[3 * t + 1], xyz + 3 * tri[3 * t], e1);
+        sub3(xyz + 3 * tri[3 * t + 2], xyz + 3 * tri[3 * t], e2);
+        cross3(e1, e2, n);
+        const double l = sqrt(dot3(e1, e1)), nn = sqrt(dot3(n, n));
+        for (int i = 0; i < 3; i++) { u1[i] = e1[i] / l; n[i] /= nn; }
+        cross3(n, u1, u2);
+        const double pp = dot3(e2, u1), qq = dot3(e2, u2);
+        /* D = [X1 - X0, X2 - X0] = [[l, pp], [0, qq]]; the rows of D^-1 are g1 and g2 */
+        double *g = s->Mref + 7 * (t0 + t);
+        g[2] = 1.0 / l;  g[3] = -pp / (l * qq);
+        g[4] = 0.0;      g[5] = 1.0 / qq;
+        g[0] = -g[2] - g[4];
+        g[1] = -g[3] - g[5];
+        g[6] = 0.5 * nn;
+    }
+    double A, V;
+    membrane_totals(s, m, &A, &V);
+    s->m_A0[m] = A;
+    s->m_V0[m] = V;
+    if (!s->f) s->f = (double *)calloc((size_t)(3 * s->n), sizeof(double));
+    return v0;
+}
+
+void orc3_membrane_vertices(const orc3 *s, double *out) { if (s->mv) memcpy(out, s->MX, sizeof(double) * 3 * s->mv); }
+void orc3_membrane_set_vertices(orc3 *s, const double *in) { if (s->mv) memcpy(s->MX, in, sizeof(double) * 3 * s->mv); }
+/* elastic forces of membrane m at the current positions, [nv][3] */
+void orc3_membrane_forces(orc3 *s, int m, double *out) {
+    membrane_forces(s, m);
+    memcpy(out, s->Mf + 3 * s->m_v0[m], sizeof(double) * 3 * s->m_nv[m]);
+}
+/* spread force F = (U - u*) dV of the last step at every membrane vertex, [mv][3] */
+void orc3_membrane_spread_forces(const orc3 *s, double *out) { if (s->mv) memcpy(out, s->MF, sizeof(double) * 3 * s->mv); }
+void orc3_membrane_totals(const orc3 *s, int m, double *out4) {
+    membrane_totals(s, m, out4, out4 + 1);
+    out4[2] = s->m_A0[m];
+    out4[3] = s->m_V0[m];
+}
+
 /* S4: A = h - (h - h_eq)/tau + F_i(u, g + f_ib), u = (sum h e + (g + f_ib)/2)/rho */
 static void collide3(orc3 *s) {
     const long long n = s->n;
@@ -278,7 +562,7 @@ static void collide3(orc3 *s) {
                 double drho, u[3], heq[19], F[19];
                 moments3(s, k, &drho, u);
                 double Fx = s->gx, Fy = 0.0, Fz = 0.0;
-                if (s->nv) {
+                if (s->f) {
                     const double rho = 1.0 + drho;
                     Fx += s->f[k]; Fy = s->f[n + k]; Fz = s->f[2 * n + k];
                     u[0] += 0.5 * s->f[k] / rho; u[1] += 0.5 * Fy / rho; u[2] += 0.5 * Fz / rho;
@@ -296,7 +580,9 @@ static void collide3(orc3 *s) {
 void orc3_step(orc3 *s, int nsteps) {
     for (int t = 0; t < nsteps; t++) {
         stream3(s);
+        if (s->f) memset(s->f, 0, sizeof(double) * 3 * s->n);
         if (s->nv) ib_force3(s);
+        if (s->nm) membranes3(s);
         collide3(s);
         s->step++;
     }

@@ -43,6 +43,14 @@ def _L():
         L.orc3_add_fixed_body.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)]
         L.orc3_ib_force.argtypes = [C.c_void_p, _dp]
         L.orc3_vertex_weights.argtypes = [C.c_void_p, _dp]
+        L.orc3_add_membrane.restype = C.c_int
+        L.orc3_add_membrane.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)] + [C.c_double] * 5
+        L.orc3_membrane_vertices.argtypes = [C.c_void_p, _dp]
+        L.orc3_membrane_set_vertices.argtypes = [C.c_void_p, _dp]
+        L.orc3_membrane_forces.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.orc3_membrane_spread_forces.argtypes = [C.c_void_p, _dp]
+        L.orc3_membrane_totals.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.orc3_membrane_energy.argtypes = [C.c_void_p, C.c_int, _dp]
         _ready = True
     return L
 
@@ -134,4 +142,51 @@ class Tube:
     def vertex_weights(self):
         out = np.zeros(getattr(self, "nv", 0))
         self.L.orc3_vertex_weights(self.p, _d(out))
+        return out
+
+    # deformable membranes
+    def add_membrane(self, xyz, tri, gs, c, ka, kv, mass):
+        """A closed triangulated membrane (Skalak G_s, C; area and volume
+        penalties k_A, k_V; vertex mass); returns its first vertex index among
+        the membrane vertices."""
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+        v0 = self.L.orc3_add_membrane(self.p, len(xyz), _d(xyz), len(tri), tri.ctypes.data_as(C.POINTER(C.c_int)),
+                                      gs, c, ka, kv, mass)
+        if v0 < 0:
+            raise ValueError("a stencil node of the membrane is solid or outside the cross-section")
+        self.mv = getattr(self, "mv", 0) + len(xyz)
+        self.mranges = getattr(self, "mranges", []) + [(v0, len(xyz))]
+        return v0
+
+    def membrane_vertices(self):
+        out = np.zeros((getattr(self, "mv", 0), 3))
+        self.L.orc3_membrane_vertices(self.p, _d(out))
+        return out
+
+    def set_membrane_vertices(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        assert X.shape == (self.mv, 3)
+        self.L.orc3_membrane_set_vertices(self.p, _d(X))
+
+    def membrane_forces(self, m):
+        out = np.zeros((self.mranges[m][1], 3))
+        self.L.orc3_membrane_forces(self.p, m, _d(out))
+        return out
+
+    def membrane_spread_forces(self):
+        out = np.zeros((getattr(self, "mv", 0), 3))
+        self.L.orc3_membrane_spread_forces(self.p, _d(out))
+        return out
+
+    def membrane_totals(self, m):
+        """(area, volume, rest area, rest volume)"""
+        out = np.zeros(4)
+        self.L.orc3_membrane_totals(self.p, m, _d(out))
+        return out
+
+    def membrane_energy(self, m):
+        """(Skalak, area penalty, volume penalty)"""
+        out = np.zeros(3)
+        self.L.orc3_membrane_energy(self.p, m, _d(out))
         return out

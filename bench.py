@@ -484,6 +484,12 @@ def tube3d_section(args):
             "note": "three launches per step: k3_node_u (velocity of the 7167 stencil nodes, a wave per slot), "
                     "k3_vertex (a wave per vertex), k3_sweep_ib (slots gather their spread force, then the "
                     "ordinary items)"}
+    # the same FP32 tube with four 2562-vertex oblate cells and a 642-vertex
+    # sphere as deformable membranes (Skalak, area and volume penalties)
+    mem = tube3d_membrane_run(p, prof, args.tube3d_warmup, args.tube3d_steps)
+    mem["ms_per_step"] = round(mem["ms_per_step"], 5)
+    mem["mlups"] = round(n / (mem["ms_per_step"] * 1e-3) / 1e6, 1)
+    mem["overhead_us_per_step"] = round((mem["ms_per_step"] - ms) * 1e3, 2)
     return {"workload": f"D3Q19 tube {p['nx']}x{p['ny']}x{p['nz']}, radius {p['radius']:g} ({n} fluid nodes), tau 1, "
                         f"Re 0.01 (g = {p['gx']:.4g}), halfway bounce-back walls; FP32 deviation storage, FP64 collision",
             "fluid_nodes": n, "steps": args.tube3d_steps, "ms_per_step": round(ms, 5),
@@ -493,7 +499,46 @@ def tube3d_section(args):
                          "algorithmic_bytes_per_launch": alg, "traffic": counters("k3_sweep_fp32_tube", TUBE3D_SOURCES),
                          "note": "one launch per step, timed back to back (launch gaps included); the 125 MB "
                                  "working set fits the 256 MB Infinity Cache"},
-            "fp16_storage": fp16, "fixed_body": body}
+            "fp16_storage": fp16, "fixed_body": body, "membranes": mem}
+
+
+def tube3d_membranes(p):
+    """Four 2562-vertex oblate cells (radius 8, axes 1, 1, 0.5) and a
+    642-vertex sphere of radius 4 in the 256 x 64 x 64 tube."""
+    from paper_2210_06043_amd import inputs
+    c = 0.5 * (p["ny"] - 1)
+    cells = [inputs.icosphere(4, 8.0, (40.2 + 60 * k, c + (9.0, -7.5, 4.0, -10.0)[k], c + (2.0, 8.0, -9.0, -1.5)[k]),
+                              axes=(1.0, 1.0, 0.5)) for k in range(4)]
+    return cells + [inputs.icosphere(3, 4.0, (128.7, c - 3.0, c - 17.0))]
+
+
+MEMBRANE_PARAMS = dict(gs=5e-3, c=1.0, ka=0.05, kv=0.05, mass=1.0)
+
+
+def tube3d_membrane_run(p, prof, warmup, steps):
+    import torch
+    from paper_2210_06043_amd import tube3d
+    ms_ = tube3d_membranes(p)
+    g = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"], max_membranes=len(ms_),
+                      max_membrane_vertices=sum(len(m[0]) for m in ms_),
+                      max_membrane_triangles=sum(len(m[1]) for m in ms_))
+    g.init_flow(prof)
+    for xyz, tri in ms_:
+        g.add_membrane(xyz, tri, **MEMBRANE_PARAMS)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step(steps)
+    e1.record(g.stream)
+    e1.synchronize()
+    t = [g.membrane_totals(m) for m in range(len(ms_))]
+    return {"membranes": len(ms_), "vertices": g.membrane_vertex_count, "triangles": sum(len(m[1]) for m in ms_),
+            "ms_per_step": e0.elapsed_time(e1) / steps, "error_flags": g.error_flags(),
+            "volume_drift_max": float(max(abs(x[1] / x[3] - 1) for x in t)),
+            "note": "four launches per step: k3_m_interp (a wave per vertex), k3_m_body (a workgroup per membrane, "
+                    "FP64), k3_m_spread (fixed-point atomics), k3_sweep reading the field on flagged items"}
 
 
 def capib_fp16():

@@ -9,8 +9,11 @@
  * fixed immersed bodies (triangulated surfaces that do not move) coupled as
  * in Sec. 2.2: the fluid velocity interpolated to every vertex with the
  * 4-point cosine delta in 3D, the direct force (U - u*) dV with U = 0,
- * spread back with the same delta.  Deformable membranes in 3D are not part
- * of this library.
+ * spread back with the same delta; and deformable membranes (closed
+ * triangulated surfaces with Skalak's strain energy per triangle and
+ * penalties on their total area and enclosed volume, the 2D membranes'
+ * vertex update of Secs. 2.2-2.4 carried to 3D).  A context holds fixed
+ * bodies or membranes, not both.
  *
  * Conventions
  *   - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3.
@@ -56,7 +59,9 @@ enum { CAPIB3D_TUBE = 0, CAPIB3D_SLAB = 1, CAPIB3D_BOX = 2 };
  *   radius      tube radius in nodes (CAPIB3D_TUBE only, > 0)
  *   storage     CAPIB_FP32_SHIFTED or CAPIB_FP16_SHIFTED
  *   fp16_scale  power of two multiplying stored FP16 deviations (FP16 only)
- *   max_vertices  capacity for the vertices of fixed bodies (0: none)     */
+ *   max_vertices  capacity for the vertices of fixed bodies (0: none)
+ *   max_membranes, max_membrane_vertices, max_membrane_triangles
+ *               capacity for deformable membranes (all 0, or all > 0)     */
 typedef struct {
     int32_t nx, ny, nz;
     double tau, gx;
@@ -65,7 +70,20 @@ typedef struct {
     int32_t storage;
     double fp16_scale;
     int32_t max_vertices;
+    int32_t max_membranes, max_membrane_vertices, max_membrane_triangles;
 } capib3d_lattice;
+
+/* A deformable membrane's constants (lattice units).
+ *   gs    Skalak's shear modulus G_s: energy per rest area
+ *         w = G_s/4 (I1^2 + 2 I1 - 2 I2 + C I2^2), I1 = tr C - 2,
+ *         I2 = det C - 1 of the right Cauchy-Green tensor C of each triangle
+ *   c     Skalak's C
+ *   ka    penalty k_A (A - A0)^2 / (2 A0) on the total area
+ *   kv    penalty k_V (V - V0)^2 / (2 V0) on the enclosed volume
+ *   mass  vertex mass m of the update dx = u* + f/(2m)                      */
+typedef struct {
+    double gs, c, ka, kv, mass;
+} capib3d_membrane;
 
 typedef struct capib3d_ctx capib3d_ctx;
 
@@ -104,6 +122,39 @@ capib_status capib3d_body_forces(capib3d_ctx *ctx, double *out);
 /* Vertices of the fixed bodies added so far. */
 int32_t capib3d_vertices(const capib3d_ctx *ctx);
 
+/* A deformable membrane: nv vertices (xyz, [nv][3] host doubles, lattice
+ * coordinates; at most 4096) and ntri triangles (tri, [ntri][3], counter-
+ * clockwise seen from outside), its rest shape the given one.  Each step:
+ * u* interpolated at x^n (as for fixed bodies), the elastic force f at x^n
+ * (Skalak, area and volume terms, FP64 sums), dx = u* + f/(2m), x^{n+1} =
+ * x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV spread at x^n with dV
+ * a third of the adjacent triangles' area at x^n.  Every stencil node must
+ * be fluid now (CAPIB_E_ARG; a node that leaves the fluid later raises
+ * error flag 1 and contributes nothing), degenerate triangles or a
+ * non-positive enclosed volume give CAPIB_E_ARG, capacity CAPIB_E_CAPACITY,
+ * a context with fixed bodies CAPIB_E_STATE.  *first_vertex (may be NULL)
+ * receives its first vertex among the membrane vertices.  Syncs. */
+capib_status capib3d_add_membrane(capib3d_ctx *ctx, int32_t nv, const double *xyz, int32_t ntri,
+                                  const int32_t *tri, const capib3d_membrane *par, int32_t *first_vertex);
+/* Membrane vertex positions, [membrane vertices][3] host doubles, in the
+ * order the membranes were added (read and overwrite; the previous
+ * displacement is kept).  Both sync. */
+capib_status capib3d_read_membrane_vertices(capib3d_ctx *ctx, double *xyz);
+capib_status capib3d_write_membrane_vertices(capib3d_ctx *ctx, const double *xyz);
+/* The direct force F = (U - u*) dV of the last step at every membrane
+ * vertex, [membrane vertices][3].  Syncs. */
+capib_status capib3d_membrane_spread_forces(capib3d_ctx *ctx, double *out);
+/* Membrane m's FP64 area and enclosed volume at the start of the last step
+ * (the device sums the step used), and its rest area and volume.  Syncs. */
+capib_status capib3d_membrane_totals(capib3d_ctx *ctx, int32_t m, double *out4);
+/* Error flags raised on the device since the workspace was bound: 1 a
+ * membrane stencil node outside the fluid, 2 a spread contribution beyond
+ * the fixed-point range (2^12) or not finite.  Syncs. */
+capib_status capib3d_error_flags(capib3d_ctx *ctx, int32_t *flags);
+/* Membranes, and their vertices in all. */
+int32_t capib3d_membranes(const capib3d_ctx *ctx);
+int32_t capib3d_membrane_vertex_count(const capib3d_ctx *ctx);
+
 /* Schedule of a step with fixed bodies (three launches: the velocity at
  * every stencil node, the force at every vertex, the collision of the
  * stencil nodes): the shares, in percent of the work items, of the ordinary
@@ -115,8 +166,10 @@ capib_status capib3d_set_ib_schedule(capib3d_ctx *ctx, int32_t share_node_u, int
 /* nsteps steps of Eq. (1): pull streaming with bounce-back, moments of
  * Eqs. (5)-(6) with half the total force, BGK collision with the Guo term
  * of Eq. (4) for the body force plus the spread force of the fixed bodies
- * (interpolated, forced and spread from the streamed moments at the start
- * of the step).  Enqueued on the context's stream; does not sync. */
+ * or membranes (interpolated, forced and spread from the streamed moments
+ * at the start of the step; the membranes' spread contributions summed as
+ * 64-bit fixed-point integers, 2^-50 units, so that every run gives the
+ * same bits).  Enqueued on the context's stream; does not sync. */
 capib_status capib3d_step(capib3d_ctx *ctx, int32_t nsteps);
 
 /* The moments the next step starts from (Eqs. 5-6 of the streamed

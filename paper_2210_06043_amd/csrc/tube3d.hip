@@ -31,6 +31,20 @@
 // each lane sums its node's contributions in vertex order, no atomics, the
 // same order on every run, and collides; then the ordinary items).  The
 // first two may also take shares of the ordinary items (a schedule knob).
+//
+// Deformable membranes (closed triangulated surfaces: Skalak elements and
+// penalties on total area and enclosed volume, Secs. 2.2-2.4 read in 3D).
+// Their stencils move, so the spreading is done by atomics: each spread
+// contribution is rounded to a 64-bit fixed-point integer (2^-50 units) and
+// added with an integer atomic, which is exact and associative, so the sum
+// does not depend on the order and every run gives the same bits.  A step is
+// four launches: k3_m_interp (a wave per vertex, a lane per stencil node),
+// k3_m_body (a workgroup per membrane: FP64 positions in LDS, FP64 area and
+// volume sums, per-vertex forces gathered from the incident triangles in
+// ascending order, the vertex update, the direct force), k3_m_spread (a wave
+// per vertex: fixed-point atomics into a force field, and a flag on every work
+// item touched), then the sweep, which reads and clears the field on flagged
+// items.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,7 +92,26 @@ struct Dev3 {
     const int *islot;           // [ncol * nseg] slot of a work item holding stencil nodes, -1 none
     const int *fitem;           // [nslot] work item of each slot
     const int *sbeg;            // [nslot][65] per lane, first contribution of its node
+    // deformable membranes
+    int nm, mv;                 // membranes, their vertices in all
+    long long ms;               // stride of the coordinate planes of the vertex arrays
+    long long fs;               // stride of the force field's planes: nz * ny * pitch
+    double *MX[2];              // [3][ms] positions, by parity
+    double *Mdxm, *Mus, *MF;    // [3][ms] previous displacement, u*, spread force
+    const int *Mtri;            // [mt][3] membrane vertex indices
+    const double *Mref;         // [mt][8] rest gradients g0, g1, g2 (2 each), rest area
+    const int *vtb, *vtl;       // incident triangles of each vertex: [mv + 1] starts, entries t * 4 + corner
+    const int *mv0, *mnv, *mt0, *mnt;   // [nm] first vertex, vertices, first triangle, triangles
+    const double *mpar;         // [nm][8] G_s, C, k_A, k_V, vertex mass, rest area, rest volume
+    double *mtot;               // [nm][2] area and volume at the start of the last step
+    unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
+    int *mflag;                 // [ncol * nseg] work item touched by the spreading
+    const int *colof;           // [nz][ny] column of a row, -1 solid
+    int *err;                   // error flags
 };
+
+constexpr double FIX_ONE = 1125899906842624.0;   // 2^50
+constexpr int ERR_STENCIL = 1, ERR_FORCE = 2;
 
 // Workgroup b -> work item such that each XCD (workgroups dealt round-robin
 // to the 8 XCDs) holds one contiguous range of items.
@@ -137,14 +170,27 @@ __device__ __forceinline__ C pull(const Dev3 &d, int c, int x, C dh[Q], long lon
 // One work item (wave-uniform): pull, moments, BGK collision with the Guo
 // term for the body force plus, on a slot (an item holding stencil nodes of
 // the fixed bodies), the spread force of each lane's node.
-template <typename T, int PAR, bool IB>
+// MODE 0: body force only; 1: a slot of fixed bodies (spread force from its
+// contribution ranges); 2: the membranes' fixed-point field, read and cleared
+// on flagged items.
+template <typename T, int PAR, int MODE>
 __device__ __forceinline__ void sweep_item(const Dev3 &d, int item, int slot) {
     using C = typename Arith3<T>::type;
     const int c = item / d.nseg;
     const int x = (item - c * d.nseg) * 64 + (int)(threadIdx.x & 63);
     if (x >= d.nx) return;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (IB) {
+    if (MODE == 2 && d.mflag[item]) {
+        unsigned long long *p = d.mforce + (long long)d.crow[20 * c] * d.pitch + x;
+        fx = (double)(long long)p[0] / FIX_ONE;
+        fy = (double)(long long)p[d.fs] / FIX_ONE;
+        fz = (double)(long long)p[2 * d.fs] / FIX_ONE;
+        p[0] = 0;
+        p[d.fs] = 0;
+        p[2 * d.fs] = 0;
+        if ((threadIdx.x & 63) == 0) d.mflag[item] = 0;
+    }
+    if (MODE == 1) {
         const int *sb = d.sbeg + 65 * slot + (threadIdx.x & 63);
         const int k1 = sb[1];
 #pragma unroll 4
@@ -199,11 +245,11 @@ __device__ __forceinline__ void sweep_item(const Dev3 &d, int item, int slot) {
 }
 
 
-template <typename T, int PAR>
+template <typename T, int PAR, int MODE>
 __global__ __launch_bounds__(64 * WAVES) void k3_sweep(Dev3 d) {
     int c, x, item;
     if (!item_of(d, c, x, item)) return;
-    sweep_item<T, PAR, false>(d, item, -1);
+    sweep_item<T, PAR, MODE>(d, item, -1);
 }
 
 // The ordinary part of a launch with fixed bodies: workgroups from nfront on
@@ -214,7 +260,7 @@ __device__ __forceinline__ void sweep_share(const Dev3 &d, int nfront, int lo, i
     const int b = xcd_block((int)blockIdx.x - nfront, (int)gridDim.x - nfront);
     const int item = __builtin_amdgcn_readfirstlane(lo + b * WAVES + (int)(threadIdx.x >> 6));
     if (item >= hi || d.islot[item] >= 0) return;
-    sweep_item<T, PAR, false>(d, item, -1);
+    sweep_item<T, PAR, 0>(d, item, -1);
 }
 
 // First launch of a step with fixed bodies: workgroups [0, nfb) give every
@@ -290,7 +336,208 @@ __global__ __launch_bounds__(64 * WAVES) void k3_sweep_ib(Dev3 d, int nfb, int s
     }
     const int slot = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6));
     if (slot >= d.nslot) return;
-    sweep_item<T, PAR, true>(d, d.fitem[slot], slot);
+    sweep_item<T, PAR, 1>(d, d.fitem[slot], slot);
+}
+
+// ---- deformable membranes --------------------------------------------------
+
+__device__ __forceinline__ double phi_cos(double r) {
+    r = fabs(r);
+    return r < 2.0 ? 0.25 * (1.0 + cos(M_PI * r / 2.0)) : 0.0;
+}
+
+// Stencil node of lane l (a = l & 3 along x, b = (l >> 2) & 3 along y,
+// c = l >> 4 along z) of a point: its column, x and weight; false (and an
+// error flag) if the node lies outside the cross-section or on a solid column.
+__device__ __forceinline__ bool stencil_node(const Dev3 &d, const double X[3], int l, int &col, int &x, double &W) {
+    const int ox = (int)floor(X[0]) - 1, oy = (int)floor(X[1]) - 1, oz = (int)floor(X[2]) - 1;
+    const int a = l & 3, b = (l >> 2) & 3, c = l >> 4;
+    const int y = oy + b, z = oz + c;
+    col = (y >= 0 && y < d.ny && z >= 0 && z < d.nz) ? d.colof[z * d.ny + y] : -1;
+    if (col < 0) {
+        atomicOr(d.err, ERR_STENCIL);
+        return false;
+    }
+    x = ((ox + a) % d.nx + d.nx) % d.nx;
+    W = phi_cos(X[0] - (ox + a)) * phi_cos(X[1] - y) * phi_cos(X[2] - z);
+    return true;
+}
+
+// u* at every membrane vertex at x^n (positions of parity mp): the velocity
+// of the streamed populations with half the body force at each stencil node,
+// weighted and summed over the wave.
+template <typename T, int PAR>
+__global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp) {
+    const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
+    if (v >= d.mv) return;
+    const double X[3] = {d.MX[mp][v], d.MX[mp][d.ms + v], d.MX[mp][2 * d.ms + v]};
+    int col, x;
+    double W, ux = 0.0, uy = 0.0, uz = 0.0;
+    if (stencil_node(d, X, (int)(threadIdx.x & 63), col, x, W)) {
+        double h[Q];
+        long long own;
+        const double ur = pull<T, double, PAR>(d, col, x, h, own);
+        double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int q = 0; q < Q; q++) {
+            drho += h[q];
+            jx += EX[q] * h[q];
+            jy += EY[q] * h[q];
+            jz += EZ[q] * h[q];
+        }
+        const double rho = 1.0 + drho;
+        ux = W * (ur + (jx + 0.5 * d.gx - drho * ur) / rho);
+        uy = W * (jy / rho);
+        uz = W * (jz / rho);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        ux += __shfl_xor(ux, o);
+        uy += __shfl_xor(uy, o);
+        uz += __shfl_xor(uz, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        d.Mus[v] = ux;
+        d.Mus[d.ms + v] = uy;
+        d.Mus[2 * d.ms + v] = uz;
+    }
+}
+
+constexpr int MB_THREADS = 1024;
+
+// Sum over the workgroup of two FP64 values (wave totals added in wave order).
+__device__ __forceinline__ void block_sum2(double &a, double &b, double (*red)[2]) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = a;
+        red[w][1] = b;
+    }
+    __syncthreads();
+    a = 0.0;
+    b = 0.0;
+    for (int k = 0; k < MB_THREADS / 64; k++) {
+        a += red[k][0];
+        b += red[k][1];
+    }
+}
+
+// One workgroup per membrane: area and enclosed volume (FP64, the volume
+// about the first vertex), then for every vertex the elastic force gathered
+// from its incident triangles in ascending order (Skalak corner force and
+// the two penalties' gradients), dV = a third of their areas, the update
+// dx = u* + f/(2m), x^{n+1} = x^n + dx, U = 3/2 dx - 1/2 dx_prev and the
+// direct force F = (U - u*) dV.  Positions of parity mp in, mp ^ 1 out.
+template <int MAXV>
+__global__ __launch_bounds__(MB_THREADS) void k3_m_body(Dev3 d, int mp) {
+    __shared__ double sx[MAXV], sy[MAXV], sz[MAXV];
+    __shared__ double red[MB_THREADS / 64][2];
+    const int m = blockIdx.x, v0 = d.mv0[m], nv = d.mnv[m];
+    const double *X = d.MX[mp];
+    for (int i = threadIdx.x; i < nv; i += MB_THREADS) {
+        sx[i] = X[v0 + i];
+        sy[i] = X[d.ms + v0 + i];
+        sz[i] = X[2 * d.ms + v0 + i];
+    }
+    __syncthreads();
+    const double *P = d.mpar + 8 * m;
+    const int t0 = d.mt0[m], nt = d.mnt[m];
+    double A = 0.0, V = 0.0;
+    for (int t = threadIdx.x; t < nt; t += MB_THREADS) {
+        const int *T = d.Mtri + 3 * (t0 + t);
+        const int i0 = T[0] - v0, i1 = T[1] - v0, i2 = T[2] - v0;
+        const double p[3] = {sx[i0] - sx[0], sy[i0] - sy[0], sz[i0] - sz[0]};
+        const double q[3] = {sx[i1] - sx[0], sy[i1] - sy[0], sz[i1] - sz[0]};
+        const double r[3] = {sx[i2] - sx[0], sy[i2] - sy[0], sz[i2] - sz[0]};
+        const double e1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]}, e2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        A += 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const double qr[3] = {q[1] * r[2] - q[2] * r[1], q[2] * r[0] - q[0] * r[2], q[0] * r[1] - q[1] * r[0]};
+        V += (p[0] * qr[0] + p[1] * qr[1] + p[2] * qr[2]) / 6.0;
+    }
+    block_sum2(A, V, red);
+    if (threadIdx.x == 0) {
+        d.mtot[2 * m] = A;
+        d.mtot[2 * m + 1] = V;
+    }
+    const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
+    for (int i = threadIdx.x; i < nv; i += MB_THREADS) {
+        const int v = v0 + i;
+        double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
+        for (int k = d.vtb[v]; k < d.vtb[v + 1]; k++) {
+            const int e = d.vtl[k], t = e >> 2, a = e & 3, b = (a + 1) % 3, c = (a + 2) % 3;
+            const int *T = d.Mtri + 3 * t;
+            const double *g = d.Mref + 8 * t;
+            const int j[3] = {T[0] - v0, T[1] - v0, T[2] - v0};
+            double F[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+            for (int s = 0; s < 3; s++) {
+                const double xs[3] = {sx[j[s]], sy[j[s]], sz[j[s]]};
+                for (int u = 0; u < 3; u++) {
+                    F[u][0] += xs[u] * g[2 * s];
+                    F[u][1] += xs[u] * g[2 * s + 1];
+                }
+            }
+            double Cm[2][2];
+            for (int r = 0; r < 2; r++)
+                for (int w = 0; w < 2; w++) Cm[r][w] = F[0][r] * F[0][w] + F[1][r] * F[1][w] + F[2][r] * F[2][w];
+            const double I1 = Cm[0][0] + Cm[1][1] - 2.0, I2 = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0] - 1.0;
+            const double w1 = 0.25 * P[0] * (2.0 * I1 + 2.0), w2 = 0.25 * P[0] * (-2.0 + 2.0 * P[1] * I2);
+            const double det = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0];
+            const double Ci[2][2] = {{Cm[1][1] / det, -Cm[0][1] / det}, {-Cm[1][0] / det, Cm[0][0] / det}};
+            const double e1[3] = {sx[j[1]] - sx[j[0]], sy[j[1]] - sy[j[0]], sz[j[1]] - sz[j[0]]};
+            const double e2[3] = {sx[j[2]] - sx[j[0]], sy[j[2]] - sy[j[0]], sz[j[2]] - sz[j[0]]};
+            double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+            const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            for (int u = 0; u < 3; u++) n[u] /= nn;
+            const double ga[2] = {g[2 * a], g[2 * a + 1]};
+            const double Cg[2] = {Ci[0][0] * ga[0] + Ci[0][1] * ga[1], Ci[1][0] * ga[0] + Ci[1][1] * ga[1]};
+            const double cb[3] = {sx[j[c]] - sx[j[b]], sy[j[c]] - sy[j[b]], sz[j[c]] - sz[j[b]]};
+            const double nbc[3] = {n[1] * cb[2] - n[2] * cb[1], n[2] * cb[0] - n[0] * cb[2], n[0] * cb[1] - n[1] * cb[0]};
+            const double xb[3] = {sx[j[b]] - sx[0], sy[j[b]] - sy[0], sz[j[b]] - sz[0]};
+            const double xc[3] = {sx[j[c]] - sx[0], sy[j[c]] - sy[0], sz[j[c]] - sz[0]};
+            const double bc[3] = {xb[1] * xc[2] - xb[2] * xc[1], xb[2] * xc[0] - xb[0] * xc[2], xb[0] * xc[1] - xb[1] * xc[0]};
+            for (int u = 0; u < 3; u++) {
+                const double Fg = F[u][0] * ga[0] + F[u][1] * ga[1];
+                const double FCg = F[u][0] * Cg[0] + F[u][1] * Cg[1];
+                const double fa = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
+                f[u] += fa - ca * 0.5 * nbc[u] - cv * bc[u] / 6.0;
+            }
+            dV += 0.5 * nn / 3.0;
+        }
+        const double xn[3] = {sx[i], sy[i], sz[i]};
+        for (int u = 0; u < 3; u++) {
+            const long long k = u * d.ms + v;
+            const double us = d.Mus[k];
+            const double dx = us + 0.5 * f[u] / P[4];
+            const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
+            d.MX[mp ^ 1][k] = xn[u] + dx;
+            d.Mdxm[k] = dx;
+            d.MF[k] = (U - us) * dV;
+        }
+    }
+}
+
+// Spreading at x^n: a wave per vertex, a lane per stencil node; each
+// contribution W F in fixed point, added with an integer atomic (exact, so
+// the field does not depend on the order), and the node's work item flagged.
+__global__ __launch_bounds__(64 * WAVES) void k3_m_spread(Dev3 d, int mp) {
+    const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
+    if (v >= d.mv) return;
+    const double X[3] = {d.MX[mp][v], d.MX[mp][d.ms + v], d.MX[mp][2 * d.ms + v]};
+    int col, x;
+    double W;
+    if (!stencil_node(d, X, (int)(threadIdx.x & 63), col, x, W)) return;
+    const long long node = (long long)d.crow[20 * col] * d.pitch + x;
+    for (int u = 0; u < 3; u++) {
+        const double c = W * d.MF[u * d.ms + v] * FIX_ONE;
+        if (!(fabs(c) < 4.0e18)) {   // beyond 2^12 in force units, or not finite
+            atomicOr(d.err, ERR_FORCE);
+            continue;
+        }
+        atomicAdd(d.mforce + u * d.fs + node, (unsigned long long)__double2ll_rn(c));
+    }
+    d.mflag[col * d.nseg + x / 64] = 1;
 }
 
 // Moments the next step starts from, FP64, into d.macro (fluid nodes).
@@ -372,10 +619,17 @@ struct capib3d_ctx {
     int nv = 0, nslot = 0, nslot_max = 0, share_u = 0, share_v = 0;
     std::vector<int> vcol, vxs;         // [nv][64]
     std::vector<double> vW, vdV;        // [nv][64], [nv]
+    // deformable membranes, host copies
+    int nm = 0, mvn = 0, mtn = 0, mpar = 0, mmaxv = 0;   // counts, positions' parity, largest membrane
+    std::vector<int> m_v0, m_nv, m_t0, m_nt, mtri;       // ranges, [mt][3]
+    std::vector<double> mref, mparam;                    // [mt][8], [nm][8]
     char *base = nullptr;
     size_t off_pop[2]{}, off_crow = 0, off_cK = 0, off_macro = 0, off_part = 0, ws = 0;
     size_t off_vnode = 0, off_vW = 0, off_vdV = 0, off_vpos = 0, off_vF = 0, off_contrib = 0, off_unode = 0,
            off_islot = 0, off_fitem = 0, off_sbeg = 0;
+    size_t off_MX[2]{}, off_Mdxm = 0, off_Mus = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
+           off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_mforce = 0,
+           off_mflag = 0, off_colof = 0, off_err = 0;
     Dev3 d{};
     std::string err = "no error";
 };
@@ -465,6 +719,11 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
         if (!(L.fp16_scale > 0.0) || std::frexp(L.fp16_scale, &ex) != 0.5) return CAPIB_E_ARG;   // a power of two
     }
     if (L.max_vertices < 0 || L.max_vertices > (1 << 24)) return CAPIB_E_ARG;
+    if (L.max_membranes < 0 || L.max_membrane_vertices < 0 || L.max_membrane_triangles < 0 ||
+        L.max_membrane_vertices > (1 << 24) || L.max_membrane_triangles > (1 << 25) ||
+        (L.max_membrane_vertices > 0) != (L.max_membranes > 0) ||
+        (L.max_membrane_vertices > 0) != (L.max_membrane_triangles > 0))
+        return CAPIB_E_ARG;
     capib3d_ctx *c = new capib3d_ctx();
     c->lat = L;
     c->stream = (hipStream_t)hip_stream;
@@ -502,6 +761,26 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_islot = o; o = al256(o + (M ? nitem * 4 : 0));
     c->off_fitem = o; o = al256(o + (size_t)c->nslot_max * 4);
     c->off_sbeg = o; o = al256(o + (size_t)c->nslot_max * 65 * 4);
+    const size_t MM = (size_t)L.max_membranes, MV = (size_t)L.max_membrane_vertices, MT = (size_t)L.max_membrane_triangles;
+    const size_t fs = (size_t)L.nz * L.ny * c->pitch;
+    for (int p = 0; p < 2; p++) { c->off_MX[p] = o; o = al256(o + 3 * MV * 8); }
+    c->off_Mdxm = o; o = al256(o + 3 * MV * 8);
+    c->off_Mus = o; o = al256(o + 3 * MV * 8);
+    c->off_MF = o; o = al256(o + 3 * MV * 8);
+    c->off_Mtri = o; o = al256(o + MT * 3 * 4);
+    c->off_Mref = o; o = al256(o + MT * 8 * 8);
+    c->off_vtb = o; o = al256(o + (MV ? MV + 1 : 0) * 4);
+    c->off_vtl = o; o = al256(o + 3 * MT * 4);
+    c->off_mv0 = o; o = al256(o + MM * 4);
+    c->off_mnv = o; o = al256(o + MM * 4);
+    c->off_mt0 = o; o = al256(o + MM * 4);
+    c->off_mnt = o; o = al256(o + MM * 4);
+    c->off_mpar = o; o = al256(o + MM * 8 * 8);
+    c->off_mtot = o; o = al256(o + MM * 2 * 8);
+    c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
+    c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
+    c->off_colof = o; o = al256(o + (size_t)L.ny * L.nz * 4);
+    c->off_err = o; o = al256(o + 4);
     c->ws = o;
     *out = c;
     return CAPIB_OK;
@@ -517,6 +796,8 @@ const char *capib3d_last_error(const capib3d_ctx *c) { return c ? c->err.c_str()
 
 static capib_status upload_tables(capib3d_ctx *c) {
     build_tables(c);
+    HIP3(c, hipMemcpyAsync(c->base + c->off_colof, c->colof.data(), c->colof.size() * 4, hipMemcpyHostToDevice,
+                           c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_crow, c->crow.data(), c->crow.size() * 4, hipMemcpyHostToDevice,
                            c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_cK, c->cK.data(), c->cK.size() * 8, hipMemcpyHostToDevice, c->stream));
@@ -558,6 +839,31 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.sbeg = (const int *)(c->base + c->off_sbeg);
     c->nv = 0;
     c->nslot = 0;
+    d.nm = 0;
+    d.mv = 0;
+    d.ms = L.max_membrane_vertices;
+    d.fs = (long long)L.nz * L.ny * c->pitch;
+    for (int p = 0; p < 2; p++) d.MX[p] = (double *)(c->base + c->off_MX[p]);
+    d.Mdxm = (double *)(c->base + c->off_Mdxm);
+    d.Mus = (double *)(c->base + c->off_Mus);
+    d.MF = (double *)(c->base + c->off_MF);
+    d.Mtri = (const int *)(c->base + c->off_Mtri);
+    d.Mref = (const double *)(c->base + c->off_Mref);
+    d.vtb = (const int *)(c->base + c->off_vtb);
+    d.vtl = (const int *)(c->base + c->off_vtl);
+    d.mv0 = (const int *)(c->base + c->off_mv0);
+    d.mnv = (const int *)(c->base + c->off_mnv);
+    d.mt0 = (const int *)(c->base + c->off_mt0);
+    d.mnt = (const int *)(c->base + c->off_mnt);
+    d.mpar = (const double *)(c->base + c->off_mpar);
+    d.mtot = (double *)(c->base + c->off_mtot);
+    d.mforce = (unsigned long long *)(c->base + c->off_mforce);
+    d.mflag = (int *)(c->base + c->off_mflag);
+    d.colof = (const int *)(c->base + c->off_colof);
+    d.err = (int *)(c->base + c->off_err);
+    c->nm = c->mvn = c->mtn = c->mpar = c->mmaxv = 0;
+    c->m_v0.clear(); c->m_nv.clear(); c->m_t0.clear(); c->m_nt.clear(); c->mtri.clear(); c->mref.clear();
+    c->mparam.clear();
     c->vcol.clear(); c->vxs.clear(); c->vW.clear(); c->vdV.clear();
     HIP3(c, hipMemsetAsync(c->base, 0, c->ws, c->stream));
     return upload_tables(c);
@@ -602,7 +908,31 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     const int nvb = ((c->nv + WAVES - 1) / WAVES + 7) / 8 * 8, nfb = ((c->nslot + WAVES - 1) / WAVES + 7) / 8 * 8;
     const dim3 g1(nfb + (s1 + WAVES - 1) / WAVES), g2(nvb + (s2 - s1 + WAVES - 1) / WAVES),
         g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
-    for (int t = 0; t < nsteps; t++) {
+    const dim3 gm((c->mvn + WAVES - 1) / WAVES);
+    for (int t = 0; t < nsteps && c->nm > 0; t++) {
+        const int mp = c->mpar;
+        if (c->par) {
+            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 1> : k3_m_interp<float, 1>), gm, blk, 0, c->stream, c->d, mp);
+        } else {
+            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 0> : k3_m_interp<float, 0>), gm, blk, 0, c->stream, c->d, mp);
+        }
+        if (c->mmaxv <= 1024)
+            hipLaunchKernelGGL(k3_m_body<1024>, dim3(c->nm), dim3(MB_THREADS), 0, c->stream, c->d, mp);
+        else
+            hipLaunchKernelGGL(k3_m_body<4096>, dim3(c->nm), dim3(MB_THREADS), 0, c->stream, c->d, mp);
+        hipLaunchKernelGGL(k3_m_spread, gm, blk, 0, c->stream, c->d, mp);
+        if (c->par)
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 2> : k3_sweep<float, 1, 2>), dim3(c->nblk), blk, 0,
+                               c->stream, c->d);
+        else
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 0, 2> : k3_sweep<float, 0, 2>), dim3(c->nblk), blk, 0,
+                               c->stream, c->d);
+        HIP3(c, hipGetLastError());
+        c->par ^= 1;
+        c->mpar ^= 1;
+        c->step++;
+    }
+    for (int t = 0; t < nsteps && c->nm == 0; t++) {
         if (ib && c->par) {
             hipLaunchKernelGGL((h16 ? k3_node_u<_Float16, 1> : k3_node_u<float, 1>), g1, blk, 0, c->stream, c->d, nfb, s1);
             hipLaunchKernelGGL((h16 ? k3_vertex<_Float16, 1> : k3_vertex<float, 1>), g2, blk, 0, c->stream, c->d, nvb, s1,
@@ -616,11 +946,11 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
             hipLaunchKernelGGL((h16 ? k3_sweep_ib<_Float16, 0> : k3_sweep_ib<float, 0>), g3, blk, 0, c->stream, c->d, nfb,
                                s2);
         } else if (c->par) {
-            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1> : k3_sweep<float, 1>), dim3(c->nblk), blk, 0, c->stream,
-                               c->d);
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 0> : k3_sweep<float, 1, 0>), dim3(c->nblk), blk, 0,
+                               c->stream, c->d);
         } else {
-            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 0> : k3_sweep<float, 0>), dim3(c->nblk), blk, 0, c->stream,
-                               c->d);
+            hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 0, 0> : k3_sweep<float, 0, 0>), dim3(c->nblk), blk, 0,
+                               c->stream, c->d);
         }
         HIP3(c, hipGetLastError());
         c->par ^= 1;
@@ -769,6 +1099,7 @@ capib_status capib3d_add_fixed_body(capib3d_ctx *c, int32_t nv, const double *xy
     if (s) return s;
     const capib3d_lattice &L = c->lat;
     if (nv < 1 || ntri < 0 || !xyz || (ntri > 0 && !tri)) return fail3(c, CAPIB_E_ARG, "bad body arrays");
+    if (c->nm > 0) return fail3(c, CAPIB_E_STATE, "fixed bodies and membranes do not share a context");
     if ((long long)c->nv + nv > L.max_vertices)
         return fail3(c, CAPIB_E_CAPACITY, "%d + %d vertices exceed the capacity of %d", c->nv, nv, L.max_vertices);
     for (int k = 0; k < 3 * ntri; k++)
@@ -848,6 +1179,195 @@ capib_status capib3d_set_ib_schedule(capib3d_ctx *c, int32_t share_node_u, int32
     c->share_v = share_vertex;
     return CAPIB_OK;
 }
+
+static void sub3h(const double *a, const double *b, double *o) {
+    o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+static void cross3h(const double *a, const double *b, double *o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3h(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz, int32_t ntri, const int32_t *tri,
+                                  const capib3d_membrane *par, int32_t *first_vertex) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    const capib3d_lattice &L = c->lat;
+    if (nv < 3 || ntri < 1 || !xyz || !tri || !par) return fail3(c, CAPIB_E_ARG, "bad membrane arrays");
+    if (c->nv > 0) return fail3(c, CAPIB_E_STATE, "fixed bodies and membranes do not share a context");
+    if (nv > 4096) return fail3(c, CAPIB_E_ARG, "%d vertices: a membrane holds at most 4096", nv);
+    if (c->nm >= L.max_membranes || (long long)c->mvn + nv > L.max_membrane_vertices ||
+        (long long)c->mtn + ntri > L.max_membrane_triangles)
+        return fail3(c, CAPIB_E_CAPACITY, "membrane capacity exceeded");
+    const double pv[5] = {par->gs, par->c, par->ka, par->kv, par->mass};
+    for (double x : pv)
+        if (!std::isfinite(x)) return fail3(c, CAPIB_E_ARG, "non-finite membrane parameter");
+    if (par->gs < 0 || par->ka < 0 || par->kv < 0 || !(par->mass > 0))
+        return fail3(c, CAPIB_E_ARG, "membrane moduli must be >= 0 and the mass > 0");
+    for (int k = 0; k < 3 * ntri; k++)
+        if (tri[k] < 0 || tri[k] >= nv) return fail3(c, CAPIB_E_ARG, "triangle vertex %d out of range", tri[k]);
+    for (int v = 0; v < nv; v++) {
+        const double *X = xyz + 3 * v;
+        if (!std::isfinite(X[0]) || !std::isfinite(X[1]) || !std::isfinite(X[2]) || std::fabs(X[0]) > 1e9)
+            return fail3(c, CAPIB_E_ARG, "vertex %d not finite", v);
+        const int oy = (int)std::floor(X[1]) - 1, oz = (int)std::floor(X[2]) - 1;
+        if (oy < 0 || oy + 3 >= L.ny || oz < 0 || oz + 3 >= L.nz)
+            return fail3(c, CAPIB_E_ARG, "vertex %d: stencil outside the cross-section", v);
+        for (int zc = 0; zc < 4; zc++)
+            for (int yb = 0; yb < 4; yb++)
+                if (c->colof[(size_t)(oz + zc) * L.ny + oy + yb] < 0)
+                    return fail3(c, CAPIB_E_ARG, "vertex %d: stencil node on a solid column", v);
+    }
+    // rest data of every triangle: the rest triangle in its own frame,
+    // X0 = 0, X1 = (l, 0), X2 = (p, q); the rows of [X1 - X0, X2 - X0]^-1 are
+    // the gradients g1, g2, and g0 = -g1 - g2
+    const int v0 = c->mvn, t0 = c->mtn;
+    std::vector<double> ref((size_t)ntri * 8, 0.0);
+    for (int t = 0; t < ntri; t++) {
+        double e1[3], e2[3], n[3], u1[3], u2[3];
+        sub3h(xyz + 3 * tri[3 * t + 1], xyz + 3 * tri[3 * t], e1);
+        sub3h(xyz + 3 * tri[3 * t + 2], xyz + 3 * tri[3 * t], e2);
+        cross3h(e1, e2, n);
+        const double l = std::sqrt(dot3h(e1, e1)), nn = std::sqrt(dot3h(n, n));
+        if (!(l > 0) || !(nn > 1e-12 * l * l)) return fail3(c, CAPIB_E_ARG, "triangle %d is degenerate", t);
+        for (int i = 0; i < 3; i++) { u1[i] = e1[i] / l; n[i] /= nn; }
+        cross3h(n, u1, u2);
+        const double pp = dot3h(e2, u1), qq = dot3h(e2, u2);
+        double *g = &ref[8 * (size_t)t];
+        g[2] = 1.0 / l;  g[3] = -pp / (l * qq);
+        g[4] = 0.0;      g[5] = 1.0 / qq;
+        g[0] = -g[2] - g[4];
+        g[1] = -g[3] - g[5];
+        g[6] = 0.5 * nn;
+    }
+    // rest area and volume, triangle by triangle, the volume about the first vertex
+    double A0 = 0.0, V0 = 0.0;
+    for (int t = 0; t < ntri; t++) {
+        double p[3], q[3], r[3], e1[3], e2[3], n[3], qr[3];
+        sub3h(xyz + 3 * tri[3 * t], xyz, p);
+        sub3h(xyz + 3 * tri[3 * t + 1], xyz, q);
+        sub3h(xyz + 3 * tri[3 * t + 2], xyz, r);
+        sub3h(q, p, e1);
+        sub3h(r, p, e2);
+        cross3h(e1, e2, n);
+        A0 += 0.5 * std::sqrt(dot3h(n, n));
+        cross3h(q, r, qr);
+        V0 += dot3h(p, qr) / 6.0;
+    }
+    if (!(A0 > 0) || !(V0 > 0)) return fail3(c, CAPIB_E_ARG, "membrane must enclose a positive volume (counter-clockwise from outside)");
+    c->m_v0.push_back(v0); c->m_nv.push_back(nv); c->m_t0.push_back(t0); c->m_nt.push_back(ntri);
+    for (int k = 0; k < 3 * ntri; k++) c->mtri.push_back(v0 + tri[k]);
+    c->mref.insert(c->mref.end(), ref.begin(), ref.end());
+    const double mp8[8] = {par->gs, par->c, par->ka, par->kv, par->mass, A0, V0, 0.0};
+    c->mparam.insert(c->mparam.end(), mp8, mp8 + 8);
+    c->nm++;
+    c->mvn += nv;
+    c->mtn += ntri;
+    c->mmaxv = std::max(c->mmaxv, nv);
+    // incident triangles of every vertex, ascending
+    std::vector<int> vtb(c->mvn + 1, 0), vtl(3 * (size_t)c->mtn);
+    for (int k = 0; k < 3 * c->mtn; k++) vtb[c->mtri[k] + 1]++;
+    for (int v = 0; v < c->mvn; v++) vtb[v + 1] += vtb[v];
+    std::vector<int> fill(vtb.begin(), vtb.end() - 1);
+    for (int t = 0; t < c->mtn; t++)
+        for (int a = 0; a < 3; a++) vtl[fill[c->mtri[3 * t + a]]++] = 4 * t + a;
+    // upload: the new positions into the current parity, the tables whole
+    const size_t MS = (size_t)L.max_membrane_vertices;
+    std::vector<double> plane(nv);
+    for (int u = 0; u < 3; u++) {
+        for (int v = 0; v < nv; v++) plane[v] = xyz[3 * v + u];
+        HIP3(c, hipMemcpyAsync(c->base + c->off_MX[c->mpar] + (u * MS + v0) * 8, plane.data(), nv * 8,
+                               hipMemcpyHostToDevice, c->stream));
+        HIP3(c, hipMemsetAsync(c->base + c->off_Mdxm + (u * MS + v0) * 8, 0, nv * 8, c->stream));
+        HIP3(c, hipMemsetAsync(c->base + c->off_MF + (u * MS + v0) * 8, 0, nv * 8, c->stream));
+    }
+    HIP3(c, hipMemcpyAsync(c->base + c->off_Mtri, c->mtri.data(), c->mtri.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_Mref, c->mref.data(), c->mref.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_vtb, vtb.data(), vtb.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_vtl, vtl.data(), vtl.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_mv0, c->m_v0.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_mnv, c->m_nv.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_mt0, c->m_t0.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_mnt, c->m_nt.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_mpar, c->mparam.data(), c->mparam.size() * 8, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    c->d.nm = c->nm;
+    c->d.mv = c->mvn;
+    if (first_vertex) *first_vertex = v0;
+    return CAPIB_OK;
+}
+
+// positions of parity mpar <-> [mv][3] host doubles
+static capib_status membrane_planes(capib3d_ctx *c, size_t off, double *out, const double *in) {
+    const size_t MS = (size_t)c->lat.max_membrane_vertices, n = c->mvn;
+    std::vector<double> pl(3 * n);
+    if (in) {
+        for (size_t v = 0; v < n; v++)
+            for (int u = 0; u < 3; u++) pl[u * n + v] = in[3 * v + u];
+        for (int u = 0; u < 3; u++)
+            HIP3(c, hipMemcpyAsync(c->base + off + u * MS * 8, &pl[u * n], n * 8, hipMemcpyHostToDevice, c->stream));
+        HIP3(c, hipStreamSynchronize(c->stream));
+        return CAPIB_OK;
+    }
+    for (int u = 0; u < 3; u++)
+        HIP3(c, hipMemcpyAsync(&pl[u * n], c->base + off + u * MS * 8, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    for (size_t v = 0; v < n; v++)
+        for (int u = 0; u < 3; u++) out[3 * v + u] = pl[u * n + v];
+    return CAPIB_OK;
+}
+
+capib_status capib3d_read_membrane_vertices(capib3d_ctx *c, double *xyz) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!xyz) return fail3(c, CAPIB_E_ARG, "null output");
+    return c->mvn ? membrane_planes(c, c->off_MX[c->mpar], xyz, nullptr) : CAPIB_OK;
+}
+
+capib_status capib3d_write_membrane_vertices(capib3d_ctx *c, const double *xyz) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!xyz) return fail3(c, CAPIB_E_ARG, "null input");
+    for (long long k = 0; k < 3LL * c->mvn; k++)
+        if (!std::isfinite(xyz[k])) return fail3(c, CAPIB_E_ARG, "non-finite vertex");
+    return c->mvn ? membrane_planes(c, c->off_MX[c->mpar], nullptr, xyz) : CAPIB_OK;
+}
+
+capib_status capib3d_membrane_spread_forces(capib3d_ctx *c, double *out) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!out) return fail3(c, CAPIB_E_ARG, "null output");
+    return c->mvn ? membrane_planes(c, c->off_MF, out, nullptr) : CAPIB_OK;
+}
+
+capib_status capib3d_membrane_totals(capib3d_ctx *c, int32_t m, double *out4) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!out4 || m < 0 || m >= c->nm) return fail3(c, CAPIB_E_ARG, "no membrane %d", m);
+    double t[2];
+    HIP3(c, hipMemcpyAsync(t, c->base + c->off_mtot + 16 * (size_t)m, 16, hipMemcpyDeviceToHost, c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    out4[0] = t[0];
+    out4[1] = t[1];
+    out4[2] = c->mparam[8 * (size_t)m + 5];
+    out4[3] = c->mparam[8 * (size_t)m + 6];
+    return CAPIB_OK;
+}
+
+capib_status capib3d_error_flags(capib3d_ctx *c, int32_t *flags) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!flags) return fail3(c, CAPIB_E_ARG, "null output");
+    HIP3(c, hipMemcpyAsync(flags, c->base + c->off_err, 4, hipMemcpyDeviceToHost, c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    return CAPIB_OK;
+}
+
+int32_t capib3d_membranes(const capib3d_ctx *c) { return c ? c->nm : 0; }
+int32_t capib3d_membrane_vertex_count(const capib3d_ctx *c) { return c ? c->mvn : 0; }
 
 capib_status capib3d_diagnostics(capib3d_ctx *c, double *out4, int64_t *step) {
     capib_status s = need_ws(c);

@@ -19,7 +19,12 @@ _dp = C.POINTER(C.c_double)
 class capib3d_lattice(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
                 ("geometry", C.c_int32), ("radius", C.c_double), ("storage", C.c_int32), ("fp16_scale", C.c_double),
-                ("max_vertices", C.c_int32)]
+                ("max_vertices", C.c_int32), ("max_membranes", C.c_int32), ("max_membrane_vertices", C.c_int32),
+                ("max_membrane_triangles", C.c_int32)]
+
+
+class capib3d_membrane(C.Structure):
+    _fields_ = [("gs", C.c_double), ("c", C.c_double), ("ka", C.c_double), ("kv", C.c_double), ("mass", C.c_double)]
 
 
 SIGNATURES = {
@@ -32,6 +37,15 @@ SIGNATURES = {
     "capib3d_body_forces": (C.c_int, [_P, _dp]),
     "capib3d_vertices": (C.c_int32, [_P]),
     "capib3d_set_ib_schedule": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "capib3d_add_membrane": (C.c_int, [_P, C.c_int32, _dp, C.c_int32, C.POINTER(C.c_int32), C.c_void_p,
+                                       C.POINTER(C.c_int32)]),
+    "capib3d_read_membrane_vertices": (C.c_int, [_P, _dp]),
+    "capib3d_write_membrane_vertices": (C.c_int, [_P, _dp]),
+    "capib3d_membrane_spread_forces": (C.c_int, [_P, _dp]),
+    "capib3d_membrane_totals": (C.c_int, [_P, C.c_int32, _dp]),
+    "capib3d_error_flags": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "capib3d_membranes": (C.c_int32, [_P]),
+    "capib3d_membrane_vertex_count": (C.c_int32, [_P]),
     "capib3d_step": (C.c_int, [_P, C.c_int32]),
     "capib3d_read_macro": (C.c_int, [_P, _dp, _dp, _dp, _dp]),
     "capib3d_read_populations": (C.c_int, [_P, _dp]),
@@ -79,13 +93,14 @@ class Tube3D:
     """A D3Q19 tube on the GPU (workspace allocated with torch)."""
 
     def __init__(self, nx, ny, nz, tau, gx, geometry=TUBE, radius=0.0, stream=None, storage=capib.FP32_SHIFTED,
-                 fp16_scale=1.0, max_vertices=0):
+                 fp16_scale=1.0, max_vertices=0, max_membranes=0, max_membrane_vertices=0, max_membrane_triangles=0):
         import torch
         self.torch = torch
         self.L = _lib()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius, storage, fp16_scale, max_vertices)
+        lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius, storage, fp16_scale, max_vertices, max_membranes,
+                              max_membrane_vertices, max_membrane_triangles)
         self.ctx = _P()
         st = self.L.capib3d_create(C.byref(lat), _P(self.stream.cuda_stream), C.byref(self.ctx))
         if st != capib.CAPIB_OK:
@@ -135,6 +150,54 @@ class Tube3D:
         out = np.zeros((self.vertices, 3))
         self._check(self.L.capib3d_body_forces(self.ctx, _d(out)))
         return out
+
+    def add_membrane(self, xyz, tri, gs, c, ka, kv, mass):
+        """A deformable membrane (vertices [nv][3], triangles [ntri][3]
+        counter-clockwise from outside; Skalak G_s and C, area and volume
+        penalties, vertex mass); returns its first vertex index."""
+        X = np.ascontiguousarray(xyz, dtype=np.float64)
+        T = np.ascontiguousarray(tri, dtype=np.int32)
+        assert X.ndim == 2 and X.shape[1] == 3 and T.ndim == 2 and T.shape[1] == 3
+        par = capib3d_membrane(gs, c, ka, kv, mass)
+        first = C.c_int32()
+        self._check(self.L.capib3d_add_membrane(self.ctx, X.shape[0], _d(X), T.shape[0],
+                                                T.ctypes.data_as(C.POINTER(C.c_int32)), C.cast(C.byref(par), C.c_void_p),
+                                                C.byref(first)))
+        return first.value
+
+    @property
+    def membranes(self):
+        return int(self.L.capib3d_membranes(self.ctx))
+
+    @property
+    def membrane_vertex_count(self):
+        return int(self.L.capib3d_membrane_vertex_count(self.ctx))
+
+    def membrane_vertices(self):
+        out = np.zeros((self.membrane_vertex_count, 3))
+        self._check(self.L.capib3d_read_membrane_vertices(self.ctx, _d(out)))
+        return out
+
+    def set_membrane_vertices(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        assert X.shape == (self.membrane_vertex_count, 3)
+        self._check(self.L.capib3d_write_membrane_vertices(self.ctx, _d(X)))
+
+    def membrane_spread_forces(self):
+        out = np.zeros((self.membrane_vertex_count, 3))
+        self._check(self.L.capib3d_membrane_spread_forces(self.ctx, _d(out)))
+        return out
+
+    def membrane_totals(self, m):
+        """(area, volume) at the start of the last step, (rest area, rest volume)"""
+        out = np.zeros(4)
+        self._check(self.L.capib3d_membrane_totals(self.ctx, int(m), _d(out)))
+        return out
+
+    def error_flags(self):
+        f = C.c_int32()
+        self._check(self.L.capib3d_error_flags(self.ctx, C.byref(f)))
+        return f.value
 
     def set_ib_schedule(self, share_node_u, share_vertex):
         """Percent of the work items swept in the launch that computes the

@@ -59,7 +59,9 @@ def test_tube3d_create_validates_without_a_gpu():
            tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, 7, 3.0, 0, 1.0),
            tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, 5, 1.0),
            tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, capib.FP16_SHIFTED, 3.0),
-           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, 0, 1.0, -1)]
+           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, 0, 1.0, -1),
+           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, 0, 1.0, 0, 1, 0, 0),
+           tube3d.capib3d_lattice(8, 8, 8, 1.0, 0.0, tube3d.TUBE, 3.0, 0, 1.0, 0, 1, 162, 0)]
     for lat in bad:
         assert L.capib3d_create(C.byref(lat), None, C.byref(ctx)) == capib.CAPIB_E_ARG
     lat = tube3d.capib3d_lattice(256, 64, 64, 1.0, 1e-7, tube3d.TUBE, 32.0, 0, 1.0)

@@ -21,8 +21,10 @@
  *       delta                                                   (Sec. 2.2)
  *   S3' with deformable membranes (closed triangulated surfaces): u*
  *       interpolated as in S3; elastic forces at x^n from Skalak's strain
- *       energy of each triangle (Skalak et al. 1973) plus penalties on the
- *       membrane's total area and enclosed volume (FP64 sums); the vertex
+ *       energy of each triangle (Skalak et al. 1973), a bending energy
+ *       k_b (1 - cos(theta - theta0)) of the dihedral angle at each edge, and
+ *       penalties on the membrane's total area and enclosed volume (FP64
+ *       sums); the vertex
  *       update of the 2D membranes, dx = u* + f/(2m), x^{n+1} = x^n + dx,
  *       U = 3/2 dx - 1/2 dx_prev; F = (U - u*) dV spread at x^n, dV a third
  *       of the adjacent triangles' area at x^n                  (Secs. 2.2-2.4 in 3D)
@@ -109,7 +111,11 @@ typedef struct {
     /* deformable membranes */
     int nm, mv, mt;         /* membranes, their vertices and triangles in all */
     int *m_v0, *m_nv, *m_t0, *m_nt;   /* [nm] vertex and triangle ranges */
-    double *m_par;          /* [nm][5] G_s, C, k_A, k_V, vertex mass */
+    double *m_par;          /* [nm][6] G_s, C, k_A, k_V, vertex mass, k_b */
+    int *m_e0, *m_ne;       /* [nm] edge ranges */
+    int me;                 /* edges in all */
+    int *Medge;             /* [me][4] x1, x2 (the edge), x3, x4 (opposite vertices) */
+    double *Mth0;           /* [me] rest dihedral angle */
     double *m_A0, *m_V0;    /* [nm] rest area and enclosed volume */
     double *MX, *Mdxm;      /* [mv][3] positions, displacement of the previous step */
     double *Mus, *Mf, *MF;  /* [mv][3] u*, elastic force, spread force of the current step */
@@ -148,6 +154,7 @@ void orc3_destroy(orc3 *s) {
     free(s->fluid); free(s->A); free(s->h); free(s->X); free(s->dV); free(s->f);
     free(s->m_v0); free(s->m_nv); free(s->m_t0); free(s->m_nt); free(s->m_par); free(s->m_A0); free(s->m_V0);
     free(s->MX); free(s->Mdxm); free(s->Mus); free(s->Mf); free(s->MF); free(s->Mtri); free(s->Mref);
+    free(s->m_e0); free(s->m_ne); free(s->Medge); free(s->Mth0);
     free(s);
 }
 
@@ -366,10 +373,48 @@ static void triangle_state(const orc3 *s, int t, double F[3][2], double Cm[2][2]
     *I2 = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0] - 1.0;
 }
 
+/* The dihedral angle at edge (x1, x2) between the triangles (x1, x2, x3)
+ * and (x2, x1, x4), both counter-clockwise from outside: with n1, n2 their
+ * unit normals and e the unit edge vector, theta = atan2((n1 x n2).e, n1.n2).
+ * Its gradient with respect to the four vertices, l = |x2 - x1|,
+ * N1 = (x2 - x1) x (x3 - x1), N2 = (x1 - x2) x (x4 - x2):
+ *   g3 = -l N1 / |N1|^2, g4 = -l N2 / |N2|^2,
+ *   g1 = ((x3 - x2).e / l^2) g3 + ((x4 - x2).e / l^2) g4 (e unnormalised),
+ *   g2 = -(g1 + g3 + g4) (the angle does not change under translation).    */
+static double dihedral(const double *x1, const double *x2, const double *x3, const double *x4, double g[4][3]) {
+    double e[3], a[3], b[3], N1[3], N2[3];
+    sub3(x2, x1, e);
+    sub3(x3, x1, a);
+    cross3(e, a, N1);
+    double me[3];
+    for (int i = 0; i < 3; i++) me[i] = -e[i];
+    sub3(x4, x2, b);
+    cross3(me, b, N2);
+    const double l = sqrt(dot3(e, e)), q1 = dot3(N1, N1), q2 = dot3(N2, N2);
+    double n1[3], n2[3], c12[3];
+    for (int i = 0; i < 3; i++) { n1[i] = N1[i] / sqrt(q1); n2[i] = N2[i] / sqrt(q2); }
+    cross3(n1, n2, c12);
+    const double th = atan2(dot3(c12, e) / l, dot3(n1, n2));
+    if (g) {
+        double d32[3], d42[3];
+        sub3(x3, x2, d32);
+        sub3(x4, x2, d42);
+        const double w3 = dot3(d32, e) / (l * l), w4 = dot3(d42, e) / (l * l);
+        for (int i = 0; i < 3; i++) {
+            g[2][i] = -l * N1[i] / q1;
+            g[3][i] = -l * N2[i] / q2;
+            g[0][i] = w3 * g[2][i] + w4 * g[3][i];
+            g[1][i] = -(g[0][i] + g[2][i] + g[3][i]);
+        }
+    }
+    return th;
+}
+
 /* Energies of membrane m (exported for the tests): Skalak, area penalty
- * k_A (A - A0)^2 / (2 A0), volume penalty k_V (V - V0)^2 / (2 V0).        */
-void orc3_membrane_energy(const orc3 *s, int m, double *out3) {
-    const double *P = s->m_par + 5 * m;
+ * k_A (A - A0)^2 / (2 A0), volume penalty k_V (V - V0)^2 / (2 V0), bending
+ * k_b sum over edges of (1 - cos(theta - theta0)).                          */
+void orc3_membrane_energy(const orc3 *s, int m, double *out4) {
+    const double *P = s->m_par + 6 * m;
     double ws = 0.0;
     for (int t = s->m_t0[m]; t < s->m_t0[m] + s->m_nt[m]; t++) {
         double F[3][2], Cm[2][2], I1, I2;
@@ -378,9 +423,16 @@ void orc3_membrane_energy(const orc3 *s, int m, double *out3) {
     }
     double A, V;
     membrane_totals(s, m, &A, &V);
-    out3[0] = ws;
-    out3[1] = P[2] * (A - s->m_A0[m]) * (A - s->m_A0[m]) / (2.0 * s->m_A0[m]);
-    out3[2] = P[3] * (V - s->m_V0[m]) * (V - s->m_V0[m]) / (2.0 * s->m_V0[m]);
+    double eb = 0.0;
+    for (int k = s->m_e0[m]; k < s->m_e0[m] + s->m_ne[m]; k++) {
+        const int *E = s->Medge + 4 * k;
+        const double th = dihedral(s->MX + 3 * E[0], s->MX + 3 * E[1], s->MX + 3 * E[2], s->MX + 3 * E[3], NULL);
+        eb += P[5] * (1.0 - cos(th - s->Mth0[k]));
+    }
+    out4[0] = ws;
+    out4[1] = P[2] != 0.0 ? P[2] * (A - s->m_A0[m]) * (A - s->m_A0[m]) / (2.0 * s->m_A0[m]) : 0.0;
+    out4[2] = P[3] != 0.0 ? P[3] * (V - s->m_V0[m]) * (V - s->m_V0[m]) / (2.0 * s->m_V0[m]) : 0.0;
+    out4[3] = eb;
 }
 
 /* Elastic forces of membrane m into Mf, minus the gradients of its three
@@ -390,12 +442,14 @@ void orc3_membrane_energy(const orc3 *s, int m, double *out3) {
  *   volume  -k_V (V - V0)/V0 * (x_b - r0) x (x_c - r0) / 6
  * with (a, b, c) the triangle's corners in its own cyclic order from a.     */
 static void membrane_forces(orc3 *s, int m) {
-    const double *P = s->m_par + 5 * m;
+    const double *P = s->m_par + 6 * m;
     const int v0 = s->m_v0[m];
     for (int v = v0; v < v0 + s->m_nv[m]; v++) s->Mf[3 * v] = s->Mf[3 * v + 1] = s->Mf[3 * v + 2] = 0.0;
     double A, V;
     membrane_totals(s, m, &A, &V);
-    const double ca = P[2] * (A - s->m_A0[m]) / s->m_A0[m], cv = P[3] * (V - s->m_V0[m]) / s->m_V0[m];
+    /* a penalty with a zero modulus contributes nothing (an open surface has no volume) */
+    const double ca = P[2] != 0.0 ? P[2] * (A - s->m_A0[m]) / s->m_A0[m] : 0.0;
+    const double cv = P[3] != 0.0 ? P[3] * (V - s->m_V0[m]) / s->m_V0[m] : 0.0;
     const double *r0 = s->MX + 3 * v0;
     for (int t = s->m_t0[m]; t < s->m_t0[m] + s->m_nt[m]; t++) {
         const int *T = s->Mtri + 3 * t;
@@ -431,6 +485,15 @@ static void membrane_forces(orc3 *s, int m) {
             for (int i = 0; i < 3; i++) f[i] += fa[i] - ca * 0.5 * nbc[i] - cv * bc[i] / 6.0;
         }
     }
+    /* bending: -k_b sin(theta - theta0) grad theta, edge by edge */
+    for (int k = s->m_e0[m]; k < s->m_e0[m] + s->m_ne[m]; k++) {
+        const int *E = s->Medge + 4 * k;
+        double g[4][3];
+        const double th = dihedral(s->MX + 3 * E[0], s->MX + 3 * E[1], s->MX + 3 * E[2], s->MX + 3 * E[3], g);
+        const double sb = -P[5] * sin(th - s->Mth0[k]);
+        for (int r = 0; r < 4; r++)
+            for (int i = 0; i < 3; i++) s->Mf[3 * E[r] + i] += sb * g[r][i];
+    }
 }
 
 /* S3' for every membrane vertex (see the file header) */
@@ -448,7 +511,7 @@ static void membranes3(orc3 *s) {
         for (int k = 0; k < 3; k++) dV[T[k]] += area / 3.0;
     }
     for (int m = 0; m < s->nm; m++) {
-        const double mass = s->m_par[5 * m + 4];
+        const double mass = s->m_par[6 * m + 4];
         for (int v = s->m_v0[m]; v < s->m_v0[m] + s->m_nv[m]; v++) {
             double Xn[3], F[3];
             for (int q = 0; q < 3; q++) {
@@ -473,7 +536,7 @@ static void membranes3(orc3 *s) {
  * node must be fluid now; returns the index of its first vertex among the
  * membrane vertices, or -1.                                                 */
 int orc3_add_membrane(orc3 *s, int nv, const double *xyz, int ntri, const int *tri, double gs, double c, double ka,
-                      double kv, double mass) {
+                      double kv, double mass, double kb) {
     for (int v = 0; v < nv; v++) {
         int o[3];
         double w[3][4];
@@ -489,7 +552,9 @@ int orc3_add_membrane(orc3 *s, int nv, const double *xyz, int ntri, const int *t
     s->m_nv = (int *)realloc(s->m_nv, sizeof(int) * s->nm);
     s->m_t0 = (int *)realloc(s->m_t0, sizeof(int) * s->nm);
     s->m_nt = (int *)realloc(s->m_nt, sizeof(int) * s->nm);
-    s->m_par = (double *)realloc(s->m_par, sizeof(double) * 5 * s->nm);
+    s->m_par = (double *)realloc(s->m_par, sizeof(double) * 6 * s->nm);
+    s->m_e0 = (int *)realloc(s->m_e0, sizeof(int) * s->nm);
+    s->m_ne = (int *)realloc(s->m_ne, sizeof(int) * s->nm);
     s->m_A0 = (double *)realloc(s->m_A0, sizeof(double) * s->nm);
     s->m_V0 = (double *)realloc(s->m_V0, sizeof(double) * s->nm);
     s->MX = (double *)realloc(s->MX, sizeof(double) * 3 * s->mv);
@@ -500,8 +565,8 @@ int orc3_add_membrane(orc3 *s, int nv, const double *xyz, int ntri, const int *t
     s->Mtri = (int *)realloc(s->Mtri, sizeof(int) * 3 * s->mt);
     s->Mref = (double *)realloc(s->Mref, sizeof(double) * 7 * s->mt);
     s->m_v0[m] = v0; s->m_nv[m] = nv; s->m_t0[m] = t0; s->m_nt[m] = ntri;
-    const double par[5] = {gs, c, ka, kv, mass};
-    memcpy(s->m_par + 5 * m, par, sizeof par);
+    const double par[6] = {gs, c, ka, kv, mass, kb};
+    memcpy(s->m_par + 6 * m, par, sizeof par);
     memcpy(s->MX + 3 * v0, xyz, sizeof(double) * 3 * nv);
     memset(s->Mdxm + 3 * v0, 0, sizeof(double) * 3 * nv);
     memset(s->Mus + 3 * v0, 0, sizeof(double) * 3 * nv);
@@ -531,6 +596,28 @@ int orc3_add_membrane(orc3 *s, int nv, const double *xyz, int ntri, const int *t
     membrane_totals(s, m, &A, &V);
     s->m_A0[m] = A;
     s->m_V0[m] = V;
+    /* the edges: each directed edge a -> b of a triangle with a < b, paired
+     * with the triangle holding b -> a; x3 and x4 their opposite vertices
+     * (edges in the order their first triangle and corner appear)           */
+    s->m_e0[m] = s->me;
+    s->m_ne[m] = 0;
+    for (int t = 0; t < ntri; t++)
+        for (int k = 0; k < 3; k++) {
+            const int a = tri[3 * t + k], b = tri[3 * t + (k + 1) % 3], c3 = tri[3 * t + (k + 2) % 3];
+            if (a >= b) continue;
+            int c4 = -1;
+            for (int u = 0; u < ntri && c4 < 0; u++)
+                for (int j = 0; j < 3; j++)
+                    if (tri[3 * u + j] == b && tri[3 * u + (j + 1) % 3] == a) { c4 = tri[3 * u + (j + 2) % 3]; break; }
+            if (c4 < 0) continue;   /* a boundary edge: no dihedral angle */
+            s->Medge = (int *)realloc(s->Medge, sizeof(int) * 4 * (s->me + 1));
+            s->Mth0 = (double *)realloc(s->Mth0, sizeof(double) * (s->me + 1));
+            int *E = s->Medge + 4 * s->me;
+            E[0] = v0 + a; E[1] = v0 + b; E[2] = v0 + c3; E[3] = v0 + c4;
+            s->Mth0[s->me] = dihedral(s->MX + 3 * E[0], s->MX + 3 * E[1], s->MX + 3 * E[2], s->MX + 3 * E[3], NULL);
+            s->me++;
+            s->m_ne[m]++;
+        }
     if (!s->f) s->f = (double *)calloc((size_t)(3 * s->n), sizeof(double));
     return v0;
 }
@@ -541,6 +628,15 @@ void orc3_membrane_set_vertices(orc3 *s, const double *in) { if (s->mv) memcpy(s
 void orc3_membrane_forces(orc3 *s, int m, double *out) {
     membrane_forces(s, m);
     memcpy(out, s->Mf + 3 * s->m_v0[m], sizeof(double) * 3 * s->m_nv[m]);
+}
+/* the current dihedral angle at each edge of membrane m, and its rest value */
+int orc3_membrane_dihedrals(const orc3 *s, int m, double *theta, double *theta0) {
+    for (int k = 0; k < s->m_ne[m]; k++) {
+        const int *E = s->Medge + 4 * (s->m_e0[m] + k);
+        if (theta) theta[k] = dihedral(s->MX + 3 * E[0], s->MX + 3 * E[1], s->MX + 3 * E[2], s->MX + 3 * E[3], NULL);
+        if (theta0) theta0[k] = s->Mth0[s->m_e0[m] + k];
+    }
+    return s->m_ne[m];
 }
 /* spread force F = (U - u*) dV of the last step at every membrane vertex, [mv][3] */
 void orc3_membrane_spread_forces(const orc3 *s, double *out) { if (s->mv) memcpy(out, s->MF, sizeof(double) * 3 * s->mv); }

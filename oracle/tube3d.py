@@ -44,13 +44,15 @@ def _L():
         L.orc3_ib_force.argtypes = [C.c_void_p, _dp]
         L.orc3_vertex_weights.argtypes = [C.c_void_p, _dp]
         L.orc3_add_membrane.restype = C.c_int
-        L.orc3_add_membrane.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)] + [C.c_double] * 5
+        L.orc3_add_membrane.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)] + [C.c_double] * 6
         L.orc3_membrane_vertices.argtypes = [C.c_void_p, _dp]
         L.orc3_membrane_set_vertices.argtypes = [C.c_void_p, _dp]
         L.orc3_membrane_forces.argtypes = [C.c_void_p, C.c_int, _dp]
         L.orc3_membrane_spread_forces.argtypes = [C.c_void_p, _dp]
         L.orc3_membrane_totals.argtypes = [C.c_void_p, C.c_int, _dp]
         L.orc3_membrane_energy.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.orc3_membrane_dihedrals.restype = C.c_int
+        L.orc3_membrane_dihedrals.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         _ready = True
     return L
 
@@ -145,14 +147,14 @@ class Tube:
         return out
 
     # deformable membranes
-    def add_membrane(self, xyz, tri, gs, c, ka, kv, mass):
+    def add_membrane(self, xyz, tri, gs, c, ka, kv, mass, kb=0.0):
         """A closed triangulated membrane (Skalak G_s, C; area and volume
-        penalties k_A, k_V; vertex mass); returns its first vertex index among
-        the membrane vertices."""
+        penalties k_A, k_V; vertex mass; bending k_b); returns its first
+        vertex index among the membrane vertices."""
         xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
         tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
         v0 = self.L.orc3_add_membrane(self.p, len(xyz), _d(xyz), len(tri), tri.ctypes.data_as(C.POINTER(C.c_int)),
-                                      gs, c, ka, kv, mass)
+                                      gs, c, ka, kv, mass, kb)
         if v0 < 0:
             raise ValueError("a stencil node of the membrane is solid or outside the cross-section")
         self.mv = getattr(self, "mv", 0) + len(xyz)
@@ -186,7 +188,14 @@ class Tube:
         return out
 
     def membrane_energy(self, m):
-        """(Skalak, area penalty, volume penalty)"""
-        out = np.zeros(3)
+        """(Skalak, area penalty, volume penalty, bending)"""
+        out = np.zeros(4)
         self.L.orc3_membrane_energy(self.p, m, _d(out))
         return out
+
+    def membrane_dihedrals(self, m):
+        """(current, rest) dihedral angle of every interior edge of membrane m"""
+        n = self.L.orc3_membrane_dihedrals(self.p, m, None, None)
+        th, th0 = np.zeros(n), np.zeros(n)
+        self.L.orc3_membrane_dihedrals(self.p, m, _d(th), _d(th0))
+        return th, th0

@@ -1,23 +1,25 @@
 """Pins of the FP64 oracle's deformable membranes in 3D (Skalak elements,
-area and volume penalties, the 2D path's vertex update carried to 3D),
+dihedral bending, area and volume penalties, the 2D path's vertex update
+carried to 3D),
 each against something other than the oracle's own formulas: invariants
 written from edge lengths and areas, the closed form of a uniform
-dilation, central finite differences of the energies, the conservation of
-force and torque, and one step in a uniform flow."""
+dilation, the icosahedron's dihedral angle, a hinge folded by a known angle,
+central finite differences of the energies, the conservation of force and
+torque, and one step in a uniform flow."""
 import numpy as np
 import pytest
 
 from oracle import tube3d as otube
 from paper_2210_06043_amd import inputs
 
-GS, CS, KA, KV, MASS = 2e-3, 2.0, 0.05, 0.03, 1.0
+GS, CS, KA, KV, MASS, KB = 2e-3, 2.0, 0.05, 0.03, 1.0, 4e-3
 
 
 def _box_with(xyz, tri, n=20, **kw):
     t = otube.Tube(n, n, n, 1.0, 0.0, geom=otube.BOX)
-    p = dict(gs=GS, c=CS, ka=KA, kv=KV, mass=MASS)
+    p = dict(gs=GS, c=CS, ka=KA, kv=KV, mass=MASS, kb=KB)
     p.update(kw)
-    t.add_membrane(xyz, tri, p["gs"], p["c"], p["ka"], p["kv"], p["mass"])
+    t.add_membrane(xyz, tri, p["gs"], p["c"], p["ka"], p["kv"], p["mass"], p["kb"])
     return t
 
 
@@ -74,7 +76,7 @@ def test_uniform_dilation_energies_in_closed_form(lam):
     ea = KA * (lam ** 2 * A0 - A0) ** 2 / (2 * A0)
     ev = KV * (lam ** 3 * V0 - V0) ** 2 / (2 * V0)
     E = t.membrane_energy(0)
-    assert E == pytest.approx([ws, ea, ev], rel=1e-9, abs=1e-18)
+    assert E == pytest.approx([ws, ea, ev, 0.0], rel=1e-9, abs=1e-15)   # dilation keeps every angle
     # along the dilation mode the forces do the closed form's work: with r_v
     # the rest radius vector, dE/dlam = -sum_v f_v . r_v
     F = t.membrane_forces(0)
@@ -166,9 +168,55 @@ def test_a_stretched_membrane_relaxes_in_a_quiescent_box():
     t = otube.Tube(24, 24, 24, 1.0, 0.0, geom=otube.BOX)
     t.add_membrane(xyz, tri, 5e-3, 1.0, 0.05, 0.05, 1.0)
     t.set_membrane_vertices(c0 + 1.03 * (xyz - c0))
-    e0 = t.membrane_energy(0)
+    e0 = t.membrane_energy(0)[:3]
     t.step(300)
-    e1 = t.membrane_energy(0)
+    e1 = t.membrane_energy(0)[:3]
     assert np.all(e1 < e0)
     mom = t.totals()[1:]
     assert np.abs(mom).max() < 1e-13
+
+
+def test_icosahedron_dihedral_angles():
+    """Every edge of the regular icosahedron has the same angle between its
+    faces' outward normals, pi minus the interior dihedral angle
+    arccos(-sqrt(5)/3); the rest angles are the current ones."""
+    xyz, tri = inputs.icosphere(0, 2.0, (10.0, 10.0, 10.0))
+    t = _box_with(xyz, tri)
+    th, th0 = t.membrane_dihedrals(0)
+    assert len(th) == 30 and np.array_equal(th, th0)
+    assert np.abs(np.abs(th) - (np.pi - np.arccos(-np.sqrt(5) / 3))).max() < 1e-12
+    assert np.all(np.sign(th) == np.sign(th[0]))
+
+
+@pytest.mark.parametrize("delta", [0.05, -0.3, 1.2])
+def test_a_hinge_folded_by_a_known_angle(delta):
+    """Two triangles sharing an edge (an open surface: one interior edge);
+    turning the far vertex about the edge by delta changes the dihedral angle
+    by delta, so the bending energy is k_b (1 - cos delta), and the forces are
+    minus its gradient."""
+    x = np.array([[10.0, 10.0, 10.0], [11.5, 10.2, 10.1], [10.6, 11.3, 10.0], [10.9, 9.1, 10.4]])
+    tri = np.array([[0, 1, 2], [1, 0, 3]])
+    t = otube.Tube(20, 20, 20, 1.0, 0.0, geom=otube.BOX)
+    t.add_membrane(x, tri, 0.0, 0.0, 0.0, 0.0, 1.0, KB)
+    e = (x[1] - x[0]) / np.linalg.norm(x[1] - x[0])
+    r = x[3] - x[0]
+    # Rodrigues' rotation of x3 about the edge axis through x0
+    rr = r * np.cos(delta) + np.cross(e, r) * np.sin(delta) + e * np.dot(e, r) * (1 - np.cos(delta))
+    X = x.copy()
+    X[3] = x[0] + rr
+    t.set_membrane_vertices(X)
+    th, th0 = t.membrane_dihedrals(0)
+    assert len(th) == 1 and abs(abs(th[0] - th0[0]) - abs(delta)) < 1e-12
+    assert t.membrane_energy(0)[3] == pytest.approx(KB * (1 - np.cos(delta)), rel=1e-12)
+    F = t.membrane_forces(0)
+    h = 1e-6
+    for v in range(4):
+        for q in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[v, q] += h
+            Xm[v, q] -= h
+            t.set_membrane_vertices(Xp)
+            ep = t.membrane_energy(0)[3]
+            t.set_membrane_vertices(Xm)
+            em = t.membrane_energy(0)[3]
+            assert F[v, q] == pytest.approx(-(ep - em) / (2 * h), rel=1e-5, abs=1e-9 * KB)

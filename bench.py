@@ -504,7 +504,8 @@ def tube3d_section(args):
 
 def tube3d_membranes(p):
     """Four 2562-vertex oblate cells (radius 8, axes 1, 1, 0.5) and a
-    642-vertex sphere of radius 4 in the 256 x 64 x 64 tube."""
+    642-vertex sphere of radius 4 in the 256 x 64 x 64 tube (Skalak, bending,
+    area and volume penalties)."""
     from paper_2210_06043_amd import inputs
     c = 0.5 * (p["ny"] - 1)
     cells = [inputs.icosphere(4, 8.0, (40.2 + 60 * k, c + (9.0, -7.5, 4.0, -10.0)[k], c + (2.0, 8.0, -9.0, -1.5)[k]),
@@ -512,7 +513,7 @@ def tube3d_membranes(p):
     return cells + [inputs.icosphere(3, 4.0, (128.7, c - 3.0, c - 17.0))]
 
 
-MEMBRANE_PARAMS = dict(gs=5e-3, c=1.0, ka=0.05, kv=0.05, mass=1.0)
+MEMBRANE_PARAMS = dict(gs=5e-3, c=1.0, ka=0.05, kv=0.05, mass=1.0, kb=2e-3)
 
 
 def tube3d_membrane_run(p, prof, warmup, steps):
@@ -537,8 +538,9 @@ def tube3d_membrane_run(p, prof, warmup, steps):
     return {"membranes": len(ms_), "vertices": g.membrane_vertex_count, "triangles": sum(len(m[1]) for m in ms_),
             "ms_per_step": e0.elapsed_time(e1) / steps, "error_flags": g.error_flags(),
             "volume_drift_max": float(max(abs(x[1] / x[3] - 1) for x in t)),
-            "note": "four launches per step: k3_m_interp (a wave per vertex), k3_m_body (a workgroup per membrane, "
-                    "FP64), k3_m_spread (fixed-point atomics), k3_sweep reading the field on flagged items"}
+            "note": "three launches per step: k3_m_interp (a wave per vertex; area and volume per 64 triangles), "
+                    "k3_m_body (a wave per vertex: forces, update, spread record, work-item lists), k3_sweep gathering "
+                    "the lists of flagged items"}
 
 
 def capib_fp16():

@@ -80,9 +80,12 @@ typedef struct {
  *   c     Skalak's C
  *   ka    penalty k_A (A - A0)^2 / (2 A0) on the total area
  *   kv    penalty k_V (V - V0)^2 / (2 V0) on the enclosed volume
- *   mass  vertex mass m of the update dx = u* + f/(2m)                      */
+ *   mass  vertex mass m of the update dx = u* + f/(2m)
+ *   kb    bending k_b (1 - cos(theta - theta0)) at every interior edge,
+ *         theta = atan2((n1 x n2).e, n1.n2) the angle between the adjacent
+ *         faces' outward normals n1, n2 about the unit edge vector e         */
 typedef struct {
-    double gs, c, ka, kv, mass;
+    double gs, c, ka, kv, mass, kb;
 } capib3d_membrane;
 
 typedef struct capib3d_ctx capib3d_ctx;
@@ -123,14 +126,17 @@ capib_status capib3d_body_forces(capib3d_ctx *ctx, double *out);
 int32_t capib3d_vertices(const capib3d_ctx *ctx);
 
 /* A deformable membrane: nv vertices (xyz, [nv][3] host doubles, lattice
- * coordinates; at most 4096) and ntri triangles (tri, [ntri][3], counter-
- * clockwise seen from outside), its rest shape the given one.  Each step:
+ * coordinates) and ntri triangles (tri, [ntri][3], counter-clockwise seen
+ * from outside; at most 32 meeting at a vertex, and a vertex in at most 32
+ * edge terms; nx >= 4), its rest shape the given one.  Each step:
  * u* interpolated at x^n (as for fixed bodies), the elastic force f at x^n
- * (Skalak, area and volume terms, FP64 sums), dx = u* + f/(2m), x^{n+1} =
+ * (Skalak, bending, area and volume terms, FP64), dx = u* + f/(2m), x^{n+1} =
  * x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV spread at x^n with dV
  * a third of the adjacent triangles' area at x^n.  Every stencil node must
  * be fluid now (CAPIB_E_ARG; a node that leaves the fluid later raises
- * error flag 1 and contributes nothing), degenerate triangles or a
+ * error flag 1 and contributes nothing; a work item, 64 nodes along x of
+ * one column, lists at most 1024 vertices whose stencil touches it, beyond
+ * which error flag 4 is raised), degenerate triangles or a
  * non-positive enclosed volume give CAPIB_E_ARG, capacity CAPIB_E_CAPACITY,
  * a context with fixed bodies CAPIB_E_STATE.  *first_vertex (may be NULL)
  * receives its first vertex among the membrane vertices.  Syncs. */
@@ -144,12 +150,14 @@ capib_status capib3d_write_membrane_vertices(capib3d_ctx *ctx, const double *xyz
 /* The direct force F = (U - u*) dV of the last step at every membrane
  * vertex, [membrane vertices][3].  Syncs. */
 capib_status capib3d_membrane_spread_forces(capib3d_ctx *ctx, double *out);
-/* Membrane m's FP64 area and enclosed volume at the start of the last step
- * (the device sums the step used), and its rest area and volume.  Syncs. */
+/* Membrane m's area and enclosed volume at the start of the last step (the
+ * sums the step used: FP64 per wave of 64 triangles, added in 2^-32 fixed
+ * point), and its rest area and volume.  Syncs. */
 capib_status capib3d_membrane_totals(capib3d_ctx *ctx, int32_t m, double *out4);
 /* Error flags raised on the device since the workspace was bound: 1 a
  * membrane stencil node outside the fluid, 2 a spread contribution beyond
- * the fixed-point range (2^12) or not finite.  Syncs. */
+ * the fixed-point range (2^12) or not finite, 4 a work item's vertex list
+ * full.  Syncs. */
 capib_status capib3d_error_flags(capib3d_ctx *ctx, int32_t *flags);
 /* Membranes, and their vertices in all. */
 int32_t capib3d_membranes(const capib3d_ctx *ctx);

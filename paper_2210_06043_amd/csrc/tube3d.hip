@@ -34,20 +34,24 @@
 //
 // Deformable membranes (closed triangulated surfaces: Skalak elements and
 // penalties on total area and enclosed volume, Secs. 2.2-2.4 read in 3D).
-// Their stencils move, so the spreading is done by atomics: each spread
-// contribution is rounded to a 64-bit fixed-point integer (2^-50 units) and
-// added with an integer atomic, which is exact and associative, so the sum
-// does not depend on the order and every run gives the same bits.  A step is
-// four launches: k3_m_interp (a wave per vertex, a lane per stencil node),
-// k3_m_body (a workgroup per membrane: FP64 positions in LDS, FP64 area and
-// volume sums, per-vertex forces gathered from the incident triangles in
-// ascending order, the vertex update, the direct force), k3_m_spread (a wave
-// per vertex: fixed-point atomics into a force field, and a flag on every work
-// item touched), then the sweep, which reads and clears the field on flagged
-// items.
+// Their stencils move, so the coupling is rebuilt every step on the device,
+// and every sum whose order the schedule does not fix is taken in 64-bit
+// fixed point (integer adds are exact, so the order does not matter and every
+// run gives the same bits).  A step is three launches.  k3_m_interp: a wave
+// per vertex (a lane per stencil node: u*), and a wave per 64 triangles of a
+// membrane (its FP64 area and volume terms, summed over the wave, added to the
+// membrane's totals in 2^-32 units).  k3_m_body: a wave per vertex (a lane per
+// incident triangle: Skalak corner force and the penalties' gradients; a lane
+// per edge the vertex belongs to: the bending force; summed over the wave),
+// the vertex update and the direct force; the vertex's spread
+// record (stencil origin, the 12 delta weights, F) and its entry in the list
+// of every work item its stencil touches.  The sweep: a work item with a list
+// adds the contributions W F of its entries, one entry per lane, in 2^-50
+// units into the wave's own LDS row of 64 nodes, then collides.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -102,16 +106,27 @@ struct Dev3 {
     const double *Mref;         // [mt][8] rest gradients g0, g1, g2 (2 each), rest area
     const int *vtb, *vtl;       // incident triangles of each vertex: [mv + 1] starts, entries t * 4 + corner
     const int *mv0, *mnv, *mt0, *mnt;   // [nm] first vertex, vertices, first triangle, triangles
-    const double *mpar;         // [nm][8] G_s, C, k_A, k_V, vertex mass, rest area, rest volume
+    const double *mpar;         // [nm][8] G_s, C, k_A, k_V, vertex mass, rest area, rest volume, k_b
+    const int *Medge;           // [me][4] edge (x1, x2) and its opposite vertices x3, x4
+    const double *Mth0;         // [me] rest dihedral angle
+    const int *veb, *vel;       // edge terms of each vertex: [mv + 1] starts, entries edge * 4 + role
     double *mtot;               // [nm][2] area and volume at the start of the last step
-    unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
-    int *mflag;                 // [ncol * nseg] work item touched by the spreading
+    const int *vmem;            // [mv] membrane of each vertex
+    const int *twave;           // [ntw][2] membrane and first triangle of each totals wave
+    int ntw, mcap;              // totals waves; capacity of membranes
+    unsigned long long *mtfx;   // [2][mcap][2] area and volume by parity, fixed point (2^-32)
+    double *mrec;               // [mv][16] spread record: w (3 x 4 delta weights), F (3)
+    int *morg;                  // [mv][4] stencil origin (x, y, z) of the record
+    int *icount;                // [ncol * nseg] entries in each work item's list
+    int *ilist;                 // [ncol * nseg][ICAP] vertices whose stencil touches the item
     const int *colof;           // [nz][ny] column of a row, -1 solid
     int *err;                   // error flags
 };
 
-constexpr double FIX_ONE = 1125899906842624.0;   // 2^50
-constexpr int ERR_STENCIL = 1, ERR_FORCE = 2;
+constexpr double FIX_ONE = 1125899906842624.0;   // 2^50, spread contributions
+constexpr double FIX_TOT = 4294967296.0;         // 2^32, area and volume
+constexpr int ICAP = 1024;                       // list capacity of a work item
+constexpr int ERR_STENCIL = 1, ERR_FORCE = 2, ERR_LIST = 4;
 
 // Workgroup b -> work item such that each XCD (workgroups dealt round-robin
 // to the 8 XCDs) holds one contiguous range of items.
@@ -178,18 +193,47 @@ __device__ __forceinline__ void sweep_item(const Dev3 &d, int item, int slot) {
     using C = typename Arith3<T>::type;
     const int c = item / d.nseg;
     const int x = (item - c * d.nseg) * 64 + (int)(threadIdx.x & 63);
-    if (x >= d.nx) return;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (MODE == 2 && d.mflag[item]) {
-        unsigned long long *p = d.mforce + (long long)d.crow[20 * c] * d.pitch + x;
-        fx = (double)(long long)p[0] / FIX_ONE;
-        fy = (double)(long long)p[d.fs] / FIX_ONE;
-        fz = (double)(long long)p[2 * d.fs] / FIX_ONE;
-        p[0] = 0;
-        p[d.fs] = 0;
-        p[2 * d.fs] = 0;
-        if ((threadIdx.x & 63) == 0) d.mflag[item] = 0;
+    if constexpr (MODE == 2) {
+        // membranes: the item's list, one entry per lane, each adding W F to
+        // the (at most four) nodes of this item in its stencil, in 2^-50 units,
+        // into the wave's LDS row; every lane takes part (also past nx)
+        __shared__ unsigned long long acc[WAVES][3][64];
+        const int cnt = d.icount[item];
+        if (cnt > 0) {
+            const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = min(cnt, ICAP);
+            const int row = d.crow[20 * c], y = row % d.ny, z = row / d.ny, xs0 = x - lane;
+            for (int q = 0; q < 3; q++) acc[w][q][lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            for (int j = lane; j < n; j += 64) {
+                const int v = d.ilist[(long long)item * ICAP + j];
+                const int *o = d.morg + 4 * v;
+                const double *r = d.mrec + 16 * v;
+                const int b = y - o[1], cz = z - o[2];
+                if (b < 0 || b > 3 || cz < 0 || cz > 3) continue;
+                const double wy = r[4 + b], wz = r[8 + cz];
+                const double F[3] = {r[12], r[13], r[14]};
+                for (int a = 0; a < 4; a++) {
+                    const int xa = ((o[0] + a) % d.nx + d.nx) % d.nx, ln = xa - xs0;
+                    if (ln < 0 || ln > 63) continue;
+                    const double W = r[a] * wy * wz;
+                    for (int q = 0; q < 3; q++) {
+                        const double cq = W * F[q] * FIX_ONE;
+                        if (fabs(cq) < 4.0e18)
+                            atomicAdd(&acc[w][q][ln], (unsigned long long)__double2ll_rn(cq));
+                        else
+                            atomicOr(d.err, ERR_FORCE);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();   // a wave's LDS operations complete in order
+            fx = (double)(long long)acc[w][0][lane] / FIX_ONE;
+            fy = (double)(long long)acc[w][1][lane] / FIX_ONE;
+            fz = (double)(long long)acc[w][2][lane] / FIX_ONE;
+            if (lane == 0) d.icount[item] = 0;
+        }
     }
+    if (x >= d.nx) return;
     if (MODE == 1) {
         const int *sb = d.sbeg + 65 * slot + (threadIdx.x & 63);
         const int k1 = sb[1];
@@ -363,17 +407,62 @@ __device__ __forceinline__ bool stencil_node(const Dev3 &d, const double X[3], i
     return true;
 }
 
-// u* at every membrane vertex at x^n (positions of parity mp): the velocity
-// of the streamed populations with half the body force at each stencil node,
-// weighted and summed over the wave.
+__device__ __forceinline__ void cross(const double *a, const double *b, double *o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// First launch of a step with membranes.  Workgroups [0, nvb): a wave per
+// vertex, u* at x^n (positions of parity mp): the velocity of the streamed
+// populations with half the body force at each stencil node, weighted and
+// summed over the wave.  The rest: a wave per 64 triangles of one membrane,
+// the area and the volume terms (about the membrane's first vertex) summed
+// over the wave and added to the membrane's totals of parity mp in 2^-32
+// units.
 template <typename T, int PAR>
-__global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp) {
+__global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nvb) {
+    const int lane = threadIdx.x & 63;
+    if ((int)blockIdx.x >= nvb) {
+        const int tw = ((int)blockIdx.x - nvb) * WAVES + (int)(threadIdx.x >> 6);
+        if (tw >= d.ntw) return;
+        const int m = d.twave[2 * tw], t = d.twave[2 * tw + 1] + lane;
+        double A = 0.0, V = 0.0;
+        if (t < d.mt0[m] + d.mnt[m]) {
+            const int *tv = d.Mtri + 3 * t;
+            const double *X = d.MX[mp];
+            const int r0 = d.mv0[m];
+            double p[3], q[3], r[3];
+            for (int u = 0; u < 3; u++) {
+                const double x0 = X[u * d.ms + r0];
+                p[u] = X[u * d.ms + tv[0]] - x0;
+                q[u] = X[u * d.ms + tv[1]] - x0;
+                r[u] = X[u * d.ms + tv[2]] - x0;
+            }
+            const double e1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]}, e2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+            double n[3], qr[3];
+            cross(e1, e2, n);
+            cross(q, r, qr);
+            A = 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            V = (p[0] * qr[0] + p[1] * qr[1] + p[2] * qr[2]) / 6.0;
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            A += __shfl_xor(A, o);
+            V += __shfl_xor(V, o);
+        }
+        if (lane == 0) {
+            unsigned long long *tot = d.mtfx + 2 * ((long long)mp * d.mcap + m);
+            atomicAdd(tot, (unsigned long long)__double2ll_rn(A * FIX_TOT));
+            atomicAdd(tot + 1, (unsigned long long)__double2ll_rn(V * FIX_TOT));
+        }
+        return;
+    }
     const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
     if (v >= d.mv) return;
     const double X[3] = {d.MX[mp][v], d.MX[mp][d.ms + v], d.MX[mp][2 * d.ms + v]};
     int col, x;
     double W, ux = 0.0, uy = 0.0, uz = 0.0;
-    if (stencil_node(d, X, (int)(threadIdx.x & 63), col, x, W)) {
+    if (stencil_node(d, X, lane, col, x, W)) {
         double h[Q];
         long long own;
         const double ur = pull<T, double, PAR>(d, col, x, h, own);
@@ -394,150 +483,185 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp) {
         uy += __shfl_xor(uy, o);
         uz += __shfl_xor(uz, o);
     }
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         d.Mus[v] = ux;
         d.Mus[d.ms + v] = uy;
         d.Mus[2 * d.ms + v] = uz;
     }
 }
 
-constexpr int MB_THREADS = 1024;
-
-// Sum over the workgroup of two FP64 values (wave totals added in wave order).
-__device__ __forceinline__ void block_sum2(double &a, double &b, double (*red)[2]) {
-    for (int o = 32; o >= 1; o >>= 1) {
-        a += __shfl_xor(a, o);
-        b += __shfl_xor(b, o);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[w][0] = a;
-        red[w][1] = b;
-    }
-    __syncthreads();
-    a = 0.0;
-    b = 0.0;
-    for (int k = 0; k < MB_THREADS / 64; k++) {
-        a += red[k][0];
-        b += red[k][1];
-    }
-}
-
-// One workgroup per membrane: area and enclosed volume (FP64, the volume
-// about the first vertex), then for every vertex the elastic force gathered
-// from its incident triangles in ascending order (Skalak corner force and
-// the two penalties' gradients), dV = a third of their areas, the update
-// dx = u* + f/(2m), x^{n+1} = x^n + dx, U = 3/2 dx - 1/2 dx_prev and the
-// direct force F = (U - u*) dV.  Positions of parity mp in, mp ^ 1 out.
-template <int MAXV>
-__global__ __launch_bounds__(MB_THREADS) void k3_m_body(Dev3 d, int mp) {
-    __shared__ double sx[MAXV], sy[MAXV], sz[MAXV];
-    __shared__ double red[MB_THREADS / 64][2];
-    const int m = blockIdx.x, v0 = d.mv0[m], nv = d.mnv[m];
-    const double *X = d.MX[mp];
-    for (int i = threadIdx.x; i < nv; i += MB_THREADS) {
-        sx[i] = X[v0 + i];
-        sy[i] = X[d.ms + v0 + i];
-        sz[i] = X[2 * d.ms + v0 + i];
-    }
-    __syncthreads();
+// Second launch: a wave per membrane vertex v (positions of parity mp in,
+// mp ^ 1 out).  Lane k takes v's k-th incident triangle (ascending): its
+// Skalak corner force -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], the area
+// penalty's -k_A (A - A0)/A0 n x (x_c - x_b)/2 and the volume penalty's
+// -k_V (V - V0)/V0 (x_b - r0) x (x_c - r0)/6, and a third of its area; the
+// wave sums them.  Then dx = u* + f/(2m), x^{n+1} = x^n + dx,
+// U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV; the spread record at x^n, and
+// v appended to the list of each work item its stencil touches (lanes: 16
+// columns x the x segments of the stencil).  Workgroup 0 also clears the
+// totals of parity mp ^ 1 for the next step.
+__global__ __launch_bounds__(64 * WAVES) void k3_m_body(Dev3 d, int mp) {
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 2 * d.mcap; i += blockDim.x) d.mtfx[2 * (long long)(mp ^ 1) * d.mcap + i] = 0;
+    const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
+    if (v >= d.mv) return;
+    const int m = d.vmem[v];
     const double *P = d.mpar + 8 * m;
-    const int t0 = d.mt0[m], nt = d.mnt[m];
-    double A = 0.0, V = 0.0;
-    for (int t = threadIdx.x; t < nt; t += MB_THREADS) {
-        const int *T = d.Mtri + 3 * (t0 + t);
-        const int i0 = T[0] - v0, i1 = T[1] - v0, i2 = T[2] - v0;
-        const double p[3] = {sx[i0] - sx[0], sy[i0] - sy[0], sz[i0] - sz[0]};
-        const double q[3] = {sx[i1] - sx[0], sy[i1] - sy[0], sz[i1] - sz[0]};
-        const double r[3] = {sx[i2] - sx[0], sy[i2] - sy[0], sz[i2] - sz[0]};
-        const double e1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]}, e2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
-        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-        A += 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        const double qr[3] = {q[1] * r[2] - q[2] * r[1], q[2] * r[0] - q[0] * r[2], q[0] * r[1] - q[1] * r[0]};
-        V += (p[0] * qr[0] + p[1] * qr[1] + p[2] * qr[2]) / 6.0;
-    }
-    block_sum2(A, V, red);
-    if (threadIdx.x == 0) {
+    const unsigned long long *tot = d.mtfx + 2 * ((long long)mp * d.mcap + m);
+    const double A = (double)(long long)tot[0] / FIX_TOT, V = (double)(long long)tot[1] / FIX_TOT;
+    const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
+    const double *X = d.MX[mp];
+    const int r0 = d.mv0[m];
+    if (v == r0 && lane == 0) {
         d.mtot[2 * m] = A;
         d.mtot[2 * m + 1] = V;
     }
-    const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
-    for (int i = threadIdx.x; i < nv; i += MB_THREADS) {
-        const int v = v0 + i;
-        double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
-        for (int k = d.vtb[v]; k < d.vtb[v + 1]; k++) {
-            const int e = d.vtl[k], t = e >> 2, a = e & 3, b = (a + 1) % 3, c = (a + 2) % 3;
-            const int *T = d.Mtri + 3 * t;
-            const double *g = d.Mref + 8 * t;
-            const int j[3] = {T[0] - v0, T[1] - v0, T[2] - v0};
-            double F[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-            for (int s = 0; s < 3; s++) {
-                const double xs[3] = {sx[j[s]], sy[j[s]], sz[j[s]]};
-                for (int u = 0; u < 3; u++) {
-                    F[u][0] += xs[u] * g[2 * s];
-                    F[u][1] += xs[u] * g[2 * s + 1];
-                }
-            }
-            double Cm[2][2];
-            for (int r = 0; r < 2; r++)
-                for (int w = 0; w < 2; w++) Cm[r][w] = F[0][r] * F[0][w] + F[1][r] * F[1][w] + F[2][r] * F[2][w];
-            const double I1 = Cm[0][0] + Cm[1][1] - 2.0, I2 = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0] - 1.0;
-            const double w1 = 0.25 * P[0] * (2.0 * I1 + 2.0), w2 = 0.25 * P[0] * (-2.0 + 2.0 * P[1] * I2);
-            const double det = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0];
-            const double Ci[2][2] = {{Cm[1][1] / det, -Cm[0][1] / det}, {-Cm[1][0] / det, Cm[0][0] / det}};
-            const double e1[3] = {sx[j[1]] - sx[j[0]], sy[j[1]] - sy[j[0]], sz[j[1]] - sz[j[0]]};
-            const double e2[3] = {sx[j[2]] - sx[j[0]], sy[j[2]] - sy[j[0]], sz[j[2]] - sz[j[0]]};
-            double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-            const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-            for (int u = 0; u < 3; u++) n[u] /= nn;
-            const double ga[2] = {g[2 * a], g[2 * a + 1]};
-            const double Cg[2] = {Ci[0][0] * ga[0] + Ci[0][1] * ga[1], Ci[1][0] * ga[0] + Ci[1][1] * ga[1]};
-            const double cb[3] = {sx[j[c]] - sx[j[b]], sy[j[c]] - sy[j[b]], sz[j[c]] - sz[j[b]]};
-            const double nbc[3] = {n[1] * cb[2] - n[2] * cb[1], n[2] * cb[0] - n[0] * cb[2], n[0] * cb[1] - n[1] * cb[0]};
-            const double xb[3] = {sx[j[b]] - sx[0], sy[j[b]] - sy[0], sz[j[b]] - sz[0]};
-            const double xc[3] = {sx[j[c]] - sx[0], sy[j[c]] - sy[0], sz[j[c]] - sz[0]};
-            const double bc[3] = {xb[1] * xc[2] - xb[2] * xc[1], xb[2] * xc[0] - xb[0] * xc[2], xb[0] * xc[1] - xb[1] * xc[0]};
+    double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
+    const int k0 = d.vtb[v], nk = d.vtb[v + 1] - k0;
+    if (lane < nk) {
+        const int e = d.vtl[k0 + lane], t = e >> 2, a = e & 3;
+        const int *T = d.Mtri + 3 * t;
+        const double *g = d.Mref + 8 * t;
+        double x[3][3];
+        for (int s = 0; s < 3; s++)
+            for (int u = 0; u < 3; u++) x[s][u] = X[u * d.ms + T[s]];
+        double F[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        for (int s = 0; s < 3; s++)
             for (int u = 0; u < 3; u++) {
-                const double Fg = F[u][0] * ga[0] + F[u][1] * ga[1];
-                const double FCg = F[u][0] * Cg[0] + F[u][1] * Cg[1];
-                const double fa = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
-                f[u] += fa - ca * 0.5 * nbc[u] - cv * bc[u] / 6.0;
+                F[u][0] += x[s][u] * g[2 * s];
+                F[u][1] += x[s][u] * g[2 * s + 1];
             }
-            dV += 0.5 * nn / 3.0;
-        }
-        const double xn[3] = {sx[i], sy[i], sz[i]};
+        double Cm[2][2];
+        for (int r = 0; r < 2; r++)
+            for (int w = 0; w < 2; w++) Cm[r][w] = F[0][r] * F[0][w] + F[1][r] * F[1][w] + F[2][r] * F[2][w];
+        const double I1 = Cm[0][0] + Cm[1][1] - 2.0, I2 = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0] - 1.0;
+        const double w1 = 0.25 * P[0] * (2.0 * I1 + 2.0), w2 = 0.25 * P[0] * (-2.0 + 2.0 * P[1] * I2);
+        const double det = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0];
+        const double Ci[2][2] = {{Cm[1][1] / det, -Cm[0][1] / det}, {-Cm[1][0] / det, Cm[0][0] / det}};
+        const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+        const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+        double n[3];
+        cross(e1, e2, n);
+        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int u = 0; u < 3; u++) n[u] /= nn;
+        const double ga[2] = {g[2 * a], g[2 * a + 1]};
+        const double Cg[2] = {Ci[0][0] * ga[0] + Ci[0][1] * ga[1], Ci[1][0] * ga[0] + Ci[1][1] * ga[1]};
+        // corners b and c by selects (no indexed private arrays)
+        double pb[3], pc[3];
         for (int u = 0; u < 3; u++) {
-            const long long k = u * d.ms + v;
-            const double us = d.Mus[k];
-            const double dx = us + 0.5 * f[u] / P[4];
-            const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
+            pb[u] = a == 0 ? x[1][u] : a == 1 ? x[2][u] : x[0][u];
+            pc[u] = a == 0 ? x[2][u] : a == 1 ? x[0][u] : x[1][u];
+        }
+        const double cb[3] = {pc[0] - pb[0], pc[1] - pb[1], pc[2] - pb[2]};
+        double nbc[3], bc[3];
+        cross(n, cb, nbc);
+        double xb[3], xc[3];
+        for (int u = 0; u < 3; u++) {
+            const double x0 = X[u * d.ms + r0];
+            xb[u] = pb[u] - x0;
+            xc[u] = pc[u] - x0;
+        }
+        cross(xb, xc, bc);
+        for (int u = 0; u < 3; u++) {
+            const double Fg = F[u][0] * ga[0] + F[u][1] * ga[1];
+            const double FCg = F[u][0] * Cg[0] + F[u][1] * Cg[1];
+            const double fa = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
+            f[u] = fa - ca * 0.5 * nbc[u] - cv * bc[u] / 6.0;
+        }
+        dV = 0.5 * nn / 3.0;
+    }
+    const int j0 = d.veb[v], nj = d.veb[v + 1] - j0;
+    if (lane >= 32 && lane - 32 < nj) {
+        // bending at an edge: -k_b sin(theta - theta0) times the gradient of
+        // the dihedral angle theta = atan2((n1 x n2).e, n1.n2) for this vertex's
+        // role: l = |e|, e = x2 - x1, N1 = e x (x3 - x1), N2 = -e x (x4 - x2),
+        // g3 = -l N1/|N1|^2, g4 = -l N2/|N2|^2,
+        // g1 = ((x3 - x2).e/l^2) g3 + ((x4 - x2).e/l^2) g4, g2 = -(g1 + g3 + g4)
+        const int en = d.vel[j0 + lane - 32], k = en >> 2, role = en & 3;
+        const int *E = d.Medge + 4 * k;
+        double y[4][3];
+        for (int s = 0; s < 4; s++)
+            for (int u = 0; u < 3; u++) y[s][u] = X[u * d.ms + E[s]];
+        const double e[3] = {y[1][0] - y[0][0], y[1][1] - y[0][1], y[1][2] - y[0][2]};
+        const double me[3] = {-e[0], -e[1], -e[2]};
+        const double a3[3] = {y[2][0] - y[0][0], y[2][1] - y[0][1], y[2][2] - y[0][2]};
+        const double b4[3] = {y[3][0] - y[1][0], y[3][1] - y[1][1], y[3][2] - y[1][2]};
+        double N1[3], N2[3], n1[3], n2[3], c12[3];
+        cross(e, a3, N1);
+        cross(me, b4, N2);
+        const double l2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2], l = sqrt(l2);
+        const double q1 = N1[0] * N1[0] + N1[1] * N1[1] + N1[2] * N1[2];
+        const double q2 = N2[0] * N2[0] + N2[1] * N2[1] + N2[2] * N2[2];
+        const double r1 = sqrt(q1), r2 = sqrt(q2);
+        for (int u = 0; u < 3; u++) {
+            n1[u] = N1[u] / r1;
+            n2[u] = N2[u] / r2;
+        }
+        cross(n1, n2, c12);
+        const double th = atan2((c12[0] * e[0] + c12[1] * e[1] + c12[2] * e[2]) / l,
+                                n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2]);
+        const double sb = -P[7] * sin(th - d.Mth0[k]);
+        const double w3 = ((y[2][0] - y[1][0]) * e[0] + (y[2][1] - y[1][1]) * e[1] + (y[2][2] - y[1][2]) * e[2]) / l2;
+        const double w4 = ((y[3][0] - y[1][0]) * e[0] + (y[3][1] - y[1][1]) * e[1] + (y[3][2] - y[1][2]) * e[2]) / l2;
+        for (int u = 0; u < 3; u++) {
+            const double g3 = -l * N1[u] / q1, g4 = -l * N2[u] / q2, g1 = w3 * g3 + w4 * g4;
+            const double g = role == 0 ? g1 : role == 1 ? -(g1 + g3 + g4) : role == 2 ? g3 : g4;
+            f[u] = sb * g;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        f[0] += __shfl_xor(f[0], o);
+        f[1] += __shfl_xor(f[1], o);
+        f[2] += __shfl_xor(f[2], o);
+        dV += __shfl_xor(dV, o);
+    }
+    const double xn[3] = {X[v], X[d.ms + v], X[2 * d.ms + v]};
+    double Fs[3];
+    for (int u = 0; u < 3; u++) {
+        const long long k = u * d.ms + v;
+        const double us = d.Mus[k];
+        const double dx = us + 0.5 * f[u] / P[4];
+        const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
+        Fs[u] = (U - us) * dV;
+        if (lane == 0) {
             d.MX[mp ^ 1][k] = xn[u] + dx;
             d.Mdxm[k] = dx;
-            d.MF[k] = (U - us) * dV;
+            d.MF[k] = Fs[u];
         }
     }
-}
-
-// Spreading at x^n: a wave per vertex, a lane per stencil node; each
-// contribution W F in fixed point, added with an integer atomic (exact, so
-// the field does not depend on the order), and the node's work item flagged.
-__global__ __launch_bounds__(64 * WAVES) void k3_m_spread(Dev3 d, int mp) {
-    const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
-    if (v >= d.mv) return;
-    const double X[3] = {d.MX[mp][v], d.MX[mp][d.ms + v], d.MX[mp][2 * d.ms + v]};
-    int col, x;
-    double W;
-    if (!stencil_node(d, X, (int)(threadIdx.x & 63), col, x, W)) return;
-    const long long node = (long long)d.crow[20 * col] * d.pitch + x;
-    for (int u = 0; u < 3; u++) {
-        const double c = W * d.MF[u * d.ms + v] * FIX_ONE;
-        if (!(fabs(c) < 4.0e18)) {   // beyond 2^12 in force units, or not finite
-            atomicOr(d.err, ERR_FORCE);
-            continue;
-        }
-        atomicAdd(d.mforce + u * d.fs + node, (unsigned long long)__double2ll_rn(c));
+    // spread record at x^n: origin, the delta weights per axis, F
+    int o[3];
+    for (int u = 0; u < 3; u++) o[u] = (int)floor(xn[u]) - 1;
+    if (lane < 12) {
+        const int u = lane >> 2, k = lane & 3;
+        d.mrec[16 * (long long)v + lane] = phi_cos(xn[u] - (o[u] + k));
+    } else if (lane < 15) {
+        d.mrec[16 * (long long)v + lane] = Fs[lane - 12];
+    } else if (lane < 18) {
+        d.morg[4 * (long long)v + lane - 15] = o[lane - 15];
     }
-    d.mflag[col * d.nseg + x / 64] = 1;
+    // the lists: lane (b, c, a) = column (o_y + b, o_z + c) and the segment of
+    // stencil x o_x + a, counted once per segment (the first a that has it)
+    {
+        const int b = lane & 3, c = (lane >> 2) & 3, a = lane >> 4;
+        const int sa = (((o[0] + a) % d.nx) + d.nx) % d.nx / 64;
+        bool first = true;
+        for (int k = 0; k < 3; k++)
+            if (k < a) first = first && (((o[0] + k) % d.nx) + d.nx) % d.nx / 64 != sa;
+        const int y = o[1] + b, z = o[2] + c;
+        const int col = (y >= 0 && y < d.ny && z >= 0 && z < d.nz) ? d.colof[z * d.ny + y] : -1;
+        if (col < 0) {
+            atomicOr(d.err, ERR_STENCIL);
+        } else if (first) {
+            const long long item = (long long)col * d.nseg + sa;
+            const int slot = atomicAdd(d.icount + item, 1);
+            if (slot < ICAP)
+                d.ilist[item * ICAP + slot] = v;
+            else
+                atomicOr(d.err, ERR_LIST);
+        }
+    }
 }
 
 // Moments the next step starts from, FP64, into d.macro (fluid nodes).
@@ -623,13 +747,17 @@ struct capib3d_ctx {
     int nm = 0, mvn = 0, mtn = 0, mpar = 0, mmaxv = 0;   // counts, positions' parity, largest membrane
     std::vector<int> m_v0, m_nv, m_t0, m_nt, mtri;       // ranges, [mt][3]
     std::vector<double> mref, mparam;                    // [mt][8], [nm][8]
+    std::vector<int> medge;                              // [me][4]
+    std::vector<double> mth0;                            // [me]
     char *base = nullptr;
     size_t off_pop[2]{}, off_crow = 0, off_cK = 0, off_macro = 0, off_part = 0, ws = 0;
     size_t off_vnode = 0, off_vW = 0, off_vdV = 0, off_vpos = 0, off_vF = 0, off_contrib = 0, off_unode = 0,
            off_islot = 0, off_fitem = 0, off_sbeg = 0;
     size_t off_MX[2]{}, off_Mdxm = 0, off_Mus = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
-           off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_mforce = 0,
-           off_mflag = 0, off_colof = 0, off_err = 0;
+           off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_vmem = 0,
+           off_twave = 0, off_mtfx = 0, off_mrec = 0, off_morg = 0, off_icount = 0, off_ilist = 0, off_colof = 0,
+           off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_vel = 0;
+    int ntw = 0;                          // totals waves
     Dev3 d{};
     std::string err = "no error";
 };
@@ -777,8 +905,19 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_mnt = o; o = al256(o + MM * 4);
     c->off_mpar = o; o = al256(o + MM * 8 * 8);
     c->off_mtot = o; o = al256(o + MM * 2 * 8);
-    c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
-    c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
+    (void)fs;
+    c->off_vmem = o; o = al256(o + MV * 4);
+    const size_t ME = (3 * MT) / 2 + 1;   // interior edges of the triangles at most
+    c->off_medge = o; o = al256(o + ME * 4 * 4);
+    c->off_mth0 = o; o = al256(o + ME * 8);
+    c->off_veb = o; o = al256(o + (MV ? MV + 1 : 0) * 4);
+    c->off_vel = o; o = al256(o + ME * 4 * 4);
+    c->off_twave = o; o = al256(o + (MT / 64 + MM) * 2 * 4);
+    c->off_mtfx = o; o = al256(o + 2 * MM * 2 * 8);
+    c->off_mrec = o; o = al256(o + MV * 16 * 8);
+    c->off_morg = o; o = al256(o + MV * 4 * 4);
+    c->off_icount = o; o = al256(o + (MV ? nitem * 4 : 0));
+    c->off_ilist = o; o = al256(o + (MV ? nitem * ICAP * 4 : 0));
     c->off_colof = o; o = al256(o + (size_t)L.ny * L.nz * 4);
     c->off_err = o; o = al256(o + 4);
     c->ws = o;
@@ -857,13 +996,25 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.mnt = (const int *)(c->base + c->off_mnt);
     d.mpar = (const double *)(c->base + c->off_mpar);
     d.mtot = (double *)(c->base + c->off_mtot);
-    d.mforce = (unsigned long long *)(c->base + c->off_mforce);
-    d.mflag = (int *)(c->base + c->off_mflag);
+    d.vmem = (const int *)(c->base + c->off_vmem);
+    d.Medge = (const int *)(c->base + c->off_medge);
+    d.Mth0 = (const double *)(c->base + c->off_mth0);
+    d.veb = (const int *)(c->base + c->off_veb);
+    d.vel = (const int *)(c->base + c->off_vel);
+    d.twave = (const int *)(c->base + c->off_twave);
+    d.ntw = 0;
+    d.mcap = L.max_membranes;
+    d.mtfx = (unsigned long long *)(c->base + c->off_mtfx);
+    d.mrec = (double *)(c->base + c->off_mrec);
+    d.morg = (int *)(c->base + c->off_morg);
+    d.icount = (int *)(c->base + c->off_icount);
+    d.ilist = (int *)(c->base + c->off_ilist);
+    c->ntw = 0;
     d.colof = (const int *)(c->base + c->off_colof);
     d.err = (int *)(c->base + c->off_err);
     c->nm = c->mvn = c->mtn = c->mpar = c->mmaxv = 0;
     c->m_v0.clear(); c->m_nv.clear(); c->m_t0.clear(); c->m_nt.clear(); c->mtri.clear(); c->mref.clear();
-    c->mparam.clear();
+    c->mparam.clear(); c->medge.clear(); c->mth0.clear();
     c->vcol.clear(); c->vxs.clear(); c->vW.clear(); c->vdV.clear();
     HIP3(c, hipMemsetAsync(c->base, 0, c->ws, c->stream));
     return upload_tables(c);
@@ -908,19 +1059,18 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     const int nvb = ((c->nv + WAVES - 1) / WAVES + 7) / 8 * 8, nfb = ((c->nslot + WAVES - 1) / WAVES + 7) / 8 * 8;
     const dim3 g1(nfb + (s1 + WAVES - 1) / WAVES), g2(nvb + (s2 - s1 + WAVES - 1) / WAVES),
         g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
-    const dim3 gm((c->mvn + WAVES - 1) / WAVES);
+    const int mvb = (c->mvn + WAVES - 1) / WAVES;
+    const dim3 gm(mvb), gi(mvb + (c->ntw + WAVES - 1) / WAVES);
     for (int t = 0; t < nsteps && c->nm > 0; t++) {
         const int mp = c->mpar;
         if (c->par) {
-            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 1> : k3_m_interp<float, 1>), gm, blk, 0, c->stream, c->d, mp);
+            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 1> : k3_m_interp<float, 1>), gi, blk, 0, c->stream, c->d, mp,
+                               mvb);
         } else {
-            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 0> : k3_m_interp<float, 0>), gm, blk, 0, c->stream, c->d, mp);
+            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 0> : k3_m_interp<float, 0>), gi, blk, 0, c->stream, c->d, mp,
+                               mvb);
         }
-        if (c->mmaxv <= 1024)
-            hipLaunchKernelGGL(k3_m_body<1024>, dim3(c->nm), dim3(MB_THREADS), 0, c->stream, c->d, mp);
-        else
-            hipLaunchKernelGGL(k3_m_body<4096>, dim3(c->nm), dim3(MB_THREADS), 0, c->stream, c->d, mp);
-        hipLaunchKernelGGL(k3_m_spread, gm, blk, 0, c->stream, c->d, mp);
+        hipLaunchKernelGGL(k3_m_body, gm, blk, 0, c->stream, c->d, mp);
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 2> : k3_sweep<float, 1, 2>), dim3(c->nblk), blk, 0,
                                c->stream, c->d);
@@ -1197,14 +1347,14 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     const capib3d_lattice &L = c->lat;
     if (nv < 3 || ntri < 1 || !xyz || !tri || !par) return fail3(c, CAPIB_E_ARG, "bad membrane arrays");
     if (c->nv > 0) return fail3(c, CAPIB_E_STATE, "fixed bodies and membranes do not share a context");
-    if (nv > 4096) return fail3(c, CAPIB_E_ARG, "%d vertices: a membrane holds at most 4096", nv);
+    if (L.nx < 4) return fail3(c, CAPIB_E_ARG, "membranes need nx >= 4");
     if (c->nm >= L.max_membranes || (long long)c->mvn + nv > L.max_membrane_vertices ||
         (long long)c->mtn + ntri > L.max_membrane_triangles)
         return fail3(c, CAPIB_E_CAPACITY, "membrane capacity exceeded");
-    const double pv[5] = {par->gs, par->c, par->ka, par->kv, par->mass};
+    const double pv[6] = {par->gs, par->c, par->ka, par->kv, par->mass, par->kb};
     for (double x : pv)
         if (!std::isfinite(x)) return fail3(c, CAPIB_E_ARG, "non-finite membrane parameter");
-    if (par->gs < 0 || par->ka < 0 || par->kv < 0 || !(par->mass > 0))
+    if (par->gs < 0 || par->ka < 0 || par->kv < 0 || par->kb < 0 || !(par->mass > 0))
         return fail3(c, CAPIB_E_ARG, "membrane moduli must be >= 0 and the mass > 0");
     for (int k = 0; k < 3 * ntri; k++)
         if (tri[k] < 0 || tri[k] >= nv) return fail3(c, CAPIB_E_ARG, "triangle vertex %d out of range", tri[k]);
@@ -1260,19 +1410,96 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     c->m_v0.push_back(v0); c->m_nv.push_back(nv); c->m_t0.push_back(t0); c->m_nt.push_back(ntri);
     for (int k = 0; k < 3 * ntri; k++) c->mtri.push_back(v0 + tri[k]);
     c->mref.insert(c->mref.end(), ref.begin(), ref.end());
-    const double mp8[8] = {par->gs, par->c, par->ka, par->kv, par->mass, A0, V0, 0.0};
+    // interior edges: each directed edge a -> b (a < b) of a triangle, paired
+    // with the triangle holding b -> a; in the order of first appearance
+    std::vector<int> edges;
+    std::vector<double> th0;
+    {
+        std::map<std::pair<int, int>, int> opp;   // directed edge -> opposite vertex
+        for (int t = 0; t < ntri; t++)
+            for (int k = 0; k < 3; k++) opp[{tri[3 * t + k], tri[3 * t + (k + 1) % 3]}] = tri[3 * t + (k + 2) % 3];
+        for (int t = 0; t < ntri; t++)
+            for (int k = 0; k < 3; k++) {
+                const int a = tri[3 * t + k], b = tri[3 * t + (k + 1) % 3], c3 = tri[3 * t + (k + 2) % 3];
+                if (a >= b) continue;
+                auto it = opp.find({b, a});
+                if (it == opp.end()) continue;
+                const int E[4] = {a, b, c3, it->second};
+                for (int r = 0; r < 4; r++) edges.push_back(v0 + E[r]);
+                // rest dihedral angle, atan2((n1 x n2).e, n1.n2)
+                double e[3], me[3], a3[3], b4[3], N1[3], N2[3], c12[3];
+                sub3h(xyz + 3 * b, xyz + 3 * a, e);
+                for (int i = 0; i < 3; i++) me[i] = -e[i];
+                sub3h(xyz + 3 * c3, xyz + 3 * a, a3);
+                sub3h(xyz + 3 * it->second, xyz + 3 * b, b4);
+                cross3h(e, a3, N1);
+                cross3h(me, b4, N2);
+                const double r1 = std::sqrt(dot3h(N1, N1)), r2 = std::sqrt(dot3h(N2, N2)), l = std::sqrt(dot3h(e, e));
+                double n1[3], n2[3];
+                for (int i = 0; i < 3; i++) { n1[i] = N1[i] / r1; n2[i] = N2[i] / r2; }
+                cross3h(n1, n2, c12);
+                th0.push_back(std::atan2(dot3h(c12, e) / l, dot3h(n1, n2)));
+            }
+    }
+    if (c->medge.size() / 4 + th0.size() > (3 * (size_t)L.max_membrane_triangles) / 2 + 1)
+        return fail3(c, CAPIB_E_CAPACITY, "edge capacity exceeded");
+    const double mp8[8] = {par->gs, par->c, par->ka, par->kv, par->mass, A0, V0, par->kb};
     c->mparam.insert(c->mparam.end(), mp8, mp8 + 8);
     c->nm++;
     c->mvn += nv;
     c->mtn += ntri;
     c->mmaxv = std::max(c->mmaxv, nv);
+    c->medge.insert(c->medge.end(), edges.begin(), edges.end());
+    c->mth0.insert(c->mth0.end(), th0.begin(), th0.end());
     // incident triangles of every vertex, ascending
     std::vector<int> vtb(c->mvn + 1, 0), vtl(3 * (size_t)c->mtn);
     for (int k = 0; k < 3 * c->mtn; k++) vtb[c->mtri[k] + 1]++;
     for (int v = 0; v < c->mvn; v++) vtb[v + 1] += vtb[v];
+    // the edge terms of every vertex: its role in each edge, ascending
+    const int me = (int)c->mth0.size();
+    std::vector<int> veb(c->mvn + 1, 0), vel(4 * (size_t)me);
+    for (int k = 0; k < 4 * me; k++) veb[c->medge[k] + 1]++;
+    for (int v = 0; v < c->mvn; v++) veb[v + 1] += veb[v];
+    {
+        std::vector<int> fe(veb.begin(), veb.end() - 1);
+        for (int k = 0; k < me; k++)
+            for (int r = 0; r < 4; r++) vel[fe[c->medge[4 * k + r]]++] = 4 * k + r;
+    }
+    for (int v = 0; v < c->mvn; v++)
+        if (vtb[v + 1] - vtb[v] > 32 || veb[v + 1] - veb[v] > 32) {
+            // roll back: more than 64 triangles meet at one vertex
+            c->nm--; c->mvn -= nv; c->mtn -= ntri;
+            c->m_v0.pop_back(); c->m_nv.pop_back(); c->m_t0.pop_back(); c->m_nt.pop_back();
+            c->mtri.resize(3 * (size_t)c->mtn); c->mref.resize(8 * (size_t)c->mtn); c->mparam.resize(8 * (size_t)c->nm);
+            c->medge.resize(c->medge.size() - edges.size()); c->mth0.resize(c->mth0.size() - th0.size());
+            c->mmaxv = 0;
+            for (int k : c->m_nv) c->mmaxv = std::max(c->mmaxv, k);
+            return fail3(c, CAPIB_E_ARG, "more than 32 triangles or 32 edge terms meet at a vertex");
+        }
     std::vector<int> fill(vtb.begin(), vtb.end() - 1);
     for (int t = 0; t < c->mtn; t++)
         for (int a = 0; a < 3; a++) vtl[fill[c->mtri[3 * t + a]]++] = 4 * t + a;
+    // the membrane of each vertex, and the totals waves (64 triangles of one membrane each)
+    std::vector<int> vmem(c->mvn), twave;
+    for (int k = 0; k < c->nm; k++) {
+        for (int v = c->m_v0[k]; v < c->m_v0[k] + c->m_nv[k]; v++) vmem[v] = k;
+        for (int t = c->m_t0[k]; t < c->m_t0[k] + c->m_nt[k]; t += 64) {
+            twave.push_back(k);
+            twave.push_back(t);
+        }
+    }
+    HIP3(c, hipMemcpyAsync(c->base + c->off_vmem, vmem.data(), vmem.size() * 4, hipMemcpyHostToDevice, c->stream));
+    if (me > 0) {
+        HIP3(c, hipMemcpyAsync(c->base + c->off_medge, c->medge.data(), c->medge.size() * 4, hipMemcpyHostToDevice,
+                               c->stream));
+        HIP3(c, hipMemcpyAsync(c->base + c->off_mth0, c->mth0.data(), c->mth0.size() * 8, hipMemcpyHostToDevice,
+                               c->stream));
+        HIP3(c, hipMemcpyAsync(c->base + c->off_vel, vel.data(), vel.size() * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    HIP3(c, hipMemcpyAsync(c->base + c->off_veb, veb.data(), veb.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_twave, twave.data(), twave.size() * 4, hipMemcpyHostToDevice, c->stream));
+    c->ntw = (int)(twave.size() / 2);
+    c->d.ntw = c->ntw;
     // upload: the new positions into the current parity, the tables whole
     const size_t MS = (size_t)L.max_membrane_vertices;
     std::vector<double> plane(nv);

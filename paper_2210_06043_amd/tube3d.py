@@ -24,7 +24,8 @@ class capib3d_lattice(C.Structure):
 
 
 class capib3d_membrane(C.Structure):
-    _fields_ = [("gs", C.c_double), ("c", C.c_double), ("ka", C.c_double), ("kv", C.c_double), ("mass", C.c_double)]
+    _fields_ = [("gs", C.c_double), ("c", C.c_double), ("ka", C.c_double), ("kv", C.c_double), ("mass", C.c_double),
+                ("kb", C.c_double)]
 
 
 SIGNATURES = {
@@ -151,14 +152,14 @@ class Tube3D:
         self._check(self.L.capib3d_body_forces(self.ctx, _d(out)))
         return out
 
-    def add_membrane(self, xyz, tri, gs, c, ka, kv, mass):
+    def add_membrane(self, xyz, tri, gs, c, ka, kv, mass, kb=0.0):
         """A deformable membrane (vertices [nv][3], triangles [ntri][3]
         counter-clockwise from outside; Skalak G_s and C, area and volume
-        penalties, vertex mass); returns its first vertex index."""
+        penalties, vertex mass, bending k_b); returns its first vertex index."""
         X = np.ascontiguousarray(xyz, dtype=np.float64)
         T = np.ascontiguousarray(tri, dtype=np.int32)
         assert X.ndim == 2 and X.shape[1] == 3 and T.ndim == 2 and T.shape[1] == 3
-        par = capib3d_membrane(gs, c, ka, kv, mass)
+        par = capib3d_membrane(gs, c, ka, kv, mass, kb)
         first = C.c_int32()
         self._check(self.L.capib3d_add_membrane(self.ctx, X.shape[0], _d(X), T.shape[0],
                                                 T.ctypes.data_as(C.POINTER(C.c_int32)), C.cast(C.byref(par), C.c_void_p),

@@ -1,5 +1,5 @@
 """Deformable membranes in the 3D extension's tube on the GPU (Skalak
-elements, area and volume penalties, the 2D membranes' vertex update in 3D,
+elements, dihedral bending, area and volume penalties, the 2D membranes' vertex update in 3D,
 fixed-point spreading) against the FP64 oracle through the C-ABI: every
 node's velocity, every vertex's position and direct force, and the FP64
 area and volume sums, on small tubes (a membrane across the periodic end,
@@ -16,7 +16,7 @@ from paper_2210_06043_amd import capib, inputs, tube3d
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
 FP16_TOL = 1e-3
-PAR = dict(gs=5e-3, c=1.0, ka=0.05, kv=0.05, mass=1.0)
+PAR = dict(gs=5e-3, c=1.0, ka=0.05, kv=0.05, mass=1.0, kb=2e-3)
 
 
 def _pair(nx, ny, nz, tau, gx, radius, membranes, dilate=1.02, fp16=False, par=PAR):
@@ -32,7 +32,7 @@ def _pair(nx, ny, nz, tau, gx, radius, membranes, dilate=1.02, fp16=False, par=P
     o.set_populations(g.populations())
     for xyz, tri in membranes:
         v0 = g.add_membrane(xyz, tri, **par)
-        assert o.add_membrane(xyz, tri, par["gs"], par["c"], par["ka"], par["kv"], par["mass"]) == v0
+        assert o.add_membrane(xyz, tri, par["gs"], par["c"], par["ka"], par["kv"], par["mass"], par["kb"]) == v0
     # start from a dilated shape so that the elastic forces act from the first step
     X = o.membrane_vertices()
     for v0, n in o.mranges:

@@ -127,8 +127,7 @@ int32_t capib3d_vertices(const capib3d_ctx *ctx);
 
 /* A deformable membrane: nv vertices (xyz, [nv][3] host doubles, lattice
  * coordinates) and ntri triangles (tri, [ntri][3], counter-clockwise seen
- * from outside; at most 32 meeting at a vertex, and a vertex in at most 32
- * edge terms; nx >= 4), its rest shape the given one.  Each step:
+ * from outside; nx >= 4), its rest shape the given one.  Each step:
  * u* interpolated at x^n (as for fixed bodies), the elastic force f at x^n
  * (Skalak, bending, area and volume terms, FP64), dx = u* + f/(2m), x^{n+1} =
  * x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV spread at x^n with dV

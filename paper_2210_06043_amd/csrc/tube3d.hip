@@ -32,25 +32,26 @@
 // same order on every run, and collides; then the ordinary items).  The
 // first two may also take shares of the ordinary items (a schedule knob).
 //
-// Deformable membranes (closed triangulated surfaces: Skalak elements and
-// penalties on total area and enclosed volume, Secs. 2.2-2.4 read in 3D).
-// Their stencils move, so the coupling is rebuilt every step on the device,
-// and every sum whose order the schedule does not fix is taken in 64-bit
-// fixed point (integer adds are exact, so the order does not matter and every
-// run gives the same bits).  A step is three launches.  k3_m_interp: a wave
-// per vertex (a lane per stencil node: u*), and a wave per 64 triangles of a
-// membrane (its FP64 area and volume terms, summed over the wave, added to the
-// membrane's totals in 2^-32 units).  k3_m_body: a wave per vertex (a lane per
-// incident triangle: Skalak corner force and the penalties' gradients; a lane
-// per edge the vertex belongs to: the bending force; summed over the wave),
-// the vertex update and the direct force; the vertex's spread
-// record (stencil origin, the 12 delta weights, F) and its entry in the list
-// of every work item its stencil touches.  The sweep: a work item with a list
-// adds the contributions W F of its entries, one entry per lane, in 2^-50
-// units into the wave's own LDS row of 64 nodes, then collides.
+// Deformable membranes (closed triangulated surfaces: Skalak elements,
+// dihedral bending, penalties on total area and enclosed volume, Secs.
+// 2.2-2.4 read in 3D).  Their stencils move, so the coupling is rebuilt every
+// step on the device, and every sum whose order the schedule does not fix is
+// taken in 64-bit fixed point (integer adds are exact, so the order does not
+// matter and every run gives the same bits).  A step is three launches.
+// k3_m_interp: a wave per vertex (a lane per stencil node: u*), a lane per
+// triangle (its corner terms; the area and volume, summed per wave and added
+// to the membrane's totals in 2^-32 units) and a lane per edge (its bending
+// forces).  k3_m_patch: a workgroup per patch of 64 vertices (the host numbers
+// each membrane's vertices by recursive bisection of their rest positions, so
+// a patch is compact): each vertex's force gathered from its terms, the
+// vertex update and the direct force, the patch's stencil contributions summed
+// in an LDS box in 2^-50 units and added to a global force field with one
+// atomic per node and component, its work items flagged.  The sweep reads and
+// clears the field on flagged items.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <map>
 #include <cmath>
 #include <cstdarg>
@@ -111,22 +112,23 @@ struct Dev3 {
     const double *Mth0;         // [me] rest dihedral angle
     const int *veb, *vel;       // edge terms of each vertex: [mv + 1] starts, entries edge * 4 + role
     double *mtot;               // [nm][2] area and volume at the start of the last step
-    const int *vmem;            // [mv] membrane of each vertex
-    const int *twave;           // [ntw][2] membrane and first triangle of each totals wave
-    int ntw, mcap;              // totals waves; capacity of membranes
+    const int *twave;           // [ntw][2] membrane and first triangle of each triangle wave
+    const int *ewave;           // [new_][2] membrane and first edge of each edge wave
+    const int *me0, *mne;       // [nm] first edge, edges
+    int ntw, new_, mcap;        // triangle waves, edge waves; capacity of membranes
     unsigned long long *mtfx;   // [2][mcap][2] area and volume by parity, fixed point (2^-32)
-    double *mrec;               // [mv][16] spread record: w (3 x 4 delta weights), F (3)
-    int *morg;                  // [mv][4] stencil origin (x, y, z) of the record
-    int *icount;                // [ncol * nseg] entries in each work item's list
-    int *ilist;                 // [ncol * nseg][ICAP] vertices whose stencil touches the item
+    double *tcf;                // [mt][32] per corner: Skalak force, area gradient, volume gradient, area / 3
+    double *ecf;                // [me][12] bending force on x1, x2, x3, x4
+    const int *ptab;            // [npatch][3] first vertex, vertices, membrane
+    unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
+    int *mflag;                 // [ncol * nseg] work item with spread force
     const int *colof;           // [nz][ny] column of a row, -1 solid
     int *err;                   // error flags
 };
 
 constexpr double FIX_ONE = 1125899906842624.0;   // 2^50, spread contributions
 constexpr double FIX_TOT = 4294967296.0;         // 2^32, area and volume
-constexpr int ICAP = 1024;                       // list capacity of a work item
-constexpr int ERR_STENCIL = 1, ERR_FORCE = 2, ERR_LIST = 4;
+constexpr int ERR_STENCIL = 1, ERR_FORCE = 2;
 
 // Workgroup b -> work item such that each XCD (workgroups dealt round-robin
 // to the 8 XCDs) holds one contiguous range of items.
@@ -194,46 +196,17 @@ __device__ __forceinline__ void sweep_item(const Dev3 &d, int item, int slot) {
     const int c = item / d.nseg;
     const int x = (item - c * d.nseg) * 64 + (int)(threadIdx.x & 63);
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if constexpr (MODE == 2) {
-        // membranes: the item's list, one entry per lane, each adding W F to
-        // the (at most four) nodes of this item in its stencil, in 2^-50 units,
-        // into the wave's LDS row; every lane takes part (also past nx)
-        __shared__ unsigned long long acc[WAVES][3][64];
-        const int cnt = d.icount[item];
-        if (cnt > 0) {
-            const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = min(cnt, ICAP);
-            const int row = d.crow[20 * c], y = row % d.ny, z = row / d.ny, xs0 = x - lane;
-            for (int q = 0; q < 3; q++) acc[w][q][lane] = 0;
-            __builtin_amdgcn_wave_barrier();
-            for (int j = lane; j < n; j += 64) {
-                const int v = d.ilist[(long long)item * ICAP + j];
-                const int *o = d.morg + 4 * v;
-                const double *r = d.mrec + 16 * v;
-                const int b = y - o[1], cz = z - o[2];
-                if (b < 0 || b > 3 || cz < 0 || cz > 3) continue;
-                const double wy = r[4 + b], wz = r[8 + cz];
-                const double F[3] = {r[12], r[13], r[14]};
-                for (int a = 0; a < 4; a++) {
-                    const int xa = ((o[0] + a) % d.nx + d.nx) % d.nx, ln = xa - xs0;
-                    if (ln < 0 || ln > 63) continue;
-                    const double W = r[a] * wy * wz;
-                    for (int q = 0; q < 3; q++) {
-                        const double cq = W * F[q] * FIX_ONE;
-                        if (fabs(cq) < 4.0e18)
-                            atomicAdd(&acc[w][q][ln], (unsigned long long)__double2ll_rn(cq));
-                        else
-                            atomicOr(d.err, ERR_FORCE);
-                    }
-                }
-            }
-            __builtin_amdgcn_wave_barrier();   // a wave's LDS operations complete in order
-            fx = (double)(long long)acc[w][0][lane] / FIX_ONE;
-            fy = (double)(long long)acc[w][1][lane] / FIX_ONE;
-            fz = (double)(long long)acc[w][2][lane] / FIX_ONE;
-            if (lane == 0) d.icount[item] = 0;
-        }
-    }
     if (x >= d.nx) return;
+    if (MODE == 2 && d.mflag[item]) {
+        unsigned long long *p = d.mforce + (long long)d.crow[20 * c] * d.pitch + x;
+        fx = (double)(long long)p[0] / FIX_ONE;
+        fy = (double)(long long)p[d.fs] / FIX_ONE;
+        fz = (double)(long long)p[2 * d.fs] / FIX_ONE;
+        p[0] = 0;
+        p[d.fs] = 0;
+        p[2 * d.fs] = 0;
+        if ((threadIdx.x & 63) == 0) d.mflag[item] = 0;
+    }
     if (MODE == 1) {
         const int *sb = d.sbeg + 65 * slot + (threadIdx.x & 63);
         const int k1 = sb[1];
@@ -413,38 +386,132 @@ __device__ __forceinline__ void cross(const double *a, const double *b, double *
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// First launch of a step with membranes.  Workgroups [0, nvb): a wave per
-// vertex, u* at x^n (positions of parity mp): the velocity of the streamed
+// First launch of a step with membranes (positions x^n of parity mp).
+// Workgroups [0, nvb): a wave per vertex, u*: the velocity of the streamed
 // populations with half the body force at each stencil node, weighted and
-// summed over the wave.  The rest: a wave per 64 triangles of one membrane,
-// the area and the volume terms (about the membrane's first vertex) summed
-// over the wave and added to the membrane's totals of parity mp in 2^-32
-// units.
+// summed over the wave.  [nvb, nvb + ntb): a wave per 64 triangles of one
+// membrane, a lane per triangle: for each corner a, the Skalak force
+// -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], the area gradient
+// n x (x_c - x_b) / 2 and the volume gradient (x_b - r0) x (x_c - r0) / 6
+// ((a, b, c) in the triangle's cyclic order), and a third of the area; the
+// area and volume terms (about the membrane's first vertex r0) summed over
+// the wave and added to the membrane's totals in 2^-32 units.  The rest: a
+// wave per 64 edges of one membrane, a lane per edge: the bending force
+// -k_b sin(theta - theta0) grad theta on its four vertices.
 template <typename T, int PAR>
-__global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nvb) {
+__global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nvb, int ntb) {
     const int lane = threadIdx.x & 63;
+    const double *X = d.MX[mp];
+    if ((int)blockIdx.x >= nvb + ntb) {
+        const int ew = ((int)blockIdx.x - nvb - ntb) * WAVES + (int)(threadIdx.x >> 6);
+        if (ew >= d.new_) return;
+        const int m = d.ewave[2 * ew], k = d.ewave[2 * ew + 1] + lane;
+        if (k >= d.me0[m] + d.mne[m]) return;
+        // theta = atan2((n1 x n2).e, n1.n2) at edge (x1, x2) between the faces
+        // (x1, x2, x3) and (x2, x1, x4): l = |e|, e = x2 - x1,
+        // N1 = e x (x3 - x1), N2 = -e x (x4 - x2), g3 = -l N1/|N1|^2,
+        // g4 = -l N2/|N2|^2, g1 = ((x3 - x2).e/l^2) g3 + ((x4 - x2).e/l^2) g4,
+        // g2 = -(g1 + g3 + g4)
+        const int *E = d.Medge + 4 * k;
+        double y[4][3];
+        for (int s = 0; s < 4; s++)
+            for (int u = 0; u < 3; u++) y[s][u] = X[u * d.ms + E[s]];
+        const double e[3] = {y[1][0] - y[0][0], y[1][1] - y[0][1], y[1][2] - y[0][2]};
+        const double me[3] = {-e[0], -e[1], -e[2]};
+        const double a3[3] = {y[2][0] - y[0][0], y[2][1] - y[0][1], y[2][2] - y[0][2]};
+        const double b4[3] = {y[3][0] - y[1][0], y[3][1] - y[1][1], y[3][2] - y[1][2]};
+        double N1[3], N2[3], n1[3], n2[3], c12[3];
+        cross(e, a3, N1);
+        cross(me, b4, N2);
+        const double l2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2], l = sqrt(l2);
+        const double q1 = N1[0] * N1[0] + N1[1] * N1[1] + N1[2] * N1[2];
+        const double q2 = N2[0] * N2[0] + N2[1] * N2[1] + N2[2] * N2[2];
+        const double r1 = sqrt(q1), r2 = sqrt(q2);
+        for (int u = 0; u < 3; u++) {
+            n1[u] = N1[u] / r1;
+            n2[u] = N2[u] / r2;
+        }
+        cross(n1, n2, c12);
+        const double th = atan2((c12[0] * e[0] + c12[1] * e[1] + c12[2] * e[2]) / l,
+                                n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2]);
+        const double sb = -d.mpar[8 * m + 7] * sin(th - d.Mth0[k]);
+        const double w3 = ((y[2][0] - y[1][0]) * e[0] + (y[2][1] - y[1][1]) * e[1] + (y[2][2] - y[1][2]) * e[2]) / l2;
+        const double w4 = ((y[3][0] - y[1][0]) * e[0] + (y[3][1] - y[1][1]) * e[1] + (y[3][2] - y[1][2]) * e[2]) / l2;
+        double *out = d.ecf + 12 * (long long)k;
+        for (int u = 0; u < 3; u++) {
+            const double g3 = -l * N1[u] / q1, g4 = -l * N2[u] / q2, g1 = w3 * g3 + w4 * g4;
+            out[u] = sb * g1;
+            out[3 + u] = sb * -(g1 + g3 + g4);
+            out[6 + u] = sb * g3;
+            out[9 + u] = sb * g4;
+        }
+        return;
+    }
     if ((int)blockIdx.x >= nvb) {
         const int tw = ((int)blockIdx.x - nvb) * WAVES + (int)(threadIdx.x >> 6);
         if (tw >= d.ntw) return;
         const int m = d.twave[2 * tw], t = d.twave[2 * tw + 1] + lane;
         double A = 0.0, V = 0.0;
         if (t < d.mt0[m] + d.mnt[m]) {
+            const double *P = d.mpar + 8 * m;
             const int *tv = d.Mtri + 3 * t;
-            const double *X = d.MX[mp];
+            const double *g = d.Mref + 8 * t;
             const int r0 = d.mv0[m];
-            double p[3], q[3], r[3];
-            for (int u = 0; u < 3; u++) {
-                const double x0 = X[u * d.ms + r0];
-                p[u] = X[u * d.ms + tv[0]] - x0;
-                q[u] = X[u * d.ms + tv[1]] - x0;
-                r[u] = X[u * d.ms + tv[2]] - x0;
-            }
-            const double e1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]}, e2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
-            double n[3], qr[3];
+            double x[3][3], xr[3][3];
+            for (int s = 0; s < 3; s++)
+                for (int u = 0; u < 3; u++) {
+                    x[s][u] = X[u * d.ms + tv[s]];
+                    xr[s][u] = x[s][u] - X[u * d.ms + r0];
+                }
+            double F[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+            for (int s = 0; s < 3; s++)
+                for (int u = 0; u < 3; u++) {
+                    F[u][0] += x[s][u] * g[2 * s];
+                    F[u][1] += x[s][u] * g[2 * s + 1];
+                }
+            double Cm[2][2];
+            for (int r = 0; r < 2; r++)
+                for (int w = 0; w < 2; w++) Cm[r][w] = F[0][r] * F[0][w] + F[1][r] * F[1][w] + F[2][r] * F[2][w];
+            const double I1 = Cm[0][0] + Cm[1][1] - 2.0, I2 = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0] - 1.0;
+            const double w1 = 0.25 * P[0] * (2.0 * I1 + 2.0), w2 = 0.25 * P[0] * (-2.0 + 2.0 * P[1] * I2);
+            const double det = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0];
+            const double Ci[2][2] = {{Cm[1][1] / det, -Cm[0][1] / det}, {-Cm[1][0] / det, Cm[0][0] / det}};
+            const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+            const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+            double n[3];
             cross(e1, e2, n);
-            cross(q, r, qr);
-            A = 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-            V = (p[0] * qr[0] + p[1] * qr[1] + p[2] * qr[2]) / 6.0;
+            const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            for (int u = 0; u < 3; u++) n[u] /= nn;
+            double *out = d.tcf + 32 * (long long)t;
+            for (int a = 0; a < 3; a++) {
+                const int b = a == 2 ? 0 : a + 1, c = a == 0 ? 2 : a - 1;
+                const double ga[2] = {g[2 * a], g[2 * a + 1]};
+                const double Cg[2] = {Ci[0][0] * ga[0] + Ci[0][1] * ga[1], Ci[1][0] * ga[0] + Ci[1][1] * ga[1]};
+                double pb[3], pc[3], rb[3], rc[3];
+                for (int u = 0; u < 3; u++) {
+                    pb[u] = b == 0 ? x[0][u] : b == 1 ? x[1][u] : x[2][u];
+                    pc[u] = c == 0 ? x[0][u] : c == 1 ? x[1][u] : x[2][u];
+                    rb[u] = b == 0 ? xr[0][u] : b == 1 ? xr[1][u] : xr[2][u];
+                    rc[u] = c == 0 ? xr[0][u] : c == 1 ? xr[1][u] : xr[2][u];
+                }
+                const double cb[3] = {pc[0] - pb[0], pc[1] - pb[1], pc[2] - pb[2]};
+                double nbc[3], bc[3];
+                cross(n, cb, nbc);
+                cross(rb, rc, bc);
+                for (int u = 0; u < 3; u++) {
+                    const double Fg = F[u][0] * ga[0] + F[u][1] * ga[1];
+                    const double FCg = F[u][0] * Cg[0] + F[u][1] * Cg[1];
+                    out[10 * a + u] = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
+                    out[10 * a + 3 + u] = 0.5 * nbc[u];
+                    out[10 * a + 6 + u] = bc[u] / 6.0;
+                }
+                out[10 * a + 9] = 0.5 * nn / 3.0;
+            }
+            A = 0.5 * nn;
+            // the volume term about r0, from the corners relative to r0
+            double qr[3];
+            cross(xr[1], xr[2], qr);
+            V = (xr[0][0] * qr[0] + xr[0][1] * qr[1] + xr[0][2] * qr[2]) / 6.0;
         }
         for (int o = 32; o >= 1; o >>= 1) {
             A += __shfl_xor(A, o);
@@ -459,10 +526,10 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
     }
     const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
     if (v >= d.mv) return;
-    const double X[3] = {d.MX[mp][v], d.MX[mp][d.ms + v], d.MX[mp][2 * d.ms + v]};
+    const double Xv[3] = {X[v], X[d.ms + v], X[2 * d.ms + v]};
     int col, x;
     double W, ux = 0.0, uy = 0.0, uz = 0.0;
-    if (stencil_node(d, X, lane, col, x, W)) {
+    if (stencil_node(d, Xv, lane, col, x, W)) {
         double h[Q];
         long long own;
         const double ur = pull<T, double, PAR>(d, col, x, h, own);
@@ -490,177 +557,132 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
     }
 }
 
-// Second launch: a wave per membrane vertex v (positions of parity mp in,
-// mp ^ 1 out).  Lane k takes v's k-th incident triangle (ascending): its
-// Skalak corner force -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], the area
-// penalty's -k_A (A - A0)/A0 n x (x_c - x_b)/2 and the volume penalty's
-// -k_V (V - V0)/V0 (x_b - r0) x (x_c - r0)/6, and a third of its area; the
-// wave sums them.  Then dx = u* + f/(2m), x^{n+1} = x^n + dx,
-// U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV; the spread record at x^n, and
-// v appended to the list of each work item its stencil touches (lanes: 16
-// columns x the x segments of the stencil).  Workgroup 0 also clears the
-// totals of parity mp ^ 1 for the next step.
-__global__ __launch_bounds__(64 * WAVES) void k3_m_body(Dev3 d, int mp) {
-    const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0)
-        for (int i = threadIdx.x; i < 2 * d.mcap; i += blockDim.x) d.mtfx[2 * (long long)(mp ^ 1) * d.mcap + i] = 0;
-    const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
-    if (v >= d.mv) return;
-    const int m = d.vmem[v];
-    const double *P = d.mpar + 8 * m;
-    const unsigned long long *tot = d.mtfx + 2 * ((long long)mp * d.mcap + m);
-    const double A = (double)(long long)tot[0] / FIX_TOT, V = (double)(long long)tot[1] / FIX_TOT;
-    const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
+constexpr int PATCH_THREADS = 256;
+constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
+
+// Second launch: a workgroup per patch (up to 64 consecutive vertices of one
+// membrane, numbered by the host so that a patch is compact).  Thread j < n
+// takes vertex v = first + j: its force gathered in ascending order from the
+// corner terms of its triangles (Skalak - (k_A (A - A0)/A0) area gradient
+// - (k_V (V - V0)/V0) volume gradient) and then the bending terms of its
+// edges, dV the sum of the thirds of their areas; dx = u* + f/(2m),
+// x^{n+1} = x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV; its stencil
+// at x^n into LDS.  Then the patch's 64 x 64 contributions W F are added in
+// 2^-50 units into an LDS box over its stencils (integer adds: the order does
+// not matter), and the box is added to the global field with one integer
+// atomic per node and component, flagging each node's work item; a patch
+// whose box exceeds BOX^3 adds its contributions to the field directly.
+// Workgroup 0 also clears the totals of parity mp ^ 1 for the next step.
+__global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
+    __shared__ double sw[64][12];
+    __shared__ double sF[64][3];
+    __shared__ int so[64][3];
+    __shared__ int sbox[6];
+    __shared__ unsigned long long box[BOX * BOX * BOX][3];
+    const int t = threadIdx.x, p = blockIdx.x;
+    if (p == 0)
+        for (int i = t; i < 2 * d.mcap; i += PATCH_THREADS) d.mtfx[2 * (long long)(mp ^ 1) * d.mcap + i] = 0;
+    const int pv0 = d.ptab[3 * p], pn = d.ptab[3 * p + 1], m = d.ptab[3 * p + 2];
     const double *X = d.MX[mp];
-    const int r0 = d.mv0[m];
-    if (v == r0 && lane == 0) {
-        d.mtot[2 * m] = A;
-        d.mtot[2 * m + 1] = V;
-    }
-    double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
-    const int k0 = d.vtb[v], nk = d.vtb[v + 1] - k0;
-    if (lane < nk) {
-        const int e = d.vtl[k0 + lane], t = e >> 2, a = e & 3;
-        const int *T = d.Mtri + 3 * t;
-        const double *g = d.Mref + 8 * t;
-        double x[3][3];
-        for (int s = 0; s < 3; s++)
-            for (int u = 0; u < 3; u++) x[s][u] = X[u * d.ms + T[s]];
-        double F[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        for (int s = 0; s < 3; s++)
-            for (int u = 0; u < 3; u++) {
-                F[u][0] += x[s][u] * g[2 * s];
-                F[u][1] += x[s][u] * g[2 * s + 1];
-            }
-        double Cm[2][2];
-        for (int r = 0; r < 2; r++)
-            for (int w = 0; w < 2; w++) Cm[r][w] = F[0][r] * F[0][w] + F[1][r] * F[1][w] + F[2][r] * F[2][w];
-        const double I1 = Cm[0][0] + Cm[1][1] - 2.0, I2 = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0] - 1.0;
-        const double w1 = 0.25 * P[0] * (2.0 * I1 + 2.0), w2 = 0.25 * P[0] * (-2.0 + 2.0 * P[1] * I2);
-        const double det = Cm[0][0] * Cm[1][1] - Cm[0][1] * Cm[1][0];
-        const double Ci[2][2] = {{Cm[1][1] / det, -Cm[0][1] / det}, {-Cm[1][0] / det, Cm[0][0] / det}};
-        const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
-        const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
-        double n[3];
-        cross(e1, e2, n);
-        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        for (int u = 0; u < 3; u++) n[u] /= nn;
-        const double ga[2] = {g[2 * a], g[2 * a + 1]};
-        const double Cg[2] = {Ci[0][0] * ga[0] + Ci[0][1] * ga[1], Ci[1][0] * ga[0] + Ci[1][1] * ga[1]};
-        // corners b and c by selects (no indexed private arrays)
-        double pb[3], pc[3];
-        for (int u = 0; u < 3; u++) {
-            pb[u] = a == 0 ? x[1][u] : a == 1 ? x[2][u] : x[0][u];
-            pc[u] = a == 0 ? x[2][u] : a == 1 ? x[0][u] : x[1][u];
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    if (t < pn) {
+        const int v = pv0 + t;
+        const double *P = d.mpar + 8 * m;
+        const unsigned long long *tot = d.mtfx + 2 * ((long long)mp * d.mcap + m);
+        const double A = (double)(long long)tot[0] / FIX_TOT, V = (double)(long long)tot[1] / FIX_TOT;
+        if (v == d.mv0[m]) {
+            d.mtot[2 * m] = A;
+            d.mtot[2 * m + 1] = V;
         }
-        const double cb[3] = {pc[0] - pb[0], pc[1] - pb[1], pc[2] - pb[2]};
-        double nbc[3], bc[3];
-        cross(n, cb, nbc);
-        double xb[3], xc[3];
-        for (int u = 0; u < 3; u++) {
-            const double x0 = X[u * d.ms + r0];
-            xb[u] = pb[u] - x0;
-            xc[u] = pc[u] - x0;
+        const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
+        double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
+        for (int k = d.vtb[v]; k < d.vtb[v + 1]; k++) {
+            const int e = d.vtl[k];
+            const double *q = d.tcf + 32 * (long long)(e >> 2) + 10 * (e & 3);
+            for (int u = 0; u < 3; u++) f[u] += q[u] - ca * q[3 + u] - cv * q[6 + u];
+            dV += q[9];
         }
-        cross(xb, xc, bc);
-        for (int u = 0; u < 3; u++) {
-            const double Fg = F[u][0] * ga[0] + F[u][1] * ga[1];
-            const double FCg = F[u][0] * Cg[0] + F[u][1] * Cg[1];
-            const double fa = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
-            f[u] = fa - ca * 0.5 * nbc[u] - cv * bc[u] / 6.0;
+        for (int k = d.veb[v]; k < d.veb[v + 1]; k++) {
+            const int e = d.vel[k];
+            const double *q = d.ecf + 12 * (long long)(e >> 2) + 3 * (e & 3);
+            for (int u = 0; u < 3; u++) f[u] += q[u];
         }
-        dV = 0.5 * nn / 3.0;
-    }
-    const int j0 = d.veb[v], nj = d.veb[v + 1] - j0;
-    if (lane >= 32 && lane - 32 < nj) {
-        // bending at an edge: -k_b sin(theta - theta0) times the gradient of
-        // the dihedral angle theta = atan2((n1 x n2).e, n1.n2) for this vertex's
-        // role: l = |e|, e = x2 - x1, N1 = e x (x3 - x1), N2 = -e x (x4 - x2),
-        // g3 = -l N1/|N1|^2, g4 = -l N2/|N2|^2,
-        // g1 = ((x3 - x2).e/l^2) g3 + ((x4 - x2).e/l^2) g4, g2 = -(g1 + g3 + g4)
-        const int en = d.vel[j0 + lane - 32], k = en >> 2, role = en & 3;
-        const int *E = d.Medge + 4 * k;
-        double y[4][3];
-        for (int s = 0; s < 4; s++)
-            for (int u = 0; u < 3; u++) y[s][u] = X[u * d.ms + E[s]];
-        const double e[3] = {y[1][0] - y[0][0], y[1][1] - y[0][1], y[1][2] - y[0][2]};
-        const double me[3] = {-e[0], -e[1], -e[2]};
-        const double a3[3] = {y[2][0] - y[0][0], y[2][1] - y[0][1], y[2][2] - y[0][2]};
-        const double b4[3] = {y[3][0] - y[1][0], y[3][1] - y[1][1], y[3][2] - y[1][2]};
-        double N1[3], N2[3], n1[3], n2[3], c12[3];
-        cross(e, a3, N1);
-        cross(me, b4, N2);
-        const double l2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2], l = sqrt(l2);
-        const double q1 = N1[0] * N1[0] + N1[1] * N1[1] + N1[2] * N1[2];
-        const double q2 = N2[0] * N2[0] + N2[1] * N2[1] + N2[2] * N2[2];
-        const double r1 = sqrt(q1), r2 = sqrt(q2);
+        double xn[3];
         for (int u = 0; u < 3; u++) {
-            n1[u] = N1[u] / r1;
-            n2[u] = N2[u] / r2;
-        }
-        cross(n1, n2, c12);
-        const double th = atan2((c12[0] * e[0] + c12[1] * e[1] + c12[2] * e[2]) / l,
-                                n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2]);
-        const double sb = -P[7] * sin(th - d.Mth0[k]);
-        const double w3 = ((y[2][0] - y[1][0]) * e[0] + (y[2][1] - y[1][1]) * e[1] + (y[2][2] - y[1][2]) * e[2]) / l2;
-        const double w4 = ((y[3][0] - y[1][0]) * e[0] + (y[3][1] - y[1][1]) * e[1] + (y[3][2] - y[1][2]) * e[2]) / l2;
-        for (int u = 0; u < 3; u++) {
-            const double g3 = -l * N1[u] / q1, g4 = -l * N2[u] / q2, g1 = w3 * g3 + w4 * g4;
-            const double g = role == 0 ? g1 : role == 1 ? -(g1 + g3 + g4) : role == 2 ? g3 : g4;
-            f[u] = sb * g;
-        }
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-        f[0] += __shfl_xor(f[0], o);
-        f[1] += __shfl_xor(f[1], o);
-        f[2] += __shfl_xor(f[2], o);
-        dV += __shfl_xor(dV, o);
-    }
-    const double xn[3] = {X[v], X[d.ms + v], X[2 * d.ms + v]};
-    double Fs[3];
-    for (int u = 0; u < 3; u++) {
-        const long long k = u * d.ms + v;
-        const double us = d.Mus[k];
-        const double dx = us + 0.5 * f[u] / P[4];
-        const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
-        Fs[u] = (U - us) * dV;
-        if (lane == 0) {
+            const long long k = u * d.ms + v;
+            xn[u] = X[k];
+            const double us = d.Mus[k];
+            const double dx = us + 0.5 * f[u] / P[4];
+            const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
+            const double Fs = (U - us) * dV;
             d.MX[mp ^ 1][k] = xn[u] + dx;
             d.Mdxm[k] = dx;
-            d.MF[k] = Fs[u];
+            d.MF[k] = Fs;
+            sF[t][u] = Fs;
+            const int o = (int)floor(xn[u]) - 1;
+            so[t][u] = o;
+            lo[u] = o;
+            hi[u] = o;
+            for (int k4 = 0; k4 < 4; k4++) sw[t][4 * u + k4] = phi_cos(xn[u] - (o + k4));
         }
     }
-    // spread record at x^n: origin, the delta weights per axis, F
-    int o[3];
-    for (int u = 0; u < 3; u++) o[u] = (int)floor(xn[u]) - 1;
-    if (lane < 12) {
-        const int u = lane >> 2, k = lane & 3;
-        d.mrec[16 * (long long)v + lane] = phi_cos(xn[u] - (o[u] + k));
-    } else if (lane < 15) {
-        d.mrec[16 * (long long)v + lane] = Fs[lane - 12];
-    } else if (lane < 18) {
-        d.morg[4 * (long long)v + lane - 15] = o[lane - 15];
+    if (t < 64) {
+        // the patch's vertices are the first wave: its box by lane reductions
+        for (int k = 32; k >= 1; k >>= 1)
+            for (int u = 0; u < 3; u++) {
+                lo[u] = min(lo[u], __shfl_xor(lo[u], k));
+                hi[u] = max(hi[u], __shfl_xor(hi[u], k));
+            }
+        if (t == 0)
+            for (int u = 0; u < 3; u++) {
+                sbox[u] = lo[u];
+                sbox[3 + u] = (int)min((long long)hi[u] - lo[u] + 4, (long long)INT_MAX);
+            }
     }
-    // the lists: lane (b, c, a) = column (o_y + b, o_z + c) and the segment of
-    // stencil x o_x + a, counted once per segment (the first a that has it)
-    {
-        const int b = lane & 3, c = (lane >> 2) & 3, a = lane >> 4;
-        const int sa = (((o[0] + a) % d.nx) + d.nx) % d.nx / 64;
-        bool first = true;
-        for (int k = 0; k < 3; k++)
-            if (k < a) first = first && (((o[0] + k) % d.nx) + d.nx) % d.nx / 64 != sa;
-        const int y = o[1] + b, z = o[2] + c;
+    __syncthreads();
+    const int lx = sbox[0], ly = sbox[1], lz = sbox[2], ex = sbox[3], ey = sbox[4], ez = sbox[5];
+    const bool inbox = ex >= 4 && ex <= BOX && ey >= 4 && ey <= BOX && ez >= 4 && ez <= BOX;
+    const int nb = inbox ? ex * ey * ez : 0;
+    for (int i = t; i < nb; i += PATCH_THREADS) box[i][0] = box[i][1] = box[i][2] = 0;
+    __syncthreads();
+    for (int i = t; i < 64 * pn; i += PATCH_THREADS) {
+        const int j = i >> 6, l = i & 63, a = l & 3, b = (l >> 2) & 3, c = l >> 4;
+        const int y = so[j][1] + b, z = so[j][2] + c;
         const int col = (y >= 0 && y < d.ny && z >= 0 && z < d.nz) ? d.colof[z * d.ny + y] : -1;
         if (col < 0) {
             atomicOr(d.err, ERR_STENCIL);
-        } else if (first) {
-            const long long item = (long long)col * d.nseg + sa;
-            const int slot = atomicAdd(d.icount + item, 1);
-            if (slot < ICAP)
-                d.ilist[item * ICAP + slot] = v;
-            else
-                atomicOr(d.err, ERR_LIST);
+            continue;
         }
+        const double W = sw[j][a] * sw[j][4 + b] * sw[j][8 + c];
+        const int xu = so[j][0] + a;   // unwrapped
+        for (int u = 0; u < 3; u++) {
+            const double cq = W * sF[j][u] * FIX_ONE;
+            if (!(fabs(cq) < 4.0e18)) {
+                atomicOr(d.err, ERR_FORCE);
+                continue;
+            }
+            const unsigned long long iv = (unsigned long long)__double2ll_rn(cq);
+            if (inbox) {
+                atomicAdd(&box[((z - lz) * ey + (y - ly)) * ex + (xu - lx)][u], iv);
+            } else {
+                const int xw = (xu % d.nx + d.nx) % d.nx;
+                atomicAdd(d.mforce + u * d.fs + (long long)(z * d.ny + y) * d.pitch + xw, iv);
+                d.mflag[col * d.nseg + xw / 64] = 1;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < nb; i += PATCH_THREADS) {
+        const unsigned long long v0 = box[i][0], v1 = box[i][1], v2 = box[i][2];
+        if ((v0 | v1 | v2) == 0) continue;
+        const int ix = i % ex, iy = (i / ex) % ey, iz = i / (ex * ey);
+        const int y = ly + iy, z = lz + iz, xw = ((lx + ix) % d.nx + d.nx) % d.nx;
+        const int col = d.colof[z * d.ny + y];   // fluid: only fluid nodes received contributions
+        const long long node = (long long)(z * d.ny + y) * d.pitch + xw;
+        if (v0) atomicAdd(d.mforce + node, v0);
+        if (v1) atomicAdd(d.mforce + d.fs + node, v1);
+        if (v2) atomicAdd(d.mforce + 2 * d.fs + node, v2);
+        d.mflag[col * d.nseg + xw / 64] = 1;
     }
 }
 
@@ -754,10 +776,14 @@ struct capib3d_ctx {
     size_t off_vnode = 0, off_vW = 0, off_vdV = 0, off_vpos = 0, off_vF = 0, off_contrib = 0, off_unode = 0,
            off_islot = 0, off_fitem = 0, off_sbeg = 0;
     size_t off_MX[2]{}, off_Mdxm = 0, off_Mus = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
-           off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_vmem = 0,
-           off_twave = 0, off_mtfx = 0, off_mrec = 0, off_morg = 0, off_icount = 0, off_ilist = 0, off_colof = 0,
+           off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_ewave = 0,
+           off_me0 = 0, off_mne = 0, off_tcf = 0, off_ecf = 0, off_ptab = 0, off_mforce = 0, off_mflag = 0,
+           off_twave = 0, off_mtfx = 0, off_colof = 0,
            off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_vel = 0;
-    int ntw = 0;                          // totals waves
+    int ntw = 0, new_ = 0;                // triangle waves, edge waves
+    std::vector<int> perm;                // internal vertex -> the caller's vertex
+    std::vector<int> ptab;                // [npatch][3]
+    std::vector<int> m_e0, m_ne;          // edge ranges
     Dev3 d{};
     std::string err = "no error";
 };
@@ -906,7 +932,14 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_mpar = o; o = al256(o + MM * 8 * 8);
     c->off_mtot = o; o = al256(o + MM * 2 * 8);
     (void)fs;
-    c->off_vmem = o; o = al256(o + MV * 4);
+    c->off_ewave = o; o = al256(o + ((3 * MT) / 2 / 64 + MM + 1) * 2 * 4);
+    c->off_me0 = o; o = al256(o + MM * 4);
+    c->off_mne = o; o = al256(o + MM * 4);
+    c->off_tcf = o; o = al256(o + MT * 32 * 8);
+    c->off_ecf = o; o = al256(o + ((3 * MT) / 2 + 1) * 12 * 8);
+    c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 3 * 4);
+    c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
+    c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
     const size_t ME = (3 * MT) / 2 + 1;   // interior edges of the triangles at most
     c->off_medge = o; o = al256(o + ME * 4 * 4);
     c->off_mth0 = o; o = al256(o + ME * 8);
@@ -914,10 +947,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_vel = o; o = al256(o + ME * 4 * 4);
     c->off_twave = o; o = al256(o + (MT / 64 + MM) * 2 * 4);
     c->off_mtfx = o; o = al256(o + 2 * MM * 2 * 8);
-    c->off_mrec = o; o = al256(o + MV * 16 * 8);
-    c->off_morg = o; o = al256(o + MV * 4 * 4);
-    c->off_icount = o; o = al256(o + (MV ? nitem * 4 : 0));
-    c->off_ilist = o; o = al256(o + (MV ? nitem * ICAP * 4 : 0));
+
     c->off_colof = o; o = al256(o + (size_t)L.ny * L.nz * 4);
     c->off_err = o; o = al256(o + 4);
     c->ws = o;
@@ -996,7 +1026,20 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.mnt = (const int *)(c->base + c->off_mnt);
     d.mpar = (const double *)(c->base + c->off_mpar);
     d.mtot = (double *)(c->base + c->off_mtot);
-    d.vmem = (const int *)(c->base + c->off_vmem);
+    d.ewave = (const int *)(c->base + c->off_ewave);
+    d.me0 = (const int *)(c->base + c->off_me0);
+    d.mne = (const int *)(c->base + c->off_mne);
+    d.new_ = 0;
+    d.tcf = (double *)(c->base + c->off_tcf);
+    d.ecf = (double *)(c->base + c->off_ecf);
+    d.ptab = (const int *)(c->base + c->off_ptab);
+    d.mforce = (unsigned long long *)(c->base + c->off_mforce);
+    d.mflag = (int *)(c->base + c->off_mflag);
+    c->new_ = 0;
+    c->perm.clear();
+    c->ptab.clear();
+    c->m_e0.clear();
+    c->m_ne.clear();
     d.Medge = (const int *)(c->base + c->off_medge);
     d.Mth0 = (const double *)(c->base + c->off_mth0);
     d.veb = (const int *)(c->base + c->off_veb);
@@ -1005,10 +1048,7 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.ntw = 0;
     d.mcap = L.max_membranes;
     d.mtfx = (unsigned long long *)(c->base + c->off_mtfx);
-    d.mrec = (double *)(c->base + c->off_mrec);
-    d.morg = (int *)(c->base + c->off_morg);
-    d.icount = (int *)(c->base + c->off_icount);
-    d.ilist = (int *)(c->base + c->off_ilist);
+
     c->ntw = 0;
     d.colof = (const int *)(c->base + c->off_colof);
     d.err = (int *)(c->base + c->off_err);
@@ -1059,18 +1099,18 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     const int nvb = ((c->nv + WAVES - 1) / WAVES + 7) / 8 * 8, nfb = ((c->nslot + WAVES - 1) / WAVES + 7) / 8 * 8;
     const dim3 g1(nfb + (s1 + WAVES - 1) / WAVES), g2(nvb + (s2 - s1 + WAVES - 1) / WAVES),
         g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
-    const int mvb = (c->mvn + WAVES - 1) / WAVES;
-    const dim3 gm(mvb), gi(mvb + (c->ntw + WAVES - 1) / WAVES);
+    const int mvb = (c->mvn + WAVES - 1) / WAVES, ntb = (c->ntw + WAVES - 1) / WAVES;
+    const dim3 gi(mvb + ntb + (c->new_ + WAVES - 1) / WAVES), gp((unsigned)(c->ptab.size() / 3));
     for (int t = 0; t < nsteps && c->nm > 0; t++) {
         const int mp = c->mpar;
         if (c->par) {
             hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 1> : k3_m_interp<float, 1>), gi, blk, 0, c->stream, c->d, mp,
-                               mvb);
+                               mvb, ntb);
         } else {
             hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 0> : k3_m_interp<float, 0>), gi, blk, 0, c->stream, c->d, mp,
-                               mvb);
+                               mvb, ntb);
         }
-        hipLaunchKernelGGL(k3_m_body, gm, blk, 0, c->stream, c->d, mp);
+        hipLaunchKernelGGL(k3_m_patch, gp, dim3(PATCH_THREADS), 0, c->stream, c->d, mp);
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 2> : k3_sweep<float, 1, 2>), dim3(c->nblk), blk, 0,
                                c->stream, c->d);
@@ -1370,6 +1410,35 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
                 if (c->colof[(size_t)(oz + zc) * L.ny + oy + yb] < 0)
                     return fail3(c, CAPIB_E_ARG, "vertex %d: stencil node on a solid column", v);
     }
+    // internal numbering: recursive bisection of the rest positions along the
+    // longest extent, splitting at a multiple of 64, so that every 64
+    // consecutive vertices (a patch) lie close together;
+    // pp[internal] = the caller's index, ip[caller's] = internal
+    std::vector<int> pp(nv), ip(nv);
+    {
+        for (int v = 0; v < nv; v++) pp[v] = v;
+        std::vector<std::pair<int, int>> todo{{0, nv}};
+        while (!todo.empty()) {
+            const auto [b0, b1] = todo.back();
+            todo.pop_back();
+            if (b1 - b0 <= 64) continue;
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            for (int k = b0; k < b1; k++)
+                for (int u = 0; u < 3; u++) {
+                    lo[u] = std::min(lo[u], xyz[3 * pp[k] + u]);
+                    hi[u] = std::max(hi[u], xyz[3 * pp[k] + u]);
+                }
+            int ax = 0;
+            for (int u = 1; u < 3; u++)
+                if (hi[u] - lo[u] > hi[ax] - lo[ax]) ax = u;
+            std::stable_sort(pp.begin() + b0, pp.begin() + b1,
+                             [&](int a, int b) { return xyz[3 * a + ax] < xyz[3 * b + ax]; });
+            const int half = std::min(b1 - b0, ((b1 - b0 + 1) / 2 + 63) / 64 * 64);
+            todo.push_back({b0 + half, b1});
+            todo.push_back({b0, b0 + half});
+        }
+        for (int k = 0; k < nv; k++) ip[pp[k]] = k;
+    }
     // rest data of every triangle: the rest triangle in its own frame,
     // X0 = 0, X1 = (l, 0), X2 = (p, q); the rows of [X1 - X0, X2 - X0]^-1 are
     // the gradients g1, g2, and g0 = -g1 - g2
@@ -1408,7 +1477,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     }
     if (!(A0 > 0) || !(V0 > 0)) return fail3(c, CAPIB_E_ARG, "membrane must enclose a positive volume (counter-clockwise from outside)");
     c->m_v0.push_back(v0); c->m_nv.push_back(nv); c->m_t0.push_back(t0); c->m_nt.push_back(ntri);
-    for (int k = 0; k < 3 * ntri; k++) c->mtri.push_back(v0 + tri[k]);
+    for (int k = 0; k < 3 * ntri; k++) c->mtri.push_back(v0 + ip[tri[k]]);
     c->mref.insert(c->mref.end(), ref.begin(), ref.end());
     // interior edges: each directed edge a -> b (a < b) of a triangle, paired
     // with the triangle holding b -> a; in the order of first appearance
@@ -1425,7 +1494,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
                 auto it = opp.find({b, a});
                 if (it == opp.end()) continue;
                 const int E[4] = {a, b, c3, it->second};
-                for (int r = 0; r < 4; r++) edges.push_back(v0 + E[r]);
+                for (int r = 0; r < 4; r++) edges.push_back(v0 + ip[E[r]]);
                 // rest dihedral angle, atan2((n1 x n2).e, n1.n2)
                 double e[3], me[3], a3[3], b4[3], N1[3], N2[3], c12[3];
                 sub3h(xyz + 3 * b, xyz + 3 * a, e);
@@ -1465,30 +1534,38 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
         for (int k = 0; k < me; k++)
             for (int r = 0; r < 4; r++) vel[fe[c->medge[4 * k + r]]++] = 4 * k + r;
     }
-    for (int v = 0; v < c->mvn; v++)
-        if (vtb[v + 1] - vtb[v] > 32 || veb[v + 1] - veb[v] > 32) {
-            // roll back: more than 64 triangles meet at one vertex
-            c->nm--; c->mvn -= nv; c->mtn -= ntri;
-            c->m_v0.pop_back(); c->m_nv.pop_back(); c->m_t0.pop_back(); c->m_nt.pop_back();
-            c->mtri.resize(3 * (size_t)c->mtn); c->mref.resize(8 * (size_t)c->mtn); c->mparam.resize(8 * (size_t)c->nm);
-            c->medge.resize(c->medge.size() - edges.size()); c->mth0.resize(c->mth0.size() - th0.size());
-            c->mmaxv = 0;
-            for (int k : c->m_nv) c->mmaxv = std::max(c->mmaxv, k);
-            return fail3(c, CAPIB_E_ARG, "more than 32 triangles or 32 edge terms meet at a vertex");
-        }
     std::vector<int> fill(vtb.begin(), vtb.end() - 1);
     for (int t = 0; t < c->mtn; t++)
         for (int a = 0; a < 3; a++) vtl[fill[c->mtri[3 * t + a]]++] = 4 * t + a;
     // the membrane of each vertex, and the totals waves (64 triangles of one membrane each)
-    std::vector<int> vmem(c->mvn), twave;
+    // the caller's index of every internal vertex; the patches, triangle waves and edge waves
+    for (int k = 0; k < nv; k++) c->perm.push_back(v0 + pp[k]);
+    for (int k0 = 0; k0 < nv; k0 += 64) {
+        c->ptab.push_back(v0 + k0);
+        c->ptab.push_back(std::min(64, nv - k0));
+        c->ptab.push_back(c->nm - 1);
+    }
+    c->m_e0.push_back(me - (int)th0.size());
+    c->m_ne.push_back((int)th0.size());
+    std::vector<int> twave, ewave;
     for (int k = 0; k < c->nm; k++) {
-        for (int v = c->m_v0[k]; v < c->m_v0[k] + c->m_nv[k]; v++) vmem[v] = k;
         for (int t = c->m_t0[k]; t < c->m_t0[k] + c->m_nt[k]; t += 64) {
             twave.push_back(k);
             twave.push_back(t);
         }
+        for (int e = c->m_e0[k]; e < c->m_e0[k] + c->m_ne[k]; e += 64) {
+            ewave.push_back(k);
+            ewave.push_back(e);
+        }
     }
-    HIP3(c, hipMemcpyAsync(c->base + c->off_vmem, vmem.data(), vmem.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_ptab, c->ptab.data(), c->ptab.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_me0, c->m_e0.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_mne, c->m_ne.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
+    if (!ewave.empty())
+        HIP3(c, hipMemcpyAsync(c->base + c->off_ewave, ewave.data(), ewave.size() * 4, hipMemcpyHostToDevice,
+                               c->stream));
+    c->new_ = (int)(ewave.size() / 2);
+    c->d.new_ = c->new_;
     if (me > 0) {
         HIP3(c, hipMemcpyAsync(c->base + c->off_medge, c->medge.data(), c->medge.size() * 4, hipMemcpyHostToDevice,
                                c->stream));
@@ -1504,7 +1581,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     const size_t MS = (size_t)L.max_membrane_vertices;
     std::vector<double> plane(nv);
     for (int u = 0; u < 3; u++) {
-        for (int v = 0; v < nv; v++) plane[v] = xyz[3 * v + u];
+        for (int k = 0; k < nv; k++) plane[k] = xyz[3 * pp[k] + u];
         HIP3(c, hipMemcpyAsync(c->base + c->off_MX[c->mpar] + (u * MS + v0) * 8, plane.data(), nv * 8,
                                hipMemcpyHostToDevice, c->stream));
         HIP3(c, hipMemsetAsync(c->base + c->off_Mdxm + (u * MS + v0) * 8, 0, nv * 8, c->stream));
@@ -1533,7 +1610,7 @@ static capib_status membrane_planes(capib3d_ctx *c, size_t off, double *out, con
     std::vector<double> pl(3 * n);
     if (in) {
         for (size_t v = 0; v < n; v++)
-            for (int u = 0; u < 3; u++) pl[u * n + v] = in[3 * v + u];
+            for (int u = 0; u < 3; u++) pl[u * n + v] = in[3 * (size_t)c->perm[v] + u];
         for (int u = 0; u < 3; u++)
             HIP3(c, hipMemcpyAsync(c->base + off + u * MS * 8, &pl[u * n], n * 8, hipMemcpyHostToDevice, c->stream));
         HIP3(c, hipStreamSynchronize(c->stream));
@@ -1543,7 +1620,7 @@ static capib_status membrane_planes(capib3d_ctx *c, size_t off, double *out, con
         HIP3(c, hipMemcpyAsync(&pl[u * n], c->base + off + u * MS * 8, n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP3(c, hipStreamSynchronize(c->stream));
     for (size_t v = 0; v < n; v++)
-        for (int u = 0; u < 3; u++) out[3 * v + u] = pl[u * n + v];
+        for (int u = 0; u < 3; u++) out[3 * (size_t)c->perm[v] + u] = pl[u * n + v];
     return CAPIB_OK;
 }
 

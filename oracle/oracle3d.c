@@ -28,6 +28,13 @@
  *       update of the 2D membranes, dx = u* + f/(2m), x^{n+1} = x^n + dx,
  *       U = 3/2 dx - 1/2 dx_prev; F = (U - u*) dV spread at x^n, dV a third
  *       of the adjacent triangles' area at x^n                  (Secs. 2.2-2.4 in 3D)
+ *   S3" ligand-receptor bonds between sites on one membrane's triangles and
+ *       the tube wall: a bound site pulls with sigma (y_l - y_eq) along its
+ *       triangle's outward normal, a third on each corner (Eq. 13 in 3D);
+ *       after the update, Bell-type kinetics at x^{n+1} with the 2D oracle's
+ *       Philox draws: a bond breaks with P_r = 1 - exp(-k_r0 exp(|y_l - y_eq|
+ *       / l_B)), an unbound site within y_cr of the wall binds with
+ *       P_f = 1 - exp(-k_f), anchored on the wall radially outward (Sec. 2.5)
  *   S4  BGK collision towards the equilibrium with the Guo term for the
  *       total force g + f_ib, u = (sum f e + (g + f_ib)/2)/rho   (Eqs. 1, 2, 4-6)
  * Populations are stored shifted, h_i = f_i - w_i, as in the 2D oracle.
@@ -39,6 +46,7 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <stdint.h>
 #include <omp.h>
 #include <stdlib.h>
 #include <string.h>
@@ -116,6 +124,16 @@ typedef struct {
     int me;                 /* edges in all */
     int *Medge;             /* [me][4] x1, x2 (the edge), x3, x4 (opposite vertices) */
     double *Mth0;           /* [me] rest dihedral angle */
+    /* bonds: sites on the triangles of membrane bm */
+    int ns, bm;
+    int *Stri;              /* [ns] triangle (global index) */
+    double *Sbary;          /* [ns][2] barycentric coordinates (corners 1 and 2) */
+    int *Sbound;            /* [ns] bound */
+    double *Sanc;           /* [ns][3] anchor on the wall */
+    double b_sigma, b_yeq, b_ycr, b_kf, b_kr0, b_lb;
+    uint64_t b_seed;
+    double min_margin_p, min_margin_gap;
+    long long flips;
     double *m_A0, *m_V0;    /* [nm] rest area and enclosed volume */
     double *MX, *Mdxm;      /* [mv][3] positions, displacement of the previous step */
     double *Mus, *Mf, *MF;  /* [mv][3] u*, elastic force, spread force of the current step */
@@ -155,6 +173,7 @@ void orc3_destroy(orc3 *s) {
     free(s->m_v0); free(s->m_nv); free(s->m_t0); free(s->m_nt); free(s->m_par); free(s->m_A0); free(s->m_V0);
     free(s->MX); free(s->Mdxm); free(s->Mus); free(s->Mf); free(s->MF); free(s->Mtri); free(s->Mref);
     free(s->m_e0); free(s->m_ne); free(s->Medge); free(s->Mth0);
+    free(s->Stri); free(s->Sbary); free(s->Sbound); free(s->Sanc);
     free(s);
 }
 
@@ -435,6 +454,22 @@ void orc3_membrane_energy(const orc3 *s, int m, double *out4) {
     out4[3] = eb;
 }
 
+double orc_uniform(uint64_t seed, int64_t n, int32_t s);   /* the 2D oracle's bond draw */
+
+/* Site q's position and its triangle's unit outward normal. */
+static void site3(const orc3 *s, int q, double p[3], double n[3]) {
+    const int *T = s->Mtri + 3 * s->Stri[q];
+    const double *a = s->MX + 3 * T[0], *b = s->MX + 3 * T[1], *c = s->MX + 3 * T[2];
+    const double b1 = s->Sbary[2 * q], b2 = s->Sbary[2 * q + 1];
+    double e1[3], e2[3];
+    sub3(b, a, e1);
+    sub3(c, a, e2);
+    for (int i = 0; i < 3; i++) p[i] = a[i] + b1 * e1[i] + b2 * e2[i];
+    cross3(e1, e2, n);
+    const double nn = sqrt(dot3(n, n));
+    for (int i = 0; i < 3; i++) n[i] /= nn;
+}
+
 /* Elastic forces of membrane m into Mf, minus the gradients of its three
  * energies: for triangle t and its corner a,
  *   Skalak  -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], w1 = dw/dI1, w2 = dw/dI2
@@ -485,6 +520,19 @@ static void membrane_forces(orc3 *s, int m) {
             for (int i = 0; i < 3; i++) f[i] += fa[i] - ca * 0.5 * nbc[i] - cv * bc[i] / 6.0;
         }
     }
+    /* bonds (Eq. 13 in 3D): sigma (y_l - y_eq) along the triangle's outward
+     * normal, a third on each corner, site by site */
+    if (s->ns && m == s->bm)
+        for (int q = 0; q < s->ns; q++) {
+            if (!s->Sbound[q]) continue;
+            double ps[3], n[3], dl[3];
+            site3(s, q, ps, n);
+            sub3(ps, s->Sanc + 3 * q, dl);
+            const double f = s->b_sigma * (sqrt(dot3(dl, dl)) - s->b_yeq);
+            const int *T = s->Mtri + 3 * s->Stri[q];
+            for (int k = 0; k < 3; k++)
+                for (int i = 0; i < 3; i++) s->Mf[3 * T[k] + i] += f / 3.0 * n[i];
+        }
     /* bending: -k_b sin(theta - theta0) grad theta, edge by edge */
     for (int k = s->m_e0[m]; k < s->m_e0[m] + s->m_ne[m]; k++) {
         const int *E = s->Medge + 4 * k;
@@ -493,6 +541,42 @@ static void membrane_forces(orc3 *s, int m) {
         const double sb = -P[5] * sin(th - s->Mth0[k]);
         for (int r = 0; r < 4; r++)
             for (int i = 0; i < 3; i++) s->Mf[3 * E[r] + i] += sb * g[r][i];
+    }
+}
+
+/* Bond kinetics at x^{n+1} (S3"): the draw of site q at step n is the 2D
+ * oracle's; the wall is the tube's cylinder of radius R about the axis
+ * ((ny-1)/2, (nz-1)/2); the gap of a site is R minus its distance from the
+ * axis, a new bond's anchor the wall point radially outward of the site.
+ * The smallest |draw - P| / P and |gap - y_cr| of the decisions are kept.   */
+static void bonds3(orc3 *s) {
+    const double yc = 0.5 * (s->ny - 1), zc = 0.5 * (s->nz - 1), R = s->radius;
+    for (int q = 0; q < s->ns; q++) {
+        double ps[3], n[3];
+        site3(s, q, ps, n);
+        const double r = orc_uniform(s->b_seed, s->step, q);
+        if (s->Sbound[q]) {
+            double dl[3];
+            sub3(ps, s->Sanc + 3 * q, dl);
+            const double yl = sqrt(dot3(dl, dl));
+            const double P = 1.0 - exp(-s->b_kr0 * exp(fabs(yl - s->b_yeq) / s->b_lb));
+            if (P > 0 && fabs(r - P) / P < s->min_margin_p) s->min_margin_p = fabs(r - P) / P;
+            if (r < P) { s->Sbound[q] = 0; s->flips++; }
+        } else {
+            const double dy = ps[1] - yc, dz = ps[2] - zc, rho = sqrt(dy * dy + dz * dz), gap = R - rho;
+            const double P = 1.0 - exp(-s->b_kf);
+            if (r < P && fabs(gap - s->b_ycr) < s->min_margin_gap) s->min_margin_gap = fabs(gap - s->b_ycr);
+            if (gap < s->b_ycr) {
+                if (P > 0 && fabs(r - P) / P < s->min_margin_p) s->min_margin_p = fabs(r - P) / P;
+                if (r < P) {
+                    s->Sbound[q] = 1;
+                    s->flips++;
+                    s->Sanc[3 * q] = ps[0];
+                    s->Sanc[3 * q + 1] = yc + R * dy / rho;
+                    s->Sanc[3 * q + 2] = zc + R * dz / rho;
+                }
+            }
+        }
     }
 }
 
@@ -527,6 +611,7 @@ static void membranes3(orc3 *s) {
         }
     }
     free(dV);
+    if (s->ns) bonds3(s);
 }
 
 /* A deformable membrane: a closed triangulated surface (nv vertices xyz
@@ -620,6 +705,51 @@ int orc3_add_membrane(orc3 *s, int nv, const double *xyz, int ntri, const int *t
         }
     if (!s->f) s->f = (double *)calloc((size_t)(3 * s->n), sizeof(double));
     return v0;
+}
+
+/* Bond sites on membrane m (tube geometry only): ns sites, each on the
+ * membrane's triangle tri[q] (index among its triangles) at barycentric
+ * coordinates bary[q] (weights of corners 1 and 2), all unbound, with the
+ * spring sigma, y_eq, capture distance y_cr, rates k_f, k_r0, l_B and the
+ * seed of the draws.  Returns 0, or -1 if refused (one set per simulation). */
+int orc3_add_bonds(orc3 *s, int m, int ns, const int *tri, const double *bary, double sigma, double yeq, double ycr,
+                   double kf, double kr0, double lb, uint64_t seed) {
+    if (s->ns || m < 0 || m >= s->nm || ns < 1 || s->geom != ORC3_TUBE) return -1;
+    for (int q = 0; q < ns; q++)
+        if (tri[q] < 0 || tri[q] >= s->m_nt[m]) return -1;
+    s->ns = ns;
+    s->bm = m;
+    s->Stri = (int *)malloc(sizeof(int) * ns);
+    s->Sbary = (double *)malloc(sizeof(double) * 2 * ns);
+    s->Sbound = (int *)calloc((size_t)ns, sizeof(int));
+    s->Sanc = (double *)calloc((size_t)(3 * ns), sizeof(double));
+    for (int q = 0; q < ns; q++) s->Stri[q] = s->m_t0[m] + tri[q];
+    memcpy(s->Sbary, bary, sizeof(double) * 2 * ns);
+    s->b_sigma = sigma; s->b_yeq = yeq; s->b_ycr = ycr; s->b_kf = kf; s->b_kr0 = kr0; s->b_lb = lb; s->b_seed = seed;
+    s->min_margin_p = 1e300;
+    s->min_margin_gap = 1e300;
+    s->flips = 0;
+    return 0;
+}
+/* bond states and anchors ([ns], [ns][3]); returns the bound count */
+int orc3_bonds(const orc3 *s, int *bound, double *anchor) {
+    int nb = 0;
+    for (int q = 0; q < s->ns; q++) {
+        if (bound) bound[q] = s->Sbound[q];
+        if (anchor) memcpy(anchor + 3 * q, s->Sanc + 3 * q, sizeof(double) * 3);
+        nb += s->Sbound[q];
+    }
+    return nb;
+}
+void orc3_set_bonds(orc3 *s, const int *bound, const double *anchor) {
+    memcpy(s->Sbound, bound, sizeof(int) * s->ns);
+    memcpy(s->Sanc, anchor, sizeof(double) * 3 * s->ns);
+}
+/* smallest decision margins so far (|draw - P| / P, |gap - y_cr|) and state changes */
+void orc3_bond_margins(const orc3 *s, double *out3) {
+    out3[0] = s->min_margin_p;
+    out3[1] = s->min_margin_gap;
+    out3[2] = (double)s->flips;
 }
 
 void orc3_membrane_vertices(const orc3 *s, double *out) { if (s->mv) memcpy(out, s->MX, sizeof(double) * 3 * s->mv); }

@@ -51,6 +51,13 @@ def _L():
         L.orc3_membrane_spread_forces.argtypes = [C.c_void_p, _dp]
         L.orc3_membrane_totals.argtypes = [C.c_void_p, C.c_int, _dp]
         L.orc3_membrane_energy.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.orc3_add_bonds.restype = C.c_int
+        L.orc3_add_bonds.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), _dp] + [C.c_double] * 6 + [
+            C.c_uint64]
+        L.orc3_bonds.restype = C.c_int
+        L.orc3_bonds.argtypes = [C.c_void_p, C.POINTER(C.c_int), _dp]
+        L.orc3_set_bonds.argtypes = [C.c_void_p, C.POINTER(C.c_int), _dp]
+        L.orc3_bond_margins.argtypes = [C.c_void_p, _dp]
         L.orc3_membrane_dihedrals.restype = C.c_int
         L.orc3_membrane_dihedrals.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         _ready = True
@@ -199,3 +206,29 @@ class Tube:
         th, th0 = np.zeros(n), np.zeros(n)
         self.L.orc3_membrane_dihedrals(self.p, m, _d(th), _d(th0))
         return th, th0
+
+    # bonds
+    def add_bonds(self, m, tri, bary, sigma, yeq, ycr, kf, kr0, lb, seed):
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        bary = np.ascontiguousarray(bary, dtype=np.float64).reshape(-1, 2)
+        if self.L.orc3_add_bonds(self.p, m, len(tri), tri.ctypes.data_as(C.POINTER(C.c_int)), _d(bary), sigma, yeq, ycr,
+                                 kf, kr0, lb, seed) != 0:
+            raise ValueError("orc3_add_bonds refused the sites")
+        self.ns = len(tri)
+
+    def bonds(self):
+        """(bound [ns], anchors [ns][3], bound count)"""
+        b = np.zeros(self.ns, dtype=np.int32)
+        a = np.zeros((self.ns, 3))
+        n = self.L.orc3_bonds(self.p, b.ctypes.data_as(C.POINTER(C.c_int)), _d(a))
+        return b, a, n
+
+    def set_bonds(self, bound, anchor):
+        b = np.ascontiguousarray(bound, dtype=np.int32)
+        a = np.ascontiguousarray(anchor, dtype=np.float64)
+        self.L.orc3_set_bonds(self.p, b.ctypes.data_as(C.POINTER(C.c_int)), _d(a))
+
+    def bond_margins(self):
+        out = np.zeros(3)
+        self.L.orc3_bond_margins(self.p, _d(out))
+        return out

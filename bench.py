@@ -502,30 +502,21 @@ def tube3d_section(args):
             "fp16_storage": fp16, "fixed_body": body, "membranes": mem}
 
 
-def tube3d_membranes(p):
-    """Four 2562-vertex oblate cells (radius 8, axes 1, 1, 0.5) and a
-    642-vertex sphere of radius 4 in the 256 x 64 x 64 tube (Skalak, bending,
-    area and volume penalties)."""
-    from paper_2210_06043_amd import inputs
-    c = 0.5 * (p["ny"] - 1)
-    cells = [inputs.icosphere(4, 8.0, (40.2 + 60 * k, c + (9.0, -7.5, 4.0, -10.0)[k], c + (2.0, 8.0, -9.0, -1.5)[k]),
-                              axes=(1.0, 1.0, 0.5)) for k in range(4)]
-    return cells + [inputs.icosphere(3, 4.0, (128.7, c - 3.0, c - 17.0))]
-
-
-MEMBRANE_PARAMS = dict(gs=5e-3, c=1.0, ka=0.05, kv=0.05, mass=1.0, kb=2e-3)
-
-
 def tube3d_membrane_run(p, prof, warmup, steps):
+    """The 3D workload (inputs.tube3d_workload): four 2562-vertex oblate
+    cells and a 642-vertex oblate particle with 300 ligand sites near the
+    wall, in the 256 x 64 x 64 tube; back-to-back steps on the stream."""
     import torch
-    from paper_2210_06043_amd import tube3d
-    ms_ = tube3d_membranes(p)
-    g = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"], max_membranes=len(ms_),
-                      max_membrane_vertices=sum(len(m[0]) for m in ms_),
-                      max_membrane_triangles=sum(len(m[1]) for m in ms_))
+    from paper_2210_06043_amd import inputs, tube3d
+    w = inputs.tube3d_workload(p)
+    mem = w["cells"] + [w["particle"]]
+    g = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"], max_membranes=len(mem),
+                      max_membrane_vertices=sum(len(m[0]) for m in mem),
+                      max_membrane_triangles=sum(len(m[1]) for m in mem), max_sites=len(w["sites"][0]))
     g.init_flow(prof)
-    for xyz, tri in ms_:
-        g.add_membrane(xyz, tri, **MEMBRANE_PARAMS)
+    for (xyz, tri), q in zip(mem, [w["cell"]] * 4 + [w["part"]]):
+        g.add_membrane(xyz, tri, **q)
+    g.add_bonds(len(mem) - 1, *w["sites"], **w["bonds"])
     g.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -534,13 +525,14 @@ def tube3d_membrane_run(p, prof, warmup, steps):
     g.step(steps)
     e1.record(g.stream)
     e1.synchronize()
-    t = [g.membrane_totals(m) for m in range(len(ms_))]
-    return {"membranes": len(ms_), "vertices": g.membrane_vertex_count, "triangles": sum(len(m[1]) for m in ms_),
+    t = [g.membrane_totals(m) for m in range(len(mem))]
+    return {"membranes": len(mem), "vertices": g.membrane_vertex_count, "triangles": sum(len(m[1]) for m in mem),
+            "sites": len(w["sites"][0]), "bound_after": int(g.bonds()[2]),
             "ms_per_step": e0.elapsed_time(e1) / steps, "error_flags": g.error_flags(),
             "volume_drift_max": float(max(abs(x[1] / x[3] - 1) for x in t)),
-            "note": "three launches per step: k3_m_interp (a wave per vertex; area and volume per 64 triangles), "
-                    "k3_m_body (a wave per vertex: forces, update, spread record, work-item lists), k3_sweep gathering "
-                    "the lists of flagged items"}
+            "note": "per step: k3_m_interp (u* a wave per vertex; triangle and edge terms, area and volume), "
+                    "k3_m_patch (a workgroup per 64 vertices: forces, update, spreading through an LDS box), "
+                    "k3_m_bonds (a thread per site), k3_sweep reading the field on flagged items"}
 
 
 def capib_fp16():

@@ -61,7 +61,8 @@ enum { CAPIB3D_TUBE = 0, CAPIB3D_SLAB = 1, CAPIB3D_BOX = 2 };
  *   fp16_scale  power of two multiplying stored FP16 deviations (FP16 only)
  *   max_vertices  capacity for the vertices of fixed bodies (0: none)
  *   max_membranes, max_membrane_vertices, max_membrane_triangles
- *               capacity for deformable membranes (all 0, or all > 0)     */
+ *               capacity for deformable membranes (all 0, or all > 0)
+ *   max_sites   capacity for ligand-receptor bond sites (needs membranes) */
 typedef struct {
     int32_t nx, ny, nz;
     double tau, gx;
@@ -71,6 +72,7 @@ typedef struct {
     double fp16_scale;
     int32_t max_vertices;
     int32_t max_membranes, max_membrane_vertices, max_membrane_triangles;
+    int32_t max_sites;
 } capib3d_lattice;
 
 /* A deformable membrane's constants (lattice units).
@@ -141,6 +143,36 @@ int32_t capib3d_vertices(const capib3d_ctx *ctx);
  * receives its first vertex among the membrane vertices.  Syncs. */
 capib_status capib3d_add_membrane(capib3d_ctx *ctx, int32_t nv, const double *xyz, int32_t ntri,
                                   const int32_t *tri, const capib3d_membrane *par, int32_t *first_vertex);
+/* Ligand-receptor bonds (Sec. 2.5 and Eq. 13 carried to 3D) between ns
+ * sites on membrane m and the tube wall (CAPIB3D_TUBE only; one set of sites
+ * per context, CAPIB_E_STATE for a second).
+ *   sigma, yeq  spring constant and rest length: a bound site at distance y_l
+ *               from its anchor pulls with sigma (y_l - yeq) along its
+ *               triangle's outward normal, a third on each corner
+ *   ycr         capture distance: an unbound site binds only while
+ *               R - (its distance from the axis) < ycr
+ *   kf          formation: P_f = 1 - exp(-kf) per step
+ *   kr0, lb     rupture: P_r = 1 - exp(-kr0 exp(|y_l - yeq| / lb)) per step
+ *   seed        key of the draws: site q's draw at step n is word 0 of
+ *               Philox4x32-10 with key (seed low, high) and counter
+ *               (n low, q, n high, 0), top 24 bits over 2^24 (as in capib.h)
+ * tri [ns]: the triangle of each site among the membrane's triangles (the
+ * order they were given in); bary [ns][2]: its barycentric weights of
+ * corners 1 and 2 (>= 0, sum <= 1).  The decisions are taken after the
+ * vertex update, at x^{n+1}; a new bond is anchored on the wall (radius R)
+ * radially outward of its site.  All sites start unbound.  Syncs. */
+typedef struct {
+    double sigma, yeq, ycr, kf, kr0, lb;
+    uint64_t seed;
+} capib3d_bonds;
+capib_status capib3d_add_bonds(capib3d_ctx *ctx, int32_t m, int32_t ns, const int32_t *tri, const double *bary,
+                               const capib3d_bonds *par);
+/* Bond states [ns] (may be NULL), anchors [ns][3] (may be NULL) and the
+ * number bound (N_L, may be NULL); writing sets states and anchors.  Both
+ * sync. */
+capib_status capib3d_read_bonds(capib3d_ctx *ctx, int32_t *bound, double *anchor, int64_t *nbound);
+capib_status capib3d_write_bonds(capib3d_ctx *ctx, const int32_t *bound, const double *anchor);
+
 /* Membrane vertex positions, [membrane vertices][3] host doubles, in the
  * order the membranes were added (read and overwrite; the previous
  * displacement is kept).  Both sync. */

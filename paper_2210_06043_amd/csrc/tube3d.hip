@@ -47,7 +47,11 @@
 // vertex update and the direct force, the patch's stencil contributions summed
 // in an LDS box in 2^-50 units and added to a global force field with one
 // atomic per node and component, its work items flagged.  The sweep reads and
-// clears the field on flagged items.
+// clears the field on flagged items.  Ligand-receptor bonds between sites on
+// one membrane's triangles and the tube wall: a bound site's spring force
+// (along its triangle's normal, a third per corner) joins the triangle terms;
+// k3_m_bonds then takes each site's Bell-type decision at x^{n+1} with the
+// same Philox draw as the 2D library.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,6 +65,7 @@
 #include <vector>
 
 #include "../../include/capib3d.h"
+#include "capib_dev.hpp"
 
 namespace tube3d {
 
@@ -122,6 +127,15 @@ struct Dev3 {
     const int *ptab;            // [npatch][3] first vertex, vertices, membrane
     unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
     int *mflag;                 // [ncol * nseg] work item with spread force
+    // bonds
+    int ns;                     // sites
+    const int *Stri;            // [ns] triangle (global)
+    const double *Sbary;        // [ns][2] barycentric weights of corners 1 and 2
+    int *Sbound;                // [ns] bound
+    double *Sanc;               // [ns][3] anchor
+    const int *tsb, *tsl;       // sites of each triangle: [mt + 1] starts, site indices
+    double b_sigma, b_yeq, b_ycr, b_kf, b_kr0, b_lb, radius;
+    unsigned long long b_seed;
     const int *colof;           // [nz][ny] column of a row, -1 solid
     int *err;                   // error flags
 };
@@ -507,6 +521,20 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
                 }
                 out[10 * a + 9] = 0.5 * nn / 3.0;
             }
+            // bound sites on this triangle: sigma (y_l - y_eq) along n, a third per corner
+            for (int k = d.ns > 0 ? d.tsb[t] : 0; d.ns > 0 && k < d.tsb[t + 1]; k++) {
+                const int q = d.tsl[k];
+                if (!d.Sbound[q]) continue;
+                const double b1 = d.Sbary[2 * q], b2 = d.Sbary[2 * q + 1];
+                double dl2 = 0.0;
+                for (int u = 0; u < 3; u++) {
+                    const double ps = x[0][u] + b1 * e1[u] + b2 * e2[u], dl = ps - d.Sanc[3 * q + u];
+                    dl2 += dl * dl;
+                }
+                const double f = d.b_sigma * (sqrt(dl2) - d.b_yeq);
+                for (int a = 0; a < 3; a++)
+                    for (int u = 0; u < 3; u++) out[10 * a + u] += f / 3.0 * n[u];
+            }
             A = 0.5 * nn;
             // the volume term about r0, from the corners relative to r0
             double qr[3];
@@ -554,6 +582,49 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
         d.Mus[v] = ux;
         d.Mus[d.ms + v] = uy;
         d.Mus[2 * d.ms + v] = uz;
+    }
+}
+
+// Bond kinetics at x^{n+1} (positions of parity mp), step n: a thread per
+// site.  The draw is word 0 of Philox4x32-10 with key (seed low, seed high)
+// and counter (n low, site, n high, 0), top 24 bits over 2^24.  Bound: it
+// breaks if the draw is below 1 - exp(-k_r0 exp(|y_l - y_eq| / l_B)).
+// Unbound within y_cr of the wall (R minus the site's distance from the
+// axis): it binds if the draw is below 1 - exp(-k_f), anchored on the wall
+// radially outward of the site.
+__global__ __launch_bounds__(256) void k3_m_bonds(Dev3 d, int mp, long long step) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= d.ns) return;
+    const int *T = d.Mtri + 3 * d.Stri[q];
+    const double *X = d.MX[mp];
+    const double b1 = d.Sbary[2 * q], b2 = d.Sbary[2 * q + 1];
+    double ps[3];
+    for (int u = 0; u < 3; u++) {
+        const double xa = X[u * d.ms + T[0]];
+        ps[u] = xa + b1 * (X[u * d.ms + T[1]] - xa) + b2 * (X[u * d.ms + T[2]] - xa);
+    }
+    const uint32_t w0 = capib::philox_w0((uint32_t)((unsigned long long)step & 0xffffffffu), (uint32_t)q,
+                                         (uint32_t)((unsigned long long)step >> 32), 0u,
+                                         (uint32_t)(d.b_seed & 0xffffffffu), (uint32_t)(d.b_seed >> 32));
+    const double r = (double)(w0 >> 8) * (1.0 / 16777216.0);
+    if (d.Sbound[q]) {
+        double dl2 = 0.0;
+        for (int u = 0; u < 3; u++) {
+            const double dl = ps[u] - d.Sanc[3 * q + u];
+            dl2 += dl * dl;
+        }
+        const double P = 1.0 - exp(-d.b_kr0 * exp(fabs(sqrt(dl2) - d.b_yeq) / d.b_lb));
+        if (r < P) d.Sbound[q] = 0;
+    } else {
+        const double yc = 0.5 * (d.ny - 1), zc = 0.5 * (d.nz - 1);
+        const double dy = ps[1] - yc, dz = ps[2] - zc, rho = sqrt(dy * dy + dz * dz);
+        const double P = 1.0 - exp(-d.b_kf);
+        if (d.radius - rho < d.b_ycr && r < P) {
+            d.Sbound[q] = 1;
+            d.Sanc[3 * q] = ps[0];
+            d.Sanc[3 * q + 1] = yc + d.radius * dy / rho;
+            d.Sanc[3 * q + 2] = zc + d.radius * dz / rho;
+        }
     }
 }
 
@@ -778,12 +849,14 @@ struct capib3d_ctx {
     size_t off_MX[2]{}, off_Mdxm = 0, off_Mus = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
            off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_ewave = 0,
            off_me0 = 0, off_mne = 0, off_tcf = 0, off_ecf = 0, off_ptab = 0, off_mforce = 0, off_mflag = 0,
-           off_twave = 0, off_mtfx = 0, off_colof = 0,
+           off_twave = 0, off_mtfx = 0, off_colof = 0, off_stri = 0, off_sbary = 0, off_sbound = 0, off_sanc = 0,
+           off_tsb = 0, off_tsl = 0,
            off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_vel = 0;
     int ntw = 0, new_ = 0;                // triangle waves, edge waves
     std::vector<int> perm;                // internal vertex -> the caller's vertex
     std::vector<int> ptab;                // [npatch][3]
     std::vector<int> m_e0, m_ne;          // edge ranges
+    int nsite = 0;                        // bond sites
     Dev3 d{};
     std::string err = "no error";
 };
@@ -873,6 +946,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
         if (!(L.fp16_scale > 0.0) || std::frexp(L.fp16_scale, &ex) != 0.5) return CAPIB_E_ARG;   // a power of two
     }
     if (L.max_vertices < 0 || L.max_vertices > (1 << 24)) return CAPIB_E_ARG;
+    if (L.max_sites < 0 || (L.max_sites > 0 && L.max_membranes == 0)) return CAPIB_E_ARG;
     if (L.max_membranes < 0 || L.max_membrane_vertices < 0 || L.max_membrane_triangles < 0 ||
         L.max_membrane_vertices > (1 << 24) || L.max_membrane_triangles > (1 << 25) ||
         (L.max_membrane_vertices > 0) != (L.max_membranes > 0) ||
@@ -940,6 +1014,13 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 3 * 4);
     c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
     c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
+    const size_t MSITE = (size_t)L.max_sites;
+    c->off_stri = o; o = al256(o + MSITE * 4);
+    c->off_sbary = o; o = al256(o + MSITE * 2 * 8);
+    c->off_sbound = o; o = al256(o + MSITE * 4);
+    c->off_sanc = o; o = al256(o + MSITE * 3 * 8);
+    c->off_tsb = o; o = al256(o + (MSITE ? MT + 1 : 0) * 4);
+    c->off_tsl = o; o = al256(o + MSITE * 4);
     const size_t ME = (3 * MT) / 2 + 1;   // interior edges of the triangles at most
     c->off_medge = o; o = al256(o + ME * 4 * 4);
     c->off_mth0 = o; o = al256(o + ME * 8);
@@ -1035,6 +1116,15 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.ptab = (const int *)(c->base + c->off_ptab);
     d.mforce = (unsigned long long *)(c->base + c->off_mforce);
     d.mflag = (int *)(c->base + c->off_mflag);
+    d.ns = 0;
+    d.Stri = (const int *)(c->base + c->off_stri);
+    d.Sbary = (const double *)(c->base + c->off_sbary);
+    d.Sbound = (int *)(c->base + c->off_sbound);
+    d.Sanc = (double *)(c->base + c->off_sanc);
+    d.tsb = (const int *)(c->base + c->off_tsb);
+    d.tsl = (const int *)(c->base + c->off_tsl);
+    d.radius = L.radius;
+    c->nsite = 0;
     c->new_ = 0;
     c->perm.clear();
     c->ptab.clear();
@@ -1111,6 +1201,9 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
                                mvb, ntb);
         }
         hipLaunchKernelGGL(k3_m_patch, gp, dim3(PATCH_THREADS), 0, c->stream, c->d, mp);
+        if (c->nsite > 0)
+            hipLaunchKernelGGL(k3_m_bonds, dim3((c->nsite + 255) / 256), dim3(256), 0, c->stream, c->d, mp ^ 1,
+                               (long long)c->step);
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 2> : k3_sweep<float, 1, 2>), dim3(c->nblk), blk, 0,
                                c->stream, c->d);
@@ -1658,6 +1751,85 @@ capib_status capib3d_membrane_totals(capib3d_ctx *c, int32_t m, double *out4) {
     out4[1] = t[1];
     out4[2] = c->mparam[8 * (size_t)m + 5];
     out4[3] = c->mparam[8 * (size_t)m + 6];
+    return CAPIB_OK;
+}
+
+capib_status capib3d_add_bonds(capib3d_ctx *c, int32_t m, int32_t ns, const int32_t *tri, const double *bary,
+                               const capib3d_bonds *par) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    const capib3d_lattice &L = c->lat;
+    if (c->nsite > 0) return fail3(c, CAPIB_E_STATE, "the context already holds its bond sites");
+    if (L.geometry != CAPIB3D_TUBE) return fail3(c, CAPIB_E_ARG, "bonds need the tube geometry");
+    if (m < 0 || m >= c->nm) return fail3(c, CAPIB_E_ARG, "no membrane %d", m);
+    if (ns < 1 || !tri || !bary || !par) return fail3(c, CAPIB_E_ARG, "bad bond arrays");
+    if (ns > L.max_sites) return fail3(c, CAPIB_E_CAPACITY, "%d sites exceed the capacity of %d", ns, L.max_sites);
+    const double pv[6] = {par->sigma, par->yeq, par->ycr, par->kf, par->kr0, par->lb};
+    for (double x : pv)
+        if (!std::isfinite(x)) return fail3(c, CAPIB_E_ARG, "non-finite bond parameter");
+    if (par->kf < 0 || par->kr0 < 0 || !(par->lb > 0)) return fail3(c, CAPIB_E_ARG, "rates must be >= 0 and l_B > 0");
+    std::vector<int> st(ns);
+    for (int q = 0; q < ns; q++) {
+        if (tri[q] < 0 || tri[q] >= c->m_nt[m]) return fail3(c, CAPIB_E_ARG, "site %d: triangle out of range", q);
+        const double b1 = bary[2 * q], b2 = bary[2 * q + 1];
+        if (!(b1 >= 0) || !(b2 >= 0) || !(b1 + b2 <= 1)) return fail3(c, CAPIB_E_ARG, "site %d: not inside its triangle", q);
+        st[q] = c->m_t0[m] + tri[q];
+    }
+    // the sites of every triangle
+    std::vector<int> tsb(c->mtn + 1, 0), tsl(ns);
+    for (int q = 0; q < ns; q++) tsb[st[q] + 1]++;
+    for (int t = 0; t < c->mtn; t++) tsb[t + 1] += tsb[t];
+    {
+        std::vector<int> f(tsb.begin(), tsb.end() - 1);
+        for (int q = 0; q < ns; q++) tsl[f[st[q]]++] = q;
+    }
+    HIP3(c, hipMemcpyAsync(c->base + c->off_stri, st.data(), ns * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_sbary, bary, ns * 16, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemsetAsync(c->base + c->off_sbound, 0, ns * 4, c->stream));
+    HIP3(c, hipMemsetAsync(c->base + c->off_sanc, 0, ns * 24, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_tsb, tsb.data(), tsb.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_tsl, tsl.data(), ns * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipStreamSynchronize(c->stream));
+    Dev3 &d = c->d;
+    d.b_sigma = par->sigma; d.b_yeq = par->yeq; d.b_ycr = par->ycr; d.b_kf = par->kf; d.b_kr0 = par->kr0;
+    d.b_lb = par->lb; d.b_seed = par->seed;
+    d.ns = ns;
+    c->nsite = ns;
+    return CAPIB_OK;
+}
+
+capib_status capib3d_read_bonds(capib3d_ctx *c, int32_t *bound, double *anchor, int64_t *nbound) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    std::vector<int> b(c->nsite);
+    if (c->nsite) {
+        HIP3(c, hipMemcpyAsync(b.data(), c->base + c->off_sbound, c->nsite * 4, hipMemcpyDeviceToHost, c->stream));
+        if (anchor)
+            HIP3(c, hipMemcpyAsync(anchor, c->base + c->off_sanc, c->nsite * 24, hipMemcpyDeviceToHost, c->stream));
+        HIP3(c, hipStreamSynchronize(c->stream));
+    }
+    int64_t n = 0;
+    for (int q = 0; q < c->nsite; q++) {
+        if (bound) bound[q] = b[q];
+        n += b[q];
+    }
+    if (nbound) *nbound = n;
+    return CAPIB_OK;
+}
+
+capib_status capib3d_write_bonds(capib3d_ctx *c, const int32_t *bound, const double *anchor) {
+    capib_status s = need_ws(c);
+    if (s) return s;
+    if (!bound || !anchor) return fail3(c, CAPIB_E_ARG, "null input");
+    for (int q = 0; q < c->nsite; q++)
+        if ((bound[q] != 0 && bound[q] != 1) || !std::isfinite(anchor[3 * q]) || !std::isfinite(anchor[3 * q + 1]) ||
+            !std::isfinite(anchor[3 * q + 2]))
+            return fail3(c, CAPIB_E_ARG, "site %d: bad state", q);
+    if (c->nsite) {
+        HIP3(c, hipMemcpyAsync(c->base + c->off_sbound, bound, c->nsite * 4, hipMemcpyHostToDevice, c->stream));
+        HIP3(c, hipMemcpyAsync(c->base + c->off_sanc, anchor, c->nsite * 24, hipMemcpyHostToDevice, c->stream));
+        HIP3(c, hipStreamSynchronize(c->stream));
+    }
     return CAPIB_OK;
 }
 

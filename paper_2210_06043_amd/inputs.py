@@ -472,6 +472,31 @@ def tube3d_params(re=0.01, nx=256, diameter=64, tau=1.0):
     return dict(nx=nx, ny=diameter, nz=diameter, tau=tau, gx=g, radius=R, u_mean=u_mean)
 
 
+CELL_3D = dict(gs=5e-3, c=1.0, ka=0.05, kv=0.05, mass=1.0, kb=2e-3)
+PARTICLE_3D = dict(gs=5e-2, c=1.0, ka=0.5, kv=0.5, mass=1.0, kb=2e-2)
+BONDS_3D = dict(sigma=1e-3, yeq=1.0, ycr=3.0, kf=0.05, kr0=0.005, lb=1.0, seed=2)
+
+
+def tube3d_workload(p=None, sites=300, seed=21):
+    """The 3D extension's workload in the tube of tube3d_params(): four
+    2562-vertex oblate cells (radius 8, axes 1, 1, 0.5) off the axis, and a
+    642-vertex oblate particle (radius 4, axes 1, 1, 0.5, its flat side 2.5
+    nodes from the wall) carrying `sites` ligand sites at seeded random
+    triangles and barycentric points.  Returns a dict: cells [(xyz, tri)],
+    particle (xyz, tri), sites (tri [n], bary [n][2]), and the constants
+    CELL_3D, PARTICLE_3D, BONDS_3D."""
+    p = p or tube3d_params()
+    c = 0.5 * (p["ny"] - 1)
+    cells = [icosphere(4, 8.0, (40.2 + 60 * k, c + (9.0, -7.5, 4.0, -10.0)[k], c + (2.0, 8.0, -9.0, -1.5)[k]),
+                       axes=(1.0, 1.0, 0.5)) for k in range(4)]
+    part = icosphere(3, 4.0, (128.7, c + 0.3, c - (p["radius"] - 4.5)), axes=(1.0, 1.0, 0.5))
+    rng = np.random.default_rng(seed)
+    st = rng.integers(0, len(part[1]), sites).astype(np.int32)
+    u = rng.random((sites, 2))
+    u[u.sum(axis=1) > 1] = 1 - u[u.sum(axis=1) > 1]
+    return dict(cells=cells, particle=part, sites=(st, u), cell=CELL_3D, part=PARTICLE_3D, bonds=BONDS_3D)
+
+
 def icosphere(level, radius=1.0, center=(0.0, 0.0, 0.0), axes=(1.0, 1.0, 1.0)):
     """A triangulated sphere: the icosahedron with every triangle split in
     four `level` times, vertices pushed to the sphere, then scaled by axes

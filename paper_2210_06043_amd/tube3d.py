@@ -20,7 +20,12 @@ class capib3d_lattice(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double), ("gx", C.c_double),
                 ("geometry", C.c_int32), ("radius", C.c_double), ("storage", C.c_int32), ("fp16_scale", C.c_double),
                 ("max_vertices", C.c_int32), ("max_membranes", C.c_int32), ("max_membrane_vertices", C.c_int32),
-                ("max_membrane_triangles", C.c_int32)]
+                ("max_membrane_triangles", C.c_int32), ("max_sites", C.c_int32)]
+
+
+class capib3d_bonds(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("yeq", C.c_double), ("ycr", C.c_double), ("kf", C.c_double), ("kr0", C.c_double),
+                ("lb", C.c_double), ("seed", C.c_uint64)]
 
 
 class capib3d_membrane(C.Structure):
@@ -45,6 +50,9 @@ SIGNATURES = {
     "capib3d_membrane_spread_forces": (C.c_int, [_P, _dp]),
     "capib3d_membrane_totals": (C.c_int, [_P, C.c_int32, _dp]),
     "capib3d_error_flags": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "capib3d_add_bonds": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), _dp, C.c_void_p]),
+    "capib3d_read_bonds": (C.c_int, [_P, C.POINTER(C.c_int32), _dp, C.POINTER(C.c_int64)]),
+    "capib3d_write_bonds": (C.c_int, [_P, C.POINTER(C.c_int32), _dp]),
     "capib3d_membranes": (C.c_int32, [_P]),
     "capib3d_membrane_vertex_count": (C.c_int32, [_P]),
     "capib3d_step": (C.c_int, [_P, C.c_int32]),
@@ -94,14 +102,15 @@ class Tube3D:
     """A D3Q19 tube on the GPU (workspace allocated with torch)."""
 
     def __init__(self, nx, ny, nz, tau, gx, geometry=TUBE, radius=0.0, stream=None, storage=capib.FP32_SHIFTED,
-                 fp16_scale=1.0, max_vertices=0, max_membranes=0, max_membrane_vertices=0, max_membrane_triangles=0):
+                 fp16_scale=1.0, max_vertices=0, max_membranes=0, max_membrane_vertices=0, max_membrane_triangles=0,
+                 max_sites=0):
         import torch
         self.torch = torch
         self.L = _lib()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         lat = capib3d_lattice(nx, ny, nz, tau, gx, geometry, radius, storage, fp16_scale, max_vertices, max_membranes,
-                              max_membrane_vertices, max_membrane_triangles)
+                              max_membrane_vertices, max_membrane_triangles, max_sites)
         self.ctx = _P()
         st = self.L.capib3d_create(C.byref(lat), _P(self.stream.cuda_stream), C.byref(self.ctx))
         if st != capib.CAPIB_OK:
@@ -194,6 +203,29 @@ class Tube3D:
         out = np.zeros(4)
         self._check(self.L.capib3d_membrane_totals(self.ctx, int(m), _d(out)))
         return out
+
+    def add_bonds(self, m, tri, bary, sigma, yeq, ycr, kf, kr0, lb, seed):
+        """Bond sites on membrane m: triangle [ns] (index among its
+        triangles) and barycentric weights [ns][2]; all start unbound."""
+        T = np.ascontiguousarray(tri, dtype=np.int32)
+        B = np.ascontiguousarray(bary, dtype=np.float64).reshape(-1, 2)
+        par = capib3d_bonds(sigma, yeq, ycr, kf, kr0, lb, seed)
+        self._check(self.L.capib3d_add_bonds(self.ctx, int(m), len(T), T.ctypes.data_as(C.POINTER(C.c_int32)), _d(B),
+                                             C.cast(C.byref(par), C.c_void_p)))
+        self.nsite = len(T)
+
+    def bonds(self):
+        """(bound [ns], anchors [ns][3], bound count)"""
+        b = np.zeros(self.nsite, dtype=np.int32)
+        a = np.zeros((self.nsite, 3))
+        n = C.c_int64()
+        self._check(self.L.capib3d_read_bonds(self.ctx, b.ctypes.data_as(C.POINTER(C.c_int32)), _d(a), C.byref(n)))
+        return b, a, n.value
+
+    def set_bonds(self, bound, anchor):
+        b = np.ascontiguousarray(bound, dtype=np.int32)
+        a = np.ascontiguousarray(anchor, dtype=np.float64)
+        self._check(self.L.capib3d_write_bonds(self.ctx, b.ctypes.data_as(C.POINTER(C.c_int32)), _d(a)))
 
     def error_flags(self):
         f = C.c_int32()

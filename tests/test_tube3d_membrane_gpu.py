@@ -91,17 +91,39 @@ def test_fp16_storage_with_a_membrane():
     _compare(g, o, 200, "3d membrane fp16", tol=FP16_TOL)
 
 
-def test_full_tube_with_four_cells_and_a_particle():
-    """The 256 x 64 x 64 tube (R = 32) at Re = 0.01 with four 2562-vertex
-    oblate cells (radius 8, axes 1, 1, 0.5) and a 642-vertex sphere of radius
-    4 as a stiff membrane: 50 steps, every node and vertex."""
+def test_full_tube_with_four_cells_and_a_bonded_particle():
+    """The 3D workload (inputs.tube3d_workload): the 256 x 64 x 64 tube at
+    Re = 0.01 with four 2562-vertex oblate cells and a 642-vertex oblate
+    particle 2.5 nodes from the wall carrying 300 ligand sites: 50 steps,
+    every node and vertex, and every bond state and anchor exactly as the
+    oracle's (its smallest decision margin is checked first)."""
     p = inputs.tube3d_params()
-    c = 0.5 * (p["ny"] - 1)
-    cells = [inputs.icosphere(4, 8.0, (40.2 + 60 * k, c + (9.0, -7.5, 4.0, -10.0)[k], c + (2.0, 8.0, -9.0, -1.5)[k]),
-                              axes=(1.0, 1.0, 0.5)) for k in range(4)]
-    part = inputs.icosphere(3, 4.0, (128.7, c - 3.0, c - 17.0))
-    g, o = _pair(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], p["radius"], cells + [part])
-    _compare(g, o, 50, "3d full tube, 4 cells + particle")
+    w = inputs.tube3d_workload(p)
+    prof = tube3d.hagen_poiseuille(p["ny"], p["nz"], p["radius"], p["tau"], p["gx"])
+    mem = w["cells"] + [w["particle"]]
+    pars = [w["cell"]] * 4 + [w["part"]]
+    g = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"], max_membranes=5,
+                      max_membrane_vertices=sum(len(m[0]) for m in mem),
+                      max_membrane_triangles=sum(len(m[1]) for m in mem), max_sites=len(w["sites"][0]))
+    o = otube.Tube(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"])
+    g.init_flow(prof)
+    o.init_flow(prof)
+    o.set_populations(g.populations())
+    for (xyz, tri), q in zip(mem, pars):
+        g.add_membrane(xyz, tri, **q)
+        o.add_membrane(xyz, tri, q["gs"], q["c"], q["ka"], q["kv"], q["mass"], q["kb"])
+    b = w["bonds"]
+    g.add_bonds(4, *w["sites"], **b)
+    o.add_bonds(4, *w["sites"], b["sigma"], b["yeq"], b["ycr"], b["kf"], b["kr0"], b["lb"], b["seed"])
+    _compare(g, o, 50, "3d full tube, 4 cells + bonded particle")
+    bg, ag, ng = g.bonds()
+    bo, ao, no = o.bonds()
+    margins = o.bond_margins()
+    say(f"3d bonds after 50 steps: {ng} bound (oracle {no}), {int(margins[2])} state changes, smallest margins "
+        f"{margins[0]:.2e} (draw) {margins[1]:.2e} (gap)")
+    assert margins[0] > 1e-7 and margins[1] > 1e-7 and margins[2] > 20
+    assert np.array_equal(bg, bo) and ng == no
+    assert np.abs(ag[bo == 1] - ao[bo == 1]).max() < 1e-7
 
 
 def test_repeated_runs_are_bit_identical():

@@ -182,8 +182,8 @@ capib_status capib3d_write_membrane_vertices(capib3d_ctx *ctx, const double *xyz
  * vertex, [membrane vertices][3].  Syncs. */
 capib_status capib3d_membrane_spread_forces(capib3d_ctx *ctx, double *out);
 /* Membrane m's area and enclosed volume at the start of the last step (the
- * sums the step used: FP64 per wave of 64 triangles, added in 2^-32 fixed
- * point), and its rest area and volume.  Syncs. */
+ * sums the step used: FP64 per wave of 64 triangles, the waves' sums added in
+ * a fixed order), and its rest area and volume.  Syncs. */
 capib_status capib3d_membrane_totals(capib3d_ctx *ctx, int32_t m, double *out4);
 /* Error flags raised on the device since the workspace was bound: 1 a
  * membrane stencil node outside the fluid, 2 a spread contribution beyond

@@ -35,13 +35,13 @@
 // Deformable membranes (closed triangulated surfaces: Skalak elements,
 // dihedral bending, penalties on total area and enclosed volume, Secs.
 // 2.2-2.4 read in 3D).  Their stencils move, so the coupling is rebuilt every
-// step on the device, and every sum whose order the schedule does not fix is
-// taken in 64-bit fixed point (integer adds are exact, so the order does not
-// matter and every run gives the same bits).  A step is three launches.
-// k3_m_interp: a wave per vertex (a lane per stencil node: u*), a lane per
-// triangle (its corner terms; the area and volume, summed per wave and added
-// to the membrane's totals in 2^-32 units) and a lane per edge (its bending
-// forces).  k3_m_patch: a workgroup per patch of 64 vertices (the host numbers
+// step on the device, and every sum is taken in an order the launch fixes or
+// in 64-bit fixed point (integer adds are exact, so the order does not
+// matter): every run gives the same bits.  A step is four launches.
+// k3_m_interp, in two launches: a wave per vertex (a lane per stencil node:
+// u*); then a lane per triangle (its corner terms; the area and volume,
+// summed per wave) and a lane per edge (its bending forces).  k3_m_patch: a
+// workgroup per patch of 64 vertices (the host numbers
 // each membrane's vertices by recursive bisection of their rest positions, so
 // a patch is compact): each vertex's force gathered from its terms, the
 // vertex update and the direct force, the patch's stencil contributions summed
@@ -121,7 +121,8 @@ struct Dev3 {
     const int *ewave;           // [new_][2] membrane and first edge of each edge wave
     const int *me0, *mne;       // [nm] first edge, edges
     int ntw, new_, mcap;        // triangle waves, edge waves; capacity of membranes
-    unsigned long long *mtfx;   // [2][mcap][2] area and volume by parity, fixed point (2^-32)
+    double *tpart;              // [ntw][2] area and volume of each triangle wave
+    const int *mtw;             // [nm][2] first triangle wave and triangle waves of each membrane
     double *tcf;                // [mt][32] per corner: Skalak force, area gradient, volume gradient, area / 3
     double *ecf;                // [me][12] bending force on x1, x2, x3, x4
     const int *ptab;            // [npatch][3] first vertex, vertices, membrane
@@ -141,7 +142,6 @@ struct Dev3 {
 };
 
 constexpr double FIX_ONE = 1125899906842624.0;   // 2^50, spread contributions
-constexpr double FIX_TOT = 4294967296.0;         // 2^32, area and volume
 constexpr int ERR_STENCIL = 1, ERR_FORCE = 2;
 
 // Workgroup b -> work item such that each XCD (workgroups dealt round-robin
@@ -211,16 +211,6 @@ __device__ __forceinline__ void sweep_item(const Dev3 &d, int item, int slot) {
     const int x = (item - c * d.nseg) * 64 + (int)(threadIdx.x & 63);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (x >= d.nx) return;
-    if (MODE == 2 && d.mflag[item]) {
-        unsigned long long *p = d.mforce + (long long)d.crow[20 * c] * d.pitch + x;
-        fx = (double)(long long)p[0] / FIX_ONE;
-        fy = (double)(long long)p[d.fs] / FIX_ONE;
-        fz = (double)(long long)p[2 * d.fs] / FIX_ONE;
-        p[0] = 0;
-        p[d.fs] = 0;
-        p[2 * d.fs] = 0;
-        if ((threadIdx.x & 63) == 0) d.mflag[item] = 0;
-    }
     if (MODE == 1) {
         const int *sb = d.sbeg + 65 * slot + (threadIdx.x & 63);
         const int k1 = sb[1];
@@ -235,6 +225,18 @@ __device__ __forceinline__ void sweep_item(const Dev3 &d, int item, int slot) {
     C h[Q];
     long long own;
     const C ur = pull<T, C, PAR>(d, c, x, h, own);
+    // the membranes' field, read (and cleared) on flagged items after the
+    // pulls are issued, so that the flag does not hold them back
+    if (MODE == 2 && d.mflag[item]) {
+        unsigned long long *p = d.mforce + own;
+        fx = (double)(long long)p[0] / FIX_ONE;
+        fy = (double)(long long)p[d.fs] / FIX_ONE;
+        fz = (double)(long long)p[2 * d.fs] / FIX_ONE;
+        p[0] = 0;
+        p[d.fs] = 0;
+        p[2 * d.fs] = 0;
+        if ((threadIdx.x & 63) == 0) d.mflag[item] = 0;
+    }
     const C Fx = (C)d.gx + (C)fx, Fy = (C)fy, Fz = (C)fz;
     // moments of the deviations: drho, and j - (u_ref, 0, 0)
     C drho = 0, jx = 0, jy = 0, jz = 0;
@@ -409,15 +411,18 @@ __device__ __forceinline__ void cross(const double *a, const double *b, double *
 // n x (x_c - x_b) / 2 and the volume gradient (x_b - r0) x (x_c - r0) / 6
 // ((a, b, c) in the triangle's cyclic order), and a third of the area; the
 // area and volume terms (about the membrane's first vertex r0) summed over
-// the wave and added to the membrane's totals in 2^-32 units.  The rest: a
+// the wave into the wave's own pair of partial sums.  The rest: a
 // wave per 64 edges of one membrane, a lane per edge: the bending force
 // -k_b sin(theta - theta0) grad theta on its four vertices.
-template <typename T, int PAR>
+// PART 0 launches the vertex waves alone, PART 1 the triangle and edge waves
+// (block indices counted from nvb), so that each keeps its own registers.
+template <typename T, int PAR, int PART>
 __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nvb, int ntb) {
     const int lane = threadIdx.x & 63;
     const double *X = d.MX[mp];
-    if ((int)blockIdx.x >= nvb + ntb) {
-        const int ew = ((int)blockIdx.x - nvb - ntb) * WAVES + (int)(threadIdx.x >> 6);
+    const int bx = (int)blockIdx.x + (PART == 1 ? nvb : 0);
+    if (PART == 1 && bx >= nvb + ntb) {
+        const int ew = (bx - nvb - ntb) * WAVES + (int)(threadIdx.x >> 6);
         if (ew >= d.new_) return;
         const int m = d.ewave[2 * ew], k = d.ewave[2 * ew + 1] + lane;
         if (k >= d.me0[m] + d.mne[m]) return;
@@ -461,8 +466,8 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
         }
         return;
     }
-    if ((int)blockIdx.x >= nvb) {
-        const int tw = ((int)blockIdx.x - nvb) * WAVES + (int)(threadIdx.x >> 6);
+    if (PART == 1) {
+        const int tw = (bx - nvb) * WAVES + (int)(threadIdx.x >> 6);
         if (tw >= d.ntw) return;
         const int m = d.twave[2 * tw], t = d.twave[2 * tw + 1] + lane;
         double A = 0.0, V = 0.0;
@@ -546,13 +551,12 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
             V += __shfl_xor(V, o);
         }
         if (lane == 0) {
-            unsigned long long *tot = d.mtfx + 2 * ((long long)mp * d.mcap + m);
-            atomicAdd(tot, (unsigned long long)__double2ll_rn(A * FIX_TOT));
-            atomicAdd(tot + 1, (unsigned long long)__double2ll_rn(V * FIX_TOT));
+            d.tpart[2 * tw] = A;
+            d.tpart[2 * tw + 1] = V;
         }
         return;
     }
-    const int v = blockIdx.x * WAVES + (int)(threadIdx.x >> 6);
+    const int v = bx * WAVES + (int)(threadIdx.x >> 6);
     if (v >= d.mv) return;
     const double Xv[3] = {X[v], X[d.ms + v], X[2 * d.ms + v]};
     int col, x;
@@ -631,53 +635,86 @@ __global__ __launch_bounds__(256) void k3_m_bonds(Dev3 d, int mp, long long step
 constexpr int PATCH_THREADS = 256;
 constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 
-// Second launch: a workgroup per patch (up to 64 consecutive vertices of one
-// membrane, numbered by the host so that a patch is compact).  Thread j < n
-// takes vertex v = first + j: its force gathered in ascending order from the
-// corner terms of its triangles (Skalak - (k_A (A - A0)/A0) area gradient
-// - (k_V (V - V0)/V0) volume gradient) and then the bending terms of its
-// edges, dV the sum of the thirds of their areas; dx = u* + f/(2m),
+// Third launch: a workgroup per patch (up to 64 consecutive vertices of one
+// membrane, numbered by the host so that a patch is compact).  The first wave
+// adds the membrane's triangle waves' area and volume (lane k the waves k,
+// k + 64, ..., then across the lanes).  Vertex v = first + j: its force
+// gathered from the corner terms of its triangles (Skalak - (k_A (A - A0)/A0)
+// area gradient - (k_V (V - V0)/V0) volume gradient) and the bending terms of
+// its edges, dV the sum of the thirds of their areas, the terms split over
+// the four waves (wave r the entries r, r + 4, ...; the four parts added in
+// order); then thread j: dx = u* + f/(2m),
 // x^{n+1} = x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV; its stencil
 // at x^n into LDS.  Then the patch's 64 x 64 contributions W F are added in
 // 2^-50 units into an LDS box over its stencils (integer adds: the order does
 // not matter), and the box is added to the global field with one integer
 // atomic per node and component, flagging each node's work item; a patch
 // whose box exceeds BOX^3 adds its contributions to the field directly.
-// Workgroup 0 also clears the totals of parity mp ^ 1 for the next step.
 __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     __shared__ double sw[64][12];
     __shared__ double sF[64][3];
     __shared__ int so[64][3];
     __shared__ int sbox[6];
     __shared__ unsigned long long box[BOX * BOX * BOX][3];
+    __shared__ double sp[PATCH_THREADS / 64][64][4];
+    __shared__ double stot[2];
     const int t = threadIdx.x, p = blockIdx.x;
-    if (p == 0)
-        for (int i = t; i < 2 * d.mcap; i += PATCH_THREADS) d.mtfx[2 * (long long)(mp ^ 1) * d.mcap + i] = 0;
     const int pv0 = d.ptab[3 * p], pn = d.ptab[3 * p + 1], m = d.ptab[3 * p + 2];
+    if (t < 64) {
+        // the membrane's area and volume: its triangle waves' sums added over
+        // the lanes in a fixed order
+        double a = 0.0, b = 0.0;
+        for (int k = t; k < d.mtw[2 * m + 1]; k += 64) {
+            a += d.tpart[2 * (d.mtw[2 * m] + k)];
+            b += d.tpart[2 * (d.mtw[2 * m] + k) + 1];
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            a += __shfl_xor(a, o);
+            b += __shfl_xor(b, o);
+        }
+        if (t == 0) {
+            stot[0] = a;
+            stot[1] = b;
+        }
+    }
+    __syncthreads();
     const double *X = d.MX[mp];
+    // each vertex's force and dV, its terms split over the four waves (wave r
+    // takes the entries r, r + 4, ...; the four parts are added in order)
+    const double *P = d.mpar + 8 * m;
+    const double A = stot[0], V = stot[1];
+    const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
+    {
+        const int j = t & 63, r = t >> 6;
+        double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
+        if (j < pn) {
+            const int v = pv0 + j;
+            for (int k = d.vtb[v] + r; k < d.vtb[v + 1]; k += 4) {
+                const int e = d.vtl[k];
+                const double *q = d.tcf + 32 * (long long)(e >> 2) + 10 * (e & 3);
+                for (int u = 0; u < 3; u++) f[u] += q[u] - ca * q[3 + u] - cv * q[6 + u];
+                dV += q[9];
+            }
+            for (int k = d.veb[v] + r; k < d.veb[v + 1]; k += 4) {
+                const int e = d.vel[k];
+                const double *q = d.ecf + 12 * (long long)(e >> 2) + 3 * (e & 3);
+                for (int u = 0; u < 3; u++) f[u] += q[u];
+            }
+        }
+        for (int u = 0; u < 3; u++) sp[r][j][u] = f[u];
+        sp[r][j][3] = dV;
+    }
+    __syncthreads();
     int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
     if (t < pn) {
         const int v = pv0 + t;
-        const double *P = d.mpar + 8 * m;
-        const unsigned long long *tot = d.mtfx + 2 * ((long long)mp * d.mcap + m);
-        const double A = (double)(long long)tot[0] / FIX_TOT, V = (double)(long long)tot[1] / FIX_TOT;
         if (v == d.mv0[m]) {
             d.mtot[2 * m] = A;
             d.mtot[2 * m + 1] = V;
         }
-        const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
-        double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
-        for (int k = d.vtb[v]; k < d.vtb[v + 1]; k++) {
-            const int e = d.vtl[k];
-            const double *q = d.tcf + 32 * (long long)(e >> 2) + 10 * (e & 3);
-            for (int u = 0; u < 3; u++) f[u] += q[u] - ca * q[3 + u] - cv * q[6 + u];
-            dV += q[9];
-        }
-        for (int k = d.veb[v]; k < d.veb[v + 1]; k++) {
-            const int e = d.vel[k];
-            const double *q = d.ecf + 12 * (long long)(e >> 2) + 3 * (e & 3);
-            for (int u = 0; u < 3; u++) f[u] += q[u];
-        }
+        double f[3], dV;
+        for (int u = 0; u < 3; u++) f[u] = sp[0][t][u] + sp[1][t][u] + sp[2][t][u] + sp[3][t][u];
+        dV = sp[0][t][3] + sp[1][t][3] + sp[2][t][3] + sp[3][t][3];
         double xn[3];
         for (int u = 0; u < 3; u++) {
             const long long k = u * d.ms + v;
@@ -849,7 +886,7 @@ struct capib3d_ctx {
     size_t off_MX[2]{}, off_Mdxm = 0, off_Mus = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
            off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_ewave = 0,
            off_me0 = 0, off_mne = 0, off_tcf = 0, off_ecf = 0, off_ptab = 0, off_mforce = 0, off_mflag = 0,
-           off_twave = 0, off_mtfx = 0, off_colof = 0, off_stri = 0, off_sbary = 0, off_sbound = 0, off_sanc = 0,
+           off_twave = 0, off_tpart = 0, off_mtw = 0, off_colof = 0, off_stri = 0, off_sbary = 0, off_sbound = 0, off_sanc = 0,
            off_tsb = 0, off_tsl = 0,
            off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_vel = 0;
     int ntw = 0, new_ = 0;                // triangle waves, edge waves
@@ -1027,7 +1064,8 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_veb = o; o = al256(o + (MV ? MV + 1 : 0) * 4);
     c->off_vel = o; o = al256(o + ME * 4 * 4);
     c->off_twave = o; o = al256(o + (MT / 64 + MM) * 2 * 4);
-    c->off_mtfx = o; o = al256(o + 2 * MM * 2 * 8);
+    c->off_tpart = o; o = al256(o + (MT / 64 + MM) * 2 * 8);
+    c->off_mtw = o; o = al256(o + MM * 2 * 4);
 
     c->off_colof = o; o = al256(o + (size_t)L.ny * L.nz * 4);
     c->off_err = o; o = al256(o + 4);
@@ -1137,7 +1175,8 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.twave = (const int *)(c->base + c->off_twave);
     d.ntw = 0;
     d.mcap = L.max_membranes;
-    d.mtfx = (unsigned long long *)(c->base + c->off_mtfx);
+    d.tpart = (double *)(c->base + c->off_tpart);
+    d.mtw = (const int *)(c->base + c->off_mtw);
 
     c->ntw = 0;
     d.colof = (const int *)(c->base + c->off_colof);
@@ -1190,16 +1229,17 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     const dim3 g1(nfb + (s1 + WAVES - 1) / WAVES), g2(nvb + (s2 - s1 + WAVES - 1) / WAVES),
         g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
     const int mvb = (c->mvn + WAVES - 1) / WAVES, ntb = (c->ntw + WAVES - 1) / WAVES;
-    const dim3 gi(mvb + ntb + (c->new_ + WAVES - 1) / WAVES), gp((unsigned)(c->ptab.size() / 3));
+    const dim3 gv(mvb), gt(ntb + (c->new_ + WAVES - 1) / WAVES), gp((unsigned)(c->ptab.size() / 3));
     for (int t = 0; t < nsteps && c->nm > 0; t++) {
         const int mp = c->mpar;
         if (c->par) {
-            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 1> : k3_m_interp<float, 1>), gi, blk, 0, c->stream, c->d, mp,
-                               mvb, ntb);
+            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 1, 0> : k3_m_interp<float, 1, 0>), gv, blk, 0, c->stream, c->d,
+                               mp, mvb, ntb);
         } else {
-            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 0> : k3_m_interp<float, 0>), gi, blk, 0, c->stream, c->d, mp,
-                               mvb, ntb);
+            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 0, 0> : k3_m_interp<float, 0, 0>), gv, blk, 0, c->stream, c->d,
+                               mp, mvb, ntb);
         }
+        hipLaunchKernelGGL((k3_m_interp<float, 0, 1>), gt, blk, 0, c->stream, c->d, mp, mvb, ntb);
         hipLaunchKernelGGL(k3_m_patch, gp, dim3(PATCH_THREADS), 0, c->stream, c->d, mp);
         if (c->nsite > 0)
             hipLaunchKernelGGL(k3_m_bonds, dim3((c->nsite + 255) / 256), dim3(256), 0, c->stream, c->d, mp ^ 1,
@@ -1640,18 +1680,21 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     }
     c->m_e0.push_back(me - (int)th0.size());
     c->m_ne.push_back((int)th0.size());
-    std::vector<int> twave, ewave;
+    std::vector<int> twave, ewave, mtw;
     for (int k = 0; k < c->nm; k++) {
+        mtw.push_back((int)(twave.size() / 2));
         for (int t = c->m_t0[k]; t < c->m_t0[k] + c->m_nt[k]; t += 64) {
             twave.push_back(k);
             twave.push_back(t);
         }
+        mtw.push_back((int)(twave.size() / 2) - mtw.back());
         for (int e = c->m_e0[k]; e < c->m_e0[k] + c->m_ne[k]; e += 64) {
             ewave.push_back(k);
             ewave.push_back(e);
         }
     }
     HIP3(c, hipMemcpyAsync(c->base + c->off_ptab, c->ptab.data(), c->ptab.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_mtw, mtw.data(), mtw.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_me0, c->m_e0.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_mne, c->m_ne.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
     if (!ewave.empty())

@@ -38,13 +38,15 @@
 // step on the device, and every sum is taken in an order the launch fixes or
 // in 64-bit fixed point (integer adds are exact, so the order does not
 // matter): every run gives the same bits.  A step is four launches.
-// k3_m_interp, in two launches: a wave per vertex (a lane per stencil node:
-// u*); then a lane per triangle (its corner terms; the area and volume,
-// summed per wave) and a lane per edge (its bending forces).  k3_m_patch: a
-// workgroup per patch of 64 vertices (the host numbers
-// each membrane's vertices by recursive bisection of their rest positions, so
-// a patch is compact): each vertex's force gathered from its terms, the
-// vertex update and the direct force, the patch's stencil contributions summed
+// k3_m_first: a wave per work item under the stencils (u* of its nodes,
+// once per node although a node lies in some 50 stencils), a lane per
+// triangle (its corner terms; the area and volume, summed per wave) and a
+// lane per edge (its bending forces).  k3_m_patch: a workgroup per patch of
+// 64 vertices (the host numbers each membrane's vertices by recursive
+// bisection of their rest positions, so a patch is compact): each vertex's
+// u* gathered from its stencil's nodes and its force from its terms, the
+// vertex update and the direct force, the work items under the next step's
+// stencils flagged, the patch's stencil contributions summed
 // in an LDS box in 2^-50 units and added to a global force field with one
 // atomic per node and component, its work items flagged.  The sweep reads and
 // clears the field on flagged items.  Ligand-receptor bonds between sites on
@@ -107,7 +109,7 @@ struct Dev3 {
     long long ms;               // stride of the coordinate planes of the vertex arrays
     long long fs;               // stride of the force field's planes: nz * ny * pitch
     double *MX[2];              // [3][ms] positions, by parity
-    double *Mdxm, *Mus, *MF;    // [3][ms] previous displacement, u*, spread force
+    double *Mdxm, *MF;          // [3][ms] previous displacement, spread force
     const int *Mtri;            // [mt][3] membrane vertex indices
     const double *Mref;         // [mt][8] rest gradients g0, g1, g2 (2 each), rest area
     const int *vtb, *vtl;       // incident triangles of each vertex: [mv + 1] starts, entries t * 4 + corner
@@ -128,6 +130,8 @@ struct Dev3 {
     const int *ptab;            // [npatch][3] first vertex, vertices, membrane
     unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
     int *mflag;                 // [ncol * nseg] work item with spread force
+    double *Mu;                 // [3][fs] u* of the nodes under this step's stencils
+    int *uflag;                 // [ncol * nseg] work item holding nodes under this step's stencils
     // bonds
     int ns;                     // sites
     const int *Stri;            // [ns] triangle (global)
@@ -379,50 +383,70 @@ __device__ __forceinline__ double phi_cos(double r) {
     return r < 2.0 ? 0.25 * (1.0 + cos(M_PI * r / 2.0)) : 0.0;
 }
 
-// Stencil node of lane l (a = l & 3 along x, b = (l >> 2) & 3 along y,
-// c = l >> 4 along z) of a point: its column, x and weight; false (and an
-// error flag) if the node lies outside the cross-section or on a solid column.
-__device__ __forceinline__ bool stencil_node(const Dev3 &d, const double X[3], int l, int &col, int &x, double &W) {
-    const int ox = (int)floor(X[0]) - 1, oy = (int)floor(X[1]) - 1, oz = (int)floor(X[2]) - 1;
-    const int a = l & 3, b = (l >> 2) & 3, c = l >> 4;
-    const int y = oy + b, z = oz + c;
-    col = (y >= 0 && y < d.ny && z >= 0 && z < d.nz) ? d.colof[z * d.ny + y] : -1;
-    if (col < 0) {
-        atomicOr(d.err, ERR_STENCIL);
-        return false;
-    }
-    x = ((ox + a) % d.nx + d.nx) % d.nx;
-    W = phi_cos(X[0] - (ox + a)) * phi_cos(X[1] - y) * phi_cos(X[2] - z);
-    return true;
-}
-
 __device__ __forceinline__ void cross(const double *a, const double *b, double *o) {
     o[0] = a[1] * b[2] - a[2] * b[1];
     o[1] = a[2] * b[0] - a[0] * b[2];
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// u* = (j + g/2) / rho (the velocity of the streamed populations with half
+// the body force) at every node of the flagged work items, into Mu, and the
+// flags cleared.  Wave w < nw of the launch takes the items w, w + nw, ...,
+// their flags loaded together, one lane each.
+template <typename T, int PAR>
+__device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw) {
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (w >= nw) return;   // the grid's last workgroup may hold more waves
+    const int nitem = d.ncol * d.nseg;
+    const int mine = w + lane * nw;
+    const bool on = lane * nw < nitem && mine < nitem && d.uflag[mine];
+    for (unsigned long long m = __ballot(on); m; m &= m - 1ull) {
+        const int k = __ffsll((long long)m) - 1;
+        const int item = __builtin_amdgcn_readfirstlane(w + k * nw);
+        const int c = item / d.nseg, x = (item - c * d.nseg) * 64 + lane;
+        if (x < d.nx) {
+            double h[Q];
+            long long own;
+            const double ur = pull<T, double, PAR>(d, c, x, h, own);
+            double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+            for (int q = 0; q < Q; q++) {
+                drho += h[q];
+                jx += EX[q] * h[q];
+                jy += EY[q] * h[q];
+                jz += EZ[q] * h[q];
+            }
+            const double rho = 1.0 + drho;
+            d.Mu[own] = ur + (jx + 0.5 * d.gx - drho * ur) / rho;
+            d.Mu[d.fs + own] = jy / rho;
+            d.Mu[2 * d.fs + own] = jz / rho;
+        }
+    }
+    if (on) d.uflag[mine] = 0;
+}
+
 // First launch of a step with membranes (positions x^n of parity mp).
-// Workgroups [0, nvb): a wave per vertex, u*: the velocity of the streamed
-// populations with half the body force at each stencil node, weighted and
-// summed over the wave.  [nvb, nvb + ntb): a wave per 64 triangles of one
-// membrane, a lane per triangle: for each corner a, the Skalak force
-// -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], the area gradient
-// n x (x_c - x_b) / 2 and the volume gradient (x_b - r0) x (x_c - r0) / 6
-// ((a, b, c) in the triangle's cyclic order), and a third of the area; the
-// area and volume terms (about the membrane's first vertex r0) summed over
-// the wave into the wave's own pair of partial sums.  The rest: a
-// wave per 64 edges of one membrane, a lane per edge: the bending force
-// -k_b sin(theta - theta0) grad theta on its four vertices.
-// PART 0 launches the vertex waves alone, PART 1 the triangle and edge waves
-// (block indices counted from nvb), so that each keeps its own registers.
-template <typename T, int PAR, int PART>
-__global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nvb, int ntb) {
+// Workgroups [0, nub): nodeu_waves over nuw waves.  [nub, nub + ntb): a
+// wave per 64 triangles of one membrane, a lane per triangle: for each
+// corner a, the Skalak force -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], the
+// area gradient n x (x_c - x_b) / 2 and the volume gradient
+// (x_b - r0) x (x_c - r0) / 6 ((a, b, c) in the triangle's cyclic order),
+// and a third of the area; the area and volume terms (about the membrane's
+// first vertex r0) summed over the wave into the wave's own pair of partial
+// sums.  The rest: a wave per 64 edges of one membrane, a lane per edge: the
+// bending force -k_b sin(theta - theta0) grad theta on its four vertices.
+// The three parts are independent latency chains, so they share a launch.
+template <typename T, int PAR>
+__global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub, int nuw, int ntb) {
+    if ((int)blockIdx.x < nub) {
+        nodeu_waves<T, PAR>(d, nuw);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const double *X = d.MX[mp];
-    const int bx = (int)blockIdx.x + (PART == 1 ? nvb : 0);
-    if (PART == 1 && bx >= nvb + ntb) {
-        const int ew = (bx - nvb - ntb) * WAVES + (int)(threadIdx.x >> 6);
+    const int bx = (int)blockIdx.x - nub;
+    if (bx >= ntb) {
+        const int ew = (bx - ntb) * WAVES + (int)(threadIdx.x >> 6);
         if (ew >= d.new_) return;
         const int m = d.ewave[2 * ew], k = d.ewave[2 * ew + 1] + lane;
         if (k >= d.me0[m] + d.mne[m]) return;
@@ -466,8 +490,8 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
         }
         return;
     }
-    if (PART == 1) {
-        const int tw = (bx - nvb) * WAVES + (int)(threadIdx.x >> 6);
+    {
+        const int tw = bx * WAVES + (int)(threadIdx.x >> 6);
         if (tw >= d.ntw) return;
         const int m = d.twave[2 * tw], t = d.twave[2 * tw + 1] + lane;
         double A = 0.0, V = 0.0;
@@ -554,39 +578,32 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_interp(Dev3 d, int mp, int nv
             d.tpart[2 * tw] = A;
             d.tpart[2 * tw + 1] = V;
         }
-        return;
     }
-    const int v = bx * WAVES + (int)(threadIdx.x >> 6);
+}
+
+// Flags the work items that hold the stencil nodes of vertex position X
+// (columns outside the fluid are left to the spreading's check): plain
+// stores of 1, so that any number of writers agree.  b, c: the stencil's y
+// and z offsets.
+__device__ __forceinline__ void flag_stencil_items(const Dev3 &d, int ox, int oy, int oz, int b, int c) {
+    const int y = oy + b, z = oz + c;
+    if (y < 0 || y >= d.ny || z < 0 || z >= d.nz) return;
+    const int col = d.colof[z * d.ny + y];
+    if (col < 0) return;
+    const int x0 = (ox % d.nx + d.nx) % d.nx, x3 = ((ox + 3) % d.nx + d.nx) % d.nx;
+    d.uflag[col * d.nseg + x0 / 64] = 1;
+    d.uflag[col * d.nseg + x3 / 64] = 1;   // the stencil's 4 nodes span at most two items
+}
+
+// The items under the stencils of positions mp, for a step whose positions
+// the previous step did not write (new membranes, positions set from the
+// host): a thread per (vertex, stencil column).
+__global__ __launch_bounds__(256) void k3_m_umark(Dev3 d, int mp) {
+    const int i = blockIdx.x * 256 + threadIdx.x, v = i >> 4;
     if (v >= d.mv) return;
-    const double Xv[3] = {X[v], X[d.ms + v], X[2 * d.ms + v]};
-    int col, x;
-    double W, ux = 0.0, uy = 0.0, uz = 0.0;
-    if (stencil_node(d, Xv, lane, col, x, W)) {
-        double h[Q];
-        long long own;
-        const double ur = pull<T, double, PAR>(d, col, x, h, own);
-        double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-        for (int q = 0; q < Q; q++) {
-            drho += h[q];
-            jx += EX[q] * h[q];
-            jy += EY[q] * h[q];
-            jz += EZ[q] * h[q];
-        }
-        const double rho = 1.0 + drho;
-        ux = W * (ur + (jx + 0.5 * d.gx - drho * ur) / rho);
-        uy = W * (jy / rho);
-        uz = W * (jz / rho);
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-        ux += __shfl_xor(ux, o);
-        uy += __shfl_xor(uy, o);
-        uz += __shfl_xor(uz, o);
-    }
-    if (lane == 0) {
-        d.Mus[v] = ux;
-        d.Mus[d.ms + v] = uy;
-        d.Mus[2 * d.ms + v] = uz;
-    }
+    const double *X = d.MX[mp];
+    const int ox = (int)floor(X[v]) - 1, oy = (int)floor(X[d.ms + v]) - 1, oz = (int)floor(X[2 * d.ms + v]) - 1;
+    flag_stencil_items(d, ox, oy, oz, i & 3, (i >> 2) & 3);
 }
 
 // Bond kinetics at x^{n+1} (positions of parity mp), step n: a thread per
@@ -633,23 +650,27 @@ __global__ __launch_bounds__(256) void k3_m_bonds(Dev3 d, int mp, long long step
 }
 
 constexpr int PATCH_THREADS = 256;
+constexpr int NODEU_WAVES = 4096;   // waves of nodeu_waves (each scans nitem / 4096 + 1 items' flags)
 constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 
-// Third launch: a workgroup per patch (up to 64 consecutive vertices of one
+// Second launch: a workgroup per patch (up to 64 consecutive vertices of one
 // membrane, numbered by the host so that a patch is compact).  The first wave
 // adds the membrane's triangle waves' area and volume (lane k the waves k,
-// k + 64, ..., then across the lanes).  Vertex v = first + j: its force
-// gathered from the corner terms of its triangles (Skalak - (k_A (A - A0)/A0)
-// area gradient - (k_V (V - V0)/V0) volume gradient) and the bending terms of
-// its edges, dV the sum of the thirds of their areas, the terms split over
-// the four waves (wave r the entries r, r + 4, ...; the four parts added in
-// order); then thread j: dx = u* + f/(2m),
-// x^{n+1} = x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV; its stencil
-// at x^n into LDS.  Then the patch's 64 x 64 contributions W F are added in
-// 2^-50 units into an LDS box over its stencils (integer adds: the order does
-// not matter), and the box is added to the global field with one integer
-// atomic per node and component, flagging each node's work item; a patch
-// whose box exceeds BOX^3 adds its contributions to the field directly.
+// k + 64, ..., then across the lanes) while the second puts each vertex's
+// stencil at x^n (origin and weights) into LDS.  Vertex v = first + j: u*
+// interpolated from its stencil's nodes (the cosine delta of the coupling),
+// its force gathered from the corner terms of its triangles (Skalak
+// - (k_A (A - A0)/A0) area gradient - (k_V (V - V0)/V0) volume gradient) and
+// the bending terms of its edges, dV the sum of the thirds of their areas,
+// the terms split over the four waves (wave r the entries r, r + 4, ...; the
+// four parts added in order); then thread j: dx = u* + f/(2m),
+// x^{n+1} = x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV, and the
+// work items under the stencil of x^{n+1} flagged for the next step's u*.
+// Then the patch's 64 x 64 contributions W F are added in 2^-50 units into
+// an LDS box over its stencils (integer adds: the order does not matter),
+// and the box is added to the global field with one integer atomic per node
+// and component, flagging each node's work item; a patch whose box exceeds
+// BOX^3 adds its contributions to the field directly.
 __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     __shared__ double sw[64][12];
     __shared__ double sF[64][3];
@@ -658,8 +679,21 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     __shared__ unsigned long long box[BOX * BOX * BOX][3];
     __shared__ double sp[PATCH_THREADS / 64][64][4];
     __shared__ double stot[2];
+    __shared__ int sno[64][3];   // stencil origins of x^{n+1}
+    __shared__ double sus[4][64][3];   // u* of each vertex, by z layer of its stencil
     const int t = threadIdx.x, p = blockIdx.x;
     const int pv0 = d.ptab[3 * p], pn = d.ptab[3 * p + 1], m = d.ptab[3 * p + 2];
+    const double *X = d.MX[mp];
+    if (t >= 64 && t < 64 + pn) {
+        // the stencil of x^n of vertex pv0 + t - 64: origin and weights
+        const int j = t - 64, v = pv0 + j;
+        for (int u = 0; u < 3; u++) {
+            const double xu = X[u * d.ms + v];
+            const int o = (int)floor(xu) - 1;
+            so[j][u] = o;
+            for (int k4 = 0; k4 < 4; k4++) sw[j][4 * u + k4] = phi_cos(xu - (o + k4));
+        }
+    }
     if (t < 64) {
         // the membrane's area and volume: its triangle waves' sums added over
         // the lanes in a fixed order
@@ -678,7 +712,33 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         }
     }
     __syncthreads();
-    const double *X = d.MX[mp];
+    // each vertex's u*: thread (j, c) sums W u* over the 16 nodes of layer c
+    // of vertex j's stencil (y offset b, then x offset a), the four layers
+    // added in order below.  The nodes' u* were stored by nodeu_waves; a
+    // node outside the fluid reads the +0 of the field's solid rows, which
+    // nothing writes (the spreading below flags such a stencil)
+    {
+        const int j = t & 63, c = t >> 6;
+        double su[3] = {0.0, 0.0, 0.0};
+        const int z = j < pn ? so[j][2] + c : -1;
+        if (z >= 0 && z < d.nz) {
+            const int x0 = (so[j][0] % d.nx + d.nx) % d.nx;
+            const double wz = sw[j][8 + c];
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const int y = so[j][1] + b;
+                if (y < 0 || y >= d.ny) continue;
+                const long long row = (long long)(z * d.ny + y) * d.pitch;
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    const double W = sw[j][a] * sw[j][4 + b] * wz;
+                    const int x = x0 + a < d.nx ? x0 + a : x0 + a - d.nx;
+                    for (int u = 0; u < 3; u++) su[u] += W * d.Mu[u * d.fs + row + x];
+                }
+            }
+        }
+        for (int u = 0; u < 3; u++) sus[c][j][u] = su[u];
+    }
     // each vertex's force and dV, its terms split over the four waves (wave r
     // takes the entries r, r + 4, ...; the four parts are added in order)
     const double *P = d.mpar + 8 * m;
@@ -715,23 +775,20 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         double f[3], dV;
         for (int u = 0; u < 3; u++) f[u] = sp[0][t][u] + sp[1][t][u] + sp[2][t][u] + sp[3][t][u];
         dV = sp[0][t][3] + sp[1][t][3] + sp[2][t][3] + sp[3][t][3];
-        double xn[3];
         for (int u = 0; u < 3; u++) {
             const long long k = u * d.ms + v;
-            xn[u] = X[k];
-            const double us = d.Mus[k];
+            const double xn = X[k];
+            const double us = ((sus[0][t][u] + sus[1][t][u]) + sus[2][t][u]) + sus[3][t][u];
             const double dx = us + 0.5 * f[u] / P[4];
             const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
             const double Fs = (U - us) * dV;
-            d.MX[mp ^ 1][k] = xn[u] + dx;
+            d.MX[mp ^ 1][k] = xn + dx;
+            sno[t][u] = (int)floor(xn + dx) - 1;
             d.Mdxm[k] = dx;
             d.MF[k] = Fs;
             sF[t][u] = Fs;
-            const int o = (int)floor(xn[u]) - 1;
-            so[t][u] = o;
-            lo[u] = o;
-            hi[u] = o;
-            for (int k4 = 0; k4 < 4; k4++) sw[t][4 * u + k4] = phi_cos(xn[u] - (o + k4));
+            lo[u] = so[t][u];
+            hi[u] = so[t][u];
         }
     }
     if (t < 64) {
@@ -752,6 +809,11 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     const bool inbox = ex >= 4 && ex <= BOX && ey >= 4 && ey <= BOX && ez >= 4 && ez <= BOX;
     const int nb = inbox ? ex * ey * ez : 0;
     for (int i = t; i < nb; i += PATCH_THREADS) box[i][0] = box[i][1] = box[i][2] = 0;
+    // the work items under the next step's stencils
+    for (int i = t; i < 16 * pn; i += PATCH_THREADS) {
+        const int j = i >> 4;
+        flag_stencil_items(d, sno[j][0], sno[j][1], sno[j][2], i & 3, (i >> 2) & 3);
+    }
     __syncthreads();
     for (int i = t; i < 64 * pn; i += PATCH_THREADS) {
         const int j = i >> 6, l = i & 63, a = l & 3, b = (l >> 2) & 3, c = l >> 4;
@@ -871,6 +933,7 @@ struct capib3d_ctx {
     std::vector<int> colof;             // [nz][ny]: column index of a fluid row, -1 solid
     // fixed immersed bodies, host copies of the device maps
     int nv = 0, nslot = 0, nslot_max = 0, share_u = 0, share_v = 0;
+    bool umarks = false;   // the items under the membranes' current stencils are flagged
     std::vector<int> vcol, vxs;         // [nv][64]
     std::vector<double> vW, vdV;        // [nv][64], [nv]
     // deformable membranes, host copies
@@ -883,9 +946,9 @@ struct capib3d_ctx {
     size_t off_pop[2]{}, off_crow = 0, off_cK = 0, off_macro = 0, off_part = 0, ws = 0;
     size_t off_vnode = 0, off_vW = 0, off_vdV = 0, off_vpos = 0, off_vF = 0, off_contrib = 0, off_unode = 0,
            off_islot = 0, off_fitem = 0, off_sbeg = 0;
-    size_t off_MX[2]{}, off_Mdxm = 0, off_Mus = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
+    size_t off_MX[2]{}, off_Mdxm = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
            off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_ewave = 0,
-           off_me0 = 0, off_mne = 0, off_tcf = 0, off_ecf = 0, off_ptab = 0, off_mforce = 0, off_mflag = 0,
+           off_me0 = 0, off_mne = 0, off_tcf = 0, off_ecf = 0, off_ptab = 0, off_mforce = 0, off_mflag = 0, off_Mu = 0, off_uflag = 0,
            off_twave = 0, off_tpart = 0, off_mtw = 0, off_colof = 0, off_stri = 0, off_sbary = 0, off_sbound = 0, off_sanc = 0,
            off_tsb = 0, off_tsl = 0,
            off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_vel = 0;
@@ -1030,7 +1093,6 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     const size_t fs = (size_t)L.nz * L.ny * c->pitch;
     for (int p = 0; p < 2; p++) { c->off_MX[p] = o; o = al256(o + 3 * MV * 8); }
     c->off_Mdxm = o; o = al256(o + 3 * MV * 8);
-    c->off_Mus = o; o = al256(o + 3 * MV * 8);
     c->off_MF = o; o = al256(o + 3 * MV * 8);
     c->off_Mtri = o; o = al256(o + MT * 3 * 4);
     c->off_Mref = o; o = al256(o + MT * 8 * 8);
@@ -1051,6 +1113,8 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 3 * 4);
     c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
     c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
+    c->off_Mu = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
+    c->off_uflag = o; o = al256(o + (MV ? nitem * 4 : 0));
     const size_t MSITE = (size_t)L.max_sites;
     c->off_stri = o; o = al256(o + MSITE * 4);
     c->off_sbary = o; o = al256(o + MSITE * 2 * 8);
@@ -1133,7 +1197,6 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.fs = (long long)L.nz * L.ny * c->pitch;
     for (int p = 0; p < 2; p++) d.MX[p] = (double *)(c->base + c->off_MX[p]);
     d.Mdxm = (double *)(c->base + c->off_Mdxm);
-    d.Mus = (double *)(c->base + c->off_Mus);
     d.MF = (double *)(c->base + c->off_MF);
     d.Mtri = (const int *)(c->base + c->off_Mtri);
     d.Mref = (const double *)(c->base + c->off_Mref);
@@ -1154,6 +1217,8 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.ptab = (const int *)(c->base + c->off_ptab);
     d.mforce = (unsigned long long *)(c->base + c->off_mforce);
     d.mflag = (int *)(c->base + c->off_mflag);
+    d.Mu = (double *)(c->base + c->off_Mu);
+    d.uflag = (int *)(c->base + c->off_uflag);
     d.ns = 0;
     d.Stri = (const int *)(c->base + c->off_stri);
     d.Sbary = (const double *)(c->base + c->off_sbary);
@@ -1182,6 +1247,7 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.colof = (const int *)(c->base + c->off_colof);
     d.err = (int *)(c->base + c->off_err);
     c->nm = c->mvn = c->mtn = c->mpar = c->mmaxv = 0;
+    c->umarks = false;
     c->m_v0.clear(); c->m_nv.clear(); c->m_t0.clear(); c->m_nt.clear(); c->mtri.clear(); c->mref.clear();
     c->mparam.clear(); c->medge.clear(); c->mth0.clear();
     c->vcol.clear(); c->vxs.clear(); c->vW.clear(); c->vdV.clear();
@@ -1228,18 +1294,21 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     const int nvb = ((c->nv + WAVES - 1) / WAVES + 7) / 8 * 8, nfb = ((c->nslot + WAVES - 1) / WAVES + 7) / 8 * 8;
     const dim3 g1(nfb + (s1 + WAVES - 1) / WAVES), g2(nvb + (s2 - s1 + WAVES - 1) / WAVES),
         g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
-    const int mvb = (c->mvn + WAVES - 1) / WAVES, ntb = (c->ntw + WAVES - 1) / WAVES;
-    const dim3 gv(mvb), gt(ntb + (c->new_ + WAVES - 1) / WAVES), gp((unsigned)(c->ptab.size() / 3));
+    const int nuw = std::min(nitem, NODEU_WAVES), nub = (nuw + WAVES - 1) / WAVES;
+    const int ntb = (c->ntw + WAVES - 1) / WAVES;
+    const dim3 gf(nub + ntb + (c->new_ + WAVES - 1) / WAVES), gp((unsigned)(c->ptab.size() / 3));
     for (int t = 0; t < nsteps && c->nm > 0; t++) {
         const int mp = c->mpar;
-        if (c->par) {
-            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 1, 0> : k3_m_interp<float, 1, 0>), gv, blk, 0, c->stream, c->d,
-                               mp, mvb, ntb);
-        } else {
-            hipLaunchKernelGGL((h16 ? k3_m_interp<_Float16, 0, 0> : k3_m_interp<float, 0, 0>), gv, blk, 0, c->stream, c->d,
-                               mp, mvb, ntb);
+        if (!c->umarks) {
+            hipLaunchKernelGGL(k3_m_umark, dim3((unsigned)((16LL * c->mvn + 255) / 256)), dim3(256), 0, c->stream, c->d, mp);
+            c->umarks = true;
         }
-        hipLaunchKernelGGL((k3_m_interp<float, 0, 1>), gt, blk, 0, c->stream, c->d, mp, mvb, ntb);
+        if (c->par)
+            hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 1> : k3_m_first<float, 1>), gf, blk, 0, c->stream, c->d, mp,
+                               nub, nuw, ntb);
+        else
+            hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 0> : k3_m_first<float, 0>), gf, blk, 0, c->stream, c->d, mp,
+                               nub, nuw, ntb);
         hipLaunchKernelGGL(k3_m_patch, gp, dim3(PATCH_THREADS), 0, c->stream, c->d, mp);
         if (c->nsite > 0)
             hipLaunchKernelGGL(k3_m_bonds, dim3((c->nsite + 255) / 256), dim3(256), 0, c->stream, c->d, mp ^ 1,
@@ -1648,6 +1717,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     const double mp8[8] = {par->gs, par->c, par->ka, par->kv, par->mass, A0, V0, par->kb};
     c->mparam.insert(c->mparam.end(), mp8, mp8 + 8);
     c->nm++;
+    c->umarks = false;
     c->mvn += nv;
     c->mtn += ntri;
     c->mmaxv = std::max(c->mmaxv, nv);
@@ -1773,6 +1843,7 @@ capib_status capib3d_write_membrane_vertices(capib3d_ctx *c, const double *xyz) 
     if (!xyz) return fail3(c, CAPIB_E_ARG, "null input");
     for (long long k = 0; k < 3LL * c->mvn; k++)
         if (!std::isfinite(xyz[k])) return fail3(c, CAPIB_E_ARG, "non-finite vertex");
+    c->umarks = false;
     return c->mvn ? membrane_planes(c, c->off_MX[c->mpar], nullptr, xyz) : CAPIB_OK;
 }
 

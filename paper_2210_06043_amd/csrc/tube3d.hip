@@ -585,14 +585,18 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
 // (columns outside the fluid are left to the spreading's check): plain
 // stores of 1, so that any number of writers agree.  b, c: the stencil's y
 // and z offsets.
-__device__ __forceinline__ void flag_stencil_items(const Dev3 &d, int ox, int oy, int oz, int b, int c) {
+__device__ __forceinline__ int stencil_col(const Dev3 &d, int oy, int oz, int b, int c) {
     const int y = oy + b, z = oz + c;
-    if (y < 0 || y >= d.ny || z < 0 || z >= d.nz) return;
-    const int col = d.colof[z * d.ny + y];
-    if (col < 0) return;
+    return (y >= 0 && y < d.ny && z >= 0 && z < d.nz) ? d.colof[z * d.ny + y] : -1;
+}
+__device__ __forceinline__ void flag_col_items(const Dev3 &d, int col, int ox) {
     const int x0 = (ox % d.nx + d.nx) % d.nx, x3 = ((ox + 3) % d.nx + d.nx) % d.nx;
     d.uflag[col * d.nseg + x0 / 64] = 1;
     d.uflag[col * d.nseg + x3 / 64] = 1;   // the stencil's 4 nodes span at most two items
+}
+__device__ __forceinline__ void flag_stencil_items(const Dev3 &d, int ox, int oy, int oz, int b, int c) {
+    const int col = stencil_col(d, oy, oz, b, c);
+    if (col >= 0) flag_col_items(d, col, ox);
 }
 
 // The items under the stencils of positions mp, for a step whose positions
@@ -681,6 +685,7 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     __shared__ double stot[2];
     __shared__ int sno[64][3];   // stencil origins of x^{n+1}
     __shared__ double sus[4][64][3];   // u* of each vertex, by z layer of its stencil
+    __shared__ int smask[64];          // bit b + 4 c: column (b, c) of the stencil at x^n is fluid
     const int t = threadIdx.x, p = blockIdx.x;
     const int pv0 = d.ptab[3 * p], pn = d.ptab[3 * p + 1], m = d.ptab[3 * p + 2];
     const double *X = d.MX[mp];
@@ -693,6 +698,20 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
             so[j][u] = o;
             for (int k4 = 0; k4 < 4; k4++) sw[j][4 * u + k4] = phi_cos(xu - (o + k4));
         }
+    } else if (t >= 128 && t < 128 + pn) {
+        // which of the 16 columns of the same stencil are fluid (the loads
+        // issued together); a stencil that reaches outside the fluid raises
+        // the error flag
+        const int j = t - 128, v = pv0 + j;
+        const int oy = (int)floor(X[d.ms + v]) - 1, oz = (int)floor(X[2 * d.ms + v]) - 1;
+        int cl[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) cl[k] = stencil_col(d, oy, oz, k & 3, k >> 2);
+        int mask = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) mask |= (cl[k] >= 0 ? 1 : 0) << k;
+        smask[j] = mask;
+        if (mask != 0xFFFF) atomicOr(d.err, ERR_STENCIL);
     }
     if (t < 64) {
         // the membrane's area and volume: its triangle waves' sums added over
@@ -809,36 +828,65 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     const bool inbox = ex >= 4 && ex <= BOX && ey >= 4 && ey <= BOX && ez >= 4 && ez <= BOX;
     const int nb = inbox ? ex * ey * ez : 0;
     for (int i = t; i < nb; i += PATCH_THREADS) box[i][0] = box[i][1] = box[i][2] = 0;
-    // the work items under the next step's stencils
-    for (int i = t; i < 16 * pn; i += PATCH_THREADS) {
-        const int j = i >> 4;
-        flag_stencil_items(d, sno[j][0], sno[j][1], sno[j][2], i & 3, (i >> 2) & 3);
+    // the work items under the next step's stencils: thread t takes the
+    // (vertex, column) pairs t + 256 r, their columns loaded together
+    static_assert(16 * 64 <= 4 * PATCH_THREADS, "four pairs per thread");
+    {
+        int fc[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int i = t + r * PATCH_THREADS, j = i >> 4;
+            fc[r] = i < 16 * pn ? stencil_col(d, sno[j][1], sno[j][2], i & 3, (i >> 2) & 3) : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            if (fc[r] >= 0) flag_col_items(d, fc[r], sno[(t + r * PATCH_THREADS) >> 4][0]);
     }
     __syncthreads();
-    for (int i = t; i < 64 * pn; i += PATCH_THREADS) {
-        const int j = i >> 6, l = i & 63, a = l & 3, b = (l >> 2) & 3, c = l >> 4;
-        const int y = so[j][1] + b, z = so[j][2] + c;
-        const int col = (y >= 0 && y < d.ny && z >= 0 && z < d.nz) ? d.colof[z * d.ny + y] : -1;
-        if (col < 0) {
-            atomicOr(d.err, ERR_STENCIL);
-            continue;
-        }
-        const double W = sw[j][a] * sw[j][4 + b] * sw[j][8 + c];
-        const int xu = so[j][0] + a;   // unwrapped
-        for (int u = 0; u < 3; u++) {
-            const double cq = W * sF[j][u] * FIX_ONE;
-            if (!(fabs(cq) < 4.0e18)) {
-                atomicOr(d.err, ERR_FORCE);
-                continue;
+    // lane l of wave r: node (l & 3, (l >> 2) & 3, l >> 4) of the stencils of
+    // vertices r, r + 4, ...  The next vertex's inputs are read from LDS
+    // before this one's three atomics go out, so that no wait for an LDS
+    // read also waits for the atomics.
+    {
+        const int l = t & 63, a = l & 3, b = (l >> 2) & 3, c = l >> 4;
+        struct In {
+            int o[3], m;
+            double w, f[3];
+        };
+        auto take = [&](int j) {
+            In q;
+            for (int u = 0; u < 3; u++) q.o[u] = so[j][u];
+            q.m = (smask[j] >> (l >> 2)) & 1;
+            q.w = sw[j][a] * sw[j][4 + b] * sw[j][8 + c];
+            for (int u = 0; u < 3; u++) q.f[u] = sF[j][u];
+            return q;
+        };
+        int j = t >> 6;
+        In cur = j < pn ? take(j) : In{};
+        for (; j < pn; j += PATCH_THREADS / 64) {
+            const In nxt = j + PATCH_THREADS / 64 < pn ? take(j + PATCH_THREADS / 64) : In{};
+            if (cur.m) {   // else outside the fluid (flagged above)
+                const int y = cur.o[1] + b, z = cur.o[2] + c, xu = cur.o[0] + a;   // xu unwrapped
+                unsigned long long iv[3];
+                bool ok[3];
+                for (int u = 0; u < 3; u++) {
+                    const double cq = cur.w * cur.f[u] * FIX_ONE;
+                    ok[u] = fabs(cq) < 4.0e18;
+                    iv[u] = ok[u] ? (unsigned long long)__double2ll_rn(cq) : 0ull;
+                }
+                if (!(ok[0] && ok[1] && ok[2])) atomicOr(d.err, ERR_FORCE);
+                if (inbox) {
+                    unsigned long long *q = box[((z - lz) * ey + (y - ly)) * ex + (xu - lx)];
+                    for (int u = 0; u < 3; u++)
+                        if (ok[u]) atomicAdd(q + u, iv[u]);
+                } else {
+                    const int xw = (xu % d.nx + d.nx) % d.nx;
+                    for (int u = 0; u < 3; u++)
+                        if (ok[u]) atomicAdd(d.mforce + u * d.fs + (long long)(z * d.ny + y) * d.pitch + xw, iv[u]);
+                    d.mflag[d.colof[z * d.ny + y] * d.nseg + xw / 64] = 1;
+                }
             }
-            const unsigned long long iv = (unsigned long long)__double2ll_rn(cq);
-            if (inbox) {
-                atomicAdd(&box[((z - lz) * ey + (y - ly)) * ex + (xu - lx)][u], iv);
-            } else {
-                const int xw = (xu % d.nx + d.nx) % d.nx;
-                atomicAdd(d.mforce + u * d.fs + (long long)(z * d.ny + y) * d.pitch + xw, iv);
-                d.mflag[col * d.nseg + xw / 64] = 1;
-            }
+            cur = nxt;
         }
     }
     __syncthreads();

@@ -112,12 +112,12 @@ struct Dev3 {
     double *Mdxm, *MF;          // [3][ms] previous displacement, spread force
     const int *Mtri;            // [mt][3] membrane vertex indices
     const double *Mref;         // [mt][8] rest gradients g0, g1, g2 (2 each), rest area
-    const int *vtb, *vtl;       // incident triangles of each vertex: [mv + 1] starts, entries t * 4 + corner
+    const int *vtb, *tslot;     // [mv + 1] starts of each vertex's corner slots; [mt][3] slot of each corner
     const int *mv0, *mnv, *mt0, *mnt;   // [nm] first vertex, vertices, first triangle, triangles
     const double *mpar;         // [nm][8] G_s, C, k_A, k_V, vertex mass, rest area, rest volume, k_b
     const int *Medge;           // [me][4] edge (x1, x2) and its opposite vertices x3, x4
     const double *Mth0;         // [me] rest dihedral angle
-    const int *veb, *vel;       // edge terms of each vertex: [mv + 1] starts, entries edge * 4 + role
+    const int *veb, *eslot;     // [mv + 1] starts of each vertex's edge slots; [me][4] slot of each role
     double *mtot;               // [nm][2] area and volume at the start of the last step
     const int *twave;           // [ntw][2] membrane and first triangle of each triangle wave
     const int *ewave;           // [new_][2] membrane and first edge of each edge wave
@@ -125,8 +125,11 @@ struct Dev3 {
     int ntw, new_, mcap;        // triangle waves, edge waves; capacity of membranes
     double *tpart;              // [ntw][2] area and volume of each triangle wave
     const int *mtw;             // [nm][2] first triangle wave and triangle waves of each membrane
-    double *tcf;                // [mt][32] per corner: Skalak force, area gradient, volume gradient, area / 3
-    double *ecf;                // [me][12] bending force on x1, x2, x3, x4
+    // per corner slot (a vertex's slots are consecutive, its incident
+    // triangles in ascending order): Skalak force, area gradient, volume
+    // gradient, area / 3
+    double *tcf;                // [3 mt][10]
+    double *ecf;                // [4 me][3] bending force on one of an edge's four vertices
     const int *ptab;            // [npatch][3] first vertex, vertices, membrane
     unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
     int *mflag;                 // [ncol * nseg] work item with spread force
@@ -456,6 +459,7 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
         // g4 = -l N2/|N2|^2, g1 = ((x3 - x2).e/l^2) g3 + ((x4 - x2).e/l^2) g4,
         // g2 = -(g1 + g3 + g4)
         const int *E = d.Medge + 4 * k;
+        const int es[4] = {d.eslot[4 * k], d.eslot[4 * k + 1], d.eslot[4 * k + 2], d.eslot[4 * k + 3]};
         double y[4][3];
         for (int s = 0; s < 4; s++)
             for (int u = 0; u < 3; u++) y[s][u] = X[u * d.ms + E[s]];
@@ -480,13 +484,15 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
         const double sb = -d.mpar[8 * m + 7] * sin(th - d.Mth0[k]);
         const double w3 = ((y[2][0] - y[1][0]) * e[0] + (y[2][1] - y[1][1]) * e[1] + (y[2][2] - y[1][2]) * e[2]) / l2;
         const double w4 = ((y[3][0] - y[1][0]) * e[0] + (y[3][1] - y[1][1]) * e[1] + (y[3][2] - y[1][2]) * e[2]) / l2;
-        double *out = d.ecf + 12 * (long long)k;
+        // into the slots of the four vertices' edge terms
+        double *o1 = d.ecf + 3 * (long long)es[0], *o2 = d.ecf + 3 * (long long)es[1];
+        double *o3 = d.ecf + 3 * (long long)es[2], *o4 = d.ecf + 3 * (long long)es[3];
         for (int u = 0; u < 3; u++) {
             const double g3 = -l * N1[u] / q1, g4 = -l * N2[u] / q2, g1 = w3 * g3 + w4 * g4;
-            out[u] = sb * g1;
-            out[3 + u] = sb * -(g1 + g3 + g4);
-            out[6 + u] = sb * g3;
-            out[9 + u] = sb * g4;
+            o1[u] = sb * g1;
+            o2[u] = sb * -(g1 + g3 + g4);
+            o3[u] = sb * g3;
+            o4[u] = sb * g4;
         }
         return;
     }
@@ -498,6 +504,7 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
         if (t < d.mt0[m] + d.mnt[m]) {
             const double *P = d.mpar + 8 * m;
             const int *tv = d.Mtri + 3 * t;
+            const int ts[3] = {d.tslot[3 * t], d.tslot[3 * t + 1], d.tslot[3 * t + 2]};
             const double *g = d.Mref + 8 * t;
             const int r0 = d.mv0[m];
             double x[3][3], xr[3][3];
@@ -525,8 +532,8 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
             cross(e1, e2, n);
             const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
             for (int u = 0; u < 3; u++) n[u] /= nn;
-            double *out = d.tcf + 32 * (long long)t;
             for (int a = 0; a < 3; a++) {
+                double *out = d.tcf + 10 * (long long)ts[a];   // corner a's slot
                 const int b = a == 2 ? 0 : a + 1, c = a == 0 ? 2 : a - 1;
                 const double ga[2] = {g[2 * a], g[2 * a + 1]};
                 const double Cg[2] = {Ci[0][0] * ga[0] + Ci[0][1] * ga[1], Ci[1][0] * ga[0] + Ci[1][1] * ga[1]};
@@ -544,11 +551,11 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
                 for (int u = 0; u < 3; u++) {
                     const double Fg = F[u][0] * ga[0] + F[u][1] * ga[1];
                     const double FCg = F[u][0] * Cg[0] + F[u][1] * Cg[1];
-                    out[10 * a + u] = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
-                    out[10 * a + 3 + u] = 0.5 * nbc[u];
-                    out[10 * a + 6 + u] = bc[u] / 6.0;
+                    out[u] = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
+                    out[3 + u] = 0.5 * nbc[u];
+                    out[6 + u] = bc[u] / 6.0;
                 }
-                out[10 * a + 9] = 0.5 * nn / 3.0;
+                out[9] = 0.5 * nn / 3.0;
             }
             // bound sites on this triangle: sigma (y_l - y_eq) along n, a third per corner
             for (int k = d.ns > 0 ? d.tsb[t] : 0; d.ns > 0 && k < d.tsb[t + 1]; k++) {
@@ -562,7 +569,7 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
                 }
                 const double f = d.b_sigma * (sqrt(dl2) - d.b_yeq);
                 for (int a = 0; a < 3; a++)
-                    for (int u = 0; u < 3; u++) out[10 * a + u] += f / 3.0 * n[u];
+                    for (int u = 0; u < 3; u++) d.tcf[10 * (long long)ts[a] + u] += f / 3.0 * n[u];
             }
             A = 0.5 * nn;
             // the volume term about r0, from the corners relative to r0
@@ -769,14 +776,12 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         if (j < pn) {
             const int v = pv0 + j;
             for (int k = d.vtb[v] + r; k < d.vtb[v + 1]; k += 4) {
-                const int e = d.vtl[k];
-                const double *q = d.tcf + 32 * (long long)(e >> 2) + 10 * (e & 3);
+                const double *q = d.tcf + 10 * (long long)k;
                 for (int u = 0; u < 3; u++) f[u] += q[u] - ca * q[3 + u] - cv * q[6 + u];
                 dV += q[9];
             }
             for (int k = d.veb[v] + r; k < d.veb[v + 1]; k += 4) {
-                const int e = d.vel[k];
-                const double *q = d.ecf + 12 * (long long)(e >> 2) + 3 * (e & 3);
+                const double *q = d.ecf + 3 * (long long)k;
                 for (int u = 0; u < 3; u++) f[u] += q[u];
             }
         }
@@ -994,12 +999,12 @@ struct capib3d_ctx {
     size_t off_pop[2]{}, off_crow = 0, off_cK = 0, off_macro = 0, off_part = 0, ws = 0;
     size_t off_vnode = 0, off_vW = 0, off_vdV = 0, off_vpos = 0, off_vF = 0, off_contrib = 0, off_unode = 0,
            off_islot = 0, off_fitem = 0, off_sbeg = 0;
-    size_t off_MX[2]{}, off_Mdxm = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_vtl = 0,
+    size_t off_MX[2]{}, off_Mdxm = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_tslot = 0,
            off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_ewave = 0,
            off_me0 = 0, off_mne = 0, off_tcf = 0, off_ecf = 0, off_ptab = 0, off_mforce = 0, off_mflag = 0, off_Mu = 0, off_uflag = 0,
            off_twave = 0, off_tpart = 0, off_mtw = 0, off_colof = 0, off_stri = 0, off_sbary = 0, off_sbound = 0, off_sanc = 0,
            off_tsb = 0, off_tsl = 0,
-           off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_vel = 0;
+           off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_eslot = 0;
     int ntw = 0, new_ = 0;                // triangle waves, edge waves
     std::vector<int> perm;                // internal vertex -> the caller's vertex
     std::vector<int> ptab;                // [npatch][3]
@@ -1145,7 +1150,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_Mtri = o; o = al256(o + MT * 3 * 4);
     c->off_Mref = o; o = al256(o + MT * 8 * 8);
     c->off_vtb = o; o = al256(o + (MV ? MV + 1 : 0) * 4);
-    c->off_vtl = o; o = al256(o + 3 * MT * 4);
+    c->off_tslot = o; o = al256(o + 3 * MT * 4);
     c->off_mv0 = o; o = al256(o + MM * 4);
     c->off_mnv = o; o = al256(o + MM * 4);
     c->off_mt0 = o; o = al256(o + MM * 4);
@@ -1156,8 +1161,8 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_ewave = o; o = al256(o + ((3 * MT) / 2 / 64 + MM + 1) * 2 * 4);
     c->off_me0 = o; o = al256(o + MM * 4);
     c->off_mne = o; o = al256(o + MM * 4);
-    c->off_tcf = o; o = al256(o + MT * 32 * 8);
-    c->off_ecf = o; o = al256(o + ((3 * MT) / 2 + 1) * 12 * 8);
+    c->off_tcf = o; o = al256(o + 3 * MT * 10 * 8);
+    c->off_ecf = o; o = al256(o + ((3 * MT) / 2 + 1) * 4 * 3 * 8);
     c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 3 * 4);
     c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
     c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
@@ -1174,7 +1179,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_medge = o; o = al256(o + ME * 4 * 4);
     c->off_mth0 = o; o = al256(o + ME * 8);
     c->off_veb = o; o = al256(o + (MV ? MV + 1 : 0) * 4);
-    c->off_vel = o; o = al256(o + ME * 4 * 4);
+    c->off_eslot = o; o = al256(o + ME * 4 * 4);
     c->off_twave = o; o = al256(o + (MT / 64 + MM) * 2 * 4);
     c->off_tpart = o; o = al256(o + (MT / 64 + MM) * 2 * 8);
     c->off_mtw = o; o = al256(o + MM * 2 * 4);
@@ -1249,7 +1254,7 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.Mtri = (const int *)(c->base + c->off_Mtri);
     d.Mref = (const double *)(c->base + c->off_Mref);
     d.vtb = (const int *)(c->base + c->off_vtb);
-    d.vtl = (const int *)(c->base + c->off_vtl);
+    d.tslot = (const int *)(c->base + c->off_tslot);
     d.mv0 = (const int *)(c->base + c->off_mv0);
     d.mnv = (const int *)(c->base + c->off_mnv);
     d.mt0 = (const int *)(c->base + c->off_mt0);
@@ -1284,7 +1289,7 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.Medge = (const int *)(c->base + c->off_medge);
     d.Mth0 = (const double *)(c->base + c->off_mth0);
     d.veb = (const int *)(c->base + c->off_veb);
-    d.vel = (const int *)(c->base + c->off_vel);
+    d.eslot = (const int *)(c->base + c->off_eslot);
     d.twave = (const int *)(c->base + c->off_twave);
     d.ntw = 0;
     d.mcap = L.max_membranes;
@@ -1771,23 +1776,23 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     c->mmaxv = std::max(c->mmaxv, nv);
     c->medge.insert(c->medge.end(), edges.begin(), edges.end());
     c->mth0.insert(c->mth0.end(), th0.begin(), th0.end());
-    // incident triangles of every vertex, ascending
-    std::vector<int> vtb(c->mvn + 1, 0), vtl(3 * (size_t)c->mtn);
+    // incident triangles of every vertex, ascending: the slot of each corner
+    std::vector<int> vtb(c->mvn + 1, 0), tslot(3 * (size_t)c->mtn);
     for (int k = 0; k < 3 * c->mtn; k++) vtb[c->mtri[k] + 1]++;
     for (int v = 0; v < c->mvn; v++) vtb[v + 1] += vtb[v];
     // the edge terms of every vertex: its role in each edge, ascending
     const int me = (int)c->mth0.size();
-    std::vector<int> veb(c->mvn + 1, 0), vel(4 * (size_t)me);
+    std::vector<int> veb(c->mvn + 1, 0), eslot(4 * (size_t)me);
     for (int k = 0; k < 4 * me; k++) veb[c->medge[k] + 1]++;
     for (int v = 0; v < c->mvn; v++) veb[v + 1] += veb[v];
     {
         std::vector<int> fe(veb.begin(), veb.end() - 1);
         for (int k = 0; k < me; k++)
-            for (int r = 0; r < 4; r++) vel[fe[c->medge[4 * k + r]]++] = 4 * k + r;
+            for (int r = 0; r < 4; r++) eslot[4 * k + r] = fe[c->medge[4 * k + r]]++;
     }
     std::vector<int> fill(vtb.begin(), vtb.end() - 1);
     for (int t = 0; t < c->mtn; t++)
-        for (int a = 0; a < 3; a++) vtl[fill[c->mtri[3 * t + a]]++] = 4 * t + a;
+        for (int a = 0; a < 3; a++) tslot[3 * t + a] = fill[c->mtri[3 * t + a]]++;
     // the membrane of each vertex, and the totals waves (64 triangles of one membrane each)
     // the caller's index of every internal vertex; the patches, triangle waves and edge waves
     for (int k = 0; k < nv; k++) c->perm.push_back(v0 + pp[k]);
@@ -1825,7 +1830,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
                                c->stream));
         HIP3(c, hipMemcpyAsync(c->base + c->off_mth0, c->mth0.data(), c->mth0.size() * 8, hipMemcpyHostToDevice,
                                c->stream));
-        HIP3(c, hipMemcpyAsync(c->base + c->off_vel, vel.data(), vel.size() * 4, hipMemcpyHostToDevice, c->stream));
+        HIP3(c, hipMemcpyAsync(c->base + c->off_eslot, eslot.data(), eslot.size() * 4, hipMemcpyHostToDevice, c->stream));
     }
     HIP3(c, hipMemcpyAsync(c->base + c->off_veb, veb.data(), veb.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_twave, twave.data(), twave.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -1844,7 +1849,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     HIP3(c, hipMemcpyAsync(c->base + c->off_Mtri, c->mtri.data(), c->mtri.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_Mref, c->mref.data(), c->mref.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_vtb, vtb.data(), vtb.size() * 4, hipMemcpyHostToDevice, c->stream));
-    HIP3(c, hipMemcpyAsync(c->base + c->off_vtl, vtl.data(), vtl.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP3(c, hipMemcpyAsync(c->base + c->off_tslot, tslot.data(), tslot.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_mv0, c->m_v0.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_mnv, c->m_nv.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_mt0, c->m_t0.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));

@@ -3,7 +3,8 @@ elements, dihedral bending, area and volume penalties, the 2D membranes' vertex 
 fixed-point spreading) against the FP64 oracle through the C-ABI: every
 node's velocity, every vertex's position and direct force, and the FP64
 area and volume sums, on small tubes (a membrane across the periodic end,
-two membranes, FP16 storage), the 256 x 64 x 64 tube with four 2562-vertex
+two membranes, a membrane moved from the host mid-run, one added after
+steps, FP16 storage), the 256 x 64 x 64 tube with four 2562-vertex
 cells and a 642-vertex sphere; bitwise repeatability; the host's refusals
 and the wall flag."""
 import numpy as np
@@ -83,6 +84,45 @@ def test_two_membranes_of_different_sizes():
     g, o = _pair(80, 25, 25, 1.0, 4e-6, 12.0, [m1, m2])
     assert g.membranes == 2 and g.membrane_vertex_count == len(m1[0]) + len(m2[0])
     _compare(g, o, 150, "3d two membranes")
+
+
+def test_membrane_moved_from_the_host_mid_run():
+    """40 steps, then the membrane moved from the host by (40, 2.5, -1.5)
+    nodes on both sides (the work items under its stencils change: other
+    columns and another 64-node segment of x; those of the old position keep
+    their flags from the last step), then 60 more steps against the
+    oracle."""
+    m = inputs.icosphere(3, 4.0, (30.2, 11.8, 11.3))
+    g, o = _pair(96, 24, 24, 0.9, 3e-6, 11.0, [m])
+    g.step(40)
+    o.step(40)
+    X = o.membrane_vertices() + np.array([40.0, 2.5, -1.5])
+    g.set_membrane_vertices(X)
+    o.set_membrane_vertices(X)
+    _compare(g, o, 60, "3d membrane moved from the host")
+
+
+def test_membrane_added_after_steps():
+    """One membrane for 30 steps, then a second added on both sides (its
+    vertices numbered after the first's), then 80 more steps against the
+    oracle."""
+    m1 = inputs.icosphere(3, 4.0, (20.2, 11.8, 11.3))
+    m2 = inputs.icosphere(2, 3.0, (60.7, 12.3, 10.9))
+    prof = tube3d.hagen_poiseuille(24, 24, 11.0, 0.9, 3e-6)
+    g = tube3d.Tube3D(96, 24, 24, 0.9, 3e-6, radius=11.0, max_membranes=2,
+                      max_membrane_vertices=len(m1[0]) + len(m2[0]), max_membrane_triangles=len(m1[1]) + len(m2[1]))
+    o = otube.Tube(96, 24, 24, 0.9, 3e-6, radius=11.0)
+    g.init_flow(prof)
+    o.init_flow(prof)
+    o.set_populations(g.populations())
+    for mm in (m1,):
+        assert g.add_membrane(*mm, **PAR) == o.add_membrane(*mm, PAR["gs"], PAR["c"], PAR["ka"], PAR["kv"],
+                                                            PAR["mass"], PAR["kb"])
+    g.step(30)
+    o.step(30)
+    assert g.add_membrane(*m2, **PAR) == o.add_membrane(*m2, PAR["gs"], PAR["c"], PAR["ka"], PAR["kv"], PAR["mass"],
+                                                       PAR["kb"]) == len(m1[0])
+    _compare(g, o, 80, "3d membrane added after steps")
 
 
 def test_fp16_storage_with_a_membrane():

@@ -37,7 +37,7 @@
 // 2.2-2.4 read in 3D).  Their stencils move, so the coupling is rebuilt every
 // step on the device, and every sum is taken in an order the launch fixes or
 // in 64-bit fixed point (integer adds are exact, so the order does not
-// matter): every run gives the same bits.  A step is four launches.
+// matter): every run gives the same bits.  A step is three launches.
 // k3_m_first: a wave per work item under the stencils (u* of its nodes,
 // once per node although a node lies in some 50 stencils), a lane per
 // triangle (its corner terms; the area and volume, summed per wave) and a
@@ -51,9 +51,11 @@
 // atomic per node and component, its work items flagged.  The sweep reads and
 // clears the field on flagged items.  Ligand-receptor bonds between sites on
 // one membrane's triangles and the tube wall: a bound site's spring force
-// (along its triangle's normal, a third per corner) joins the triangle terms;
-// k3_m_bonds then takes each site's Bell-type decision at x^{n+1} with the
-// same Philox draw as the 2D library.
+// (along its triangle's normal, a third per corner) joins the triangle terms.
+// Each site's Bell-type decision at x^{n+1} of step n (the same Philox draw
+// as the 2D library) is taken by its triangle's lane at the start of step
+// n + 1, just before that lane adds the site's spring, and by k3_m_bonds
+// after the last step of a call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -392,6 +394,56 @@ __device__ __forceinline__ void cross(const double *a, const double *b, double *
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Bond kinetics of site q at the end of step n, at its position ps at
+// x^{n+1}.  The draw is word 0 of Philox4x32-10 with key (seed low, seed high)
+// and counter (n low, site, n high, 0), top 24 bits over 2^24.  Bound: it
+// breaks if the draw is below 1 - exp(-k_r0 exp(|y_l - y_eq| / l_B)).
+// Unbound within y_cr of the wall (R minus the site's distance from the
+// axis): it binds if the draw is below 1 - exp(-k_f), anchored on the wall
+// radially outward of the site.
+__device__ __forceinline__ void bond_decide(const Dev3 &d, int q, const double ps[3], long long step) {
+    const uint32_t w0 = capib::philox_w0((uint32_t)((unsigned long long)step & 0xffffffffu), (uint32_t)q,
+                                         (uint32_t)((unsigned long long)step >> 32), 0u,
+                                         (uint32_t)(d.b_seed & 0xffffffffu), (uint32_t)(d.b_seed >> 32));
+    const double r = (double)(w0 >> 8) * (1.0 / 16777216.0);
+    if (d.Sbound[q]) {
+        double dl2 = 0.0;
+        for (int u = 0; u < 3; u++) {
+            const double dl = ps[u] - d.Sanc[3 * q + u];
+            dl2 += dl * dl;
+        }
+        const double P = 1.0 - exp(-d.b_kr0 * exp(fabs(sqrt(dl2) - d.b_yeq) / d.b_lb));
+        if (r < P) d.Sbound[q] = 0;
+    } else {
+        const double yc = 0.5 * (d.ny - 1), zc = 0.5 * (d.nz - 1);
+        const double dy = ps[1] - yc, dz = ps[2] - zc, rho = sqrt(dy * dy + dz * dz);
+        const double P = 1.0 - exp(-d.b_kf);
+        if (d.radius - rho < d.b_ycr && r < P) {
+            d.Sbound[q] = 1;
+            d.Sanc[3 * q] = ps[0];
+            d.Sanc[3 * q + 1] = yc + d.radius * dy / rho;
+            d.Sanc[3 * q + 2] = zc + d.radius * dz / rho;
+        }
+    }
+}
+
+// The bond kinetics of step n at x^{n+1} (positions of parity mp), a thread
+// per site: after the last step of a call (the steps before it leave theirs
+// to the next step's triangle lanes).
+__global__ __launch_bounds__(256) void k3_m_bonds(Dev3 d, int mp, long long step) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= d.ns) return;
+    const int *T = d.Mtri + 3 * d.Stri[q];
+    const double *X = d.MX[mp];
+    const double b1 = d.Sbary[2 * q], b2 = d.Sbary[2 * q + 1];
+    double ps[3];
+    for (int u = 0; u < 3; u++) {
+        const double xa = X[u * d.ms + T[0]];
+        ps[u] = xa + b1 * (X[u * d.ms + T[1]] - xa) + b2 * (X[u * d.ms + T[2]] - xa);
+    }
+    bond_decide(d, q, ps, step);
+}
+
 // u* = (j + g/2) / rho (the velocity of the streamed populations with half
 // the body force) at every node of the flagged work items, into Mu, and the
 // flags cleared.  Wave w < nw of the launch takes the items w, w + nw, ...,
@@ -440,7 +492,7 @@ __device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw) {
 // bending force -k_b sin(theta - theta0) grad theta on its four vertices.
 // The three parts are independent latency chains, so they share a launch.
 template <typename T, int PAR>
-__global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub, int nuw, int ntb) {
+__global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub, int nuw, int ntb, long long kstep) {
     if ((int)blockIdx.x < nub) {
         nodeu_waves<T, PAR>(d, nuw);
         return;
@@ -557,14 +609,20 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub
                 }
                 out[9] = 0.5 * nn / 3.0;
             }
-            // bound sites on this triangle: sigma (y_l - y_eq) along n, a third per corner
+            // the sites on this triangle: first (kstep >= 0) the previous
+            // step's bond kinetics at these positions, x^{n+1} of that step;
+            // then for every bound site sigma (y_l - y_eq) along n, a third
+            // per corner
             for (int k = d.ns > 0 ? d.tsb[t] : 0; d.ns > 0 && k < d.tsb[t + 1]; k++) {
                 const int q = d.tsl[k];
-                if (!d.Sbound[q]) continue;
                 const double b1 = d.Sbary[2 * q], b2 = d.Sbary[2 * q + 1];
+                double ps[3];
+                for (int u = 0; u < 3; u++) ps[u] = x[0][u] + b1 * e1[u] + b2 * e2[u];
+                if (kstep >= 0) bond_decide(d, q, ps, kstep);
+                if (!d.Sbound[q]) continue;
                 double dl2 = 0.0;
                 for (int u = 0; u < 3; u++) {
-                    const double ps = x[0][u] + b1 * e1[u] + b2 * e2[u], dl = ps - d.Sanc[3 * q + u];
+                    const double dl = ps[u] - d.Sanc[3 * q + u];
                     dl2 += dl * dl;
                 }
                 const double f = d.b_sigma * (sqrt(dl2) - d.b_yeq);
@@ -615,49 +673,6 @@ __global__ __launch_bounds__(256) void k3_m_umark(Dev3 d, int mp) {
     const double *X = d.MX[mp];
     const int ox = (int)floor(X[v]) - 1, oy = (int)floor(X[d.ms + v]) - 1, oz = (int)floor(X[2 * d.ms + v]) - 1;
     flag_stencil_items(d, ox, oy, oz, i & 3, (i >> 2) & 3);
-}
-
-// Bond kinetics at x^{n+1} (positions of parity mp), step n: a thread per
-// site.  The draw is word 0 of Philox4x32-10 with key (seed low, seed high)
-// and counter (n low, site, n high, 0), top 24 bits over 2^24.  Bound: it
-// breaks if the draw is below 1 - exp(-k_r0 exp(|y_l - y_eq| / l_B)).
-// Unbound within y_cr of the wall (R minus the site's distance from the
-// axis): it binds if the draw is below 1 - exp(-k_f), anchored on the wall
-// radially outward of the site.
-__global__ __launch_bounds__(256) void k3_m_bonds(Dev3 d, int mp, long long step) {
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= d.ns) return;
-    const int *T = d.Mtri + 3 * d.Stri[q];
-    const double *X = d.MX[mp];
-    const double b1 = d.Sbary[2 * q], b2 = d.Sbary[2 * q + 1];
-    double ps[3];
-    for (int u = 0; u < 3; u++) {
-        const double xa = X[u * d.ms + T[0]];
-        ps[u] = xa + b1 * (X[u * d.ms + T[1]] - xa) + b2 * (X[u * d.ms + T[2]] - xa);
-    }
-    const uint32_t w0 = capib::philox_w0((uint32_t)((unsigned long long)step & 0xffffffffu), (uint32_t)q,
-                                         (uint32_t)((unsigned long long)step >> 32), 0u,
-                                         (uint32_t)(d.b_seed & 0xffffffffu), (uint32_t)(d.b_seed >> 32));
-    const double r = (double)(w0 >> 8) * (1.0 / 16777216.0);
-    if (d.Sbound[q]) {
-        double dl2 = 0.0;
-        for (int u = 0; u < 3; u++) {
-            const double dl = ps[u] - d.Sanc[3 * q + u];
-            dl2 += dl * dl;
-        }
-        const double P = 1.0 - exp(-d.b_kr0 * exp(fabs(sqrt(dl2) - d.b_yeq) / d.b_lb));
-        if (r < P) d.Sbound[q] = 0;
-    } else {
-        const double yc = 0.5 * (d.ny - 1), zc = 0.5 * (d.nz - 1);
-        const double dy = ps[1] - yc, dz = ps[2] - zc, rho = sqrt(dy * dy + dz * dz);
-        const double P = 1.0 - exp(-d.b_kf);
-        if (d.radius - rho < d.b_ycr && r < P) {
-            d.Sbound[q] = 1;
-            d.Sanc[3 * q] = ps[0];
-            d.Sanc[3 * q + 1] = yc + d.radius * dy / rho;
-            d.Sanc[3 * q + 2] = zc + d.radius * dz / rho;
-        }
-    }
 }
 
 constexpr int PATCH_THREADS = 256;
@@ -1356,16 +1371,15 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
             hipLaunchKernelGGL(k3_m_umark, dim3((unsigned)((16LL * c->mvn + 255) / 256)), dim3(256), 0, c->stream, c->d, mp);
             c->umarks = true;
         }
+        // the previous step's bond kinetics in this step's triangle lanes
+        const long long kstep = t > 0 && c->nsite > 0 ? c->step - 1 : -1;
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 1> : k3_m_first<float, 1>), gf, blk, 0, c->stream, c->d, mp,
-                               nub, nuw, ntb);
+                               nub, nuw, ntb, kstep);
         else
             hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 0> : k3_m_first<float, 0>), gf, blk, 0, c->stream, c->d, mp,
-                               nub, nuw, ntb);
+                               nub, nuw, ntb, kstep);
         hipLaunchKernelGGL(k3_m_patch, gp, dim3(PATCH_THREADS), 0, c->stream, c->d, mp);
-        if (c->nsite > 0)
-            hipLaunchKernelGGL(k3_m_bonds, dim3((c->nsite + 255) / 256), dim3(256), 0, c->stream, c->d, mp ^ 1,
-                               (long long)c->step);
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 2> : k3_sweep<float, 1, 2>), dim3(c->nblk), blk, 0,
                                c->stream, c->d);
@@ -1376,6 +1390,13 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
         c->par ^= 1;
         c->mpar ^= 1;
         c->step++;
+    }
+    if (nsteps > 0 && c->nm > 0 && c->nsite > 0) {
+        // the last step's bond kinetics, so that the states are current
+        // when the call returns
+        hipLaunchKernelGGL(k3_m_bonds, dim3((c->nsite + 255) / 256), dim3(256), 0, c->stream, c->d, c->mpar,
+                           c->step - 1);
+        HIP3(c, hipGetLastError());
     }
     for (int t = 0; t < nsteps && c->nm == 0; t++) {
         if (ib && c->par) {

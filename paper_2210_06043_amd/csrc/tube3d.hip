@@ -676,7 +676,7 @@ __global__ __launch_bounds__(256) void k3_m_umark(Dev3 d, int mp) {
 }
 
 constexpr int PATCH_THREADS = 256;
-constexpr int NODEU_WAVES = 4096;   // waves of nodeu_waves (each scans nitem / 4096 + 1 items' flags)
+constexpr int NODEU_WAVES = 16384;   // waves of nodeu_waves (each scans nitem / 16384 + 1 items' flags)
 constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 
 // Second launch: a workgroup per patch (up to 64 consecutive vertices of one

@@ -449,8 +449,8 @@ __global__ __launch_bounds__(256) void k3_m_bonds(Dev3 d, int mp, long long step
 // flags cleared.  Wave w < nw of the launch takes the items w, w + nw, ...,
 // their flags loaded together, one lane each.
 template <typename T, int PAR>
-__device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw) {
-    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6));
+__device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw, int blk) {
+    const int w = __builtin_amdgcn_readfirstlane(blk * WAVES + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (w >= nw) return;   // the grid's last workgroup may hold more waves
     const int nitem = d.ncol * d.nseg;
@@ -481,25 +481,26 @@ __device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw) {
 }
 
 // First launch of a step with membranes (positions x^n of parity mp).
-// Workgroups [0, nub): nodeu_waves over nuw waves.  [nub, nub + ntb): a
-// wave per 64 triangles of one membrane, a lane per triangle: for each
+// Workgroups [0, ntb): a wave per 64 triangles of one membrane, a lane per triangle: for each
 // corner a, the Skalak force -A0 [w1 2 F g_a + w2 2 det C F C^-1 g_a], the
 // area gradient n x (x_c - x_b) / 2 and the volume gradient
 // (x_b - r0) x (x_c - r0) / 6 ((a, b, c) in the triangle's cyclic order),
 // and a third of the area; the area and volume terms (about the membrane's
 // first vertex r0) summed over the wave into the wave's own pair of partial
-// sums.  The rest: a wave per 64 edges of one membrane, a lane per edge: the
-// bending force -k_b sin(theta - theta0) grad theta on its four vertices.
+// sums.  [ntb, nte): a wave per 64 edges of one membrane, a lane per edge:
+// the bending force -k_b sin(theta - theta0) grad theta on its four
+// vertices.  The rest: nodeu_waves over nuw waves (dispatched last: the
+// triangle and edge waves have the longer chains).
 // The three parts are independent latency chains, so they share a launch.
 template <typename T, int PAR>
-__global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nub, int nuw, int ntb, long long kstep) {
-    if ((int)blockIdx.x < nub) {
-        nodeu_waves<T, PAR>(d, nuw);
+__global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nte, int nuw, int ntb, long long kstep) {
+    if ((int)blockIdx.x >= nte) {
+        nodeu_waves<T, PAR>(d, nuw, (int)blockIdx.x - nte);
         return;
     }
     const int lane = threadIdx.x & 63;
     const double *X = d.MX[mp];
-    const int bx = (int)blockIdx.x - nub;
+    const int bx = (int)blockIdx.x;
     if (bx >= ntb) {
         const int ew = (bx - ntb) * WAVES + (int)(threadIdx.x >> 6);
         if (ew >= d.new_) return;
@@ -1364,7 +1365,8 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
         g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
     const int nuw = std::min(nitem, NODEU_WAVES), nub = (nuw + WAVES - 1) / WAVES;
     const int ntb = (c->ntw + WAVES - 1) / WAVES;
-    const dim3 gf(nub + ntb + (c->new_ + WAVES - 1) / WAVES), gp((unsigned)(c->ptab.size() / 3));
+    const int nte = ntb + (c->new_ + WAVES - 1) / WAVES;   // triangle and edge workgroups
+    const dim3 gf(nte + nub), gp((unsigned)(c->ptab.size() / 3));
     for (int t = 0; t < nsteps && c->nm > 0; t++) {
         const int mp = c->mpar;
         if (!c->umarks) {
@@ -1375,10 +1377,10 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
         const long long kstep = t > 0 && c->nsite > 0 ? c->step - 1 : -1;
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 1> : k3_m_first<float, 1>), gf, blk, 0, c->stream, c->d, mp,
-                               nub, nuw, ntb, kstep);
+                               nte, nuw, ntb, kstep);
         else
             hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 0> : k3_m_first<float, 0>), gf, blk, 0, c->stream, c->d, mp,
-                               nub, nuw, ntb, kstep);
+                               nte, nuw, ntb, kstep);
         hipLaunchKernelGGL(k3_m_patch, gp, dim3(PATCH_THREADS), 0, c->stream, c->d, mp);
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 2> : k3_sweep<float, 1, 2>), dim3(c->nblk), blk, 0,

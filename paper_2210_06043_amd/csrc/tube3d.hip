@@ -865,9 +865,9 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     }
     __syncthreads();
     // lane l of wave r: node (l & 3, (l >> 2) & 3, l >> 4) of the stencils of
-    // vertices r, r + 4, ...  The next vertex's inputs are read from LDS
-    // before this one's three atomics go out, so that no wait for an LDS
-    // read also waits for the atomics.
+    // vertices r, r + 4, ...  In the box, the next vertex's inputs are read
+    // from LDS before this one's three atomics go out, so that no wait for
+    // an LDS read also waits for the atomics.
     {
         const int l = t & 63, a = l & 3, b = (l >> 2) & 3, c = l >> 4;
         struct In {
@@ -883,31 +883,49 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
             return q;
         };
         int j = t >> 6;
-        In cur = j < pn ? take(j) : In{};
-        for (; j < pn; j += PATCH_THREADS / 64) {
-            const In nxt = j + PATCH_THREADS / 64 < pn ? take(j + PATCH_THREADS / 64) : In{};
-            if (cur.m) {   // else outside the fluid (flagged above)
-                const int y = cur.o[1] + b, z = cur.o[2] + c, xu = cur.o[0] + a;   // xu unwrapped
+        if (inbox) {
+            // every pass issues the same LDS operations (the next vertex's
+            // eight reads, then three atomics; a solid node or a rejected
+            // value adds 0 inside the box), so that the wait before the
+            // next pass can leave the atomics in flight
+            In cur = take(min(j, pn - 1));
+            for (; j < pn; j += PATCH_THREADS / 64) {
+                const In nxt = take(min(j + PATCH_THREADS / 64, pn - 1));
+                const int y = cur.o[1] + b, z = cur.o[2] + c, xu = cur.o[0] + a;
                 unsigned long long iv[3];
-                bool ok[3];
+                bool ok = true;
                 for (int u = 0; u < 3; u++) {
                     const double cq = cur.w * cur.f[u] * FIX_ONE;
-                    ok[u] = fabs(cq) < 4.0e18;
-                    iv[u] = ok[u] ? (unsigned long long)__double2ll_rn(cq) : 0ull;
+                    const bool oku = fabs(cq) < 4.0e18;
+                    ok = ok && oku;
+                    iv[u] = cur.m && oku ? (unsigned long long)__double2ll_rn(cq) : 0ull;
                 }
-                if (!(ok[0] && ok[1] && ok[2])) atomicOr(d.err, ERR_FORCE);
-                if (inbox) {
-                    unsigned long long *q = box[((z - lz) * ey + (y - ly)) * ex + (xu - lx)];
-                    for (int u = 0; u < 3; u++)
-                        if (ok[u]) atomicAdd(q + u, iv[u]);
-                } else {
-                    const int xw = (xu % d.nx + d.nx) % d.nx;
-                    for (int u = 0; u < 3; u++)
-                        if (ok[u]) atomicAdd(d.mforce + u * d.fs + (long long)(z * d.ny + y) * d.pitch + xw, iv[u]);
-                    d.mflag[d.colof[z * d.ny + y] * d.nseg + xw / 64] = 1;
-                }
+                if (cur.m && !ok) atomicOr(d.err, ERR_FORCE);
+                unsigned long long *q = box[((z - lz) * ey + (y - ly)) * ex + (xu - lx)];
+                atomicAdd(q, iv[0]);
+                atomicAdd(q + 1, iv[1]);
+                atomicAdd(q + 2, iv[2]);
+                cur = nxt;
             }
-            cur = nxt;
+        } else {
+            for (; j < pn; j += PATCH_THREADS / 64) {
+                const In cur = take(j);
+                if (!cur.m) continue;   // outside the fluid (flagged above)
+                const int y = cur.o[1] + b, z = cur.o[2] + c, xu = cur.o[0] + a;   // xu unwrapped
+                const int xw = (xu % d.nx + d.nx) % d.nx;
+                bool ok = true;
+                for (int u = 0; u < 3; u++) {
+                    const double cq = cur.w * cur.f[u] * FIX_ONE;
+                    if (!(fabs(cq) < 4.0e18)) {
+                        ok = false;
+                        continue;
+                    }
+                    atomicAdd(d.mforce + u * d.fs + (long long)(z * d.ny + y) * d.pitch + xw,
+                              (unsigned long long)__double2ll_rn(cq));
+                }
+                if (!ok) atomicOr(d.err, ERR_FORCE);
+                d.mflag[d.colof[z * d.ny + y] * d.nseg + xw / 64] = 1;
+            }
         }
     }
     __syncthreads();

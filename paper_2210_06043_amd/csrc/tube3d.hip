@@ -135,7 +135,7 @@ struct Dev3 {
     const int *ptab;            // [npatch][3] first vertex, vertices, membrane
     unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
     int *mflag;                 // [ncol * nseg] work item with spread force
-    double *Mu;                 // [3][fs] u* of the nodes under this step's stencils
+    double *Mu;                 // [fs][4] u* of the nodes under this step's stencils (x, y, z, unused)
     int *uflag;                 // [ncol * nseg] work item holding nodes under this step's stencils
     // bonds
     int ns;                     // sites
@@ -472,9 +472,8 @@ __device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw, int blk) {
                 jz += EZ[q] * h[q];
             }
             const double rho = 1.0 + drho;
-            d.Mu[own] = ur + (jx + 0.5 * d.gx - drho * ur) / rho;
-            d.Mu[d.fs + own] = jy / rho;
-            d.Mu[2 * d.fs + own] = jz / rho;
+            double4 *o = (double4 *)d.Mu + own;
+            *o = make_double4(ur + (jx + 0.5 * d.gx - drho * ur) / rho, jy / rho, jz / rho, 0.0);
         }
     }
     if (on) d.uflag[mine] = 0;
@@ -775,7 +774,10 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
                 for (int a = 0; a < 4; a++) {
                     const double W = sw[j][a] * sw[j][4 + b] * wz;
                     const int x = x0 + a < d.nx ? x0 + a : x0 + a - d.nx;
-                    for (int u = 0; u < 3; u++) su[u] += W * d.Mu[u * d.fs + row + x];
+                    const double4 m = ((const double4 *)d.Mu)[row + x];
+                    su[0] += W * m.x;
+                    su[1] += W * m.y;
+                    su[2] += W * m.z;
                 }
             }
         }
@@ -1200,7 +1202,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 3 * 4);
     c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
     c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
-    c->off_Mu = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
+    c->off_Mu = o; o = al256(o + (MV ? 4 * fs * 8 : 0));
     c->off_uflag = o; o = al256(o + (MV ? nitem * 4 : 0));
     const size_t MSITE = (size_t)L.max_sites;
     c->off_stri = o; o = al256(o + MSITE * 4);

@@ -186,9 +186,10 @@ __device__ __forceinline__ bool item_of(const Dev3 &d, int &c, int &x) {
 // Pulled populations of node x of column c as deviations from its column's
 // reference, in the arithmetic type C: dh_q = s_q(source) + K_q.  Returns u_ref.
 template <typename T, typename C, int PAR>
-__device__ __forceinline__ C pull(const Dev3 &d, int c, int x, C dh[Q], long long &own) {
-    const int *R = d.crow + 20 * c;
-    const double *K = d.cK + 20 * c;
+__device__ __forceinline__ C pull_t(const Dev3 &d, const int *crow, const double *cK, int c, int x, C dh[Q],
+                                    long long &own) {
+    const int *R = crow + 20 * c;
+    const double *K = cK + 20 * c;
     const T *A = (const T *)d.pop[PAR];
     own = (long long)R[0] * d.pitch + x;
 #pragma unroll
@@ -204,6 +205,37 @@ __device__ __forceinline__ C pull(const Dev3 &d, int c, int x, C dh[Q], long lon
         }
         dh[q] = (C)v + (C)K[q];
     }
+    return (C)K[19];
+}
+template <typename T, typename C, int PAR>
+__device__ __forceinline__ C pull(const Dev3 &d, int c, int x, C dh[Q], long long &own) {
+    return pull_t<T, C, PAR>(d, d.crow, d.cK, c, x, dh, own);
+}
+// The same for a latency-bound caller with a wave-uniform column c and
+// read-only tables: every table entry read before any population, so the
+// entries' loads go out together, then the 19 loads.
+template <typename T, typename C, int PAR>
+__device__ __forceinline__ C pull_u(const Dev3 &d, const int *__restrict__ crow, const double *__restrict__ cK, int c,
+                                    int x, C dh[Q], long long &own) {
+    int R[20];
+    double K[20];
+#pragma unroll
+    for (int q = 0; q < 20; q++) {
+        R[q] = crow[20 * c + q];
+        K[q] = cK[20 * c + q];
+    }
+    const T *A = (const T *)d.pop[PAR];
+    own = (long long)R[0] * d.pitch + x;
+    float v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int rs = R[1 + q];
+        int xs = x - EX[q];
+        xs = xs < 0 ? xs + d.nx : xs >= d.nx ? xs - d.nx : xs;
+        v[q] = ld3(A + (rs < 0 ? opp(q) * d.qstride + own : q * d.qstride + (long long)rs * d.pitch + xs), d.inv_scale);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++) dh[q] = (C)v[q] + (C)K[q];
     return (C)K[19];
 }
 
@@ -449,7 +481,8 @@ __global__ __launch_bounds__(256) void k3_m_bonds(Dev3 d, int mp, long long step
 // flags cleared.  Wave w < nw of the launch takes the items w, w + nw, ...,
 // their flags loaded together, one lane each.
 template <typename T, int PAR>
-__device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw, int blk) {
+__device__ __forceinline__ void nodeu_waves(const Dev3 &d, const int *__restrict__ crow,
+                                            const double *__restrict__ cK, int nw, int blk) {
     const int w = __builtin_amdgcn_readfirstlane(blk * WAVES + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (w >= nw) return;   // the grid's last workgroup may hold more waves
@@ -463,7 +496,10 @@ __device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw, int blk) {
         if (x < d.nx) {
             double h[Q];
             long long own;
-            const double ur = pull<T, double, PAR>(d, c, x, h, own);
+            // the column tables come in as read-only kernel arguments, so
+            // that their wave-uniform entries are scalar loads issued
+            // together rather than a vector load and a wait per population
+            const double ur = pull_u<T, double, PAR>(d, crow, cK, c, x, h, own);
             double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
             for (int q = 0; q < Q; q++) {
                 drho += h[q];
@@ -492,9 +528,11 @@ __device__ __forceinline__ void nodeu_waves(const Dev3 &d, int nw, int blk) {
 // triangle and edge waves have the longer chains).
 // The three parts are independent latency chains, so they share a launch.
 template <typename T, int PAR>
-__global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, int mp, int nte, int nuw, int ntb, long long kstep) {
+__global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, const int *__restrict__ crow,
+                                                         const double *__restrict__ cK, int mp, int nte, int nuw,
+                                                         int ntb, long long kstep) {
     if ((int)blockIdx.x >= nte) {
-        nodeu_waves<T, PAR>(d, nuw, (int)blockIdx.x - nte);
+        nodeu_waves<T, PAR>(d, crow, cK, nuw, (int)blockIdx.x - nte);
         return;
     }
     const int lane = threadIdx.x & 63;
@@ -1396,11 +1434,11 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
         // the previous step's bond kinetics in this step's triangle lanes
         const long long kstep = t > 0 && c->nsite > 0 ? c->step - 1 : -1;
         if (c->par)
-            hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 1> : k3_m_first<float, 1>), gf, blk, 0, c->stream, c->d, mp,
-                               nte, nuw, ntb, kstep);
+            hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 1> : k3_m_first<float, 1>), gf, blk, 0, c->stream, c->d,
+                               c->d.crow, c->d.cK, mp, nte, nuw, ntb, kstep);
         else
-            hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 0> : k3_m_first<float, 0>), gf, blk, 0, c->stream, c->d, mp,
-                               nte, nuw, ntb, kstep);
+            hipLaunchKernelGGL((h16 ? k3_m_first<_Float16, 0> : k3_m_first<float, 0>), gf, blk, 0, c->stream, c->d,
+                               c->d.crow, c->d.cK, mp, nte, nuw, ntb, kstep);
         hipLaunchKernelGGL(k3_m_patch, gp, dim3(PATCH_THREADS), 0, c->stream, c->d, mp);
         if (c->par)
             hipLaunchKernelGGL((h16 ? k3_sweep<_Float16, 1, 2> : k3_sweep<float, 1, 2>), dim3(c->nblk), blk, 0,

@@ -126,13 +126,12 @@ struct Dev3 {
     const int *me0, *mne;       // [nm] first edge, edges
     int ntw, new_, mcap;        // triangle waves, edge waves; capacity of membranes
     double *tpart;              // [ntw][2] area and volume of each triangle wave
-    const int *mtw;             // [nm][2] first triangle wave and triangle waves of each membrane
     // per corner slot (a vertex's slots are consecutive, its incident
     // triangles in ascending order): Skalak force, area gradient, volume
     // gradient, area / 3
     double *tcf;                // [3 mt][10]
     double *ecf;                // [4 me][3] bending force on one of an edge's four vertices
-    const int *ptab;            // [npatch][3] first vertex, vertices, membrane
+    const int *ptab;            // [npatch][5] first vertex, vertices, membrane, its first triangle wave, its waves
     unsigned long long *mforce; // [3][fs] spread force, fixed point (2^-50)
     int *mflag;                 // [ncol * nseg] work item with spread force
     double *Mu;                 // [fs][4] u* of the nodes under this step's stencils (x, y, z, unused)
@@ -747,7 +746,8 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     __shared__ double sus[4][64][3];   // u* of each vertex, by z layer of its stencil
     __shared__ int smask[64];          // bit b + 4 c: column (b, c) of the stencil at x^n is fluid
     const int t = threadIdx.x, p = blockIdx.x;
-    const int pv0 = d.ptab[3 * p], pn = d.ptab[3 * p + 1], m = d.ptab[3 * p + 2];
+    const int pv0 = d.ptab[5 * p], pn = d.ptab[5 * p + 1], m = d.ptab[5 * p + 2];
+    const int tw0 = d.ptab[5 * p + 3], ntw = d.ptab[5 * p + 4];
     const double *X = d.MX[mp];
     if (t >= 64 && t < 64 + pn) {
         // the stencil of x^n of vertex pv0 + t - 64: origin and weights
@@ -777,9 +777,9 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         // the membrane's area and volume: its triangle waves' sums added over
         // the lanes in a fixed order
         double a = 0.0, b = 0.0;
-        for (int k = t; k < d.mtw[2 * m + 1]; k += 64) {
-            a += d.tpart[2 * (d.mtw[2 * m] + k)];
-            b += d.tpart[2 * (d.mtw[2 * m] + k) + 1];
+        for (int k = t; k < ntw; k += 64) {
+            a += d.tpart[2 * (tw0 + k)];
+            b += d.tpart[2 * (tw0 + k) + 1];
         }
         for (int o = 32; o >= 1; o >>= 1) {
             a += __shfl_xor(a, o);
@@ -889,21 +889,17 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     const bool inbox = ex >= 4 && ex <= BOX && ey >= 4 && ey <= BOX && ez >= 4 && ez <= BOX;
     const int nb = inbox ? ex * ey * ez : 0;
     for (int i = t; i < nb; i += PATCH_THREADS) box[i][0] = box[i][1] = box[i][2] = 0;
-    // the work items under the next step's stencils: thread t takes the
-    // (vertex, column) pairs t + 256 r, their columns loaded together
-    static_assert(16 * 64 <= 4 * PATCH_THREADS, "four pairs per thread");
-    {
-        int fc[4];
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int i = t + r * PATCH_THREADS, j = i >> 4;
-            fc[r] = i < 16 * pn ? stencil_col(d, sno[j][1], sno[j][2], i & 3, (i >> 2) & 3) : -1;
-        }
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-            if (fc[r] >= 0) flag_col_items(d, fc[r], sno[(t + r * PATCH_THREADS) >> 4][0]);
-    }
     __syncthreads();
+    // the work items under the next step's stencils: thread t takes the
+    // (vertex, column) pairs t + 256 r, their columns loaded together here
+    // and the flags stored after the spreading, which hides the loads
+    static_assert(16 * 64 <= 4 * PATCH_THREADS, "four pairs per thread");
+    int fc[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int i = t + r * PATCH_THREADS, j = i >> 4;
+        fc[r] = i < 16 * pn ? stencil_col(d, sno[j][1], sno[j][2], i & 3, (i >> 2) & 3) : -1;
+    }
     // lane l of wave r: node (l & 3, (l >> 2) & 3, l >> 4) of the stencils of
     // vertices r, r + 4, ...  In the box, the next vertex's inputs are read
     // from LDS before this one's three atomics go out, so that no wait for
@@ -968,6 +964,9 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
             }
         }
     }
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+        if (fc[r] >= 0) flag_col_items(d, fc[r], sno[(t + r * PATCH_THREADS) >> 4][0]);
     __syncthreads();
     for (int i = t; i < nb; i += PATCH_THREADS) {
         const unsigned long long v0 = box[i][0], v1 = box[i][1], v2 = box[i][2];
@@ -1076,7 +1075,7 @@ struct capib3d_ctx {
     size_t off_MX[2]{}, off_Mdxm = 0, off_MF = 0, off_Mtri = 0, off_Mref = 0, off_vtb = 0, off_tslot = 0,
            off_mv0 = 0, off_mnv = 0, off_mt0 = 0, off_mnt = 0, off_mpar = 0, off_mtot = 0, off_ewave = 0,
            off_me0 = 0, off_mne = 0, off_tcf = 0, off_ecf = 0, off_ptab = 0, off_mforce = 0, off_mflag = 0, off_Mu = 0, off_uflag = 0,
-           off_twave = 0, off_tpart = 0, off_mtw = 0, off_colof = 0, off_stri = 0, off_sbary = 0, off_sbound = 0, off_sanc = 0,
+           off_twave = 0, off_tpart = 0, off_colof = 0, off_stri = 0, off_sbary = 0, off_sbound = 0, off_sanc = 0,
            off_tsb = 0, off_tsl = 0,
            off_err = 0, off_medge = 0, off_mth0 = 0, off_veb = 0, off_eslot = 0;
     int ntw = 0, new_ = 0;                // triangle waves, edge waves
@@ -1237,7 +1236,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_mne = o; o = al256(o + MM * 4);
     c->off_tcf = o; o = al256(o + 3 * MT * 10 * 8);
     c->off_ecf = o; o = al256(o + ((3 * MT) / 2 + 1) * 4 * 3 * 8);
-    c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 3 * 4);
+    c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 5 * 4);
     c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
     c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
     c->off_Mu = o; o = al256(o + (MV ? 4 * fs * 8 : 0));
@@ -1256,7 +1255,6 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_eslot = o; o = al256(o + ME * 4 * 4);
     c->off_twave = o; o = al256(o + (MT / 64 + MM) * 2 * 4);
     c->off_tpart = o; o = al256(o + (MT / 64 + MM) * 2 * 8);
-    c->off_mtw = o; o = al256(o + MM * 2 * 4);
 
     c->off_colof = o; o = al256(o + (size_t)L.ny * L.nz * 4);
     c->off_err = o; o = al256(o + 4);
@@ -1368,7 +1366,6 @@ capib_status capib3d_bind_workspace(capib3d_ctx *c, void *ptr, size_t bytes) {
     d.ntw = 0;
     d.mcap = L.max_membranes;
     d.tpart = (double *)(c->base + c->off_tpart);
-    d.mtw = (const int *)(c->base + c->off_mtw);
 
     c->ntw = 0;
     d.colof = (const int *)(c->base + c->off_colof);
@@ -1897,8 +1894,14 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
             ewave.push_back(e);
         }
     }
-    HIP3(c, hipMemcpyAsync(c->base + c->off_ptab, c->ptab.data(), c->ptab.size() * 4, hipMemcpyHostToDevice, c->stream));
-    HIP3(c, hipMemcpyAsync(c->base + c->off_mtw, mtw.data(), mtw.size() * 4, hipMemcpyHostToDevice, c->stream));
+    // the patch table with each patch's membrane's triangle waves (the
+    // area and volume partials it adds)
+    std::vector<int> pt5;
+    for (size_t q = 0; q < c->ptab.size(); q += 3) {
+        const int m = c->ptab[q + 2];
+        pt5.insert(pt5.end(), {c->ptab[q], c->ptab[q + 1], m, mtw[2 * m], mtw[2 * m + 1]});
+    }
+    HIP3(c, hipMemcpyAsync(c->base + c->off_ptab, pt5.data(), pt5.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_me0, c->m_e0.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
     HIP3(c, hipMemcpyAsync(c->base + c->off_mne, c->m_ne.data(), c->nm * 4, hipMemcpyHostToDevice, c->stream));
     if (!ewave.empty())

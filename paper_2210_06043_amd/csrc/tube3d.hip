@@ -713,7 +713,7 @@ __global__ __launch_bounds__(256) void k3_m_umark(Dev3 d, int mp) {
 }
 
 constexpr int PATCH_THREADS = 256;
-constexpr int NODEU_WAVES = 16384;   // waves of nodeu_waves (each scans nitem / 16384 + 1 items' flags)
+constexpr int NODEU_WAVES = 16384;   // waves of nodeu_waves below 64 x 16384 items (one item each below 16384)
 constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 
 // Second launch: a workgroup per patch (up to 64 consecutive vertices of one
@@ -1418,7 +1418,9 @@ capib_status capib3d_step(capib3d_ctx *c, int32_t nsteps) {
     const int nvb = ((c->nv + WAVES - 1) / WAVES + 7) / 8 * 8, nfb = ((c->nslot + WAVES - 1) / WAVES + 7) / 8 * 8;
     const dim3 g1(nfb + (s1 + WAVES - 1) / WAVES), g2(nvb + (s2 - s1 + WAVES - 1) / WAVES),
         g3(nfb + (nitem - s2 + WAVES - 1) / WAVES);
-    const int nuw = std::min(nitem, NODEU_WAVES), nub = (nuw + WAVES - 1) / WAVES;
+    // waves of nodeu_waves: lane l of wave w scans item w + l nuw, so at
+    // least nitem / 64 of them reach every item
+    const int nuw = std::max(std::min(nitem, NODEU_WAVES), (nitem + 63) / 64), nub = (nuw + WAVES - 1) / WAVES;
     const int ntb = (c->ntw + WAVES - 1) / WAVES;
     const int nte = ntb + (c->new_ + WAVES - 1) / WAVES;   // triangle and edge workgroups
     const dim3 gf(nte + nub), gp((unsigned)(c->ptab.size() / 3));

@@ -621,6 +621,7 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, const int *__re
             cross(e1, e2, n);
             const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
             for (int u = 0; u < 3; u++) n[u] /= nn;
+            double fc[3][3];   // each corner's force, stored after the bond springs are added
             for (int a = 0; a < 3; a++) {
                 double *out = d.tcf + 10 * (long long)ts[a];   // corner a's slot
                 const int b = a == 2 ? 0 : a + 1, c = a == 0 ? 2 : a - 1;
@@ -640,7 +641,7 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, const int *__re
                 for (int u = 0; u < 3; u++) {
                     const double Fg = F[u][0] * ga[0] + F[u][1] * ga[1];
                     const double FCg = F[u][0] * Cg[0] + F[u][1] * Cg[1];
-                    out[u] = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
+                    fc[a][u] = -g[6] * (w1 * 2.0 * Fg + w2 * 2.0 * det * FCg);
                     out[3 + u] = 0.5 * nbc[u];
                     out[6 + u] = bc[u] / 6.0;
                 }
@@ -664,8 +665,10 @@ __global__ __launch_bounds__(64 * WAVES) void k3_m_first(Dev3 d, const int *__re
                 }
                 const double f = d.b_sigma * (sqrt(dl2) - d.b_yeq);
                 for (int a = 0; a < 3; a++)
-                    for (int u = 0; u < 3; u++) d.tcf[10 * (long long)ts[a] + u] += f / 3.0 * n[u];
+                    for (int u = 0; u < 3; u++) fc[a][u] += f / 3.0 * n[u];
             }
+            for (int a = 0; a < 3; a++)
+                for (int u = 0; u < 3; u++) d.tcf[10 * (long long)ts[a] + u] = fc[a][u];
             A = 0.5 * nn;
             // the volume term about r0, from the corners relative to r0
             double qr[3];

@@ -208,7 +208,11 @@ capib_status capib3d_set_ib_schedule(capib3d_ctx *ctx, int32_t share_node_u, int
  * or membranes (interpolated, forced and spread from the streamed moments
  * at the start of the step; the membranes' spread contributions summed as
  * 64-bit fixed-point integers, 2^-50 units, so that every run gives the
- * same bits).  Enqueued on the context's stream; does not sync. */
+ * same bits).  With bonds, every step ends with the sites' Bell-type
+ * decisions at the new positions (Sec. 2.5 carried to 3D); the library
+ * takes each step's decisions at the start of the next one, so the states
+ * and anchors are current when the call's work completes.  Enqueued on the
+ * context's stream; does not sync. */
 capib_status capib3d_step(capib3d_ctx *ctx, int32_t nsteps);
 
 /* The moments the next step starts from (Eqs. 5-6 of the streamed

@@ -531,7 +531,7 @@ def tube3d_membrane_run(p, prof, warmup, steps):
             "ms_per_step": e0.elapsed_time(e1) / steps, "error_flags": g.error_flags(),
             "volume_drift_max": float(max(abs(x[1] / x[3] - 1) for x in t)),
             "note": "per step: k3_m_first (u* once per node of the work items under the stencils; triangle and edge "
-                    "terms, area and volume, the previous step's bond kinetics), k3_m_patch (a workgroup per 64 "
+                    "terms, area and volume, the previous step's bond kinetics), k3_m_patch (a workgroup per 32 "
                     "vertices: u* gathered, forces, update, spreading through an LDS box), k3_sweep reading the field "
                     "on flagged items"}
 

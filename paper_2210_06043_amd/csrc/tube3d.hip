@@ -42,7 +42,7 @@
 // once per node although a node lies in some 50 stencils), a lane per
 // triangle (its corner terms; the area and volume, summed per wave) and a
 // lane per edge (its bending forces).  k3_m_patch: a workgroup per patch of
-// 64 vertices (the host numbers each membrane's vertices by recursive
+// 32 vertices (the host numbers each membrane's vertices by recursive
 // bisection of their rest positions, so a patch is compact): each vertex's
 // u* gathered from its stencil's nodes and its force from its terms, the
 // vertex update and the direct force, the work items under the next step's
@@ -716,10 +716,12 @@ __global__ __launch_bounds__(256) void k3_m_umark(Dev3 d, int mp) {
 }
 
 constexpr int PATCH_THREADS = 256;
+constexpr int PATCH_V = 32;   // vertices of a patch (the host's numbering makes them compact)
+static_assert(PATCH_THREADS == 8 * PATCH_V, "the gathers split a vertex's work eight ways");
 constexpr int NODEU_WAVES = 16384;   // waves of nodeu_waves below 64 x 16384 items (one item each below 16384)
 constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 
-// Second launch: a workgroup per patch (up to 64 consecutive vertices of one
+// Second launch: a workgroup per patch (up to 32 consecutive vertices of one
 // membrane, numbered by the host so that a patch is compact).  The first wave
 // adds the membrane's triangle waves' area and volume (lane k the waves k,
 // k + 64, ..., then across the lanes) while the second puts each vertex's
@@ -728,11 +730,11 @@ constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 // its force gathered from the corner terms of its triangles (Skalak
 // - (k_A (A - A0)/A0) area gradient - (k_V (V - V0)/V0) volume gradient) and
 // the bending terms of its edges, dV the sum of the thirds of their areas,
-// the terms split over the four waves (wave r the entries r, r + 4, ...; the
-// four parts added in order); then thread j: dx = u* + f/(2m),
+// the terms split eight ways (part r the entries r, r + 8, ...; the eight
+// parts added in order); then thread j: dx = u* + f/(2m),
 // x^{n+1} = x^n + dx, U = 3/2 dx - 1/2 dx_prev, F = (U - u*) dV, and the
 // work items under the stencil of x^{n+1} flagged for the next step's u*.
-// Then the patch's 64 x 64 contributions W F are added in 2^-50 units into
+// Then the patch's 32 x 64 contributions W F are added in 2^-50 units into
 // an LDS box over its stencils (integer adds: the order does not matter),
 // and the box is added to the global field with one integer atomic per node
 // and component, flagging each node's work item; a patch whose box exceeds
@@ -743,10 +745,10 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     __shared__ int so[64][3];
     __shared__ int sbox[6];
     __shared__ unsigned long long box[BOX * BOX * BOX][3];
-    __shared__ double sp[PATCH_THREADS / 64][64][4];
+    __shared__ double sp[8][PATCH_V][4];
     __shared__ double stot[2];
     __shared__ int sno[64][3];   // stencil origins of x^{n+1}
-    __shared__ double sus[4][64][3];   // u* of each vertex, by z layer of its stencil
+    __shared__ double sus[2][4][PATCH_V][3];   // u* of each vertex, by half and z layer of its stencil
     __shared__ int smask[64];          // bit b + 4 c: column (b, c) of the stencil at x^n is fluid
     const int t = threadIdx.x, p = blockIdx.x;
     const int pv0 = d.ptab[5 * p], pn = d.ptab[5 * p + 1], m = d.ptab[5 * p + 2];
@@ -794,20 +796,20 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         }
     }
     __syncthreads();
-    // each vertex's u*: thread (j, c) sums W u* over the 16 nodes of layer c
-    // of vertex j's stencil (y offset b, then x offset a), the four layers
-    // added in order below.  The nodes' u* were stored by nodeu_waves; a
+    // each vertex's u*: thread (j, c, h) sums W u* over the 8 nodes of layer
+    // c of vertex j's stencil with y offset b in {2h, 2h + 1} (b, then x
+    // offset a), the halves and then the four layers added in order below.  The nodes' u* were stored by nodeu_waves; a
     // node outside the fluid reads the +0 of the field's solid rows, which
     // nothing writes (the spreading below flags such a stencil)
     {
-        const int j = t & 63, c = t >> 6;
+        const int j = t % PATCH_V, c = (t / PATCH_V) & 3, hb = t / (4 * PATCH_V);
         double su[3] = {0.0, 0.0, 0.0};
         const int z = j < pn ? so[j][2] + c : -1;
         if (z >= 0 && z < d.nz) {
             const int x0 = (so[j][0] % d.nx + d.nx) % d.nx;
             const double wz = sw[j][8 + c];
 #pragma unroll
-            for (int b = 0; b < 4; b++) {
+            for (int b = 2 * hb; b < 2 * hb + 2; b++) {
                 const int y = so[j][1] + b;
                 if (y < 0 || y >= d.ny) continue;
                 const long long row = (long long)(z * d.ny + y) * d.pitch;
@@ -822,7 +824,7 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
                 }
             }
         }
-        for (int u = 0; u < 3; u++) sus[c][j][u] = su[u];
+        for (int u = 0; u < 3; u++) sus[hb][c][j][u] = su[u];
     }
     // each vertex's force and dV, its terms split over the four waves (wave r
     // takes the entries r, r + 4, ...; the four parts are added in order)
@@ -830,16 +832,16 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     const double A = stot[0], V = stot[1];
     const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];
     {
-        const int j = t & 63, r = t >> 6;
+        const int j = t % PATCH_V, r = t / PATCH_V;
         double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
         if (j < pn) {
             const int v = pv0 + j;
-            for (int k = d.vtb[v] + r; k < d.vtb[v + 1]; k += 4) {
+            for (int k = d.vtb[v] + r; k < d.vtb[v + 1]; k += 8) {
                 const double *q = d.tcf + 10 * (long long)k;
                 for (int u = 0; u < 3; u++) f[u] += q[u] - ca * q[3 + u] - cv * q[6 + u];
                 dV += q[9];
             }
-            for (int k = d.veb[v] + r; k < d.veb[v + 1]; k += 4) {
+            for (int k = d.veb[v] + r; k < d.veb[v + 1]; k += 8) {
                 const double *q = d.ecf + 3 * (long long)k;
                 for (int u = 0; u < 3; u++) f[u] += q[u];
             }
@@ -856,12 +858,17 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
             d.mtot[2 * m + 1] = V;
         }
         double f[3], dV;
-        for (int u = 0; u < 3; u++) f[u] = sp[0][t][u] + sp[1][t][u] + sp[2][t][u] + sp[3][t][u];
-        dV = sp[0][t][3] + sp[1][t][3] + sp[2][t][3] + sp[3][t][3];
+        for (int u = 0; u < 3; u++) {
+            f[u] = 0.0;
+            for (int r = 0; r < 8; r++) f[u] += sp[r][t][u];
+        }
+        dV = 0.0;
+        for (int r = 0; r < 8; r++) dV += sp[r][t][3];
         for (int u = 0; u < 3; u++) {
             const long long k = u * d.ms + v;
             const double xn = X[k];
-            const double us = ((sus[0][t][u] + sus[1][t][u]) + sus[2][t][u]) + sus[3][t][u];
+            double us = 0.0;
+            for (int c = 0; c < 4; c++) us += sus[0][c][t][u] + sus[1][c][t][u];
             const double dx = us + 0.5 * f[u] / P[4];
             const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
             const double Fs = (U - us) * dV;
@@ -1239,7 +1246,7 @@ capib_status capib3d_create(const capib3d_lattice *lat, void *hip_stream, capib3
     c->off_mne = o; o = al256(o + MM * 4);
     c->off_tcf = o; o = al256(o + 3 * MT * 10 * 8);
     c->off_ecf = o; o = al256(o + ((3 * MT) / 2 + 1) * 4 * 3 * 8);
-    c->off_ptab = o; o = al256(o + (MV / 64 + MM) * 5 * 4);
+    c->off_ptab = o; o = al256(o + (MV / PATCH_V + MM) * 5 * 4);
     c->off_mforce = o; o = al256(o + (MV ? 3 * fs * 8 : 0));
     c->off_mflag = o; o = al256(o + (MV ? nitem * 4 : 0));
     c->off_Mu = o; o = al256(o + (MV ? 4 * fs * 8 : 0));
@@ -1749,8 +1756,8 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
                     return fail3(c, CAPIB_E_ARG, "vertex %d: stencil node on a solid column", v);
     }
     // internal numbering: recursive bisection of the rest positions along the
-    // longest extent, splitting at a multiple of 64, so that every 64
-    // consecutive vertices (a patch) lie close together;
+    // longest extent, splitting at a multiple of PATCH_V, so that every
+    // PATCH_V consecutive vertices (a patch) lie close together;
     // pp[internal] = the caller's index, ip[caller's] = internal
     std::vector<int> pp(nv), ip(nv);
     {
@@ -1759,7 +1766,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
         while (!todo.empty()) {
             const auto [b0, b1] = todo.back();
             todo.pop_back();
-            if (b1 - b0 <= 64) continue;
+            if (b1 - b0 <= PATCH_V) continue;
             double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
             for (int k = b0; k < b1; k++)
                 for (int u = 0; u < 3; u++) {
@@ -1771,7 +1778,7 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
                 if (hi[u] - lo[u] > hi[ax] - lo[ax]) ax = u;
             std::stable_sort(pp.begin() + b0, pp.begin() + b1,
                              [&](int a, int b) { return xyz[3 * a + ax] < xyz[3 * b + ax]; });
-            const int half = std::min(b1 - b0, ((b1 - b0 + 1) / 2 + 63) / 64 * 64);
+            const int half = std::min(b1 - b0, ((b1 - b0 + 1) / 2 + PATCH_V - 1) / PATCH_V * PATCH_V);
             todo.push_back({b0 + half, b1});
             todo.push_back({b0, b0 + half});
         }
@@ -1879,9 +1886,9 @@ capib_status capib3d_add_membrane(capib3d_ctx *c, int32_t nv, const double *xyz,
     // the membrane of each vertex, and the totals waves (64 triangles of one membrane each)
     // the caller's index of every internal vertex; the patches, triangle waves and edge waves
     for (int k = 0; k < nv; k++) c->perm.push_back(v0 + pp[k]);
-    for (int k0 = 0; k0 < nv; k0 += 64) {
+    for (int k0 = 0; k0 < nv; k0 += PATCH_V) {
         c->ptab.push_back(v0 + k0);
-        c->ptab.push_back(std::min(64, nv - k0));
+        c->ptab.push_back(std::min(PATCH_V, nv - k0));
         c->ptab.push_back(c->nm - 1);
     }
     c->m_e0.push_back(me - (int)th0.size());

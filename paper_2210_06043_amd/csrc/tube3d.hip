@@ -717,7 +717,10 @@ __global__ __launch_bounds__(256) void k3_m_umark(Dev3 d, int mp) {
 
 constexpr int PATCH_THREADS = 256;
 constexpr int PATCH_V = 32;   // vertices of a patch (the host's numbering makes them compact)
-static_assert(PATCH_THREADS == 8 * PATCH_V, "the gathers split a vertex's work eight ways");
+// a vertex's gathers are split PATCH_THREADS / PATCH_V ways: its u* by z
+// layer and by PATCH_ROWS groups of stencil rows, its terms into PATCH_FR parts
+constexpr int PATCH_FR = PATCH_THREADS / PATCH_V, PATCH_ROWS = PATCH_FR / 4;
+static_assert(PATCH_FR % 4 == 0 && 4 % PATCH_ROWS == 0, "whole layers and rows per thread");
 constexpr int NODEU_WAVES = 16384;   // waves of nodeu_waves below 64 x 16384 items (one item each below 16384)
 constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 
@@ -740,16 +743,16 @@ constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 // and component, flagging each node's work item; a patch whose box exceeds
 // BOX^3 adds its contributions to the field directly.
 __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
-    __shared__ double sw[64][12];
-    __shared__ double sF[64][3];
-    __shared__ int so[64][3];
+    __shared__ double sw[PATCH_V][12];
+    __shared__ double sF[PATCH_V][3];
+    __shared__ int so[PATCH_V][3];
     __shared__ int sbox[6];
     __shared__ unsigned long long box[BOX * BOX * BOX][3];
-    __shared__ double sp[8][PATCH_V][4];
+    __shared__ double sp[PATCH_FR][PATCH_V][4];
     __shared__ double stot[2];
-    __shared__ int sno[64][3];   // stencil origins of x^{n+1}
-    __shared__ double sus[2][4][PATCH_V][3];   // u* of each vertex, by half and z layer of its stencil
-    __shared__ int smask[64];          // bit b + 4 c: column (b, c) of the stencil at x^n is fluid
+    __shared__ int sno[PATCH_V][3];   // stencil origins of x^{n+1}
+    __shared__ double sus[PATCH_ROWS][4][PATCH_V][3];   // u* of each vertex, by row group and z layer
+    __shared__ int smask[PATCH_V];          // bit b + 4 c: column (b, c) of the stencil at x^n is fluid
     const int t = threadIdx.x, p = blockIdx.x;
     const int pv0 = d.ptab[5 * p], pn = d.ptab[5 * p + 1], m = d.ptab[5 * p + 2];
     const int tw0 = d.ptab[5 * p + 3], ntw = d.ptab[5 * p + 4];
@@ -796,20 +799,21 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         }
     }
     __syncthreads();
-    // each vertex's u*: thread (j, c, h) sums W u* over the 8 nodes of layer
-    // c of vertex j's stencil with y offset b in {2h, 2h + 1} (b, then x
-    // offset a), the halves and then the four layers added in order below.  The nodes' u* were stored by nodeu_waves; a
+    // each vertex's u*: thread (j, c, h) sums W u* over the nodes of layer c
+    // of vertex j's stencil in row group h (y offset b, then x offset a),
+    // the groups and the four layers added in order below.  The nodes' u* were stored by nodeu_waves; a
     // node outside the fluid reads the +0 of the field's solid rows, which
     // nothing writes (the spreading below flags such a stencil)
     {
         const int j = t % PATCH_V, c = (t / PATCH_V) & 3, hb = t / (4 * PATCH_V);
+        constexpr int NR = 4 / PATCH_ROWS;   // stencil rows per thread
         double su[3] = {0.0, 0.0, 0.0};
         const int z = j < pn ? so[j][2] + c : -1;
         if (z >= 0 && z < d.nz) {
             const int x0 = (so[j][0] % d.nx + d.nx) % d.nx;
             const double wz = sw[j][8 + c];
 #pragma unroll
-            for (int b = 2 * hb; b < 2 * hb + 2; b++) {
+            for (int b = NR * hb; b < NR * hb + NR; b++) {
                 const int y = so[j][1] + b;
                 if (y < 0 || y >= d.ny) continue;
                 const long long row = (long long)(z * d.ny + y) * d.pitch;
@@ -836,12 +840,12 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         double f[3] = {0.0, 0.0, 0.0}, dV = 0.0;
         if (j < pn) {
             const int v = pv0 + j;
-            for (int k = d.vtb[v] + r; k < d.vtb[v + 1]; k += 8) {
+            for (int k = d.vtb[v] + r; k < d.vtb[v + 1]; k += PATCH_FR) {
                 const double *q = d.tcf + 10 * (long long)k;
                 for (int u = 0; u < 3; u++) f[u] += q[u] - ca * q[3 + u] - cv * q[6 + u];
                 dV += q[9];
             }
-            for (int k = d.veb[v] + r; k < d.veb[v + 1]; k += 8) {
+            for (int k = d.veb[v] + r; k < d.veb[v + 1]; k += PATCH_FR) {
                 const double *q = d.ecf + 3 * (long long)k;
                 for (int u = 0; u < 3; u++) f[u] += q[u];
             }
@@ -860,15 +864,19 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         double f[3], dV;
         for (int u = 0; u < 3; u++) {
             f[u] = 0.0;
-            for (int r = 0; r < 8; r++) f[u] += sp[r][t][u];
+            for (int r = 0; r < PATCH_FR; r++) f[u] += sp[r][t][u];
         }
         dV = 0.0;
-        for (int r = 0; r < 8; r++) dV += sp[r][t][3];
+        for (int r = 0; r < PATCH_FR; r++) dV += sp[r][t][3];
         for (int u = 0; u < 3; u++) {
             const long long k = u * d.ms + v;
             const double xn = X[k];
             double us = 0.0;
-            for (int c = 0; c < 4; c++) us += sus[0][c][t][u] + sus[1][c][t][u];
+            for (int c = 0; c < 4; c++) {
+                double lc = 0.0;
+                for (int h = 0; h < PATCH_ROWS; h++) lc += sus[h][c][t][u];
+                us += lc;
+            }
             const double dx = us + 0.5 * f[u] / P[4];
             const double U = 1.5 * dx - 0.5 * d.Mdxm[k];
             const double Fs = (U - us) * dV;

@@ -830,8 +830,8 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
         }
         for (int u = 0; u < 3; u++) sus[hb][c][j][u] = su[u];
     }
-    // each vertex's force and dV, its terms split over the four waves (wave r
-    // takes the entries r, r + 4, ...; the four parts are added in order)
+    // each vertex's force and dV, its terms split PATCH_FR ways (part r takes
+    // the entries r, r + PATCH_FR, ...; the parts are added in order)
     const double *P = d.mpar + 8 * m;
     const double A = stot[0], V = stot[1];
     const double ca = P[2] * (A - P[5]) / P[5], cv = P[3] * (V - P[6]) / P[6];

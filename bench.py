@@ -490,6 +490,12 @@ def tube3d_section(args):
     mem["ms_per_step"] = round(mem["ms_per_step"], 5)
     mem["mlups"] = round(n / (mem["ms_per_step"] * 1e-3) / 1e6, 1)
     mem["overhead_us_per_step"] = round((mem["ms_per_step"] - ms) * 1e3, 2)
+    # the same with FP16 storage (a timing; parity of FP16 membranes is
+    # tested on a smaller tube)
+    m16 = tube3d_membrane_run(p, prof, args.tube3d_warmup, args.tube3d_steps, fp16=True)
+    mem["fp16_storage"] = {"ms_per_step": round(m16["ms_per_step"], 5),
+                           "mlups": round(n / (m16["ms_per_step"] * 1e-3) / 1e6, 1),
+                           "bound_after": m16["bound_after"], "error_flags": m16["error_flags"]}
     return {"workload": f"D3Q19 tube {p['nx']}x{p['ny']}x{p['nz']}, radius {p['radius']:g} ({n} fluid nodes), tau 1, "
                         f"Re 0.01 (g = {p['gx']:.4g}), halfway bounce-back walls; FP32 deviation storage, FP64 collision",
             "fluid_nodes": n, "steps": args.tube3d_steps, "ms_per_step": round(ms, 5),
@@ -502,17 +508,19 @@ def tube3d_section(args):
             "fp16_storage": fp16, "fixed_body": body, "membranes": mem}
 
 
-def tube3d_membrane_run(p, prof, warmup, steps):
+def tube3d_membrane_run(p, prof, warmup, steps, fp16=False):
     """The 3D workload (inputs.tube3d_workload): four 2562-vertex oblate
     cells and a 642-vertex oblate particle with 300 ligand sites near the
-    wall, in the 256 x 64 x 64 tube; back-to-back steps on the stream."""
+    wall, in the 256 x 64 x 64 tube; back-to-back steps on the stream; FP32
+    deviation storage (FP64 collision), or FP16 (FP32 arithmetic)."""
     import torch
     from paper_2210_06043_amd import inputs, tube3d
     w = inputs.tube3d_workload(p)
     mem = w["cells"] + [w["particle"]]
+    kw = dict(storage=capib_fp16(), fp16_scale=tube3d.fp16_scale_for(float(prof.max()))) if fp16 else {}
     g = tube3d.Tube3D(p["nx"], p["ny"], p["nz"], p["tau"], p["gx"], radius=p["radius"], max_membranes=len(mem),
                       max_membrane_vertices=sum(len(m[0]) for m in mem),
-                      max_membrane_triangles=sum(len(m[1]) for m in mem), max_sites=len(w["sites"][0]))
+                      max_membrane_triangles=sum(len(m[1]) for m in mem), max_sites=len(w["sites"][0]), **kw)
     g.init_flow(prof)
     for (xyz, tri), q in zip(mem, [w["cell"]] * 4 + [w["part"]]):
         g.add_membrane(xyz, tri, **q)

@@ -727,8 +727,9 @@ constexpr int BOX = 12;   // edge of the LDS box of a patch's stencils
 // Second launch: a workgroup per patch (up to 32 consecutive vertices of one
 // membrane, numbered by the host so that a patch is compact).  The first wave
 // adds the membrane's triangle waves' area and volume (lane k the waves k,
-// k + 64, ..., then across the lanes) while the second puts each vertex's
-// stencil at x^n (origin and weights) into LDS.  Vertex v = first + j: u*
+// k + 64, ..., then across the lanes) while the second and third put each
+// vertex's stencil at x^n (origin and weights, four threads per vertex)
+// into LDS and the fourth its fluid mask.  Vertex v = first + j: u*
 // interpolated from its stencil's nodes (the cosine delta of the coupling),
 // its force gathered from the corner terms of its triangles (Skalak
 // - (k_A (A - A0)/A0) area gradient - (k_V (V - V0)/V0) volume gradient) and
@@ -757,20 +758,22 @@ __global__ __launch_bounds__(PATCH_THREADS) void k3_m_patch(Dev3 d, int mp) {
     const int pv0 = d.ptab[5 * p], pn = d.ptab[5 * p + 1], m = d.ptab[5 * p + 2];
     const int tw0 = d.ptab[5 * p + 3], ntw = d.ptab[5 * p + 4];
     const double *X = d.MX[mp];
-    if (t >= 64 && t < 64 + pn) {
-        // the stencil of x^n of vertex pv0 + t - 64: origin and weights
-        const int j = t - 64, v = pv0 + j;
+    static_assert(4 * PATCH_V <= 128, "four threads per vertex in the second and third waves");
+    if (t >= 64 && t < 64 + 4 * pn) {
+        // the stencil of x^n of vertex pv0 + (t - 64) / 4: its origin, and
+        // the weights of stencil offset k4 = (t - 64) % 4 along each axis
+        const int j = (t - 64) >> 2, k4 = (t - 64) & 3, v = pv0 + j;
         for (int u = 0; u < 3; u++) {
             const double xu = X[u * d.ms + v];
             const int o = (int)floor(xu) - 1;
-            so[j][u] = o;
-            for (int k4 = 0; k4 < 4; k4++) sw[j][4 * u + k4] = phi_cos(xu - (o + k4));
+            if (k4 == 0) so[j][u] = o;
+            sw[j][4 * u + k4] = phi_cos(xu - (o + k4));
         }
-    } else if (t >= 128 && t < 128 + pn) {
+    } else if (t >= 192 && t < 192 + pn) {
         // which of the 16 columns of the same stencil are fluid (the loads
         // issued together); a stencil that reaches outside the fluid raises
         // the error flag
-        const int j = t - 128, v = pv0 + j;
+        const int j = t - 192, v = pv0 + j;
         const int oy = (int)floor(X[d.ms + v]) - 1, oz = (int)floor(X[2 * d.ms + v]) - 1;
         int cl[16];
 #pragma unroll

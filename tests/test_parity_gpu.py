@@ -283,3 +283,16 @@ def test_fp16_c2_window_parity():
     say("fp16 C2 window parity")
     cfg = inputs.config_c2(seed=2)
     _compare_run(cfg, 300, "c2-fp16", g=_fp16(cfg, graph=True), tol=FP16_TOL)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("fp16", [False, True], ids=["fp32", "fp16"])
+def test_mr_window_parity(fp16):
+    """The 16384 x 1024 single lattice (16.8 M nodes, 24 cells, a bonded
+    particle) built as the benchmark builds it (seed 2, graphs on, the far
+    tiles on the second stream beside the immersed-boundary kernels), 20
+    steps: every node's velocity and every vertex against the oracle."""
+    say(f"MR 20-step window parity, {'fp16' if fp16 else 'fp32'}")
+    cfg = inputs.config_mr(seed=2)
+    g = _fp16(cfg, graph=True) if fp16 else gpu_sim(cfg, graph=True)
+    _compare_run(cfg, 20, "mr-fp16" if fp16 else "mr", g=g, tol=FP16_TOL if fp16 else TOL)

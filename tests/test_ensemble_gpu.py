@@ -184,25 +184,35 @@ def test_large_ensemble_list_sweep_equals_single_runs():
 
 
 @pytest.mark.timeout(900)
-def test_batched_workload_fp16_members_match_their_oracles():
+@pytest.mark.parametrize("fp16,tol,members", [(True, 1e-3, (0, 2, 5, 6, 11)), (False, 1e-5, (2, 6))],
+                         ids=["fp16", "fp32"])
+def test_batched_workload_members_match_their_oracles(fp16, tol, members):
     """The ensemble exactly as the benchmark runs it: the 256 capillaries of
     the batched workload (lengths 256-2048 x 64, 1-4 cells, one particle
-    each), FP16 storage, graphs, 131,072 tiles, so the far tiles run in
-    their own launch beside the membrane phase with streaming stores and
-    the near tiles over the list.  After 200 steps five members (rigid and
-    soft particles, 1-4 cells, short and long) match their own FP64 oracle
-    runs within 1e-3 (velocity and marker displacement), bonds exact."""
+    each), FP16 and FP32 storage, graphs, 131,072 tiles, so the far tiles
+    run in their own launch beside the membrane phase with streaming stores
+    and the near tiles over the list.  After 200 steps the members match
+    their own FP64 oracle runs (velocity and marker displacement), bonds
+    exact: with FP16 storage five members (rigid and soft particles, 1-4
+    cells, short and long) within 1e-3; with FP32 storage the two
+    rigid-particle members within 1e-5.  Member 0, whose particle is
+    deformable at Ca = 1.0e-5, differs by 3.4e-5 in FP32 storage, and so
+    does its own single-lattice run, so the ensemble's launches are not the
+    cause; it is not held to 1e-5 here."""
     steps = 200
     cfgs = inputs.config_c3(seed=0, members=256)
-    scale = capib.fp16_scale_for(cfgs[0])
-    sim, first = capib.from_ensemble(cfgs, storage=capib.FP16_SHIFTED, fp16_scale=scale, graph=True)
+    if fp16:
+        kw = dict(storage=capib.FP16_SHIFTED, fp16_scale=capib.fp16_scale_for(cfgs[0]))
+    else:
+        kw = dict(storage=capib.FP32_SHIFTED)
+    sim, first = capib.from_ensemble(cfgs, graph=True, **kw)
     d0 = sim.diagnostics()
     assert d0["tiles"] == 131072
     sim.step(steps)
     d = sim.diagnostics()
     assert d["error_flags"] == 0 and d["step"] == steps
     _, ux, uy = sim.macro()
-    for k in (0, 2, 5, 6, 11):
+    for k in members:
         cfg = cfgs[k]
         o = oracle_sim(cfg)
         x0 = [o.vertices(b).copy() for b in range(len(cfg.bodies))]
@@ -213,9 +223,9 @@ def test_batched_workload_fp16_members_match_their_oracles():
         eu = rel_max(ug, np.stack([uxo, uyo]))
         kind = "rigid" if cfg.meta["ca"] == 0 else f"soft Ca={cfg.meta['ca']:.1e}"
         say(f"batched member {k} ({cfg.nx}x{ny}, {cfg.meta['ncell']} cells, {kind}): velocity rel err {eu:.3e}")
-        assert eu < 1e-3
+        assert eu < tol
         for b in range(len(cfg.bodies)):
             dx = rel_max(sim.vertices(first[k] + b) - x0[b], o.vertices(b) - x0[b])
             say(f"batched member {k} body {b}: displacement rel err {dx:.3e}")
-            assert dx < 1e-3
+            assert dx < tol
         check_bonds(o, sim, cfg, f"batched member {k}", first=first[k])
